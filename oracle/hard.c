@@ -1,0 +1,334 @@
+/* CPU oracle: hard-process events that feed the shower (appendix C and the
+ * workload definitions).  Test infrastructure only. */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle_int.h"
+
+#define STREAM_HARD 2u
+#define LO_MAXATT 1000
+
+/* Li2 by its power series on [0, 1/2] and the reflection
+ * Li2(x) = pi^2/6 - ln(x) ln(1-x) - Li2(1-x) above; x < 0 through
+ * Li2(x) = -Li2(x/(x-1)) - ln^2(1-x)/2. */
+double or_li2(double x) {
+    if (x == 1.0) return OR_PI * OR_PI / 6.0;
+    if (x < 0.0) {
+        double l = log(1.0 - x);
+        return -or_li2(x / (x - 1.0)) - 0.5 * l * l;
+    }
+    if (x > 0.5) return OR_PI * OR_PI / 6.0 - log(x) * log(1.0 - x) - or_li2(1.0 - x);
+    double sum = 0.0, xk = x;
+    for (int k = 1; k < 200; ++k) {
+        double term = xk / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+        xk *= x;
+    }
+    return sum;
+}
+
+/* cos(theta) distributed as 1 + cos^2(theta): invert the cubic CDF (Cardano) */
+static double cos_1pc2(double u) {
+    double q = 4.0 - 8.0 * u;
+    double sd = sqrt(0.25 * q * q + 1.0);
+    return cbrt(-0.5 * q + sd) + cbrt(-0.5 * q - sd);
+}
+
+/* V^2 + A^2 of the Z coupling to quark flavour |f| */
+static double zcoup(const or_state* s, int f) {
+    int a = abs(f);
+    double V, A;
+    if (a % 2 == 0) { V = 0.5 - 4.0 / 3.0 * s->c.sw2; A = 0.5; }
+    else { V = -0.5 + 2.0 / 3.0 * s->c.sw2; A = -0.5; }
+    return V * V + A * A;
+}
+
+static double xfp(const or_state* s, int pid, double x, double q2) {
+    return or_pdf_xf(s, or_pdf_table(pid), x, q2);
+}
+
+static void put(or_events* o, int64_t e, int slot, const double* p, int pid, int col, int acol,
+                int st) {
+    int64_t k = (int64_t)slot * o->cap + e;
+    o->E[k] = p[0]; o->px[k] = p[1]; o->py[k] = p[2]; o->pz[k] = p[3];
+    o->pid[k] = pid; o->col[k] = col; o->acol[k] = acol; o->status[k] = (int8_t)st;
+}
+
+/* Z -> e- e+ with 1 + cos^2 in the Z rest frame, boosted along pZ */
+static void decay_z(const double* pZ, double m, double ucos, double uphi, double* em, double* ep) {
+    double c = cos_1pc2(ucos), st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * OR_PI * uphi;
+    double k[4] = {0.5 * m, 0.5 * m * st * cos(ph), 0.5 * m * st * sin(ph), 0.5 * m * c};
+    double pk = pZ[1] * k[1] + pZ[2] * k[2] + pZ[3] * k[3];
+    double E1 = (pZ[0] * k[0] + pk) / m;
+    double f = (k[0] + E1) / (pZ[0] + m);
+    em[0] = E1;
+    for (int m3 = 1; m3 < 4; ++m3) em[m3] = k[m3] + f * pZ[m3];
+    for (int m3 = 0; m3 < 4; ++m3) ep[m3] = pZ[m3] - em[m3];
+}
+
+static void clear_counters(or_events* o, int64_t e) {
+    if (o->n_cycles) o->n_cycles[e] = 0;
+    if (o->n_trials) o->n_trials[e] = 0;
+    if (o->n_accept) o->n_accept[e] = 0;
+    if (o->n_viol) o->n_viol[e] = 0;
+    if (o->t1) o->t1[e] = 0.0;
+}
+
+static void gen_ee(const or_state* s, int64_t id, uint64_t seed, or_events* o, int64_t e) {
+    double u[4];
+    or_rng_block(seed, STREAM_HARD, id, 0u, 0u, u);
+    int f = 1 + (int)(u[0] * s->c.nf);
+    if (f > s->c.nf) f = s->c.nf;
+    double c = cos_1pc2(u[1]), st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * OR_PI * u[2];
+    double E = 0.5 * s->sqrtS;
+    double q[4] = {E, E * st * cos(ph), E * st * sin(ph), E * c};
+    double qb[4] = {E, -q[1], -q[2], -q[3]};
+    put(o, e, 0, q, f, 1, 0, 1);
+    put(o, e, 1, qb, -f, 0, 1, 1);
+    o->n[e] = 2; o->w[e] = 1.0; o->t_start[e] = s->S; o->flags[e] = 0;
+}
+
+/* Drell-Yan luminosity sum over the ten q qbar orientations at (m, y) */
+static double lo_lumi(const or_state* s, double m, double y, double* csub) {
+    double m2 = m * m;
+    double e1 = m / s->sqrtS * exp(y), e2 = m / s->sqrtS * exp(-y);
+    double L = 0.0;
+    for (int f = 1; f <= s->c.nf; ++f) {
+        double v = zcoup(s, f);
+        double a = v * xfp(s, f, e1, m2) * xfp(s, -f, e2, m2);
+        double b = v * xfp(s, -f, e1, m2) * xfp(s, f, e2, m2);
+        if (csub) { csub[2 * (f - 1)] = a; csub[2 * (f - 1) + 1] = b; }
+        L += a + b;
+    }
+    return L;
+}
+
+double or_lo_scan_wmax(const or_state* s) {
+    double best = 0.0;
+    for (int i = 0; i < 64; ++i) {
+        double m = s->c.mll_min + (s->c.mll_max - s->c.mll_min) * i / 63.0;
+        double Y = log(s->sqrtS / m);
+        for (int j = 0; j < 128; ++j) {
+            double y = -Y + 2.0 * Y * (j + 0.5) / 128.0;
+            double W = lo_lumi(s, m, y, NULL) * 2.0 * Y;
+            if (W > best) best = W;
+        }
+    }
+    return or_quarter_octave_up(1.25 * best);
+}
+
+static void gen_lo(const or_state* s, int64_t id, uint64_t seed, or_events* o, int64_t e) {
+    double mz2 = s->c.mz * s->c.mz, mg = s->c.mz * s->c.gz;
+    double r1 = atan((s->c.mll_min * s->c.mll_min - mz2) / mg);
+    double r2 = atan((s->c.mll_max * s->c.mll_max - mz2) / mg);
+    double csub[10];
+    for (int k = 0; k < LO_MAXATT; ++k) {
+        double u[4];
+        or_rng_block(seed, STREAM_HARD, id, (uint32_t)k, 0u, u);
+        double m2 = mz2 + mg * tan(r1 + u[0] * (r2 - r1));
+        double m = sqrt(m2);
+        double Y = log(s->sqrtS / m), y = -Y + 2.0 * Y * u[1];
+        double L = lo_lumi(s, m, y, csub);
+        if (!(u[2] * s->lo_wmax < L * 2.0 * Y)) continue;
+        double target = u[3] * L, cum = 0.0;
+        int sel = 2 * s->c.nf - 1;
+        for (int q = 0; q < 2 * s->c.nf; ++q) {
+            cum += csub[q];
+            if (target < cum) { sel = q; break; }
+        }
+        int f = sel / 2 + 1;
+        int pa = (sel % 2 == 0) ? f : -f, pb = -pa;
+        double e1 = m / s->sqrtS * exp(y), e2 = m / s->sqrtS * exp(-y);
+        double Ea = 0.5 * e1 * s->sqrtS, Eb = 0.5 * e2 * s->sqrtS;
+        double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+        put(o, e, 0, A, pa, pa > 0 ? 1 : 0, pa > 0 ? 0 : 1, -1);
+        put(o, e, 1, B, pb, pb > 0 ? 1 : 0, pb > 0 ? 0 : 1, -1);
+        double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4];
+        double ud[4];
+        or_rng_block(seed, STREAM_HARD, id, 0xFFFFFFFFu, 0u, ud);
+        decay_z(pZ, m, ud[0], ud[1], em, ep);
+        put(o, e, 2, em, 11, 0, 0, 1);
+        put(o, e, 3, ep, -11, 0, 0, 1);
+        o->n[e] = 4; o->w[e] = 1.0; o->t_start[e] = s->S; o->flags[e] = 0;
+        return;
+    }
+    o->n[e] = 0; o->w[e] = 0.0; o->t_start[e] = s->S; o->flags[e] = OR_F_HARDFAIL;
+}
+
+/* NLO building blocks of appendix C.3-C.4 at muF = muR = mZ (the logarithms of
+ * muF^2/m^2 vanish) */
+double or_nlo_bvi_factor(const or_state* s) {
+    return 1.0 + OR_CF * s->c.alphas_mz / (2.0 * OR_PI) * 2.0;
+}
+double or_nlo_aqq(const or_state* s) {
+    return OR_CF * s->c.alphas_mz / (2.0 * OR_PI) * (-5.0 + 2.0 * OR_PI * OR_PI / 3.0);
+}
+double or_nlo_bqq(const or_state* s, double eta) {
+    double l = log(1.0 - eta);
+    return OR_CF * s->c.alphas_mz / (2.0 * OR_PI) * 2.0 *
+           (OR_PI * OR_PI / 6.0 - l * l - or_li2(1.0 - eta));
+}
+double or_nlo_gqq(const or_state* s, double x) {
+    double L = log((1.0 - x) / x) + log(1.0 - x);
+    return OR_CF * s->c.alphas_mz / (2.0 * OR_PI) * (2.0 / (1.0 - x)) * L;
+}
+static double nlo_hqq(const or_state* s, double x) {
+    double L = log((1.0 - x) / x) + log(1.0 - x);
+    return OR_CF * s->c.alphas_mz / (2.0 * OR_PI) * (-(1.0 + x) * L + (1.0 - x));
+}
+static double nlo_hqg(const or_state* s, double x) {
+    double L = log((1.0 - x) / x) + log(1.0 - x);
+    return OR_TR * s->c.alphas_mz / (2.0 * OR_PI) *
+           (2.0 * x * (1.0 - x) + (x * x + (1.0 - x) * (1.0 - x)) * L);
+}
+
+/* collinear insertion for one leg with Born parton b at eta, one-point sample x */
+static double k_leg(const or_state* s, int b, double eta, double x, double q2) {
+    double den = or_pdf_f(s, or_pdf_table(b), eta, q2);
+    if (!(den > 0.0)) return 0.0;
+    double rq = or_pdf_f(s, or_pdf_table(b), eta / x, q2) / (x * den);
+    double rg = or_pdf_f(s, 0, eta / x, q2) / (x * den);
+    return or_nlo_aqq(s) - or_nlo_bqq(s, eta) +
+           (1.0 - eta) * ((rq - 1.0) * or_nlo_gqq(s, x) + rq * nlo_hqq(s, x) + rg * nlo_hqg(s, x));
+}
+
+/* real minus subtraction in closed form (appendix C.2); kind 0: q qbar -> Z g,
+ * kind 1: g q -> Z q with ubar measured from the gluon */
+void or_nlo_rs(const or_state* s, int kind, double sbar, double tbar, double ubar, double mborn2,
+               double* r_minus_s) {
+    double m2 = s->c.mz * s->c.mz;
+    (void)tbar;
+    if (kind == 0) *r_minus_s = 8.0 * OR_PI * s->c.alphas_mz * OR_CF / m2 * mborn2 * (-2.0);
+    else *r_minus_s = 8.0 * OR_PI * s->c.alphas_mz * OR_TR / m2 * mborn2 * ((2.0 * m2 - ubar) / sbar);
+}
+
+static double mborn2(const or_state* s, int f) {
+    double m2 = s->c.mz * s->c.mz;
+    return 1.0 / OR_NC * 0.25 * sqrt(2.0) * s->c.gf * m2 * m2 * zcoup(s, f);
+}
+
+static void gen_nlo(const or_state* s, int64_t id, uint64_t seed, or_events* o, int64_t e) {
+    double u0[4], u1[4];
+    or_rng_block(seed, STREAM_HARD, id, 0u, 0u, u0);
+    or_rng_block(seed, STREAM_HARD, id, 1u, 0u, u1);
+    const double m = s->c.mz, m2 = m * m, q2 = m2;
+    const int nf = s->c.nf;
+    if (u0[0] < s->c.p_s) {
+        /* S event: Born x (B + V + I + collinear) */
+        double Y = log(s->sqrtS / m), y = -Y + 2.0 * Y * u0[2];
+        double e1 = m / s->sqrtS * exp(y), e2 = m / s->sqrtS * exp(-y);
+        double xa = e1 + (1.0 - e1) * u1[0], xb = e2 + (1.0 - e2) * u1[1];
+        double csub[10], W = 0.0;
+        for (int f = 1; f <= nf; ++f)
+            for (int o2 = 0; o2 < 2; ++o2) {
+                int a = o2 == 0 ? f : -f, b = -a;
+                double born = OR_PI / (m2 * m2) * mborn2(s, f) * xfp(s, a, e1, q2) * xfp(s, b, e2, q2);
+                double corr = or_nlo_bvi_factor(s) + k_leg(s, a, e1, xa, q2) + k_leg(s, b, e2, xb, q2);
+                csub[2 * (f - 1) + o2] = born * corr;
+                W += fabs(born * corr);
+            }
+        double target = u0[1] * W, cum = 0.0;
+        int sel = 2 * nf - 1;
+        for (int q = 0; q < 2 * nf; ++q) {
+            cum += fabs(csub[q]);
+            if (target < cum) { sel = q; break; }
+        }
+        int f = sel / 2 + 1, a = (sel % 2 == 0) ? f : -f, b = -a;
+        double Ea = 0.5 * e1 * s->sqrtS, Eb = 0.5 * e2 * s->sqrtS;
+        double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+        put(o, e, 0, A, a, a > 0 ? 1 : 0, a > 0 ? 0 : 1, -1);
+        put(o, e, 1, B, b, b > 0 ? 1 : 0, b > 0 ? 0 : 1, -1);
+        double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4];
+        decay_z(pZ, m, u0[3], u1[3], em, ep);
+        put(o, e, 2, em, 11, 0, 0, 1);
+        put(o, e, 3, ep, -11, 0, 0, 1);
+        o->n[e] = 4;
+        o->w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y / s->c.p_s;
+        o->t_start[e] = s->S;
+        o->flags[e] = 0;
+        return;
+    }
+    /* H event: real minus subtraction, kinematics from the II map with j = 2 */
+    double xmin = m2 / s->S;
+    double x = xmin + (1.0 - xmin) * u1[0], sbar = m2 / x;
+    double YH = 0.5 * log(s->S * x / m2), y = -YH + 2.0 * YH * u0[2];
+    double ea = exp(y) * sqrt(sbar / s->S), eb = exp(-y) * sqrt(sbar / s->S);
+    double v = (1.0 - x) * u1[1], ph = 2.0 * OR_PI * u1[2];
+    double Ea = 0.5 * ea * s->sqrtS, Eb = 0.5 * eb * s->sqrtS;
+    double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+    double kt0 = sqrt(v * (1.0 - x - v) * sbar);
+    double J[4];
+    for (int k = 0; k < 4; ++k) J[k] = (1.0 - x - v) * A[k] + v * B[k];
+    J[1] -= kt0 * cos(ph);
+    J[2] -= kt0 * sin(ph);
+    double pZ[4];
+    for (int k = 0; k < 4; ++k) pZ[k] = A[k] + B[k] - J[k];
+    double ubar = -2.0 * (A[0] * J[0] - A[1] * J[1] - A[2] * J[2] - A[3] * J[3]);
+    double tbar = -2.0 * (B[0] * J[0] - B[1] * J[1] - B[2] * J[2] - B[3] * J[3]);
+    double csub[30], W = 0.0;
+    int pa[30], pb[30], kind[30];
+    int q = 0;
+    for (int f = 1; f <= nf; ++f) {
+        double mb = mborn2(s, f), rs;
+        or_nlo_rs(s, 0, sbar, tbar, ubar, mb, &rs);
+        pa[q] = f; pb[q] = -f; kind[q] = 0; csub[q++] = rs;
+        pa[q] = -f; pb[q] = f; kind[q] = 0; csub[q++] = rs;
+        or_nlo_rs(s, 1, sbar, tbar, ubar, mb, &rs);
+        pa[q] = 21; pb[q] = f; kind[q] = 1; csub[q++] = rs;
+        pa[q] = 21; pb[q] = -f; kind[q] = 1; csub[q++] = rs;
+        or_nlo_rs(s, 1, sbar, ubar, tbar, mb, &rs);
+        pa[q] = f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
+        pa[q] = -f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
+    }
+    for (int k = 0; k < q; ++k) {
+        csub[k] *= xfp(s, pa[k], ea, q2) * xfp(s, pb[k], eb, q2) / (16.0 * OR_PI * m2);
+        W += fabs(csub[k]);
+    }
+    double target = u0[1] * W, cum = 0.0;
+    int sel = q - 1;
+    for (int k = 0; k < q; ++k) {
+        cum += fabs(csub[k]);
+        if (target < cum) { sel = k; break; }
+    }
+    int a = pa[sel], b = pb[sel];
+    int ca, aa, cb, ab, jp, cj, aj;
+    if (kind[sel] == 0) {
+        /* q qbar -> Z g: quark colour 1, antiquark anticolour 2, gluon (1, 2) */
+        ca = a > 0 ? 1 : 0; aa = a > 0 ? 0 : 2;
+        cb = b > 0 ? 1 : 0; ab = b > 0 ? 0 : 2;
+        jp = 21; cj = 1; aj = 2;
+    } else {
+        int qk = kind[sel] == 1 ? b : a; /* the incoming (anti)quark */
+        int cg = 1, ag = 2, cq, aq;
+        if (qk > 0) { cq = 2; aq = 0; cj = 1; aj = 0; }
+        else { cq = 0; aq = 1; cj = 0; aj = 2; }
+        jp = qk;
+        if (kind[sel] == 1) { ca = cg; aa = ag; cb = cq; ab = aq; }
+        else { ca = cq; aa = aq; cb = cg; ab = ag; }
+    }
+    put(o, e, 0, A, a, ca, aa, -1);
+    put(o, e, 1, B, b, cb, ab, -1);
+    put(o, e, 2, J, jp, cj, aj, 1);
+    double em[4], ep[4];
+    decay_z(pZ, m, u0[3], u1[3], em, ep);
+    put(o, e, 3, em, 11, 0, 0, 1);
+    put(o, e, 4, ep, -11, 0, 0, 1);
+    o->n[e] = 5;
+    o->w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * YH * (1.0 - xmin) * (1.0 - x) / (1.0 - s->c.p_s);
+    o->t_start[e] = s->S;
+    o->flags[e] = OR_F_HEVENT;
+}
+
+int or_hard_events(const or_state* s, int64_t first_id, int64_t n, uint64_t seed, or_events* out) {
+    for (int64_t e = 0; e < n; ++e) {
+        int64_t id = first_id + e;
+        out->id[e] = id;
+        clear_counters(out, e);
+        if (s->c.process == 0) gen_ee(s, id, seed, out, e);
+        else if (s->c.process == 1) gen_lo(s, id, seed, out, e);
+        else gen_nlo(s, id, seed, out, e);
+    }
+    return 0;
+}

@@ -1,0 +1,114 @@
+/*
+ * CPU oracle for the GAPS-2 dipole shower (arXiv:2511.19633).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded FP64
+ * implementation of the shower's veto algorithm written from the paper
+ * (section 2, appendix A, appendix B, appendix C).  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It shares
+ * no source with the GPU library: the two only see the same input tables (the
+ * toy PDF grid and the workload constants).
+ *
+ * Event records are structure-of-arrays, slot-major: field[slot * cap + e].
+ *
+ * Parity status of each part (see the tests for the pins):
+ *   Philox4x32-10 ............ pinned (Random123 known-answer vectors)
+ *   alpha_s, PDF interpolation  pinned (RGE property, library interpolator)
+ *   FF/FI/IF/II maps, II boost  pinned (CS variables recomputed from momenta,
+ *                               masslessness, momentum conservation, Lambda)
+ *   veto loop ................. pinned (no-emission closed form; first-emission
+ *                               CDF vs 2-D quadrature of the Sudakov integrands)
+ *   NLO pieces ................ pinned (printed B+V+I factor, B = int g,
+ *                               Li2 vs library, R-S identities)
+ *   observables ............... pinned (thrust/jets on hand-built events)
+ */
+#ifndef GAPS_ORACLE_H
+#define GAPS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int process;        /* 0 e+e- -> qq, 1 pp LO Z->ee, 2 pp NLO S/H */
+    int nf;             /* active flavours (5) */
+    double sqrt_s, t_cut, alphas_mz, mz, gz, sw2, gf, mc, mb;
+    double mll_min, mll_max, p_s;
+    const float* pdf;   /* [ntab][nq][nx] node values of x*f */
+    int nx, nq, ntab;
+    double lnx0, lnx1, lnq0, lnq1;
+    double over_scale;  /* multiplies every channel overestimate (1 default) */
+} or_config;
+
+typedef struct {
+    int64_t* id; double* w; double* t_start; int32_t* n; uint32_t* flags;
+    double *E, *px, *py, *pz;
+    int32_t *pid, *col, *acol; int8_t* status;
+    uint32_t *n_cycles, *n_trials, *n_accept, *n_viol; /* may be NULL */
+    double* t1;                                         /* may be NULL */
+    int32_t max_slots; int64_t cap;
+} or_events;
+
+/* per-event flags */
+#define OR_F_OVERFLOW 1u
+#define OR_F_COLOUR   2u
+#define OR_F_NAN      4u
+#define OR_F_FALLBACK 8u
+#define OR_F_VIOL     16u
+#define OR_F_HARDFAIL 32u
+#define OR_F_HEVENT   64u
+#define OR_F_MAXCYC   128u
+
+typedef struct or_state or_state;
+
+or_state* or_init(const or_config* cfg);
+void or_free(or_state* s);
+
+/* counter-based generator, Philox4x32-10 */
+void or_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+double or_alphas(const or_state* s, double t);
+double or_pdf_xf(const or_state* s, int tab, double x, double q2);
+int or_pdf_table(int pid);
+
+/* overestimate table: or_bounds_shape gives (nent, nbin); copy out */
+void or_bounds_shape(int* nent, int* nbin);
+void or_bounds(const or_state* s, double* out);
+double or_lo_wmax(const or_state* s);
+
+/* hard events for ids first_id .. first_id+n-1 into out[0..n-1] */
+int or_hard_events(const or_state* s, int64_t first_id, int64_t n, uint64_t seed,
+                   or_events* out);
+
+/* shower events in[0..n-1] into out[0..n-1] on nthreads threads (1 = serial) */
+int or_shower(const or_state* s, const or_events* in, int64_t n, uint64_t seed,
+              or_events* out, int nthreads);
+
+/* kinematic maps, exposed for the identity tests.
+ * type: 0 FF, 1 FI, 2 IF, 3 II.  pe, ps: emitter/spectator before (E,px,py,pz).
+ * vars: FF (z, y), FI (z, x), IF (x, u), II (x, v); phi azimuth.
+ * out: new emitter, emitted, spectator (3 x 4 doubles).
+ * For II the boost acts on nrest extra momenta in-place (rest, nrest x 4). */
+void or_map(int type, const double pe[4], const double ps[4], double v1, double v2,
+            double phi, double out[12], double* rest, int nrest);
+/* IF/II: (z, t, s) -> CS variables (x, u or v) */
+void or_is_vars(int type, double z, double t, double s, double* x, double* uv);
+
+/* per-event observables: see observables.c for the layout */
+int or_n_obs(void);
+int or_observables(const or_state* s, const or_events* ev, int64_t n, double* obs);
+
+/* NLO building blocks exposed for the pins */
+double or_li2(double x);
+double or_nlo_bvi_factor(const or_state* s);
+double or_nlo_aqq(const or_state* s);
+double or_nlo_bqq(const or_state* s, double eta);
+double or_nlo_gqq(const or_state* s, double x);
+void or_nlo_rs(const or_state* s, int kind, double sbar, double tbar, double ubar,
+               double mborn2, double* r_minus_s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,212 @@
+"""ctypes binding of the CPU oracle.  TEST INFRASTRUCTURE ONLY: loaded by the
+tests, the smoke check and the CPU-baseline leg of the benchmark, never by the
+GPU library or its binding."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from gapsinputs import records
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build():
+    subprocess.check_call(["sh", os.path.join(_HERE, "build.sh")])
+
+
+class OrConfig(C.Structure):
+    _fields_ = [
+        ("process", C.c_int), ("nf", C.c_int),
+        ("sqrt_s", C.c_double), ("t_cut", C.c_double), ("alphas_mz", C.c_double),
+        ("mz", C.c_double), ("gz", C.c_double), ("sw2", C.c_double), ("gf", C.c_double),
+        ("mc", C.c_double), ("mb", C.c_double),
+        ("mll_min", C.c_double), ("mll_max", C.c_double), ("p_s", C.c_double),
+        ("pdf", C.POINTER(C.c_float)), ("nx", C.c_int), ("nq", C.c_int), ("ntab", C.c_int),
+        ("lnx0", C.c_double), ("lnx1", C.c_double), ("lnq0", C.c_double), ("lnq1", C.c_double),
+        ("over_scale", C.c_double),
+    ]
+
+
+class OrEvents(C.Structure):
+    _fields_ = [
+        ("id", C.c_void_p), ("w", C.c_void_p), ("t_start", C.c_void_p), ("n", C.c_void_p),
+        ("flags", C.c_void_p),
+        ("E", C.c_void_p), ("px", C.c_void_p), ("py", C.c_void_p), ("pz", C.c_void_p),
+        ("pid", C.c_void_p), ("col", C.c_void_p), ("acol", C.c_void_p), ("status", C.c_void_p),
+        ("n_cycles", C.c_void_p), ("n_trials", C.c_void_p), ("n_accept", C.c_void_p),
+        ("n_viol", C.c_void_p), ("t1", C.c_void_p),
+        ("max_slots", C.c_int32), ("cap", C.c_int64),
+    ]
+
+
+def _lib():
+    if not os.path.exists(_LIB):
+        build()
+    lib = C.CDLL(_LIB)
+    lib.or_init.restype = C.c_void_p
+    lib.or_init.argtypes = [C.POINTER(OrConfig)]
+    lib.or_free.argtypes = [C.c_void_p]
+    lib.or_philox4x32.argtypes = [C.POINTER(C.c_uint32)] * 3
+    lib.or_alphas.restype = C.c_double
+    lib.or_alphas.argtypes = [C.c_void_p, C.c_double]
+    lib.or_pdf_xf.restype = C.c_double
+    lib.or_pdf_xf.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
+    lib.or_bounds_shape.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.or_bounds.argtypes = [C.c_void_p, C.c_void_p]
+    lib.or_lo_wmax.restype = C.c_double
+    lib.or_lo_wmax.argtypes = [C.c_void_p]
+    lib.or_hard_events.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, C.POINTER(OrEvents)]
+    lib.or_shower.argtypes = [C.c_void_p, C.POINTER(OrEvents), C.c_int64, C.c_uint64,
+                              C.POINTER(OrEvents), C.c_int]
+    lib.or_map.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                           C.c_void_p, C.c_void_p, C.c_int]
+    lib.or_is_vars.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.or_n_obs.restype = C.c_int
+    lib.or_observables.argtypes = [C.c_void_p, C.POINTER(OrEvents), C.c_int64, C.c_void_p]
+    for name in ("or_li2",):
+        getattr(lib, name).restype = C.c_double
+        getattr(lib, name).argtypes = [C.c_double]
+    for name in ("or_nlo_bvi_factor", "or_nlo_aqq"):
+        getattr(lib, name).restype = C.c_double
+        getattr(lib, name).argtypes = [C.c_void_p]
+    for name in ("or_nlo_bqq", "or_nlo_gqq"):
+        getattr(lib, name).restype = C.c_double
+        getattr(lib, name).argtypes = [C.c_void_p, C.c_double]
+    lib.or_nlo_rs.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                              C.POINTER(C.c_double)]
+    return lib
+
+
+LIB = None
+
+
+def lib():
+    global LIB
+    if LIB is None:
+        LIB = _lib()
+    return LIB
+
+
+def philox4x32(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().or_philox4x32(c, k, o)
+    return list(o)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def events_struct(ev: records.Events) -> OrEvents:
+    s = OrEvents()
+    for name in ev.fields():
+        setattr(s, name, _ptr(getattr(ev, name)))
+    s.max_slots = ev.max_slots
+    s.cap = ev.cap
+    return s
+
+
+class Oracle:
+    """One configured oracle instance (keeps the config arrays alive)."""
+
+    def __init__(self, cfg: dict, over_scale: float = 1.0):
+        self._pdf = np.ascontiguousarray(cfg["pdf"], dtype=np.float32)
+        c = OrConfig()
+        for name, _ in OrConfig._fields_:
+            if name in ("pdf",):
+                continue
+            if name in cfg:
+                setattr(c, name, cfg[name])
+        c.nf = cfg.get("nf", 5)
+        c.pdf = self._pdf.ctypes.data_as(C.POINTER(C.c_float))
+        c.over_scale = over_scale
+        self.cfg = cfg
+        self._c = c
+        self.h = lib().or_init(C.byref(c))
+
+    def __del__(self):
+        if getattr(self, "h", None) and LIB is not None:
+            LIB.or_free(self.h)
+            self.h = None
+
+    def alphas(self, t):
+        return lib().or_alphas(self.h, t)
+
+    def pdf_xf(self, tab, x, q2):
+        return lib().or_pdf_xf(self.h, tab, x, q2)
+
+    def bounds(self):
+        ne, nb = C.c_int(), C.c_int()
+        lib().or_bounds_shape(C.byref(ne), C.byref(nb))
+        out = np.zeros((ne.value, nb.value), dtype=np.float64)
+        lib().or_bounds(self.h, _ptr(out))
+        return out
+
+    def lo_wmax(self):
+        return lib().or_lo_wmax(self.h)
+
+    def hard_events(self, first_id, n, seed, max_slots=128):
+        ev = records.Events(n, max_slots)
+        s = events_struct(ev)
+        lib().or_hard_events(self.h, first_id, n, seed, C.byref(s))
+        return ev
+
+    def shower(self, ev_in: records.Events, seed, nthreads=1, max_slots=None):
+        out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
+        si, so = events_struct(ev_in), events_struct(out)
+        lib().or_shower(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads)
+        return out
+
+    def observables(self, ev: records.Events):
+        nobs = lib().or_n_obs()
+        obs = np.zeros((ev.cap, nobs), dtype=np.float64)
+        s = events_struct(ev)
+        lib().or_observables(self.h, C.byref(s), ev.cap, _ptr(obs))
+        return obs
+
+    # NLO pieces
+    def li2(self, x):
+        return lib().or_li2(x)
+
+    def bvi_factor(self):
+        return lib().or_nlo_bvi_factor(self.h)
+
+    def aqq(self):
+        return lib().or_nlo_aqq(self.h)
+
+    def bqq(self, eta):
+        return lib().or_nlo_bqq(self.h, eta)
+
+    def gqq(self, x):
+        return lib().or_nlo_gqq(self.h, x)
+
+    def rs(self, kind, sbar, tbar, ubar, mborn2):
+        r = C.c_double()
+        lib().or_nlo_rs(self.h, kind, sbar, tbar, ubar, mborn2, C.byref(r))
+        return r.value
+
+
+def kin_map(typ, pe, ps, v1, v2, phi, rest=None):
+    pe = np.ascontiguousarray(pe, dtype=np.float64)
+    ps = np.ascontiguousarray(ps, dtype=np.float64)
+    out = np.zeros(12)
+    nrest = 0
+    if rest is not None:
+        rest = np.ascontiguousarray(rest, dtype=np.float64).copy()
+        nrest = rest.shape[0]
+    lib().or_map(typ, _ptr(pe), _ptr(ps), v1, v2, phi, _ptr(out), _ptr(rest), nrest)
+    return out.reshape(3, 4), rest
+
+
+def is_vars(typ, z, t, s):
+    x, uv = C.c_double(), C.c_double()
+    lib().or_is_vars(typ, z, t, s, C.byref(x), C.byref(uv))
+    return x.value, uv.value

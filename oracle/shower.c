@@ -1,0 +1,618 @@
+/* CPU oracle: the dipole-shower veto algorithm (paper section 2 and appendices
+ * A and B), one event at a time, FP64.  Test infrastructure only. */
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle_int.h"
+
+enum { T_FF = 0, T_FI = 1, T_IF = 2, T_II = 3 };
+enum { SH_SOFT = 0, SH_FLAT = 1, SH_S1 = 2, SH_S3 = 3 };
+/* splitting families: final-state emitters, then backward (initial-state) steps */
+enum { K_QQG = 0, K_GGG = 1, K_GQQ = 2, K_A = 3, K_B = 4, K_C = 5, K_D = 6 };
+
+typedef struct {
+    int n, maxtag;
+    double p[OR_MAXM][4];
+    int pid[OR_MAXM], col[OR_MAXM], acol[OR_MAXM], st[OR_MAXM];
+} ev_t;
+
+typedef struct { int kern, shape, flav; double coefR, c; } term_t;
+
+typedef struct {
+    int i, k, side, type, alive, heavy;
+    double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
+    double zlo, zhi, omzlo, omzhi;
+    int nterm;
+    term_t term[12];
+    double c, invc;
+} chan_t;
+
+static double dot4(const double* a, const double* b) {
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+/* colours seen as if every parton were outgoing: an incoming parton's colour
+ * and anticolour swap roles */
+static int effc(const ev_t* e, int i) { return e->st[i] < 0 ? e->acol[i] : e->col[i]; }
+static int effa(const ev_t* e, int i) { return e->st[i] < 0 ? e->col[i] : e->acol[i]; }
+static void set_eff(ev_t* e, int i, int c, int a) {
+    if (e->st[i] < 0) { e->col[i] = a; e->acol[i] = c; }
+    else { e->col[i] = c; e->acol[i] = a; }
+}
+
+static int eta_bin(double eta) {
+    double dle = -OR_LNETA0 / OR_NB;
+    double b = floor((log(eta) - OR_LNETA0) / dle);
+    if (b < 0.0) return 0;
+    if (b > OR_NB - 1) return OR_NB - 1;
+    return (int)b;
+}
+
+static double shape_int(int sh, const chan_t* ch) {
+    switch (sh) {
+    case SH_SOFT: return log(ch->omzlo / ch->omzhi);
+    case SH_FLAT: return ch->zhi - ch->zlo;
+    case SH_S1: return log(ch->zhi / ch->omzhi) - log(ch->zlo / ch->omzlo);
+    default: return log(ch->zhi / ch->zlo);
+    }
+}
+
+static void shape_sample(int sh, const chan_t* ch, double I, double u, double* z, double* omz) {
+    switch (sh) {
+    case SH_SOFT: *omz = ch->omzlo * exp(-u * I); *z = 1.0 - *omz; break;
+    case SH_FLAT: *z = ch->zlo + u * (ch->zhi - ch->zlo); *omz = 1.0 - *z; break;
+    case SH_S1: {
+        double L = log(ch->zlo / ch->omzlo) + u * I;
+        double e = exp(-L);
+        *z = 1.0 / (1.0 + e);
+        *omz = e / (1.0 + e);
+        break;
+    }
+    default: *z = ch->zlo * exp(u * I); *omz = 1.0 - *z; break;
+    }
+}
+
+static double shape_val(int sh, double z, double omz) {
+    switch (sh) {
+    case SH_SOFT: return 1.0 / omz;
+    case SH_FLAT: return 1.0;
+    case SH_S1: return 1.0 / (z * omz);
+    default: return 1.0 / z;
+    }
+}
+
+static void add_term(chan_t* ch, int kern, int shape, int flav, double coefR) {
+    term_t* t = &ch->term[ch->nterm++];
+    t->kern = kern; t->shape = shape; t->flav = flav; t->coefR = coefR; t->c = 0.0;
+}
+
+/* Channel constants (dipole end i with spectator k on colour side `side`):
+ * invariant mass, momentum fractions, kinematic limit, the widest z range (at
+ * the cutoff), the overestimate terms and their integrals. */
+static void setup_channel(const or_state* S, const ev_t* e, int i, int side, int k, chan_t* ch) {
+    memset(ch, 0, sizeof(*ch));
+    ch->i = i; ch->k = k; ch->side = side;
+    int isE = e->st[i] < 0, isS = e->st[k] < 0;
+    ch->type = isE ? (isS ? T_II : T_IF) : (isS ? T_FI : T_FF);
+    ch->s = 2.0 * dot4(e->p[i], e->p[k]);
+    ch->eta = isE ? 2.0 * e->p[i][0] / S->sqrtS : 0.0;
+    ch->etak = isS ? 2.0 * e->p[k][0] / S->sqrtS : 0.0;
+    double tc = ch->type == T_FF ? S->c.t_cut : S->tc_is;
+    double s = ch->s, eta = ch->eta, etak = ch->etak, d;
+    if (!(s > 0.0)) return;
+    switch (ch->type) {
+    case T_FF: ch->tlim = s / 4.0; d = 4.0 * tc / s; break;
+    case T_FI: ch->tlim = s * (1.0 - etak) / (4.0 * etak); d = 4.0 * tc * etak / (s * (1.0 - etak)); break;
+    case T_IF: ch->tlim = s * (1.0 - eta) / (4.0 * eta); d = 4.0 * tc * eta / (s * (1.0 - eta)); break;
+    default: ch->tlim = s * (1.0 - eta) * (1.0 - eta) / (4.0 * eta);
+        d = 4.0 * tc * eta / (s * (1.0 - eta) * (1.0 - eta)); break;
+    }
+    ch->tcut = tc;
+    if (isE) {
+        int ap = abs(e->pid[i]);
+        if (ap == 4) ch->m2 = S->c.mc * S->c.mc;
+        if (ap == 5) ch->m2 = S->c.mb * S->c.mb;
+        if (ch->m2 > 0.0) {
+            ch->heavy = 1;
+            double th = ch->m2 + S->c.t_cut;
+            if (th > ch->tcut) ch->tcut = th;
+        }
+    }
+    if (!(d < 1.0) || !(ch->tlim > ch->tcut)) return;
+    ch->lntlim = log(ch->tlim);
+    ch->lntcut = log(ch->tcut);
+    double sq = sqrt(1.0 - d);
+    if (ch->type == T_FF || ch->type == T_FI) {
+        ch->zlo = 0.5 * d / (1.0 + sq);
+        ch->omzhi = ch->zlo;
+        ch->zhi = 1.0 - ch->zlo;
+        ch->omzlo = 1.0 - ch->zlo;
+    } else {
+        ch->omzhi = 0.5 * (1.0 - eta) * d / (1.0 + sq);
+        ch->zhi = 1.0 - ch->omzhi;
+        ch->zlo = (4.0 * eta + (1.0 - eta) * (1.0 - eta) * d) /
+                  (2.0 * ((1.0 + eta) + (1.0 - eta) * sq));
+        ch->omzlo = 1.0 - ch->zlo;
+    }
+    /* overestimate terms */
+    if (!isE) {
+        double R = 1.0;
+        if (ch->type == T_FI) R = S->bound[OR_ENT_FI(or_pdf_table(e->pid[k]))][eta_bin(etak)];
+        if (e->pid[i] == 21) {
+            add_term(ch, K_GGG, SH_SOFT, 0, OR_CA * R);
+            for (int f = 1; f <= S->c.nf; ++f) add_term(ch, K_GQQ, SH_FLAT, f, 0.5 * OR_TR * R);
+        } else {
+            add_term(ch, K_QQG, SH_SOFT, 0, 2.0 * OR_CF * R);
+        }
+    } else {
+        int bin = eta_bin(eta);
+        int sh2 = ch->type == T_II ? SH_S3 : SH_S1;
+        if (e->pid[i] == 21) {
+            add_term(ch, K_C, SH_S1, 0, S->bound[OR_ENT_S1(FAM_C, 0)][bin]);
+            static const int par[10] = {1, 2, 3, 4, 5, -1, -2, -3, -4, -5};
+            for (int m = 0; m < 10; ++m) {
+                int a = par[m];
+                if (abs(a) > S->c.nf) continue;
+                int T = or_pdf_table(a);
+                double R = ch->type == T_II ? S->bound[OR_ENT_S3(FAM_D, T)][bin]
+                                            : S->bound[OR_ENT_S1(FAM_D, T)][bin];
+                add_term(ch, K_D, sh2, a, R);
+            }
+        } else {
+            int T = or_pdf_table(e->pid[i]);
+            add_term(ch, K_A, SH_S1, 0, S->bound[OR_ENT_S1(FAM_A, T)][bin]);
+            double R = ch->type == T_II ? S->bound[OR_ENT_S3(FAM_B, T)][bin]
+                                        : S->bound[OR_ENT_S1(FAM_B, T)][bin];
+            add_term(ch, K_B, sh2, 0, R);
+        }
+    }
+    double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
+    double c = 0.0;
+    for (int m = 0; m < ch->nterm; ++m) {
+        term_t* t = &ch->term[m];
+        t->c = af * t->coefR * shape_int(t->shape, ch);
+        c += t->c;
+    }
+    if (!(c > 0.0)) return;
+    ch->c = c;
+    ch->invc = 1.0 / c;
+    ch->alive = 1;
+}
+
+/* channel list in (parton slot, side) order; returns -1 on a broken colour flow */
+static int build_channels(const or_state* S, const ev_t* e, chan_t* ch, int* nch) {
+    int m = 0;
+    for (int i = 0; i < e->n; ++i) {
+        if (e->col[i] == 0 && e->acol[i] == 0) continue;
+        for (int side = 0; side < 2; ++side) {
+            int tag = side == 0 ? effc(e, i) : effa(e, i);
+            if (!tag) continue;
+            int k = -1;
+            for (int j = 0; j < e->n; ++j) {
+                if (j == i) continue;
+                int other = side == 0 ? effa(e, j) : effc(e, j);
+                if (other == tag) { k = j; break; }
+            }
+            if (k < 0) return -1;
+            setup_channel(S, e, i, side, k, &ch[m++]);
+        }
+    }
+    *nch = m;
+    return 0;
+}
+
+/* transverse momentum of size sqrt(tp) at azimuth phi, orthogonal to pa and pb */
+static void kperp(const double* pa, const double* pb, double tp, double phi, double* kt) {
+    double pab = dot4(pa, pb);
+    double na = sqrt(pa[1] * pa[1] + pa[2] * pa[2] + pa[3] * pa[3]);
+    double nb = sqrt(pb[1] * pb[1] + pb[2] * pb[2] + pb[3] * pb[3]);
+    double d[3];
+    for (int m = 0; m < 3; ++m) d[m] = pb[m + 1] / nb - pa[m + 1] / na;
+    int ax = 0;
+    double best = fabs(d[0]);
+    for (int m = 1; m < 3; ++m)
+        if (fabs(d[m]) < best) { best = fabs(d[m]); ax = m; }
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    r[ax + 1] = 1.0;
+    double ra = dot4(r, pa), rb = dot4(r, pb);
+    double n1[4];
+    for (int m = 0; m < 4; ++m) n1[m] = r[m] - rb / pab * pa[m] - ra / pab * pb[m];
+    double n1n = sqrt(-dot4(n1, n1));
+    for (int m = 0; m < 4; ++m) n1[m] /= n1n;
+    double A[4] = {pa[0], -pa[1], -pa[2], -pa[3]};
+    double B[4] = {pb[0], -pb[1], -pb[2], -pb[3]};
+    double C[4] = {n1[0], -n1[1], -n1[2], -n1[3]};
+    double n2[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        int cc[3], q = 0;
+        for (int m = 0; m < 4; ++m)
+            if (m != mu) cc[q++] = m;
+        int c0 = cc[0], c1 = cc[1], c2 = cc[2];
+        double det = A[c0] * (B[c1] * C[c2] - B[c2] * C[c1]) -
+                     A[c1] * (B[c0] * C[c2] - B[c2] * C[c0]) +
+                     A[c2] * (B[c0] * C[c1] - B[c1] * C[c0]);
+        n2[mu] = (mu & 1) ? -det : det;
+    }
+    double n2n = sqrt(-dot4(n2, n2));
+    for (int m = 0; m < 4; ++m) n2[m] /= n2n;
+    double kt0 = sqrt(tp), cp = cos(phi), sp = sin(phi);
+    for (int m = 0; m < 4; ++m) kt[m] = kt0 * (cp * n1[m] + sp * n2[m]);
+}
+
+/* II recoil: the Lorentz transformation of appendix B.5 mapping K' onto K,
+ * applied to one momentum */
+static void ii_lambda(const double* Kp, const double* K, double* p) {
+    double KK[4];
+    for (int m = 0; m < 4; ++m) KK[m] = K[m] + Kp[m];
+    double KK2 = dot4(KK, KK), Kp2 = dot4(Kp, Kp);
+    double c1 = 2.0 * dot4(KK, p) / KK2;
+    double c2 = 2.0 * dot4(Kp, p) / Kp2;
+    for (int m = 0; m < 4; ++m) p[m] = p[m] - c1 * KK[m] + c2 * K[m];
+}
+
+/* IF and II: Catani-Seymour variables from the shower's (z, t) (appendix B.4
+ * and B.5).  The IF x is written as 2z(1-z)/((1-z+r)(1+sqrt(1-d))), an exact
+ * rearrangement of the printed root that does not cancel at small r. */
+static void is_vars(int type, double z, double omz, double t, double s, double* x, double* uv) {
+    double r = t / s;
+    if (type == T_IF) {
+        double D = omz + r;
+        double dd = 4.0 * r * z * omz / (D * D);
+        *x = 2.0 * z * omz / (D * (1.0 + sqrt(1.0 - dd)));
+    } else {
+        *x = z * omz / (omz + r);
+    }
+    *uv = *x * r / omz;
+}
+
+void or_is_vars(int type, double z, double t, double s, double* x, double* uv) {
+    is_vars(type, z, 1.0 - z, t, s, x, uv);
+}
+
+/* Momenta after the emission; out = {emitter', emitted, spectator'}. */
+static void do_map(int type, const double* pe, const double* ps, double s, double z, double omz,
+                   double v1, double v2, double phi, double* pi, double* pj, double* pk) {
+    double kt[4], tp;
+    if (type == T_FF) { /* v1 = y */
+        double y = v1;
+        tp = z * omz * y * s;
+        kperp(pe, ps, tp, phi, kt);
+        for (int m = 0; m < 4; ++m) {
+            pi[m] = z * pe[m] + y * omz * ps[m] + kt[m];
+            pj[m] = omz * pe[m] + y * z * ps[m] - kt[m];
+            pk[m] = (1.0 - y) * ps[m];
+        }
+    } else if (type == T_FI) { /* v1 = x, v2 = 1 - x */
+        double x = v1, omx = v2;
+        tp = z * omz * omx / x * s;
+        kperp(pe, ps, tp, phi, kt);
+        double a = omz * omx / x, b = z * omx / x;
+        for (int m = 0; m < 4; ++m) {
+            pi[m] = z * pe[m] + a * ps[m] + kt[m];
+            pj[m] = omz * pe[m] + b * ps[m] - kt[m];
+            pk[m] = ps[m] / x;
+        }
+    } else if (type == T_IF) { /* v1 = x, v2 = u */
+        double x = v1, u = v2, omx = 1.0 - x;
+        tp = u * (1.0 - u) * omx / x * s;
+        kperp(pe, ps, tp, phi, kt);
+        double a = (1.0 - u) * omx / x, b = u * omx / x;
+        for (int m = 0; m < 4; ++m) {
+            pi[m] = pe[m] / x;
+            pj[m] = a * pe[m] + u * ps[m] - kt[m];
+            pk[m] = b * pe[m] + (1.0 - u) * ps[m] + kt[m];
+        }
+    } else { /* II: v1 = x, v2 = v */
+        double x = v1, v = v2;
+        tp = v * (1.0 - x - v) / x * s;
+        kperp(pe, ps, tp, phi, kt);
+        double a = (1.0 - x - v) / x;
+        for (int m = 0; m < 4; ++m) {
+            pi[m] = pe[m] / x;
+            pj[m] = a * pe[m] + v * ps[m] - kt[m];
+            pk[m] = ps[m];
+        }
+    }
+}
+
+void or_map(int type, const double pe[4], const double ps[4], double v1, double v2, double phi,
+            double out[12], double* rest, int nrest) {
+    double s = 2.0 * dot4(pe, ps);
+    double z = 0.0, omz = 0.0, a1 = v1, a2 = v2;
+    if (type == T_FF || type == T_FI) { z = v1; omz = 1.0 - v1; a1 = v2; a2 = 1.0 - v2; }
+    if (type == T_FF) a2 = 0.0;
+    do_map(type, pe, ps, s, z, omz, a1, a2, phi, out, out + 4, out + 8);
+    if (type == T_II) {
+        double Kp[4], K[4];
+        for (int m = 0; m < 4; ++m) {
+            Kp[m] = pe[m] + ps[m];
+            K[m] = out[m] + out[8 + m] - out[4 + m];
+        }
+        for (int q = 0; q < nrest; ++q) ii_lambda(Kp, K, rest + 4 * q);
+    }
+}
+
+typedef struct {
+    int ok;
+    double x, omx, y, uv, w;
+} veto_t;
+
+/* acceptance weight of the winner trial (term tm, scale t, momentum fraction z) */
+static veto_t weight(const or_state* S, const ev_t* e, const chan_t* ch, const term_t* tm,
+                     double t, double z, double omz) {
+    veto_t r;
+    memset(&r, 0, sizeof(r));
+    double W = 0.0, s = ch->s;
+    if (ch->type == T_FF) {
+        double y = t / (z * omz * s);
+        if (!(y < 1.0)) return r;
+        double den1 = omz + z * y;
+        double P;
+        if (tm->kern == K_QQG) P = OR_CF * (2.0 / den1 - (1.0 + z));
+        else if (tm->kern == K_GGG) P = 0.5 * OR_CA * (2.0 / den1 - 2.0 + z * omz);
+        else P = 0.5 * OR_TR * (1.0 - 2.0 * z * omz);
+        W = (1.0 - y) * P;
+        r.y = y;
+    } else if (ch->type == T_FI) {
+        double kap = t / (z * omz * s);
+        double x = 1.0 / (1.0 + kap), omx = kap * x;
+        if (!(x > ch->etak)) return r;
+        double den1 = omz + omx;
+        double P;
+        if (tm->kern == K_QQG) P = OR_CF * (2.0 / den1 - (1.0 + z));
+        else if (tm->kern == K_GGG) P = 0.5 * OR_CA * (2.0 / den1 - 2.0 + z * omz);
+        else P = 0.5 * OR_TR * (1.0 - 2.0 * z * omz);
+        int Tk = or_pdf_table(e->pid[ch->k]);
+        double den = or_pdf_f(S, Tk, ch->etak, t);
+        double pr = den > 0.0 ? or_pdf_f(S, Tk, ch->etak / x, t) / den : 0.0;
+        W = P * pr;
+        r.x = x; r.omx = omx;
+    } else {
+        double x, uv;
+        is_vars(ch->type, z, omz, t, s, &x, &uv);
+        if (!(x > ch->eta)) return r;
+        if (ch->type == T_IF && !(uv < 1.0)) return r;
+        double omx = 1.0 - x, P, J;
+        int Ti = or_pdf_table(e->pid[ch->i]);
+        int Tnum, Tden;
+        if (ch->type == T_IF) {
+            J = 1.0 / (uv + x - 2.0 * uv * x);
+            switch (tm->kern) {
+            case K_A: P = OR_CF * (2.0 / (omx + uv) - (1.0 + x)); break;
+            case K_B: P = OR_TR * (1.0 - 2.0 * x * omx); break;
+            case K_C: P = OR_CA * (1.0 / (omx + uv) + omx / x - 1.0 + x * omx); break;
+            default: P = OR_CF * (x + 2.0 * omx / x); break;
+            }
+        } else {
+            J = 1.0 / z;
+            switch (tm->kern) {
+            case K_A: P = OR_CF * (2.0 / omx - (1.0 + x)); break;
+            case K_B: P = OR_TR * (1.0 - 2.0 * x * omx); break;
+            case K_C: P = OR_CA * (1.0 / omx + omx / x - 1.0 + x * omx); break;
+            default: P = OR_CF * (x + 2.0 * omx / x); break;
+            }
+        }
+        switch (tm->kern) {
+        case K_A: Tnum = Ti; Tden = Ti; break;
+        case K_B: Tnum = 0; Tden = Ti; break;
+        case K_C: Tnum = 0; Tden = 0; break;
+        default: Tnum = or_pdf_table(tm->flav); Tden = 0; break;
+        }
+        double den = or_pdf_f(S, Tden, ch->eta, t);
+        double pr = den > 0.0 ? or_pdf_f(S, Tnum, ch->eta / x, t) / den : 0.0;
+        double hf = ch->heavy ? (t - ch->m2) / t : 1.0;
+        W = J * P * pr * hf;
+        r.x = x; r.omx = omx; r.uv = uv;
+    }
+    double over = S->c.over_scale * tm->coefR * shape_val(tm->shape, z, omz);
+    r.w = or_alphas(S, t) / S->as_over * W / over;
+    r.ok = 1;
+    return r;
+}
+
+/* apply the accepted emission: momenta, flavours and colour tags; j appended */
+static void emit(const or_state* S, ev_t* e, const chan_t* ch, const term_t* tm, double z,
+                 double omz, const veto_t* v, double phi) {
+    int i = ch->i, k = ch->k, j = e->n;
+    double pe[4], ps[4], pi[4], pj[4], pk[4];
+    memcpy(pe, e->p[i], sizeof(pe));
+    memcpy(ps, e->p[k], sizeof(ps));
+    double a1 = 0.0, a2 = 0.0;
+    if (ch->type == T_FF) a1 = v->y;
+    else if (ch->type == T_FI) { a1 = v->x; a2 = v->omx; }
+    else { a1 = v->x; a2 = v->uv; }
+    do_map(ch->type, pe, ps, ch->s, z, omz, a1, a2, phi, pi, pj, pk);
+    if (ch->type == T_II) {
+        double Kp[4], K[4];
+        for (int m = 0; m < 4; ++m) { Kp[m] = pe[m] + ps[m]; K[m] = pi[m] + pk[m] - pj[m]; }
+        for (int q = 0; q < e->n; ++q)
+            if (q != i && q != k && e->st[q] > 0) ii_lambda(Kp, K, e->p[q]);
+    }
+    memcpy(e->p[i], pi, sizeof(pi));
+    memcpy(e->p[k], pk, sizeof(pk));
+    memcpy(e->p[j], pj, sizeof(pj));
+    e->st[j] = 1;
+    int ec = effc(e, i), ea = effa(e, i), jc = 0, ja = 0;
+    switch (tm->kern) {
+    case K_QQG: case K_GGG: case K_A: case K_C: {
+        int N = ++e->maxtag;
+        if (ch->side == 0) { set_eff(e, i, N, ea); jc = ec; ja = N; }
+        else { set_eff(e, i, ec, N); jc = N; ja = ea; }
+        e->pid[j] = 21;
+        break;
+    }
+    case K_GQQ: {
+        int f = tm->flav;
+        if (ch->side == 0) { e->pid[i] = f; set_eff(e, i, ec, 0); e->pid[j] = -f; jc = 0; ja = ea; }
+        else { e->pid[i] = -f; set_eff(e, i, 0, ea); e->pid[j] = f; jc = ec; ja = 0; }
+        break;
+    }
+    case K_B: {
+        int N = ++e->maxtag;
+        e->pid[j] = -e->pid[i];
+        if (ec == 0) { set_eff(e, i, N, ea); jc = 0; ja = N; }
+        else { set_eff(e, i, ec, N); jc = N; ja = 0; }
+        e->pid[i] = 21;
+        break;
+    }
+    default: { /* K_D */
+        int a = tm->flav;
+        if (a > 0) { set_eff(e, i, 0, ea); jc = ec; ja = 0; }
+        else { set_eff(e, i, ec, 0); jc = 0; ja = ea; }
+        e->pid[i] = a;
+        e->pid[j] = a;
+        break;
+    }
+    }
+    e->col[j] = jc;
+    e->acol[j] = ja;
+    e->n += 1;
+}
+
+static int finite4(const double* p) {
+    return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(p[3]);
+}
+
+static void shower_one(const or_state* S, const or_events* in, int64_t e_in, uint64_t seed,
+                       or_events* out, int64_t e_out, ev_t* ev, chan_t* ch) {
+    const int64_t ci = in->cap, co = out->cap;
+    int M = out->max_slots < OR_MAXM ? out->max_slots : OR_MAXM;
+    ev->n = in->n[e_in];
+    ev->maxtag = 0;
+    uint32_t flags = in->flags ? in->flags[e_in] : 0u;
+    for (int q = 0; q < ev->n; ++q) {
+        int64_t o = (int64_t)q * ci + e_in;
+        ev->p[q][0] = in->E[o]; ev->p[q][1] = in->px[o];
+        ev->p[q][2] = in->py[o]; ev->p[q][3] = in->pz[o];
+        ev->pid[q] = in->pid[o]; ev->col[q] = in->col[o]; ev->acol[q] = in->acol[o];
+        ev->st[q] = in->status[o];
+        if (ev->col[q] > ev->maxtag) ev->maxtag = ev->col[q];
+        if (ev->acol[q] > ev->maxtag) ev->maxtag = ev->acol[q];
+    }
+    int64_t id = in->id[e_in];
+    double T = in->t_start[e_in], lnT = log(T), t1 = 0.0;
+    uint32_t ncyc = 0, ntri = 0, nacc = 0, nviol = 0;
+    int nch = 0;
+    if (ev->n > M) flags |= OR_F_OVERFLOW;
+    else if (build_channels(S, ev, ch, &nch) < 0) flags |= OR_F_COLOUR;
+    else {
+        uint32_t cycle = 0;
+        for (;;) {
+            if (cycle >= OR_MAXCYC) { flags |= OR_F_MAXCYC; break; }
+            /* trial scales of every channel; the winner is the largest */
+            double best = -INFINITY;
+            int win = -1;
+            uint32_t curblk = 0xFFFFFFFFu;
+            double ub[4];
+            for (int c = 0; c < nch; ++c) {
+                const chan_t* C = &ch[c];
+                if (!C->alive) continue;
+                double Tch = T < C->tlim ? T : C->tlim;
+                double lnTch = lnT < C->lntlim ? lnT : C->lntlim;
+                if (!(Tch > C->tcut)) continue;
+                uint32_t slot = 2u * (uint32_t)C->i + (uint32_t)C->side;
+                if ((slot >> 2) != curblk) {
+                    curblk = slot >> 2;
+                    or_rng_block(seed, 0u, id, cycle, curblk, ub);
+                }
+                double lu = log(ub[slot & 3u]);
+                ntri += 1;
+                double key;
+                if (!C->heavy) key = lnTch + lu * C->invc;
+                else key = log(C->m2 + (Tch - C->m2) * exp(lu * C->invc));
+                if (key < C->lntcut) continue;
+                if (key > best) { best = key; win = c; }
+            }
+            if (win < 0) break;
+            double t = exp(best);
+            const chan_t* C = &ch[win];
+            double u[4];
+            or_rng_block(seed, 0u, id, cycle, 0xFFFFFFFFu, u);
+            /* splitting family and flavour in proportion to their overestimates */
+            double target = u[0] * C->c, cum = 0.0;
+            int sel = -1;
+            for (int m = 0; m < C->nterm; ++m) {
+                cum += C->term[m].c;
+                if (target < cum) { sel = m; break; }
+            }
+            if (sel < 0)
+                for (int m = C->nterm - 1; m >= 0; --m)
+                    if (C->term[m].c > 0.0) { sel = m; break; }
+            const term_t* tm = &C->term[sel];
+            double I = shape_int(tm->shape, C);
+            double z, omz;
+            shape_sample(tm->shape, C, I, u[1], &z, &omz);
+            double phi = 2.0 * OR_PI * u[2];
+            veto_t v = weight(S, ev, C, tm, t, z, omz);
+            if (v.ok && v.w > 1.0) { nviol += 1; flags |= OR_F_VIOL; }
+            if (v.ok && u[3] < v.w) {
+                if (ev->n + 1 > M) { flags |= OR_F_OVERFLOW; break; }
+                emit(S, ev, C, tm, z, omz, &v, phi);
+                nacc += 1;
+                if (t1 == 0.0) t1 = t;
+                int bad = 0;
+                for (int q = 0; q < ev->n; ++q) bad |= !finite4(ev->p[q]);
+                if (bad) { flags |= OR_F_NAN; cycle += 1; break; }
+                if (build_channels(S, ev, ch, &nch) < 0) { flags |= OR_F_COLOUR; cycle += 1; break; }
+            }
+            T = t;
+            lnT = best;
+            cycle += 1;
+        }
+        ncyc = cycle;
+    }
+    out->id[e_out] = id;
+    out->w[e_out] = in->w[e_in];
+    out->t_start[e_out] = in->t_start[e_in];
+    out->n[e_out] = ev->n;
+    if (out->flags) out->flags[e_out] = flags;
+    for (int q = 0; q < ev->n && q < out->max_slots; ++q) {
+        int64_t o = (int64_t)q * co + e_out;
+        out->E[o] = ev->p[q][0]; out->px[o] = ev->p[q][1];
+        out->py[o] = ev->p[q][2]; out->pz[o] = ev->p[q][3];
+        out->pid[o] = ev->pid[q]; out->col[o] = ev->col[q]; out->acol[o] = ev->acol[q];
+        out->status[o] = (int8_t)ev->st[q];
+    }
+    if (out->n_cycles) out->n_cycles[e_out] = ncyc;
+    if (out->n_trials) out->n_trials[e_out] = ntri;
+    if (out->n_accept) out->n_accept[e_out] = nacc;
+    if (out->n_viol) out->n_viol[e_out] = nviol;
+    if (out->t1) out->t1[e_out] = t1;
+}
+
+typedef struct {
+    const or_state* S;
+    const or_events* in;
+    or_events* out;
+    uint64_t seed;
+    int64_t lo, hi;
+} job_t;
+
+static void* run_job(void* arg) {
+    job_t* J = (job_t*)arg;
+    ev_t* ev = (ev_t*)malloc(sizeof(ev_t));
+    chan_t* ch = (chan_t*)malloc(sizeof(chan_t) * OR_MAXCH);
+    for (int64_t e = J->lo; e < J->hi; ++e) shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch);
+    free(ev);
+    free(ch);
+    return NULL;
+}
+
+int or_shower(const or_state* S, const or_events* in, int64_t n, uint64_t seed, or_events* out,
+              int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    job_t jobs[256];
+    pthread_t th[256];
+    for (int k = 0; k < nthreads; ++k) {
+        jobs[k].S = S; jobs[k].in = in; jobs[k].out = out; jobs[k].seed = seed;
+        jobs[k].lo = n * k / nthreads;
+        jobs[k].hi = n * (k + 1) / nthreads;
+    }
+    if (nthreads == 1) { run_job(&jobs[0]); return 0; }
+    for (int k = 0; k < nthreads; ++k) pthread_create(&th[k], NULL, run_job, &jobs[k]);
+    for (int k = 0; k < nthreads; ++k) pthread_join(th[k], NULL);
+    return 0;
+}
