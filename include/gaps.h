@@ -1,0 +1,173 @@
+/*
+ * libgaps: MI355X (gfx950) implementation of the GAPS-2 dipole parton shower
+ * (Seymour and Sule, "An NLO-Matched Initial and Final State Parton Shower on a
+ * GPU", arXiv:2511.19633).
+ *
+ * The library showers hard-process events one event per lane: the max-veto
+ * algorithm of section 2 (trial scales against overestimates, winner,
+ * accept/veto, emission), initial-state backward evolution guided by PDF
+ * ratios (appendix A), the FF/FI/IF/II kernels, kinematic maps and the II
+ * recoil transformation (appendix B), on LO or MC@NLO-style S/H inputs
+ * (appendix C).  Kinematics and weights are FP64.
+ *
+ * Conventions for every entry point:
+ *  - Device pointers point to memory on the current HIP device; host pointers
+ *    are marked as such.  The caller owns all buffers it passes; the library
+ *    owns only what gaps_init uploads plus its scratch space.
+ *  - Event records are structure-of-arrays, slot-major: a per-particle field
+ *    of event e, slot q lives at [q * cap + e]; per-event fields at [e].
+ *  - Calls taking a stream are asynchronous on that stream.  Argument and state
+ *    errors are reported synchronously by the return value; device-side
+ *    per-event problems are reported in the event's flags word.
+ *  - Results are a pure function of the inputs, the seed and the
+ *    configuration: the event id (not the array position) keys the random
+ *    numbers, so block size, grid size and batching never change an event.
+ */
+#ifndef GAPS_H
+#define GAPS_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gaps_ctx_s* gaps_ctx;
+
+typedef enum {
+    GAPS_OK = 0,
+    GAPS_EINVAL = -1,    /* bad argument (null pointer, size, layout) */
+    GAPS_ENOMEM = -2,    /* device allocation failed */
+    GAPS_EHIP = -3,      /* a HIP call failed */
+    GAPS_ECAPACITY = -4, /* a size exceeds what the context was built for */
+    GAPS_ESTATE = -5     /* call not valid in the current state */
+} gaps_status;
+
+/* per-event flag bits */
+#define GAPS_F_OVERFLOW 1u  /* an accepted emission would exceed max_slots */
+#define GAPS_F_COLOUR 2u    /* a colour line has no partner */
+#define GAPS_F_NAN 4u       /* a non-finite momentum appeared */
+#define GAPS_F_FALLBACK 8u  /* learned mode: bound violated, event re-run plain */
+#define GAPS_F_VIOL 16u     /* a veto weight exceeded one (counted in n_viol) */
+#define GAPS_F_HARDFAIL 32u /* the hard-event sampler found no event */
+#define GAPS_F_HEVENT 64u   /* NLO H (real-emission) event */
+#define GAPS_F_MAXCYC 128u  /* cycle guard reached */
+
+/* Physics configuration, read from host memory by gaps_init (section 4 and
+ * appendix C constants; the PDF grid stands in for the paper's LHAPDF set). */
+typedef struct {
+    int process;        /* 0: e+e- -> q qbar (final state only)
+                           1: pp -> Z -> e+e- LO,  2: pp -> Z NLO S/H events */
+    int nf;             /* active quark flavours (5) */
+    double sqrt_s;      /* collider energy, GeV */
+    double t_cut;       /* shower cutoff on t = pT^2, GeV^2 */
+    double alphas_mz;   /* alpha_s(mZ^2), one-loop running */
+    double mz, gz;      /* Z mass and width, GeV */
+    double sw2, gf;     /* sin^2(theta_W), Fermi constant */
+    double mc, mb;      /* charm and bottom masses (heavy-quark measure) */
+    double mll_min, mll_max; /* LO dilepton mass window, GeV */
+    double p_s;         /* NLO: probability of generating an S event */
+    const float* pdf_xf; /* HOST [ntab][nq][nx] node values of x*f(x, Q^2) */
+    int nx, nq, ntab;   /* grid sizes; ntab must be 8 (g d u s c b dbar ubar) */
+    double lnx0, lnx1, lnq0, lnq1; /* node ranges in ln x and ln Q^2 */
+    double over_scale;  /* multiplies every overestimate (1 = default) */
+} gaps_config;
+
+/* Event record: DEVICE pointers.  The optional counters may be NULL. */
+typedef struct {
+    int64_t* id;         /* event id: keys the random numbers */
+    double* w;           /* event weight (signed for NLO) */
+    double* t_start;     /* starting scale of the evolution, GeV^2 */
+    int32_t* n;          /* particles in the record */
+    uint32_t* flags;     /* GAPS_F_* */
+    double *E, *px, *py, *pz;   /* [max_slots][cap] momenta, GeV */
+    int32_t *pid, *col, *acol;  /* [max_slots][cap] PDG id, colour tags */
+    int8_t* status;             /* [max_slots][cap] -1 incoming, +1 outgoing */
+    uint32_t *n_cycles, *n_trials, *n_accept, *n_viol; /* per-event counters */
+    double* t1;          /* scale of the first accepted emission (0 if none) */
+    int32_t max_slots;   /* slots per event (<= 256) */
+    int64_t cap;         /* events the arrays hold */
+} gaps_events;
+
+#define GAPS_MODE_PLAIN 0
+#define GAPS_MODE_LEARNED 1
+#define GAPS_MODE_LOG 2
+
+/* statistics accumulated by gaps_shower when params.stats != NULL
+ * (device array of GAPS_NSTATS unsigned 64-bit counters, caller-zeroed) */
+#define GAPS_ST_CYCLES 0      /* winner cycles, summed over events */
+#define GAPS_ST_TRIALS 1      /* channel trials */
+#define GAPS_ST_ACCEPT 2      /* accepted emissions */
+#define GAPS_ST_VIOL 3        /* weights above one */
+#define GAPS_ST_LANE_ITERS 4  /* wave iterations x 64 (lane slots offered) */
+#define GAPS_ST_LANE_ACTIVE 5 /* lanes doing work in those iterations */
+#define GAPS_ST_FALLBACK 6    /* learned-mode events re-run plain */
+#define GAPS_ST_NULL 7        /* learned-mode cell boundary (null) winners */
+#define GAPS_NSTATS 8
+
+typedef struct {
+    int mode;            /* GAPS_MODE_* */
+    int block;           /* threads per block, multiple of 64 (0: 256) */
+    int grid;            /* blocks of the persistent launch (0: fill the GPU) */
+    int compact_every;   /* cycles between wave refills (0: 8) */
+    float* trial_log;    /* LOG mode: device [log_cap][5] floats */
+    int64_t log_cap;
+    unsigned long long* log_count; /* LOG mode: device counter */
+    unsigned long long* stats;     /* optional device [GAPS_NSTATS] */
+} gaps_params;
+
+/* Create a context: validates the configuration, uploads the PDF grid and
+ * computes the overestimate table on the device (appendix A.2 procedure).
+ * Synchronous.  Returns GAPS_EINVAL for a bad configuration. */
+gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out);
+
+/* Release every device allocation of the context. */
+gaps_status gaps_destroy(gaps_ctx ctx);
+
+const char* gaps_strerror(gaps_status s);
+
+/* Hard events (appendix C; e+e- and LO by the workload definitions) for ids
+ * first_id .. first_id+n-1 into out[0..n-1].  out->cap >= n, max_slots >= 5. */
+gaps_status gaps_hard_events(gaps_ctx ctx, int64_t first_id, int64_t n, uint64_t seed,
+                             gaps_events* out, hipStream_t stream);
+
+/* Shower in[0..n-1] into out[0..n-1] (section 2, appendices A and B).
+ * in and out must not alias; out->max_slots bounds the final multiplicity
+ * (GAPS_F_OVERFLOW otherwise).  params may be NULL (plain mode, defaults). */
+gaps_status gaps_shower(gaps_ctx ctx, const gaps_events* in, int64_t n, const gaps_params* params,
+                        uint64_t seed, gaps_events* out, hipStream_t stream);
+
+/* Per-event observables (section 4.1): obs is device [n][12], layout as in
+ * the oracle's observables (Z pT, y, phi, phi*, jets; thrust and Durham y for
+ * e+e-). */
+gaps_status gaps_observables(gaps_ctx ctx, const gaps_events* ev, int64_t n, double* obs,
+                             hipStream_t stream);
+
+/* Weighted histogram of column col of obs (device [n][12]) with weights w
+ * (device [n], or NULL for unit weights): nbins uniform bins on [lo, hi),
+ * device sumw/sumw2 [nbins] accumulated (caller zeroes them). */
+gaps_status gaps_histogram(gaps_ctx ctx, const double* obs, const double* w, int64_t n, int col,
+                           double lo, double hi, int nbins, double* sumw, double* sumw2,
+                           hipStream_t stream);
+
+/* Copy the overestimate table (72 entries x 48 eta bins, doubles) to HOST
+ * memory host_out.  Synchronous. */
+gaps_status gaps_bounds(gaps_ctx ctx, double* host_out);
+
+/* PDF evaluation x*f(tab, x, q2) for n device points (the grid lookup of the
+ * shower, exposed for tests and the lookup micro-benchmark). */
+gaps_status gaps_pdf_eval(gaps_ctx ctx, const int32_t* tab, const double* x, const double* q2,
+                          int64_t n, double* out, hipStream_t stream);
+
+/* Philox4x32-10 blocks: out[4*k..4*k+3] for counter (id[k], c2[k], c3[k]) and
+ * key (seed, stream id), all device arrays of length n. */
+gaps_status gaps_rng_blocks(uint64_t seed, uint32_t stream_id, const int64_t* id,
+                            const uint32_t* c2, const uint32_t* c3, int64_t n, uint32_t* out,
+                            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

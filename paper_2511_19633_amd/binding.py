@@ -1,0 +1,221 @@
+"""ctypes binding of libgaps (include/gaps.h).
+
+Argument marshalling only: torch tensors provide device memory and streams;
+every step of the shower runs in the library's HIP kernels.  Importing this
+module never falls back to anything else: if libgaps.so is missing or no GPU
+is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+from gapsinputs import records
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgaps.so")
+
+MODE_PLAIN, MODE_LEARNED, MODE_LOG = 0, 1, 2
+NSTATS = 8
+ST_CYCLES, ST_TRIALS, ST_ACCEPT, ST_VIOL, ST_LANE_ITERS, ST_LANE_ACTIVE, ST_FALLBACK, ST_NULL = range(8)
+NOBS = 12
+
+
+class GapsError(RuntimeError):
+    pass
+
+
+class GapsConfig(C.Structure):
+    _fields_ = [
+        ("process", C.c_int), ("nf", C.c_int),
+        ("sqrt_s", C.c_double), ("t_cut", C.c_double), ("alphas_mz", C.c_double),
+        ("mz", C.c_double), ("gz", C.c_double), ("sw2", C.c_double), ("gf", C.c_double),
+        ("mc", C.c_double), ("mb", C.c_double),
+        ("mll_min", C.c_double), ("mll_max", C.c_double), ("p_s", C.c_double),
+        ("pdf_xf", C.POINTER(C.c_float)), ("nx", C.c_int), ("nq", C.c_int), ("ntab", C.c_int),
+        ("lnx0", C.c_double), ("lnx1", C.c_double), ("lnq0", C.c_double), ("lnq1", C.c_double),
+        ("over_scale", C.c_double),
+    ]
+
+
+class GapsEvents(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in
+                ("id", "w", "t_start", "n", "flags", "E", "px", "py", "pz", "pid", "col", "acol",
+                 "status", "n_cycles", "n_trials", "n_accept", "n_viol", "t1")] + [
+        ("max_slots", C.c_int32), ("cap", C.c_int64)]
+
+
+class GapsParams(C.Structure):
+    _fields_ = [("mode", C.c_int), ("block", C.c_int), ("grid", C.c_int), ("compact_every", C.c_int),
+                ("trial_log", C.c_void_p), ("log_cap", C.c_int64), ("log_count", C.c_void_p),
+                ("stats", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GapsError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, u64 = C.c_void_p, C.c_int64, C.c_uint64
+        L.gaps_init.argtypes = [C.POINTER(GapsConfig), C.POINTER(vp)]
+        L.gaps_destroy.argtypes = [vp]
+        L.gaps_strerror.restype = C.c_char_p
+        L.gaps_strerror.argtypes = [C.c_int]
+        L.gaps_hard_events.argtypes = [vp, i64, i64, u64, C.POINTER(GapsEvents), vp]
+        L.gaps_shower.argtypes = [vp, C.POINTER(GapsEvents), i64, C.POINTER(GapsParams), u64,
+                                  C.POINTER(GapsEvents), vp]
+        L.gaps_observables.argtypes = [vp, C.POINTER(GapsEvents), i64, vp, vp]
+        L.gaps_histogram.argtypes = [vp, vp, vp, i64, C.c_int, C.c_double, C.c_double, C.c_int, vp, vp, vp]
+        L.gaps_bounds.argtypes = [vp, vp]
+        L.gaps_pdf_eval.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.gaps_rng_blocks.argtypes = [u64, C.c_uint32, vp, vp, vp, i64, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise GapsError(f"libgaps: {lib().gaps_strerror(status).decode()} ({status})")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+_TORCH = {np.int64: torch.int64, np.float64: torch.float64, np.int32: torch.int32,
+          np.uint32: torch.uint32, np.int8: torch.int8}
+
+
+class DeviceEvents:
+    """Event record in device memory (same layout as gapsinputs.records)."""
+
+    def __init__(self, cap: int, max_slots: int, device="cuda"):
+        self.cap, self.max_slots = int(cap), int(max_slots)
+        for name, dt in records.PER_EVENT + records.COUNTERS:
+            setattr(self, name, torch.zeros(self.cap, dtype=_TORCH[dt], device=device))
+        for name, dt in records.PER_SLOT:
+            setattr(self, name, torch.zeros((self.max_slots, self.cap), dtype=_TORCH[dt], device=device))
+
+    def fields(self):
+        return [n for n, _ in records.PER_EVENT + records.PER_SLOT + records.COUNTERS]
+
+    def struct(self) -> GapsEvents:
+        s = GapsEvents()
+        for name in self.fields():
+            setattr(s, name, getattr(self, name).data_ptr())
+        s.max_slots, s.cap = self.max_slots, self.cap
+        return s
+
+    @classmethod
+    def from_host(cls, ev: records.Events) -> "DeviceEvents":
+        d = cls(ev.cap, ev.max_slots)
+        for name in d.fields():
+            getattr(d, name).copy_(torch.from_numpy(np.ascontiguousarray(getattr(ev, name))))
+        return d
+
+    def to_host(self) -> records.Events:
+        ev = records.Events(self.cap, self.max_slots)
+        for name in self.fields():
+            getattr(ev, name)[...] = getattr(self, name).cpu().numpy()
+        return ev
+
+
+class Gaps:
+    """A configured libgaps context on the current device."""
+
+    def __init__(self, cfg: dict, over_scale: float = 1.0):
+        if not torch.cuda.is_available():
+            raise GapsError("libgaps needs a GPU; none is visible")
+        self._pdf = np.ascontiguousarray(cfg["pdf"], dtype=np.float32)
+        c = GapsConfig()
+        for name, _ in GapsConfig._fields_:
+            if name == "pdf_xf":
+                continue
+            if name in cfg:
+                setattr(c, name, cfg[name])
+        c.nf = cfg.get("nf", 5)
+        c.pdf_xf = self._pdf.ctypes.data_as(C.POINTER(C.c_float))
+        c.over_scale = over_scale
+        self.cfg = cfg
+        h = C.c_void_p()
+        torch.cuda.init()
+        _check(lib().gaps_init(C.byref(c), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gaps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bounds(self) -> np.ndarray:
+        out = np.zeros((72, 48), dtype=np.float64)
+        _check(lib().gaps_bounds(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def hard_events(self, first_id: int, n: int, seed: int, max_slots: int = 128, out=None,
+                    stream=None) -> DeviceEvents:
+        ev = out if out is not None else DeviceEvents(n, max_slots)
+        s = ev.struct()
+        _check(lib().gaps_hard_events(self.h, first_id, n, seed, C.byref(s), _stream(stream)))
+        return ev
+
+    def shower(self, ev_in: DeviceEvents, seed: int, n: int | None = None, out=None, max_slots=None,
+               mode=MODE_PLAIN, block=0, grid=0, compact_every=0, stats=None, trial_log=None,
+               log_count=None, stream=None) -> DeviceEvents:
+        n = ev_in.cap if n is None else n
+        ev_out = out if out is not None else DeviceEvents(n, max_slots or ev_in.max_slots)
+        p = GapsParams()
+        p.mode, p.block, p.grid, p.compact_every = mode, block, grid, compact_every
+        p.stats = stats.data_ptr() if stats is not None else None
+        if trial_log is not None:
+            p.trial_log = trial_log.data_ptr()
+            p.log_cap = trial_log.shape[0]
+            p.log_count = log_count.data_ptr()
+        si, so = ev_in.struct(), ev_out.struct()
+        _check(lib().gaps_shower(self.h, C.byref(si), n, C.byref(p), seed, C.byref(so), _stream(stream)))
+        return ev_out
+
+    def observables(self, ev: DeviceEvents, n: int | None = None, stream=None) -> torch.Tensor:
+        n = ev.cap if n is None else n
+        obs = torch.zeros((n, NOBS), dtype=torch.float64, device="cuda")
+        s = ev.struct()
+        _check(lib().gaps_observables(self.h, C.byref(s), n, _ptr(obs), _stream(stream)))
+        return obs
+
+    def histogram(self, obs: torch.Tensor, w, col: int, lo: float, hi: float, nbins: int, stream=None):
+        sw = torch.zeros(nbins, dtype=torch.float64, device="cuda")
+        sw2 = torch.zeros(nbins, dtype=torch.float64, device="cuda")
+        _check(lib().gaps_histogram(self.h, _ptr(obs), _ptr(w), obs.shape[0], col, lo, hi, nbins,
+                                    _ptr(sw), _ptr(sw2), _stream(stream)))
+        return sw, sw2
+
+    def pdf_eval(self, tab: torch.Tensor, x: torch.Tensor, q2: torch.Tensor, stream=None) -> torch.Tensor:
+        out = torch.zeros_like(x)
+        _check(lib().gaps_pdf_eval(self.h, _ptr(tab), _ptr(x), _ptr(q2), x.numel(), _ptr(out), _stream(stream)))
+        return out
+
+
+def rng_blocks(seed: int, stream_id: int, ids: torch.Tensor, c2: torch.Tensor, c3: torch.Tensor,
+               stream=None) -> torch.Tensor:
+    out = torch.zeros((ids.numel(), 4), dtype=torch.uint32, device="cuda")
+    _check(lib().gaps_rng_blocks(seed, stream_id, _ptr(ids), _ptr(c2), _ptr(c3), ids.numel(), _ptr(out),
+                                 _stream(stream)))
+    return out

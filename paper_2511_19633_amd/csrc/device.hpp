@@ -1,0 +1,552 @@
+// Device-side physics of the gfx950 shower: random numbers, coupling, PDF
+// lookup, channel constants, trial scales, veto weights and the kinematic maps
+// (arXiv:2511.19633 section 2, appendices A and B).  FP64 throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace gaps {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kCF = 4.0 / 3.0;
+constexpr double kCA = 3.0;
+constexpr double kTR = 0.5;
+constexpr double kNC = 3.0;
+
+// Overestimate table: 48 eta bins uniform in ln(eta) on [1e-6, 1); entries
+// FI[T], S1[family][T], S3[family][T] (T: PDF table, family A..D).
+constexpr int kNB = 48;
+constexpr double kLnEta0 = -13.815510557964274;  // ln(1e-6)
+constexpr int kNEnt = 72;
+__host__ __device__ constexpr int ent_fi(int T) { return T; }
+__host__ __device__ constexpr int ent_s1(int f, int T) { return 8 + 8 * f + T; }
+__host__ __device__ constexpr int ent_s3(int f, int T) { return 40 + 8 * f + T; }
+
+constexpr int kMaxSlots = 256;
+constexpr int kMaxTerms = 11;
+constexpr uint32_t kMaxCycles = 2000000u;
+
+enum : int { kFF = 0, kFI = 1, kIF = 2, kII = 3 };
+enum : int { kSoft = 0, kFlat = 1, kS1 = 2, kS3 = 3 };
+// splitting families: final-state q->qg, g->gg, g->qqbar; backward steps
+// A (q <- q, gluon emitted), B (q <- g), C (g <- g), D (g <- q)
+enum : int { kQQG = 0, kGGG = 1, kGQQ = 2, kA = 3, kB = 4, kC = 5, kD = 6 };
+enum : int { famA = 0, famB = 1, famC = 2, famD = 3 };
+
+enum : uint32_t {
+  fOverflow = 1u, fColour = 2u, fNaN = 4u, fFallback = 8u, fViol = 16u,
+  fHardFail = 32u, fHEvent = 64u, fMaxCyc = 128u
+};
+
+// Everything the kernels need, passed by value (kernel-argument segment).
+struct Cfg {
+  int process, nf, nx, nq;
+  double sqrt_s, S, t_cut, tc_is, alphas_mz, mz, gz, mz2, b0, as_over;
+  double mc2, mb2, tch_c, tch_b, ln_tc, ln_tcis, ln_tch_c, ln_tch_b;
+  double sw2, gf, mll_min, mll_max, p_s, over_scale;
+  double lnx0, lnx1, lnq0, lnq1, dlnx, dlnq;
+  double lo_wmax;
+  const float* pdf;      // [8][nq][nx]
+  const double* bound;   // [72][48]
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11), counter (id_lo, id_hi, c2, c3), key
+// (seed_lo, seed_hi ^ stream).
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1, uint32_t o[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  o[0] = c0; o[1] = c1; o[2] = c2; o[3] = c3;
+}
+
+__device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386963e-10; }
+
+__device__ __forceinline__ void rng4(uint64_t seed, uint32_t stream, int64_t id, uint32_t c2,
+                                     uint32_t c3, double u[4]) {
+  uint32_t o[4];
+  philox((uint32_t)(uint64_t)id, (uint32_t)((uint64_t)id >> 32), c2, c3, (uint32_t)seed,
+         (uint32_t)(seed >> 32) ^ stream, o);
+  u[0] = u01(o[0]); u[1] = u01(o[1]); u[2] = u01(o[2]); u[3] = u01(o[3]);
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double alphas(const Cfg& C, double t) {
+  return C.alphas_mz / (1.0 + C.alphas_mz * C.b0 * log(t / C.mz2));
+}
+
+__device__ __forceinline__ int pdf_tab(int pid) {
+  switch (pid) {
+    case 21: return 0;
+    case 1: return 1;
+    case 2: return 2;
+    case 3: case -3: return 3;
+    case 4: case -4: return 4;
+    case 5: case -5: return 5;
+    case -1: return 6;
+    case -2: return 7;
+    default: return -1;
+  }
+}
+
+// x*f: bilinear in (ln x, ln Q^2) of the node values, zero outside the grid
+// (no extrapolation, appendix B.6).
+__device__ inline double pdf_xf(const Cfg& C, int tab, double x, double q2) {
+  if (!(x > 0.0) || x >= 1.0 || !(q2 > 0.0)) return 0.0;
+  double lx = log(x), lq = log(q2);
+  if (lx < C.lnx0 || lq < C.lnq0 || lq > C.lnq1) return 0.0;
+  double fx = (lx - C.lnx0) / C.dlnx;
+  int i = (int)fx;
+  if (i > C.nx - 2) i = C.nx - 2;
+  double a = fx - (double)i;
+  double fq = (lq - C.lnq0) / C.dlnq;
+  int j = (int)fq;
+  if (j > C.nq - 2) j = C.nq - 2;
+  double b = fq - (double)j;
+  const float* F = C.pdf + (size_t)tab * C.nq * C.nx;
+  double f00 = F[j * C.nx + i], f10 = F[j * C.nx + i + 1];
+  double f01 = F[(j + 1) * C.nx + i], f11 = F[(j + 1) * C.nx + i + 1];
+  return (1.0 - b) * ((1.0 - a) * f00 + a * f10) + b * ((1.0 - a) * f01 + a * f11);
+}
+
+__device__ __forceinline__ double pdf_f(const Cfg& C, int tab, double x, double q2) {
+  double xf = pdf_xf(C, tab, x, q2);
+  return xf > 0.0 ? xf / x : 0.0;
+}
+
+__device__ __forceinline__ double dot4(const double* a, const double* b) {
+  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+// ---------------------------------------------------------------------------
+// Working event record of one lane: slot-major arrays with stride G (lanes).
+struct Rec {
+  double *E, *px, *py, *pz;
+  int32_t *pid, *col, *acol;
+  int8_t* st;
+  int64_t G, lane;
+  __device__ __forceinline__ int64_t o(int q) const { return (int64_t)q * G + lane; }
+  __device__ __forceinline__ void get(int q, double p[4]) const {
+    int64_t k = o(q);
+    p[0] = E[k]; p[1] = px[k]; p[2] = py[k]; p[3] = pz[k];
+  }
+  __device__ __forceinline__ void set(int q, const double p[4]) const {
+    int64_t k = o(q);
+    E[k] = p[0]; px[k] = p[1]; py[k] = p[2]; pz[k] = p[3];
+  }
+  // colours as if every parton were outgoing (incoming ones swap)
+  __device__ __forceinline__ int effc(int q) const { int64_t k = o(q); return st[k] < 0 ? acol[k] : col[k]; }
+  __device__ __forceinline__ int effa(int q) const { int64_t k = o(q); return st[k] < 0 ? col[k] : acol[k]; }
+  __device__ __forceinline__ void set_eff(int q, int c, int a) const {
+    int64_t k = o(q);
+    if (st[k] < 0) { col[k] = a; acol[k] = c; } else { col[k] = c; acol[k] = a; }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Channel: dipole end (emitter i, spectator k, colour side) with its constants.
+struct Chan {
+  int i, k, side, type, heavy, alive, nterm;
+  double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
+  double zlo, zhi, omzlo, omzhi, c, invc;
+  int kern[kMaxTerms], shape[kMaxTerms], flav[kMaxTerms];
+  double coefR[kMaxTerms], tc[kMaxTerms];
+};
+
+__device__ __forceinline__ int eta_bin(double eta) {
+  const double dle = -kLnEta0 / kNB;
+  double b = floor((log(eta) - kLnEta0) / dle);
+  if (!(b >= 0.0)) return 0;
+  if (b > kNB - 1) return kNB - 1;
+  return (int)b;
+}
+
+__device__ __forceinline__ double shape_int(int sh, const Chan& ch) {
+  switch (sh) {
+    case kSoft: return log(ch.omzlo / ch.omzhi);
+    case kFlat: return ch.zhi - ch.zlo;
+    case kS1: return log(ch.zhi / ch.omzhi) - log(ch.zlo / ch.omzlo);
+    default: return log(ch.zhi / ch.zlo);
+  }
+}
+
+__device__ __forceinline__ void shape_sample(int sh, const Chan& ch, double I, double u, double& z,
+                                             double& omz) {
+  switch (sh) {
+    case kSoft: omz = ch.omzlo * exp(-u * I); z = 1.0 - omz; break;
+    case kFlat: z = ch.zlo + u * (ch.zhi - ch.zlo); omz = 1.0 - z; break;
+    case kS1: {
+      double L = log(ch.zlo / ch.omzlo) + u * I;
+      double e = exp(-L);
+      z = 1.0 / (1.0 + e);
+      omz = e / (1.0 + e);
+      break;
+    }
+    default: z = ch.zlo * exp(u * I); omz = 1.0 - z; break;
+  }
+}
+
+__device__ __forceinline__ double shape_val(int sh, double z, double omz) {
+  switch (sh) {
+    case kSoft: return 1.0 / omz;
+    case kFlat: return 1.0;
+    case kS1: return 1.0 / (z * omz);
+    default: return 1.0 / z;
+  }
+}
+
+__device__ __forceinline__ void push_term(Chan& ch, int kern, int shape, int flav, double coefR) {
+  int m = ch.nterm++;
+  ch.kern[m] = kern; ch.shape[m] = shape; ch.flav[m] = flav; ch.coefR[m] = coefR; ch.tc[m] = 0.0;
+}
+
+// Constants of dipole end (i, side) with spectator k: invariant, momentum
+// fractions, kinematic limit (appendix B), widest z range (at the cutoff), and
+// the overestimate terms G = c/t (appendix A.1) with their z integrals.
+__device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, int k, Chan& ch) {
+  ch.i = i; ch.k = k; ch.side = side; ch.alive = 0; ch.heavy = 0; ch.nterm = 0;
+  ch.m2 = 0.0; ch.c = 0.0; ch.invc = 0.0;
+  int sti = R.st[R.o(i)], stk = R.st[R.o(k)];
+  bool isE = sti < 0, isS = stk < 0;
+  ch.type = isE ? (isS ? kII : kIF) : (isS ? kFI : kFF);
+  double pi[4], pk[4];
+  R.get(i, pi);
+  R.get(k, pk);
+  ch.s = 2.0 * dot4(pi, pk);
+  ch.eta = isE ? 2.0 * pi[0] / C.sqrt_s : 0.0;
+  ch.etak = isS ? 2.0 * pk[0] / C.sqrt_s : 0.0;
+  double tc = ch.type == kFF ? C.t_cut : C.tc_is;
+  double s = ch.s, eta = ch.eta, etak = ch.etak, d;
+  ch.tcut = tc;
+  ch.lntcut = ch.type == kFF ? C.ln_tc : C.ln_tcis;
+  ch.tlim = 0.0;
+  if (!(s > 0.0)) return;
+  switch (ch.type) {
+    case kFF: ch.tlim = s / 4.0; d = 4.0 * tc / s; break;
+    case kFI: ch.tlim = s * (1.0 - etak) / (4.0 * etak); d = 4.0 * tc * etak / (s * (1.0 - etak)); break;
+    case kIF: ch.tlim = s * (1.0 - eta) / (4.0 * eta); d = 4.0 * tc * eta / (s * (1.0 - eta)); break;
+    default:
+      ch.tlim = s * (1.0 - eta) * (1.0 - eta) / (4.0 * eta);
+      d = 4.0 * tc * eta / (s * (1.0 - eta) * (1.0 - eta));
+      break;
+  }
+  int pidi = R.pid[R.o(i)];
+  if (isE) {
+    int ap = pidi < 0 ? -pidi : pidi;
+    if (ap == 4) { ch.heavy = 1; ch.m2 = C.mc2; ch.tcut = C.tch_c; ch.lntcut = C.ln_tch_c; }
+    if (ap == 5) { ch.heavy = 2; ch.m2 = C.mb2; ch.tcut = C.tch_b; ch.lntcut = C.ln_tch_b; }
+  }
+  if (!(d < 1.0) || !(ch.tlim > ch.tcut)) return;
+  ch.lntlim = log(ch.tlim);
+  double sq = sqrt(1.0 - d);
+  if (ch.type == kFF || ch.type == kFI) {
+    ch.zlo = 0.5 * d / (1.0 + sq);
+    ch.omzhi = ch.zlo;
+    ch.zhi = 1.0 - ch.zlo;
+    ch.omzlo = 1.0 - ch.zlo;
+  } else {
+    ch.omzhi = 0.5 * (1.0 - eta) * d / (1.0 + sq);
+    ch.zhi = 1.0 - ch.omzhi;
+    ch.zlo = (4.0 * eta + (1.0 - eta) * (1.0 - eta) * d) / (2.0 * ((1.0 + eta) + (1.0 - eta) * sq));
+    ch.omzlo = 1.0 - ch.zlo;
+  }
+  if (!isE) {
+    double Rv = 1.0;
+    if (ch.type == kFI) {
+      int Tk = pdf_tab(R.pid[R.o(k)]);
+      if (Tk < 0) return;
+      Rv = C.bound[ent_fi(Tk) * kNB + eta_bin(etak)];
+    }
+    if (pidi == 21) {
+      push_term(ch, kGGG, kSoft, 0, kCA * Rv);
+      for (int f = 1; f <= C.nf; ++f) push_term(ch, kGQQ, kFlat, f, 0.5 * kTR * Rv);
+    } else {
+      push_term(ch, kQQG, kSoft, 0, 2.0 * kCF * Rv);
+    }
+  } else {
+    int bin = eta_bin(eta);
+    int sh2 = ch.type == kII ? kS3 : kS1;
+    if (pidi == 21) {
+      push_term(ch, kC, kS1, 0, C.bound[ent_s1(famC, 0) * kNB + bin]);
+      for (int m = 0; m < 10; ++m) {
+        int a = m < 5 ? m + 1 : -(m - 4);
+        int aa = a < 0 ? -a : a;
+        if (aa > C.nf) continue;
+        int T = pdf_tab(a);
+        double Rv = ch.type == kII ? C.bound[ent_s3(famD, T) * kNB + bin] : C.bound[ent_s1(famD, T) * kNB + bin];
+        push_term(ch, kD, sh2, a, Rv);
+      }
+    } else {
+      int T = pdf_tab(pidi);
+      if (T < 0) return;
+      push_term(ch, kA, kS1, 0, C.bound[ent_s1(famA, T) * kNB + bin]);
+      double Rv = ch.type == kII ? C.bound[ent_s3(famB, T) * kNB + bin] : C.bound[ent_s1(famB, T) * kNB + bin];
+      push_term(ch, kB, sh2, 0, Rv);
+    }
+  }
+  double af = C.as_over / (2.0 * kPi) * C.over_scale;
+  double c = 0.0;
+  for (int m = 0; m < ch.nterm; ++m) {
+    ch.tc[m] = af * ch.coefR[m] * shape_int(ch.shape[m], ch);
+    c += ch.tc[m];
+  }
+  if (!(c > 0.0)) return;
+  ch.c = c;
+  ch.invc = 1.0 / c;
+  ch.alive = 1;
+}
+
+// transverse momentum of size sqrt(tp) at azimuth phi, orthogonal to pa, pb
+__device__ inline void kperp(const double* pa, const double* pb, double tp, double phi, double* kt) {
+  double pab = dot4(pa, pb);
+  double na = sqrt(pa[1] * pa[1] + pa[2] * pa[2] + pa[3] * pa[3]);
+  double nb = sqrt(pb[1] * pb[1] + pb[2] * pb[2] + pb[3] * pb[3]);
+  double d0 = pb[1] / nb - pa[1] / na, d1 = pb[2] / nb - pa[2] / na, d2 = pb[3] / nb - pa[3] / na;
+  int ax = 0;
+  double best = fabs(d0);
+  if (fabs(d1) < best) { best = fabs(d1); ax = 1; }
+  if (fabs(d2) < best) { best = fabs(d2); ax = 2; }
+  double r[4] = {0.0, 0.0, 0.0, 0.0};
+  r[ax + 1] = 1.0;
+  double ra = dot4(r, pa), rb = dot4(r, pb);
+  double n1[4];
+  for (int m = 0; m < 4; ++m) n1[m] = r[m] - rb / pab * pa[m] - ra / pab * pb[m];
+  double n1n = sqrt(-dot4(n1, n1));
+  for (int m = 0; m < 4; ++m) n1[m] /= n1n;
+  double A[4] = {pa[0], -pa[1], -pa[2], -pa[3]};
+  double B[4] = {pb[0], -pb[1], -pb[2], -pb[3]};
+  double Cc[4] = {n1[0], -n1[1], -n1[2], -n1[3]};
+  double n2[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    // the three columns other than mu, ascending
+    int c0 = mu == 0 ? 1 : 0;
+    int c1 = mu <= 1 ? 2 : 1;
+    int c2 = mu <= 2 ? 3 : 2;
+    double det = A[c0] * (B[c1] * Cc[c2] - B[c2] * Cc[c1]) - A[c1] * (B[c0] * Cc[c2] - B[c2] * Cc[c0]) +
+                 A[c2] * (B[c0] * Cc[c1] - B[c1] * Cc[c0]);
+    n2[mu] = (mu & 1) ? -det : det;
+  }
+  double n2n = sqrt(-dot4(n2, n2));
+  for (int m = 0; m < 4; ++m) n2[m] /= n2n;
+  double kt0 = sqrt(tp), cp = cos(phi), sp = sin(phi);
+  for (int m = 0; m < 4; ++m) kt[m] = kt0 * (cp * n1[m] + sp * n2[m]);
+}
+
+// II recoil transformation (appendix B.5) of one momentum: maps K' to K
+__device__ __forceinline__ void ii_lambda(const double* Kp, const double* K, double* p) {
+  double KK[4];
+  for (int m = 0; m < 4; ++m) KK[m] = K[m] + Kp[m];
+  double KK2 = dot4(KK, KK), Kp2 = dot4(Kp, Kp);
+  double c1 = 2.0 * dot4(KK, p) / KK2;
+  double c2 = 2.0 * dot4(Kp, p) / Kp2;
+  for (int m = 0; m < 4; ++m) p[m] = p[m] - c1 * KK[m] + c2 * K[m];
+}
+
+struct Veto {
+  int ok;
+  double x, omx, y, uv, w;
+};
+
+// IF and II: (z, t) -> (x, u or v); the IF root in a cancellation-free form
+__device__ __forceinline__ void is_vars(int type, double z, double omz, double t, double s, double& x,
+                                        double& uv) {
+  double r = t / s;
+  if (type == kIF) {
+    double D = omz + r;
+    double dd = 4.0 * r * z * omz / (D * D);
+    x = 2.0 * z * omz / (D * (1.0 + sqrt(1.0 - dd)));
+  } else {
+    x = z * omz / (omz + r);
+  }
+  uv = x * r / omz;
+}
+
+// acceptance weight of the winner trial
+__device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, int m, double t, double z,
+                                   double omz) {
+  Veto r;
+  r.ok = 0; r.x = 0.0; r.omx = 0.0; r.y = 0.0; r.uv = 0.0; r.w = 0.0;
+  double W = 0.0, s = ch.s;
+  int kern = ch.kern[m];
+  if (ch.type == kFF) {
+    double y = t / (z * omz * s);
+    if (!(y < 1.0)) return r;
+    double den1 = omz + z * y;
+    double P;
+    if (kern == kQQG) P = kCF * (2.0 / den1 - (1.0 + z));
+    else if (kern == kGGG) P = 0.5 * kCA * (2.0 / den1 - 2.0 + z * omz);
+    else P = 0.5 * kTR * (1.0 - 2.0 * z * omz);
+    W = (1.0 - y) * P;
+    r.y = y;
+  } else if (ch.type == kFI) {
+    double kap = t / (z * omz * s);
+    double x = 1.0 / (1.0 + kap), omx = kap * x;
+    if (!(x > ch.etak)) return r;
+    double den1 = omz + omx;
+    double P;
+    if (kern == kQQG) P = kCF * (2.0 / den1 - (1.0 + z));
+    else if (kern == kGGG) P = 0.5 * kCA * (2.0 / den1 - 2.0 + z * omz);
+    else P = 0.5 * kTR * (1.0 - 2.0 * z * omz);
+    int Tk = pdf_tab(R.pid[R.o(ch.k)]);
+    if (Tk < 0) return r;
+    double den = pdf_f(C, Tk, ch.etak, t);
+    double pr = den > 0.0 ? pdf_f(C, Tk, ch.etak / x, t) / den : 0.0;
+    W = P * pr;
+    r.x = x; r.omx = omx;
+  } else {
+    double x, uv;
+    is_vars(ch.type, z, omz, t, s, x, uv);
+    if (!(x > ch.eta)) return r;
+    if (ch.type == kIF && !(uv < 1.0)) return r;
+    double omx = 1.0 - x, P, J;
+    int Ti = pdf_tab(R.pid[R.o(ch.i)]);
+    if (Ti < 0) return r;
+    if (ch.type == kIF) {
+      J = 1.0 / (uv + x - 2.0 * uv * x);
+      switch (kern) {
+        case kA: P = kCF * (2.0 / (omx + uv) - (1.0 + x)); break;
+        case kB: P = kTR * (1.0 - 2.0 * x * omx); break;
+        case kC: P = kCA * (1.0 / (omx + uv) + omx / x - 1.0 + x * omx); break;
+        default: P = kCF * (x + 2.0 * omx / x); break;
+      }
+    } else {
+      J = 1.0 / z;
+      switch (kern) {
+        case kA: P = kCF * (2.0 / omx - (1.0 + x)); break;
+        case kB: P = kTR * (1.0 - 2.0 * x * omx); break;
+        case kC: P = kCA * (1.0 / omx + omx / x - 1.0 + x * omx); break;
+        default: P = kCF * (x + 2.0 * omx / x); break;
+      }
+    }
+    int Tnum, Tden;
+    switch (kern) {
+      case kA: Tnum = Ti; Tden = Ti; break;
+      case kB: Tnum = 0; Tden = Ti; break;
+      case kC: Tnum = 0; Tden = 0; break;
+      default: Tnum = pdf_tab(ch.flav[m]); Tden = 0; break;
+    }
+    double den = pdf_f(C, Tden, ch.eta, t);
+    double pr = den > 0.0 ? pdf_f(C, Tnum, ch.eta / x, t) / den : 0.0;
+    double hf = ch.heavy ? (t - ch.m2) / t : 1.0;
+    W = J * P * pr * hf;
+    r.x = x; r.omx = omx; r.uv = uv;
+  }
+  double over = C.over_scale * ch.coefR[m] * shape_val(ch.shape[m], z, omz);
+  r.w = alphas(C, t) / C.as_over * W / over;
+  r.ok = 1;
+  return r;
+}
+
+// momenta after the emission: emitter', emitted, spectator'
+__device__ inline void do_map(int type, const double* pe, const double* ps, double s, double z, double omz,
+                              double v1, double v2, double phi, double* pi, double* pj, double* pk) {
+  double kt[4], tp;
+  if (type == kFF) {
+    double y = v1;
+    tp = z * omz * y * s;
+    kperp(pe, ps, tp, phi, kt);
+    for (int m = 0; m < 4; ++m) {
+      pi[m] = z * pe[m] + y * omz * ps[m] + kt[m];
+      pj[m] = omz * pe[m] + y * z * ps[m] - kt[m];
+      pk[m] = (1.0 - y) * ps[m];
+    }
+  } else if (type == kFI) {
+    double x = v1, omx = v2;
+    tp = z * omz * omx / x * s;
+    kperp(pe, ps, tp, phi, kt);
+    double a = omz * omx / x, b = z * omx / x;
+    for (int m = 0; m < 4; ++m) {
+      pi[m] = z * pe[m] + a * ps[m] + kt[m];
+      pj[m] = omz * pe[m] + b * ps[m] - kt[m];
+      pk[m] = ps[m] / x;
+    }
+  } else if (type == kIF) {
+    double x = v1, u = v2, omx = 1.0 - x;
+    tp = u * (1.0 - u) * omx / x * s;
+    kperp(pe, ps, tp, phi, kt);
+    double a = (1.0 - u) * omx / x, b = u * omx / x;
+    for (int m = 0; m < 4; ++m) {
+      pi[m] = pe[m] / x;
+      pj[m] = a * pe[m] + u * ps[m] - kt[m];
+      pk[m] = b * pe[m] + (1.0 - u) * ps[m] + kt[m];
+    }
+  } else {
+    double x = v1, v = v2;
+    tp = v * (1.0 - x - v) / x * s;
+    kperp(pe, ps, tp, phi, kt);
+    double a = (1.0 - x - v) / x;
+    for (int m = 0; m < 4; ++m) {
+      pi[m] = pe[m] / x;
+      pj[m] = a * pe[m] + v * ps[m] - kt[m];
+      pk[m] = ps[m];
+    }
+  }
+}
+
+// apply the accepted emission of term m: momenta, flavours and colour tags;
+// the emitted parton is appended at slot n
+__device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, int m, double z, double omz,
+                            const Veto& v, double phi) {
+  int i = ch.i, k = ch.k, j = n;
+  double pe[4], ps[4], pi[4], pj[4], pk[4];
+  R.get(i, pe);
+  R.get(k, ps);
+  double a1 = 0.0, a2 = 0.0;
+  if (ch.type == kFF) a1 = v.y;
+  else if (ch.type == kFI) { a1 = v.x; a2 = v.omx; }
+  else { a1 = v.x; a2 = v.uv; }
+  do_map(ch.type, pe, ps, ch.s, z, omz, a1, a2, phi, pi, pj, pk);
+  if (ch.type == kII) {
+    double Kp[4], K[4];
+    for (int q = 0; q < 4; ++q) { Kp[q] = pe[q] + ps[q]; K[q] = pi[q] + pk[q] - pj[q]; }
+    for (int q = 0; q < n; ++q) {
+      if (q == i || q == k || R.st[R.o(q)] <= 0) continue;
+      double p[4];
+      R.get(q, p);
+      ii_lambda(Kp, K, p);
+      R.set(q, p);
+    }
+  }
+  R.set(i, pi);
+  R.set(k, pk);
+  R.set(j, pj);
+  R.st[R.o(j)] = 1;
+  int ec = R.effc(i), ea = R.effa(i), jc = 0, ja = 0;
+  int kern = ch.kern[m];
+  int pidi = R.pid[R.o(i)];
+  if (kern == kQQG || kern == kGGG || kern == kA || kern == kC) {
+    int N = ++maxtag;
+    if (ch.side == 0) { R.set_eff(i, N, ea); jc = ec; ja = N; }
+    else { R.set_eff(i, ec, N); jc = N; ja = ea; }
+    R.pid[R.o(j)] = 21;
+  } else if (kern == kGQQ) {
+    int f = ch.flav[m];
+    if (ch.side == 0) { R.pid[R.o(i)] = f; R.set_eff(i, ec, 0); R.pid[R.o(j)] = -f; jc = 0; ja = ea; }
+    else { R.pid[R.o(i)] = -f; R.set_eff(i, 0, ea); R.pid[R.o(j)] = f; jc = ec; ja = 0; }
+  } else if (kern == kB) {
+    int N = ++maxtag;
+    R.pid[R.o(j)] = -pidi;
+    if (ec == 0) { R.set_eff(i, N, ea); jc = 0; ja = N; }
+    else { R.set_eff(i, ec, N); jc = N; ja = 0; }
+    R.pid[R.o(i)] = 21;
+  } else {  // kD
+    int a = ch.flav[m];
+    if (a > 0) { R.set_eff(i, 0, ea); jc = ec; ja = 0; }
+    else { R.set_eff(i, ec, 0); jc = 0; ja = ea; }
+    R.pid[R.o(i)] = a;
+    R.pid[R.o(j)] = a;
+  }
+  R.col[R.o(j)] = jc;
+  R.acol[R.o(j)] = ja;
+}
+
+}  // namespace gaps

@@ -1,0 +1,441 @@
+// gfx950 kernels of libgaps: overestimate table, hard events, the shower,
+// observables and small helpers (arXiv:2511.19633).
+#include "kernels.hpp"
+
+namespace gaps {
+
+// ---------------------------------------------------------------------------
+// small helpers
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_rng_blocks(uint64_t seed, uint32_t stream, const int64_t* id, const uint32_t* c2,
+                             const uint32_t* c3, int64_t n, uint32_t* out) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint32_t o[4];
+  uint64_t u = (uint64_t)id[k];
+  philox((uint32_t)u, (uint32_t)(u >> 32), c2[k], c3[k], (uint32_t)seed, (uint32_t)(seed >> 32) ^ stream, o);
+  for (int m = 0; m < 4; ++m) out[4 * k + m] = o[m];
+}
+
+__global__ void k_pdf_eval(Cfg C, const int32_t* tab, const double* x, const double* q2, int64_t n,
+                           double* out) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int t = tab[k];
+  out[k] = (t >= 0 && t < 8) ? pdf_xf(C, t, x[k], q2[k]) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Overestimate table (appendix A.2 procedure made strict): one thread per
+// (entry, eta bin).  Upper envelope over the grid rows (the scale
+// interpolant is a mediant of rows), over cells of the parent momentum
+// fraction (bounded by node values), times 1.5, rounded up to a quarter
+// octave.
+__device__ double gbound(int shape, int fam, double x) {
+  double omx = 1.0 - x;
+  if (shape == 1) {
+    switch (fam) {
+      case famA: return kCF * (1.0 + x * x);
+      case famB: return omx * kTR * (1.0 - 2.0 * x * omx);
+      case famC: return kCA * (1.0 + omx * omx / x - omx + x * omx * omx);
+      default: return omx * kCF * (x + 2.0 * omx / x);
+    }
+  }
+  if (fam == famB) return kTR * (1.0 - 2.0 * x * omx);
+  return kCF * (x + 2.0 * omx / x);
+}
+
+__device__ double quarter_octave_up(double v) {
+  if (!(v > 0.0)) return 0.0;
+  int e;
+  double m = frexp(v, &e);
+  double q;
+  if (m <= 0.5) q = 0.5;
+  else if (m <= 0.5946035575013605) q = 0.5946035575013605;
+  else if (m <= 0.7071067811865476) q = 0.7071067811865476;
+  else if (m <= 0.8408964152537145) q = 0.8408964152537145;
+  else q = 1.0;
+  return ldexp(q, e);
+}
+
+__device__ double xf_on_row(const Cfg& C, int tab, int j, double x) {
+  if (!(x > 0.0) || x >= 1.0) return 0.0;
+  double lx = log(x);
+  if (lx < C.lnx0) return 0.0;
+  double fx = (lx - C.lnx0) / C.dlnx;
+  int i = (int)fx;
+  if (i > C.nx - 2) i = C.nx - 2;
+  double a = fx - (double)i;
+  const float* F = C.pdf + ((size_t)tab * C.nq + j) * C.nx;
+  return (1.0 - a) * (double)F[i] + a * (double)F[i + 1];
+}
+
+__global__ void k_bounds(Cfg C, double* bound) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kNEnt * kNB) return;
+  int e = t / kNB, bin = t % kNB;
+  // which transition this entry bounds
+  int kind, fam = -1, T, num, den;
+  double m2 = 0.0;
+  bool valid = true;
+  if (e < 8) {
+    kind = 0; T = e; num = e; den = e;
+  } else {
+    kind = e < 40 ? 1 : 3;
+    int r = e - (kind == 1 ? 8 : 40);
+    fam = r / 8; T = r % 8;
+    num = den = 0;
+    if (fam == famC) {
+      valid = (kind == 1 && T == 0);
+    } else {
+      if (T == 0 || (kind == 3 && fam == famA)) valid = false;
+      if (fam == famA) { num = T; den = T; }
+      if (fam == famB) { num = 0; den = T; }
+      if (fam == famD) { num = T; den = 0; }
+      if (fam == famA || fam == famB) {
+        if (T == 4) m2 = C.mc2;
+        if (T == 5) m2 = C.mb2;
+      }
+    }
+  }
+  if (!valid) { bound[e * kNB + bin] = 0.0; return; }
+  const int nx = C.nx, nq = C.nq;
+  const double dle = -kLnEta0 / kNB;
+  double vrow[64];
+  double best = 0.0;
+  for (int p = 0; p < 3; ++p) {
+    double eta = exp(kLnEta0 + (bin + 0.5 * p) * dle);
+    if (!(eta < 1.0)) continue;
+    double fx = (log(eta) - C.lnx0) / C.dlnx;
+    int i0 = (int)fx;
+    if (i0 > nx - 2) i0 = nx - 2;
+    for (int j = 0; j < nq; ++j) {
+      double d = xf_on_row(C, den, j, eta) / eta;
+      vrow[j] = -1.0;
+      if (!(d > 0.0)) continue;
+      const float* F = C.pdf + ((size_t)num * nq + j) * nx;
+      double m = 0.0;
+      for (int i = i0; i <= nx - 2; ++i) {
+        double xlo = (i == i0) ? eta : exp(C.lnx0 + i * C.dlnx);
+        double xhi = exp(C.lnx0 + (i + 1) * C.dlnx);
+        double flo = (i == i0) ? xf_on_row(C, num, j, eta) : (double)F[i];
+        double fhi = (double)F[i + 1];
+        double nc = (flo > fhi ? flo : fhi) / xlo;
+        double val = nc;
+        if (kind != 0) {
+          int sh = kind == 1 ? 1 : 3;
+          double ga = gbound(sh, fam, eta / xlo), gb = gbound(sh, fam, eta / xhi);
+          val = (ga > gb ? ga : gb) * nc;
+        }
+        if (val > m) m = val;
+      }
+      vrow[j] = m / d;
+    }
+    double tmin = m2 > 0.0 ? m2 + C.t_cut : C.tc_is;
+    for (int j = 0; j + 1 < nq; ++j) {
+      double qhi = exp(C.lnq0 + (j + 1) * C.dlnq);
+      if (qhi < tmin) continue;
+      double a = vrow[j], b = vrow[j + 1];
+      double m = a > b ? a : b;
+      if (m < 0.0) continue;
+      if (m2 > 0.0) m *= (qhi - m2) / qhi;
+      if (m > best) best = m;
+    }
+  }
+  bound[e * kNB + bin] = quarter_octave_up(1.5 * best);
+}
+
+// ---------------------------------------------------------------------------
+// Hard events (appendix C; e+e- and LO from the workload definitions)
+__device__ double cos_1pc2(double u) {
+  double q = 4.0 - 8.0 * u;
+  double sd = sqrt(0.25 * q * q + 1.0);
+  return cbrt(-0.5 * q + sd) + cbrt(-0.5 * q - sd);
+}
+
+__device__ double zcoup(const Cfg& C, int f) {
+  int a = f < 0 ? -f : f;
+  double V, A;
+  if (a % 2 == 0) { V = 0.5 - 4.0 / 3.0 * C.sw2; A = 0.5; }
+  else { V = -0.5 + 2.0 / 3.0 * C.sw2; A = -0.5; }
+  return V * V + A * A;
+}
+
+__device__ double lo_lumi(const Cfg& C, double m, double y, double* csub) {
+  double m2 = m * m;
+  double e1 = m / C.sqrt_s * exp(y), e2 = m / C.sqrt_s * exp(-y);
+  double L = 0.0;
+  for (int f = 1; f <= C.nf; ++f) {
+    double v = zcoup(C, f);
+    double a = v * pdf_xf(C, pdf_tab(f), e1, m2) * pdf_xf(C, pdf_tab(-f), e2, m2);
+    double b = v * pdf_xf(C, pdf_tab(-f), e1, m2) * pdf_xf(C, pdf_tab(f), e2, m2);
+    if (csub) { csub[2 * (f - 1)] = a; csub[2 * (f - 1) + 1] = b; }
+    L += a + b;
+  }
+  return L;
+}
+
+__global__ void k_lo_scan(Cfg C, double* w) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 64 * 128) return;
+  int i = t / 128, j = t % 128;
+  double m = C.mll_min + (C.mll_max - C.mll_min) * i / 63.0;
+  double Y = log(C.sqrt_s / m);
+  double y = -Y + 2.0 * Y * (j + 0.5) / 128.0;
+  w[t] = lo_lumi(C, m, y, nullptr) * 2.0 * Y;
+}
+
+__global__ void k_lo_max(const double* w, int n, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double best = 0.0;
+  for (int k = 0; k < n; ++k) best = w[k] > best ? w[k] : best;
+  *out = quarter_octave_up(1.25 * best);
+}
+
+struct HardOut {
+  const gaps_events* o;
+  int64_t e;
+  __device__ void put(int slot, const double* p, int pid, int col, int acol, int st) const {
+    int64_t k = (int64_t)slot * o->cap + e;
+    o->E[k] = p[0]; o->px[k] = p[1]; o->py[k] = p[2]; o->pz[k] = p[3];
+    o->pid[k] = pid; o->col[k] = col; o->acol[k] = acol; o->status[k] = (int8_t)st;
+  }
+};
+
+__device__ void decay_z(const double* pZ, double m, double ucos, double uphi, double* em, double* ep) {
+  double c = cos_1pc2(ucos), st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * kPi * uphi;
+  double k[4] = {0.5 * m, 0.5 * m * st * cos(ph), 0.5 * m * st * sin(ph), 0.5 * m * c};
+  double pk = pZ[1] * k[1] + pZ[2] * k[2] + pZ[3] * k[3];
+  double E1 = (pZ[0] * k[0] + pk) / m;
+  double f = (k[0] + E1) / (pZ[0] + m);
+  em[0] = E1;
+  for (int q = 1; q < 4; ++q) em[q] = k[q] + f * pZ[q];
+  for (int q = 0; q < 4; ++q) ep[q] = pZ[q] - em[q];
+}
+
+__device__ double li2(double x) {
+  // power series on [0, 1/2]; reflections elsewhere
+  double sign = 1.0, add = 0.0;
+  if (x == 1.0) return kPi * kPi / 6.0;
+  if (x < 0.0) {
+    double l = log(1.0 - x);
+    add = -0.5 * l * l;
+    sign = -1.0;
+    x = x / (x - 1.0);
+  }
+  double base = 0.0, s2 = 1.0;
+  if (x > 0.5) {
+    base = kPi * kPi / 6.0 - log(x) * log(1.0 - x);
+    s2 = -1.0;
+    x = 1.0 - x;
+  }
+  double sum = 0.0, xk = x;
+  for (int k = 1; k < 200; ++k) {
+    double term = xk / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-18 * sum) break;
+    xk *= x;
+  }
+  return sign * (base + s2 * sum) + add;
+}
+
+__device__ double mborn2(const Cfg& C, int f) {
+  return 1.0 / kNC * 0.25 * sqrt(2.0) * C.gf * C.mz2 * C.mz2 * zcoup(C, f);
+}
+
+// collinear insertion (K + P at muF = mZ) for a leg with Born parton b at eta
+__device__ double k_leg(const Cfg& C, int b, double eta, double x, double q2) {
+  double den = pdf_f(C, pdf_tab(b), eta, q2);
+  if (!(den > 0.0)) return 0.0;
+  double rq = pdf_f(C, pdf_tab(b), eta / x, q2) / (x * den);
+  double rg = pdf_f(C, 0, eta / x, q2) / (x * den);
+  double pq = kCF * C.alphas_mz / (2.0 * kPi), pg = kTR * C.alphas_mz / (2.0 * kPi);
+  double A = pq * (-5.0 + 2.0 * kPi * kPi / 3.0);
+  double l = log(1.0 - eta);
+  double B = pq * 2.0 * (kPi * kPi / 6.0 - l * l - li2(1.0 - eta));
+  double L = log((1.0 - x) / x) + log(1.0 - x);
+  double g = pq * (2.0 / (1.0 - x)) * L;
+  double h = pq * (-(1.0 + x) * L + (1.0 - x));
+  double hg = pg * (2.0 * x * (1.0 - x) + (x * x + (1.0 - x) * (1.0 - x)) * L);
+  return A - B + (1.0 - eta) * ((rq - 1.0) * g + rq * h + rg * hg);
+}
+
+__global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint32_t SH = 2u;  // stream of the hard process
+  int64_t id = first_id + e;
+  o.id[e] = id;
+  if (o.n_cycles) o.n_cycles[e] = 0;
+  if (o.n_trials) o.n_trials[e] = 0;
+  if (o.n_accept) o.n_accept[e] = 0;
+  if (o.n_viol) o.n_viol[e] = 0;
+  if (o.t1) o.t1[e] = 0.0;
+  HardOut H{&o, e};
+  if (C.process == 0) {
+    double u[4];
+    rng4(seed, SH, id, 0u, 0u, u);
+    int f = 1 + (int)(u[0] * C.nf);
+    if (f > C.nf) f = C.nf;
+    double c = cos_1pc2(u[1]), st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * kPi * u[2];
+    double E = 0.5 * C.sqrt_s;
+    double q[4] = {E, E * st * cos(ph), E * st * sin(ph), E * c};
+    double qb[4] = {E, -q[1], -q[2], -q[3]};
+    H.put(0, q, f, 1, 0, 1);
+    H.put(1, qb, -f, 0, 1, 1);
+    o.n[e] = 2; o.w[e] = 1.0; o.t_start[e] = C.S; o.flags[e] = 0u;
+    return;
+  }
+  if (C.process == 1) {
+    double mg = C.mz * C.gz;
+    double r1 = atan((C.mll_min * C.mll_min - C.mz2) / mg);
+    double r2 = atan((C.mll_max * C.mll_max - C.mz2) / mg);
+    double csub[10];
+    for (int k = 0; k < 1000; ++k) {
+      double u[4];
+      rng4(seed, SH, id, (uint32_t)k, 0u, u);
+      double m2 = C.mz2 + mg * tan(r1 + u[0] * (r2 - r1));
+      double m = sqrt(m2);
+      double Y = log(C.sqrt_s / m), y = -Y + 2.0 * Y * u[1];
+      double L = lo_lumi(C, m, y, csub);
+      if (!(u[2] * C.lo_wmax < L * 2.0 * Y)) continue;
+      double target = u[3] * L, cum = 0.0;
+      int sel = 2 * C.nf - 1;
+      for (int q = 0; q < 2 * C.nf; ++q) {
+        cum += csub[q];
+        if (target < cum) { sel = q; break; }
+      }
+      int f = sel / 2 + 1;
+      int pa = (sel % 2 == 0) ? f : -f, pb = -pa;
+      double e1 = m / C.sqrt_s * exp(y), e2 = m / C.sqrt_s * exp(-y);
+      double Ea = 0.5 * e1 * C.sqrt_s, Eb = 0.5 * e2 * C.sqrt_s;
+      double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+      H.put(0, A, pa, pa > 0 ? 1 : 0, pa > 0 ? 0 : 1, -1);
+      H.put(1, B, pb, pb > 0 ? 1 : 0, pb > 0 ? 0 : 1, -1);
+      double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4], ud[4];
+      rng4(seed, SH, id, 0xFFFFFFFFu, 0u, ud);
+      decay_z(pZ, m, ud[0], ud[1], em, ep);
+      H.put(2, em, 11, 0, 0, 1);
+      H.put(3, ep, -11, 0, 0, 1);
+      o.n[e] = 4; o.w[e] = 1.0; o.t_start[e] = C.S; o.flags[e] = 0u;
+      return;
+    }
+    o.n[e] = 0; o.w[e] = 0.0; o.t_start[e] = C.S; o.flags[e] = fHardFail;
+    return;
+  }
+  // NLO S and H events
+  double u0[4], u1[4];
+  rng4(seed, SH, id, 0u, 0u, u0);
+  rng4(seed, SH, id, 1u, 0u, u1);
+  const double m = C.mz, m2 = C.mz2, q2 = m2;
+  const int nf = C.nf;
+  if (u0[0] < C.p_s) {
+    double Y = log(C.sqrt_s / m), y = -Y + 2.0 * Y * u0[2];
+    double e1 = m / C.sqrt_s * exp(y), e2 = m / C.sqrt_s * exp(-y);
+    double xa = e1 + (1.0 - e1) * u1[0], xb = e2 + (1.0 - e2) * u1[1];
+    double csub[10], W = 0.0;
+    double bvi = 1.0 + kCF * C.alphas_mz / (2.0 * kPi) * 2.0;
+    for (int f = 1; f <= nf; ++f)
+      for (int o2 = 0; o2 < 2; ++o2) {
+        int a = o2 == 0 ? f : -f, b = -a;
+        double born = kPi / (m2 * m2) * mborn2(C, f) * pdf_xf(C, pdf_tab(a), e1, q2) * pdf_xf(C, pdf_tab(b), e2, q2);
+        double corr = bvi + k_leg(C, a, e1, xa, q2) + k_leg(C, b, e2, xb, q2);
+        csub[2 * (f - 1) + o2] = born * corr;
+        W += fabs(born * corr);
+      }
+    double target = u0[1] * W, cum = 0.0;
+    int sel = 2 * nf - 1;
+    for (int q = 0; q < 2 * nf; ++q) {
+      cum += fabs(csub[q]);
+      if (target < cum) { sel = q; break; }
+    }
+    int f = sel / 2 + 1, a = (sel % 2 == 0) ? f : -f, b = -a;
+    double Ea = 0.5 * e1 * C.sqrt_s, Eb = 0.5 * e2 * C.sqrt_s;
+    double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+    H.put(0, A, a, a > 0 ? 1 : 0, a > 0 ? 0 : 1, -1);
+    H.put(1, B, b, b > 0 ? 1 : 0, b > 0 ? 0 : 1, -1);
+    double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4];
+    decay_z(pZ, m, u0[3], u1[3], em, ep);
+    H.put(2, em, 11, 0, 0, 1);
+    H.put(3, ep, -11, 0, 0, 1);
+    o.n[e] = 4;
+    o.w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y / C.p_s;
+    o.t_start[e] = C.S;
+    o.flags[e] = 0u;
+    return;
+  }
+  double xmin = m2 / C.S;
+  double x = xmin + (1.0 - xmin) * u1[0], sbar = m2 / x;
+  double YH = 0.5 * log(C.S * x / m2), y = -YH + 2.0 * YH * u0[2];
+  double ea = exp(y) * sqrt(sbar / C.S), eb = exp(-y) * sqrt(sbar / C.S);
+  double v = (1.0 - x) * u1[1], ph = 2.0 * kPi * u1[2];
+  double Ea = 0.5 * ea * C.sqrt_s, Eb = 0.5 * eb * C.sqrt_s;
+  double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+  double kt0 = sqrt(v * (1.0 - x - v) * sbar);
+  double J[4];
+  for (int q = 0; q < 4; ++q) J[q] = (1.0 - x - v) * A[q] + v * B[q];
+  J[1] -= kt0 * cos(ph);
+  J[2] -= kt0 * sin(ph);
+  double pZ[4];
+  for (int q = 0; q < 4; ++q) pZ[q] = A[q] + B[q] - J[q];
+  double ubar = -2.0 * (A[0] * J[0] - A[1] * J[1] - A[2] * J[2] - A[3] * J[3]);
+  double tbar = -2.0 * (B[0] * J[0] - B[1] * J[1] - B[2] * J[2] - B[3] * J[3]);
+  double csub[30], W = 0.0;
+  int pa[30], pb[30], kind[30];
+  int q = 0;
+  double pre_q = 8.0 * kPi * C.alphas_mz * kCF / m2, pre_g = 8.0 * kPi * C.alphas_mz * kTR / m2;
+  for (int f = 1; f <= nf; ++f) {
+    double mb = mborn2(C, f);
+    double rs = pre_q * mb * (-2.0);
+    pa[q] = f; pb[q] = -f; kind[q] = 0; csub[q++] = rs;
+    pa[q] = -f; pb[q] = f; kind[q] = 0; csub[q++] = rs;
+    rs = pre_g * mb * ((2.0 * m2 - ubar) / sbar);
+    pa[q] = 21; pb[q] = f; kind[q] = 1; csub[q++] = rs;
+    pa[q] = 21; pb[q] = -f; kind[q] = 1; csub[q++] = rs;
+    rs = pre_g * mb * ((2.0 * m2 - tbar) / sbar);
+    pa[q] = f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
+    pa[q] = -f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
+  }
+  for (int k = 0; k < q; ++k) {
+    csub[k] *= pdf_xf(C, pdf_tab(pa[k]), ea, q2) * pdf_xf(C, pdf_tab(pb[k]), eb, q2) / (16.0 * kPi * m2);
+    W += fabs(csub[k]);
+  }
+  double target = u0[1] * W, cum = 0.0;
+  int sel = q - 1;
+  for (int k = 0; k < q; ++k) {
+    cum += fabs(csub[k]);
+    if (target < cum) { sel = k; break; }
+  }
+  int a = pa[sel], b = pb[sel];
+  int ca, aa, cb, ab, jp, cj, aj;
+  if (kind[sel] == 0) {
+    ca = a > 0 ? 1 : 0; aa = a > 0 ? 0 : 2;
+    cb = b > 0 ? 1 : 0; ab = b > 0 ? 0 : 2;
+    jp = 21; cj = 1; aj = 2;
+  } else {
+    int qk = kind[sel] == 1 ? b : a;
+    int cq, aq;
+    if (qk > 0) { cq = 2; aq = 0; cj = 1; aj = 0; }
+    else { cq = 0; aq = 1; cj = 0; aj = 2; }
+    jp = qk;
+    if (kind[sel] == 1) { ca = 1; aa = 2; cb = cq; ab = aq; }
+    else { ca = cq; aa = aq; cb = 1; ab = 2; }
+  }
+  H.put(0, A, a, ca, aa, -1);
+  H.put(1, B, b, cb, ab, -1);
+  H.put(2, J, jp, cj, aj, 1);
+  double em[4], ep[4];
+  decay_z(pZ, m, u0[3], u1[3], em, ep);
+  H.put(3, em, 11, 0, 0, 1);
+  H.put(4, ep, -11, 0, 0, 1);
+  o.n[e] = 5;
+  o.w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * YH * (1.0 - xmin) * (1.0 - x) / (1.0 - C.p_s);
+  o.t_start[e] = C.S;
+  o.flags[e] = fHEvent;
+}
+
+}  // namespace gaps

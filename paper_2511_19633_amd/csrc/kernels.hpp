@@ -1,0 +1,49 @@
+// Kernel declarations shared by the translation units of libgaps.
+#pragma once
+
+#include "../../include/gaps.h"
+#include "device.hpp"
+
+namespace gaps {
+
+// Per-lane working storage of the shower kernels: event records and channel
+// caches, slot-major with stride = number of lanes (coalesced across a wave).
+struct Scratch {
+  int64_t lanes;
+  int max_slots;
+  double *E, *px, *py, *pz;
+  int32_t *pid, *col, *acol;
+  int8_t* st;
+  // channel cache [2*max_slots][lanes]
+  uint32_t* cinfo;
+  double *ctlim, *clntlim, *cinvc;
+  unsigned long long* queue;  // work-queue counters
+};
+
+struct ShowerArgs {
+  int mode;
+  int compact_every;
+  uint32_t stream;
+  uint64_t seed;
+  int64_t n;
+  float* log;
+  int64_t log_cap;
+  unsigned long long* log_count;
+  unsigned long long* stats;
+};
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v);
+__global__ void k_rng_blocks(uint64_t seed, uint32_t stream, const int64_t* id, const uint32_t* c2,
+                             const uint32_t* c3, int64_t n, uint32_t* out);
+__global__ void k_pdf_eval(Cfg C, const int32_t* tab, const double* x, const double* q2, int64_t n,
+                           double* out);
+__global__ void k_bounds(Cfg C, double* bound);
+__global__ void k_lo_scan(Cfg C, double* w);
+__global__ void k_lo_max(const double* w, int n, double* out);
+__global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o);
+__global__ void k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_observables(Cfg C, gaps_events ev, int64_t n, double* obs);
+__global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
+                            int nbins, double* sumw, double* sumw2);
+
+}  // namespace gaps

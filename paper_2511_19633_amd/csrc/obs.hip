@@ -1,0 +1,226 @@
+// Observables and histograms (section 4.1: Z observables, anti-kT jets; thrust
+// and Durham jet rates for the e+e- workload), one event per thread.
+#include "kernels.hpp"
+
+namespace gaps {
+
+namespace {
+
+constexpr int kObsMax = 256;
+constexpr int kNObs = 12;
+
+__device__ __forceinline__ bool is_parton(int pid) { return pid == 21 || (pid != 0 && pid <= 5 && pid >= -5); }
+__device__ __forceinline__ double rapidity(const double* p) { return 0.5 * log((p[0] + p[3]) / (p[0] - p[3])); }
+__device__ __forceinline__ double pseudorap(const double* p) {
+  double pt = sqrt(p[1] * p[1] + p[2] * p[2]);
+  return asinh(p[3] / pt);
+}
+
+// anti-kT with E-scheme recombination over q[0..n-1] (modified in place);
+// jets written to jets[] sorted by pT (descending)
+__device__ int antikt(double (*q)[4], int n, double R, double (*jets)[4], bool* on) {
+  int alive = n, nj = 0;
+  for (int i = 0; i < n; ++i) on[i] = true;
+  while (alive > 0) {
+    double best = INFINITY;
+    int bi = -1, bj = -1;
+    for (int i = 0; i < n; ++i) {
+      if (!on[i]) continue;
+      double pti2 = q[i][1] * q[i][1] + q[i][2] * q[i][2];
+      double diB = 1.0 / pti2;
+      if (diB < best) { best = diB; bi = i; bj = -1; }
+      double yi = rapidity(q[i]), phii = atan2(q[i][2], q[i][1]);
+      for (int j = i + 1; j < n; ++j) {
+        if (!on[j]) continue;
+        double ptj2 = q[j][1] * q[j][1] + q[j][2] * q[j][2];
+        double dy = yi - rapidity(q[j]);
+        double dphi = fabs(phii - atan2(q[j][2], q[j][1]));
+        if (dphi > kPi) dphi = 2.0 * kPi - dphi;
+        double dR2 = dy * dy + dphi * dphi;
+        double dij = fmin(1.0 / pti2, 1.0 / ptj2) * dR2 / (R * R);
+        if (dij < best) { best = dij; bi = i; bj = j; }
+      }
+    }
+    if (bj < 0) {
+      for (int m = 0; m < 4; ++m) jets[nj][m] = q[bi][m];
+      ++nj;
+      on[bi] = false;
+    } else {
+      for (int m = 0; m < 4; ++m) q[bi][m] += q[bj][m];
+      on[bj] = false;
+    }
+    --alive;
+  }
+  for (int i = 1; i < nj; ++i) {
+    double tmp[4] = {jets[i][0], jets[i][1], jets[i][2], jets[i][3]};
+    double pti = tmp[1] * tmp[1] + tmp[2] * tmp[2];
+    int j = i - 1;
+    while (j >= 0 && jets[j][1] * jets[j][1] + jets[j][2] * jets[j][2] < pti) {
+      for (int m = 0; m < 4; ++m) jets[j + 1][m] = jets[j][m];
+      --j;
+    }
+    for (int m = 0; m < 4; ++m) jets[j + 1][m] = tmp[m];
+  }
+  return nj;
+}
+
+__device__ double thrust(double (*p)[4], int n) {
+  double sum = 0.0;
+  for (int i = 0; i < n; ++i) sum += sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+  if (n < 2 || !(sum > 0.0)) return 1.0;
+  if (n == 2) {
+    double d0 = p[0][1] - p[1][1], d1 = p[0][2] - p[1][2], d2 = p[0][3] - p[1][3];
+    return sqrt(d0 * d0 + d1 * d1 + d2 * d2) / sum;
+  }
+  double best = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      double nv0 = p[i][2] * p[j][3] - p[i][3] * p[j][2];
+      double nv1 = p[i][3] * p[j][1] - p[i][1] * p[j][3];
+      double nv2 = p[i][1] * p[j][2] - p[i][2] * p[j][1];
+      double P0 = 0.0, P1 = 0.0, P2 = 0.0;
+      for (int k = 0; k < n; ++k) {
+        if (k == i || k == j) continue;
+        double d = p[k][1] * nv0 + p[k][2] * nv1 + p[k][3] * nv2;
+        double sg = d >= 0.0 ? 1.0 : -1.0;
+        P0 += sg * p[k][1]; P1 += sg * p[k][2]; P2 += sg * p[k][3];
+      }
+      for (int si = -1; si <= 1; si += 2)
+        for (int sj = -1; sj <= 1; sj += 2) {
+          double Q0 = P0 + si * p[i][1] + sj * p[j][1];
+          double Q1 = P1 + si * p[i][2] + sj * p[j][2];
+          double Q2 = P2 + si * p[i][3] + sj * p[j][3];
+          double v = sqrt(Q0 * Q0 + Q1 * Q1 + Q2 * Q2);
+          if (v > best) best = v;
+        }
+    }
+  return best / sum;
+}
+
+__device__ void durham(double (*q)[4], int n, double* y, bool* on) {
+  double Evis = 0.0;
+  for (int i = 0; i < n; ++i) { on[i] = true; Evis += q[i][0]; }
+  for (int k = 0; k < 4; ++k) y[k] = 0.0;
+  int alive = n;
+  while (alive > 1) {
+    double best = INFINITY;
+    int bi = -1, bj = -1;
+    for (int i = 0; i < n; ++i) {
+      if (!on[i]) continue;
+      double ai = sqrt(q[i][1] * q[i][1] + q[i][2] * q[i][2] + q[i][3] * q[i][3]);
+      for (int j = i + 1; j < n; ++j) {
+        if (!on[j]) continue;
+        double aj = sqrt(q[j][1] * q[j][1] + q[j][2] * q[j][2] + q[j][3] * q[j][3]);
+        double c = (q[i][1] * q[j][1] + q[i][2] * q[j][2] + q[i][3] * q[j][3]) / (ai * aj);
+        double emin = fmin(q[i][0], q[j][0]);
+        double yij = 2.0 * emin * emin * (1.0 - c) / (Evis * Evis);
+        if (yij < best) { best = yij; bi = i; bj = j; }
+      }
+    }
+    int k = alive - 1;
+    if (k >= 2 && k <= 5) y[k - 2] = best;
+    for (int m = 0; m < 4; ++m) q[bi][m] += q[bj][m];
+    on[bj] = false;
+    --alive;
+  }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(64) k_observables(Cfg C, gaps_events ev, int64_t n, double* obs) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double ps[kObsMax][4];
+  double jets[kObsMax][4];
+  bool on[kObsMax];
+  double* o = obs + e * kNObs;
+  for (int k = 0; k < kNObs; ++k) o[k] = 0.0;
+  int np = 0, nn = ev.n[e];
+  if (nn > ev.max_slots) nn = ev.max_slots;
+  double lm[4] = {0, 0, 0, 0}, lp[4] = {0, 0, 0, 0}, bal[4] = {0, 0, 0, 0};
+  for (int q = 0; q < nn; ++q) {
+    int64_t k = (int64_t)q * ev.cap + e;
+    double p[4] = {ev.E[k], ev.px[k], ev.py[k], ev.pz[k]};
+    int st = ev.status[k];
+    for (int m = 0; m < 4; ++m) bal[m] += st > 0 ? p[m] : -p[m];
+    if (st <= 0) continue;
+    int pid = ev.pid[k];
+    if (pid == 11) { for (int m = 0; m < 4; ++m) lm[m] = p[m]; }
+    else if (pid == -11) { for (int m = 0; m < 4; ++m) lp[m] = p[m]; }
+    else if (is_parton(pid) && np < kObsMax) { for (int m = 0; m < 4; ++m) ps[np][m] = p[m]; ++np; }
+  }
+  if (C.process == 0) bal[0] -= C.sqrt_s;
+  double imb = 0.0;
+  for (int m = 0; m < 4; ++m) imb = fmax(imb, fabs(bal[m]));
+  o[9] = np;
+  o[10] = imb;
+  if (C.process == 0) {
+    o[0] = 1.0 - thrust(ps, np);
+    double y[4];
+    durham(ps, np, y, on);
+    for (int k = 0; k < 4; ++k) o[1 + k] = y[k];
+    return;
+  }
+  double Z[4];
+  for (int m = 0; m < 4; ++m) Z[m] = lm[m] + lp[m];
+  o[0] = sqrt(Z[1] * Z[1] + Z[2] * Z[2]);
+  o[1] = rapidity(Z);
+  o[2] = (Z[1] == 0.0 && Z[2] == 0.0) ? 0.0 : atan2(Z[2], Z[1]);
+  double dphi = fabs(atan2(lm[2], lm[1]) - atan2(lp[2], lp[1]));
+  if (dphi > kPi) dphi = 2.0 * kPi - dphi;
+  double cth = tanh(0.5 * (pseudorap(lm) - pseudorap(lp)));
+  o[3] = tan(0.5 * (kPi - dphi)) * sqrt(fmax(0.0, 1.0 - cth * cth));
+  int nq = 0;
+  for (int i = 0; i < np; ++i)
+    if (ps[i][1] * ps[i][1] + ps[i][2] * ps[i][2] > 1e-18 * C.S) {
+      for (int m = 0; m < 4; ++m) ps[nq][m] = ps[i][m];
+      ++nq;
+    }
+  int nj = antikt(ps, nq, 0.4, jets, on);
+  int njet = 0, n_eta = 0;
+  double j1[4] = {0, 0, 0, 0}, j2[4] = {0, 0, 0, 0};
+  double j1pt = 0.0, j2pt = 0.0, j1eta = 0.0;
+  bool have1 = false;
+  for (int k = 0; k < nj; ++k) {
+    double pt = sqrt(jets[k][1] * jets[k][1] + jets[k][2] * jets[k][2]);
+    double et = pseudorap(jets[k]);
+    if (fabs(et) < 5.0) {
+      if (n_eta == 0) j1pt = pt;
+      else if (n_eta == 1) j2pt = pt;
+      ++n_eta;
+    }
+    if (pt > 5.0 && !have1) { j1eta = et; have1 = true; }
+    if (pt > 5.0 && fabs(et) < 5.0) {
+      if (njet == 0) { for (int m = 0; m < 4; ++m) j1[m] = jets[k][m]; }
+      else if (njet == 1) { for (int m = 0; m < 4; ++m) j2[m] = jets[k][m]; }
+      ++njet;
+    }
+  }
+  o[4] = njet;
+  o[5] = j1pt;
+  o[6] = j1eta;
+  o[7] = j2pt;
+  if (njet >= 2) {
+    double dy = pseudorap(j1) - pseudorap(j2);
+    double dp = fabs(atan2(j1[2], j1[1]) - atan2(j2[2], j2[1]));
+    if (dp > kPi) dp = 2.0 * kPi - dp;
+    o[8] = sqrt(dy * dy + dp * dp);
+  } else {
+    o[8] = -1.0;
+  }
+}
+
+__global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
+                            int nbins, double* sumw, double* sumw2) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = obs[e * kNObs + col];
+  if (!(v >= lo && v < hi)) return;
+  int b = (int)((v - lo) / (hi - lo) * nbins);
+  if (b >= nbins) b = nbins - 1;
+  double ww = w ? w[e] : 1.0;
+  atomicAdd(sumw + b, ww);
+  atomicAdd(sumw2 + b, ww * ww);
+}
+
+}  // namespace gaps

@@ -1,0 +1,199 @@
+// The shower kernel: the max-veto algorithm of section 2 with the initial-state
+// extension of appendix A and the dipole kinematics of appendix B, one event
+// per lane.  Lanes fetch events from a work queue, so the launch is persistent
+// and finished lanes refill at once; every lane keeps its event record and its
+// channel cache in slot-major scratch (stride = lanes), so a wave's accesses
+// coalesce whatever events the lanes hold.
+#include "kernels.hpp"
+
+namespace gaps {
+
+namespace {
+
+// channel cache word: emitter slot, spectator slot, side, type, heavy flavour, alive
+__device__ __forceinline__ uint32_t pack_info(const Chan& ch) {
+  return (uint32_t)ch.i | ((uint32_t)ch.k << 8) | ((uint32_t)ch.side << 16) | ((uint32_t)ch.type << 17) |
+         ((uint32_t)ch.heavy << 19) | ((uint32_t)ch.alive << 21);
+}
+
+// rebuild the channel list in (slot, side) order; -1 on a broken colour line
+__device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& S, int& nch) {
+  int m = 0;
+  Chan ch;
+  for (int i = 0; i < n; ++i) {
+    int64_t oi = R.o(i);
+    if (R.col[oi] == 0 && R.acol[oi] == 0) continue;
+    for (int side = 0; side < 2; ++side) {
+      int tag = side == 0 ? R.effc(i) : R.effa(i);
+      if (!tag) continue;
+      int k = -1;
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        int other = side == 0 ? R.effa(j) : R.effc(j);
+        if (other == tag) { k = j; break; }
+      }
+      if (k < 0) return -1;
+      chan_setup(C, R, i, side, k, ch);
+      int64_t oc = (int64_t)m * R.G + R.lane;
+      S.cinfo[oc] = pack_info(ch);
+      S.ctlim[oc] = ch.tlim;
+      S.clntlim[oc] = ch.lntlim;
+      S.cinvc[oc] = ch.invc;
+      ++m;
+    }
+  }
+  nch = m;
+  return 0;
+}
+
+__device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const gaps_events& out,
+                           const Rec& R, const Scratch& S, const ShowerArgs& A, unsigned long long* st) {
+  const int M = out.max_slots < kMaxSlots ? out.max_slots : kMaxSlots;
+  const int64_t ci = in.cap, co = out.cap;
+  int n = in.n[e];
+  uint32_t flags = in.flags ? in.flags[e] : 0u;
+  int maxtag = 0;
+  bool fits = n >= 0 && n <= M && n <= in.max_slots;
+  if (fits) {
+    for (int q = 0; q < n; ++q) {
+      int64_t k = (int64_t)q * ci + e, o = R.o(q);
+      R.E[o] = in.E[k]; R.px[o] = in.px[k]; R.py[o] = in.py[k]; R.pz[o] = in.pz[k];
+      R.pid[o] = in.pid[k]; R.col[o] = in.col[k]; R.acol[o] = in.acol[k]; R.st[o] = in.status[k];
+      maxtag = in.col[k] > maxtag ? in.col[k] : maxtag;
+      maxtag = in.acol[k] > maxtag ? in.acol[k] : maxtag;
+    }
+  }
+  const int64_t id = in.id[e];
+  double T = in.t_start[e], lnT = log(T), t1 = 0.0;
+  uint32_t ncyc = 0, ntri = 0, nacc = 0, nviol = 0;
+  int nch = 0;
+  if (!fits) {
+    flags |= fOverflow;
+  } else if (build_channels(C, R, n, S, nch) < 0) {
+    flags |= fColour;
+  } else {
+    uint32_t cycle = 0;
+    const uint64_t seed = A.seed;
+    const uint32_t stream = A.stream;
+    for (;;) {
+      if (cycle >= kMaxCycles) { flags |= fMaxCyc; break; }
+      double best = -INFINITY;
+      int win = -1;
+      uint32_t curblk = 0xFFFFFFFFu;
+      double ub[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int c = 0; c < nch; ++c) {
+        int64_t oc = (int64_t)c * R.G + R.lane;
+        uint32_t info = S.cinfo[oc];
+        if (!((info >> 21) & 1u)) continue;
+        double tlim = S.ctlim[oc], lntlim = S.clntlim[oc];
+        int type = (info >> 17) & 3u, heavy = (info >> 19) & 3u;
+        double tcut, lntcut, m2 = 0.0;
+        if (heavy == 1) { tcut = C.tch_c; lntcut = C.ln_tch_c; m2 = C.mc2; }
+        else if (heavy == 2) { tcut = C.tch_b; lntcut = C.ln_tch_b; m2 = C.mb2; }
+        else if (type == kFF) { tcut = C.t_cut; lntcut = C.ln_tc; }
+        else { tcut = C.tc_is; lntcut = C.ln_tcis; }
+        double Tch = T < tlim ? T : tlim;
+        double lnTch = lnT < lntlim ? lnT : lntlim;
+        if (!(Tch > tcut)) continue;
+        uint32_t slot = 2u * (info & 0xFFu) + ((info >> 16) & 1u);
+        if ((slot >> 2) != curblk) {
+          curblk = slot >> 2;
+          rng4(seed, stream, id, cycle, curblk, ub);
+        }
+        double lu = log(ub[slot & 3u]);
+        ntri += 1;
+        double invc = S.cinvc[oc];
+        double key;
+        if (!heavy) key = lnTch + lu * invc;
+        else key = log(m2 + (Tch - m2) * exp(lu * invc));
+        if (key < lntcut) continue;
+        if (key > best) { best = key; win = c; }
+      }
+      if (win < 0) break;
+      double t = exp(best);
+      uint32_t info = S.cinfo[(int64_t)win * R.G + R.lane];
+      Chan ch;
+      chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
+      double u[4];
+      rng4(seed, stream, id, cycle, 0xFFFFFFFFu, u);
+      double target = u[0] * ch.c, cum = 0.0;
+      int sel = -1;
+      for (int m = 0; m < ch.nterm; ++m) {
+        cum += ch.tc[m];
+        if (target < cum) { sel = m; break; }
+      }
+      if (sel < 0)
+        for (int m = ch.nterm - 1; m >= 0; --m)
+          if (ch.tc[m] > 0.0) { sel = m; break; }
+      double I = shape_int(ch.shape[sel], ch);
+      double z, omz;
+      shape_sample(ch.shape[sel], ch, I, u[1], z, omz);
+      double phi = 2.0 * kPi * u[2];
+      Veto v = veto_weight(C, R, ch, sel, t, z, omz);
+      if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
+      if (v.ok && u[3] < v.w) {
+        if (n + 1 > M) { flags |= fOverflow; break; }
+        emit(R, n, maxtag, ch, sel, z, omz, v, phi);
+        n += 1;
+        nacc += 1;
+        if (t1 == 0.0) t1 = t;
+        bool bad = false;
+        for (int q = 0; q < n; ++q) {
+          int64_t o = R.o(q);
+          bad |= !(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o]));
+        }
+        if (bad) { flags |= fNaN; cycle += 1; break; }
+        if (build_channels(C, R, n, S, nch) < 0) { flags |= fColour; cycle += 1; break; }
+      }
+      T = t;
+      lnT = best;
+      cycle += 1;
+    }
+    ncyc = cycle;
+  }
+  out.id[e] = id;
+  out.w[e] = in.w[e];
+  out.t_start[e] = in.t_start[e];
+  out.n[e] = fits ? n : in.n[e];
+  if (out.flags) out.flags[e] = flags;
+  if (fits) {
+    for (int q = 0; q < n && q < out.max_slots; ++q) {
+      int64_t k = (int64_t)q * co + e, o = R.o(q);
+      out.E[k] = R.E[o]; out.px[k] = R.px[o]; out.py[k] = R.py[o]; out.pz[k] = R.pz[o];
+      out.pid[k] = R.pid[o]; out.col[k] = R.col[o]; out.acol[k] = R.acol[o]; out.status[k] = R.st[o];
+    }
+  } else {
+    // record larger than the output capacity: pass the slots that fit through
+    for (int q = 0; q < n && q < out.max_slots && q < in.max_slots; ++q) {
+      int64_t k = (int64_t)q * co + e, ki = (int64_t)q * ci + e;
+      out.E[k] = in.E[ki]; out.px[k] = in.px[ki]; out.py[k] = in.py[ki]; out.pz[k] = in.pz[ki];
+      out.pid[k] = in.pid[ki]; out.col[k] = in.col[ki]; out.acol[k] = in.acol[ki]; out.status[k] = in.status[ki];
+    }
+  }
+  if (out.n_cycles) out.n_cycles[e] = ncyc;
+  if (out.n_trials) out.n_trials[e] = ntri;
+  if (out.n_accept) out.n_accept[e] = nacc;
+  if (out.n_viol) out.n_viol[e] = nviol;
+  if (out.t1) out.t1[e] = t1;
+  if (st) {
+    atomicAdd(st + 0, (unsigned long long)ncyc);
+    atomicAdd(st + 1, (unsigned long long)ntri);
+    atomicAdd(st + 2, (unsigned long long)nacc);
+    atomicAdd(st + 3, (unsigned long long)nviol);
+  }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S,
+                                                      ShowerArgs A) {
+  const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  Rec R{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, S.lanes, lane};
+  for (;;) {
+    unsigned long long e = atomicAdd(S.queue, 1ULL);
+    if (e >= (unsigned long long)A.n) break;
+    shower_one(C, in, (int64_t)e, out, R, S, A, A.stats);
+  }
+}
+
+}  // namespace gaps
