@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--events", type=int, default=1_000_000)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--compact-every", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=150_000)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -83,7 +85,8 @@ def main():
     stats = torch.zeros(binding.NSTATS, dtype=torch.uint64, device="cuda")
 
     for _ in range(args.warmup):
-        G.shower(ev_in, seed, out=ev_out, block=args.block)
+        G.shower(ev_in, seed, out=ev_out, block=args.block, compact_every=args.compact_every,
+                 variant=args.variant)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
@@ -94,7 +97,8 @@ def main():
     for k in range(args.steps):
         stats.zero_()
         starts[k].record(stream)
-        G.shower(ev_in, seed, out=ev_out, block=args.block, stats=stats)
+        G.shower(ev_in, seed, out=ev_out, block=args.block, compact_every=args.compact_every,
+                 variant=args.variant, stats=stats)
         ends[k].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -134,16 +138,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "pp_nlo_1m: NLO-matched Z production at 13 TeV, MC@NLO-style S/H "
                                "events, toy PDF grid 100x50, 10^6 events per step, FP64 kinematics",
-                   "events_per_step": n, "mode": "plain", "max_slots": workloads.MAX_SLOTS},
+                   "events_per_step": n, "mode": "plain", "max_slots": workloads.MAX_SLOTS,
+                   "kernel": "k_shower_lanes" if args.variant == 1 else "k_shower_wave",
+                   "block": args.block or 256, "compact_every": args.compact_every or 4},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_shower_lanes", "launch_ms": mean_launch_s * 1e3,
+                     "kernel": "k_shower_lanes" if args.variant == 1 else "k_shower_wave",
+                     "launch_ms": mean_launch_s * 1e3,
                      "ops_per_launch": ops},
         "shower_stats": {"trials_per_event": trials / n, "winner_cycles_per_event": winners / n,
                          "accepted_per_event": accepts / n,
                          "veto_trials_per_accepted_emission": winners / max(accepts, 1.0),
                          "channel_trials_per_accepted_emission": trials / max(accepts, 1.0),
-                         "weight_violations": viol, "mean_final_multiplicity": nfin},
+                         "weight_violations": viol, "mean_final_multiplicity": nfin,
+                         "active_lane_fraction": (st[binding.ST_LANE_ACTIVE] / st[binding.ST_LANE_ITERS]
+                                                  if st[binding.ST_LANE_ITERS] > 0 else None)},
         "component_s": {"hard_events": t_hard, "shower_per_step": ms_per_step / 1e3, "observables": t_obs},
     }
     if not args.no_cpu:

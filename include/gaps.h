@@ -111,11 +111,15 @@ typedef struct {
     int mode;            /* GAPS_MODE_* */
     int block;           /* threads per block, multiple of 64 (0: 256) */
     int grid;            /* blocks of the persistent launch (0: fill the GPU) */
-    int compact_every;   /* cycles between wave refills (0: 8) */
+    int compact_every;   /* cycles between wave refills (0: 4) */
     float* trial_log;    /* LOG mode: device [log_cap][5] floats */
     int64_t log_cap;
     unsigned long long* log_count; /* LOG mode: device counter */
     unsigned long long* stats;     /* optional device [GAPS_NSTATS] */
+    int variant;         /* 0: wave-cooperative kernel (default)
+                            1: one event per lane, no cooperation (reference) */
+    int waves_per_simd;  /* wave kernel register budget: 2, 3 or 4 resident
+                            waves per SIMD (0: 2) */
 } gaps_params;
 
 /* Create a context: validates the configuration, uploads the PDF grid and

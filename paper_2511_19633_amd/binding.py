@@ -51,7 +51,7 @@ class GapsEvents(C.Structure):
 class GapsParams(C.Structure):
     _fields_ = [("mode", C.c_int), ("block", C.c_int), ("grid", C.c_int), ("compact_every", C.c_int),
                 ("trial_log", C.c_void_p), ("log_cap", C.c_int64), ("log_count", C.c_void_p),
-                ("stats", C.c_void_p)]
+                ("stats", C.c_void_p), ("variant", C.c_int), ("waves_per_simd", C.c_int)]
 
 
 _lib = None
@@ -179,11 +179,13 @@ class Gaps:
 
     def shower(self, ev_in: DeviceEvents, seed: int, n: int | None = None, out=None, max_slots=None,
                mode=MODE_PLAIN, block=0, grid=0, compact_every=0, stats=None, trial_log=None,
-               log_count=None, stream=None) -> DeviceEvents:
+               log_count=None, variant=0, waves_per_simd=0, stream=None) -> DeviceEvents:
         n = ev_in.cap if n is None else n
         ev_out = out if out is not None else DeviceEvents(n, max_slots or ev_in.max_slots)
         p = GapsParams()
         p.mode, p.block, p.grid, p.compact_every = mode, block, grid, compact_every
+        p.variant = variant
+        p.waves_per_simd = waves_per_simd
         p.stats = stats.data_ptr() if stats is not None else None
         if trial_log is not None:
             p.trial_log = trial_log.data_ptr()

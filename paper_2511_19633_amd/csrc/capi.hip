@@ -38,10 +38,10 @@ bool bad_events(const gaps_events* e, int64_t n, int min_slots) {
 unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 gaps_status ensure_scratch(gaps_ctx c, int64_t lanes, int slots) {
-  const int nch = 2 * slots;
+  const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   size_t per_lane = (size_t)slots * (4 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int8_t)) +
-                    (size_t)nch * (sizeof(uint32_t) + 3 * sizeof(double));
-  size_t need = per_lane * (size_t)lanes + 256 * 16 + 64;
+                    (size_t)nch * (sizeof(uint32_t) + 9 * sizeof(double));
+  size_t need = per_lane * (size_t)lanes + 256 * 24 + 64;
   if (need > c->scratch_bytes || c->S.lanes != lanes || c->S.max_slots != slots) {
     if (need > c->scratch_bytes) {
       if (c->scratch) (void)hipFree(c->scratch);
@@ -66,6 +66,8 @@ gaps_status ensure_scratch(gaps_ctx c, int64_t lanes, int slots) {
     S.st = (int8_t*)take(ps);
     S.cinfo = (uint32_t*)take(cs * 4);
     S.ctlim = (double*)take(cs * 8); S.clntlim = (double*)take(cs * 8); S.cinvc = (double*)take(cs * 8);
+    S.cc = (double*)take(cs * 8); S.cs = (double*)take(cs * 8); S.czlo = (double*)take(cs * 8);
+    S.comzhi = (double*)take(cs * 8); S.cI1 = (double*)take(cs * 8); S.cI2 = (double*)take(cs * 8);
     S.queue = (unsigned long long*)take(64);
     if ((size_t)(p - (char*)c->scratch) > c->scratch_bytes) return GAPS_ENOMEM;
   }
@@ -197,8 +199,15 @@ gaps_status gaps_shower(gaps_ctx c, const gaps_events* in, int64_t n, const gaps
   int block = P.block > 0 ? P.block : 256;
   if (block % 64 != 0 || block > 256) return GAPS_EINVAL;
   if (n == 0) return GAPS_OK;
+  if (P.variant < 0 || P.variant > 1) return GAPS_EINVAL;
+  const int wps = P.waves_per_simd > 0 ? P.waves_per_simd : 2;
+  if (wps < 2 || wps > 4) return GAPS_EINVAL;
+  const void* kern = P.variant == 1 ? (const void*)gaps::k_shower_lanes
+                     : wps == 2     ? (const void*)gaps::k_shower_wave
+                     : wps == 3     ? (const void*)gaps::k_shower_wave3
+                                    : (const void*)gaps::k_shower_wave4;
   int per_cu = 0;
-  GAPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gaps::k_shower_lanes, block, 0));
+  GAPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0));
   if (per_cu < 1) per_cu = 1;
   int64_t grid = P.grid > 0 ? P.grid : (int64_t)per_cu * c->cus;
   int64_t need_blocks = (n + block - 1) / block;
@@ -209,12 +218,13 @@ gaps_status gaps_shower(gaps_ctx c, const gaps_events* in, int64_t n, const gaps
   hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->S.queue, (int64_t)1, 0ULL);
   gaps::ShowerArgs A{};
   A.mode = P.mode;
-  A.compact_every = P.compact_every > 0 ? P.compact_every : 8;
+  A.compact_every = P.compact_every > 0 ? P.compact_every : 4;
   A.stream = 0u;
   A.seed = seed;
   A.n = n;
   A.stats = P.stats;
-  hipLaunchKernelGGL(gaps::k_shower_lanes, dim3((unsigned)grid), dim3(block), 0, stream, c->C, *in, *out, c->S, A);
+  void* args[] = {(void*)&c->C, (void*)in, (void*)out, (void*)&c->S, (void*)&A};
+  GAPS_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(block), args, 0, stream));
   GAPS_HIP(hipGetLastError());
   return GAPS_OK;
 }

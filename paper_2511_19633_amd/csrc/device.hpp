@@ -25,7 +25,6 @@ __host__ __device__ constexpr int ent_s1(int f, int T) { return 8 + 8 * f + T; }
 __host__ __device__ constexpr int ent_s3(int f, int T) { return 40 + 8 * f + T; }
 
 constexpr int kMaxSlots = 256;
-constexpr int kMaxTerms = 11;
 constexpr uint32_t kMaxCycles = 2000000u;
 
 enum : int { kFF = 0, kFI = 1, kIF = 2, kII = 3 };
@@ -118,6 +117,31 @@ __device__ inline double pdf_xf(const Cfg& C, int tab, double x, double q2) {
   return (1.0 - b) * ((1.0 - a) * f00 + a * f10) + b * ((1.0 - a) * f01 + a * f11);
 }
 
+// the same lookup with ln(q2) supplied by the caller (shared by the two
+// lookups of a PDF ratio)
+__device__ inline double pdf_xf_l(const Cfg& C, int tab, double x, double q2, double lq) {
+  if (!(x > 0.0) || x >= 1.0 || !(q2 > 0.0)) return 0.0;
+  double lx = log(x);
+  if (lx < C.lnx0 || lq < C.lnq0 || lq > C.lnq1) return 0.0;
+  double fx = (lx - C.lnx0) / C.dlnx;
+  int i = (int)fx;
+  if (i > C.nx - 2) i = C.nx - 2;
+  double a = fx - (double)i;
+  double fq = (lq - C.lnq0) / C.dlnq;
+  int j = (int)fq;
+  if (j > C.nq - 2) j = C.nq - 2;
+  double b = fq - (double)j;
+  const float* F = C.pdf + (size_t)tab * C.nq * C.nx;
+  double f00 = F[j * C.nx + i], f10 = F[j * C.nx + i + 1];
+  double f01 = F[(j + 1) * C.nx + i], f11 = F[(j + 1) * C.nx + i + 1];
+  return (1.0 - b) * ((1.0 - a) * f00 + a * f10) + b * ((1.0 - a) * f01 + a * f11);
+}
+
+__device__ __forceinline__ double pdf_f_l(const Cfg& C, int tab, double x, double q2, double lq) {
+  double xf = pdf_xf_l(C, tab, x, q2, lq);
+  return xf > 0.0 ? xf / x : 0.0;
+}
+
 __device__ __forceinline__ double pdf_f(const Cfg& C, int tab, double x, double q2) {
   double xf = pdf_xf(C, tab, x, q2);
   return xf > 0.0 ? xf / x : 0.0;
@@ -128,13 +152,15 @@ __device__ __forceinline__ double dot4(const double* a, const double* b) {
 }
 
 // ---------------------------------------------------------------------------
-// Working event record of one lane: slot-major arrays with stride G (lanes).
+// Working event record of one lane: particle q of state slot `lane` lives at
+// q * sq + lane * sl (slot-major: sq = lanes, sl = 1; lane-major: sq = 1,
+// sl = slots).
 struct Rec {
   double *E, *px, *py, *pz;
   int32_t *pid, *col, *acol;
   int8_t* st;
-  int64_t G, lane;
-  __device__ __forceinline__ int64_t o(int q) const { return (int64_t)q * G + lane; }
+  int64_t sq, sl, lane;
+  __device__ __forceinline__ int64_t o(int q) const { return (int64_t)q * sq + lane * sl; }
   __device__ __forceinline__ void get(int q, double p[4]) const {
     int64_t k = o(q);
     p[0] = E[k]; p[1] = px[k]; p[2] = py[k]; p[3] = pz[k];
@@ -154,12 +180,17 @@ struct Rec {
 
 // ---------------------------------------------------------------------------
 // Channel: dipole end (emitter i, spectator k, colour side) with its constants.
+// Its overestimate terms are enumerated on demand by term_at(); the z
+// integrals of the (at most two) z shapes a channel uses are I1 and I2.
 struct Chan {
-  int i, k, side, type, heavy, alive, nterm;
+  int i, k, side, type, heavy, alive, ebin, kbin, pidi, pidk, nterm;
   double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
-  double zlo, zhi, omzlo, omzhi, c, invc;
-  int kern[kMaxTerms], shape[kMaxTerms], flav[kMaxTerms];
-  double coefR[kMaxTerms], tc[kMaxTerms];
+  double zlo, zhi, omzlo, omzhi, I1, I2, c, invc;
+};
+
+struct Term {
+  int kern, shape, flav;
+  double coefR, I;
 };
 
 __device__ __forceinline__ int eta_bin(double eta) {
@@ -170,12 +201,12 @@ __device__ __forceinline__ int eta_bin(double eta) {
   return (int)b;
 }
 
-__device__ __forceinline__ double shape_int(int sh, const Chan& ch) {
+__device__ __forceinline__ double shape_int(int sh, double zlo, double zhi, double omzlo, double omzhi) {
   switch (sh) {
-    case kSoft: return log(ch.omzlo / ch.omzhi);
-    case kFlat: return ch.zhi - ch.zlo;
-    case kS1: return log(ch.zhi / ch.omzhi) - log(ch.zlo / ch.omzlo);
-    default: return log(ch.zhi / ch.zlo);
+    case kSoft: return log(omzlo / omzhi);
+    case kFlat: return zhi - zlo;
+    case kS1: return log(zhi / omzhi) - log(zlo / omzlo);
+    default: return log(zhi / zlo);
   }
 }
 
@@ -204,19 +235,65 @@ __device__ __forceinline__ double shape_val(int sh, double z, double omz) {
   }
 }
 
-__device__ __forceinline__ void push_term(Chan& ch, int kern, int shape, int flav, double coefR) {
-  int m = ch.nterm++;
-  ch.kern[m] = kern; ch.shape[m] = shape; ch.flav[m] = flav; ch.coefR[m] = coefR; ch.tc[m] = 0.0;
+__device__ __forceinline__ bool is_fs(const Chan& ch) { return ch.type == kFF || ch.type == kFI; }
+
+__device__ __forceinline__ int n_terms(const Chan& ch, int nf) {
+  if (is_fs(ch)) return ch.pidi == 21 ? 1 + nf : 1;
+  return ch.pidi == 21 ? 1 + 2 * nf : 2;
 }
 
-// Constants of dipole end (i, side) with spectator k: invariant, momentum
-// fractions, kinematic limit (appendix B), widest z range (at the cutoff), and
-// the overestimate terms G = c/t (appendix A.1) with their z integrals.
+// Term m of a channel: splitting family, z shape, flavour, and the constant in
+// front of the shape (kernel coefficient, and the PDF-ratio / Jacobian bound
+// of the overestimate table for initial-state and final-initial channels).
+__device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
+  Term t;
+  if (is_fs(ch)) {
+    double R = 1.0;
+    if (ch.type == kFI) R = C.bound[ent_fi(pdf_tab(ch.pidk)) * kNB + ch.kbin];
+    if (ch.pidi == 21) {
+      if (m == 0) { t.kern = kGGG; t.shape = kSoft; t.flav = 0; t.coefR = kCA * R; t.I = ch.I1; }
+      else { t.kern = kGQQ; t.shape = kFlat; t.flav = m; t.coefR = 0.5 * kTR * R; t.I = ch.I2; }
+    } else {
+      t.kern = kQQG; t.shape = kSoft; t.flav = 0; t.coefR = 2.0 * kCF * R; t.I = ch.I1;
+    }
+    return t;
+  }
+  const bool ii = ch.type == kII;
+  const int sh2 = ii ? kS3 : kS1;
+  if (ch.pidi == 21) {
+    if (m == 0) {
+      t.kern = kC; t.shape = kS1; t.flav = 0; t.coefR = C.bound[ent_s1(famC, 0) * kNB + ch.ebin]; t.I = ch.I1;
+    } else {
+      int a = m <= C.nf ? m : -(m - C.nf);
+      int T = pdf_tab(a);
+      t.kern = kD; t.shape = sh2; t.flav = a;
+      t.coefR = ii ? C.bound[ent_s3(famD, T) * kNB + ch.ebin] : C.bound[ent_s1(famD, T) * kNB + ch.ebin];
+      t.I = ch.I2;
+    }
+  } else {
+    int T = pdf_tab(ch.pidi);
+    if (m == 0) {
+      t.kern = kA; t.shape = kS1; t.flav = 0; t.coefR = C.bound[ent_s1(famA, T) * kNB + ch.ebin]; t.I = ch.I1;
+    } else {
+      t.kern = kB; t.shape = sh2; t.flav = 0;
+      t.coefR = ii ? C.bound[ent_s3(famB, T) * kNB + ch.ebin] : C.bound[ent_s1(famB, T) * kNB + ch.ebin];
+      t.I = ch.I2;
+    }
+  }
+  return t;
+}
+
+// Channel constants of dipole end (i, side) with spectator k: invariant,
+// momentum fractions, kinematic limit (appendix B), the widest z range (at the
+// cutoff), and the total overestimate c of G = c/t (appendix A.1).
 __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, int k, Chan& ch) {
   ch.i = i; ch.k = k; ch.side = side; ch.alive = 0; ch.heavy = 0; ch.nterm = 0;
-  ch.m2 = 0.0; ch.c = 0.0; ch.invc = 0.0;
+  ch.m2 = 0.0; ch.c = 0.0; ch.invc = 0.0; ch.ebin = 0; ch.kbin = 0;
+  ch.zlo = ch.zhi = ch.omzlo = ch.omzhi = ch.I1 = ch.I2 = 0.0;
   int sti = R.st[R.o(i)], stk = R.st[R.o(k)];
   bool isE = sti < 0, isS = stk < 0;
+  ch.pidi = R.pid[R.o(i)];
+  ch.pidk = R.pid[R.o(k)];
   ch.type = isE ? (isS ? kII : kIF) : (isS ? kFI : kFF);
   double pi[4], pk[4];
   R.get(i, pi);
@@ -229,6 +306,7 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
   ch.tcut = tc;
   ch.lntcut = ch.type == kFF ? C.ln_tc : C.ln_tcis;
   ch.tlim = 0.0;
+  ch.lntlim = 0.0;
   if (!(s > 0.0)) return;
   switch (ch.type) {
     case kFF: ch.tlim = s / 4.0; d = 4.0 * tc / s; break;
@@ -239,11 +317,13 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
       d = 4.0 * tc * eta / (s * (1.0 - eta) * (1.0 - eta));
       break;
   }
-  int pidi = R.pid[R.o(i)];
   if (isE) {
-    int ap = pidi < 0 ? -pidi : pidi;
+    int ap = ch.pidi < 0 ? -ch.pidi : ch.pidi;
     if (ap == 4) { ch.heavy = 1; ch.m2 = C.mc2; ch.tcut = C.tch_c; ch.lntcut = C.ln_tch_c; }
     if (ap == 5) { ch.heavy = 2; ch.m2 = C.mb2; ch.tcut = C.tch_b; ch.lntcut = C.ln_tch_b; }
+    if (pdf_tab(ch.pidi) < 0) return;
+  } else if (ch.type == kFI && pdf_tab(ch.pidk) < 0) {
+    return;
   }
   if (!(d < 1.0) || !(ch.tlim > ch.tcut)) return;
   ch.lntlim = log(ch.tlim);
@@ -259,50 +339,39 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
     ch.zlo = (4.0 * eta + (1.0 - eta) * (1.0 - eta) * d) / (2.0 * ((1.0 + eta) + (1.0 - eta) * sq));
     ch.omzlo = 1.0 - ch.zlo;
   }
-  if (!isE) {
-    double Rv = 1.0;
-    if (ch.type == kFI) {
-      int Tk = pdf_tab(R.pid[R.o(k)]);
-      if (Tk < 0) return;
-      Rv = C.bound[ent_fi(Tk) * kNB + eta_bin(etak)];
-    }
-    if (pidi == 21) {
-      push_term(ch, kGGG, kSoft, 0, kCA * Rv);
-      for (int f = 1; f <= C.nf; ++f) push_term(ch, kGQQ, kFlat, f, 0.5 * kTR * Rv);
-    } else {
-      push_term(ch, kQQG, kSoft, 0, 2.0 * kCF * Rv);
-    }
-  } else {
-    int bin = eta_bin(eta);
-    int sh2 = ch.type == kII ? kS3 : kS1;
-    if (pidi == 21) {
-      push_term(ch, kC, kS1, 0, C.bound[ent_s1(famC, 0) * kNB + bin]);
-      for (int m = 0; m < 10; ++m) {
-        int a = m < 5 ? m + 1 : -(m - 4);
-        int aa = a < 0 ? -a : a;
-        if (aa > C.nf) continue;
-        int T = pdf_tab(a);
-        double Rv = ch.type == kII ? C.bound[ent_s3(famD, T) * kNB + bin] : C.bound[ent_s1(famD, T) * kNB + bin];
-        push_term(ch, kD, sh2, a, Rv);
-      }
-    } else {
-      int T = pdf_tab(pidi);
-      if (T < 0) return;
-      push_term(ch, kA, kS1, 0, C.bound[ent_s1(famA, T) * kNB + bin]);
-      double Rv = ch.type == kII ? C.bound[ent_s3(famB, T) * kNB + bin] : C.bound[ent_s1(famB, T) * kNB + bin];
-      push_term(ch, kB, sh2, 0, Rv);
-    }
-  }
+  if (isE) ch.ebin = eta_bin(eta);
+  if (ch.type == kFI) ch.kbin = eta_bin(etak);
+  int sh1 = is_fs(ch) ? kSoft : kS1;
+  int sh2 = is_fs(ch) ? kFlat : (ch.type == kII ? kS3 : kS1);
+  ch.I1 = shape_int(sh1, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi);
+  ch.I2 = shape_int(sh2, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi);
+  ch.nterm = n_terms(ch, C.nf);
   double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double c = 0.0;
   for (int m = 0; m < ch.nterm; ++m) {
-    ch.tc[m] = af * ch.coefR[m] * shape_int(ch.shape[m], ch);
-    c += ch.tc[m];
+    Term t = term_at(C, ch, m);
+    c += af * t.coefR * t.I;
   }
   if (!(c > 0.0)) return;
   ch.c = c;
   ch.invc = 1.0 / c;
   ch.alive = 1;
+}
+
+// Splitting family (term) of the winner in proportion to the overestimates
+__device__ inline Term select_term(const Cfg& C, const Chan& ch, double u) {
+  double af = C.as_over / (2.0 * kPi) * C.over_scale;
+  double target = u * ch.c, cum = 0.0;
+  for (int m = 0; m < ch.nterm; ++m) {
+    Term t = term_at(C, ch, m);
+    cum += af * t.coefR * t.I;
+    if (target < cum) return t;
+  }
+  for (int m = ch.nterm - 1; m >= 0; --m) {
+    Term t = term_at(C, ch, m);
+    if (af * t.coefR * t.I > 0.0) return t;
+  }
+  return term_at(C, ch, 0);
 }
 
 // transverse momentum of size sqrt(tp) at azimuth phi, orthogonal to pa, pb
@@ -370,77 +439,80 @@ __device__ __forceinline__ void is_vars(int type, double z, double omz, double t
   uv = x * r / omz;
 }
 
-// acceptance weight of the winner trial
-__device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, int m, double t, double z,
-                                   double omz) {
+// acceptance weight of the winner trial: kinematic variables and phase-space
+// check per dipole type, the splitting kernel, then one shared pair of PDF
+// lookups for the ratio (spectator for FI, emitter for IF and II)
+__device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, const Term& tm, double t,
+                                   double z, double omz) {
   Veto r;
   r.ok = 0; r.x = 0.0; r.omx = 0.0; r.y = 0.0; r.uv = 0.0; r.w = 0.0;
-  double W = 0.0, s = ch.s;
-  int kern = ch.kern[m];
-  if (ch.type == kFF) {
-    double y = t / (z * omz * s);
+  const double s = ch.s;
+  const int kern = tm.kern, type = ch.type;
+  const bool fs = type == kFF || type == kFI;
+  double x = 0.0, omx = 0.0, y = 0.0, uv = 0.0;
+  if (type == kFF) {
+    y = t / (z * omz * s);
     if (!(y < 1.0)) return r;
-    double den1 = omz + z * y;
-    double P;
-    if (kern == kQQG) P = kCF * (2.0 / den1 - (1.0 + z));
-    else if (kern == kGGG) P = 0.5 * kCA * (2.0 / den1 - 2.0 + z * omz);
-    else P = 0.5 * kTR * (1.0 - 2.0 * z * omz);
-    W = (1.0 - y) * P;
-    r.y = y;
-  } else if (ch.type == kFI) {
+  } else if (type == kFI) {
     double kap = t / (z * omz * s);
-    double x = 1.0 / (1.0 + kap), omx = kap * x;
+    x = 1.0 / (1.0 + kap);
+    omx = kap * x;
     if (!(x > ch.etak)) return r;
-    double den1 = omz + omx;
-    double P;
+  } else {
+    is_vars(type, z, omz, t, s, x, uv);
+    if (!(x > ch.eta)) return r;
+    if (type == kIF && !(uv < 1.0)) return r;
+    omx = 1.0 - x;
+  }
+  // splitting kernel (and the IF/II Jacobian)
+  double P, J = 1.0;
+  if (fs) {
+    const double den1 = type == kFF ? omz + z * y : omz + omx;
     if (kern == kQQG) P = kCF * (2.0 / den1 - (1.0 + z));
     else if (kern == kGGG) P = 0.5 * kCA * (2.0 / den1 - 2.0 + z * omz);
     else P = 0.5 * kTR * (1.0 - 2.0 * z * omz);
-    int Tk = pdf_tab(R.pid[R.o(ch.k)]);
-    if (Tk < 0) return r;
-    double den = pdf_f(C, Tk, ch.etak, t);
-    double pr = den > 0.0 ? pdf_f(C, Tk, ch.etak / x, t) / den : 0.0;
-    W = P * pr;
-    r.x = x; r.omx = omx;
   } else {
-    double x, uv;
-    is_vars(ch.type, z, omz, t, s, x, uv);
-    if (!(x > ch.eta)) return r;
-    if (ch.type == kIF && !(uv < 1.0)) return r;
-    double omx = 1.0 - x, P, J;
-    int Ti = pdf_tab(R.pid[R.o(ch.i)]);
-    if (Ti < 0) return r;
-    if (ch.type == kIF) {
-      J = 1.0 / (uv + x - 2.0 * uv * x);
-      switch (kern) {
-        case kA: P = kCF * (2.0 / (omx + uv) - (1.0 + x)); break;
-        case kB: P = kTR * (1.0 - 2.0 * x * omx); break;
-        case kC: P = kCA * (1.0 / (omx + uv) + omx / x - 1.0 + x * omx); break;
-        default: P = kCF * (x + 2.0 * omx / x); break;
-      }
-    } else {
-      J = 1.0 / z;
-      switch (kern) {
-        case kA: P = kCF * (2.0 / omx - (1.0 + x)); break;
-        case kB: P = kTR * (1.0 - 2.0 * x * omx); break;
-        case kC: P = kCA * (1.0 / omx + omx / x - 1.0 + x * omx); break;
-        default: P = kCF * (x + 2.0 * omx / x); break;
-      }
-    }
-    int Tnum, Tden;
+    const bool iff = type == kIF;
+    J = iff ? 1.0 / (uv + x - 2.0 * uv * x) : 1.0 / z;
+    const double soft = iff ? omx + uv : omx;
     switch (kern) {
-      case kA: Tnum = Ti; Tden = Ti; break;
-      case kB: Tnum = 0; Tden = Ti; break;
-      case kC: Tnum = 0; Tden = 0; break;
-      default: Tnum = pdf_tab(ch.flav[m]); Tden = 0; break;
+      case kA: P = kCF * (2.0 / soft - (1.0 + x)); break;
+      case kB: P = kTR * (1.0 - 2.0 * x * omx); break;
+      case kC: P = kCA * (1.0 / soft + omx / x - 1.0 + x * omx); break;
+      default: P = kCF * (x + 2.0 * omx / x); break;
     }
-    double den = pdf_f(C, Tden, ch.eta, t);
-    double pr = den > 0.0 ? pdf_f(C, Tnum, ch.eta / x, t) / den : 0.0;
-    double hf = ch.heavy ? (t - ch.m2) / t : 1.0;
-    W = J * P * pr * hf;
-    r.x = x; r.omx = omx; r.uv = uv;
   }
-  double over = C.over_scale * ch.coefR[m] * shape_val(ch.shape[m], z, omz);
+  // PDF ratio: which tables at which momentum fractions
+  double pr = 1.0;
+  if (type != kFF) {
+    int tnum, tden;
+    double xd, xn;
+    if (type == kFI) {
+      tnum = tden = pdf_tab(ch.pidk);
+      xd = ch.etak;
+      xn = ch.etak / x;
+    } else {
+      const int Ti = pdf_tab(ch.pidi);
+      switch (kern) {
+        case kA: tnum = Ti; tden = Ti; break;
+        case kB: tnum = 0; tden = Ti; break;
+        case kC: tnum = 0; tden = 0; break;
+        default: tnum = pdf_tab(tm.flav); tden = 0; break;
+      }
+      xd = ch.eta;
+      xn = ch.eta / x;
+    }
+    if (tnum < 0 || tden < 0) return r;
+    const double lq = log(t);
+    const double den = pdf_f_l(C, tden, xd, t, lq);
+    pr = den > 0.0 ? pdf_f_l(C, tnum, xn, t, lq) / den : 0.0;
+  }
+  double W;
+  if (type == kFF) W = (1.0 - y) * P;
+  else if (type == kFI) W = P * pr;
+  else W = J * P * pr * (ch.heavy ? (t - ch.m2) / t : 1.0);
+  r.x = x; r.omx = omx; r.y = y; r.uv = uv;
+  const double over = C.over_scale * tm.coefR * shape_val(tm.shape, z, omz);
   r.w = alphas(C, t) / C.as_over * W / over;
   r.ok = 1;
   return r;
@@ -450,40 +522,41 @@ __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, i
 __device__ inline void do_map(int type, const double* pe, const double* ps, double s, double z, double omz,
                               double v1, double v2, double phi, double* pi, double* pj, double* pk) {
   double kt[4], tp;
+  // ordering variable recomputed from the map variables, so that the new
+  // momenta are massless to rounding
+  switch (type) {
+    case kFF: tp = z * omz * v1 * s; break;
+    case kFI: tp = z * omz * v2 / v1 * s; break;
+    case kIF: tp = v2 * (1.0 - v2) * (1.0 - v1) / v1 * s; break;
+    default: tp = v2 * (1.0 - v1 - v2) / v1 * s; break;
+  }
+  kperp(pe, ps, tp, phi, kt);
   if (type == kFF) {
-    double y = v1;
-    tp = z * omz * y * s;
-    kperp(pe, ps, tp, phi, kt);
+    const double y = v1;
     for (int m = 0; m < 4; ++m) {
       pi[m] = z * pe[m] + y * omz * ps[m] + kt[m];
       pj[m] = omz * pe[m] + y * z * ps[m] - kt[m];
       pk[m] = (1.0 - y) * ps[m];
     }
   } else if (type == kFI) {
-    double x = v1, omx = v2;
-    tp = z * omz * omx / x * s;
-    kperp(pe, ps, tp, phi, kt);
-    double a = omz * omx / x, b = z * omx / x;
+    const double x = v1, omx = v2;
+    const double a = omz * omx / x, b = z * omx / x;
     for (int m = 0; m < 4; ++m) {
       pi[m] = z * pe[m] + a * ps[m] + kt[m];
       pj[m] = omz * pe[m] + b * ps[m] - kt[m];
       pk[m] = ps[m] / x;
     }
   } else if (type == kIF) {
-    double x = v1, u = v2, omx = 1.0 - x;
-    tp = u * (1.0 - u) * omx / x * s;
-    kperp(pe, ps, tp, phi, kt);
-    double a = (1.0 - u) * omx / x, b = u * omx / x;
+    const double x = v1, u = v2, omx = 1.0 - x;
+    const double a = (1.0 - u) * omx / x, b = u * omx / x;
     for (int m = 0; m < 4; ++m) {
       pi[m] = pe[m] / x;
       pj[m] = a * pe[m] + u * ps[m] - kt[m];
       pk[m] = b * pe[m] + (1.0 - u) * ps[m] + kt[m];
     }
   } else {
-    double x = v1, v = v2;
-    tp = v * (1.0 - x - v) / x * s;
-    kperp(pe, ps, tp, phi, kt);
-    double a = (1.0 - x - v) / x;
+    const double x = v1, v = v2;
+    const double a = (1.0 - x - v) / x;
     for (int m = 0; m < 4; ++m) {
       pi[m] = pe[m] / x;
       pj[m] = a * pe[m] + v * ps[m] - kt[m];
@@ -494,8 +567,8 @@ __device__ inline void do_map(int type, const double* pe, const double* ps, doub
 
 // apply the accepted emission of term m: momenta, flavours and colour tags;
 // the emitted parton is appended at slot n
-__device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, int m, double z, double omz,
-                            const Veto& v, double phi) {
+__device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, const Term& tm, double z,
+                            double omz, const Veto& v, double phi) {
   int i = ch.i, k = ch.k, j = n;
   double pe[4], ps[4], pi[4], pj[4], pk[4];
   R.get(i, pe);
@@ -521,7 +594,7 @@ __device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, in
   R.set(j, pj);
   R.st[R.o(j)] = 1;
   int ec = R.effc(i), ea = R.effa(i), jc = 0, ja = 0;
-  int kern = ch.kern[m];
+  int kern = tm.kern;
   int pidi = R.pid[R.o(i)];
   if (kern == kQQG || kern == kGGG || kern == kA || kern == kC) {
     int N = ++maxtag;
@@ -529,7 +602,7 @@ __device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, in
     else { R.set_eff(i, ec, N); jc = N; ja = ea; }
     R.pid[R.o(j)] = 21;
   } else if (kern == kGQQ) {
-    int f = ch.flav[m];
+    int f = tm.flav;
     if (ch.side == 0) { R.pid[R.o(i)] = f; R.set_eff(i, ec, 0); R.pid[R.o(j)] = -f; jc = 0; ja = ea; }
     else { R.pid[R.o(i)] = -f; R.set_eff(i, 0, ea); R.pid[R.o(j)] = f; jc = ec; ja = 0; }
   } else if (kern == kB) {
@@ -539,7 +612,7 @@ __device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, in
     else { R.set_eff(i, ec, N); jc = N; ja = 0; }
     R.pid[R.o(i)] = 21;
   } else {  // kD
-    int a = ch.flav[m];
+    int a = tm.flav;
     if (a > 0) { R.set_eff(i, 0, ea); jc = ec; ja = 0; }
     else { R.set_eff(i, ec, 0); jc = 0; ja = ea; }
     R.pid[R.o(i)] = a;

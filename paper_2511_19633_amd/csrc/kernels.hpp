@@ -14,9 +14,10 @@ struct Scratch {
   double *E, *px, *py, *pz;
   int32_t *pid, *col, *acol;
   int8_t* st;
-  // channel cache [2*max_slots][lanes]
+  // channel cache [2*max_slots][lanes]: trial data, then winner data
   uint32_t* cinfo;
   double *ctlim, *clntlim, *cinvc;
+  double *cc, *cs, *czlo, *comzhi, *cI1, *cI2;
   unsigned long long* queue;  // work-queue counters
 };
 
@@ -42,6 +43,9 @@ __global__ void k_lo_scan(Cfg C, double* w);
 __global__ void k_lo_max(const double* w, int n, double* out);
 __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o);
 __global__ void k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_shower_wave(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_shower_wave3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_shower_wave4(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_observables(Cfg C, gaps_events ev, int64_t n, double* obs);
 __global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
                             int nbins, double* sumw, double* sumw2);

@@ -34,7 +34,7 @@ __device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& 
       }
       if (k < 0) return -1;
       chan_setup(C, R, i, side, k, ch);
-      int64_t oc = (int64_t)m * R.G + R.lane;
+      int64_t oc = (int64_t)m * S.lanes + R.lane;
       S.cinfo[oc] = pack_info(ch);
       S.ctlim[oc] = ch.tlim;
       S.clntlim[oc] = ch.lntlim;
@@ -82,7 +82,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       uint32_t curblk = 0xFFFFFFFFu;
       double ub[4] = {0.0, 0.0, 0.0, 0.0};
       for (int c = 0; c < nch; ++c) {
-        int64_t oc = (int64_t)c * R.G + R.lane;
+        int64_t oc = (int64_t)c * S.lanes + R.lane;
         uint32_t info = S.cinfo[oc];
         if (!((info >> 21) & 1u)) continue;
         double tlim = S.ctlim[oc], lntlim = S.clntlim[oc];
@@ -111,29 +111,20 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       }
       if (win < 0) break;
       double t = exp(best);
-      uint32_t info = S.cinfo[(int64_t)win * R.G + R.lane];
+      uint32_t info = S.cinfo[(int64_t)win * S.lanes + R.lane];
       Chan ch;
       chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
       double u[4];
       rng4(seed, stream, id, cycle, 0xFFFFFFFFu, u);
-      double target = u[0] * ch.c, cum = 0.0;
-      int sel = -1;
-      for (int m = 0; m < ch.nterm; ++m) {
-        cum += ch.tc[m];
-        if (target < cum) { sel = m; break; }
-      }
-      if (sel < 0)
-        for (int m = ch.nterm - 1; m >= 0; --m)
-          if (ch.tc[m] > 0.0) { sel = m; break; }
-      double I = shape_int(ch.shape[sel], ch);
+      Term tm = select_term(C, ch, u[0]);
       double z, omz;
-      shape_sample(ch.shape[sel], ch, I, u[1], z, omz);
+      shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
       double phi = 2.0 * kPi * u[2];
-      Veto v = veto_weight(C, R, ch, sel, t, z, omz);
+      Veto v = veto_weight(C, R, ch, tm, t, z, omz);
       if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
       if (v.ok && u[3] < v.w) {
         if (n + 1 > M) { flags |= fOverflow; break; }
-        emit(R, n, maxtag, ch, sel, z, omz, v, phi);
+        emit(R, n, maxtag, ch, tm, z, omz, v, phi);
         n += 1;
         nacc += 1;
         if (t1 == 0.0) t1 = t;
@@ -188,7 +179,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
 __global__ void __launch_bounds__(256) k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S,
                                                       ShowerArgs A) {
   const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  Rec R{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, S.lanes, lane};
+  Rec R{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, S.lanes, 1, lane};
   for (;;) {
     unsigned long long e = atomicAdd(S.queue, 1ULL);
     if (e >= (unsigned long long)A.n) break;

@@ -160,9 +160,12 @@ def test_scheduling_invariance(gpu):
     n = 4000
     gin = G.hard_events(0, n, 11)
     a = G.shower(gin, 5, block=256).to_host()
-    b = G.shower(gin, 5, block=64, grid=7).to_host()
-    for name in a.fields():
-        assert np.array_equal(getattr(a, name), getattr(b, name)), name
+    for kw in (dict(block=64, grid=7), dict(block=128, compact_every=1), dict(compact_every=33),
+               dict(variant=1), dict(variant=1, block=64, grid=5), dict(waves_per_simd=3),
+               dict(waves_per_simd=4, block=64)):
+        b = G.shower(gin, 5, **kw).to_host()
+        for name in a.fields():
+            assert np.array_equal(getattr(a, name), getattr(b, name)), (kw, name)
     # two batches
     from paper_2511_19633_amd import binding
     h = gin.to_host()
