@@ -109,7 +109,8 @@ typedef struct {
 
 typedef struct {
     int mode;            /* GAPS_MODE_* */
-    int block;           /* threads per block, multiple of 64 (0: 256) */
+    int block;           /* threads per block, multiple of 64, at most 512 for
+                            the 2-wave kernel and 256 otherwise (0: largest) */
     int grid;            /* blocks of the persistent launch (0: fill the GPU) */
     int compact_every;   /* cycles between wave refills (0: 4) */
     float* trial_log;    /* LOG mode: device [log_cap][5] floats */
@@ -120,6 +121,9 @@ typedef struct {
                             1: one event per lane, no cooperation (reference) */
     int waves_per_simd;  /* wave kernel register budget: 2, 3 or 4 resident
                             waves per SIMD (0: 2) */
+    int tail_every;      /* wave kernel: once the queue is empty, repack live
+                            events into the block's first waves every this
+                            many cycles (0: off) */
 } gaps_params;
 
 /* Create a context: validates the configuration, uploads the PDF grid and
@@ -142,6 +146,42 @@ gaps_status gaps_hard_events(gaps_ctx ctx, int64_t first_id, int64_t n, uint64_t
  * (GAPS_F_OVERFLOW otherwise).  params may be NULL (plain mode, defaults). */
 gaps_status gaps_shower(gaps_ctx ctx, const gaps_events* in, int64_t n, const gaps_params* params,
                         uint64_t seed, gaps_events* out, hipStream_t stream);
+
+/* One batch of a stream: input and output records (their pointers are DEVICE
+ * pointers, as in gaps_shower) and the number of events n (in->cap, out->cap >= n). */
+typedef struct {
+    gaps_events in;
+    gaps_events out;
+    int64_t n;
+} gaps_batch;
+
+#define GAPS_MAX_BATCHES 4096
+
+/* Shower a stream of batches in ONE persistent launch (the batching of the
+ * section 3 implementation): lanes take events from the batches in order and
+ * refill across batch boundaries, so the drain at the end of one batch
+ * overlaps the next.  batches is a HOST array of nbatch descriptors
+ * (1 <= nbatch <= GAPS_MAX_BATCHES), validated like gaps_shower's arguments
+ * and copied by the call (the host array may be reused at once).  The output
+ * slot limit is the smallest out.max_slots of the batches; with equal limits
+ * every event equals what gaps_shower gives for its batch.  Only the wave
+ * kernel (params->variant 0) streams.  Calls on one context share its
+ * scratch: issue them on one stream. */
+gaps_status gaps_shower_stream(gaps_ctx ctx, const gaps_batch* batches, int nbatch,
+                               const gaps_params* params, uint64_t seed, hipStream_t stream);
+
+/* A HIP graph of one gaps_shower_stream call (batch table upload, queue reset
+ * and the persistent launch), captured on `stream` (not the null stream).  The
+ * graph owns its own scratch, so graphs and direct calls may be mixed; the
+ * records the batches point to must stay valid while it is used.  Replay with
+ * gaps_graph_launch (asynchronous; replays of one graph must not overlap);
+ * gaps_graph_destroy frees it. */
+typedef struct gaps_graph_s* gaps_graph;
+gaps_status gaps_graph_capture(gaps_ctx ctx, const gaps_batch* batches, int nbatch,
+                               const gaps_params* params, uint64_t seed, hipStream_t stream,
+                               gaps_graph* out);
+gaps_status gaps_graph_launch(gaps_graph g, hipStream_t stream);
+gaps_status gaps_graph_destroy(gaps_graph g);
 
 /* Per-event observables (section 4.1): obs is device [n][12], layout as in
  * the oracle's observables (Z pT, y, phi, phi*, jets; thrust and Durham y for

@@ -51,8 +51,15 @@ class GapsEvents(C.Structure):
 class GapsParams(C.Structure):
     _fields_ = [("mode", C.c_int), ("block", C.c_int), ("grid", C.c_int), ("compact_every", C.c_int),
                 ("trial_log", C.c_void_p), ("log_cap", C.c_int64), ("log_count", C.c_void_p),
-                ("stats", C.c_void_p), ("variant", C.c_int), ("waves_per_simd", C.c_int)]
+                ("stats", C.c_void_p), ("variant", C.c_int), ("waves_per_simd", C.c_int),
+                ("tail_every", C.c_int)]
 
+
+class GapsBatch(C.Structure):
+    _fields_ = [("in_", GapsEvents), ("out", GapsEvents), ("n", C.c_int64)]
+
+
+MAX_BATCHES = 4096
 
 _lib = None
 
@@ -71,6 +78,11 @@ def lib():
         L.gaps_hard_events.argtypes = [vp, i64, i64, u64, C.POINTER(GapsEvents), vp]
         L.gaps_shower.argtypes = [vp, C.POINTER(GapsEvents), i64, C.POINTER(GapsParams), u64,
                                   C.POINTER(GapsEvents), vp]
+        L.gaps_shower_stream.argtypes = [vp, C.POINTER(GapsBatch), C.c_int, C.POINTER(GapsParams), u64, vp]
+        L.gaps_graph_capture.argtypes = [vp, C.POINTER(GapsBatch), C.c_int, C.POINTER(GapsParams), u64, vp,
+                                         C.POINTER(vp)]
+        L.gaps_graph_launch.argtypes = [vp, vp]
+        L.gaps_graph_destroy.argtypes = [vp]
         L.gaps_observables.argtypes = [vp, C.POINTER(GapsEvents), i64, vp, vp]
         L.gaps_histogram.argtypes = [vp, vp, vp, i64, C.c_int, C.c_double, C.c_double, C.c_int, vp, vp, vp]
         L.gaps_bounds.argtypes = [vp, vp]
@@ -177,23 +189,55 @@ class Gaps:
         _check(lib().gaps_hard_events(self.h, first_id, n, seed, C.byref(s), _stream(stream)))
         return ev
 
-    def shower(self, ev_in: DeviceEvents, seed: int, n: int | None = None, out=None, max_slots=None,
-               mode=MODE_PLAIN, block=0, grid=0, compact_every=0, stats=None, trial_log=None,
-               log_count=None, variant=0, waves_per_simd=0, stream=None) -> DeviceEvents:
-        n = ev_in.cap if n is None else n
-        ev_out = out if out is not None else DeviceEvents(n, max_slots or ev_in.max_slots)
+    @staticmethod
+    def _params(mode=MODE_PLAIN, block=0, grid=0, compact_every=0, stats=None, trial_log=None,
+                log_count=None, variant=0, waves_per_simd=0, tail_every=0) -> GapsParams:
         p = GapsParams()
         p.mode, p.block, p.grid, p.compact_every = mode, block, grid, compact_every
         p.variant = variant
         p.waves_per_simd = waves_per_simd
+        p.tail_every = tail_every
         p.stats = stats.data_ptr() if stats is not None else None
         if trial_log is not None:
             p.trial_log = trial_log.data_ptr()
             p.log_cap = trial_log.shape[0]
             p.log_count = log_count.data_ptr()
+        return p
+
+    def shower(self, ev_in: DeviceEvents, seed: int, n: int | None = None, out=None, max_slots=None,
+               stream=None, **params) -> DeviceEvents:
+        n = ev_in.cap if n is None else n
+        ev_out = out if out is not None else DeviceEvents(n, max_slots or ev_in.max_slots)
+        p = self._params(**params)
         si, so = ev_in.struct(), ev_out.struct()
         _check(lib().gaps_shower(self.h, C.byref(si), n, C.byref(p), seed, C.byref(so), _stream(stream)))
         return ev_out
+
+    @staticmethod
+    def _batches(batches):
+        """[(ev_in, ev_out[, n]), ...] -> ctypes array of GapsBatch."""
+        arr = (GapsBatch * max(len(batches), 1))()
+        for k, b in enumerate(batches):
+            ev_in, ev_out = b[0], b[1]
+            arr[k].in_ = ev_in.struct()
+            arr[k].out = ev_out.struct()
+            arr[k].n = b[2] if len(b) > 2 else ev_in.cap
+        return arr
+
+    def shower_stream(self, batches, seed: int, stream=None, **params):
+        """Shower a list of (ev_in, ev_out[, n]) batches in one persistent launch."""
+        arr = self._batches(batches)
+        p = self._params(**params)
+        _check(lib().gaps_shower_stream(self.h, arr, len(batches), C.byref(p), seed, _stream(stream)))
+
+    def capture(self, batches, seed: int, stream, **params) -> "Graph":
+        """HIP graph of one shower_stream call, captured on `stream` (a side stream)."""
+        arr = self._batches(batches)
+        p = self._params(**params)
+        g = C.c_void_p()
+        _check(lib().gaps_graph_capture(self.h, arr, len(batches), C.byref(p), seed, _stream(stream),
+                                        C.byref(g)))
+        return Graph(g, batches)
 
     def observables(self, ev: DeviceEvents, n: int | None = None, stream=None) -> torch.Tensor:
         n = ev.cap if n is None else n
@@ -213,6 +257,28 @@ class Gaps:
         out = torch.zeros_like(x)
         _check(lib().gaps_pdf_eval(self.h, _ptr(tab), _ptr(x), _ptr(q2), x.numel(), _ptr(out), _stream(stream)))
         return out
+
+
+class Graph:
+    """A captured shower stream; holds the batch records it points to."""
+
+    def __init__(self, handle, batches):
+        self.h = handle
+        self._keep = batches
+
+    def launch(self, stream=None):
+        _check(lib().gaps_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().gaps_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def rng_blocks(seed: int, stream_id: int, ids: torch.Tensor, c2: torch.Tensor, c3: torch.Tensor,

@@ -7,19 +7,6 @@
 
 using gaps::Cfg;
 
-struct gaps_ctx_s {
-  gaps_config cfg;
-  Cfg C;
-  int device = 0;
-  int cus = 0;
-  float* d_pdf = nullptr;
-  double* d_bound = nullptr;
-  // shower scratch, grown on demand
-  void* scratch = nullptr;
-  size_t scratch_bytes = 0;
-  gaps::Scratch S{};
-};
-
 #define GAPS_HIP(call)                       \
   do {                                       \
     if ((call) != hipSuccess) return GAPS_EHIP; \
@@ -37,26 +24,33 @@ bool bad_events(const gaps_events* e, int64_t n, int min_slots) {
 
 unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-gaps_status ensure_scratch(gaps_ctx c, int64_t lanes, int slots) {
+// Per-lane shower scratch held in one allocation (grown on demand).
+struct ScratchMem {
+  void* mem = nullptr;
+  size_t bytes = 0;
+  gaps::Scratch S{};
+};
+
+gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   size_t per_lane = (size_t)slots * (4 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int8_t)) +
                     (size_t)nch * (sizeof(uint32_t) + 9 * sizeof(double));
   size_t need = per_lane * (size_t)lanes + 256 * 24 + 64;
-  if (need > c->scratch_bytes || c->S.lanes != lanes || c->S.max_slots != slots) {
-    if (need > c->scratch_bytes) {
-      if (c->scratch) (void)hipFree(c->scratch);
-      c->scratch = nullptr;
-      c->scratch_bytes = 0;
-      if (hipMalloc(&c->scratch, need) != hipSuccess) return GAPS_ENOMEM;
-      c->scratch_bytes = need;
+  if (need > m.bytes || m.S.lanes != lanes || m.S.max_slots != slots) {
+    if (need > m.bytes) {
+      if (m.mem) (void)hipFree(m.mem);
+      m.mem = nullptr;
+      m.bytes = 0;
+      if (hipMalloc(&m.mem, need) != hipSuccess) return GAPS_ENOMEM;
+      m.bytes = need;
     }
-    char* p = (char*)c->scratch;
+    char* p = (char*)m.mem;
     auto take = [&](size_t bytes) {
       char* r = p;
       p += (bytes + 255) & ~(size_t)255;
       return (void*)r;
     };
-    gaps::Scratch& S = c->S;
+    gaps::Scratch& S = m.S;
     S.lanes = lanes;
     S.max_slots = slots;
     size_t ps = (size_t)slots * lanes, cs = (size_t)nch * lanes;
@@ -69,12 +63,56 @@ gaps_status ensure_scratch(gaps_ctx c, int64_t lanes, int slots) {
     S.cc = (double*)take(cs * 8); S.cs = (double*)take(cs * 8); S.czlo = (double*)take(cs * 8);
     S.comzhi = (double*)take(cs * 8); S.cI1 = (double*)take(cs * 8); S.cI2 = (double*)take(cs * 8);
     S.queue = (unsigned long long*)take(64);
-    if ((size_t)(p - (char*)c->scratch) > c->scratch_bytes) return GAPS_ENOMEM;
+    if ((size_t)(p - (char*)m.mem) > m.bytes) return GAPS_ENOMEM;
   }
   return GAPS_OK;
 }
 
+// Device copy of a stream's batch table and its offsets (grown on demand).
+struct BatchMem {
+  gaps_batch* table = nullptr;
+  int64_t* prefix = nullptr;
+  int cap = 0;
+};
+
+gaps_status ensure_batches(BatchMem& m, int nbatch) {
+  if (nbatch <= m.cap) return GAPS_OK;
+  if (m.table) (void)hipFree(m.table);
+  if (m.prefix) (void)hipFree(m.prefix);
+  m.table = nullptr;
+  m.prefix = nullptr;
+  m.cap = 0;
+  if (hipMalloc((void**)&m.table, sizeof(gaps_batch) * (size_t)nbatch) != hipSuccess) return GAPS_ENOMEM;
+  if (hipMalloc((void**)&m.prefix, sizeof(int64_t) * ((size_t)nbatch + 1)) != hipSuccess) return GAPS_ENOMEM;
+  m.cap = nbatch;
+  return GAPS_OK;
+}
+
+void free_batches(BatchMem& m) {
+  if (m.table) (void)hipFree(m.table);
+  if (m.prefix) (void)hipFree(m.prefix);
+  m = BatchMem{};
+}
+
 }  // namespace
+
+struct gaps_ctx_s {
+  gaps_config cfg;
+  Cfg C;
+  int device = 0;
+  int cus = 0;
+  float* d_pdf = nullptr;
+  double* d_bound = nullptr;
+  ScratchMem scratch;  // shower scratch, grown on demand
+  BatchMem batches;    // batch table of gaps_shower_stream
+};
+
+struct gaps_graph_s {
+  ScratchMem scratch;
+  BatchMem batches;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -169,7 +207,8 @@ gaps_status gaps_destroy(gaps_ctx c) {
   if (!c) return GAPS_EINVAL;
   if (c->d_pdf) (void)hipFree(c->d_pdf);
   if (c->d_bound) (void)hipFree(c->d_bound);
-  if (c->scratch) (void)hipFree(c->scratch);
+  if (c->scratch.mem) (void)hipFree(c->scratch.mem);
+  free_batches(c->batches);
   delete c;
   return GAPS_OK;
 }
@@ -189,43 +228,189 @@ gaps_status gaps_hard_events(gaps_ctx c, int64_t first_id, int64_t n, uint64_t s
   return GAPS_OK;
 }
 
-gaps_status gaps_shower(gaps_ctx c, const gaps_events* in, int64_t n, const gaps_params* params, uint64_t seed,
-                        gaps_events* out, hipStream_t stream) {
-  if (!c || bad_events(in, n, 1) || bad_events(out, n, 1)) return GAPS_EINVAL;
-  if (n > 0 && (in->E == out->E || in->n == out->n)) return GAPS_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Kernel, block and grid of a shower launch over n events.
+struct Plan {
+  const void* kern;
+  int block;
+  int64_t grid;
+  size_t dyn;
+  gaps::ShowerArgs A;
+};
+
+gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64_t seed, Plan& pl) {
   gaps_params P{};
   if (params) P = *params;
   if (P.mode != GAPS_MODE_PLAIN) return GAPS_ESTATE;
-  int block = P.block > 0 ? P.block : 256;
-  if (block % 64 != 0 || block > 256) return GAPS_EINVAL;
-  if (n == 0) return GAPS_OK;
   if (P.variant < 0 || P.variant > 1) return GAPS_EINVAL;
   const int wps = P.waves_per_simd > 0 ? P.waves_per_simd : 2;
   if (wps < 2 || wps > 4) return GAPS_EINVAL;
-  const void* kern = P.variant == 1 ? (const void*)gaps::k_shower_lanes
-                     : wps == 2     ? (const void*)gaps::k_shower_wave
-                     : wps == 3     ? (const void*)gaps::k_shower_wave3
-                                    : (const void*)gaps::k_shower_wave4;
+  // the 2-wave kernel compacts its tail across up to 8 waves of a block
+  const int max_block = (P.variant == 0 && wps == 2) ? 512 : 256;
+  pl.block = P.block > 0 ? P.block : max_block;
+  if (pl.block % 64 != 0 || pl.block > max_block) return GAPS_EINVAL;
+  if (P.grid < 0 || P.compact_every < 0 || P.tail_every < 0) return GAPS_EINVAL;
+  pl.dyn = P.variant == 1 ? 0 : (size_t)pl.block * gaps::kLaneStateBytes;
+  pl.kern = P.variant == 1 ? (const void*)gaps::k_shower_lanes
+            : wps == 2     ? (const void*)gaps::k_shower_wave
+            : wps == 3     ? (const void*)gaps::k_shower_wave3
+                           : (const void*)gaps::k_shower_wave4;
   int per_cu = 0;
-  GAPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0));
+  GAPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pl.kern, pl.block, pl.dyn));
   if (per_cu < 1) per_cu = 1;
-  int64_t grid = P.grid > 0 ? P.grid : (int64_t)per_cu * c->cus;
-  int64_t need_blocks = (n + block - 1) / block;
-  if (grid > need_blocks) grid = need_blocks;
-  int64_t lanes = grid * block;
-  gaps_status s = ensure_scratch(c, lanes, out->max_slots);
-  if (s != GAPS_OK) return s;
-  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->S.queue, (int64_t)1, 0ULL);
-  gaps::ShowerArgs A{};
+  pl.grid = P.grid > 0 ? P.grid : (int64_t)per_cu * c->cus;
+  const int64_t need_blocks = (n + pl.block - 1) / pl.block;
+  if (pl.grid > need_blocks) pl.grid = need_blocks;
+  if (pl.grid < 1) pl.grid = 1;
+  gaps::ShowerArgs& A = pl.A;
+  A = gaps::ShowerArgs{};
   A.mode = P.mode;
   A.compact_every = P.compact_every > 0 ? P.compact_every : 4;
+  A.tail_every = P.tail_every;
   A.stream = 0u;
   A.seed = seed;
   A.n = n;
   A.stats = P.stats;
-  void* args[] = {(void*)&c->C, (void*)in, (void*)out, (void*)&c->S, (void*)&A};
-  GAPS_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(block), args, 0, stream));
+  return GAPS_OK;
+}
+
+// Validate a host batch table; total events and the smallest output slot limit.
+gaps_status check_batches(const gaps_batch* b, int nbatch, int64_t& total, int& slots) {
+  if (!b || nbatch < 1 || nbatch > GAPS_MAX_BATCHES) return GAPS_EINVAL;
+  total = 0;
+  slots = gaps::kMaxSlots;
+  for (int k = 0; k < nbatch; ++k) {
+    const gaps_batch& x = b[k];
+    if (bad_events(&x.in, x.n, 1) || bad_events(&x.out, x.n, 1)) return GAPS_EINVAL;
+    if (x.n > 0 && (x.in.E == x.out.E || x.in.n == x.out.n)) return GAPS_EINVAL;
+    if (x.n > 0 && x.out.max_slots < slots) slots = x.out.max_slots;
+    total += x.n;
+  }
+  return GAPS_OK;
+}
+
+// Upload a host batch table, by value in kernel arguments (stream-ordered and
+// capturable; the host table is not referenced after the calls return).
+gaps_status store_batches(const gaps_batch* b, int nbatch, int64_t total, BatchMem& m, hipStream_t stream) {
+  int64_t first = 0;
+  for (int at = 0; at < nbatch; at += gaps::kBatchChunk) {
+    gaps::BatchChunk ch{};
+    ch.at = at;
+    ch.count = nbatch - at < gaps::kBatchChunk ? nbatch - at : gaps::kBatchChunk;
+    for (int k = 0; k < ch.count; ++k) {
+      ch.b[k] = b[at + k];
+      ch.first[k] = first;
+      first += b[at + k].n;
+    }
+    ch.last = at + ch.count == nbatch;
+    ch.total = total;
+    hipLaunchKernelGGL(gaps::k_store_batches, dim3(1), dim3(64), 0, stream, ch, m.table, m.prefix, nbatch);
+    GAPS_HIP(hipGetLastError());
+  }
+  return GAPS_OK;
+}
+
+// Queue reset and the persistent launch.
+gaps_status launch_shower(gaps_ctx c, const Plan& pl, const gaps_events* in, const gaps_events* out,
+                          const gaps::Scratch& S, hipStream_t stream) {
+  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, S.queue, (int64_t)1, 0ULL);
   GAPS_HIP(hipGetLastError());
+  gaps_events none{};
+  void* args[] = {(void*)&c->C, (void*)(in ? in : &none), (void*)(out ? out : &none), (void*)&S,
+                  (void*)&pl.A};
+  GAPS_HIP(hipLaunchKernel(pl.kern, dim3((unsigned)pl.grid), dim3(pl.block), args, pl.dyn, stream));
+  GAPS_HIP(hipGetLastError());
+  return GAPS_OK;
+}
+
+// Batch upload, plan and scratch of a stream call into (scratch, batches).
+gaps_status prepare_stream(gaps_ctx c, const gaps_batch* batches, int nbatch, const gaps_params* params,
+                           uint64_t seed, ScratchMem& sm, BatchMem& bm, Plan& pl, int64_t& total) {
+  int slots = 0;
+  gaps_status s = check_batches(batches, nbatch, total, slots);
+  if (s != GAPS_OK) return s;
+  if (params && params->variant != 0) return GAPS_EINVAL;
+  s = plan_shower(c, params, total, seed, pl);
+  if (s != GAPS_OK) return s;
+  s = ensure_scratch(sm, pl.grid * pl.block, slots);
+  if (s != GAPS_OK) return s;
+  s = ensure_batches(bm, nbatch);
+  if (s != GAPS_OK) return s;
+  pl.A.batches = bm.table;
+  pl.A.prefix = bm.prefix;
+  pl.A.nbatch = nbatch;
+  return GAPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gaps_status gaps_shower(gaps_ctx c, const gaps_events* in, int64_t n, const gaps_params* params, uint64_t seed,
+                        gaps_events* out, hipStream_t stream) {
+  if (!c || bad_events(in, n, 1) || bad_events(out, n, 1)) return GAPS_EINVAL;
+  if (n > 0 && (in->E == out->E || in->n == out->n)) return GAPS_EINVAL;
+  Plan pl;
+  gaps_status s = plan_shower(c, params, n, seed, pl);
+  if (s != GAPS_OK || n == 0) return s;
+  s = ensure_scratch(c->scratch, pl.grid * pl.block, out->max_slots);
+  if (s != GAPS_OK) return s;
+  return launch_shower(c, pl, in, out, c->scratch.S, stream);
+}
+
+gaps_status gaps_shower_stream(gaps_ctx c, const gaps_batch* batches, int nbatch, const gaps_params* params,
+                               uint64_t seed, hipStream_t stream) {
+  if (!c) return GAPS_EINVAL;
+  Plan pl;
+  int64_t total = 0;
+  gaps_status s = prepare_stream(c, batches, nbatch, params, seed, c->scratch, c->batches, pl, total);
+  if (s != GAPS_OK || total == 0) return s;
+  s = store_batches(batches, nbatch, total, c->batches, stream);
+  if (s != GAPS_OK) return s;
+  return launch_shower(c, pl, nullptr, nullptr, c->scratch.S, stream);
+}
+
+gaps_status gaps_graph_capture(gaps_ctx c, const gaps_batch* batches, int nbatch, const gaps_params* params,
+                               uint64_t seed, hipStream_t stream, gaps_graph* out) {
+  if (!c || !out || stream == nullptr) return GAPS_EINVAL;
+  *out = nullptr;
+  gaps_graph g = new gaps_graph_s();
+  Plan pl;
+  int64_t total = 0;
+  gaps_status s = prepare_stream(c, batches, nbatch, params, seed, g->scratch, g->batches, pl, total);
+  if (s == GAPS_OK && hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) s = GAPS_EHIP;
+  if (s == GAPS_OK) {
+    gaps_status s1 = store_batches(batches, nbatch, total, g->batches, stream);
+    if (s1 == GAPS_OK && total > 0) s1 = launch_shower(c, pl, nullptr, nullptr, g->scratch.S, stream);
+    hipError_t e = hipStreamEndCapture(stream, &g->graph);
+    if (s1 != GAPS_OK) s = s1;
+    else if (e != hipSuccess) s = GAPS_EHIP;
+  }
+  if (s == GAPS_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) s = GAPS_EHIP;
+  if (s != GAPS_OK) {
+    gaps_graph_destroy(g);
+    return s;
+  }
+  *out = g;
+  return GAPS_OK;
+}
+
+gaps_status gaps_graph_launch(gaps_graph g, hipStream_t stream) {
+  if (!g || !g->exec) return GAPS_EINVAL;
+  GAPS_HIP(hipGraphLaunch(g->exec, stream));
+  return GAPS_OK;
+}
+
+gaps_status gaps_graph_destroy(gaps_graph g) {
+  if (!g) return GAPS_EINVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->scratch.mem) (void)hipFree(g->scratch.mem);
+  free_batches(g->batches);
+  delete g;
   return GAPS_OK;
 }
 

@@ -11,6 +11,16 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
   if (i < n) p[i] = v;
 }
 
+// store one chunk of a stream's batch table (and its stream offsets)
+__global__ void k_store_batches(BatchChunk ch, gaps_batch* table, int64_t* prefix, int nbatch) {
+  const int k = threadIdx.x;
+  if (k < ch.count) {
+    table[ch.at + k] = ch.b[k];
+    prefix[ch.at + k] = ch.first[k];
+  }
+  if (k == 0 && ch.last) prefix[nbatch] = ch.total;
+}
+
 __global__ void k_rng_blocks(uint64_t seed, uint32_t stream, const int64_t* id, const uint32_t* c2,
                              const uint32_t* c3, int64_t n, uint32_t* out) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

@@ -21,12 +21,19 @@ struct Scratch {
   unsigned long long* queue;  // work-queue counters
 };
 
+// bytes of LDS per thread for the tail-compaction state pool of the wave kernel
+constexpr size_t kLaneStateBytes = 96;
+
 struct ShowerArgs {
   int mode;
   int compact_every;
+  int tail_every;
   uint32_t stream;
   uint64_t seed;
   int64_t n;
+  const gaps_batch* batches;  // device table of a stream (nbatch > 0), else the kernel's in/out
+  const int64_t* prefix;      // device [nbatch + 1]: first stream index of each batch
+  int nbatch;
   float* log;
   int64_t log_cap;
   unsigned long long* log_count;
@@ -46,6 +53,17 @@ __global__ void k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S
 __global__ void k_shower_wave(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave4(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+// a chunk of a stream's batch table, passed by value (fits the kernel-argument space)
+constexpr int kBatchChunk = 8;
+struct BatchChunk {
+  gaps_batch b[kBatchChunk];
+  int64_t first[kBatchChunk];  // stream index of each batch's first event
+  int count;
+  int at;                      // table position of b[0]
+  int64_t total;               // written to prefix[nbatch] by the last chunk
+  int last;
+};
+__global__ void k_store_batches(BatchChunk ch, gaps_batch* table, int64_t* prefix, int nbatch);
 __global__ void k_observables(Cfg C, gaps_events ev, int64_t n, double* obs);
 __global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
                             int nbins, double* sumw, double* sumw2);

@@ -6,7 +6,14 @@
 //    one channel set-up instead of 2n sequential ones on one lane while the
 //    other 63 wait;
 //  - refill: finished lanes take new event ids from the work queue with one
-//    atomic per wave (ballot + prefix count), every `compact_every` cycles.
+//    atomic per wave (ballot + prefix count), every `compact_every` cycles;
+//  - tail compaction: once the queue is empty, waves drain and would keep
+//    paying full price per cycle for a few live lanes.  When every wave of the
+//    block has seen the queue empty (an LDS counter, no barrier before that),
+//    the block switches to tail mode: every 16 iterations it pools the
+//    register state of its live events in LDS and packs them into its first
+//    waves (each event keeps its state slot, so records and channel caches
+//    stay where they are); emptied waves park at the block barrier.
 // Event records are lane-major (one event contiguous) so cooperative reads of
 // another lane's event coalesce; the channel cache is indexed by (slot, side),
 // the coordinate that also keys the random numbers, stored [entry][lane] so
@@ -28,10 +35,19 @@ __device__ __forceinline__ unsigned long long lanemask_lt(int lane) { return (1u
 struct WaveCtx {
   const Cfg& C;
   const Scratch& S;
-  int64_t wbase;  // state slot of lane 0
   int lane;
   int M;
 };
+
+// register state of one in-flight event (what moves when the tail compacts)
+struct LaneState {
+  int64_t e, id, slot;
+  int32_t b, pad;
+  double T, lnT, t1;
+  uint32_t cycle, ntri, nacc, nviol, flags;
+  int32_t n, maxtag, loaded, stop;
+};
+static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
 __device__ __forceinline__ Rec rec_of(const Scratch& S, int64_t slot) {
   return Rec{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, 1, S.max_slots, slot};
@@ -43,14 +59,14 @@ __device__ __forceinline__ Rec rec_of(const Scratch& S, int64_t slot) {
 // is found with register reads instead of a search through memory; then lane
 // c sets up entry c = 2 * slot + side.  Returns (per lane) whether this
 // lane's own event hit a broken colour line or a non-finite momentum.
-__device__ uint32_t coop_build(const WaveCtx& W, unsigned long long mask, int n) {
+__device__ uint32_t coop_build(const WaveCtx& W, unsigned long long mask, int n, int64_t myslot) {
   uint32_t myflags = 0u;
   __threadfence_block();
   while (mask) {
     const int L = __ffsll((long long)mask) - 1;
     mask &= mask - 1ull;
     const int nL = __shfl(n, L);
-    const int64_t slot = W.wbase + L;
+    const int64_t slot = __shfl(myslot, L);
     const Rec R = rec_of(W.S, slot);
     // colours of particles lane and lane + 64 in registers
     int ec0 = 0, ea0 = 0, ec1 = 0, ea1 = 0;
@@ -142,32 +158,93 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.nterm = n_terms(ch, C.nf);
 }
 
+// batch of global queue index g: the last b with prefix[b] <= g
+__device__ __forceinline__ int batch_of(const ShowerArgs& A, int64_t g) {
+  int lo = 0, hi = A.nbatch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.prefix[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 }  // namespace
 
-__device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_events& in, const gaps_events& out,
+__device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_events& in1, const gaps_events& out1,
                                                  const Scratch& S, const ShowerArgs& A) {
   // the overestimate table, staged in LDS for the term loops
   __shared__ double s_bound[kNEnt * kNB];
+  __shared__ int s_cnt[16], s_nexh;
+  extern __shared__ LaneState s_pool[];
   for (int q = threadIdx.x; q < kNEnt * kNB; q += blockDim.x) s_bound[q] = Cg.bound[q];
+  if (threadIdx.x == 0) s_nexh = 0;
   __syncthreads();
   Cfg C = Cg;
   C.bound = s_bound;
-  const int lane = threadIdx.x & 63;
-  const int64_t slot = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int M = out.max_slots < S.max_slots ? out.max_slots : S.max_slots;
-  const WaveCtx W{C, S, slot - lane, lane, M};
-  const Rec R = rec_of(S, slot);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int64_t slot = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // every batch's output has at least S.max_slots slots (checked by the host)
+  const int M = S.max_slots;
+  const WaveCtx W{C, S, lane, M};
+  Rec R = rec_of(S, slot);
   const int K = A.compact_every > 0 ? A.compact_every : 4;
+  const unsigned KC = A.tail_every > 0 ? (unsigned)A.tail_every : 16u;
+  const bool compact = A.tail_every > 0;
 
   bool active = false, exhausted = false, loaded = false, stop = false;
   int64_t e = 0, id = 0;
+  int b = 0;
   double T = 0.0, lnT = 0.0, t1 = 0.0;
   uint32_t cycle = 0, ntri = 0, nacc = 0, nviol = 0, flags = 0;
   int n = 0, maxtag = 0;
   unsigned long long st_cyc = 0, st_tri = 0, st_acc = 0, st_viol = 0, st_iters = 0, st_active = 0;
   int since = 1 << 30;
+  bool counted = false, tail = false;
+  unsigned it_tail = 0;
 
-  for (;;) {
+  for (unsigned it = 0;; ++it) {
+    // ---- tail mode starts when every wave of the block has seen the queue empty
+    if (compact && !tail && exhausted) {
+      if (!counted) {
+        if (lane == 0) atomicAdd(&s_nexh, 1);
+        counted = true;
+      }
+      tail = __builtin_amdgcn_readfirstlane(*(volatile int*)&s_nexh) == nw;
+      if (tail) it_tail = it;
+    }
+    // ---- tail mode: block bookkeeping, termination and compaction
+    if (tail && (it - it_tail) % KC == 0u) {
+      const unsigned long long a0 = __ballot(active);
+      if (lane == 0) s_cnt[wid] = __popcll(a0);
+      __syncthreads();
+      int total = 0, used = 0, prefix = 0;
+      for (int w = 0; w < nw; ++w) {
+        const int cw = s_cnt[w];
+        if (w < wid) prefix += cw;
+        total += cw;
+        used += cw > 0 ? 1 : 0;
+      }
+      if (total == 0) break;
+      if ((total + 63) / 64 < used) {
+        if (active) {
+          LaneState& X = s_pool[prefix + __popcll(a0 & lanemask_lt(lane))];
+          X.e = e; X.id = id; X.slot = slot; X.b = b; X.T = T; X.lnT = lnT; X.t1 = t1;
+          X.cycle = cycle; X.ntri = ntri; X.nacc = nacc; X.nviol = nviol; X.flags = flags;
+          X.n = n; X.maxtag = maxtag; X.loaded = loaded; X.stop = stop;
+        }
+        __syncthreads();
+        active = (int)threadIdx.x < total;
+        if (active) {
+          const LaneState& X = s_pool[threadIdx.x];
+          e = X.e; id = X.id; slot = X.slot; b = X.b; T = X.T; lnT = X.lnT; t1 = X.t1;
+          cycle = X.cycle; ntri = X.ntri; nacc = X.nacc; nviol = X.nviol; flags = X.flags;
+          n = X.n; maxtag = X.maxtag; loaded = X.loaded != 0; stop = X.stop != 0;
+          R = rec_of(S, slot);
+        }
+      }
+      __syncthreads();
+    }
     // ---- refill finished lanes from the work queue (one atomic per wave)
     unsigned long long act = __ballot(active);
     if (!exhausted && (since >= K || act == 0ull)) {
@@ -181,7 +258,9 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (!active) {
         const unsigned long long ev = base + (unsigned long long)__popcll(idle & lanemask_lt(lane));
         if (ev < (unsigned long long)A.n) {
-          e = (int64_t)ev;
+          b = A.nbatch > 0 ? batch_of(A, (int64_t)ev) : 0;
+          e = (int64_t)ev - (A.nbatch > 0 ? A.prefix[b] : 0);
+          const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
           n = in.n[e];
           id = in.id[e];
           flags = in.flags ? in.flags[e] : 0u;
@@ -211,14 +290,15 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       }
       {
         // a broken colour line stops the event before its first cycle
-        const uint32_t f = coop_build(W, __ballot(fresh), n) & fColour;
+        const uint32_t f = coop_build(W, __ballot(fresh), n, slot) & fColour;
         if (fresh && f) { flags |= f; stop = true; }
       }
       since = 0;
       act = __ballot(active);
     }
     if (act == 0ull) {
-      if (exhausted) break;
+      if (!compact && exhausted) break;  // no tail mode: a drained wave just leaves
+      if (exhausted && !tail) __builtin_amdgcn_s_sleep(2);
       continue;
     }
     st_iters += 64ull;
@@ -342,12 +422,14 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     // ---- cooperative channel rebuild for the lanes that emitted
     const unsigned long long emitted = __ballot(accepted);
     if (emitted) {
-      uint32_t f = coop_build(W, emitted, n);
+      uint32_t f = coop_build(W, emitted, n, slot);
       if (f & fNaN) f = fNaN;  // a non-finite momentum is reported before the colour check
       if (accepted && f) { flags |= f; done = true; }
     }
     // ---- finished events: write out and free the lane
     if (active && done) {
+      const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
+      const gaps_events& out = A.nbatch > 0 ? A.batches[b].out : out1;
       const int64_t co = out.cap;
       const int nin = in.n[e];
       const bool fits = loaded;
@@ -395,7 +477,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
 
 // The same body at three register budgets (waves resident per SIMD): more
 // waves hide more latency, fewer registers per wave spill more.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 k_shower_wave(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
   shower_wave_body(C, in, out, S, A);
 }

@@ -32,3 +32,13 @@ def test_argument_errors_without_device_work():
     assert lib.gaps_hard_events(None, 0, 0, 0, None, None) == -1
     assert lib.gaps_destroy(None) == -1
     assert lib.gaps_strerror(-4) == b"size exceeds capacity"
+
+
+def test_stream_and_graph_argument_errors():
+    from paper_2511_19633_amd import binding
+    lib = binding.lib()
+    assert lib.gaps_shower_stream(None, None, 0, None, 0, None) == -1
+    assert lib.gaps_graph_capture(None, None, 0, None, 0, None, None) == -1
+    assert lib.gaps_graph_launch(None, None) == -1
+    assert lib.gaps_graph_destroy(None) == -1
+    assert C.sizeof(binding.GapsBatch) == 2 * C.sizeof(binding.GapsEvents) + 8

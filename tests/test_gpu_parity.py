@@ -162,7 +162,7 @@ def test_scheduling_invariance(gpu):
     a = G.shower(gin, 5, block=256).to_host()
     for kw in (dict(block=64, grid=7), dict(block=128, compact_every=1), dict(compact_every=33),
                dict(variant=1), dict(variant=1, block=64, grid=5), dict(waves_per_simd=3),
-               dict(waves_per_simd=4, block=64)):
+               dict(waves_per_simd=4, block=64), dict(tail_every=16), dict(tail_every=3, block=256)):
         b = G.shower(gin, 5, **kw).to_host()
         for name in a.fields():
             assert np.array_equal(getattr(a, name), getattr(b, name)), (kw, name)
@@ -175,6 +175,98 @@ def test_scheduling_invariance(gpu):
     for name in ("n", "E", "pz", "pid", "n_cycles"):
         joined = np.concatenate([getattr(c1, name), getattr(c2, name)], axis=-1)
         assert np.array_equal(joined, getattr(a, name)), name
+
+
+def _assert_same(a, b, what):
+    for name in a.fields():
+        assert np.array_equal(getattr(a, name), getattr(b, name)), (what, name)
+
+
+def _split(G, ids_sizes, seed):
+    """Hard events in consecutive id ranges, one device record per batch."""
+    out, first = [], 0
+    for n in ids_sizes:
+        out.append(G.hard_events(first, n, seed) if n > 0 else None)
+        first += n
+    return out
+
+
+def test_stream_equals_batches(gpu):
+    """One persistent launch over uneven batches gives every event exactly what
+    a launch per batch gives (lanes refill across batch boundaries)."""
+    from paper_2511_19633_amd import binding
+    G = gpu["nlo"]
+    sizes = workloads.batch_sizes(9000, seed=4, lo=100, hi=3000)
+    sizes.insert(2, 0)  # an empty batch in the middle
+    say("stream sizes", sizes)
+    ins = _split(G, sizes, 13)
+    batches = []
+    for ev, n in zip(ins, sizes):
+        if ev is None:
+            ev = binding.DeviceEvents(1, workloads.MAX_SLOTS)
+        batches.append((ev, binding.DeviceEvents(max(n, 1), workloads.MAX_SLOTS), n))
+    for kw in (dict(), dict(block=128, compact_every=2), dict(waves_per_simd=3, grid=11), dict(tail_every=8)):
+        for _, o, _ in batches:
+            o.n.zero_()
+        G.shower_stream(batches, 21, **kw)
+        for (ev, o, n) in batches:
+            if n == 0:
+                continue
+            ref = G.shower(ev, 21).to_host()
+            _assert_same(ref, o.to_host(), ("stream", kw, n))
+
+
+def test_stream_slot_limit_and_errors(gpu):
+    from paper_2511_19633_amd import binding
+    G = gpu["nlo"]
+    a = G.hard_events(0, 300, 2)
+    b = G.hard_events(300, 200, 2)
+    oa, ob = binding.DeviceEvents(300, 8), binding.DeviceEvents(200, 8)
+    G.shower_stream([(a, oa), (b, ob)], 3)
+    ra = G.shower(a, 3, max_slots=8).to_host()
+    _assert_same(ra, oa.to_host(), "slots a")
+    rb = G.shower(b, 3, max_slots=8).to_host()
+    _assert_same(rb, ob.to_host(), "slots b")
+    with pytest.raises(binding.GapsError):
+        G.shower_stream([(a, a)], 3)  # in and out alias
+    with pytest.raises(binding.GapsError):
+        G.shower_stream([(a, oa)], 3, variant=1)  # only the wave kernel streams
+    with pytest.raises(binding.GapsError):
+        G.shower_stream([(a, binding.DeviceEvents(100, 8), 300)], 3)  # out too small
+    with pytest.raises(binding.GapsError):
+        G.shower_stream([], 3)
+
+
+def test_graph_replays_match_eager(gpu):
+    """A captured stream replays several times, with eager work and
+    synchronisations between replays; every replay equals the eager result."""
+    import torch
+    from paper_2511_19633_amd import binding
+    G = gpu["nlo"]
+    sizes = [700, 1500, 64, 900]
+    ins = _split(G, sizes, 17)
+    outs = [binding.DeviceEvents(n, workloads.MAX_SLOTS) for n in sizes]
+    batches = list(zip(ins, outs, sizes))
+    refs = [G.shower(ev, 8).to_host() for ev in ins]
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = G.capture(batches, 8, side)
+    try:
+        for rep in range(3):
+            for o in outs:
+                o.n.zero_()
+                o.E.zero_()
+                o.flags.fill_(7)
+            torch.cuda.synchronize()
+            g.launch(side)
+            side.synchronize()
+            for ref, o in zip(refs, outs):
+                _assert_same(ref, o.to_host(), ("replay", rep))
+            # eager library work between replays
+            G.shower(ins[0], 8)
+            torch.cuda.synchronize()
+    finally:
+        g.close()
 
 
 @pytest.mark.parametrize("key,n", [("ee", 10000), ("nlo", 3000)])
