@@ -113,7 +113,11 @@ typedef struct {
                             the 2-wave kernel and 256 otherwise (0: largest) */
     int grid;            /* blocks of the persistent launch (0: fill the GPU) */
     int compact_every;   /* cycles between wave refills (0: 4) */
-    float* trial_log;    /* LOG mode: device [log_cap][5] floats */
+    float* trial_log;    /* LOG mode: device [log_cap][5] floats, one row per
+                            initial-state winner trial with a positive weight:
+                            ln t, ln eta, z, table entry, ln(alpha_s(t)/
+                            alpha_s(t_c) W / shape(z)); rows beyond log_cap are
+                            counted, not stored */
     int64_t log_cap;
     unsigned long long* log_count; /* LOG mode: device counter */
     unsigned long long* stats;     /* optional device [GAPS_NSTATS] */
@@ -143,7 +147,10 @@ gaps_status gaps_hard_events(gaps_ctx ctx, int64_t first_id, int64_t n, uint64_t
 
 /* Shower in[0..n-1] into out[0..n-1] (section 2, appendices A and B).
  * in and out must not alias; out->max_slots bounds the final multiplicity
- * (GAPS_F_OVERFLOW otherwise).  params may be NULL (plain mode, defaults). */
+ * (GAPS_F_OVERFLOW otherwise).  params may be NULL (plain mode, defaults).
+ * Modes: PLAIN; LOG (plain, plus the trial log); LEARNED (needs
+ * gaps_mlp_tabulate first, else GAPS_ESTATE).  LOG and LEARNED run on the wave
+ * kernel (variant 0) only. */
 gaps_status gaps_shower(gaps_ctx ctx, const gaps_events* in, int64_t n, const gaps_params* params,
                         uint64_t seed, gaps_events* out, hipStream_t stream);
 
@@ -182,6 +189,79 @@ gaps_status gaps_graph_capture(gaps_ctx ctx, const gaps_batch* batches, int nbat
                                gaps_graph* out);
 gaps_status gaps_graph_launch(gaps_graph g, hipStream_t stream);
 gaps_status gaps_graph_destroy(gaps_graph g);
+
+/* ---- Learned initial-state veto bound (LEARNED mode) ----
+ * The paper bounds the PDF ratio x kernel of initial-state emissions with
+ * maxima fitted against eta (appendix A.2).  LEARNED mode replaces that
+ * constant, for the channels of the incoming partons (slots 0 and 1), by a
+ * learned bound per (table entry, eta bin, ln t cell): 8 cells uniform in ln t
+ * over the PDF grid's ln Q^2 range.  A channel draws against its cell's
+ * constant; a trial below the cell is a null at the cell edge (the evolution
+ * continues from there, exact by the factorisation of the no-emission
+ * probability); every real trial checks its weight against the bound and an
+ * event whose weight exceeds it is showered again in plain mode
+ * (GAPS_F_FALLBACK), so no violation is ever used.  Random-number stream 1.
+ *
+ * The bound comes from a network 4 -> 64 -> 64 -> 1 (ReLU) on features
+ * ((ln t - 10)/10, (ln eta + 7)/7, 2z - 1, (entry - 40)/32) predicting an upper
+ * quantile of ln(W / R) for logged trials (LOG mode rows), trained with the
+ * pinball loss: bfloat16 weights and first hidden layer, FP32 accumulation on
+ * the matrix cores, FP32 master weights and Adam.  Calibration takes, per
+ * entry, the largest residual on held-out rows plus 2^-6 (entries with fewer
+ * than 2000 rows keep the analytic bound); tabulation evaluates the network
+ * on 48 probe points per cell (3 ln t x 2 ln eta x 8 z), takes
+ * v = clip(delta + max, -20, 0) and stores min(R, R e^v rounded up to a 7-bit
+ * mantissa).  Parameter layout (4545 floats): W1[64][4] b1[64] W2[64][64]
+ * b2[64] W3[64] b3. */
+#define GAPS_MLP_PARAMS 4545
+#define GAPS_LEARN_CELLS (64 * 48 * 8)
+
+/* Network weights of the context: Philox He-uniform initialisation (key
+ * (seed, stream 4)) and zeroed Adam moments.  Synchronous. */
+gaps_status gaps_mlp_init(gaps_ctx ctx, uint64_t seed);
+/* Copy the FP32 master weights from / to HOST memory (GAPS_MLP_PARAMS floats);
+ * set also resets the Adam moments.  Synchronous. */
+gaps_status gaps_mlp_set(gaps_ctx ctx, const float* host_theta);
+gaps_status gaps_mlp_get(gaps_ctx ctx, float* host_theta);
+/* Features of n logged trials: rows device [n][5] -> x device [n][4], y [n],
+ * ent [n] (may be NULL). */
+gaps_status gaps_mlp_features(gaps_ctx ctx, const float* rows, int64_t n, float* x, float* y, int32_t* ent,
+                              hipStream_t stream);
+/* f[i] = network(x[i]), device arrays. */
+gaps_status gaps_mlp_forward(gaps_ctx ctx, const float* x, int64_t n, float* f, hipStream_t stream);
+/* Pinball-loss (quantile tau) gradient of the mean over n rows, ADDED to
+ * device grad[GAPS_MLP_PARAMS] and *loss (device; may be NULL). */
+gaps_status gaps_mlp_grad(gaps_ctx ctx, const float* x, const float* y, int64_t n, float tau, float* grad,
+                          float* loss, hipStream_t stream);
+
+typedef struct {
+    int64_t steps;       /* Adam steps */
+    int64_t batch;       /* rows per step, drawn at random from the n rows */
+    float lr, beta1, beta2, eps, tau;
+    uint64_t seed;       /* batch sampling (Philox stream 5) */
+} gaps_train_params;
+
+/* Train the context's network on device rows x [n][4], y [n]; step losses go
+ * to device loss[steps] (may be NULL).  Asynchronous. */
+gaps_status gaps_mlp_train(gaps_ctx ctx, const float* x, const float* y, int64_t n, const gaps_train_params* p,
+                           float* loss, hipStream_t stream);
+/* Calibration margins from held-out device rows (x, y, ent): per entry the
+ * largest y - f plus 2^-6, or +inf below 2000 rows.  Asynchronous. */
+gaps_status gaps_mlp_calibrate(gaps_ctx ctx, const float* x, const float* y, const int32_t* ent, int64_t n,
+                               hipStream_t stream);
+/* Margins from / to HOST memory (64 doubles, entries 8..71; +inf: analytic). */
+gaps_status gaps_mlp_set_delta(gaps_ctx ctx, const double* host_delta);
+gaps_status gaps_mlp_get_delta(gaps_ctx ctx, double* host_delta);
+/* Tabulate the learned bound from the current weights and margins and enable
+ * LEARNED mode for later gaps_shower calls on the same stream.  Asynchronous. */
+gaps_status gaps_mlp_tabulate(gaps_ctx ctx, hipStream_t stream);
+/* Copy the learned bound [64][48][8] (doubles) to HOST memory.  Synchronous;
+ * GAPS_ESTATE before gaps_mlp_tabulate. */
+gaps_status gaps_learned_table(gaps_ctx ctx, double* host_out);
+/* Install a learned bound [64][48][8] given in HOST memory (every value must be
+ * finite and at most the analytic table's entry; GAPS_EINVAL otherwise) and
+ * enable LEARNED mode.  Synchronous. */
+gaps_status gaps_learned_set_table(gaps_ctx ctx, const double* host_table);
 
 /* Per-event observables (section 4.1): obs is device [n][12], layout as in
  * the oracle's observables (Z pT, y, phi, phi*, jets; thrust and Durham y for

@@ -268,6 +268,8 @@ or_state* or_init(const or_config* cfg) {
     s->as_over = or_alphas(s, cfg->t_cut);
     double q2min = exp(cfg->lnq0);
     s->tc_is = cfg->t_cut > q2min ? cfg->t_cut : q2min;
+    for (int k = 0; k <= OR_NTB; ++k)
+        s->cell_edge[k] = cfg->lnq0 + (double)k * ((cfg->lnq1 - cfg->lnq0) / OR_NTB);
     if (cfg->pdf) {
         or_compute_bounds(s);
         if (cfg->process == 1) s->lo_wmax = or_lo_scan_wmax(s);
@@ -276,3 +278,7 @@ or_state* or_init(const or_config* cfg) {
 }
 
 void or_free(or_state* s) { free(s); }
+
+void or_cell_edges(const or_state* s, double* out) {
+    for (int k = 0; k <= OR_NTB; ++k) out[k] = s->cell_edge[k];
+}

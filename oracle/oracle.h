@@ -85,6 +85,35 @@ int or_hard_events(const or_state* s, int64_t first_id, int64_t n, uint64_t seed
 int or_shower(const or_state* s, const or_events* in, int64_t n, uint64_t seed,
               or_events* out, int nthreads);
 
+/* shower modes */
+#define OR_MODE_PLAIN 0
+#define OR_MODE_LEARNED 1
+#define OR_MODE_LOG 2
+
+typedef struct {
+    int mode;            /* OR_MODE_* */
+    /* LOG: one row of 5 floats per initial-state (IF, II) winner trial with a
+     * positive weight: ln t, ln eta, z, table entry of the splitting term,
+     * ln(alpha_s(t)/alpha_s(t_c) * W / shape(z)), the quantity the entry's
+     * constant bounds.  Rows beyond log_cap are counted, not stored. */
+    float* log;
+    int64_t log_cap;
+    int64_t* log_count;  /* in/out: rows so far */
+    /* LEARNED: the learned bound R_theta[64][48][8] (initial-state entries
+     * 8..71, eta bins, ln t cells) for the initial-state channels of the
+     * partons in slots 0 and 1; random-number stream 1; an event whose
+     * weight exceeds its learned bound is showered again in plain mode and
+     * flagged OR_F_FALLBACK. */
+    const double* learned;
+} or_opts;
+
+#define OR_LEARN_NTB 8
+/* ln t edges of the learned-bound cells (OR_LEARN_NTB + 1 values) */
+void or_cell_edges(const or_state* s, double* out);
+
+int or_shower_ex(const or_state* s, const or_events* in, int64_t n, uint64_t seed,
+                 or_events* out, int nthreads, const or_opts* opts);
+
 /* kinematic maps, exposed for the identity tests.
  * type: 0 FF, 1 FI, 2 IF, 3 II.  pe, ps: emitter/spectator before (E,px,py,pz).
  * vars: FF (z, y), FI (z, x), IF (x, u), II (x, v); phi azimuth.

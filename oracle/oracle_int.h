@@ -20,6 +20,12 @@
 #define OR_ENT_S3(f, T) (40 + 8 * (f) + (T))
 enum { FAM_A = 0, FAM_B = 1, FAM_C = 2, FAM_D = 3 };
 
+/* learned bound: initial-state entries 8..71, eta bins, OR_NTB cells uniform in
+ * ln t over the PDF grid's ln Q^2 range */
+#define OR_NTB 8
+#define OR_NIS 64
+#define OR_IS0 8
+
 #define OR_MAXM 256
 #define OR_MAXCH (2 * OR_MAXM)
 #define OR_MAXCYC 2000000
@@ -33,6 +39,7 @@ struct or_state {
     double tc_is;              /* cutoff of channels that need a PDF ratio */
     double b0;
     double bound[OR_NENT][OR_NB];
+    double cell_edge[OR_NTB + 1]; /* ln t edges of the learned-bound cells */
     double lo_wmax;
 };
 

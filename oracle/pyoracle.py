@@ -15,6 +15,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
+MODE_PLAIN, MODE_LEARNED, MODE_LOG = 0, 1, 2
+
+
+class OrOpts(C.Structure):
+    _fields_ = [("mode", C.c_int), ("log", C.POINTER(C.c_float)), ("log_cap", C.c_int64),
+                ("log_count", C.POINTER(C.c_int64)), ("learned", C.POINTER(C.c_double))]
+
+
 def build():
     subprocess.check_call(["sh", os.path.join(_HERE, "build.sh")])
 
@@ -63,6 +71,9 @@ def _lib():
     lib.or_hard_events.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, C.POINTER(OrEvents)]
     lib.or_shower.argtypes = [C.c_void_p, C.POINTER(OrEvents), C.c_int64, C.c_uint64,
                               C.POINTER(OrEvents), C.c_int]
+    lib.or_shower_ex.argtypes = [C.c_void_p, C.POINTER(OrEvents), C.c_int64, C.c_uint64,
+                                 C.POINTER(OrEvents), C.c_int, C.POINTER(OrOpts)]
+    lib.or_cell_edges.argtypes = [C.c_void_p, C.c_void_p]
     lib.or_map.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
                            C.c_void_p, C.c_void_p, C.c_int]
     lib.or_is_vars.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
@@ -163,6 +174,37 @@ class Oracle:
         out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
         si, so = events_struct(ev_in), events_struct(out)
         lib().or_shower(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads)
+        return out
+
+    def shower_log(self, ev_in: records.Events, seed, log_cap, nthreads=1, max_slots=None):
+        """LOG mode: the plain shower plus its initial-state trial log
+        (rows: ln t, ln eta, z, table entry, ln weight).  Returns (events, rows,
+        total rows seen)."""
+        out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
+        si, so = events_struct(ev_in), events_struct(out)
+        log = np.zeros((max(int(log_cap), 1), 5), dtype=np.float32)
+        cnt = C.c_int64(0)
+        o = OrOpts(MODE_LOG, log.ctypes.data_as(C.POINTER(C.c_float)), int(log_cap), C.pointer(cnt), None)
+        rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
+        if rc != 0:
+            raise RuntimeError("or_shower_ex failed")
+        return out, log[:min(cnt.value, int(log_cap))], cnt.value
+
+    def shower_learned(self, ev_in: records.Events, seed, table, nthreads=1, max_slots=None):
+        """LEARNED mode with the bound table [64][48][8] (doubles)."""
+        out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
+        si, so = events_struct(ev_in), events_struct(out)
+        tab = np.ascontiguousarray(table, dtype=np.float64)
+        assert tab.shape == (64, 48, 8)
+        o = OrOpts(MODE_LEARNED, None, 0, None, tab.ctypes.data_as(C.POINTER(C.c_double)))
+        rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
+        if rc != 0:
+            raise RuntimeError("or_shower_ex failed")
+        return out
+
+    def cell_edges(self):
+        out = np.zeros(9, dtype=np.float64)
+        lib().or_cell_edges(self.h, out.ctypes.data_as(C.c_void_p))
         return out
 
     def observables(self, ev: records.Events):

@@ -18,10 +18,10 @@ typedef struct {
     int pid[OR_MAXM], col[OR_MAXM], acol[OR_MAXM], st[OR_MAXM];
 } ev_t;
 
-typedef struct { int kern, shape, flav; double coefR, c; } term_t;
+typedef struct { int kern, shape, flav, ent; double coefR, c; } term_t;
 
 typedef struct {
-    int i, k, side, type, alive, heavy;
+    int i, k, side, type, alive, heavy, ebin;
     double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
     double zlo, zhi, omzlo, omzhi;
     int nterm;
@@ -83,9 +83,9 @@ static double shape_val(int sh, double z, double omz) {
     }
 }
 
-static void add_term(chan_t* ch, int kern, int shape, int flav, double coefR) {
+static void add_term(chan_t* ch, int kern, int shape, int flav, double coefR, int ent) {
     term_t* t = &ch->term[ch->nterm++];
-    t->kern = kern; t->shape = shape; t->flav = flav; t->coefR = coefR; t->c = 0.0;
+    t->kern = kern; t->shape = shape; t->flav = flav; t->coefR = coefR; t->c = 0.0; t->ent = ent;
 }
 
 /* Channel constants (dipole end i with spectator k on colour side `side`):
@@ -139,33 +139,36 @@ static void setup_channel(const or_state* S, const ev_t* e, int i, int side, int
     /* overestimate terms */
     if (!isE) {
         double R = 1.0;
-        if (ch->type == T_FI) R = S->bound[OR_ENT_FI(or_pdf_table(e->pid[k]))][eta_bin(etak)];
+        int ent = -1;
+        if (ch->type == T_FI) {
+            ent = OR_ENT_FI(or_pdf_table(e->pid[k]));
+            R = S->bound[ent][eta_bin(etak)];
+        }
         if (e->pid[i] == 21) {
-            add_term(ch, K_GGG, SH_SOFT, 0, OR_CA * R);
-            for (int f = 1; f <= S->c.nf; ++f) add_term(ch, K_GQQ, SH_FLAT, f, 0.5 * OR_TR * R);
+            add_term(ch, K_GGG, SH_SOFT, 0, OR_CA * R, ent);
+            for (int f = 1; f <= S->c.nf; ++f) add_term(ch, K_GQQ, SH_FLAT, f, 0.5 * OR_TR * R, ent);
         } else {
-            add_term(ch, K_QQG, SH_SOFT, 0, 2.0 * OR_CF * R);
+            add_term(ch, K_QQG, SH_SOFT, 0, 2.0 * OR_CF * R, ent);
         }
     } else {
         int bin = eta_bin(eta);
+        ch->ebin = bin;
         int sh2 = ch->type == T_II ? SH_S3 : SH_S1;
         if (e->pid[i] == 21) {
-            add_term(ch, K_C, SH_S1, 0, S->bound[OR_ENT_S1(FAM_C, 0)][bin]);
+            add_term(ch, K_C, SH_S1, 0, S->bound[OR_ENT_S1(FAM_C, 0)][bin], OR_ENT_S1(FAM_C, 0));
             static const int par[10] = {1, 2, 3, 4, 5, -1, -2, -3, -4, -5};
             for (int m = 0; m < 10; ++m) {
                 int a = par[m];
                 if (abs(a) > S->c.nf) continue;
                 int T = or_pdf_table(a);
-                double R = ch->type == T_II ? S->bound[OR_ENT_S3(FAM_D, T)][bin]
-                                            : S->bound[OR_ENT_S1(FAM_D, T)][bin];
-                add_term(ch, K_D, sh2, a, R);
+                int ent = ch->type == T_II ? OR_ENT_S3(FAM_D, T) : OR_ENT_S1(FAM_D, T);
+                add_term(ch, K_D, sh2, a, S->bound[ent][bin], ent);
             }
         } else {
             int T = or_pdf_table(e->pid[i]);
-            add_term(ch, K_A, SH_S1, 0, S->bound[OR_ENT_S1(FAM_A, T)][bin]);
-            double R = ch->type == T_II ? S->bound[OR_ENT_S3(FAM_B, T)][bin]
-                                        : S->bound[OR_ENT_S1(FAM_B, T)][bin];
-            add_term(ch, K_B, sh2, 0, R);
+            add_term(ch, K_A, SH_S1, 0, S->bound[OR_ENT_S1(FAM_A, T)][bin], OR_ENT_S1(FAM_A, T));
+            int ent = ch->type == T_II ? OR_ENT_S3(FAM_B, T) : OR_ENT_S1(FAM_B, T);
+            add_term(ch, K_B, sh2, 0, S->bound[ent][bin], ent);
         }
     }
     double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
@@ -337,6 +340,7 @@ void or_map(int type, const double pe[4], const double ps[4], double v1, double 
 typedef struct {
     int ok;
     double x, omx, y, uv, w;
+    double wn; /* the weight before division by the table constant: w * over_scale * coefR */
 } veto_t;
 
 /* acceptance weight of the winner trial (term tm, scale t, momentum fraction z) */
@@ -407,7 +411,9 @@ static veto_t weight(const or_state* S, const ev_t* e, const chan_t* ch, const t
         r.x = x; r.omx = omx; r.uv = uv;
     }
     double over = S->c.over_scale * tm->coefR * shape_val(tm->shape, z, omz);
-    r.w = or_alphas(S, t) / S->as_over * W / over;
+    double ar = or_alphas(S, t) / S->as_over;
+    r.w = ar * W / over;
+    r.wn = ar * W / shape_val(tm->shape, z, omz);
     r.ok = 1;
     return r;
 }
@@ -475,8 +481,62 @@ static int finite4(const double* p) {
     return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(p[3]);
 }
 
-static void shower_one(const or_state* S, const or_events* in, int64_t e_in, uint64_t seed,
-                       or_events* out, int64_t e_out, ev_t* ev, chan_t* ch) {
+/* ---- learned bound (LEARNED mode) ----
+ * An initial-state channel's overestimate constant depends on the cell of its
+ * current scale: c_k = sum over terms of alpha_s(t_c)/(2 pi) * R_theta[entry][eta
+ * bin][k] * (z integral of the term's shape).  Cell k spans (edge[k], edge[k+1]]. */
+static double lrn(const double* L, int ent, int ebin, int k) {
+    return L[((ent - OR_IS0) * OR_NB + ebin) * OR_NTB + k];
+}
+
+/* the cell of a scale: the largest k with edge[k] < ln t (0 if none) */
+static int cell_of(const or_state* S, double lnt) {
+    int k = OR_NTB - 1;
+    while (k > 0 && !(S->cell_edge[k] < lnt)) --k;
+    return k;
+}
+
+static double learned_c(const or_state* S, const chan_t* ch, const double* L, int k) {
+    double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
+    double c = 0.0;
+    for (int m = 0; m < ch->nterm; ++m) {
+        const term_t* t = &ch->term[m];
+        c += af * lrn(L, t->ent, ch->ebin, k) * shape_int(t->shape, ch);
+    }
+    return c;
+}
+
+/* trial log shared by the threads of one or_shower_ex call */
+typedef struct {
+    const or_opts* o;
+    pthread_mutex_t mu;
+} logsink_t;
+
+/* one row per initial-state winner trial with a positive weight (LOG mode) */
+static void log_trial(logsink_t* L, double t, double eta, double z, int ent, double wn) {
+    pthread_mutex_lock(&L->mu);
+    int64_t k = *L->o->log_count;
+    *L->o->log_count = k + 1;
+    if (k < L->o->log_cap) {
+        float* r = L->o->log + 5 * k;
+        r[0] = (float)log(t);
+        r[1] = (float)log(eta);
+        r[2] = (float)z;
+        r[3] = (float)ent;
+        r[4] = (float)log(wn);
+    }
+    pthread_mutex_unlock(&L->mu);
+}
+
+/* Shower one event.  mode OR_MODE_LEARNED draws the initial-state channels
+ * against the cell constants of the learned table Lt (random-number stream 1)
+ * and returns 1, writing nothing, as soon as a weight exceeds its learned bound;
+ * the caller then showers the event again in plain mode. */
+static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint64_t seed,
+                      or_events* out, int64_t e_out, ev_t* ev, chan_t* ch, logsink_t* L,
+                      int mode, const double* Lt) {
+    const int learned = mode == OR_MODE_LEARNED;
+    const uint32_t stream = learned ? 1u : 0u;
     const int64_t ci = in->cap, co = out->cap;
     int M = out->max_slots < OR_MAXM ? out->max_slots : OR_MAXM;
     ev->n = in->n[e_in];
@@ -501,9 +561,11 @@ static void shower_one(const or_state* S, const or_events* in, int64_t e_in, uin
         uint32_t cycle = 0;
         for (;;) {
             if (cycle >= OR_MAXCYC) { flags |= OR_F_MAXCYC; break; }
-            /* trial scales of every channel; the winner is the largest */
+            /* trial scales of every channel; the winner is the largest.  In
+             * learned mode a trial of an initial-state channel that falls below
+             * its cell is a null candidate at the cell edge. */
             double best = -INFINITY;
-            int win = -1;
+            int win = -1, wnull = 0, wcell = 0;
             uint32_t curblk = 0xFFFFFFFFu;
             double ub[4];
             for (int c = 0; c < nch; ++c) {
@@ -515,37 +577,63 @@ static void shower_one(const or_state* S, const or_events* in, int64_t e_in, uin
                 uint32_t slot = 2u * (uint32_t)C->i + (uint32_t)C->side;
                 if ((slot >> 2) != curblk) {
                     curblk = slot >> 2;
-                    or_rng_block(seed, 0u, id, cycle, curblk, ub);
+                    or_rng_block(seed, stream, id, cycle, curblk, ub);
                 }
                 double lu = log(ub[slot & 3u]);
                 ntri += 1;
+                double invc = C->invc, floor = -INFINITY;
+                /* learned cells apply to the incoming partons' channels (emitter slot 0 or 1) */
+                int lch = learned && (C->type == T_IF || C->type == T_II) && C->i < 2, k = 0;
+                if (lch) {
+                    k = cell_of(S, lnTch);
+                    invc = 1.0 / learned_c(S, C, Lt, k);
+                    floor = S->cell_edge[k];
+                }
                 double key;
-                if (!C->heavy) key = lnTch + lu * C->invc;
-                else key = log(C->m2 + (Tch - C->m2) * exp(lu * C->invc));
+                if (!C->heavy) key = lnTch + lu * invc;
+                else key = log(C->m2 + (Tch - C->m2) * exp(lu * invc));
+                int isnull = 0;
+                if (lch && key < floor && floor > C->lntcut) { key = floor; isnull = 1; }
                 if (key < C->lntcut) continue;
-                if (key > best) { best = key; win = c; }
+                if (key > best) { best = key; win = c; wnull = isnull; wcell = k; }
             }
             if (win < 0) break;
+            if (wnull) {
+                /* no channel emits above the edge: continue from it */
+                T = exp(best);
+                lnT = best;
+                cycle += 1;
+                continue;
+            }
             double t = exp(best);
             const chan_t* C = &ch[win];
+            const int lch = learned && (C->type == T_IF || C->type == T_II) && C->i < 2;
             double u[4];
-            or_rng_block(seed, 0u, id, cycle, 0xFFFFFFFFu, u);
+            or_rng_block(seed, stream, id, cycle, 0xFFFFFFFFu, u);
             /* splitting family and flavour in proportion to their overestimates */
-            double target = u[0] * C->c, cum = 0.0;
+            double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
+            double ctot = lch ? learned_c(S, C, Lt, wcell) : C->c;
+            double target = u[0] * ctot, cum = 0.0;
             int sel = -1;
             for (int m = 0; m < C->nterm; ++m) {
-                cum += C->term[m].c;
+                cum += lch ? af * lrn(Lt, C->term[m].ent, C->ebin, wcell) * shape_int(C->term[m].shape, C)
+                           : C->term[m].c;
                 if (target < cum) { sel = m; break; }
             }
             if (sel < 0)
                 for (int m = C->nterm - 1; m >= 0; --m)
                     if (C->term[m].c > 0.0) { sel = m; break; }
-            const term_t* tm = &C->term[sel];
+            term_t tsel = C->term[sel];
+            if (lch) tsel.coefR = lrn(Lt, tsel.ent, C->ebin, wcell);
+            const term_t* tm = &tsel;
             double I = shape_int(tm->shape, C);
             double z, omz;
             shape_sample(tm->shape, C, I, u[1], &z, &omz);
             double phi = 2.0 * OR_PI * u[2];
             veto_t v = weight(S, ev, C, tm, t, z, omz);
+            if (L && (C->type == T_IF || C->type == T_II) && v.ok && v.wn > 0.0)
+                log_trial(L, t, C->eta, z, tm->ent, v.wn);
+            if (lch && v.ok && v.w > 1.0) return 1; /* the learned bound failed */
             if (v.ok && v.w > 1.0) { nviol += 1; flags |= OR_F_VIOL; }
             if (v.ok && u[3] < v.w) {
                 if (ev->n + 1 > M) { flags |= OR_F_OVERFLOW; break; }
@@ -580,6 +668,7 @@ static void shower_one(const or_state* S, const or_events* in, int64_t e_in, uin
     if (out->n_accept) out->n_accept[e_out] = nacc;
     if (out->n_viol) out->n_viol[e_out] = nviol;
     if (out->t1) out->t1[e_out] = t1;
+    return 0;
 }
 
 typedef struct {
@@ -588,31 +677,61 @@ typedef struct {
     or_events* out;
     uint64_t seed;
     int64_t lo, hi;
+    logsink_t* L;
+    int mode;
+    const double* Lt;
 } job_t;
 
 static void* run_job(void* arg) {
     job_t* J = (job_t*)arg;
     ev_t* ev = (ev_t*)malloc(sizeof(ev_t));
     chan_t* ch = (chan_t*)malloc(sizeof(chan_t) * OR_MAXCH);
-    for (int64_t e = J->lo; e < J->hi; ++e) shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch);
+    for (int64_t e = J->lo; e < J->hi; ++e) {
+        if (J->mode == OR_MODE_LEARNED &&
+            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt) == 0)
+            continue;
+        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL);
+        if (J->mode == OR_MODE_LEARNED && J->out->flags) J->out->flags[e] |= OR_F_FALLBACK;
+    }
     free(ev);
     free(ch);
     return NULL;
 }
 
-int or_shower(const or_state* S, const or_events* in, int64_t n, uint64_t seed, or_events* out,
-              int nthreads) {
+int or_shower_ex(const or_state* S, const or_events* in, int64_t n, uint64_t seed, or_events* out,
+                 int nthreads, const or_opts* opts) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
+    int mode = opts ? opts->mode : OR_MODE_PLAIN;
+    if (mode != OR_MODE_PLAIN && mode != OR_MODE_LOG && mode != OR_MODE_LEARNED) return -1;
+    if (mode == OR_MODE_LEARNED && !opts->learned) return -1;
+    logsink_t sink, *L = NULL;
+    if (mode == OR_MODE_LOG) {
+        if (!opts->log_count || (opts->log_cap > 0 && !opts->log)) return -1;
+        sink.o = opts;
+        pthread_mutex_init(&sink.mu, NULL);
+        L = &sink;
+    }
     job_t jobs[256];
     pthread_t th[256];
     for (int k = 0; k < nthreads; ++k) {
         jobs[k].S = S; jobs[k].in = in; jobs[k].out = out; jobs[k].seed = seed;
         jobs[k].lo = n * k / nthreads;
         jobs[k].hi = n * (k + 1) / nthreads;
+        jobs[k].L = L;
+        jobs[k].mode = mode;
+        jobs[k].Lt = mode == OR_MODE_LEARNED ? opts->learned : NULL;
     }
-    if (nthreads == 1) { run_job(&jobs[0]); return 0; }
-    for (int k = 0; k < nthreads; ++k) pthread_create(&th[k], NULL, run_job, &jobs[k]);
-    for (int k = 0; k < nthreads; ++k) pthread_join(th[k], NULL);
+    if (nthreads == 1) run_job(&jobs[0]);
+    else {
+        for (int k = 0; k < nthreads; ++k) pthread_create(&th[k], NULL, run_job, &jobs[k]);
+        for (int k = 0; k < nthreads; ++k) pthread_join(th[k], NULL);
+    }
+    if (L) pthread_mutex_destroy(&sink.mu);
     return 0;
+}
+
+int or_shower(const or_state* S, const or_events* in, int64_t n, uint64_t seed, or_events* out,
+              int nthreads) {
+    return or_shower_ex(S, in, n, seed, out, nthreads, NULL);
 }

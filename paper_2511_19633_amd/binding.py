@@ -60,6 +60,13 @@ class GapsBatch(C.Structure):
 
 
 MAX_BATCHES = 4096
+MLP_PARAMS = 4545
+LEARN_SHAPE = (64, 48, 8)
+
+
+class GapsTrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("batch", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("tau", C.c_float), ("seed", C.c_uint64)]
 
 _lib = None
 
@@ -84,6 +91,19 @@ def lib():
         L.gaps_graph_launch.argtypes = [vp, vp]
         L.gaps_graph_destroy.argtypes = [vp]
         L.gaps_observables.argtypes = [vp, C.POINTER(GapsEvents), i64, vp, vp]
+        L.gaps_mlp_init.argtypes = [vp, u64]
+        L.gaps_mlp_set.argtypes = [vp, vp]
+        L.gaps_mlp_get.argtypes = [vp, vp]
+        L.gaps_mlp_features.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.gaps_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.gaps_mlp_grad.argtypes = [vp, vp, vp, i64, C.c_float, vp, vp, vp]
+        L.gaps_mlp_train.argtypes = [vp, vp, vp, i64, C.POINTER(GapsTrainParams), vp, vp]
+        L.gaps_mlp_calibrate.argtypes = [vp, vp, vp, vp, i64, vp]
+        L.gaps_mlp_set_delta.argtypes = [vp, vp]
+        L.gaps_mlp_get_delta.argtypes = [vp, vp]
+        L.gaps_mlp_tabulate.argtypes = [vp, vp]
+        L.gaps_learned_table.argtypes = [vp, vp]
+        L.gaps_learned_set_table.argtypes = [vp, vp]
         L.gaps_histogram.argtypes = [vp, vp, vp, i64, C.c_int, C.c_double, C.c_double, C.c_int, vp, vp, vp]
         L.gaps_bounds.argtypes = [vp, vp]
         L.gaps_pdf_eval.argtypes = [vp, vp, vp, vp, i64, vp, vp]
@@ -238,6 +258,85 @@ class Gaps:
         _check(lib().gaps_graph_capture(self.h, arr, len(batches), C.byref(p), seed, _stream(stream),
                                         C.byref(g)))
         return Graph(g, batches)
+
+    # ---- trial log and the learned bound
+    def shower_log(self, ev_in: DeviceEvents, seed: int, log_cap: int, stream=None, **params):
+        """LOG mode: returns (events, rows [min(count, cap)][5] device tensor, count)."""
+        log = torch.zeros((max(int(log_cap), 1), 5), dtype=torch.float32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.uint64, device="cuda")
+        out = self.shower(ev_in, seed, mode=MODE_LOG, trial_log=log, log_count=cnt, stream=stream, **params)
+        torch.cuda.synchronize()
+        count = int(cnt.item())
+        return out, log[:min(count, int(log_cap))], count
+
+    def mlp_init(self, seed: int):
+        _check(lib().gaps_mlp_init(self.h, seed))
+
+    def mlp_set(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.shape == (MLP_PARAMS,)
+        _check(lib().gaps_mlp_set(self.h, th.ctypes.data_as(C.c_void_p)))
+
+    def mlp_get(self) -> np.ndarray:
+        th = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib().gaps_mlp_get(self.h, th.ctypes.data_as(C.c_void_p)))
+        return th
+
+    def mlp_features(self, rows: torch.Tensor, stream=None):
+        n = rows.shape[0]
+        x = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+        y = torch.zeros(n, dtype=torch.float32, device="cuda")
+        ent = torch.zeros(n, dtype=torch.int32, device="cuda")
+        _check(lib().gaps_mlp_features(self.h, _ptr(rows.contiguous()), n, _ptr(x), _ptr(y), _ptr(ent),
+                                       _stream(stream)))
+        return x, y, ent
+
+    def mlp_forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        f = torch.zeros(x.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().gaps_mlp_forward(self.h, _ptr(x.contiguous()), x.shape[0], _ptr(f), _stream(stream)))
+        return f
+
+    def mlp_grad(self, x: torch.Tensor, y: torch.Tensor, tau: float, stream=None):
+        g = torch.zeros(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        _check(lib().gaps_mlp_grad(self.h, _ptr(x.contiguous()), _ptr(y.contiguous()), x.shape[0], tau, _ptr(g),
+                                   _ptr(loss), _stream(stream)))
+        return g, loss
+
+    def mlp_train(self, x: torch.Tensor, y: torch.Tensor, steps: int, batch: int = 65536, lr: float = 3e-3,
+                  tau: float = 0.999, beta1=0.9, beta2=0.999, eps=1e-8, seed=0, stream=None) -> torch.Tensor:
+        p = GapsTrainParams(steps, batch, lr, beta1, beta2, eps, tau, seed)
+        loss = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
+        _check(lib().gaps_mlp_train(self.h, _ptr(x.contiguous()), _ptr(y.contiguous()), x.shape[0], C.byref(p),
+                                    _ptr(loss), _stream(stream)))
+        return loss
+
+    def mlp_calibrate(self, x, y, ent, stream=None):
+        _check(lib().gaps_mlp_calibrate(self.h, _ptr(x.contiguous()), _ptr(y.contiguous()), _ptr(ent.contiguous()),
+                                        x.shape[0], _stream(stream)))
+
+    def mlp_set_delta(self, delta):
+        d = np.ascontiguousarray(delta, dtype=np.float64)
+        assert d.shape == (64,)
+        _check(lib().gaps_mlp_set_delta(self.h, d.ctypes.data_as(C.c_void_p)))
+
+    def mlp_get_delta(self) -> np.ndarray:
+        d = np.zeros(64, dtype=np.float64)
+        _check(lib().gaps_mlp_get_delta(self.h, d.ctypes.data_as(C.c_void_p)))
+        return d
+
+    def mlp_tabulate(self, stream=None):
+        _check(lib().gaps_mlp_tabulate(self.h, _stream(stream)))
+
+    def learned_table(self) -> np.ndarray:
+        t = np.zeros(LEARN_SHAPE, dtype=np.float64)
+        _check(lib().gaps_learned_table(self.h, t.ctypes.data_as(C.c_void_p)))
+        return t
+
+    def learned_set_table(self, table):
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        assert t.shape == LEARN_SHAPE
+        _check(lib().gaps_learned_set_table(self.h, t.ctypes.data_as(C.c_void_p)))
 
     def observables(self, ev: DeviceEvents, n: int | None = None, stream=None) -> torch.Tensor:
         n = ev.cap if n is None else n

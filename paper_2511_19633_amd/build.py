@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["capi.hip", "kernels.hip", "shower.hip", "shower_wave.hip", "obs.hip"]
+SOURCES = ["capi.hip", "kernels.hip", "shower.hip", "shower_wave.hip", "obs.hip", "mlp.hip"]
 LIB = os.path.join(HERE, "libgaps.so")
 
 FLAGS = [

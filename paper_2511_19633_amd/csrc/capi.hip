@@ -34,8 +34,8 @@ struct ScratchMem {
 gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   size_t per_lane = (size_t)slots * (4 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int8_t)) +
-                    (size_t)nch * (sizeof(uint32_t) + 9 * sizeof(double));
-  size_t need = per_lane * (size_t)lanes + 256 * 24 + 64;
+                    (size_t)nch * (sizeof(uint32_t) + 9 * sizeof(double)) + 2 * gaps::kNTB * 4 * sizeof(double);
+  size_t need = per_lane * (size_t)lanes + 256 * 26 + 64;
   if (need > m.bytes || m.S.lanes != lanes || m.S.max_slots != slots) {
     if (need > m.bytes) {
       if (m.mem) (void)hipFree(m.mem);
@@ -62,6 +62,8 @@ gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
     S.ctlim = (double*)take(cs * 8); S.clntlim = (double*)take(cs * 8); S.cinvc = (double*)take(cs * 8);
     S.cc = (double*)take(cs * 8); S.cs = (double*)take(cs * 8); S.czlo = (double*)take(cs * 8);
     S.comzhi = (double*)take(cs * 8); S.cI1 = (double*)take(cs * 8); S.cI2 = (double*)take(cs * 8);
+    S.cinvk = (double*)take((size_t)gaps::kNTB * 4 * lanes * 8);
+    S.cck = (double*)take((size_t)gaps::kNTB * 4 * lanes * 8);
     S.queue = (unsigned long long*)take(64);
     if ((size_t)(p - (char*)m.mem) > m.bytes) return GAPS_ENOMEM;
   }
@@ -105,6 +107,14 @@ struct gaps_ctx_s {
   double* d_bound = nullptr;
   ScratchMem scratch;  // shower scratch, grown on demand
   BatchMem batches;    // batch table of gaps_shower_stream
+  // learned-bound network: one allocation for weights, Adam state, margins, table
+  void* mlp_mem = nullptr;
+  float *theta = nullptr, *mom1 = nullptr, *mom2 = nullptr, *grad = nullptr;
+  uint16_t* wb = nullptr;
+  double *delta = nullptr, *table = nullptr;
+  unsigned long long *maxbits = nullptr, *count = nullptr;
+  float *probe_x = nullptr, *probe_f = nullptr;
+  int64_t adam_step = 0;
 };
 
 struct gaps_graph_s {
@@ -173,6 +183,9 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   C.sw2 = cfg->sw2; C.gf = cfg->gf; C.mll_min = cfg->mll_min; C.mll_max = cfg->mll_max; C.p_s = cfg->p_s;
   C.over_scale = cfg->over_scale > 0.0 ? cfg->over_scale : 1.0;
   C.lnx0 = cfg->lnx0; C.lnx1 = cfg->lnx1; C.lnq0 = cfg->lnq0; C.lnq1 = cfg->lnq1;
+  for (int k = 0; k <= gaps::kNTB; ++k)
+    C.cell_edge[k] = cfg->lnq0 + (double)k * ((cfg->lnq1 - cfg->lnq0) / gaps::kNTB);
+  C.learn = nullptr;
   C.dlnx = (cfg->lnx1 - cfg->lnx0) / (cfg->nx - 1);
   C.dlnq = (cfg->lnq1 - cfg->lnq0) / (cfg->nq - 1);
   C.pdf = c->d_pdf;
@@ -209,6 +222,9 @@ gaps_status gaps_destroy(gaps_ctx c) {
   if (c->d_bound) (void)hipFree(c->d_bound);
   if (c->scratch.mem) (void)hipFree(c->scratch.mem);
   free_batches(c->batches);
+  if (c->mlp_mem) (void)hipFree(c->mlp_mem);
+  if (c->probe_x) (void)hipFree(c->probe_x);
+  if (c->probe_f) (void)hipFree(c->probe_f);
   delete c;
   return GAPS_OK;
 }
@@ -244,8 +260,17 @@ struct Plan {
 gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64_t seed, Plan& pl) {
   gaps_params P{};
   if (params) P = *params;
-  if (P.mode != GAPS_MODE_PLAIN) return GAPS_ESTATE;
   if (P.variant < 0 || P.variant > 1) return GAPS_EINVAL;
+  if (P.mode != GAPS_MODE_PLAIN) {
+    if (P.variant != 0) return GAPS_EINVAL;  // the reference variant runs plain mode only
+    if (P.mode == GAPS_MODE_LEARNED) {
+      if (!c->C.learn) return GAPS_ESTATE;
+    } else if (P.mode == GAPS_MODE_LOG) {
+      if (!P.log_count || P.log_cap < 0 || (P.log_cap > 0 && !P.trial_log)) return GAPS_EINVAL;
+    } else {
+      return GAPS_EINVAL;
+    }
+  }
   const int wps = P.waves_per_simd > 0 ? P.waves_per_simd : 2;
   if (wps < 2 || wps > 4) return GAPS_EINVAL;
   // the 2-wave kernel compacts its tail across up to 8 waves of a block
@@ -274,6 +299,9 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   A.seed = seed;
   A.n = n;
   A.stats = P.stats;
+  A.log = P.trial_log;
+  A.log_cap = P.log_cap;
+  A.log_count = P.log_count;
   return GAPS_OK;
 }
 
@@ -449,6 +477,226 @@ gaps_status gaps_rng_blocks(uint64_t seed, uint32_t stream_id, const int64_t* id
   hipLaunchKernelGGL(gaps::k_rng_blocks, dim3(grid_for(n, 256)), dim3(256), 0, stream, seed, stream_id, id, c2, c3,
                      n, out);
   GAPS_HIP(hipGetLastError());
+  return GAPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned initial-state veto bound: network state, training, tabulation
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kNP = gaps::kMlpParams;
+
+gaps_status mlp_alloc(gaps_ctx c) {
+  if (c->mlp_mem) return GAPS_OK;
+  const size_t fl = ((size_t)kNP * 4 + 255) & ~(size_t)255;
+  const size_t need = 4 * fl + (((size_t)kNP * 2 + 255) & ~(size_t)255) + 64 * 8 +
+                      (size_t)GAPS_LEARN_CELLS * 8 + 2 * 64 * 8 + 1024;
+  if (hipMalloc(&c->mlp_mem, need) != hipSuccess) return GAPS_ENOMEM;
+  char* p = (char*)c->mlp_mem;
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return (void*)r;
+  };
+  c->theta = (float*)take((size_t)kNP * 4);
+  c->mom1 = (float*)take((size_t)kNP * 4);
+  c->mom2 = (float*)take((size_t)kNP * 4);
+  c->grad = (float*)take((size_t)kNP * 4);
+  c->wb = (uint16_t*)take((size_t)kNP * 2);
+  c->delta = (double*)take(64 * 8);
+  c->table = (double*)take((size_t)GAPS_LEARN_CELLS * 8);
+  c->maxbits = (unsigned long long*)take(64 * 8);
+  c->count = (unsigned long long*)take(64 * 8);
+  return GAPS_OK;
+}
+
+// fresh optimiser state and analytic margins around new weights in c->theta
+gaps_status mlp_reset(gaps_ctx c) {
+  GAPS_HIP(hipMemset(c->mom1, 0, (size_t)kNP * 4));
+  GAPS_HIP(hipMemset(c->mom2, 0, (size_t)kNP * 4));
+  GAPS_HIP(hipMemset(c->grad, 0, (size_t)kNP * 4));
+  hipLaunchKernelGGL(gaps::k_mlp_pack, dim3((kNP + 255) / 256), dim3(256), 0, 0, c->theta, c->wb, kNP);
+  GAPS_HIP(hipGetLastError());
+  double inf[64];
+  for (int q = 0; q < 64; ++q) inf[q] = INFINITY;
+  GAPS_HIP(hipMemcpy(c->delta, inf, sizeof(inf), hipMemcpyHostToDevice));
+  GAPS_HIP(hipDeviceSynchronize());
+  c->adam_step = 0;
+  return GAPS_OK;
+}
+
+unsigned mlp_grid(int64_t rows, unsigned cap) {
+  const int64_t tiles = (rows + 15) / 16;
+  int64_t blocks = (tiles + 3) / 4;
+  if (blocks < 1) blocks = 1;
+  return (unsigned)(blocks < cap ? blocks : cap);
+}
+
+}  // namespace
+
+extern "C" {
+
+gaps_status gaps_mlp_init(gaps_ctx c, uint64_t seed) {
+  if (!c) return GAPS_EINVAL;
+  gaps_status s = mlp_alloc(c);
+  if (s != GAPS_OK) return s;
+  hipLaunchKernelGGL(gaps::k_mlp_init, dim3((kNP + 255) / 256), dim3(256), 0, 0, seed, c->theta, kNP);
+  GAPS_HIP(hipGetLastError());
+  return mlp_reset(c);
+}
+
+gaps_status gaps_mlp_set(gaps_ctx c, const float* host_theta) {
+  if (!c || !host_theta) return GAPS_EINVAL;
+  gaps_status s = mlp_alloc(c);
+  if (s != GAPS_OK) return s;
+  GAPS_HIP(hipMemcpy(c->theta, host_theta, (size_t)kNP * 4, hipMemcpyHostToDevice));
+  return mlp_reset(c);
+}
+
+gaps_status gaps_mlp_get(gaps_ctx c, float* host_theta) {
+  if (!c || !host_theta) return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  GAPS_HIP(hipDeviceSynchronize());
+  GAPS_HIP(hipMemcpy(host_theta, c->theta, (size_t)kNP * 4, hipMemcpyDeviceToHost));
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_features(gaps_ctx c, const float* rows, int64_t n, float* x, float* y, int32_t* ent,
+                              hipStream_t stream) {
+  if (!c || n < 0 || (n > 0 && (!rows || !x || !y))) return GAPS_EINVAL;
+  if (n == 0) return GAPS_OK;
+  hipLaunchKernelGGL(gaps::k_mlp_features, dim3(grid_for(n, 256)), dim3(256), 0, stream, rows, n, c->d_bound, x, y,
+                     ent);
+  GAPS_HIP(hipGetLastError());
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_forward(gaps_ctx c, const float* x, int64_t n, float* f, hipStream_t stream) {
+  if (!c || n < 0 || (n > 0 && (!x || !f))) return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  if (n == 0) return GAPS_OK;
+  hipLaunchKernelGGL(gaps::k_mlp_fwd, dim3(mlp_grid(n, 4096)), dim3(256), 0, stream, c->wb, x, n, f);
+  GAPS_HIP(hipGetLastError());
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_grad(gaps_ctx c, const float* x, const float* y, int64_t n, float tau, float* grad, float* loss,
+                          hipStream_t stream) {
+  if (!c || n <= 0 || !x || !y || !grad || !(tau > 0.f && tau < 1.f)) return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  hipLaunchKernelGGL(gaps::k_mlp_grad, dim3(mlp_grid(n, 256)), dim3(256), 0, stream, c->wb, x, y, n, n, 0ull,
+                     (int64_t)0, 0, tau, (float)(1.0 / (double)n), grad, loss);
+  GAPS_HIP(hipGetLastError());
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_train(gaps_ctx c, const float* x, const float* y, int64_t n, const gaps_train_params* p,
+                           float* loss, hipStream_t stream) {
+  if (!c || !p || n <= 0 || !x || !y || p->steps < 0 || p->batch <= 0) return GAPS_EINVAL;
+  if (!(p->tau > 0.f && p->tau < 1.f) || !(p->lr > 0.f) || !(p->beta1 >= 0.f && p->beta1 < 1.f) ||
+      !(p->beta2 >= 0.f && p->beta2 < 1.f) || !(p->eps > 0.f))
+    return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  const float inv_n = (float)(1.0 / (double)p->batch);
+  const unsigned gg = mlp_grid(p->batch, 256);
+  for (int64_t k = 0; k < p->steps; ++k) {
+    const int64_t t = c->adam_step + 1;
+    hipLaunchKernelGGL(gaps::k_mlp_grad, dim3(gg), dim3(256), 0, stream, c->wb, x, y, p->batch, n, p->seed, t, 1, p->tau,
+                       inv_n, c->grad, loss ? loss + k : (float*)nullptr);
+    const float bc1 = (float)(1.0 - pow((double)p->beta1, (double)t));
+    const float bc2 = (float)(1.0 - pow((double)p->beta2, (double)t));
+    hipLaunchKernelGGL(gaps::k_adam, dim3((kNP + 255) / 256), dim3(256), 0, stream, c->theta, c->wb, c->grad, c->mom1,
+                       c->mom2, kNP, p->lr, p->beta1, p->beta2, p->eps, bc1, bc2);
+    c->adam_step = t;
+  }
+  GAPS_HIP(hipGetLastError());
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_calibrate(gaps_ctx c, const float* x, const float* y, const int32_t* ent, int64_t n,
+                               hipStream_t stream) {
+  if (!c || n <= 0 || !x || !y || !ent) return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  float* f = nullptr;
+  if (hipMalloc((void**)&f, (size_t)n * 4) != hipSuccess) return GAPS_ENOMEM;
+  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->maxbits, (int64_t)64, 0ull);
+  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->count, (int64_t)64, 0ull);
+  hipLaunchKernelGGL(gaps::k_mlp_fwd, dim3(mlp_grid(n, 4096)), dim3(256), 0, stream, c->wb, x, n, f);
+  hipLaunchKernelGGL(gaps::k_mlp_resid, dim3(grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024), dim3(256), 0, stream,
+                     f, y, ent, n, c->maxbits, c->count);
+  hipLaunchKernelGGL(gaps::k_mlp_delta, dim3(1), dim3(64), 0, stream, c->maxbits, c->count, 2000ll, 0.015625,
+                     c->delta);
+  hipError_t e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(stream);
+  (void)hipFree(f);
+  if (e != hipSuccess || e2 != hipSuccess) return GAPS_EHIP;
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_set_delta(gaps_ctx c, const double* host_delta) {
+  if (!c || !host_delta) return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  GAPS_HIP(hipDeviceSynchronize());
+  GAPS_HIP(hipMemcpy(c->delta, host_delta, 64 * sizeof(double), hipMemcpyHostToDevice));
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_get_delta(gaps_ctx c, double* host_delta) {
+  if (!c || !host_delta) return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  GAPS_HIP(hipDeviceSynchronize());
+  GAPS_HIP(hipMemcpy(host_delta, c->delta, 64 * sizeof(double), hipMemcpyDeviceToHost));
+  return GAPS_OK;
+}
+
+gaps_status gaps_mlp_tabulate(gaps_ctx c, hipStream_t stream) {
+  if (!c) return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  const int64_t np = gaps::kMlpProbeRows;
+  if (!c->probe_x) {
+    if (hipMalloc((void**)&c->probe_x, (size_t)np * 16) != hipSuccess) return GAPS_ENOMEM;
+    if (hipMalloc((void**)&c->probe_f, (size_t)np * 4) != hipSuccess) return GAPS_ENOMEM;
+  }
+  hipLaunchKernelGGL(gaps::k_mlp_probes, dim3(grid_for(np, 256)), dim3(256), 0, stream, c->C, c->probe_x);
+  hipLaunchKernelGGL(gaps::k_mlp_fwd, dim3(mlp_grid(np, 4096)), dim3(256), 0, stream, c->wb, c->probe_x, np,
+                     c->probe_f);
+  hipLaunchKernelGGL(gaps::k_mlp_table, dim3(grid_for(GAPS_LEARN_CELLS, 256)), dim3(256), 0, stream, c->probe_f,
+                     c->delta, c->d_bound, c->table);
+  GAPS_HIP(hipGetLastError());
+  c->C.learn = c->table;
+  return GAPS_OK;
+}
+
+gaps_status gaps_learned_table(gaps_ctx c, double* host_out) {
+  if (!c || !host_out) return GAPS_EINVAL;
+  if (!c->C.learn) return GAPS_ESTATE;
+  GAPS_HIP(hipDeviceSynchronize());
+  GAPS_HIP(hipMemcpy(host_out, c->table, (size_t)GAPS_LEARN_CELLS * 8, hipMemcpyDeviceToHost));
+  return GAPS_OK;
+}
+
+gaps_status gaps_learned_set_table(gaps_ctx c, const double* host_table) {
+  if (!c || !host_table) return GAPS_EINVAL;
+  gaps_status s = mlp_alloc(c);
+  if (s != GAPS_OK) return s;
+  double* an = (double*)malloc(sizeof(double) * gaps::kNEnt * gaps::kNB);
+  if (!an) return GAPS_ENOMEM;
+  hipError_t e = hipMemcpy(an, c->d_bound, sizeof(double) * gaps::kNEnt * gaps::kNB, hipMemcpyDeviceToHost);
+  bool ok = e == hipSuccess;
+  for (int q = 0; ok && q < GAPS_LEARN_CELLS; ++q) {
+    const int ent = q / (gaps::kNB * gaps::kNTB) + gaps::kIS0, b = (q / gaps::kNTB) % gaps::kNB;
+    const double v = host_table[q];
+    ok = isfinite(v) && v >= 0.0 && v <= an[ent * gaps::kNB + b];
+  }
+  free(an);
+  if (e != hipSuccess) return GAPS_EHIP;
+  if (!ok) return GAPS_EINVAL;
+  GAPS_HIP(hipDeviceSynchronize());
+  GAPS_HIP(hipMemcpy(c->table, host_table, (size_t)GAPS_LEARN_CELLS * 8, hipMemcpyHostToDevice));
+  c->C.learn = c->table;
   return GAPS_OK;
 }
 

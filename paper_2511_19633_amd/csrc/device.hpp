@@ -24,6 +24,11 @@ __host__ __device__ constexpr int ent_fi(int T) { return T; }
 __host__ __device__ constexpr int ent_s1(int f, int T) { return 8 + 8 * f + T; }
 __host__ __device__ constexpr int ent_s3(int f, int T) { return 40 + 8 * f + T; }
 
+// learned bound: initial-state entries kIS0.. (kNIS of them), kNTB cells in ln t
+constexpr int kIS0 = 8;
+constexpr int kNIS = 64;
+constexpr int kNTB = 8;
+
 constexpr int kMaxSlots = 256;
 constexpr uint32_t kMaxCycles = 2000000u;
 
@@ -47,8 +52,10 @@ struct Cfg {
   double sw2, gf, mll_min, mll_max, p_s, over_scale;
   double lnx0, lnx1, lnq0, lnq1, dlnx, dlnq;
   double lo_wmax;
+  double cell_edge[kNTB + 1];  // ln t edges of the learned-bound cells
   const float* pdf;      // [8][nq][nx]
   const double* bound;   // [72][48]
+  const double* learn;   // [64][48][8] learned bound (LEARNED mode), or null
 };
 
 // ---------------------------------------------------------------------------
@@ -189,7 +196,7 @@ struct Chan {
 };
 
 struct Term {
-  int kern, shape, flav;
+  int kern, shape, flav, ent;  // ent: overestimate-table entry (-1: none)
   double coefR, I;
 };
 
@@ -249,7 +256,11 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
   Term t;
   if (is_fs(ch)) {
     double R = 1.0;
-    if (ch.type == kFI) R = C.bound[ent_fi(pdf_tab(ch.pidk)) * kNB + ch.kbin];
+    t.ent = -1;
+    if (ch.type == kFI) {
+      t.ent = ent_fi(pdf_tab(ch.pidk));
+      R = C.bound[t.ent * kNB + ch.kbin];
+    }
     if (ch.pidi == 21) {
       if (m == 0) { t.kern = kGGG; t.shape = kSoft; t.flav = 0; t.coefR = kCA * R; t.I = ch.I1; }
       else { t.kern = kGQQ; t.shape = kFlat; t.flav = m; t.coefR = 0.5 * kTR * R; t.I = ch.I2; }
@@ -262,24 +273,21 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
   const int sh2 = ii ? kS3 : kS1;
   if (ch.pidi == 21) {
     if (m == 0) {
-      t.kern = kC; t.shape = kS1; t.flav = 0; t.coefR = C.bound[ent_s1(famC, 0) * kNB + ch.ebin]; t.I = ch.I1;
+      t.kern = kC; t.shape = kS1; t.flav = 0; t.ent = ent_s1(famC, 0); t.I = ch.I1;
     } else {
       int a = m <= C.nf ? m : -(m - C.nf);
       int T = pdf_tab(a);
-      t.kern = kD; t.shape = sh2; t.flav = a;
-      t.coefR = ii ? C.bound[ent_s3(famD, T) * kNB + ch.ebin] : C.bound[ent_s1(famD, T) * kNB + ch.ebin];
-      t.I = ch.I2;
+      t.kern = kD; t.shape = sh2; t.flav = a; t.ent = ii ? ent_s3(famD, T) : ent_s1(famD, T); t.I = ch.I2;
     }
   } else {
     int T = pdf_tab(ch.pidi);
     if (m == 0) {
-      t.kern = kA; t.shape = kS1; t.flav = 0; t.coefR = C.bound[ent_s1(famA, T) * kNB + ch.ebin]; t.I = ch.I1;
+      t.kern = kA; t.shape = kS1; t.flav = 0; t.ent = ent_s1(famA, T); t.I = ch.I1;
     } else {
-      t.kern = kB; t.shape = sh2; t.flav = 0;
-      t.coefR = ii ? C.bound[ent_s3(famB, T) * kNB + ch.ebin] : C.bound[ent_s1(famB, T) * kNB + ch.ebin];
-      t.I = ch.I2;
+      t.kern = kB; t.shape = sh2; t.flav = 0; t.ent = ii ? ent_s3(famB, T) : ent_s1(famB, T); t.I = ch.I2;
     }
   }
+  t.coefR = C.bound[t.ent * kNB + ch.ebin];
   return t;
 }
 
@@ -374,6 +382,54 @@ __device__ inline Term select_term(const Cfg& C, const Chan& ch, double u) {
   return term_at(C, ch, 0);
 }
 
+// ---------------------------------------------------------------------------
+// Learned bound (LEARNED mode): an initial-state channel's overestimate
+// constant in cell k of ln t is the sum over its terms, in order, of
+// alpha_s(t_c)/(2 pi) * R_theta[entry][eta bin][k] * (z integral of the shape)
+// (computed for all cells at the channel build).
+__device__ __forceinline__ double learned_R(const Cfg& C, int ent, int ebin, int k) {
+  return C.learn[((ent - kIS0) * kNB + ebin) * kNTB + k];
+}
+
+// the cell of a scale: the largest k with edge[k] < ln t (0 if none), and its
+// lower edge (constant indices only, so the edges stay in registers)
+__device__ __forceinline__ int cell_of(const Cfg& C, double lnt, double& edge) {
+  int k = 0;
+  edge = C.cell_edge[0];
+#pragma unroll
+  for (int j = 1; j < kNTB; ++j) {
+    if (C.cell_edge[j] < lnt) {
+      k = j;
+      edge = C.cell_edge[j];
+    }
+  }
+  return k;
+}
+
+// select_term with the cell constants (ck: the channel's constant in cell k);
+// the chosen term carries its cell R
+__device__ inline Term select_term_cell(const Cfg& C, const Chan& ch, double u, int k, double ck) {
+  const double af = C.as_over / (2.0 * kPi) * C.over_scale;
+  const double target = u * ck;
+  double cum = 0.0;
+  for (int m = 0; m < ch.nterm; ++m) {
+    Term t = term_at(C, ch, m);
+    t.coefR = learned_R(C, t.ent, ch.ebin, k);
+    cum += af * t.coefR * t.I;
+    if (target < cum) return t;
+  }
+  for (int m = ch.nterm - 1; m >= 0; --m) {
+    Term t = term_at(C, ch, m);
+    if (af * t.coefR * t.I > 0.0) {
+      t.coefR = learned_R(C, t.ent, ch.ebin, k);
+      return t;
+    }
+  }
+  Term t = term_at(C, ch, 0);
+  t.coefR = learned_R(C, t.ent, ch.ebin, k);
+  return t;
+}
+
 // transverse momentum of size sqrt(tp) at azimuth phi, orthogonal to pa, pb
 __device__ inline void kperp(const double* pa, const double* pb, double tp, double phi, double* kt) {
   double pab = dot4(pa, pb);
@@ -423,6 +479,7 @@ __device__ __forceinline__ void ii_lambda(const double* Kp, const double* K, dou
 struct Veto {
   int ok;
   double x, omx, y, uv, w;
+  double wn;  // the weight before division by the table constant (trial log)
 };
 
 // IF and II: (z, t) -> (x, u or v); the IF root in a cancellation-free form
@@ -445,7 +502,7 @@ __device__ __forceinline__ void is_vars(int type, double z, double omz, double t
 __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, const Term& tm, double t,
                                    double z, double omz) {
   Veto r;
-  r.ok = 0; r.x = 0.0; r.omx = 0.0; r.y = 0.0; r.uv = 0.0; r.w = 0.0;
+  r.ok = 0; r.x = 0.0; r.omx = 0.0; r.y = 0.0; r.uv = 0.0; r.w = 0.0; r.wn = 0.0;
   const double s = ch.s;
   const int kern = tm.kern, type = ch.type;
   const bool fs = type == kFF || type == kFI;
@@ -513,7 +570,9 @@ __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, c
   else W = J * P * pr * (ch.heavy ? (t - ch.m2) / t : 1.0);
   r.x = x; r.omx = omx; r.y = y; r.uv = uv;
   const double over = C.over_scale * tm.coefR * shape_val(tm.shape, z, omz);
-  r.w = alphas(C, t) / C.as_over * W / over;
+  const double ar = alphas(C, t) / C.as_over;
+  r.w = ar * W / over;
+  r.wn = ar * W / shape_val(tm.shape, z, omz);
   r.ok = 1;
   return r;
 }

@@ -18,6 +18,8 @@ struct Scratch {
   uint32_t* cinfo;
   double *ctlim, *clntlim, *cinvc;
   double *cc, *cs, *czlo, *comzhi, *cI1, *cI2;
+  double* cinvk;              // learned mode: [kNTB][4][lanes] 1/c per ln t cell, entries 0..3
+  double* cck;                // learned mode: [kNTB][4][lanes] c per ln t cell
   unsigned long long* queue;  // work-queue counters
 };
 
@@ -65,6 +67,25 @@ struct BatchChunk {
 };
 __global__ void k_store_batches(BatchChunk ch, gaps_batch* table, int64_t* prefix, int nbatch);
 __global__ void k_observables(Cfg C, gaps_events ev, int64_t n, double* obs);
+
+// learned bound network (4 -> 64 -> 64 -> 1)
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = 4545;
+constexpr int64_t kMlpProbeRows = (int64_t)kNIS * kNB * kNTB * 48;
+__global__ void k_mlp_fwd(const uint16_t* wb, const float* x, int64_t n, float* f);
+__global__ void k_mlp_grad(const uint16_t* wb, const float* x, const float* y, int64_t nrows, int64_t nsrc,
+                           uint64_t seed, int64_t step, int sample, float tau, float inv_n, float* grad, float* loss);
+__global__ void k_adam(float* theta, uint16_t* wb, float* grad, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2);
+__global__ void k_mlp_pack(const float* theta, uint16_t* wb, int n);
+__global__ void k_mlp_init(uint64_t seed, float* theta, int n);
+__global__ void k_mlp_features(const float* rows, int64_t n, const double* bound, float* x, float* y, int32_t* ent);
+__global__ void k_mlp_resid(const float* f, const float* y, const int32_t* ent, int64_t n,
+                            unsigned long long* maxbits, unsigned long long* count);
+__global__ void k_mlp_delta(const unsigned long long* maxbits, const unsigned long long* count, long long min_count,
+                            double margin, double* delta);
+__global__ void k_mlp_probes(Cfg C, float* x);
+__global__ void k_mlp_table(const float* f, const double* delta, const double* bound, double* table);
 __global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
                             int nbins, double* sumw, double* sumw2);
 

@@ -24,10 +24,12 @@ namespace gaps {
 
 namespace {
 
-// cache word: alive | type<<1 | heavy<<3 | spectator<<5 | eta bin<<13 | spectator eta bin<<19
+// cache word: alive | type<<1 | heavy<<3 | spectator<<5 | eta bin<<13 | spectator eta bin<<19 |
+// learned cell<<25 (the cell whose 1/c the trial entry holds; 15: none yet)
+constexpr uint32_t kCellShift = 25u, kCellMask = 15u << kCellShift, kCellNone = 15u;
 __device__ __forceinline__ uint32_t pack(const Chan& ch) {
   return (uint32_t)ch.alive | ((uint32_t)ch.type << 1) | ((uint32_t)ch.heavy << 3) | ((uint32_t)ch.k << 5) |
-         ((uint32_t)ch.ebin << 13) | ((uint32_t)ch.kbin << 19);
+         ((uint32_t)ch.ebin << 13) | ((uint32_t)ch.kbin << 19) | (kCellNone << kCellShift);
 }
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
@@ -42,10 +44,10 @@ struct WaveCtx {
 // register state of one in-flight event (what moves when the tail compacts)
 struct LaneState {
   int64_t e, id, slot;
-  int32_t b, pad;
+  int32_t b, lrn;
   double T, lnT, t1;
   uint32_t cycle, ntri, nacc, nviol, flags;
-  int32_t n, maxtag, loaded, stop;
+  int32_t n, maxtag, loaded, stop, pending;
 };
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
@@ -59,7 +61,7 @@ __device__ __forceinline__ Rec rec_of(const Scratch& S, int64_t slot) {
 // is found with register reads instead of a search through memory; then lane
 // c sets up entry c = 2 * slot + side.  Returns (per lane) whether this
 // lane's own event hit a broken colour line or a non-finite momentum.
-__device__ uint32_t coop_build(const WaveCtx& W, unsigned long long mask, int n, int64_t myslot) {
+__device__ uint32_t coop_build(const WaveCtx& W, unsigned long long mask, int n, int64_t myslot, bool mylrn) {
   uint32_t myflags = 0u;
   __threadfence_block();
   while (mask) {
@@ -67,6 +69,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, unsigned long long mask, int n,
     mask &= mask - 1ull;
     const int nL = __shfl(n, L);
     const int64_t slot = __shfl(myslot, L);
+    const bool lrnL = __shfl((int)mylrn, L) != 0;
     const Rec R = rec_of(W.S, slot);
     // colours of particles lane and lane + 64 in registers
     int ec0 = 0, ea0 = 0, ec1 = 0, ea1 = 0;
@@ -120,6 +123,27 @@ __device__ uint32_t coop_build(const WaveCtx& W, unsigned long long mask, int n,
       W.S.comzhi[oc] = ch.omzhi;
       W.S.cI1[oc] = ch.I1;
       W.S.cI2[oc] = ch.I2;
+      if (lrnL && c < 4 && ch.alive && (ch.type == kIF || ch.type == kII)) {
+        // learned mode: the constant of every ln t cell of this channel, in one
+        // pass over the terms (a term's eight cell values share a cache line);
+        // per cell the sum runs over the terms in order, as learned_c does
+        const double af = W.C.as_over / (2.0 * kPi) * W.C.over_scale;
+        double ck[kNTB];
+#pragma unroll
+        for (int k = 0; k < kNTB; ++k) ck[k] = 0.0;
+        for (int m = 0; m < ch.nterm; ++m) {
+          const Term t = term_at(W.C, ch, m);
+          const double* Rp = W.C.learn + ((t.ent - kIS0) * kNB + ch.ebin) * kNTB;
+#pragma unroll
+          for (int k = 0; k < kNTB; ++k) ck[k] += af * Rp[k] * t.I;
+        }
+#pragma unroll
+        for (int k = 0; k < kNTB; ++k) {
+          const int64_t ok = ((int64_t)k * 4 + c) * W.S.lanes + slot;
+          W.S.cinvk[ok] = 1.0 / ck[k];
+          W.S.cck[ok] = ck[k];
+        }
+      }
     }
     const bool anymiss = __ballot(missing) != 0ull;
     const bool anybad = __ballot(bad) != 0ull;
@@ -191,17 +215,52 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   const int K = A.compact_every > 0 ? A.compact_every : 4;
   const unsigned KC = A.tail_every > 0 ? (unsigned)A.tail_every : 16u;
   const bool compact = A.tail_every > 0;
+  const bool learned_mode = A.mode == GAPS_MODE_LEARNED;
+  const bool log_mode = A.mode == GAPS_MODE_LOG;
 
   bool active = false, exhausted = false, loaded = false, stop = false;
+  bool lrn = false;      // this event draws against the learned bound (stream 1)
+  bool pending = false;  // reload event (b, e) in plain mode: its learned bound failed
   int64_t e = 0, id = 0;
   int b = 0;
   double T = 0.0, lnT = 0.0, t1 = 0.0;
   uint32_t cycle = 0, ntri = 0, nacc = 0, nviol = 0, flags = 0;
   int n = 0, maxtag = 0;
   unsigned long long st_cyc = 0, st_tri = 0, st_acc = 0, st_viol = 0, st_iters = 0, st_active = 0;
+  unsigned long long st_fb = 0, st_null = 0;
   int since = 1 << 30;
   bool counted = false, tail = false;
   unsigned it_tail = 0;
+
+  // load event e of batch b into this lane's record; false if it does not fit
+  auto load = [&](bool learned) -> bool {
+    const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
+    n = in.n[e];
+    id = in.id[e];
+    flags = in.flags ? in.flags[e] : 0u;
+    T = in.t_start[e];
+    lnT = log(T);
+    t1 = 0.0;
+    cycle = ntri = nacc = nviol = 0u;
+    maxtag = 0;
+    stop = false;
+    lrn = learned;
+    if (n < 0 || n > M || n > in.max_slots) {
+      flags |= fOverflow;
+      stop = true;
+      loaded = false;
+      return false;
+    }
+    loaded = true;
+    for (int q = 0; q < n; ++q) {
+      const int64_t k = (int64_t)q * in.cap + e, o = R.o(q);
+      R.E[o] = in.E[k]; R.px[o] = in.px[k]; R.py[o] = in.py[k]; R.pz[o] = in.pz[k];
+      R.pid[o] = in.pid[k]; R.col[o] = in.col[k]; R.acol[o] = in.acol[k]; R.st[o] = in.status[k];
+      maxtag = in.col[k] > maxtag ? in.col[k] : maxtag;
+      maxtag = in.acol[k] > maxtag ? in.acol[k] : maxtag;
+    }
+    return true;
+  };
 
   for (unsigned it = 0;; ++it) {
     // ---- tail mode starts when every wave of the block has seen the queue empty
@@ -215,7 +274,9 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     }
     // ---- tail mode: block bookkeeping, termination and compaction
     if (tail && (it - it_tail) % KC == 0u) {
-      const unsigned long long a0 = __ballot(active);
+      // live lanes: showering, or waiting to reload their event in plain mode
+      const bool live = active || pending;
+      const unsigned long long a0 = __ballot(live);
       if (lane == 0) s_cnt[wid] = __popcll(a0);
       __syncthreads();
       int total = 0, used = 0, prefix = 0;
@@ -227,73 +288,63 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       }
       if (total == 0) break;
       if ((total + 63) / 64 < used) {
-        if (active) {
+        if (live) {
           LaneState& X = s_pool[prefix + __popcll(a0 & lanemask_lt(lane))];
-          X.e = e; X.id = id; X.slot = slot; X.b = b; X.T = T; X.lnT = lnT; X.t1 = t1;
+          X.e = e; X.id = id; X.slot = slot; X.b = b; X.lrn = lrn; X.T = T; X.lnT = lnT; X.t1 = t1;
           X.cycle = cycle; X.ntri = ntri; X.nacc = nacc; X.nviol = nviol; X.flags = flags;
-          X.n = n; X.maxtag = maxtag; X.loaded = loaded; X.stop = stop;
+          X.n = n; X.maxtag = maxtag; X.loaded = loaded; X.stop = stop; X.pending = pending;
         }
         __syncthreads();
-        active = (int)threadIdx.x < total;
-        if (active) {
+        const bool got = (int)threadIdx.x < total;
+        active = false;
+        pending = false;
+        if (got) {
           const LaneState& X = s_pool[threadIdx.x];
-          e = X.e; id = X.id; slot = X.slot; b = X.b; T = X.T; lnT = X.lnT; t1 = X.t1;
+          e = X.e; id = X.id; slot = X.slot; b = X.b; lrn = X.lrn != 0; T = X.T; lnT = X.lnT; t1 = X.t1;
           cycle = X.cycle; ntri = X.ntri; nacc = X.nacc; nviol = X.nviol; flags = X.flags;
           n = X.n; maxtag = X.maxtag; loaded = X.loaded != 0; stop = X.stop != 0;
+          pending = X.pending != 0;
+          active = !pending;
           R = rec_of(S, slot);
         }
       }
       __syncthreads();
     }
-    // ---- refill finished lanes from the work queue (one atomic per wave)
+    // ---- refill finished lanes from the work queue (one atomic per wave);
+    // lanes whose learned bound failed reload their own event in plain mode
     unsigned long long act = __ballot(active);
-    if (!exhausted && (since >= K || act == 0ull)) {
-      unsigned long long idle = ~act;
-      const int cnt = __popcll(idle);
-      unsigned long long base = 0ull;
-      if (lane == 0) base = atomicAdd(S.queue, (unsigned long long)cnt);
-      base = __shfl(base, 0);
-      if (base + (unsigned long long)cnt >= (unsigned long long)A.n) exhausted = true;
+    const unsigned long long pend = __ballot(pending);
+    if (pend || (!exhausted && (since >= K || act == 0ull))) {
       bool fresh = false;
-      if (!active) {
-        const unsigned long long ev = base + (unsigned long long)__popcll(idle & lanemask_lt(lane));
-        if (ev < (unsigned long long)A.n) {
-          b = A.nbatch > 0 ? batch_of(A, (int64_t)ev) : 0;
-          e = (int64_t)ev - (A.nbatch > 0 ? A.prefix[b] : 0);
-          const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
-          n = in.n[e];
-          id = in.id[e];
-          flags = in.flags ? in.flags[e] : 0u;
-          T = in.t_start[e];
-          lnT = log(T);
-          t1 = 0.0;
-          cycle = ntri = nacc = nviol = 0u;
-          maxtag = 0;
-          active = true;
-          loaded = false;
-          stop = false;
-          if (n < 0 || n > M || n > in.max_slots) {
-            flags |= fOverflow;
-            stop = true;
-          } else {
-            loaded = true;
-            for (int q = 0; q < n; ++q) {
-              const int64_t k = (int64_t)q * in.cap + e, o = R.o(q);
-              R.E[o] = in.E[k]; R.px[o] = in.px[k]; R.py[o] = in.py[k]; R.pz[o] = in.pz[k];
-              R.pid[o] = in.pid[k]; R.col[o] = in.col[k]; R.acol[o] = in.acol[k]; R.st[o] = in.status[k];
-              maxtag = in.col[k] > maxtag ? in.col[k] : maxtag;
-              maxtag = in.acol[k] > maxtag ? in.acol[k] : maxtag;
-            }
-            fresh = true;
+      if (pending) {
+        pending = false;
+        active = true;
+        fresh = load(false);
+        flags |= fFallback;
+      }
+      if (!exhausted && (since >= K || act == 0ull)) {
+        const unsigned long long idle = ~(act | pend);
+        const int cnt = __popcll(idle);
+        unsigned long long base = 0ull;
+        if (lane == 0) base = atomicAdd(S.queue, (unsigned long long)cnt);
+        base = __shfl(base, 0);
+        if (base + (unsigned long long)cnt >= (unsigned long long)A.n) exhausted = true;
+        if (!active) {
+          const unsigned long long ev = base + (unsigned long long)__popcll(idle & lanemask_lt(lane));
+          if (ev < (unsigned long long)A.n) {
+            b = A.nbatch > 0 ? batch_of(A, (int64_t)ev) : 0;
+            e = (int64_t)ev - (A.nbatch > 0 ? A.prefix[b] : 0);
+            active = true;
+            fresh = load(learned_mode);
           }
         }
+        since = 0;
       }
       {
         // a broken colour line stops the event before its first cycle
-        const uint32_t f = coop_build(W, __ballot(fresh), n, slot) & fColour;
+        const uint32_t f = coop_build(W, __ballot(fresh), n, slot, lrn) & fColour;
         if (fresh && f) { flags |= f; stop = true; }
       }
-      since = 0;
       act = __ballot(active);
     }
     if (act == 0ull) {
@@ -313,10 +364,14 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       // ties to the lowest entry).  Each key is first bounded with the
       // hardware single-precision log of u and a rigorous error margin; the
       // double-precision log is taken only where the bounds cannot decide
-      // (overlapping candidates, the cutoff) and for the final winner, so the
-      // result is exactly that of evaluating every key in double precision.
-      int win = -1;
-      bool wexact = false;
+      // (overlapping candidates, the cutoff, a cell edge) and for the final
+      // winner, so the result is exactly that of evaluating every key in
+      // double precision.  In learned mode an initial-state channel of the
+      // incoming partons draws against its cell constant, and a trial below
+      // the cell is a null candidate at the cell's lower edge.
+      const uint32_t strm = lrn ? 1u : 0u;
+      int win = -1, wcell = 0;
+      bool wexact = false, wnull = false;
       double wlo = 0.0, whi = 0.0, wkey = 0.0, wu = 0.5, wlnT = 0.0, winv = 0.0;
       for (int c0 = 0; c0 < 2 * n; c0 += 4) {
         uint32_t inf[4];
@@ -331,7 +386,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         }
         if (!((inf[0] | inf[1] | inf[2] | inf[3]) & 1u)) continue;
         double ub[4];
-        rng4(A.seed, A.stream, id, cycle, (uint32_t)c0 >> 2, ub);
+        rng4(A.seed, strm, id, cycle, (uint32_t)c0 >> 2, ub);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int c = c0 + j;
@@ -347,11 +402,25 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           const double lnTch = lnT < ltl[j] ? lnT : ltl[j];
           if (!(Tch > tcut)) continue;
           ntri += 1;
-          const double u = ub[j], invc = ic[j];
+          const double u = ub[j];
+          double invc = ic[j], floor = -INFINITY;
+          int cell = 0;
+          if (lrn && c < 4 && (type == kIF || type == kII)) {
+            cell = cell_of(C, lnTch, floor);
+            if ((int)((info & kCellMask) >> kCellShift) != cell) {
+              // the scale entered a new cell: its constant replaces the entry's
+              invc = S.cinvk[((int64_t)cell * 4 + c) * S.lanes + slot];
+              const int64_t oc = (int64_t)c * S.lanes + slot;
+              S.cinvc[oc] = invc;
+              S.cinfo[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+            }
+            if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
+          }
           double lo, hi, key = 0.0;
-          bool exact;
+          bool exact, isnull = false;
           if (heavy) {
             key = log(m2 + (Tch - m2) * exp(log(u) * invc));
+            if (key < floor) { key = floor; isnull = true; }
             if (key < lntcut) continue;
             lo = hi = key;
             exact = true;
@@ -361,8 +430,16 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             const double err = invc * (fabs(lf) * 0x1p-17 + 0x1p-19) + 1e-12;
             lo = ka - err;
             hi = ka + err;
-            if (hi < lntcut) continue;
             exact = false;
+            if (hi < floor) {
+              key = floor; lo = hi = key; exact = true; isnull = true;
+            } else if (lo < floor) {
+              key = lnTch + log(u) * invc;
+              if (key < floor) { key = floor; isnull = true; }
+              lo = hi = key;
+              exact = true;
+            }
+            if (hi < lntcut) continue;
             if (lo < lntcut) {
               key = lnTch + log(u) * invc;
               if (key < lntcut) continue;
@@ -372,57 +449,91 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           }
           if (win < 0) {
             win = c; wlo = lo; whi = hi; wkey = key; wexact = exact; wu = u; wlnT = lnTch; winv = invc;
+            wnull = isnull; wcell = cell;
             continue;
           }
           if (hi <= wlo) continue;
           if (!(lo > whi)) {
-            // the bounds overlap: decide with exact keys
+            // the bounds overlap: decide with exact keys (a null key is exact)
             if (!wexact) { wkey = wlnT + log(wu) * winv; wlo = whi = wkey; wexact = true; }
             if (!exact) { key = lnTch + log(u) * invc; lo = hi = key; exact = true; }
             if (!(key > wkey)) continue;
           }
           win = c; wlo = lo; whi = hi; wkey = key; wexact = exact; wu = u; wlnT = lnTch; winv = invc;
+          wnull = isnull; wcell = cell;
         }
       }
       double best = -INFINITY;
       if (win >= 0) best = wexact ? wkey : wlnT + log(wu) * winv;
       if (win < 0) {
         done = true;
+      } else if (wnull) {
+        // no channel emits above the cell edge: continue the evolution from it
+        T = exp(best);
+        lnT = best;
+        cycle += 1;
+        st_null += 1;
       } else {
         const double t = exp(best);
         Chan ch;
         chan_from_cache(C, S, R, slot, win, ch);
+        const bool lch = lrn && win < 4 && (ch.type == kIF || ch.type == kII);
         double u[4];
-        rng4(A.seed, A.stream, id, cycle, 0xFFFFFFFFu, u);
-        const Term tm = select_term(C, ch, u[0]);
+        rng4(A.seed, strm, id, cycle, 0xFFFFFFFFu, u);
+        const Term tm = lch ? select_term_cell(C, ch, u[0], wcell, S.cck[((int64_t)wcell * 4 + win) * S.lanes + slot])
+                            : select_term(C, ch, u[0]);
         double z, omz;
         shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
         const double phi = 2.0 * kPi * u[2];
         const Veto v = veto_weight(C, R, ch, tm, t, z, omz);
-        if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
-        if (v.ok && u[3] < v.w) {
-          if (n + 1 > M) {
-            flags |= fOverflow;
-            done = true;
-          } else {
-            emit(R, n, maxtag, ch, tm, z, omz, v, phi);
-            n += 1;
-            nacc += 1;
-            if (t1 == 0.0) t1 = t;
-            accepted = true;
+        if (log_mode) {
+          // trial log: one atomic for the lanes of this branch that log
+          const bool dolog = (ch.type == kIF || ch.type == kII) && v.ok && v.wn > 0.0;
+          const unsigned long long lm = __ballot(dolog);
+          if (lm) {
+            const int leader = __ffsll((long long)lm) - 1;
+            unsigned long long base = 0ull;
+            if (lane == leader) base = atomicAdd(A.log_count, (unsigned long long)__popcll(lm));
+            base = __shfl(base, leader);
+            const unsigned long long r = base + (unsigned long long)__popcll(lm & lanemask_lt(lane));
+            if (dolog && r < (unsigned long long)A.log_cap) {
+              float* row = A.log + 5ull * r;
+              row[0] = (float)log(t); row[1] = (float)log(ch.eta); row[2] = (float)z;
+              row[3] = (float)tm.ent; row[4] = (float)log(v.wn);
+            }
           }
         }
-        if (!done) {
-          T = t;
-          lnT = best;
-          cycle += 1;
+        if (lch && v.ok && v.w > 1.0) {
+          // the learned bound failed: shower this event again in plain mode
+          pending = true;
+          active = false;
+          st_fb += 1;
+        } else {
+          if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
+          if (v.ok && u[3] < v.w) {
+            if (n + 1 > M) {
+              flags |= fOverflow;
+              done = true;
+            } else {
+              emit(R, n, maxtag, ch, tm, z, omz, v, phi);
+              n += 1;
+              nacc += 1;
+              if (t1 == 0.0) t1 = t;
+              accepted = true;
+            }
+          }
+          if (!done) {
+            T = t;
+            lnT = best;
+            cycle += 1;
+          }
         }
       }
     }
     // ---- cooperative channel rebuild for the lanes that emitted
     const unsigned long long emitted = __ballot(accepted);
     if (emitted) {
-      uint32_t f = coop_build(W, emitted, n, slot);
+      uint32_t f = coop_build(W, emitted, n, slot, lrn);
       if (f & fNaN) f = fNaN;  // a non-finite momentum is reported before the colour check
       if (accepted && f) { flags |= f; done = true; }
     }
@@ -468,6 +579,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     atomicAdd(A.stats + 1, st_tri);
     atomicAdd(A.stats + 2, st_acc);
     atomicAdd(A.stats + 3, st_viol);
+    atomicAdd(A.stats + 6, st_fb);
+    atomicAdd(A.stats + 7, st_null);
     if (lane == 0) {
       atomicAdd(A.stats + 4, st_iters);
       atomicAdd(A.stats + 5, st_active);

@@ -1,0 +1,221 @@
+"""Pins of the oracle's learned initial-state bound: the network arithmetic
+(closed forms, finite differences, the first Adam step), the tabulation rules,
+and the learned shower (exact first-emission distribution with null trials,
+forced fallback identical to the plain shower, histograms against plain)."""
+import math
+
+import numpy as np
+import pytest
+
+from gapsinputs import records, toypdf, workloads
+from oracle import mlp
+from tests.test_oracle_sudakov import PDF, _ii_channel, compare, delta_curve, replicate
+
+
+def test_bf16_rounding():
+    v = np.array([1.0, 3.14159265, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 0.0, 1e-30], dtype=np.float32)
+    r = mlp.bf16(v)
+    # 8 significant bits, nearest, ties to even
+    assert r[0] == 1.0 and r[1] == np.float32(3.140625) and r[2] == 1.0 and r[3] == np.float32(1.0 + 2 ** -6)
+    assert r[4] == -2.5 and r[5] == 0.0
+    assert abs(r[6] - 1e-30) / 1e-30 < 2 ** -8
+
+
+def _identity_net():
+    th = np.zeros(mlp.NPARAM, dtype=np.float32)
+    W1 = th[mlp.OFF_W1:mlp.OFF_B1].reshape(64, 4)
+    W2 = th[mlp.OFF_W2:mlp.OFF_B2].reshape(64, 64)
+    for c in range(4):
+        W1[c, c] = 1.0
+        W2[c, c] = 1.0
+    th[mlp.OFF_W3:mlp.OFF_W3 + 4] = 1.0
+    th[mlp.OFF_B3] = 0.25
+    return th
+
+
+def test_forward_closed_form():
+    """A network that routes each input through one ReLU unit per layer sums
+    the positive parts: f = sum_c max(x_c, 0) + b3."""
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(257, 4)).astype(np.float32)
+    th = _identity_net()
+    f = mlp.forward(th, x, dtype=np.float64, round_bf16=False)
+    assert np.allclose(f, np.maximum(x, 0).astype(np.float64).sum(axis=1) + 0.25, rtol=0, atol=1e-12)
+    fb = mlp.forward(th, x)  # bf16 first layer: the positive parts rounded to 8 bits
+    ref = mlp.bf16(np.maximum(x, 0)).astype(np.float64).sum(axis=1) + 0.25
+    assert np.allclose(fb, ref, rtol=1e-6, atol=1e-6)
+
+
+def test_gradient_finite_differences():
+    rng = np.random.default_rng(5)
+    th = mlp.init_params(11).astype(np.float64)
+    th[mlp.OFF_B1:mlp.OFF_W2] = 0.1
+    th[mlp.OFF_B2:mlp.OFF_W3] = 0.1
+    x = rng.normal(size=(64, 4))
+    y = rng.normal(size=64)
+    tau = 0.9
+
+    def loss(t):
+        W1, b1, W2, b2, W3, b3 = mlp.unpack(t)
+        h1 = np.maximum(x @ W1.T + b1, 0)
+        h2 = np.maximum(h1 @ W2.T + b2, 0)
+        r = y - (h2 @ W3 + b3)
+        return np.mean(np.where(r >= 0, tau * r, (tau - 1) * r))
+
+    # the oracle's analytic gradient at FP64 parameters (no rounding)
+    W1, b1, W2, b2, W3, b3 = [np.asarray(a, dtype=np.float64) for a in mlp.unpack(th)]
+    _, g = mlp.loss_grad(th.astype(np.float32), x, y, tau, round_bf16=False)
+    # recompute at the float32 parameters the gradient used
+    th32 = th.astype(np.float32).astype(np.float64)
+    idx = np.concatenate([rng.choice(np.arange(mlp.OFF_W1, mlp.OFF_B1), 10),
+                          rng.choice(np.arange(mlp.OFF_B1, mlp.OFF_W2), 5),
+                          rng.choice(np.arange(mlp.OFF_W2, mlp.OFF_B2), 15),
+                          rng.choice(np.arange(mlp.OFF_B2, mlp.OFF_W3), 5),
+                          rng.choice(np.arange(mlp.OFF_W3, mlp.OFF_B3), 5), [mlp.OFF_B3]])
+    h = 1e-6
+    for p in idx:
+        tp, tm = th32.copy(), th32.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (loss(tp) - loss(tm)) / (2 * h)
+        assert abs(fd - g[p]) <= 1e-6 + 1e-5 * abs(fd), (p, fd, g[p])
+
+
+def test_adam_first_step_closed_form():
+    """Bias correction makes the first Adam step lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(1)
+    th, g = rng.normal(size=50), rng.normal(size=50)
+    t1, m, v = mlp.adam_step(th, np.zeros(50), np.zeros(50), g, 1, 0.01)
+    assert np.allclose(t1, th - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_init_distribution():
+    th = mlp.init_params(2)
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(th)
+    assert not b1.any() and not b2.any() and b3 == 0.0
+    for W, fan in ((W1, 4), (W2, 64), (W3, 64)):
+        lim = math.sqrt(6.0 / fan)
+        assert np.all(np.abs(W) <= lim)
+        assert abs(W.mean()) < 0.1 * lim
+        assert abs(W.var() - lim * lim / 3) < 0.15 * lim * lim / 3
+    assert np.array_equal(th, mlp.init_params(2)) and not np.array_equal(th, mlp.init_params(3))
+
+
+def test_up6_and_tabulation(oracles):
+    v = np.array([1.0, 0.3, 1.7, 1e-5, 123.456])
+    u = mlp.up6(v)
+    assert np.all(u >= v) and np.all(u <= v * (1 + 2.0 ** -6))
+    m, _ = np.frexp(u)
+    assert np.all(m * 128 == np.round(m * 128))
+    assert np.array_equal(mlp.up6(u), u)
+    o = oracles["nlo"]
+    B = o.bounds()
+    R = B[8:72]
+    fm = np.zeros((64, 48, 8), dtype=np.float32)
+    # no margins: the analytic table in every cell
+    t0 = mlp.tabulate(None, np.full(64, np.inf), B, o.cell_edges(), fmax=fm)
+    assert np.array_equal(t0, np.broadcast_to(R[:, :, None], t0.shape))
+    # v = delta + max f, clipped to [-20, 0], applied as R e^v rounded up
+    d = np.full(64, -1.0)
+    d[5] = 3.0
+    fm[:, :, 2] = -30.0
+    t1 = mlp.tabulate(None, d, B, o.cell_edges(), fmax=fm)
+    for e in (0, 9, 17, 45):
+        assert np.array_equal(t1[e, :, 0], np.minimum(R[e], mlp.up6(R[e] * math.exp(-1.0))))
+        assert np.array_equal(t1[e, :, 2], np.minimum(R[e], mlp.up6(R[e] * math.exp(-20.0))))
+    assert np.array_equal(t1[5, :, 0], R[5])  # v clipped at 0: the analytic constant
+    assert np.array_equal(t1[5, :, 2], np.minimum(R[5], mlp.up6(R[5] * math.exp(-20.0))))
+    assert np.all(t1 <= R[:, :, None])
+
+
+def _plain_fields_equal(a, b, mask):
+    for name in a.fields():
+        x, y = getattr(a, name), getattr(b, name)
+        if name == "flags":
+            x, y = x & ~np.uint32(records.FLAG_FALLBACK), y & ~np.uint32(records.FLAG_FALLBACK)
+        if x.ndim == 1:
+            assert np.array_equal(x[mask], y[mask]), name
+        else:
+            assert np.array_equal(x[:, mask], y[:, mask]), name
+
+
+def test_forced_fallback_equals_plain(oracles):
+    """A bound 16 times below the analytic one fails on most events' first
+    initial-state winners: each such event is showered again in plain mode and
+    equals the plain result.  (A bound far lower still would hardly ever be
+    tested: its channels almost never propose an emission, which is why the
+    learned bound is calibrated on held-out trials.)"""
+    o = oracles["nlo"]
+    B = o.bounds()
+    tab = np.ascontiguousarray(np.broadcast_to(B[8:72, :, None] * 2.0 ** -4, (64, 48, 8)))
+    ev = o.hard_events(0, 400, 4)
+    p = o.shower(ev, 9)
+    l = o.shower_learned(ev, 9, tab)
+    fb = (l.flags & records.FLAG_FALLBACK) != 0
+    assert fb.mean() > 0.5
+    _plain_fields_equal(p, l, fb)
+
+
+@pytest.mark.slow
+def test_learned_first_emission_with_null_trials(oracles, cfgs):
+    """With the analytic constants in every cell, learned mode draws each
+    initial-state channel cell by cell (a null at every cell edge it crosses);
+    the first-emission distribution still equals the Sudakov quadrature."""
+    o, pdf = oracles["lo"], PDF(cfgs["lo"]["pdf"])
+    B = o.bounds()
+    tab = np.ascontiguousarray(np.broadcast_to(B[8:72, :, None], (64, 48, 8)))
+    base = o.hard_events(0, 64, 3)
+    k = next(e for e in range(64) if abs(base.pid[0, e]) == 2)
+    n = 20000
+    ev = replicate(base, k, n)
+    out = o.shower_learned(ev, 5, tab, nthreads=8)
+    assert not np.any(out.flags & records.FLAG_FALLBACK)
+    plain = o.shower(ev, 5, nthreads=8)
+    assert out.n_cycles.mean() > plain.n_cycles.mean()  # the null winners
+    S = 13000.0 ** 2
+    ea, eb = 2 * base.E[0, k] / 13000.0, 2 * base.E[1, k] / 13000.0
+    s = ea * eb * S
+    chans = [_ii_channel(pdf, s, ea, toypdf.TABLE_NAMES.index("u" if base.pid[0, k] == 2 else "ubar")),
+             _ii_channel(pdf, s, eb, toypdf.TABLE_NAMES.index("u" if base.pid[1, k] == 2 else "ubar"))]
+    tgrid = np.array([1.7, 3.0, 10.0, 30.0, 100.0, 1000.0, 1e4, 1e5])
+    compare(out.t1, tgrid, delta_curve(chans, 1.69, tgrid))
+
+
+@pytest.fixture(scope="module")
+def trained(oracles):
+    """A bound trained by the oracle's own reference loop on oracle trial logs."""
+    o = oracles["nlo"]
+    B = o.bounds()
+    _, rows, _ = o.shower_log(o.hard_events(1_000_000, 12000, 1), 1, 3_000_000, nthreads=8)
+    x, y, ent = mlp.features(rows, B)
+    ntr = int(0.8 * len(x))
+    th = mlp.train(mlp.init_params(7), x[:ntr], y[:ntr], steps=250, batch=4096, lr=3e-3, tau=0.999)
+    delta, _ = mlp.calibrate(th, x[ntr:], y[ntr:], ent[ntr:])
+    return th, delta, mlp.tabulate(th, delta, B, o.cell_edges())
+
+
+@pytest.mark.slow
+def test_learned_histograms_match_plain(oracles, trained):
+    """Learned and plain showers of the same NLO inputs agree in distribution
+    (Z pT, number of partons), with fewer cycles and rare fallbacks."""
+    o = oracles["nlo"]
+    _, _, tab = trained
+    n = 20000
+    ev = o.hard_events(0, n, 1)
+    p = o.shower(ev, 3, nthreads=8)
+    l = o.shower_learned(ev, 3, tab, nthreads=8)
+    fb = (l.flags & records.FLAG_FALLBACK) != 0
+    assert fb.mean() < 0.02
+    assert l.n_cycles[~fb].mean() < 0.8 * p.n_cycles.mean()
+    assert l.n_trials[~fb].mean() < p.n_trials.mean()
+    op, ol = o.observables(p), o.observables(l)
+    chi = []
+    for col, lo, hi in ((0, 0.0, 60.0), (9, 3.5, 30.5)):
+        hp, _ = np.histogram(op[:, col], bins=27, range=(lo, hi), weights=ev.w)
+        hp2, _ = np.histogram(op[:, col], bins=27, range=(lo, hi), weights=ev.w ** 2)
+        hl, _ = np.histogram(ol[:, col], bins=27, range=(lo, hi), weights=ev.w)
+        hl2, _ = np.histogram(ol[:, col], bins=27, range=(lo, hi), weights=ev.w ** 2)
+        m = (hp2 + hl2) > 0
+        chi.append(np.sum((hp[m] - hl[m]) ** 2 / (hp2[m] + hl2[m])) / m.sum())
+    assert max(chi) < 1.5, chi
