@@ -8,6 +8,12 @@ lanes refill across batch boundaries; --launch per-step launches gaps_shower
 once per batch instead.  Hard-event generation and observables are timed
 separately, as the paper's component table does, and are not part of `value`.
 
+With --mode learned (default) the learned initial-state bound is first
+trained on the GPU (trial log of the plain shower on separate event ids,
+training, calibration, tabulation; reported under "learned"), then the same
+batches are showered plain and learned; `value` is the learned shower and the
+plain one is reported beside it.
+
 Prints one JSON line.  Extra objects:
   roofline      the shower kernel against the FP64 vector peak, with the
                 algorithmic operation count of the launches that were timed
@@ -28,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+LOG_ID0 = 1 << 40  # event ids of the trial-log run (disjoint from the timed steps)
 HBM_PEAK_GBS = 8000.0
 # algorithmic FP64 work per unit (a transcendental counted as 20 operations)
 OPS_TRIAL = 6 + 20            # one log, the key arithmetic and the compare
@@ -65,8 +72,9 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel):
-    """HBM bytes per event of `kernel` from the committed counter summary, or None."""
+def stored_traffic(kernel, mode):
+    """HBM bytes per event of `kernel` in `mode` ("plain" or "learned") from the
+    committed counter summary, or None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_pp_nlo.traffic.json")
     if not os.path.exists(path):
         return None
@@ -74,7 +82,7 @@ def stored_traffic(kernel):
         d = json.load(f)
     if d.get("source_hash") != source_hash():
         return None
-    return d
+    return d.get("modes", {}).get(mode)
 
 
 def copy_probe(nbytes):
@@ -89,15 +97,104 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
+def learned_pipeline(G, binding, args, seed):
+    """Trial log of the plain shower, training, calibration and tabulation, all
+    on the GPU with the library's kernels (untimed for `value`, reported)."""
+    import torch
+    rep = {}
+    G.mlp_init(seed + 10)
+    t0 = time.perf_counter()
+    hin = G.hard_events(LOG_ID0, args.log_events, seed, max_slots=8)
+    _, rows, cnt = G.shower_log(hin, seed, args.log_rows)
+    torch.cuda.synchronize()
+    rep["log_s"], rep["log_events"], rep["log_rows"] = time.perf_counter() - t0, args.log_events, int(rows.shape[0])
+    del hin
+    t0 = time.perf_counter()
+    x, y, ent = G.mlp_features(rows)
+    del rows
+    ntr = int(0.8 * x.shape[0])
+    loss = G.mlp_train(x[:ntr], y[:ntr], steps=args.train_steps, batch=args.train_batch, lr=3e-3, tau=0.999,
+                       seed=seed)
+    torch.cuda.synchronize()
+    rep["train_s"], rep["train_steps"], rep["train_batch"] = time.perf_counter() - t0, args.train_steps, args.train_batch
+    lv = loss.cpu().numpy()
+    rep["loss_first"], rep["loss_last"] = float(lv[:10].mean()), float(lv[-10:].mean())
+    t0 = time.perf_counter()
+    G.mlp_calibrate(x[ntr:], y[ntr:], ent[ntr:])
+    G.mlp_tabulate()
+    torch.cuda.synchronize()
+    rep["calibrate_tabulate_s"] = time.perf_counter() - t0
+    tab = G.learned_table()
+    rep["mean_bound_over_analytic"] = float(np.mean(tab[tab > 0] / np.repeat(
+        G.bounds()[8:72, :, None], 8, axis=2)[tab > 0]))
+    del x, y, ent
+    return rep
+
+
+def timed_stream(G, binding, batches, seed, args, kw, mode):
+    """Warm-up passes and one timed pass of the graph-captured stream."""
+    import torch
+    stats = torch.zeros(binding.NSTATS, dtype=torch.uint64, device="cuda")
+    K = len(batches)
+    if args.launch == "stream":
+        stream = torch.cuda.Stream()
+        graph = G.capture(batches, seed, stream, stats=stats, mode=mode, **kw)
+        run = lambda: graph.launch(stream)  # noqa: E731
+    else:
+        stream = torch.cuda.current_stream()
+        graph = None
+
+        def run():
+            for ev_in, ev_out, _ in batches:
+                G.shower(ev_in, seed, out=ev_out, stats=stats, stream=stream, mode=mode, **kw)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    stats.zero_()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    start.record(stream)
+    run()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    launch_ms = start.elapsed_time(end)
+    if graph is not None:
+        graph.close()
+    n = sum(b[2] for b in batches)
+    return {"wall_s": wall, "launch_ms": launch_ms, "events": n, "stats": stats.cpu().numpy().astype(float),
+            "launches": 1 if args.launch == "stream" else K}
+
+
+def shower_stats(st, nev, nfin, overflow):
+    trials, winners, accepts = st[1], st[0], st[2]
+    return {"trials_per_event": trials / nev, "winner_cycles_per_event": winners / nev,
+            "accepted_per_event": accepts / nev,
+            "veto_trials_per_accepted_emission": winners / max(accepts, 1.0),
+            "channel_trials_per_accepted_emission": trials / max(accepts, 1.0),
+            "weight_violations": int(st[3]), "overflow_events": overflow,
+            "fallback_events": int(st[6]), "null_winners_per_event": st[7] / nev,
+            "mean_final_multiplicity": nfin,
+            "active_lane_fraction": st[5] / st[4] if st[4] > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--events", type=int, default=1_000_000, help="events per step (one batch)")
+    ap.add_argument("--mode", choices=["learned", "plain"], default="learned",
+                    help="learned: train the bound first and report the learned shower as `value`, "
+                         "the plain shower beside it; plain: the plain shower only")
     ap.add_argument("--launch", choices=["stream", "per-step"], default="stream",
                     help="stream: the timed steps' batches go through one graph-captured persistent "
                          "launch; per-step: one launch per step")
+    ap.add_argument("--log-events", type=int, default=420_000, help="events whose trials train the bound")
+    ap.add_argument("--log-rows", type=int, default=50_000_000)
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--train-batch", type=int, default=65536)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
@@ -113,8 +210,8 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
-    if args.launch == "stream" and args.variant != 0:
-        ap.error("only the wave kernel (variant 0) streams batches")
+    if args.variant != 0 and (args.launch == "stream" or args.mode == "learned"):
+        ap.error("only the wave kernel (variant 0) streams batches and runs the learned mode")
 
     import torch
     from gapsinputs import workloads
@@ -127,7 +224,6 @@ def main():
     G = binding.Gaps(cfg)
     kw = dict(block=args.block, compact_every=args.compact_every, waves_per_simd=args.waves_per_simd,
               variant=args.variant)
-    stats = torch.zeros(binding.NSTATS, dtype=torch.uint64, device="cuda")
 
     # hard events of every step (ids k*n .. (k+1)*n-1); timed separately, not part of the metric
     t0 = time.perf_counter()
@@ -136,61 +232,66 @@ def main():
     t_hard = (time.perf_counter() - t0) / K
     outs = [binding.DeviceEvents(n, workloads.MAX_SLOTS) for _ in range(K)]
     batches = [(ins[k], outs[k], n) for k in range(K)]
-
-    if args.launch == "stream":
-        stream = torch.cuda.Stream()
-        graph = G.capture(batches, seed, stream, stats=stats, **kw)
-        run = lambda: graph.launch(stream)  # noqa: E731
-    else:
-        stream = torch.cuda.current_stream()
-        def run():
-            for k in range(K):
-                G.shower(ins[k], seed, out=outs[k], stats=stats, stream=stream, **kw)
-
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} passes over {K} batches)")
-
-    # timed: K steps; HIP events on the stream the shower kernel runs on
-    stats.zero_()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    start.record(stream)
-    run()
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    launch_ms = start.elapsed_time(end)
-    launches = 1 if args.launch == "stream" else K
-    log(f"timed {K} steps: wall {wall * 1e3:.1f} ms, device {launch_ms:.1f} ms")
-    st = stats.cpu().numpy().astype(float)
-
-    ms_per_step = wall * 1e3 / K
-    value = n * K / wall
-    mean_launch_s = launch_ms / 1e3 / launches
-    nev_launch = n * K / launches
-
-    # observables of the last batch (timed separately)
-    t0 = time.perf_counter()
-    obs = G.observables(outs[-1])
-    torch.cuda.synchronize()
-    t_obs = time.perf_counter() - t0
-
-    nfin = float(np.mean([o.n.double().mean().item() for o in outs]))
-    flags = torch.cat([o.flags.to(torch.int64) for o in outs])
-    overflow = int(((flags & 1) != 0).sum().item())
-    trials, winners, accepts = st[binding.ST_TRIALS], st[binding.ST_CYCLES], st[binding.ST_ACCEPT]
-    ops = (trials * OPS_TRIAL + winners * OPS_WINNER +
-           accepts * (OPS_ACCEPT_BASE + OPS_ACCEPT_PER_PARTON * 0.5 * nfin)) / launches
-    achieved = ops / mean_launch_s / 1e12
-    viol = int(st[binding.ST_VIOL])
     kernel = {1: "k_shower_lanes", 0: {0: "k_shower_wave", 2: "k_shower_wave", 3: "k_shower_wave3",
                                        4: "k_shower_wave4"}[args.waves_per_simd]}[args.variant]
-    tr = stored_traffic(kernel)
-    traffic = None if tr is None else tr["bytes_per_event"] * nev_launch
-    nev = n * K
+
+    def summarise(r, mode):
+        nfin = float(np.mean([o.n.double().mean().item() for o in outs]))
+        flags = torch.cat([o.flags.to(torch.int64) for o in outs])
+        overflow = int(((flags & 1) != 0).sum().item())
+        st = r["stats"]
+        nev_launch = r["events"] / r["launches"]
+        mean_launch_s = r["launch_ms"] / 1e3 / r["launches"]
+        ops = (st[1] * OPS_TRIAL + st[0] * OPS_WINNER +
+               st[2] * (OPS_ACCEPT_BASE + OPS_ACCEPT_PER_PARTON * 0.5 * nfin)) / r["launches"]
+        achieved = ops / mean_launch_s / 1e12
+        tr = stored_traffic(kernel, mode)
+        traffic = None if tr is None else tr["bytes_per_event"] * nev_launch
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel,
+                "launch_ms": mean_launch_s * 1e3, "events_per_launch": nev_launch, "ops_per_launch": ops,
+                "hbm_gbs": None if traffic is None else traffic / mean_launch_s / 1e9}
+        return (r["events"] / r["wall_s"], r["wall_s"] * 1e3 / K, roof,
+                shower_stats(st, r["events"], nfin, overflow))
+
+    def histos():
+        ob = G.observables(outs[-1])
+        w = ins[-1].w
+        hs = []
+        for col, lo, hi in ((0, 0.0, 60.0), (3, 0.0, 1.0), (4, -0.5, 6.5)):
+            sw, sw2 = G.histogram(ob, w, col, lo, hi, 30)
+            hs.append((sw.cpu().numpy(), sw2.cpu().numpy()))
+        return hs
+
+    out_extra = {}
+    r_plain = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_PLAIN)
+    v_plain, ms_plain, roof_plain, st_plain = summarise(r_plain, "plain")
+    t0 = time.perf_counter()
+    h_plain = histos()
+    torch.cuda.synchronize()
+    t_obs = time.perf_counter() - t0
+    log(f"plain: {v_plain:.4g} events/s")
+    if args.mode == "learned":
+        rep = learned_pipeline(G, binding, args, seed)
+        log(f"trained bound: {rep}")
+        r_l = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
+        v_l, ms_l, roof_l, st_l = summarise(r_l, "learned")
+        # a weight above its bound that was used without the plain fallback
+        unhandled = int(sum(((o.flags.to(torch.int64) & binding.F_VIOL) != 0).sum().item() for o in outs))
+        log(f"learned: {v_l:.4g} events/s")
+        h_l = histos()
+        chi = {}
+        for name, (a, a2), (b, b2) in zip(("z_pt", "phi_star", "n_jets"), h_plain, h_l):
+            m = (a2 + b2) > 0
+            chi[name] = float(np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m])) / max(m.sum(), 1))
+        value, ms_per_step, roof, stats_main = v_l, ms_l, roof_l, st_l
+        out_extra["plain"] = {"value": v_plain, "ms_per_step": ms_plain, "roofline": roof_plain,
+                              "shower_stats": st_plain}
+        out_extra["learned"] = dict(rep, speedup_over_plain=v_l / v_plain,
+                                    histogram_chi2_ndf_vs_plain=chi,
+                                    unhandled_bound_violations=unhandled)
+    else:
+        value, ms_per_step, roof, stats_main = v_plain, ms_plain, roof_plain, st_plain
 
     out = {
         "metric": "showered events/sec, NLO pp→Z 13 TeV, 1 MI355X; plain vs learned-proposal",
@@ -208,32 +309,19 @@ def main():
         "config": {"workload": "pp_nlo_1m: NLO-matched Z production at 13 TeV (MC@NLO-style S/H events, "
                                "toy PDF grid 100x50), one step = one batch of 10^6 events with its own ids, "
                                "FP64 kinematics, up to 128 partons per event",
-                   "events_per_step": n, "mode": "plain", "launch": args.launch,
+                   "events_per_step": n, "mode": args.mode, "launch": args.launch,
                    "max_slots": workloads.MAX_SLOTS, "kernel": kernel, "block": args.block or "auto",
                    "compact_every": args.compact_every or 4},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": kernel, "launch_ms": mean_launch_s * 1e3, "events_per_launch": nev_launch,
-                     "ops_per_launch": ops,
-                     "hbm_gbs": None if traffic is None else traffic / mean_launch_s / 1e9},
-        "shower_stats": {"trials_per_event": trials / nev, "winner_cycles_per_event": winners / nev,
-                         "accepted_per_event": accepts / nev,
-                         "veto_trials_per_accepted_emission": winners / max(accepts, 1.0),
-                         "channel_trials_per_accepted_emission": trials / max(accepts, 1.0),
-                         "weight_violations": viol, "overflow_events": overflow,
-                         "mean_final_multiplicity": nfin,
-                         "active_lane_fraction": (st[binding.ST_LANE_ACTIVE] / st[binding.ST_LANE_ITERS]
-                                                  if st[binding.ST_LANE_ITERS] > 0 else None)},
+        "roofline": roof,
+        "shower_stats": stats_main,
         "component_s": {"hard_events_per_step": t_hard, "shower_per_step": ms_per_step / 1e3,
                         "observables_per_step": t_obs},
     }
-    if args.launch == "stream":
-        graph.close()
+    out.update(out_extra)
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, seed)
     print(json.dumps(out))
-    del obs
 
 
 if __name__ == "__main__":

@@ -22,6 +22,8 @@ MODE_PLAIN, MODE_LEARNED, MODE_LOG = 0, 1, 2
 NSTATS = 8
 ST_CYCLES, ST_TRIALS, ST_ACCEPT, ST_VIOL, ST_LANE_ITERS, ST_LANE_ACTIVE, ST_FALLBACK, ST_NULL = range(8)
 NOBS = 12
+# per-event flags (GAPS_F_* of include/gaps.h)
+F_OVERFLOW, F_COLOUR, F_NAN, F_FALLBACK, F_VIOL, F_HARDFAIL, F_HEVENT, F_MAXCYC = (1 << k for k in range(8))
 
 
 class GapsError(RuntimeError):
