@@ -391,6 +391,28 @@ __device__ __forceinline__ double learned_R(const Cfg& C, int ent, int ebin, int
   return C.learn[((ent - kIS0) * kNB + ebin) * kNTB + k];
 }
 
+// constant of cell k of an initial-state channel (type IF or II) whose emitter
+// has flavour pidi: its terms in the order term_at enumerates them (family A
+// then B for a quark; C then D over the flavours 1..nf, -1..-nf for a gluon)
+__device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k) {
+  const double af = C.as_over / (2.0 * kPi) * C.over_scale;
+  const bool ii = type == kII;
+  double c = 0.0;
+  if (pidi == 21) {
+    c += af * learned_R(C, ent_s1(famC, 0), ebin, k) * I1;
+    for (int m = 1; m <= 2 * C.nf; ++m) {
+      const int a = m <= C.nf ? m : -(m - C.nf);
+      const int T = pdf_tab(a);
+      c += af * learned_R(C, ii ? ent_s3(famD, T) : ent_s1(famD, T), ebin, k) * I2;
+    }
+  } else {
+    const int T = pdf_tab(pidi);
+    c += af * learned_R(C, ent_s1(famA, T), ebin, k) * I1;
+    c += af * learned_R(C, ii ? ent_s3(famB, T) : ent_s1(famB, T), ebin, k) * I2;
+  }
+  return c;
+}
+
 // the cell of a scale: the largest k with edge[k] < ln t (0 if none), and its
 // lower edge (constant indices only, so the edges stay in registers)
 __device__ __forceinline__ int cell_of(const Cfg& C, double lnt, double& edge) {

@@ -18,8 +18,6 @@ struct Scratch {
   uint32_t* cinfo;
   double *ctlim, *clntlim, *cinvc;
   double *cc, *cs, *czlo, *comzhi, *cI1, *cI2;
-  double* cinvk;              // learned mode: [kNTB][4][lanes] 1/c per ln t cell, entries 0..3
-  double* cck;                // learned mode: [kNTB][4][lanes] c per ln t cell
   unsigned long long* queue;  // work-queue counters
 };
 

@@ -47,7 +47,9 @@ struct LaneState {
   int32_t b, lrn;
   double T, lnT, t1;
   uint32_t cycle, ntri, nacc, nviol, flags;
-  int32_t n, maxtag, loaded, stop, pending;
+  int32_t n, maxtag;
+  uint32_t bits;  // loaded | stop << 1 | pending << 2 | rebuild << 3 | em_all << 4
+  int32_t emik;   // emitter | spectator << 16 of the emission awaiting its channel rebuild
 };
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
@@ -55,102 +57,130 @@ __device__ __forceinline__ Rec rec_of(const Scratch& S, int64_t slot) {
   return Rec{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, 1, S.max_slots, slot};
 }
 
-// Cooperative (re)build of every channel entry of the events whose lanes are
-// set in `mask`.  For each such event, lane j holds the effective colour
-// tags of particles j and j + 64, so the colour partner of every dipole end
-// is found with register reads instead of a search through memory; then lane
-// c sets up entry c = 2 * slot + side.  Returns (per lane) whether this
-// lane's own event hit a broken colour line or a non-finite momentum.
-__device__ uint32_t coop_build(const WaveCtx& W, unsigned long long mask, int n, int64_t myslot, bool mylrn) {
-  uint32_t myflags = 0u;
+// LDS of one wave for the cooperative channel build: a ring of entries that
+// need their constants set up, and one flag word per lane.
+constexpr int kBuildRing = 128;
+struct BuildLds {
+  uint32_t ring[kBuildRing];  // lane L | particle q << 6 | side << 14 | spectator k << 15
+  uint32_t flags[64];
+};
+
+// set up the channel constants of up to 64 queued entries, one per lane
+__device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int head, int cnt, int64_t myslot) {
+  const bool valid = W.lane < cnt;
+  const uint32_t it = valid ? B.ring[(head + W.lane) & (kBuildRing - 1)] : 0u;
+  const int L = (int)(it & 63u);
+  const int64_t slot = __shfl(myslot, L);
+  if (!valid) return;
+  const int q = (int)((it >> 6) & 0xFFu), side = (int)((it >> 14) & 1u), k = (int)(it >> 15);
+  const Rec R = rec_of(W.S, slot);
+  Chan ch;
+  chan_setup(W.C, R, q, side, k, ch);
+  const int64_t oc = (int64_t)(2 * q + side) * W.S.lanes + slot;
+  W.S.cinfo[oc] = pack(ch);
+  W.S.ctlim[oc] = ch.tlim;
+  W.S.clntlim[oc] = ch.lntlim;
+  W.S.cinvc[oc] = ch.invc;
+  W.S.cc[oc] = ch.c;
+  W.S.cs[oc] = ch.s;
+  W.S.czlo[oc] = ch.zlo;
+  W.S.comzhi[oc] = ch.omzhi;
+  W.S.cI1[oc] = ch.I1;
+  W.S.cI2[oc] = ch.I2;
+}
+
+// Cooperative (re)build of the channel entries of the events whose lanes are
+// set in `mask`.  The entries (slot, side) of all these events are laid end to
+// end and the wave walks them 64 at a time: each lane finds the colour partner
+// of one entry by scanning its event's colour tags.  Only entries whose
+// constants can have changed are set up again: all of them after a refill
+// (`all`) or an initial-initial emission (whose recoil boosts every
+// final-state momentum); otherwise those of emitter `ei`, spectator `ek` and
+// the new parton n - 1, entries whose partner is one of those three, and
+// entries whose partner changed.  The others are bitwise what a full set-up
+// would write, because their inputs did not change.  Entries to set up are
+// queued in LDS and set up 64 at a time, one per lane.  Returns (per lane)
+// whether this lane's own event has a broken colour line or a non-finite
+// momentum.
+__device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long mask, int n, int64_t myslot,
+                               bool all, int ei, int ek) {
   __threadfence_block();
-  while (mask) {
-    const int L = __ffsll((long long)mask) - 1;
-    mask &= mask - 1ull;
-    const int nL = __shfl(n, L);
-    const int64_t slot = __shfl(myslot, L);
-    const bool lrnL = __shfl((int)mylrn, L) != 0;
-    const Rec R = rec_of(W.S, slot);
-    // colours of particles lane and lane + 64 in registers
-    int ec0 = 0, ea0 = 0, ec1 = 0, ea1 = 0;
-    bool bad = false;
-    for (int r = 0; r < 2; ++r) {
-      const int q = W.lane + 64 * r;
-      if (q >= nL) continue;
-      const int64_t o = R.o(q);
-      const int st = R.st[o], cl = R.col[o], al = R.acol[o];
-      const int ec = st < 0 ? al : cl, ea = st < 0 ? cl : al;
-      if (r == 0) { ec0 = ec; ea0 = ea; } else { ec1 = ec; ea1 = ea; }
-      bad |= !(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o]));
-    }
-    bool missing = false;
-    for (int base = 0; base < 2 * nL; base += 64) {
-      const int c = base + W.lane;
-      const int i = c >> 1, side = c & 1;
-      // this entry's tag: colour (side 0) or anticolour (side 1) of particle i
-      const int src = i & 63;
-      const int tc0 = __shfl(ec0, src), ta0 = __shfl(ea0, src);
-      const int tc1 = __shfl(ec1, src), ta1 = __shfl(ea1, src);
-      const int tag = c < 2 * nL ? (i < 64 ? (side == 0 ? tc0 : ta0) : (side == 0 ? tc1 : ta1)) : 0;
-      int k = -1;
-      if (nL <= 128) {
-        for (int j = 0; j < nL; ++j) {
-          const int oc = j < 64 ? __shfl(ec0, j) : __shfl(ec1, j - 64);
-          const int oa = j < 64 ? __shfl(ea0, j) : __shfl(ea1, j - 64);
-          const int other = side == 0 ? oa : oc;
-          if (k < 0 && j != i && tag != 0 && other == tag) k = j;
-        }
-      } else if (tag != 0) {
-        for (int j = 0; j < nL; ++j) {
-          if (j == i) continue;
-          const int other = side == 0 ? R.effa(j) : R.effc(j);
-          if (other == tag) { k = j; break; }
-        }
-      }
-      if (c >= 2 * nL) continue;
-      if (tag != 0 && k < 0) missing = true;
-      const int64_t oc = (int64_t)c * W.S.lanes + slot;
-      if (k < 0) { W.S.cinfo[oc] = 0u; continue; }
-      Chan ch;
-      chan_setup(W.C, R, i, side, k, ch);
-      W.S.cinfo[oc] = pack(ch);
-      W.S.ctlim[oc] = ch.tlim;
-      W.S.clntlim[oc] = ch.lntlim;
-      W.S.cinvc[oc] = ch.invc;
-      W.S.cc[oc] = ch.c;
-      W.S.cs[oc] = ch.s;
-      W.S.czlo[oc] = ch.zlo;
-      W.S.comzhi[oc] = ch.omzhi;
-      W.S.cI1[oc] = ch.I1;
-      W.S.cI2[oc] = ch.I2;
-      if (lrnL && c < 4 && ch.alive && (ch.type == kIF || ch.type == kII)) {
-        // learned mode: the constant of every ln t cell of this channel, in one
-        // pass over the terms (a term's eight cell values share a cache line);
-        // per cell the sum runs over the terms in order, as learned_c does
-        const double af = W.C.as_over / (2.0 * kPi) * W.C.over_scale;
-        double ck[kNTB];
+  const bool mine = (mask >> W.lane) & 1ull;
+  const int ne = mine ? 2 * n : 0;
+  int incl = ne;
 #pragma unroll
-        for (int k = 0; k < kNTB; ++k) ck[k] = 0.0;
-        for (int m = 0; m < ch.nterm; ++m) {
-          const Term t = term_at(W.C, ch, m);
-          const double* Rp = W.C.learn + ((t.ent - kIS0) * kNB + ch.ebin) * kNTB;
-#pragma unroll
-          for (int k = 0; k < kNTB; ++k) ck[k] += af * Rp[k] * t.I;
-        }
-#pragma unroll
-        for (int k = 0; k < kNTB; ++k) {
-          const int64_t ok = ((int64_t)k * 4 + c) * W.S.lanes + slot;
-          W.S.cinvk[ok] = 1.0 / ck[k];
-          W.S.cck[ok] = ck[k];
-        }
-      }
-    }
-    const bool anymiss = __ballot(missing) != 0ull;
-    const bool anybad = __ballot(bad) != 0ull;
-    if (W.lane == L) myflags = (anymiss ? fColour : 0u) | (anybad ? fNaN : 0u);
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, (unsigned)o);
+    if (W.lane >= o) incl += v;
   }
+  const int total = __shfl(incl, 63);
+  if (mine) B.flags[W.lane] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  int head = 0, cnt = 0;
+  for (int g0 = 0; g0 < total; g0 += 64) {
+    const int g = g0 + W.lane;
+    // owner lane: the number of lanes whose inclusive prefix is <= g
+    int L = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const int v = __shfl(incl, L + step - 1);
+      if (v <= g) L += step;
+    }
+    L = L > 63 ? 63 : L;
+    const int nL = __shfl(n, L);
+    const int firstL = __shfl(incl, L) - 2 * nL;
+    const int64_t slot = __shfl(myslot, L);
+    const bool allL = __shfl((int)all, L) != 0;
+    const int iL = __shfl(ei, L), kL = __shfl(ek, L);
+    bool queue = false;
+    int q = 0, side = 0, k = -1;
+    if (g < total) {
+      const int e = g - firstL;
+      q = e >> 1;
+      side = e & 1;
+      const Rec R = rec_of(W.S, slot);
+      const int tag = side == 0 ? R.effc(q) : R.effa(q);
+      if (tag != 0) {
+        for (int j = 0; j < nL; ++j) {
+          if (j == q) continue;
+          if ((side == 0 ? R.effa(j) : R.effc(j)) == tag) { k = j; break; }
+        }
+        if (k < 0) atomicOr(&B.flags[L], fColour);
+      }
+      if (side == 0) {
+        const int64_t o = R.o(q);
+        if (!(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o])))
+          atomicOr(&B.flags[L], fNaN);
+      }
+      const int64_t oc = (int64_t)e * W.S.lanes + slot;
+      const uint32_t old = W.S.cinfo[oc];
+      const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
+      const int jL = nL - 1;
+      const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
+      if (dirty) {
+        if (k < 0) W.S.cinfo[oc] = 0u;
+        else queue = true;
+      }
+    }
+    const unsigned long long qm = __ballot(queue);
+    if (queue) {
+      const int r = __popcll(qm & lanemask_lt(W.lane));
+      B.ring[(head + cnt + r) & (kBuildRing - 1)] =
+          (uint32_t)L | ((uint32_t)q << 6) | ((uint32_t)side << 14) | ((uint32_t)k << 15);
+    }
+    cnt += __popcll(qm);
+    __builtin_amdgcn_wave_barrier();
+    if (cnt >= 64) {
+      build_setup(W, B, head, 64, myslot);
+      head = (head + 64) & (kBuildRing - 1);
+      cnt -= 64;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (cnt > 0) build_setup(W, B, head, cnt, myslot);
+  __builtin_amdgcn_wave_barrier();
   __threadfence_block();
-  return myflags;
+  return mine ? B.flags[W.lane] : 0u;
 }
 
 // rebuild the channel description of cache entry c from the cache and record
@@ -200,6 +230,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   // the overestimate table, staged in LDS for the term loops
   __shared__ double s_bound[kNEnt * kNB];
   __shared__ int s_cnt[16], s_nexh;
+  __shared__ BuildLds s_build[8];  // one per wave (blocks of at most 512 threads)
   extern __shared__ LaneState s_pool[];
   for (int q = threadIdx.x; q < kNEnt * kNB; q += blockDim.x) s_bound[q] = Cg.bound[q];
   if (threadIdx.x == 0) s_nexh = 0;
@@ -229,6 +260,10 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   unsigned long long st_cyc = 0, st_tri = 0, st_acc = 0, st_viol = 0, st_iters = 0, st_active = 0;
   unsigned long long st_fb = 0, st_null = 0;
   int since = 1 << 30;
+  // the last cycle's accepted emission, whose channels are rebuilt at the top
+  // of the next iteration together with the refilled lanes
+  bool rebuild = false, em_all = false;
+  int em_i = 0, em_k = 0;
   bool counted = false, tail = false;
   unsigned it_tail = 0;
 
@@ -292,18 +327,24 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           LaneState& X = s_pool[prefix + __popcll(a0 & lanemask_lt(lane))];
           X.e = e; X.id = id; X.slot = slot; X.b = b; X.lrn = lrn; X.T = T; X.lnT = lnT; X.t1 = t1;
           X.cycle = cycle; X.ntri = ntri; X.nacc = nacc; X.nviol = nviol; X.flags = flags;
-          X.n = n; X.maxtag = maxtag; X.loaded = loaded; X.stop = stop; X.pending = pending;
+          X.n = n; X.maxtag = maxtag;
+          X.bits = (uint32_t)loaded | ((uint32_t)stop << 1) | ((uint32_t)pending << 2) | ((uint32_t)rebuild << 3) |
+                   ((uint32_t)em_all << 4);
+          X.emik = (em_i & 0xFFFF) | (em_k << 16);
         }
         __syncthreads();
         const bool got = (int)threadIdx.x < total;
         active = false;
         pending = false;
+        rebuild = false;
         if (got) {
           const LaneState& X = s_pool[threadIdx.x];
           e = X.e; id = X.id; slot = X.slot; b = X.b; lrn = X.lrn != 0; T = X.T; lnT = X.lnT; t1 = X.t1;
           cycle = X.cycle; ntri = X.ntri; nacc = X.nacc; nviol = X.nviol; flags = X.flags;
-          n = X.n; maxtag = X.maxtag; loaded = X.loaded != 0; stop = X.stop != 0;
-          pending = X.pending != 0;
+          n = X.n; maxtag = X.maxtag;
+          loaded = (X.bits & 1u) != 0; stop = (X.bits & 2u) != 0; pending = (X.bits & 4u) != 0;
+          rebuild = (X.bits & 8u) != 0; em_all = (X.bits & 16u) != 0;
+          em_i = X.emik & 0xFFFF; em_k = X.emik >> 16;
           active = !pending;
           R = rec_of(S, slot);
         }
@@ -314,8 +355,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     // lanes whose learned bound failed reload their own event in plain mode
     unsigned long long act = __ballot(active);
     const unsigned long long pend = __ballot(pending);
+    bool fresh = false;
     if (pend || (!exhausted && (since >= K || act == 0ull))) {
-      bool fresh = false;
       if (pending) {
         pending = false;
         active = true;
@@ -340,12 +381,22 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         }
         since = 0;
       }
-      {
-        // a broken colour line stops the event before its first cycle
-        const uint32_t f = coop_build(W, __ballot(fresh), n, slot, lrn) & fColour;
-        if (fresh && f) { flags |= f; stop = true; }
-      }
       act = __ballot(active);
+    }
+    // ---- one cooperative channel build for the refilled lanes and the lanes
+    // that emitted in the last cycle.  A broken colour line stops a refilled
+    // event before its first cycle; after an emission a non-finite momentum
+    // (reported first) or a broken colour line stops the event (its cycle
+    // was already counted).
+    {
+      const unsigned long long bm = __ballot(fresh || rebuild);
+      if (bm) {
+        uint32_t f = coop_build(W, s_build[wid], bm, n, slot, fresh || em_all, em_i, em_k);
+        if (fresh) f &= fColour;
+        if (f & fNaN) f = fNaN;
+        if ((fresh || rebuild) && f) { flags |= f; stop = true; }
+        rebuild = false;
+      }
     }
     if (act == 0ull) {
       if (!compact && exhausted) break;  // no tail mode: a drained wave just leaves
@@ -356,7 +407,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     st_active += (unsigned long long)__popcll(act);
 
     // ---- one cycle of the veto algorithm on every active lane
-    bool done = false, accepted = false;
+    bool done = false;
     if (active && stop) done = true;
     if (active && !done && cycle >= kMaxCycles) { flags |= fMaxCyc; done = true; }
     if (active && !done) {
@@ -408,10 +459,14 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           if (lrn && c < 4 && (type == kIF || type == kII)) {
             cell = cell_of(C, lnTch, floor);
             if ((int)((info & kCellMask) >> kCellShift) != cell) {
-              // the scale entered a new cell: its constant replaces the entry's
-              invc = S.cinvk[((int64_t)cell * 4 + c) * S.lanes + slot];
+              // the scale entered a new cell: that cell's constant replaces the
+              // entry's (1/c for the trials, c for the winner's term choice)
               const int64_t oc = (int64_t)c * S.lanes + slot;
+              const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cI1[oc],
+                                          S.cI2[oc], cell);
+              invc = 1.0 / ck;
               S.cinvc[oc] = invc;
+              S.cc[oc] = ck;
               S.cinfo[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
             }
             if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
@@ -480,8 +535,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         const bool lch = lrn && win < 4 && (ch.type == kIF || ch.type == kII);
         double u[4];
         rng4(A.seed, strm, id, cycle, 0xFFFFFFFFu, u);
-        const Term tm = lch ? select_term_cell(C, ch, u[0], wcell, S.cck[((int64_t)wcell * 4 + win) * S.lanes + slot])
-                            : select_term(C, ch, u[0]);
+        // a learned channel's cached c is that of its current cell (the winner's)
+        const Term tm = lch ? select_term_cell(C, ch, u[0], wcell, ch.c) : select_term(C, ch, u[0]);
         double z, omz;
         shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
         const double phi = 2.0 * kPi * u[2];
@@ -516,10 +571,14 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
               done = true;
             } else {
               emit(R, n, maxtag, ch, tm, z, omz, v, phi);
+              // an initial-initial recoil boosts every final-state momentum
+              rebuild = true;
+              em_all = ch.type == kII;
+              em_i = ch.i;
+              em_k = ch.k;
               n += 1;
               nacc += 1;
               if (t1 == 0.0) t1 = t;
-              accepted = true;
             }
           }
           if (!done) {
@@ -529,13 +588,6 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           }
         }
       }
-    }
-    // ---- cooperative channel rebuild for the lanes that emitted
-    const unsigned long long emitted = __ballot(accepted);
-    if (emitted) {
-      uint32_t f = coop_build(W, emitted, n, slot, lrn);
-      if (f & fNaN) f = fNaN;  // a non-finite momentum is reported before the colour check
-      if (accepted && f) { flags |= f; done = true; }
     }
     // ---- finished events: write out and free the lane
     if (active && done) {
