@@ -20,7 +20,8 @@ MODE_PLAIN, MODE_LEARNED, MODE_LOG = 0, 1, 2
 
 class OrOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("log", C.POINTER(C.c_float)), ("log_cap", C.c_int64),
-                ("log_count", C.POINTER(C.c_int64)), ("learned", C.POINTER(C.c_double))]
+                ("log_count", C.POINTER(C.c_int64)), ("learned", C.POINTER(C.c_double)),
+                ("retain", C.c_int)]
 
 
 def build():
@@ -170,13 +171,20 @@ class Oracle:
         lib().or_hard_events(self.h, first_id, n, seed, C.byref(s))
         return ev
 
-    def shower(self, ev_in: records.Events, seed, nthreads=1, max_slots=None):
+    def shower(self, ev_in: records.Events, seed, nthreads=1, max_slots=None, retain=False):
+        """Plain shower; retain=True: the retained-trial form of the competition."""
         out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
         si, so = events_struct(ev_in), events_struct(out)
-        lib().or_shower(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads)
+        if not retain:
+            lib().or_shower(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads)
+            return out
+        o = OrOpts(MODE_PLAIN, None, 0, None, None, 1)
+        rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
+        if rc != 0:
+            raise RuntimeError("or_shower_ex failed")
         return out
 
-    def shower_log(self, ev_in: records.Events, seed, log_cap, nthreads=1, max_slots=None):
+    def shower_log(self, ev_in: records.Events, seed, log_cap, nthreads=1, max_slots=None, retain=False):
         """LOG mode: the plain shower plus its initial-state trial log
         (rows: ln t, ln eta, z, table entry, ln weight).  Returns (events, rows,
         total rows seen)."""
@@ -184,19 +192,20 @@ class Oracle:
         si, so = events_struct(ev_in), events_struct(out)
         log = np.zeros((max(int(log_cap), 1), 5), dtype=np.float32)
         cnt = C.c_int64(0)
-        o = OrOpts(MODE_LOG, log.ctypes.data_as(C.POINTER(C.c_float)), int(log_cap), C.pointer(cnt), None)
+        o = OrOpts(MODE_LOG, log.ctypes.data_as(C.POINTER(C.c_float)), int(log_cap), C.pointer(cnt), None,
+                   int(retain))
         rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
         if rc != 0:
             raise RuntimeError("or_shower_ex failed")
         return out, log[:min(cnt.value, int(log_cap))], cnt.value
 
-    def shower_learned(self, ev_in: records.Events, seed, table, nthreads=1, max_slots=None):
+    def shower_learned(self, ev_in: records.Events, seed, table, nthreads=1, max_slots=None, retain=False):
         """LEARNED mode with the bound table [64][48][8] (doubles)."""
         out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
         si, so = events_struct(ev_in), events_struct(out)
         tab = np.ascontiguousarray(table, dtype=np.float64)
         assert tab.shape == (64, 48, 8)
-        o = OrOpts(MODE_LEARNED, None, 0, None, tab.ctypes.data_as(C.POINTER(C.c_double)))
+        o = OrOpts(MODE_LEARNED, None, 0, None, tab.ctypes.data_as(C.POINTER(C.c_double)), int(retain))
         rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
         if rc != 0:
             raise RuntimeError("or_shower_ex failed")

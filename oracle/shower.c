@@ -528,13 +528,49 @@ static void log_trial(logsink_t* L, double t, double eta, double z, int ent, dou
     pthread_mutex_unlock(&L->mu);
 }
 
+/* One trial of channel C from the evolution scale (T, lnT), with the random
+ * number of its entry 2i+side at cycle cyc.  Returns the key ln t of the trial,
+ * or -INFINITY when the channel has no trial above its cutoff (then nothing is
+ * counted).  In learned mode an initial-state channel of the incoming partons
+ * draws against the constant of the cell of its starting scale, and a trial
+ * below that cell is a null at the cell's lower edge (*isnull, *cell). */
+static double draw_trial(const or_state* S, const chan_t* C, double T, double lnT, uint64_t seed,
+                         uint32_t stream, int64_t id, uint32_t cyc, int learned, const double* Lt,
+                         uint32_t* ntri, int* isnull, int* cell) {
+    *isnull = 0;
+    *cell = 0;
+    if (!C->alive) return -INFINITY;
+    double Tch = T < C->tlim ? T : C->tlim;
+    double lnTch = lnT < C->lntlim ? lnT : C->lntlim;
+    if (!(Tch > C->tcut)) return -INFINITY;
+    uint32_t slot = 2u * (uint32_t)C->i + (uint32_t)C->side;
+    double ub[4];
+    or_rng_block(seed, stream, id, cyc, slot >> 2, ub);
+    double lu = log(ub[slot & 3u]);
+    *ntri += 1;
+    double invc = C->invc, floor = -INFINITY;
+    int lch = learned && (C->type == T_IF || C->type == T_II) && C->i < 2, k = 0;
+    if (lch) {
+        k = cell_of(S, lnTch);
+        invc = 1.0 / learned_c(S, C, Lt, k);
+        floor = S->cell_edge[k];
+    }
+    double key;
+    if (!C->heavy) key = lnTch + lu * invc;
+    else key = log(C->m2 + (Tch - C->m2) * exp(lu * invc));
+    if (lch && key < floor && floor > C->lntcut) { key = floor; *isnull = 1; }
+    *cell = k;
+    if (key < C->lntcut) return -INFINITY;
+    return key;
+}
+
 /* Shower one event.  mode OR_MODE_LEARNED draws the initial-state channels
  * against the cell constants of the learned table Lt (random-number stream 1)
  * and returns 1, writing nothing, as soon as a weight exceeds its learned bound;
  * the caller then showers the event again in plain mode. */
 static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint64_t seed,
                       or_events* out, int64_t e_out, ev_t* ev, chan_t* ch, logsink_t* L,
-                      int mode, const double* Lt) {
+                      int mode, const double* Lt, int retain) {
     const int learned = mode == OR_MODE_LEARNED;
     const uint32_t stream = learned ? 1u : 0u;
     const int64_t ci = in->cap, co = out->cap;
@@ -555,10 +591,16 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
     double T = in->t_start[e_in], lnT = log(T), t1 = 0.0;
     uint32_t ncyc = 0, ntri = 0, nacc = 0, nviol = 0;
     int nch = 0;
+    /* retained-trial form: the pending trial of every channel */
+    static _Thread_local double key[OR_MAXCH];
+    static _Thread_local int knull[OR_MAXCH], kcell[OR_MAXCH];
     if (ev->n > M) flags |= OR_F_OVERFLOW;
     else if (build_channels(S, ev, ch, &nch) < 0) flags |= OR_F_COLOUR;
     else {
         uint32_t cycle = 0;
+        if (retain)
+            for (int c = 0; c < nch; ++c)
+                key[c] = draw_trial(S, &ch[c], T, lnT, seed, stream, id, 0u, learned, Lt, &ntri, &knull[c], &kcell[c]);
         for (;;) {
             if (cycle >= OR_MAXCYC) { flags |= OR_F_MAXCYC; break; }
             /* trial scales of every channel; the winner is the largest.  In
@@ -568,7 +610,13 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
             int win = -1, wnull = 0, wcell = 0;
             uint32_t curblk = 0xFFFFFFFFu;
             double ub[4];
-            for (int c = 0; c < nch; ++c) {
+            if (retain) {
+                /* the largest pending trial; ties go to the lowest entry */
+                for (int c = 0; c < nch; ++c)
+                    if (key[c] > best) { best = key[c]; win = c; }
+                if (win >= 0) { wnull = knull[win]; wcell = kcell[win]; }
+            }
+            for (int c = 0; !retain && c < nch; ++c) {
                 const chan_t* C = &ch[c];
                 if (!C->alive) continue;
                 double Tch = T < C->tlim ? T : C->tlim;
@@ -603,6 +651,9 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
                 T = exp(best);
                 lnT = best;
                 cycle += 1;
+                if (retain)
+                    key[win] = draw_trial(S, &ch[win], T, lnT, seed, stream, id, cycle, learned, Lt, &ntri,
+                                          &knull[win], &kcell[win]);
                 continue;
             }
             double t = exp(best);
@@ -635,8 +686,10 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
                 log_trial(L, t, C->eta, z, tm->ent, v.wn);
             if (lch && v.ok && v.w > 1.0) return 1; /* the learned bound failed */
             if (v.ok && v.w > 1.0) { nviol += 1; flags |= OR_F_VIOL; }
+            int emitted = 0;
             if (v.ok && u[3] < v.w) {
                 if (ev->n + 1 > M) { flags |= OR_F_OVERFLOW; break; }
+                emitted = 1;
                 emit(S, ev, C, tm, z, omz, &v, phi);
                 nacc += 1;
                 if (t1 == 0.0) t1 = t;
@@ -648,6 +701,13 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
             T = t;
             lnT = best;
             cycle += 1;
+            if (retain) {
+                /* after an emission every channel draws again from the new
+                 * scale; after a veto only the winner does */
+                for (int c = emitted ? 0 : win; c < (emitted ? nch : win + 1); ++c)
+                    key[c] = draw_trial(S, &ch[c], T, lnT, seed, stream, id, cycle, learned, Lt, &ntri,
+                                        &knull[c], &kcell[c]);
+            }
         }
         ncyc = cycle;
     }
@@ -680,6 +740,7 @@ typedef struct {
     logsink_t* L;
     int mode;
     const double* Lt;
+    int retain;
 } job_t;
 
 static void* run_job(void* arg) {
@@ -688,9 +749,9 @@ static void* run_job(void* arg) {
     chan_t* ch = (chan_t*)malloc(sizeof(chan_t) * OR_MAXCH);
     for (int64_t e = J->lo; e < J->hi; ++e) {
         if (J->mode == OR_MODE_LEARNED &&
-            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt) == 0)
+            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt, J->retain) == 0)
             continue;
-        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL);
+        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL, J->retain);
         if (J->mode == OR_MODE_LEARNED && J->out->flags) J->out->flags[e] |= OR_F_FALLBACK;
     }
     free(ev);
@@ -721,6 +782,7 @@ int or_shower_ex(const or_state* S, const or_events* in, int64_t n, uint64_t see
         jobs[k].L = L;
         jobs[k].mode = mode;
         jobs[k].Lt = mode == OR_MODE_LEARNED ? opts->learned : NULL;
+        jobs[k].retain = opts ? opts->retain != 0 : 0;
     }
     if (nthreads == 1) run_job(&jobs[0]);
     else {

@@ -158,7 +158,8 @@ def test_forced_fallback_equals_plain(oracles):
 
 
 @pytest.mark.slow
-def test_learned_first_emission_with_null_trials(oracles, cfgs):
+@pytest.mark.parametrize("retain", [False, True], ids=["regenerate", "retain"])
+def test_learned_first_emission_with_null_trials(oracles, cfgs, retain):
     """With the analytic constants in every cell, learned mode draws each
     initial-state channel cell by cell (a null at every cell edge it crosses);
     the first-emission distribution still equals the Sudakov quadrature."""
@@ -169,9 +170,9 @@ def test_learned_first_emission_with_null_trials(oracles, cfgs):
     k = next(e for e in range(64) if abs(base.pid[0, e]) == 2)
     n = 20000
     ev = replicate(base, k, n)
-    out = o.shower_learned(ev, 5, tab, nthreads=8)
+    out = o.shower_learned(ev, 5, tab, nthreads=8, retain=retain)
     assert not np.any(out.flags & records.FLAG_FALLBACK)
-    plain = o.shower(ev, 5, nthreads=8)
+    plain = o.shower(ev, 5, nthreads=8, retain=retain)
     assert out.n_cycles.mean() > plain.n_cycles.mean()  # the null winners
     S = 13000.0 ** 2
     ea, eb = 2 * base.E[0, k] / 13000.0, 2 * base.E[1, k] / 13000.0
@@ -196,15 +197,16 @@ def trained(oracles):
 
 
 @pytest.mark.slow
-def test_learned_histograms_match_plain(oracles, trained):
+@pytest.mark.parametrize("retain", [False, True], ids=["regenerate", "retain"])
+def test_learned_histograms_match_plain(oracles, trained, retain):
     """Learned and plain showers of the same NLO inputs agree in distribution
     (Z pT, number of partons), with fewer cycles and rare fallbacks."""
     o = oracles["nlo"]
     _, _, tab = trained
     n = 20000
     ev = o.hard_events(0, n, 1)
-    p = o.shower(ev, 3, nthreads=8)
-    l = o.shower_learned(ev, 3, tab, nthreads=8)
+    p = o.shower(ev, 3, nthreads=8, retain=retain)
+    l = o.shower_learned(ev, 3, tab, nthreads=8, retain=retain)
     fb = (l.flags & records.FLAG_FALLBACK) != 0
     assert fb.mean() < 0.02
     assert l.n_cycles[~fb].mean() < 0.8 * p.n_cycles.mean()

@@ -87,12 +87,16 @@ def replicate(ev, k, n):
     return out
 
 
+RETAIN = pytest.mark.parametrize("retain", [False, True], ids=["regenerate", "retain"])
+
+
 @pytest.mark.slow
-def test_ff_first_emission_ee(oracles, cfgs):
+@RETAIN
+def test_ff_first_emission_ee(oracles, cfgs, retain):
     o = oracles["ee"]
     n = 20000
     ev = o.hard_events(0, n, 7)
-    out = o.shower(ev, 11)
+    out = o.shower(ev, 11, nthreads=8, retain=retain)
     s = 91.2 ** 2
 
     def F(t):
@@ -134,14 +138,15 @@ def _ii_channel(pdf, s, eta, tq):
 
 
 @pytest.mark.slow
-def test_ii_first_emission_drell_yan(oracles, cfgs):
+@RETAIN
+def test_ii_first_emission_drell_yan(oracles, cfgs, retain):
     o, pdf = oracles["lo"], PDF(cfgs["lo"]["pdf"])
     base = o.hard_events(0, 64, 3)
     # pick a u ubar Born
     k = next(e for e in range(64) if abs(base.pid[0, e]) == 2)
     n = 20000
     ev = replicate(base, k, n)
-    out = o.shower(ev, 5)
+    out = o.shower(ev, 5, nthreads=8, retain=retain)
     S = 13000.0 ** 2
     ea, eb = 2 * base.E[0, k] / 13000.0, 2 * base.E[1, k] / 13000.0
     s = ea * eb * S
@@ -153,7 +158,8 @@ def test_ii_first_emission_drell_yan(oracles, cfgs):
 
 
 @pytest.mark.slow
-def test_fi_if_first_emission_h_event(oracles, cfgs):
+@RETAIN
+def test_fi_if_first_emission_h_event(oracles, cfgs, retain):
     o, pdf = oracles["nlo"], PDF(cfgs["nlo"]["pdf"])
     base = o.hard_events(0, 400, 9)
     pick = [e for e in range(400) if (base.flags[e] & records.FLAG_HEVENT) and base.pid[2, e] == 21
@@ -161,7 +167,7 @@ def test_fi_if_first_emission_h_event(oracles, cfgs):
     k = pick[0]
     n = 20000
     ev = replicate(base, k, n)
-    out = o.shower(ev, 13)
+    out = o.shower(ev, 13, nthreads=8, retain=retain)
     sqS = 13000.0
     pa = np.array([base.E[0, k], base.px[0, k], base.py[0, k], base.pz[0, k]])
     pb = np.array([base.E[1, k], base.px[1, k], base.py[1, k], base.pz[1, k]])
@@ -224,11 +230,12 @@ def test_fi_if_first_emission_h_event(oracles, cfgs):
     compare(out.t1, tgrid, delta)
 
 
-def test_no_violations_and_conservation(oracles):
+@RETAIN
+def test_no_violations_and_conservation(oracles, retain):
     for key, n in (("ee", 3000), ("lo", 1500), ("nlo", 1500)):
         o = oracles[key]
         ev = o.hard_events(0, n, 21)
-        out = o.shower(ev, 21)
+        out = o.shower(ev, 21, retain=retain)
         assert int(out.n_viol.sum()) == 0, key
         assert int((out.flags & ~np.uint32(records.FLAG_HEVENT)).sum()) == 0, key
         obs = o.observables(out)
@@ -249,14 +256,15 @@ def test_no_violations_and_conservation(oracles):
 
 
 @pytest.mark.slow
-def test_overestimate_scaling_invariance(cfgs):
+@RETAIN
+def test_overestimate_scaling_invariance(cfgs, retain):
     """Doubling every overestimate changes the random path, not the physics."""
     from oracle.pyoracle import Oracle
     o1, o2 = Oracle(cfgs["lo"], 1.0), Oracle(cfgs["lo"], 2.0)
     n = 12000
     ev = o1.hard_events(0, n, 4)
-    a = o1.observables(o1.shower(ev, 1))
-    b = o2.observables(o2.shower(ev, 2))
+    a = o1.observables(o1.shower(ev, 1, nthreads=8, retain=retain))
+    b = o2.observables(o2.shower(ev, 2, nthreads=8, retain=retain))
     for col, edges in ((0, np.array([0, 1, 2, 4, 7, 10, 15, 20, 30, 50, 80, 150, 1e9])),
                        (4, np.arange(-0.5, 6.5, 1.0)),
                        (9, np.arange(-0.5, 30.5, 2.0))):
@@ -265,3 +273,35 @@ def test_overestimate_scaling_invariance(cfgs):
         m = (ha + hb) > 0
         chi2 = (((ha - hb) ** 2)[m] / (ha + hb)[m]).sum() / m.sum()
         assert chi2 < 2.0, (col, chi2)
+
+
+@pytest.mark.slow
+def test_retained_trials_match_regenerated(oracles):
+    """The retained-trial competition (a losing channel keeps its trial) and
+    the paper's form (every channel draws again each cycle) are the same
+    Markov chain: on NLO inputs the two give the same distributions of the
+    number of emissions, the cycle count and the observables, while the
+    retained form needs about a quarter of the trials.  A retained form that
+    kept stale trials across an emission, or kept the winner's, would shift
+    these distributions."""
+    o = oracles["nlo"]
+    n = 40000
+    ev = o.hard_events(0, n, 2)
+    a = o.shower(ev, 3, nthreads=8)
+    b = o.shower(ev, 4, nthreads=8, retain=True)
+    assert b.n_trials.mean() < 0.35 * a.n_trials.mean()
+    for name, edges in (("n_accept", np.arange(-0.5, 40.5)), ("n_cycles", np.arange(0, 800, 20))):
+        ha, _ = np.histogram(getattr(a, name), edges)
+        hb, _ = np.histogram(getattr(b, name), edges)
+        m = (ha + hb) > 0
+        chi2 = (((ha - hb) ** 2)[m] / (ha + hb)[m]).sum() / m.sum()
+        assert chi2 < 1.6, (name, chi2)
+    oa, ob = o.observables(a), o.observables(b)
+    for col, lo, hi in ((0, 0.0, 60.0), (3, 0.0, 1.0), (4, -0.5, 6.5), (9, 3.5, 30.5)):
+        ha, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w)
+        ha2, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w ** 2)
+        hb, _ = np.histogram(ob[:, col], bins=28, range=(lo, hi), weights=ev.w)
+        hb2, _ = np.histogram(ob[:, col], bins=28, range=(lo, hi), weights=ev.w ** 2)
+        m = (ha2 + hb2) > 0
+        chi2 = np.sum((ha[m] - hb[m]) ** 2 / (ha2[m] + hb2[m])) / m.sum()
+        assert chi2 < 2.0, (col, chi2)  # p < 0.2 % at 28 degrees of freedom
