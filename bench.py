@@ -105,7 +105,7 @@ def learned_pipeline(G, binding, args, seed):
     G.mlp_init(seed + 10)
     t0 = time.perf_counter()
     hin = G.hard_events(LOG_ID0, args.log_events, seed, max_slots=8)
-    _, rows, cnt = G.shower_log(hin, seed, args.log_rows)
+    _, rows, cnt = G.shower_log(hin, seed, args.log_rows, retain=args.trials == "retain")
     torch.cuda.synchronize()
     rep["log_s"], rep["log_events"], rep["log_rows"] = time.perf_counter() - t0, args.log_events, int(rows.shape[0])
     del hin
@@ -195,6 +195,9 @@ def main():
     ap.add_argument("--log-rows", type=int, default=50_000_000)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=65536)
+    ap.add_argument("--trials", choices=["retain", "regenerate"], default="regenerate",
+                    help="retain: a losing channel keeps its trial scale (the same Markov chain, fewer draws); "
+                         "regenerate: every channel draws again each cycle")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
@@ -223,7 +226,7 @@ def main():
     n, K = args.events, args.steps
     G = binding.Gaps(cfg)
     kw = dict(block=args.block, compact_every=args.compact_every, waves_per_simd=args.waves_per_simd,
-              variant=args.variant)
+              variant=args.variant, retain=args.trials == "retain")
 
     # hard events of every step (ids k*n .. (k+1)*n-1); timed separately, not part of the metric
     t0 = time.perf_counter()
@@ -234,6 +237,8 @@ def main():
     batches = [(ins[k], outs[k], n) for k in range(K)]
     kernel = {1: "k_shower_lanes", 0: {0: "k_shower_wave", 2: "k_shower_wave", 3: "k_shower_wave3",
                                        4: "k_shower_wave4"}[args.waves_per_simd]}[args.variant]
+    if args.trials == "retain":
+        kernel = "k_shower_wave_rt"
 
     def summarise(r, mode):
         nfin = float(np.mean([o.n.double().mean().item() for o in outs]))
@@ -258,8 +263,9 @@ def main():
         ob = G.observables(outs[-1])
         w = ins[-1].w
         hs = []
-        for col, lo, hi in ((0, 0.0, 60.0), (3, 0.0, 1.0), (4, -0.5, 6.5)):
-            sw, sw2 = G.histogram(ob, w, col, lo, hi, 30)
+        # Z pT and phi* in 30 bins, the jet count one bin per integer
+        for col, lo, hi, nb in ((0, 0.0, 60.0, 30), (3, 0.0, 1.0, 30), (4, -0.5, 6.5, 7)):
+            sw, sw2 = G.histogram(ob, w, col, lo, hi, nb)
             hs.append((sw.cpu().numpy(), sw2.cpu().numpy()))
         return hs
 
@@ -309,7 +315,7 @@ def main():
         "config": {"workload": "pp_nlo_1m: NLO-matched Z production at 13 TeV (MC@NLO-style S/H events, "
                                "toy PDF grid 100x50), one step = one batch of 10^6 events with its own ids, "
                                "FP64 kinematics, up to 128 partons per event",
-                   "events_per_step": n, "mode": args.mode, "launch": args.launch,
+                   "events_per_step": n, "mode": args.mode, "trials": args.trials, "launch": args.launch,
                    "max_slots": workloads.MAX_SLOTS, "kernel": kernel, "block": args.block or "auto",
                    "compact_every": args.compact_every or 4},
         "roofline": roof,

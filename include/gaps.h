@@ -128,6 +128,18 @@ typedef struct {
     int tail_every;      /* wave kernel: once the queue is empty, repack live
                             events into the block's first waves every this
                             many cycles (0: off) */
+    int retain;          /* 0: every channel draws a new trial scale each
+                            cycle (the max-veto competition of section 2);
+                            1: retained trials, the same Markov chain with
+                            fewer draws: a channel that loses keeps its trial
+                            (still the first point of its own process below
+                            the new scale), so only the winner draws again
+                            after a veto or a null, every channel after an
+                            emission.  Channel entry 2i+side draws at cycle j
+                            with word (2i+side) mod 4 of block (id, j,
+                            (2i+side)/4); initial draws at cycle 0, redraws at
+                            the cycle after the one they replace.  Wave kernel
+                            at 2 waves per SIMD only (GAPS_EINVAL otherwise). */
 } gaps_params;
 
 /* Create a context: validates the configuration, uploads the PDF grid and

@@ -34,7 +34,7 @@ struct ScratchMem {
 gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   size_t per_lane = (size_t)slots * (4 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int8_t)) +
-                    (size_t)nch * (sizeof(uint32_t) + 9 * sizeof(double));
+                    (size_t)nch * (sizeof(uint32_t) + 10 * sizeof(double));
   size_t need = per_lane * (size_t)lanes + 256 * 26 + 64;
   if (need > m.bytes || m.S.lanes != lanes || m.S.max_slots != slots) {
     if (need > m.bytes) {
@@ -62,6 +62,7 @@ gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
     S.ctlim = (double*)take(cs * 8); S.clntlim = (double*)take(cs * 8); S.cinvc = (double*)take(cs * 8);
     S.cc = (double*)take(cs * 8); S.cs = (double*)take(cs * 8); S.czlo = (double*)take(cs * 8);
     S.comzhi = (double*)take(cs * 8); S.cI1 = (double*)take(cs * 8); S.cI2 = (double*)take(cs * 8);
+    S.ckey = (double*)take(cs * 8);
     S.queue = (unsigned long long*)take(64);
     if ((size_t)(p - (char*)m.mem) > m.bytes) return GAPS_ENOMEM;
   }
@@ -271,6 +272,7 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   }
   const int wps = P.waves_per_simd > 0 ? P.waves_per_simd : 2;
   if (wps < 2 || wps > 4) return GAPS_EINVAL;
+  if (P.retain != 0 && (P.retain != 1 || P.variant != 0 || wps != 2)) return GAPS_EINVAL;
   // the 2-wave kernel compacts its tail across up to 8 waves of a block
   const int max_block = (P.variant == 0 && wps == 2) ? 512 : 256;
   pl.block = P.block > 0 ? P.block : max_block;
@@ -278,6 +280,7 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   if (P.grid < 0 || P.compact_every < 0 || P.tail_every < 0) return GAPS_EINVAL;
   pl.dyn = P.variant == 1 ? 0 : (size_t)pl.block * gaps::kLaneStateBytes;
   pl.kern = P.variant == 1 ? (const void*)gaps::k_shower_lanes
+            : P.retain     ? (const void*)gaps::k_shower_wave_rt
             : wps == 2     ? (const void*)gaps::k_shower_wave
             : wps == 3     ? (const void*)gaps::k_shower_wave3
                            : (const void*)gaps::k_shower_wave4;

@@ -17,6 +17,7 @@ struct Scratch {
   // channel cache [2*max_slots][lanes]: trial data, then winner data
   uint32_t* cinfo;
   double *ctlim, *clntlim, *cinvc;
+  double* ckey;  // retained trials: the entry's pending trial ln t (-inf: none above the cutoff)
   double *cc, *cs, *czlo, *comzhi, *cI1, *cI2;
   unsigned long long* queue;  // work-queue counters
 };
@@ -51,6 +52,7 @@ __global__ void k_lo_max(const double* w, int n, double* out);
 __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o);
 __global__ void k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_shower_wave_rt(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave4(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 // a chunk of a stream's batch table, passed by value (fits the kernel-argument space)

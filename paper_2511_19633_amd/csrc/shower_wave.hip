@@ -27,6 +27,8 @@ namespace {
 // cache word: alive | type<<1 | heavy<<3 | spectator<<5 | eta bin<<13 | spectator eta bin<<19 |
 // learned cell<<25 (the cell whose 1/c the trial entry holds; 15: none yet)
 constexpr uint32_t kCellShift = 25u, kCellMask = 15u << kCellShift, kCellNone = 15u;
+// retained trials: the entry's pending trial is a null at its cell's lower edge
+constexpr uint32_t kNullBit = 1u << 29;
 __device__ __forceinline__ uint32_t pack(const Chan& ch) {
   return (uint32_t)ch.alive | ((uint32_t)ch.type << 1) | ((uint32_t)ch.heavy << 3) | ((uint32_t)ch.k << 5) |
          ((uint32_t)ch.ebin << 13) | ((uint32_t)ch.kbin << 19) | (kCellNone << kCellShift);
@@ -48,8 +50,8 @@ struct LaneState {
   double T, lnT, t1;
   uint32_t cycle, ntri, nacc, nviol, flags;
   int32_t n, maxtag;
-  uint32_t bits;  // loaded | stop << 1 | pending << 2 | rebuild << 3 | em_all << 4
-  int32_t emik;   // emitter | spectator << 16 of the emission awaiting its channel rebuild
+  uint32_t bits;  // loaded | stop << 1 | pending << 2 | rebuild << 3 | em_all << 4 | redraw << 5
+  int32_t emik;   // emitter | spectator << 8 of the emission awaiting its channel rebuild | rw << 16
 };
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
@@ -63,6 +65,18 @@ constexpr int kBuildRing = 128;
 struct BuildLds {
   uint32_t ring[kBuildRing];  // lane L | particle q << 6 | side << 14 | spectator k << 15
   uint32_t flags[64];
+  uint32_t count[64];         // retained trials: draws per lane's event in a draw pass
+};
+
+// LDS of one wave for the trial tournament: the winner of each lane's group
+// of four entries (bits: entry | exact << 9 | null << 10 | cell << 11 |
+// valid << 15) and its trial count.
+struct TrialCand {
+  double lo, hi, key, u, lnT, invc;
+  uint32_t bits, ntri;
+};
+struct TrialLds {
+  TrialCand c[64];
 };
 
 // set up the channel constants of up to 64 queued entries, one per lane
@@ -212,6 +226,55 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.nterm = n_terms(ch, C.nf);
 }
 
+// Retained trials: draw a new trial for cache entry c of the event in state
+// slot `slot` from the evolution scale (T, lnT), with random number u.  The key
+// ln t is stored in the entry (-inf: no trial above the cutoff) with its null
+// bit; in learned mode an initial-state entry of the incoming partons draws
+// against the constant of its scale's cell (refreshed here when the cell
+// changed), and a trial below the cell is a null at the cell's lower edge.
+// Returns whether a trial was drawn (the channel is open at this scale).
+__device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64_t slot, int c, uint32_t info,
+                                           double tl, double ltl, double ic, double u, double T, double lnT,
+                                           bool lrn) {
+  const int64_t oc = (int64_t)c * S.lanes + slot;
+  double key = -INFINITY;
+  bool isnull = false, tried = false;
+  if (info & 1u) {
+    const int type = (info >> 1) & 3u, heavy = (info >> 3) & 3u;
+    double tcut, lntcut, m2 = 0.0;
+    if (heavy == 1) { tcut = C.tch_c; lntcut = C.ln_tch_c; m2 = C.mc2; }
+    else if (heavy == 2) { tcut = C.tch_b; lntcut = C.ln_tch_b; m2 = C.mb2; }
+    else if (type == kFF) { tcut = C.t_cut; lntcut = C.ln_tc; }
+    else { tcut = C.tc_is; lntcut = C.ln_tcis; }
+    const double Tch = T < tl ? T : tl;
+    const double lnTch = lnT < ltl ? lnT : ltl;
+    if (Tch > tcut) {
+      tried = true;
+      double invc = ic, floor = -INFINITY;
+      if (lrn && c < 4 && (type == kIF || type == kII)) {
+        const int cell = cell_of(C, lnTch, floor);
+        if ((int)((info & kCellMask) >> kCellShift) != cell) {
+          const Rec R = Rec{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, 1, S.max_slots, slot};
+          const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cI1[oc],
+                                      S.cI2[oc], cell);
+          invc = 1.0 / ck;
+          S.cinvc[oc] = invc;
+          S.cc[oc] = ck;
+          info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+        }
+        if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
+      }
+      if (heavy) key = log(m2 + (Tch - m2) * exp(log(u) * invc));
+      else key = lnTch + log(u) * invc;
+      if (key < floor) { key = floor; isnull = true; }
+      if (key < lntcut) { key = -INFINITY; isnull = false; }
+    }
+    S.cinfo[oc] = isnull ? (info | kNullBit) : (info & ~kNullBit);
+  }
+  S.ckey[oc] = key;
+  return tried;
+}
+
 // batch of global queue index g: the last b with prefix[b] <= g
 __device__ __forceinline__ int batch_of(const ShowerArgs& A, int64_t g) {
   int lo = 0, hi = A.nbatch - 1;
@@ -225,12 +288,17 @@ __device__ __forceinline__ int batch_of(const ShowerArgs& A, int64_t g) {
 
 }  // namespace
 
+// RETAIN: the retained-trial form of the competition (a losing channel keeps
+// its trial; only the winner draws again after a veto or a null, every channel
+// after an emission); otherwise every channel draws again each cycle.
+template <bool RETAIN>
 __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_events& in1, const gaps_events& out1,
                                                  const Scratch& S, const ShowerArgs& A) {
   // the overestimate table, staged in LDS for the term loops
   __shared__ double s_bound[kNEnt * kNB];
   __shared__ int s_cnt[16], s_nexh;
   __shared__ BuildLds s_build[8];  // one per wave (blocks of at most 512 threads)
+  __shared__ TrialLds s_trial[8];
   extern __shared__ LaneState s_pool[];
   for (int q = threadIdx.x; q < kNEnt * kNB; q += blockDim.x) s_bound[q] = Cg.bound[q];
   if (threadIdx.x == 0) s_nexh = 0;
@@ -264,6 +332,9 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   // of the next iteration together with the refilled lanes
   bool rebuild = false, em_all = false;
   int em_i = 0, em_k = 0;
+  // retained trials: the last cycle's winner entry rw draws again
+  bool redraw = false;
+  int rw = 0;
   bool counted = false, tail = false;
   unsigned it_tail = 0;
 
@@ -329,22 +400,23 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           X.cycle = cycle; X.ntri = ntri; X.nacc = nacc; X.nviol = nviol; X.flags = flags;
           X.n = n; X.maxtag = maxtag;
           X.bits = (uint32_t)loaded | ((uint32_t)stop << 1) | ((uint32_t)pending << 2) | ((uint32_t)rebuild << 3) |
-                   ((uint32_t)em_all << 4);
-          X.emik = (em_i & 0xFFFF) | (em_k << 16);
+                   ((uint32_t)em_all << 4) | ((uint32_t)redraw << 5);
+          X.emik = (em_i & 0xFF) | ((em_k & 0xFF) << 8) | (rw << 16);
         }
         __syncthreads();
         const bool got = (int)threadIdx.x < total;
         active = false;
         pending = false;
         rebuild = false;
+        redraw = false;
         if (got) {
           const LaneState& X = s_pool[threadIdx.x];
           e = X.e; id = X.id; slot = X.slot; b = X.b; lrn = X.lrn != 0; T = X.T; lnT = X.lnT; t1 = X.t1;
           cycle = X.cycle; ntri = X.ntri; nacc = X.nacc; nviol = X.nviol; flags = X.flags;
           n = X.n; maxtag = X.maxtag;
           loaded = (X.bits & 1u) != 0; stop = (X.bits & 2u) != 0; pending = (X.bits & 4u) != 0;
-          rebuild = (X.bits & 8u) != 0; em_all = (X.bits & 16u) != 0;
-          em_i = X.emik & 0xFFFF; em_k = X.emik >> 16;
+          rebuild = (X.bits & 8u) != 0; em_all = (X.bits & 16u) != 0; redraw = (X.bits & 32u) != 0;
+          em_i = X.emik & 0xFF; em_k = (X.emik >> 8) & 0xFF; rw = X.emik >> 16;
           active = !pending;
           R = rec_of(S, slot);
         }
@@ -388,15 +460,84 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     // event before its first cycle; after an emission a non-finite momentum
     // (reported first) or a broken colour line stops the event (its cycle
     // was already counted).
+    const bool built = fresh || rebuild;
     {
-      const unsigned long long bm = __ballot(fresh || rebuild);
+      const unsigned long long bm = __ballot(built);
       if (bm) {
         uint32_t f = coop_build(W, s_build[wid], bm, n, slot, fresh || em_all, em_i, em_k);
         if (fresh) f &= fColour;
         if (f & fNaN) f = fNaN;
-        if ((fresh || rebuild) && f) { flags |= f; stop = true; }
+        if (built && f) { flags |= f; stop = true; }
         rebuild = false;
       }
+    }
+    if constexpr (RETAIN) {
+      // ---- retained trials: new draws for every entry of the events just
+      // built, and for the last winner of the others, from the current scale
+      // at the current cycle.  The groups of four entries that draw (one
+      // random block each) are spread over the wave, one per lane.
+      BuildLds& B = s_build[wid];
+      const bool all = built && active && !stop;
+      const bool one = !built && redraw && active && !stop;
+      const int nd = all ? (2 * n + 3) >> 2 : (one ? 1 : 0);
+      int incl = nd;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, (unsigned)o);
+        if (lane >= o) incl += v;
+      }
+      const int total = __shfl(incl, 63);
+      if (total > 0) {
+        B.count[lane] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        for (int g0 = 0; g0 < total; g0 += 64) {
+          const int g = g0 + lane;
+          int L = 0;
+#pragma unroll
+          for (int step = 32; step > 0; step >>= 1) {
+            const int v = __shfl(incl, L + step - 1);
+            if (v <= g) L += step;
+          }
+          L = L > 63 ? 63 : L;
+          const int64_t sL = __shfl(slot, L);
+          const int64_t idL = __shfl(id, L);
+          const uint32_t cyL = (uint32_t)__shfl((int)cycle, L);
+          const double TL = __shfl(T, L), lnTL = __shfl(lnT, L);
+          const int nL = __shfl(n, L), ndL = __shfl(nd, L), fL = __shfl(incl, L) - ndL;
+          const bool allL = __shfl((int)all, L) != 0, lrnL = __shfl((int)lrn, L) != 0;
+          const int rwL = __shfl(rw, L);
+          if (g < total) {
+            const int gi = allL ? g - fL : rwL >> 2;
+            const unsigned mask = allL ? 15u : 1u << (rwL & 3);
+            const int c0 = 4 * gi;
+            uint32_t inf[4];
+            double tl[4], ltl[4], ic[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int64_t oc = (int64_t)(c0 + j) * S.lanes + sL;
+              inf[j] = S.cinfo[oc];
+              tl[j] = S.ctlim[oc];
+              ltl[j] = S.clntlim[oc];
+              ic[j] = S.cinvc[oc];
+            }
+            double ub[4];
+            rng4(A.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)gi, ub);
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int c = c0 + j;
+              if (!((mask >> j) & 1u) || c >= 2 * nL) continue;
+              cnt += draw_entry(C, S, sL, c, inf[j], tl[j], ltl[j], ic[j], ub[j], TL, lnTL, lrnL) ? 1u : 0u;
+            }
+            if (cnt) atomicAdd(&B.count[L], cnt);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        ntri += B.count[lane];
+        // the owner reads its entries' keys and bits in the scan
+        __threadfence_block();
+      }
+      redraw = false;
     }
     if (act == 0ull) {
       if (!compact && exhausted) break;  // no tail mode: a drained wave just leaves
@@ -410,114 +551,242 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     bool done = false;
     if (active && stop) done = true;
     if (active && !done && cycle >= kMaxCycles) { flags |= fMaxCyc; done = true; }
-    if (active && !done) {
-      // Trial scales of every channel and the winner (largest key = ln t,
-      // ties to the lowest entry).  Each key is first bounded with the
-      // hardware single-precision log of u and a rigorous error margin; the
-      // double-precision log is taken only where the bounds cannot decide
-      // (overlapping candidates, the cutoff, a cell edge) and for the final
-      // winner, so the result is exactly that of evaluating every key in
-      // double precision.  In learned mode an initial-state channel of the
-      // incoming partons draws against its cell constant, and a trial below
-      // the cell is a null candidate at the cell's lower edge.
-      const uint32_t strm = lrn ? 1u : 0u;
-      int win = -1, wcell = 0;
-      bool wexact = false, wnull = false;
-      double wlo = 0.0, whi = 0.0, wkey = 0.0, wu = 0.5, wlnT = 0.0, winv = 0.0;
-      for (int c0 = 0; c0 < 2 * n; c0 += 4) {
-        uint32_t inf[4];
-        double tl[4], ltl[4], ic[4];
+    // Trial scales of every channel and the winner (largest key = ln t, ties
+    // to the lowest entry), for every lane that has a cycle to run.  Each key
+    // is first bounded with the hardware single-precision log of u and a
+    // rigorous error margin; the double-precision log is taken only where the
+    // bounds cannot decide (overlapping candidates, the cutoff, a cell edge)
+    // and for the final winner, so the result is exactly that of evaluating
+    // every key in double precision.  In learned mode an initial-state channel
+    // of the incoming partons draws against its cell constant, and a trial
+    // below the cell is a null candidate at the cell's lower edge.
+    //
+    // The work is spread over the whole wave: the events' groups of four
+    // entries (one random block each) are laid end to end and taken 64 at a
+    // time, one per lane, so that a lane whose event has few channels works on
+    // another event's groups instead of idling.  Each group yields its own
+    // winner; the owner lane of each event then merges its groups' winners in
+    // entry order with the same rule, which gives the same winner as one pass
+    // over all entries.
+    const bool trialing = active && !done;
+    const uint32_t strm = lrn ? 1u : 0u;
+    int win = -1, wcell = 0;
+    bool wexact = false, wnull = false;
+    double wlo = 0.0, whi = 0.0, wkey = RETAIN ? -INFINITY : 0.0, wu = 0.5, wlnT = 0.0, winv = 0.0;
+    if constexpr (RETAIN) {
+      // ---- retained trials: the winner is the largest pending trial, ties
+      // to the lowest entry.  The events' groups of four entries are spread
+      // over the wave, one per lane; each owner merges its groups in order.
+      TrialLds& TQ = s_trial[wid];
+      const int ng = trialing ? (2 * n + 3) >> 2 : 0;
+      int incl = ng;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int64_t oc = (int64_t)(c0 + j) * S.lanes + slot;
-          inf[j] = S.cinfo[oc];
-          tl[j] = S.ctlim[oc];
-          ltl[j] = S.clntlim[oc];
-          ic[j] = S.cinvc[oc];
-        }
-        if (!((inf[0] | inf[1] | inf[2] | inf[3]) & 1u)) continue;
-        double ub[4];
-        rng4(A.seed, strm, id, cycle, (uint32_t)c0 >> 2, ub);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = c0 + j;
-          const uint32_t info = inf[j];
-          if (c >= 2 * n || !(info & 1u)) continue;
-          const int type = (info >> 1) & 3u, heavy = (info >> 3) & 3u;
-          double tcut, lntcut, m2 = 0.0;
-          if (heavy == 1) { tcut = C.tch_c; lntcut = C.ln_tch_c; m2 = C.mc2; }
-          else if (heavy == 2) { tcut = C.tch_b; lntcut = C.ln_tch_b; m2 = C.mb2; }
-          else if (type == kFF) { tcut = C.t_cut; lntcut = C.ln_tc; }
-          else { tcut = C.tc_is; lntcut = C.ln_tcis; }
-          const double Tch = T < tl[j] ? T : tl[j];
-          const double lnTch = lnT < ltl[j] ? lnT : ltl[j];
-          if (!(Tch > tcut)) continue;
-          ntri += 1;
-          const double u = ub[j];
-          double invc = ic[j], floor = -INFINITY;
-          int cell = 0;
-          if (lrn && c < 4 && (type == kIF || type == kII)) {
-            cell = cell_of(C, lnTch, floor);
-            if ((int)((info & kCellMask) >> kCellShift) != cell) {
-              // the scale entered a new cell: that cell's constant replaces the
-              // entry's (1/c for the trials, c for the winner's term choice)
-              const int64_t oc = (int64_t)c * S.lanes + slot;
-              const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cI1[oc],
-                                          S.cI2[oc], cell);
-              invc = 1.0 / ck;
-              S.cinvc[oc] = invc;
-              S.cc[oc] = ck;
-              S.cinfo[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
-            }
-            if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
-          }
-          double lo, hi, key = 0.0;
-          bool exact, isnull = false;
-          if (heavy) {
-            key = log(m2 + (Tch - m2) * exp(log(u) * invc));
-            if (key < floor) { key = floor; isnull = true; }
-            if (key < lntcut) continue;
-            lo = hi = key;
-            exact = true;
-          } else {
-            const double lf = (double)__builtin_amdgcn_logf((float)u) * 0.69314718055994530942;
-            const double ka = lnTch + lf * invc;
-            const double err = invc * (fabs(lf) * 0x1p-17 + 0x1p-19) + 1e-12;
-            lo = ka - err;
-            hi = ka + err;
-            exact = false;
-            if (hi < floor) {
-              key = floor; lo = hi = key; exact = true; isnull = true;
-            } else if (lo < floor) {
-              key = lnTch + log(u) * invc;
-              if (key < floor) { key = floor; isnull = true; }
-              lo = hi = key;
-              exact = true;
-            }
-            if (hi < lntcut) continue;
-            if (lo < lntcut) {
-              key = lnTch + log(u) * invc;
-              if (key < lntcut) continue;
-              lo = hi = key;
-              exact = true;
-            }
-          }
-          if (win < 0) {
-            win = c; wlo = lo; whi = hi; wkey = key; wexact = exact; wu = u; wlnT = lnTch; winv = invc;
-            wnull = isnull; wcell = cell;
-            continue;
-          }
-          if (hi <= wlo) continue;
-          if (!(lo > whi)) {
-            // the bounds overlap: decide with exact keys (a null key is exact)
-            if (!wexact) { wkey = wlnT + log(wu) * winv; wlo = whi = wkey; wexact = true; }
-            if (!exact) { key = lnTch + log(u) * invc; lo = hi = key; exact = true; }
-            if (!(key > wkey)) continue;
-          }
-          win = c; wlo = lo; whi = hi; wkey = key; wexact = exact; wu = u; wlnT = lnTch; winv = invc;
-          wnull = isnull; wcell = cell;
-        }
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, (unsigned)o);
+        if (lane >= o) incl += v;
       }
+      const int total = __shfl(incl, 63);
+      const int first = incl - ng;
+      for (int g0 = 0; g0 < total; g0 += 64) {
+        const int g = g0 + lane;
+        int L = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const int v = __shfl(incl, L + step - 1);
+          if (v <= g) L += step;
+        }
+        L = L > 63 ? 63 : L;
+        const int64_t sL = __shfl(slot, L);
+        const int nL = __shfl(n, L), fL = __shfl(first, L);
+        double gk = -INFINITY;
+        int gc = 0;
+        if (g < total) {
+          const int c0 = 4 * (g - fL);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double k = S.ckey[(int64_t)(c0 + j) * S.lanes + sL];
+            if (c0 + j < 2 * nL && k > gk) { gk = k; gc = c0 + j; }
+          }
+        }
+        TQ.c[lane].key = gk;
+        TQ.c[lane].bits = (uint32_t)gc;
+        __builtin_amdgcn_wave_barrier();
+        if (trialing) {
+          const int kb = (first > g0 ? first : g0) - g0;
+          const int ke = (incl < g0 + 64 ? incl : g0 + 64) - g0;
+          for (int k = kb; k < ke; ++k) {
+            const double y = TQ.c[k].key;
+            if (y > wkey) { wkey = y; win = (int)TQ.c[k].bits; }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (trialing && win >= 0) {
+        const uint32_t info = S.cinfo[(int64_t)win * S.lanes + slot];
+        wnull = (info & kNullBit) != 0u;
+        wcell = (int)((info & kCellMask) >> kCellShift);
+      }
+      wexact = true;
+    } else {
+      TrialLds& TQ = s_trial[wid];
+      const int ng = trialing ? (2 * n + 3) >> 2 : 0;
+      int incl = ng;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, (unsigned)o);
+        if (lane >= o) incl += v;
+      }
+      const int total = __shfl(incl, 63);
+      const int first = incl - ng;
+      for (int g0 = 0; g0 < total; g0 += 64) {
+        const int g = g0 + lane;
+        int L = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const int v = __shfl(incl, L + step - 1);
+          if (v <= g) L += step;
+        }
+        L = L > 63 ? 63 : L;
+        const int64_t sL = __shfl(slot, L);
+        const int64_t idL = __shfl(id, L);
+        const uint32_t cyL = (uint32_t)__shfl((int)cycle, L);
+        const double TL = __shfl(T, L), lnTL = __shfl(lnT, L);
+        const int nL = __shfl(n, L), fL = __shfl(first, L);
+        const bool lrnL = __shfl((int)lrn, L) != 0;
+        // this lane's group: its winner (gw < 0: none) and trial count
+        int gw = -1, gcell = 0;
+        bool gexact = false, gnull = false;
+        double glo = 0.0, ghi = 0.0, gkey = 0.0, gu = 0.5, glnT = 0.0, ginv = 0.0;
+        uint32_t gtri = 0;
+        if (g < total) {
+          const int c0 = 4 * (g - fL);
+          uint32_t inf[4];
+          double tl[4], ltl[4], ic[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int64_t oc = (int64_t)(c0 + j) * S.lanes + sL;
+            inf[j] = S.cinfo[oc];
+            tl[j] = S.ctlim[oc];
+            ltl[j] = S.clntlim[oc];
+            ic[j] = S.cinvc[oc];
+          }
+          if ((inf[0] | inf[1] | inf[2] | inf[3]) & 1u) {
+            double ub[4];
+            rng4(A.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)c0 >> 2, ub);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int c = c0 + j;
+              const uint32_t info = inf[j];
+              if (c >= 2 * nL || !(info & 1u)) continue;
+              const int type = (info >> 1) & 3u, heavy = (info >> 3) & 3u;
+              double tcut, lntcut, m2 = 0.0;
+              if (heavy == 1) { tcut = C.tch_c; lntcut = C.ln_tch_c; m2 = C.mc2; }
+              else if (heavy == 2) { tcut = C.tch_b; lntcut = C.ln_tch_b; m2 = C.mb2; }
+              else if (type == kFF) { tcut = C.t_cut; lntcut = C.ln_tc; }
+              else { tcut = C.tc_is; lntcut = C.ln_tcis; }
+              const double Tch = TL < tl[j] ? TL : tl[j];
+              const double lnTch = lnTL < ltl[j] ? lnTL : ltl[j];
+              if (!(Tch > tcut)) continue;
+              gtri += 1;
+              const double u = ub[j];
+              double invc = ic[j], floor = -INFINITY;
+              int cell = 0;
+              if (lrnL && c < 4 && (type == kIF || type == kII)) {
+                cell = cell_of(C, lnTch, floor);
+                if ((int)((info & kCellMask) >> kCellShift) != cell) {
+                  // the scale entered a new cell: that cell's constant replaces the
+                  // entry's (1/c for the trials, c for the winner's term choice)
+                  const int64_t oc = (int64_t)c * S.lanes + sL;
+                  const Rec RL = rec_of(S, sL);
+                  const double ck = learned_c(C, type, RL.pid[RL.o(c >> 1)], (int)((info >> 13) & 0x3Fu),
+                                              S.cI1[oc], S.cI2[oc], cell);
+                  invc = 1.0 / ck;
+                  S.cinvc[oc] = invc;
+                  S.cc[oc] = ck;
+                  S.cinfo[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+                }
+                if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
+              }
+              double lo, hi, key = 0.0;
+              bool exact, isnull = false;
+              if (heavy) {
+                key = log(m2 + (Tch - m2) * exp(log(u) * invc));
+                if (key < floor) { key = floor; isnull = true; }
+                if (key < lntcut) continue;
+                lo = hi = key;
+                exact = true;
+              } else {
+                const double lf = (double)__builtin_amdgcn_logf((float)u) * 0.69314718055994530942;
+                const double ka = lnTch + lf * invc;
+                const double err = invc * (fabs(lf) * 0x1p-17 + 0x1p-19) + 1e-12;
+                lo = ka - err;
+                hi = ka + err;
+                exact = false;
+                if (hi < floor) {
+                  key = floor; lo = hi = key; exact = true; isnull = true;
+                } else if (lo < floor) {
+                  key = lnTch + log(u) * invc;
+                  if (key < floor) { key = floor; isnull = true; }
+                  lo = hi = key;
+                  exact = true;
+                }
+                if (hi < lntcut) continue;
+                if (lo < lntcut) {
+                  key = lnTch + log(u) * invc;
+                  if (key < lntcut) continue;
+                  lo = hi = key;
+                  exact = true;
+                }
+              }
+              if (gw >= 0) {
+                if (hi <= glo) continue;
+                if (!(lo > ghi)) {
+                  // the bounds overlap: decide with exact keys (a null key is exact)
+                  if (!gexact) { gkey = glnT + log(gu) * ginv; glo = ghi = gkey; gexact = true; }
+                  if (!exact) { key = lnTch + log(u) * invc; lo = hi = key; exact = true; }
+                  if (!(key > gkey)) continue;
+                }
+              }
+              gw = c; glo = lo; ghi = hi; gkey = key; gexact = exact; gu = u; glnT = lnTch; ginv = invc;
+              gnull = isnull; gcell = cell;
+            }
+          }
+        }
+        TrialCand& X = TQ.c[lane];
+        X.lo = glo; X.hi = ghi; X.key = gkey; X.u = gu; X.lnT = glnT; X.invc = ginv;
+        X.bits = (uint32_t)(gw & 0x1FF) | ((uint32_t)gexact << 9) | ((uint32_t)gnull << 10) |
+                 ((uint32_t)gcell << 11) | ((uint32_t)(gw >= 0) << 15);
+        X.ntri = gtri;
+        __builtin_amdgcn_wave_barrier();
+        // owner: merge the winners of this event's groups in this pass, in order
+        if (trialing) {
+          const int kb = (first > g0 ? first : g0) - g0;
+          const int ke = (incl < g0 + 64 ? incl : g0 + 64) - g0;
+          for (int k = kb; k < ke; ++k) {
+            const TrialCand& Y = TQ.c[k];
+            ntri += Y.ntri;
+            const uint32_t yb = Y.bits;
+            if (!(yb & (1u << 15))) continue;
+            double lo = Y.lo, hi = Y.hi, key = Y.key;
+            bool exact = (yb >> 9) & 1u;
+            if (win >= 0) {
+              if (hi <= wlo) continue;
+              if (!(lo > whi)) {
+                if (!wexact) { wkey = wlnT + log(wu) * winv; wlo = whi = wkey; wexact = true; }
+                if (!exact) { key = Y.lnT + log(Y.u) * Y.invc; lo = hi = key; exact = true; }
+                if (!(key > wkey)) continue;
+              }
+            }
+            win = (int)(yb & 0x1FFu); wlo = lo; whi = hi; wkey = key; wexact = exact; wu = Y.u; wlnT = Y.lnT;
+            winv = Y.invc; wnull = (yb >> 10) & 1u; wcell = (int)((yb >> 11) & 15u);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      // learned mode: cell constants written by one lane are read by the owner
+      if (learned_mode) __threadfence_block();
+    }
+    if (trialing) {
       double best = -INFINITY;
       if (win >= 0) best = wexact ? wkey : wlnT + log(wu) * winv;
       if (win < 0) {
@@ -528,6 +797,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         lnT = best;
         cycle += 1;
         st_null += 1;
+        if constexpr (RETAIN) { redraw = true; rw = win; }
       } else {
         const double t = exp(best);
         Chan ch;
@@ -585,6 +855,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             T = t;
             lnT = best;
             cycle += 1;
+            // retained trials: after a veto only the winner draws again
+            if constexpr (RETAIN) if (!rebuild) { redraw = true; rw = win; }
           }
         }
       }
@@ -644,15 +916,19 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
 // waves hide more latency, fewer registers per wave spill more.
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 k_shower_wave(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
-  shower_wave_body(C, in, out, S, A);
+  shower_wave_body<false>(C, in, out, S, A);
+}
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+k_shower_wave_rt(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
+  shower_wave_body<true>(C, in, out, S, A);
 }
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_shower_wave3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
-  shower_wave_body(C, in, out, S, A);
+  shower_wave_body<false>(C, in, out, S, A);
 }
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_shower_wave4(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
-  shower_wave_body(C, in, out, S, A);
+  shower_wave_body<false>(C, in, out, S, A);
 }
 
 }  // namespace gaps

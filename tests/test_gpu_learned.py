@@ -292,14 +292,11 @@ def test_trained_bound_gains_over_plain(G):
     assert tl < tp
     ap, al = out_p.n_accept.double().cpu().numpy(), out_l.n_accept.double().cpu().numpy()
     assert abs(ap.mean() - al.mean()) < 5 * math.sqrt(ap.var() * 2 / n)
+    from tests.histcheck import chi2_compare
     op, ol = G.observables(out_p).cpu().numpy(), G.observables(out_l).cpu().numpy()
     w = gin.w.cpu().numpy()
-    for col, lo, hi in ((0, 0.0, 60.0), (4, -0.5, 6.5), (9, 3.5, 30.5)):
-        a, _ = np.histogram(op[:, col], bins=28, range=(lo, hi), weights=w)
-        a2, _ = np.histogram(op[:, col], bins=28, range=(lo, hi), weights=w * w)
-        b, _ = np.histogram(ol[:, col], bins=28, range=(lo, hi), weights=w)
-        b2, _ = np.histogram(ol[:, col], bins=28, range=(lo, hi), weights=w * w)
-        m = (a2 + b2) > 0
-        chi = np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m])) / m.sum()
-        say(f"  column {col}: chi2/ndf {chi:.3f}")
-        assert chi < 1.5
+    # Z pT (28 bins), jet count and parton count (one bin per integer)
+    for col, edges in ((0, np.linspace(0.0, 60.0, 29)), (4, np.arange(-0.5, 7.0)), (9, np.arange(3.5, 31.0))):
+        chi, ndf, p = chi2_compare(op[:, col], ol[:, col], w, w, edges)
+        say(f"  column {col}: chi2/ndf {chi / ndf:.3f} (ndf {ndf}, p {p:.3g})")
+        assert p > 1e-3
