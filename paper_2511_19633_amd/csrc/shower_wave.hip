@@ -36,6 +36,14 @@ __device__ __forceinline__ uint32_t pack(const Chan& ch) {
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
+// element j of a four-element register array, by selects (no private-memory
+// indexing), so that a per-entry loop can stay rolled and its body is emitted
+// once rather than four times
+template <typename T>
+__device__ __forceinline__ T pick4(const T (&a)[4], int j) {
+  return j == 0 ? a[0] : (j == 1 ? a[1] : (j == 2 ? a[2] : a[3]));
+}
+
 struct WaveCtx {
   const Cfg& C;
   const Scratch& S;
@@ -50,8 +58,8 @@ struct LaneState {
   double T, lnT, t1;
   uint32_t cycle, ntri, nacc, nviol, flags;
   int32_t n, maxtag;
-  uint32_t bits;  // loaded | stop << 1 | pending << 2 | rebuild << 3 | em_all << 4 | redraw << 5
-  int32_t emik;   // emitter | spectator << 8 of the emission awaiting its channel rebuild | rw << 16
+  uint32_t bits;  // loaded | stop << 1 | pending << 2 | rebuild << 3 | em_all << 4
+  int32_t emik;   // emitter | spectator << 8 of the emission awaiting its channel rebuild
 };
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
@@ -67,164 +75,6 @@ struct BuildLds {
   uint32_t flags[64];
   uint32_t count[64];         // retained trials: draws per lane's event in a draw pass
 };
-
-// LDS of one wave for the trial tournament: the winner of each lane's group
-// of four entries (bits: entry | exact << 9 | null << 10 | cell << 11 |
-// valid << 15) and its trial count.
-struct TrialCand {
-  double lo, hi, key, u, lnT, invc;
-  uint32_t bits, ntri;
-};
-struct TrialLds {
-  TrialCand c[64];
-};
-
-// set up the channel constants of up to 64 queued entries, one per lane
-__device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int head, int cnt, int64_t myslot) {
-  const bool valid = W.lane < cnt;
-  const uint32_t it = valid ? B.ring[(head + W.lane) & (kBuildRing - 1)] : 0u;
-  const int L = (int)(it & 63u);
-  const int64_t slot = __shfl(myslot, L);
-  if (!valid) return;
-  const int q = (int)((it >> 6) & 0xFFu), side = (int)((it >> 14) & 1u), k = (int)(it >> 15);
-  const Rec R = rec_of(W.S, slot);
-  Chan ch;
-  chan_setup(W.C, R, q, side, k, ch);
-  const int64_t oc = (int64_t)(2 * q + side) * W.S.lanes + slot;
-  W.S.cinfo[oc] = pack(ch);
-  W.S.ctlim[oc] = ch.tlim;
-  W.S.clntlim[oc] = ch.lntlim;
-  W.S.cinvc[oc] = ch.invc;
-  W.S.cc[oc] = ch.c;
-  W.S.cs[oc] = ch.s;
-  W.S.czlo[oc] = ch.zlo;
-  W.S.comzhi[oc] = ch.omzhi;
-  W.S.cI1[oc] = ch.I1;
-  W.S.cI2[oc] = ch.I2;
-}
-
-// Cooperative (re)build of the channel entries of the events whose lanes are
-// set in `mask`.  The entries (slot, side) of all these events are laid end to
-// end and the wave walks them 64 at a time: each lane finds the colour partner
-// of one entry by scanning its event's colour tags.  Only entries whose
-// constants can have changed are set up again: all of them after a refill
-// (`all`) or an initial-initial emission (whose recoil boosts every
-// final-state momentum); otherwise those of emitter `ei`, spectator `ek` and
-// the new parton n - 1, entries whose partner is one of those three, and
-// entries whose partner changed.  The others are bitwise what a full set-up
-// would write, because their inputs did not change.  Entries to set up are
-// queued in LDS and set up 64 at a time, one per lane.  Returns (per lane)
-// whether this lane's own event has a broken colour line or a non-finite
-// momentum.
-__device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long mask, int n, int64_t myslot,
-                               bool all, int ei, int ek) {
-  __threadfence_block();
-  const bool mine = (mask >> W.lane) & 1ull;
-  const int ne = mine ? 2 * n : 0;
-  int incl = ne;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int v = __shfl_up(incl, (unsigned)o);
-    if (W.lane >= o) incl += v;
-  }
-  const int total = __shfl(incl, 63);
-  if (mine) B.flags[W.lane] = 0u;
-  __builtin_amdgcn_wave_barrier();
-  int head = 0, cnt = 0;
-  for (int g0 = 0; g0 < total; g0 += 64) {
-    const int g = g0 + W.lane;
-    // owner lane: the number of lanes whose inclusive prefix is <= g
-    int L = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1) {
-      const int v = __shfl(incl, L + step - 1);
-      if (v <= g) L += step;
-    }
-    L = L > 63 ? 63 : L;
-    const int nL = __shfl(n, L);
-    const int firstL = __shfl(incl, L) - 2 * nL;
-    const int64_t slot = __shfl(myslot, L);
-    const bool allL = __shfl((int)all, L) != 0;
-    const int iL = __shfl(ei, L), kL = __shfl(ek, L);
-    bool queue = false;
-    int q = 0, side = 0, k = -1;
-    if (g < total) {
-      const int e = g - firstL;
-      q = e >> 1;
-      side = e & 1;
-      const Rec R = rec_of(W.S, slot);
-      const int tag = side == 0 ? R.effc(q) : R.effa(q);
-      if (tag != 0) {
-        for (int j = 0; j < nL; ++j) {
-          if (j == q) continue;
-          if ((side == 0 ? R.effa(j) : R.effc(j)) == tag) { k = j; break; }
-        }
-        if (k < 0) atomicOr(&B.flags[L], fColour);
-      }
-      if (side == 0) {
-        const int64_t o = R.o(q);
-        if (!(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o])))
-          atomicOr(&B.flags[L], fNaN);
-      }
-      const int64_t oc = (int64_t)e * W.S.lanes + slot;
-      const uint32_t old = W.S.cinfo[oc];
-      const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
-      const int jL = nL - 1;
-      const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
-      if (dirty) {
-        if (k < 0) W.S.cinfo[oc] = 0u;
-        else queue = true;
-      }
-    }
-    const unsigned long long qm = __ballot(queue);
-    if (queue) {
-      const int r = __popcll(qm & lanemask_lt(W.lane));
-      B.ring[(head + cnt + r) & (kBuildRing - 1)] =
-          (uint32_t)L | ((uint32_t)q << 6) | ((uint32_t)side << 14) | ((uint32_t)k << 15);
-    }
-    cnt += __popcll(qm);
-    __builtin_amdgcn_wave_barrier();
-    if (cnt >= 64) {
-      build_setup(W, B, head, 64, myslot);
-      head = (head + 64) & (kBuildRing - 1);
-      cnt -= 64;
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  if (cnt > 0) build_setup(W, B, head, cnt, myslot);
-  __builtin_amdgcn_wave_barrier();
-  __threadfence_block();
-  return mine ? B.flags[W.lane] : 0u;
-}
-
-// rebuild the channel description of cache entry c from the cache and record
-__device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, const Rec& R, int64_t slot, int c,
-                                                Chan& ch) {
-  const int64_t oc = (int64_t)c * S.lanes + slot;
-  uint32_t info = S.cinfo[oc];
-  ch.alive = 1;
-  ch.i = c >> 1;
-  ch.side = c & 1;
-  ch.type = (info >> 1) & 3u;
-  ch.heavy = (info >> 3) & 3u;
-  ch.k = (info >> 5) & 0xFFu;
-  ch.ebin = (info >> 13) & 0x3Fu;
-  ch.kbin = (info >> 19) & 0x3Fu;
-  ch.m2 = ch.heavy == 1 ? C.mc2 : (ch.heavy == 2 ? C.mb2 : 0.0);
-  ch.pidi = R.pid[R.o(ch.i)];
-  ch.pidk = R.pid[R.o(ch.k)];
-  ch.s = S.cs[oc];
-  ch.c = S.cc[oc];
-  ch.zlo = S.czlo[oc];
-  ch.omzhi = S.comzhi[oc];
-  ch.zhi = 1.0 - ch.omzhi;
-  ch.omzlo = 1.0 - ch.zlo;
-  ch.I1 = S.cI1[oc];
-  ch.I2 = S.cI2[oc];
-  ch.eta = (ch.type == kIF || ch.type == kII) ? 2.0 * R.E[R.o(ch.i)] / C.sqrt_s : 0.0;
-  ch.etak = (ch.type == kFI || ch.type == kII) ? 2.0 * R.E[R.o(ch.k)] / C.sqrt_s : 0.0;
-  ch.nterm = n_terms(ch, C.nf);
-}
 
 // Retained trials: draw a new trial for cache entry c of the event in state
 // slot `slot` from the evolution scale (T, lnT), with random number u.  The key
@@ -273,6 +123,242 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
   }
   S.ckey[oc] = key;
   return tried;
+}
+
+// LDS of one wave for the trial tournament: the winner of each lane's group
+// of four entries (bits: entry | exact << 9 | null << 10 | cell << 11 |
+// valid << 15) and its trial count.
+struct TrialCand {
+  double lo, hi, key, u, lnT, invc;
+  uint32_t bits, ntri;
+};
+struct TrialLds {
+  TrialCand c[64];
+};
+
+// Retained trials: what a lane's event needs for its entries to draw new
+// trials while they are built (scale, cycle, id, stream).
+struct DrawState {
+  double T, lnT;
+  int64_t id;
+  uint32_t cycle;
+  bool lrn;
+  uint64_t seed;
+};
+
+// set up the channel constants of up to 64 queued entries, one per lane
+// (DRAW: and draw each entry's first trial from its event's scale)
+template <bool DRAW>
+__device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int head, int cnt, int64_t myslot,
+                                            const DrawState& D) {
+  const bool valid = W.lane < cnt;
+  const uint32_t it = valid ? B.ring[(head + W.lane) & (kBuildRing - 1)] : 0u;
+  const int L = (int)(it & 63u);
+  const int64_t slot = __shfl(myslot, L);
+  double TL = 0.0, lnTL = 0.0;
+  int64_t idL = 0;
+  uint32_t cyL = 0;
+  bool lrnL = false;
+  if constexpr (DRAW) {
+    TL = __shfl(D.T, L); lnTL = __shfl(D.lnT, L); idL = __shfl(D.id, L);
+    cyL = (uint32_t)__shfl((int)D.cycle, L); lrnL = __shfl((int)D.lrn, L) != 0;
+  }
+  if (!valid) return;
+  const int q = (int)((it >> 6) & 0xFFu), side = (int)((it >> 14) & 1u), k = (int)(it >> 15);
+  const Rec R = rec_of(W.S, slot);
+  Chan ch;
+  chan_setup(W.C, R, q, side, k, ch);
+  const int c = 2 * q + side;
+  const int64_t oc = (int64_t)c * W.S.lanes + slot;
+  W.S.cinfo[oc] = pack(ch);
+  W.S.ctlim[oc] = ch.tlim;
+  W.S.clntlim[oc] = ch.lntlim;
+  W.S.cinvc[oc] = ch.invc;
+  W.S.cc[oc] = ch.c;
+  W.S.cs[oc] = ch.s;
+  W.S.czlo[oc] = ch.zlo;
+  W.S.comzhi[oc] = ch.omzhi;
+  W.S.cI1[oc] = ch.I1;
+  W.S.cI2[oc] = ch.I2;
+  if constexpr (DRAW) {
+    double ub[4];
+    rng4(D.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)c >> 2, ub);
+    if (draw_entry(W.C, W.S, slot, c, pack(ch), ch.tlim, ch.lntlim, ch.invc, pick4(ub, c & 3), TL, lnTL, lrnL))
+      atomicAdd(&B.count[L], 1u);
+  }
+}
+
+// Cooperative (re)build of the channel entries of the events whose lanes are
+// set in `mask`.  The entries (slot, side) of all these events are laid end to
+// end and the wave walks them 64 at a time: each lane finds the colour partner
+// of one entry by scanning its event's colour tags.  Only entries whose
+// constants can have changed are set up again: all of them after a refill
+// (`all`) or an initial-initial emission (whose recoil boosts every
+// final-state momentum); otherwise those of emitter `ei`, spectator `ek` and
+// the new parton n - 1, entries whose partner is one of those three, and
+// entries whose partner changed.  The others are bitwise what a full set-up
+// would write, because their inputs did not change.  Entries to set up are
+// queued in LDS and set up 64 at a time, one per lane.  Returns (per lane)
+// whether this lane's own event has a broken colour line or a non-finite
+// momentum.  DRAW (retained trials): every entry of these events also draws a
+// new trial from its event's scale at its current cycle, an unchanged entry
+// in the partner pass and a changed one right after its set-up; `drawn` gets
+// the number of trials drawn for this lane's event.
+template <bool DRAW>
+__device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long mask, int n, int64_t myslot,
+                               bool all, int ei, int ek, const DrawState& D, uint32_t& drawn) {
+  __threadfence_block();
+  const bool mine = (mask >> W.lane) & 1ull;
+  const int ne = mine ? 2 * n : 0;
+  int incl = ne;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, (unsigned)o);
+    if (W.lane >= o) incl += v;
+  }
+  const int total = __shfl(incl, 63);
+  if (mine) B.flags[W.lane] = 0u;
+  if constexpr (DRAW) B.count[W.lane] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  int head = 0, cnt = 0;
+  for (int g0 = 0; g0 < total; g0 += 64) {
+    const int g = g0 + W.lane;
+    // owner lane: the number of lanes whose inclusive prefix is <= g
+    int L = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const int v = __shfl(incl, L + step - 1);
+      if (v <= g) L += step;
+    }
+    L = L > 63 ? 63 : L;
+    const int nL = __shfl(n, L);
+    const int firstL = __shfl(incl, L) - 2 * nL;
+    const int64_t slot = __shfl(myslot, L);
+    const bool allL = __shfl((int)all, L) != 0;
+    const int iL = __shfl(ei, L), kL = __shfl(ek, L);
+    double TL = 0.0, lnTL = 0.0;
+    int64_t idL = 0;
+    uint32_t cyL = 0;
+    bool lrnL = false;
+    if constexpr (DRAW) {
+      TL = __shfl(D.T, L); lnTL = __shfl(D.lnT, L); idL = __shfl(D.id, L);
+      cyL = (uint32_t)__shfl((int)D.cycle, L); lrnL = __shfl((int)D.lrn, L) != 0;
+    }
+    bool queue = false;
+    int q = 0, side = 0, k = -1;
+    if (g < total) {
+      const int e = g - firstL;
+      q = e >> 1;
+      side = e & 1;
+      const Rec R = rec_of(W.S, slot);
+      const int tag = side == 0 ? R.effc(q) : R.effa(q);
+      if (tag != 0) {
+        // the partner: the first other parton whose opposite tag matches,
+        // looked up eight partons at a time (independent loads)
+        for (int j0 = 0; j0 < nL && k < 0; j0 += 8) {
+          int oth[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u;
+            oth[u] = j < nL ? (side == 0 ? R.effa(j) : R.effc(j)) : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u;
+            if (k < 0 && j < nL && j != q && oth[u] == tag) k = j;
+          }
+        }
+        if (k < 0) atomicOr(&B.flags[L], fColour);
+      }
+      if (side == 0) {
+        const int64_t o = R.o(q);
+        if (!(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o])))
+          atomicOr(&B.flags[L], fNaN);
+      }
+      const int64_t oc = (int64_t)e * W.S.lanes + slot;
+      const uint32_t old = W.S.cinfo[oc];
+      const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
+      const int jL = nL - 1;
+      const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
+      if (dirty) {
+        if (k < 0) W.S.cinfo[oc] = 0u;
+        else queue = true;
+      }
+      if constexpr (DRAW) {
+        if (k < 0) {
+          W.S.ckey[oc] = -INFINITY;
+        } else if (!dirty) {
+          // an unchanged entry draws from its cached constants
+          double ub[4];
+          rng4(D.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)e >> 2, ub);
+          if (draw_entry(W.C, W.S, slot, e, old, W.S.ctlim[oc], W.S.clntlim[oc], W.S.cinvc[oc], pick4(ub, e & 3),
+                         TL, lnTL, lrnL))
+            atomicAdd(&B.count[L], 1u);
+        }
+      }
+    }
+    const unsigned long long qm = __ballot(queue);
+    if (queue) {
+      const int r = __popcll(qm & lanemask_lt(W.lane));
+      B.ring[(head + cnt + r) & (kBuildRing - 1)] =
+          (uint32_t)L | ((uint32_t)q << 6) | ((uint32_t)side << 14) | ((uint32_t)k << 15);
+    }
+    cnt += __popcll(qm);
+    __builtin_amdgcn_wave_barrier();
+    if (cnt >= 64) {
+      build_setup<DRAW>(W, B, head, 64, myslot, D);
+      head = (head + 64) & (kBuildRing - 1);
+      cnt -= 64;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (cnt > 0) build_setup<DRAW>(W, B, head, cnt, myslot, D);
+  __builtin_amdgcn_wave_barrier();
+  __threadfence_block();
+  if constexpr (DRAW) drawn = mine ? B.count[W.lane] : 0u;
+  return mine ? B.flags[W.lane] : 0u;
+}
+
+// rebuild the channel description of cache entry c from the cache and record
+__device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, const Rec& R, int64_t slot, int c,
+                                                Chan& ch) {
+  const int64_t oc = (int64_t)c * S.lanes + slot;
+  uint32_t info = S.cinfo[oc];
+  ch.alive = 1;
+  ch.i = c >> 1;
+  ch.side = c & 1;
+  ch.type = (info >> 1) & 3u;
+  ch.heavy = (info >> 3) & 3u;
+  ch.k = (info >> 5) & 0xFFu;
+  ch.ebin = (info >> 13) & 0x3Fu;
+  ch.kbin = (info >> 19) & 0x3Fu;
+  ch.m2 = ch.heavy == 1 ? C.mc2 : (ch.heavy == 2 ? C.mb2 : 0.0);
+  ch.pidi = R.pid[R.o(ch.i)];
+  ch.pidk = R.pid[R.o(ch.k)];
+  ch.s = S.cs[oc];
+  ch.c = S.cc[oc];
+  ch.zlo = S.czlo[oc];
+  ch.omzhi = S.comzhi[oc];
+  ch.zhi = 1.0 - ch.omzhi;
+  ch.omzlo = 1.0 - ch.zlo;
+  ch.I1 = S.cI1[oc];
+  ch.I2 = S.cI2[oc];
+  ch.eta = (ch.type == kIF || ch.type == kII) ? 2.0 * R.E[R.o(ch.i)] / C.sqrt_s : 0.0;
+  ch.etak = (ch.type == kFI || ch.type == kII) ? 2.0 * R.E[R.o(ch.k)] / C.sqrt_s : 0.0;
+  ch.nterm = n_terms(ch, C.nf);
+}
+
+// Retained trials: the winner entry c of a vetoed or null cycle draws again,
+// in its own lane, at the new cycle from the new scale (T, lnT).
+__device__ __forceinline__ bool redraw_winner(const Cfg& C, const Scratch& S, uint64_t seed, uint32_t strm,
+                                              int64_t id, uint32_t cycle, int64_t slot, int c, double T, double lnT,
+                                              bool lrn) {
+  const int64_t oc = (int64_t)c * S.lanes + slot;
+  const uint32_t info = S.cinfo[oc];
+  const double tl = S.ctlim[oc], ltl = S.clntlim[oc], ic = S.cinvc[oc];
+  double ub[4];
+  rng4(seed, strm, id, cycle, (uint32_t)c >> 2, ub);
+  return draw_entry(C, S, slot, c, info, tl, ltl, ic, pick4(ub, c & 3), T, lnT, lrn);
 }
 
 // batch of global queue index g: the last b with prefix[b] <= g
@@ -332,9 +418,6 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   // of the next iteration together with the refilled lanes
   bool rebuild = false, em_all = false;
   int em_i = 0, em_k = 0;
-  // retained trials: the last cycle's winner entry rw draws again
-  bool redraw = false;
-  int rw = 0;
   bool counted = false, tail = false;
   unsigned it_tail = 0;
 
@@ -400,23 +483,22 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           X.cycle = cycle; X.ntri = ntri; X.nacc = nacc; X.nviol = nviol; X.flags = flags;
           X.n = n; X.maxtag = maxtag;
           X.bits = (uint32_t)loaded | ((uint32_t)stop << 1) | ((uint32_t)pending << 2) | ((uint32_t)rebuild << 3) |
-                   ((uint32_t)em_all << 4) | ((uint32_t)redraw << 5);
-          X.emik = (em_i & 0xFF) | ((em_k & 0xFF) << 8) | (rw << 16);
+                   ((uint32_t)em_all << 4);
+          X.emik = (em_i & 0xFF) | ((em_k & 0xFF) << 8);
         }
         __syncthreads();
         const bool got = (int)threadIdx.x < total;
         active = false;
         pending = false;
         rebuild = false;
-        redraw = false;
         if (got) {
           const LaneState& X = s_pool[threadIdx.x];
           e = X.e; id = X.id; slot = X.slot; b = X.b; lrn = X.lrn != 0; T = X.T; lnT = X.lnT; t1 = X.t1;
           cycle = X.cycle; ntri = X.ntri; nacc = X.nacc; nviol = X.nviol; flags = X.flags;
           n = X.n; maxtag = X.maxtag;
           loaded = (X.bits & 1u) != 0; stop = (X.bits & 2u) != 0; pending = (X.bits & 4u) != 0;
-          rebuild = (X.bits & 8u) != 0; em_all = (X.bits & 16u) != 0; redraw = (X.bits & 32u) != 0;
-          em_i = X.emik & 0xFF; em_k = (X.emik >> 8) & 0xFF; rw = X.emik >> 16;
+          rebuild = (X.bits & 8u) != 0; em_all = (X.bits & 16u) != 0;
+          em_i = X.emik & 0xFF; em_k = (X.emik >> 8) & 0xFF;
           active = !pending;
           R = rec_of(S, slot);
         }
@@ -464,80 +546,16 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     {
       const unsigned long long bm = __ballot(built);
       if (bm) {
-        uint32_t f = coop_build(W, s_build[wid], bm, n, slot, fresh || em_all, em_i, em_k);
+        const DrawState D{T, lnT, id, cycle, lrn, A.seed};
+        uint32_t drawn = 0;
+        uint32_t f = coop_build<RETAIN>(W, s_build[wid], bm, n, slot, fresh || em_all, em_i, em_k, D, drawn);
         if (fresh) f &= fColour;
         if (f & fNaN) f = fNaN;
+        // an event stopped here draws nothing (its draws are not counted)
         if (built && f) { flags |= f; stop = true; }
+        else ntri += drawn;
         rebuild = false;
       }
-    }
-    if constexpr (RETAIN) {
-      // ---- retained trials: new draws for every entry of the events just
-      // built, and for the last winner of the others, from the current scale
-      // at the current cycle.  The groups of four entries that draw (one
-      // random block each) are spread over the wave, one per lane.
-      BuildLds& B = s_build[wid];
-      const bool all = built && active && !stop;
-      const bool one = !built && redraw && active && !stop;
-      const int nd = all ? (2 * n + 3) >> 2 : (one ? 1 : 0);
-      int incl = nd;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, (unsigned)o);
-        if (lane >= o) incl += v;
-      }
-      const int total = __shfl(incl, 63);
-      if (total > 0) {
-        B.count[lane] = 0u;
-        __builtin_amdgcn_wave_barrier();
-        for (int g0 = 0; g0 < total; g0 += 64) {
-          const int g = g0 + lane;
-          int L = 0;
-#pragma unroll
-          for (int step = 32; step > 0; step >>= 1) {
-            const int v = __shfl(incl, L + step - 1);
-            if (v <= g) L += step;
-          }
-          L = L > 63 ? 63 : L;
-          const int64_t sL = __shfl(slot, L);
-          const int64_t idL = __shfl(id, L);
-          const uint32_t cyL = (uint32_t)__shfl((int)cycle, L);
-          const double TL = __shfl(T, L), lnTL = __shfl(lnT, L);
-          const int nL = __shfl(n, L), ndL = __shfl(nd, L), fL = __shfl(incl, L) - ndL;
-          const bool allL = __shfl((int)all, L) != 0, lrnL = __shfl((int)lrn, L) != 0;
-          const int rwL = __shfl(rw, L);
-          if (g < total) {
-            const int gi = allL ? g - fL : rwL >> 2;
-            const unsigned mask = allL ? 15u : 1u << (rwL & 3);
-            const int c0 = 4 * gi;
-            uint32_t inf[4];
-            double tl[4], ltl[4], ic[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int64_t oc = (int64_t)(c0 + j) * S.lanes + sL;
-              inf[j] = S.cinfo[oc];
-              tl[j] = S.ctlim[oc];
-              ltl[j] = S.clntlim[oc];
-              ic[j] = S.cinvc[oc];
-            }
-            double ub[4];
-            rng4(A.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)gi, ub);
-            uint32_t cnt = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int c = c0 + j;
-              if (!((mask >> j) & 1u) || c >= 2 * nL) continue;
-              cnt += draw_entry(C, S, sL, c, inf[j], tl[j], ltl[j], ic[j], ub[j], TL, lnTL, lrnL) ? 1u : 0u;
-            }
-            if (cnt) atomicAdd(&B.count[L], cnt);
-          }
-        }
-        __builtin_amdgcn_wave_barrier();
-        ntri += B.count[lane];
-        // the owner reads its entries' keys and bits in the scan
-        __threadfence_block();
-      }
-      redraw = false;
     }
     if (act == 0ull) {
       if (!compact && exhausted) break;  // no tail mode: a drained wave just leaves
@@ -676,7 +694,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const int c = c0 + j;
-              const uint32_t info = inf[j];
+              const uint32_t info = pick4(inf, j);
               if (c >= 2 * nL || !(info & 1u)) continue;
               const int type = (info >> 1) & 3u, heavy = (info >> 3) & 3u;
               double tcut, lntcut, m2 = 0.0;
@@ -684,12 +702,12 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
               else if (heavy == 2) { tcut = C.tch_b; lntcut = C.ln_tch_b; m2 = C.mb2; }
               else if (type == kFF) { tcut = C.t_cut; lntcut = C.ln_tc; }
               else { tcut = C.tc_is; lntcut = C.ln_tcis; }
-              const double Tch = TL < tl[j] ? TL : tl[j];
-              const double lnTch = lnTL < ltl[j] ? lnTL : ltl[j];
+              const double Tch = TL < pick4(tl, j) ? TL : pick4(tl, j);
+              const double lnTch = lnTL < pick4(ltl, j) ? lnTL : pick4(ltl, j);
               if (!(Tch > tcut)) continue;
               gtri += 1;
-              const double u = ub[j];
-              double invc = ic[j], floor = -INFINITY;
+              const double u = pick4(ub, j);
+              double invc = pick4(ic, j), floor = -INFINITY;
               int cell = 0;
               if (lrnL && c < 4 && (type == kIF || type == kII)) {
                 cell = cell_of(C, lnTch, floor);
@@ -786,6 +804,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       // learned mode: cell constants written by one lane are read by the owner
       if (learned_mode) __threadfence_block();
     }
+    bool rdw = false;  // retained trials: the winner of a vetoed or null cycle draws again
     if (trialing) {
       double best = -INFINITY;
       if (win >= 0) best = wexact ? wkey : wlnT + log(wu) * winv;
@@ -797,7 +816,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         lnT = best;
         cycle += 1;
         st_null += 1;
-        if constexpr (RETAIN) { redraw = true; rw = win; }
+        rdw = true;
       } else {
         const double t = exp(best);
         Chan ch;
@@ -856,11 +875,13 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             lnT = best;
             cycle += 1;
             // retained trials: after a veto only the winner draws again
-            if constexpr (RETAIN) if (!rebuild) { redraw = true; rw = win; }
+            rdw = !rebuild;
           }
         }
       }
     }
+    if constexpr (RETAIN)
+      if (rdw) ntri += redraw_winner(C, S, A.seed, strm, id, cycle, slot, win, T, lnT, lrn) ? 1u : 0u;
     // ---- finished events: write out and free the lane
     if (active && done) {
       const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
