@@ -73,8 +73,32 @@ constexpr int kBuildRing = 128;
 struct BuildLds {
   uint32_t ring[kBuildRing];  // lane L | particle q << 6 | side << 14 | spectator k << 15
   uint32_t flags[64];
-  uint32_t count[64];         // retained trials: draws per lane's event in a draw pass
+  uint32_t count[64];         // retained trials: draws per lane's event in a build
+  int tag[64];                // refill: the largest colour tag of each lane's new event
 };
+
+// Owner lane of item g when every lane L contributes items
+// [incl_L - count_L, incl_L) (incl: inclusive prefix of the counts over the
+// wave): the number of lanes whose inclusive prefix is <= g.
+__device__ __forceinline__ int owner_of(int incl, int g) {
+  int L = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1) {
+    const int v = __shfl(incl, L + step - 1);
+    if (v <= g) L += step;
+  }
+  return L > 63 ? 63 : L;
+}
+
+// inclusive prefix sum of v over the wave
+__device__ __forceinline__ int wave_incl(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, (unsigned)o);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
 
 // Retained trials: draw a new trial for cache entry c of the event in state
 // slot `slot` from the evolution scale (T, lnT), with random number u.  The key
@@ -421,7 +445,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   bool counted = false, tail = false;
   unsigned it_tail = 0;
 
-  // load event e of batch b into this lane's record; false if it does not fit
+  // load the header of event e of batch b; false if the event does not fit
+  // this lane's record
   auto load = [&](bool learned) -> bool {
     const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
     n = in.n[e];
@@ -441,14 +466,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       return false;
     }
     loaded = true;
-    for (int q = 0; q < n; ++q) {
-      const int64_t k = (int64_t)q * in.cap + e, o = R.o(q);
-      R.E[o] = in.E[k]; R.px[o] = in.px[k]; R.py[o] = in.py[k]; R.pz[o] = in.pz[k];
-      R.pid[o] = in.pid[k]; R.col[o] = in.col[k]; R.acol[o] = in.acol[k]; R.st[o] = in.status[k];
-      maxtag = in.col[k] > maxtag ? in.col[k] : maxtag;
-      maxtag = in.acol[k] > maxtag ? in.acol[k] : maxtag;
-    }
-    return true;
+    return true;  // the partons are copied by the whole wave (below)
   };
 
   for (unsigned it = 0;; ++it) {
@@ -536,6 +554,33 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         since = 0;
       }
       act = __ballot(active);
+      // the refilled events' partons into their records, one parton per lane,
+      // and the largest colour tag of each event
+      const int np = fresh ? n : 0;
+      const int incl = wave_incl(np, lane);
+      const int total = __shfl(incl, 63);
+      if (total > 0) {
+        BuildLds& B = s_build[wid];
+        B.tag[lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int g0 = 0; g0 < total; g0 += 64) {
+          const int g = g0 + lane;
+          const int L = owner_of(incl, g);
+          const int nL = __shfl(n, L), fL = __shfl(incl, L) - nL, bL = __shfl(b, L);
+          const int64_t sL = __shfl(slot, L), eL = __shfl(e, L);
+          if (g < total) {
+            const gaps_events& in = A.nbatch > 0 ? A.batches[bL].in : in1;
+            const int q = g - fL;
+            const int64_t k = (int64_t)q * in.cap + eL, o = rec_of(S, sL).o(q);
+            const int cl = in.col[k], al = in.acol[k];
+            S.E[o] = in.E[k]; S.px[o] = in.px[k]; S.py[o] = in.py[k]; S.pz[o] = in.pz[k];
+            S.pid[o] = in.pid[k]; S.col[o] = cl; S.acol[o] = al; S.st[o] = in.status[k];
+            atomicMax(&B.tag[L], cl > al ? cl : al);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (fresh) maxtag = B.tag[lane];
+      }
     }
     // ---- one cooperative channel build for the refilled lanes and the lanes
     // that emitted in the last cycle.  A broken colour line stops a refilled
@@ -883,6 +928,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     if constexpr (RETAIN)
       if (rdw) ntri += redraw_winner(C, S, A.seed, strm, id, cycle, slot, win, T, lnT, lrn) ? 1u : 0u;
     // ---- finished events: write out and free the lane
+    const bool wout = active && done && loaded;  // partons copied by the wave below
     if (active && done) {
       const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
       const gaps_events& out = A.nbatch > 0 ? A.batches[b].out : out1;
@@ -894,11 +940,6 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       out.t_start[e] = in.t_start[e];
       if (fits) {
         out.n[e] = n;
-        for (int q = 0; q < n; ++q) {
-          const int64_t k = (int64_t)q * co + e, o = R.o(q);
-          out.E[k] = R.E[o]; out.px[k] = R.px[o]; out.py[k] = R.py[o]; out.pz[k] = R.pz[o];
-          out.pid[k] = R.pid[o]; out.col[k] = R.col[o]; out.acol[k] = R.acol[o]; out.status[k] = R.st[o];
-        }
       } else {
         out.n[e] = nin;
         for (int q = 0; q < nin && q < out.max_slots && q < in.max_slots; ++q) {
@@ -916,6 +957,25 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (out.t1) out.t1[e] = t1;
       st_cyc += cycle; st_tri += ntri; st_acc += nacc; st_viol += nviol;
       active = false;
+    }
+    {
+      // finished events' partons to their outputs, one parton per lane
+      const int np = wout ? n : 0;
+      const int incl = wave_incl(np, lane);
+      const int total = __shfl(incl, 63);
+      for (int g0 = 0; g0 < total; g0 += 64) {
+        const int g = g0 + lane;
+        const int L = owner_of(incl, g);
+        const int nL = __shfl(n, L), fL = __shfl(incl, L) - nL, bL = __shfl(b, L);
+        const int64_t sL = __shfl(slot, L), eL = __shfl(e, L);
+        if (g < total) {
+          const gaps_events& out = A.nbatch > 0 ? A.batches[bL].out : out1;
+          const int q = g - fL;
+          const int64_t k = (int64_t)q * out.cap + eL, o = rec_of(S, sL).o(q);
+          out.E[k] = S.E[o]; out.px[k] = S.px[o]; out.py[k] = S.py[o]; out.pz[k] = S.pz[o];
+          out.pid[k] = S.pid[o]; out.col[k] = S.col[o]; out.acol[k] = S.acol[o]; out.status[k] = S.st[o];
+        }
+      }
     }
     since += 1;
   }
