@@ -18,6 +18,8 @@ struct Scratch {
   uint32_t* cinfo;
   double *ctlim, *clntlim, *cinvc;
   double* ckey;  // retained trials: the entry's pending trial ln t (-inf: none above the cutoff)
+  double *ceta, *cetak;  // momentum fractions 2E/sqrt(S) of an incoming emitter and spectator (0: outgoing)
+  uint32_t* cpid;        // flavours of emitter and spectator (int8 each)
   double *cc, *cs, *czlo, *comzhi, *cI1, *cI2;
   unsigned long long* queue;  // work-queue counters
 };

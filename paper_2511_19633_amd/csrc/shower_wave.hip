@@ -204,6 +204,9 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   W.S.comzhi[oc] = ch.omzhi;
   W.S.cI1[oc] = ch.I1;
   W.S.cI2[oc] = ch.I2;
+  W.S.ceta[oc] = ch.eta;
+  W.S.cetak[oc] = ch.etak;
+  W.S.cpid[oc] = (uint32_t)(ch.pidi & 0xFF) | ((uint32_t)(ch.pidk & 0xFF) << 8);
   if constexpr (DRAW) {
     double ub[4];
     rng4(D.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)c >> 2, ub);
@@ -357,8 +360,9 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.ebin = (info >> 13) & 0x3Fu;
   ch.kbin = (info >> 19) & 0x3Fu;
   ch.m2 = ch.heavy == 1 ? C.mc2 : (ch.heavy == 2 ? C.mb2 : 0.0);
-  ch.pidi = R.pid[R.o(ch.i)];
-  ch.pidk = R.pid[R.o(ch.k)];
+  const uint32_t pk = S.cpid[oc];
+  ch.pidi = (int)(int8_t)(pk & 0xFFu);
+  ch.pidk = (int)(int8_t)((pk >> 8) & 0xFFu);
   ch.s = S.cs[oc];
   ch.c = S.cc[oc];
   ch.zlo = S.czlo[oc];
@@ -367,19 +371,17 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.omzlo = 1.0 - ch.zlo;
   ch.I1 = S.cI1[oc];
   ch.I2 = S.cI2[oc];
-  ch.eta = (ch.type == kIF || ch.type == kII) ? 2.0 * R.E[R.o(ch.i)] / C.sqrt_s : 0.0;
-  ch.etak = (ch.type == kFI || ch.type == kII) ? 2.0 * R.E[R.o(ch.k)] / C.sqrt_s : 0.0;
+  ch.eta = S.ceta[oc];
+  ch.etak = S.cetak[oc];
   ch.nterm = n_terms(ch, C.nf);
 }
 
 // Retained trials: the winner entry c of a vetoed or null cycle draws again,
 // in its own lane, at the new cycle from the new scale (T, lnT).
+// info, tl, ltl, ic: the entry's cache word and trial constants.
 __device__ __forceinline__ bool redraw_winner(const Cfg& C, const Scratch& S, uint64_t seed, uint32_t strm,
-                                              int64_t id, uint32_t cycle, int64_t slot, int c, double T, double lnT,
-                                              bool lrn) {
-  const int64_t oc = (int64_t)c * S.lanes + slot;
-  const uint32_t info = S.cinfo[oc];
-  const double tl = S.ctlim[oc], ltl = S.clntlim[oc], ic = S.cinvc[oc];
+                                              int64_t id, uint32_t cycle, int64_t slot, int c, uint32_t info,
+                                              double tl, double ltl, double ic, double T, double lnT, bool lrn) {
   double ub[4];
   rng4(seed, strm, id, cycle, (uint32_t)c >> 2, ub);
   return draw_entry(C, S, slot, c, info, tl, ltl, ic, pick4(ub, c & 3), T, lnT, lrn);
@@ -636,6 +638,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     int win = -1, wcell = 0;
     bool wexact = false, wnull = false;
     double wlo = 0.0, whi = 0.0, wkey = RETAIN ? -INFINITY : 0.0, wu = 0.5, wlnT = 0.0, winv = 0.0;
+    uint32_t rinfo = 0u;
+    double rtl = 0.0, rltl = 0.0, ric = 0.0;
     if constexpr (RETAIN) {
       // ---- retained trials: the winner is the largest pending trial, ties
       // to the lowest entry.  The events' groups of four entries are spread
@@ -685,9 +689,15 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         __builtin_amdgcn_wave_barrier();
       }
       if (trialing && win >= 0) {
-        const uint32_t info = S.cinfo[(int64_t)win * S.lanes + slot];
-        wnull = (info & kNullBit) != 0u;
-        wcell = (int)((info & kCellMask) >> kCellShift);
+        // the winner's entry: null and cell bits now, trial constants for its
+        // redraw after a veto (loaded together, one memory round trip)
+        const int64_t ow = (int64_t)win * S.lanes + slot;
+        rinfo = S.cinfo[ow];
+        rtl = S.ctlim[ow];
+        rltl = S.clntlim[ow];
+        ric = S.cinvc[ow];
+        wnull = (rinfo & kNullBit) != 0u;
+        wcell = (int)((rinfo & kCellMask) >> kCellShift);
       }
       wexact = true;
     } else {
@@ -926,7 +936,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       }
     }
     if constexpr (RETAIN)
-      if (rdw) ntri += redraw_winner(C, S, A.seed, strm, id, cycle, slot, win, T, lnT, lrn) ? 1u : 0u;
+      if (rdw) ntri += redraw_winner(C, S, A.seed, strm, id, cycle, slot, win, rinfo, rtl, rltl, ric, T, lnT, lrn) ? 1u : 0u;
     // ---- finished events: write out and free the lane
     const bool wout = active && done && loaded;  // partons copied by the wave below
     if (active && done) {
