@@ -134,8 +134,12 @@ typedef struct {
                             fewer draws: a channel that loses keeps its trial
                             (still the first point of its own process below
                             the new scale), so only the winner draws again
-                            after a veto or a null, every channel after an
-                            emission.  Channel entry 2i+side draws at cycle j
+                            after a veto or a null; after an emission only
+                            the channels whose process changed (emitter or
+                            spectator among the emission's emitter, spectator
+                            and new parton, a new spectator, or every channel
+                            after an initial-initial emission, whose recoil
+                            boosts the final state).  Channel entry 2i+side draws at cycle j
                             with word (2i+side) mod 4 of block (id, j,
                             (2i+side)/4); initial draws at cycle 0, redraws at
                             the cycle after the one they replace.  Wave kernel

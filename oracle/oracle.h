@@ -109,12 +109,16 @@ typedef struct {
      * channel's trial scale is the first point below the current scale of its
      * own Poisson process of intensity c/t; a channel that loses a cycle keeps
      * its trial, which is still that process's first point below the new
-     * scale, so only the winner draws again after a veto or a null (and every
-     * channel after an emission, which changes the channel list).  Same
-     * distribution as redrawing every channel each cycle; different use of
-     * the random numbers: channel entry 2i+side draws at cycle j with word
-     * (2i+side) mod 4 of block (id, j, (2i+side)/4), the first draws at cycle
-     * 0 and the redraws at the cycle that follows the one they replace. */
+     * scale, so only the winner draws again after a veto or a null.  After an
+     * emission a channel keeps its trial only when its process is unchanged:
+     * the same spectator, and neither its emitter nor its spectator is the
+     * emitter, the spectator or the new parton of the emission (whose recoil
+     * is local); after an initial-initial emission, which boosts every
+     * final-state parton, every channel draws again.  Same distribution as
+     * redrawing every channel each cycle; different use of the random
+     * numbers: channel entry 2i+side draws at cycle j with word (2i+side) mod
+     * 4 of block (id, j, (2i+side)/4), the first draws at cycle 0 and the
+     * redraws at the cycle that follows the one they replace. */
     int retain;
 } or_opts;
 

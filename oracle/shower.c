@@ -592,8 +592,9 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
     uint32_t ncyc = 0, ntri = 0, nacc = 0, nviol = 0;
     int nch = 0;
     /* retained-trial form: the pending trial of every channel */
-    static _Thread_local double key[OR_MAXCH];
+    static _Thread_local double key[OR_MAXCH], okey[2 * OR_MAXM];
     static _Thread_local int knull[OR_MAXCH], kcell[OR_MAXCH];
+    static _Thread_local int okspec[2 * OR_MAXM], onull[2 * OR_MAXM], ocell[2 * OR_MAXM];
     if (ev->n > M) flags |= OR_F_OVERFLOW;
     else if (build_channels(S, ev, ch, &nch) < 0) flags |= OR_F_COLOUR;
     else {
@@ -686,10 +687,21 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
                 log_trial(L, t, C->eta, z, tm->ent, v.wn);
             if (lch && v.ok && v.w > 1.0) return 1; /* the learned bound failed */
             if (v.ok && v.w > 1.0) { nviol += 1; flags |= OR_F_VIOL; }
-            int emitted = 0;
+            int emitted = 0, e_i = C->i, e_k = C->k, e_all = C->type == T_II;
             if (v.ok && u[3] < v.w) {
                 if (ev->n + 1 > M) { flags |= OR_F_OVERFLOW; break; }
                 emitted = 1;
+                if (retain) {
+                    /* the pending trial and spectator of every entry 2i+side */
+                    for (int q = 0; q < 2 * ev->n; ++q) okspec[q] = -1;
+                    for (int c = 0; c < nch; ++c) {
+                        int q = 2 * ch[c].i + ch[c].side;
+                        okspec[q] = ch[c].k;
+                        okey[q] = key[c];
+                        onull[q] = knull[c];
+                        ocell[q] = kcell[c];
+                    }
+                }
                 emit(S, ev, C, tm, z, omz, &v, phi);
                 nacc += 1;
                 if (t1 == 0.0) t1 = t;
@@ -701,12 +713,32 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
             T = t;
             lnT = best;
             cycle += 1;
-            if (retain) {
-                /* after an emission every channel draws again from the new
-                 * scale; after a veto only the winner does */
-                for (int c = emitted ? 0 : win; c < (emitted ? nch : win + 1); ++c)
-                    key[c] = draw_trial(S, &ch[c], T, lnT, seed, stream, id, cycle, learned, Lt, &ntri,
-                                        &knull[c], &kcell[c]);
+            if (retain && !emitted) {
+                /* after a veto only the winner draws again */
+                key[win] = draw_trial(S, &ch[win], T, lnT, seed, stream, id, cycle, learned, Lt, &ntri,
+                                      &knull[win], &kcell[win]);
+            } else if (retain) {
+                /* after an emission a channel keeps its trial when its process
+                 * is unchanged: same spectator, and neither its emitter nor its
+                 * spectator is the emitter, the spectator or the new parton of
+                 * the emission, whose recoil is local (an initial-initial
+                 * emission boosts every final-state parton, so then every
+                 * channel draws again) */
+                const int j = ev->n - 1;
+                for (int c = 0; c < nch; ++c) {
+                    const chan_t* D = &ch[c];
+                    const int q = 2 * D->i + D->side;
+                    const int kept = !e_all && q < 2 * j && okspec[q] == D->k && D->i != e_i && D->i != e_k &&
+                                     D->i != j && D->k != e_i && D->k != e_k && D->k != j;
+                    if (kept) {
+                        key[c] = okey[q];
+                        knull[c] = onull[q];
+                        kcell[c] = ocell[q];
+                    } else {
+                        key[c] = draw_trial(S, D, T, lnT, seed, stream, id, cycle, learned, Lt, &ntri, &knull[c],
+                                            &kcell[c]);
+                    }
+                }
             }
         }
         ncyc = cycle;

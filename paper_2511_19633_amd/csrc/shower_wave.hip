@@ -227,10 +227,10 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
 // would write, because their inputs did not change.  Entries to set up are
 // queued in LDS and set up 64 at a time, one per lane.  Returns (per lane)
 // whether this lane's own event has a broken colour line or a non-finite
-// momentum.  DRAW (retained trials): every entry of these events also draws a
-// new trial from its event's scale at its current cycle, an unchanged entry
-// in the partner pass and a changed one right after its set-up; `drawn` gets
-// the number of trials drawn for this lane's event.
+// momentum.  DRAW (retained trials): every entry that is set up also draws a
+// new trial from its event's scale at its current cycle; an unchanged entry
+// keeps its pending trial (its overestimate process is unchanged).  `drawn`
+// gets the number of trials drawn for this lane's event.
 template <bool DRAW>
 __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long mask, int n, int64_t myslot,
                                bool all, int ei, int ek, const DrawState& D, uint32_t& drawn) {
@@ -263,14 +263,6 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
     const int64_t slot = __shfl(myslot, L);
     const bool allL = __shfl((int)all, L) != 0;
     const int iL = __shfl(ei, L), kL = __shfl(ek, L);
-    double TL = 0.0, lnTL = 0.0;
-    int64_t idL = 0;
-    uint32_t cyL = 0;
-    bool lrnL = false;
-    if constexpr (DRAW) {
-      TL = __shfl(D.T, L); lnTL = __shfl(D.lnT, L); idL = __shfl(D.id, L);
-      cyL = (uint32_t)__shfl((int)D.cycle, L); lrnL = __shfl((int)D.lrn, L) != 0;
-    }
     bool queue = false;
     int q = 0, side = 0, k = -1;
     if (g < total) {
@@ -311,18 +303,10 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
         if (k < 0) W.S.cinfo[oc] = 0u;
         else queue = true;
       }
-      if constexpr (DRAW) {
-        if (k < 0) {
-          W.S.ckey[oc] = -INFINITY;
-        } else if (!dirty) {
-          // an unchanged entry draws from its cached constants
-          double ub[4];
-          rng4(D.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)e >> 2, ub);
-          if (draw_entry(W.C, W.S, slot, e, old, W.S.ctlim[oc], W.S.clntlim[oc], W.S.cinvc[oc], pick4(ub, e & 3),
-                         TL, lnTL, lrnL))
-            atomicAdd(&B.count[L], 1u);
-        }
-      }
+      // retained trials: an unchanged entry keeps its pending trial (its
+      // process is unchanged); an entry without a partner has none
+      if constexpr (DRAW)
+        if (k < 0) W.S.ckey[oc] = -INFINITY;
     }
     const unsigned long long qm = __ballot(queue);
     if (queue) {
