@@ -14,6 +14,12 @@ training, calibration, tabulation; reported under "learned"), then the same
 batches are showered plain and learned; `value` is the learned shower and the
 plain one is reported beside it.
 
+--trials retain (default) runs the competition of the veto algorithm in its
+retained-trial form (a losing channel keeps its trial scale; the same Markov
+chain with fewer draws); the same batches are then also timed with every
+channel redrawn each cycle, the paper's form, and reported under
+"paper_form".
+
 Prints one JSON line.  Extra objects:
   roofline      the shower kernel against the FP64 vector peak, with the
                 algorithmic operation count of the launches that were timed
@@ -47,16 +53,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, n_sample, seed):
+def cpu_baseline(cfg, n_sample, seed, retain):
     from oracle.pyoracle import Oracle
     threads = min(16, os.cpu_count() or 1)
     o = Oracle(cfg)
     ev = o.hard_events(0, n_sample, seed)
     t0 = time.perf_counter()
-    o.shower(ev, seed, nthreads=threads)
+    o.shower(ev, seed, nthreads=threads, retain=retain)
     dt = time.perf_counter() - t0
+    form = "retained trials" if retain else "every channel redrawn each cycle"
     return {"value": n_sample / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_sample} NLO pp->Z event ids (seed {seed}), shower only, "
+            "sample": f"first {n_sample} NLO pp->Z event ids (seed {seed}), plain shower ({form}), "
                       f"{threads} threads over contiguous id ranges, {dt:.2f} s wall"}
 
 
@@ -195,9 +202,12 @@ def main():
     ap.add_argument("--log-rows", type=int, default=50_000_000)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=65536)
-    ap.add_argument("--trials", choices=["retain", "regenerate"], default="regenerate",
+    ap.add_argument("--trials", choices=["retain", "regenerate"], default="retain",
                     help="retain: a losing channel keeps its trial scale (the same Markov chain, fewer draws); "
                          "regenerate: every channel draws again each cycle")
+    ap.add_argument("--no-paper-form", action="store_true",
+                    help="with --trials retain: skip timing the same batches with every channel redrawn each "
+                         "cycle (the paper's form of the competition), reported under \"paper_form\"")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
@@ -240,7 +250,7 @@ def main():
     if args.trials == "retain":
         kernel = "k_shower_wave_rt"
 
-    def summarise(r, mode):
+    def summarise(r, mode, kname=None):
         nfin = float(np.mean([o.n.double().mean().item() for o in outs]))
         flags = torch.cat([o.flags.to(torch.int64) for o in outs])
         overflow = int(((flags & 1) != 0).sum().item())
@@ -250,10 +260,11 @@ def main():
         ops = (st[1] * OPS_TRIAL + st[0] * OPS_WINNER +
                st[2] * (OPS_ACCEPT_BASE + OPS_ACCEPT_PER_PARTON * 0.5 * nfin)) / r["launches"]
         achieved = ops / mean_launch_s / 1e12
-        tr = stored_traffic(kernel, mode)
+        kname = kname or kernel
+        tr = stored_traffic(kname, mode)
         traffic = None if tr is None else tr["bytes_per_event"] * nev_launch
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel,
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kname,
                 "launch_ms": mean_launch_s * 1e3, "events_per_launch": nev_launch, "ops_per_launch": ops,
                 "hbm_gbs": None if traffic is None else traffic / mean_launch_s / 1e9}
         return (r["events"] / r["wall_s"], r["wall_s"] * 1e3 / K, roof,
@@ -298,6 +309,20 @@ def main():
                                     unhandled_bound_violations=unhandled)
     else:
         value, ms_per_step, roof, stats_main = v_plain, ms_plain, roof_plain, st_plain
+    if args.trials == "retain" and not args.no_paper_form and args.variant == 0:
+        # the same batches with every channel redrawn each cycle (same Markov chain)
+        kw_p = dict(kw, retain=False)
+        kname_p = {0: "k_shower_wave", 2: "k_shower_wave", 3: "k_shower_wave3",
+                   4: "k_shower_wave4"}[args.waves_per_simd]
+        pf = {"kernel": kname_p}
+        for md, nm in ((binding.MODE_PLAIN, "plain"), (binding.MODE_LEARNED, "learned")):
+            if md == binding.MODE_LEARNED and args.mode != "learned":
+                continue
+            r = timed_stream(G, binding, batches, seed, args, kw_p, md)
+            v, ms, rf, st = summarise(r, nm, kname_p)
+            log(f"paper form {nm}: {v:.4g} events/s")
+            pf[nm] = {"value": v, "ms_per_step": ms, "roofline": rf, "shower_stats": st}
+        out_extra["paper_form"] = pf
 
     out = {
         "metric": "showered events/sec, NLO pp→Z 13 TeV, 1 MI355X; plain vs learned-proposal",
@@ -326,7 +351,7 @@ def main():
     out.update(out_extra)
     if not args.no_cpu:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, seed)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, seed, args.trials == "retain")
     print(json.dumps(out))
 
 

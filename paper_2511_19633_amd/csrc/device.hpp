@@ -30,6 +30,8 @@ constexpr int kNIS = 64;
 constexpr int kNTB = 8;
 
 constexpr int kMaxSlots = 256;
+// most overestimate terms of a channel: an initial-state gluon, 1 + 2 nf (nf <= 5)
+constexpr int kMaxTerms = 11;
 constexpr uint32_t kMaxCycles = 2000000u;
 
 enum : int { kFF = 0, kFI = 1, kIF = 2, kII = 3 };
@@ -397,19 +399,34 @@ __device__ __forceinline__ double learned_R(const Cfg& C, int ent, int ebin, int
 __device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
   const bool ii = type == kII;
-  double c = 0.0;
+  // every term's constant first (independent loads), then the sum in order
+  double R[kMaxTerms];
+  int nt;
   if (pidi == 21) {
-    c += af * learned_R(C, ent_s1(famC, 0), ebin, k) * I1;
-    for (int m = 1; m <= 2 * C.nf; ++m) {
-      const int a = m <= C.nf ? m : -(m - C.nf);
-      const int T = pdf_tab(a);
-      c += af * learned_R(C, ii ? ent_s3(famD, T) : ent_s1(famD, T), ebin, k) * I2;
+    nt = 1 + 2 * C.nf;
+    R[0] = learned_R(C, ent_s1(famC, 0), ebin, k);
+#pragma unroll
+    for (int m = 1; m < kMaxTerms; ++m) {
+      R[m] = 0.0;
+      if (m < nt) {
+        const int a = m <= C.nf ? m : -(m - C.nf);
+        const int T = pdf_tab(a);
+        R[m] = learned_R(C, ii ? ent_s3(famD, T) : ent_s1(famD, T), ebin, k);
+      }
     }
   } else {
+    nt = 2;
     const int T = pdf_tab(pidi);
-    c += af * learned_R(C, ent_s1(famA, T), ebin, k) * I1;
-    c += af * learned_R(C, ii ? ent_s3(famB, T) : ent_s1(famB, T), ebin, k) * I2;
+    R[0] = learned_R(C, ent_s1(famA, T), ebin, k);
+    R[1] = learned_R(C, ii ? ent_s3(famB, T) : ent_s1(famB, T), ebin, k);
+#pragma unroll
+    for (int m = 2; m < kMaxTerms; ++m) R[m] = 0.0;
   }
+  double c = 0.0;
+  c += af * R[0] * I1;
+#pragma unroll
+  for (int m = 1; m < kMaxTerms; ++m)
+    if (m < nt) c += af * R[m] * I2;
   return c;
 }
 
