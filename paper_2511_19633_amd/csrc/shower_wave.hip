@@ -270,16 +270,30 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       q = e >> 1;
       side = e & 1;
       const Rec R = rec_of(W.S, slot);
-      const int tag = side == 0 ? R.effc(q) : R.effa(q);
+      // everything this entry reads is independent of the rest, so it is
+      // requested at once: its cache word, its parton's tags (and momentum,
+      // for the finiteness check), and the tags of the first eight partons
+      const int64_t oc = (int64_t)e * W.S.lanes + slot;
+      const uint32_t old = W.S.cinfo[oc];
+      const int64_t oq = R.o(q);
+      const int stq = R.st[oq], clq = R.col[oq], alq = R.acol[oq];
+      bool fin = true;
+      if (side == 0) fin = isfinite(R.E[oq]) && isfinite(R.px[oq]) && isfinite(R.py[oq]) && isfinite(R.pz[oq]);
+      int oth[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) oth[u] = u < nL ? (side == 0 ? R.effa(u) : R.effc(u)) : 0;
+      // this entry's tag: colour (side 0) or anticolour (side 1), as if outgoing
+      const int tag = side == 0 ? (stq < 0 ? alq : clq) : (stq < 0 ? clq : alq);
       if (tag != 0) {
         // the partner: the first other parton whose opposite tag matches,
-        // looked up eight partons at a time (independent loads)
+        // eight partons at a time
         for (int j0 = 0; j0 < nL && k < 0; j0 += 8) {
-          int oth[8];
+          if (j0 > 0) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int j = j0 + u;
-            oth[u] = j < nL ? (side == 0 ? R.effa(j) : R.effc(j)) : 0;
+            for (int u = 0; u < 8; ++u) {
+              const int j = j0 + u;
+              oth[u] = j < nL ? (side == 0 ? R.effa(j) : R.effc(j)) : 0;
+            }
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -289,13 +303,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
         }
         if (k < 0) atomicOr(&B.flags[L], fColour);
       }
-      if (side == 0) {
-        const int64_t o = R.o(q);
-        if (!(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o])))
-          atomicOr(&B.flags[L], fNaN);
-      }
-      const int64_t oc = (int64_t)e * W.S.lanes + slot;
-      const uint32_t old = W.S.cinfo[oc];
+      if (!fin) atomicOr(&B.flags[L], fNaN);
       const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
       const int jL = nL - 1;
       const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
