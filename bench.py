@@ -271,14 +271,17 @@ def main():
                 shower_stats(st, r["events"], nfin, overflow))
 
     def histos():
-        ob = G.observables(outs[-1])
-        w = ins[-1].w
-        hs = []
-        # Z pT and phi* in 30 bins, the jet count one bin per integer
-        for col, lo, hi, nb in ((0, 0.0, 60.0, 30), (3, 0.0, 1.0, 30), (4, -0.5, 6.5, 7)):
-            sw, sw2 = G.histogram(ob, w, col, lo, hi, nb)
-            hs.append((sw.cpu().numpy(), sw2.cpu().numpy()))
-        return hs
+        """Weighted histograms (sum w, sum w^2) over every timed batch: Z pT and
+        phi* in 30 bins, the jet count one bin per integer."""
+        spec = ((0, 0.0, 60.0, 30), (3, 0.0, 1.0, 30), (4, -0.5, 6.5, 7))
+        acc = [None] * len(spec)
+        for ev_in, ev_out, _ in batches:
+            ob = G.observables(ev_out)
+            for k, (col, lo, hi, nb) in enumerate(spec):
+                sw, sw2 = G.histogram(ob, ev_in.w, col, lo, hi, nb)
+                acc[k] = (sw, sw2) if acc[k] is None else (acc[k][0] + sw, acc[k][1] + sw2)
+            del ob
+        return [(a.cpu().numpy(), b.cpu().numpy()) for a, b in acc]
 
     out_extra = {}
     r_plain = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_PLAIN)
@@ -286,7 +289,7 @@ def main():
     t0 = time.perf_counter()
     h_plain = histos()
     torch.cuda.synchronize()
-    t_obs = time.perf_counter() - t0
+    t_obs = (time.perf_counter() - t0) / K  # observables and histograms of one step
     log(f"plain: {v_plain:.4g} events/s")
     if args.mode == "learned":
         rep = learned_pipeline(G, binding, args, seed)
@@ -297,10 +300,12 @@ def main():
         unhandled = int(sum(((o.flags.to(torch.int64) & binding.F_VIOL) != 0).sum().item() for o in outs))
         log(f"learned: {v_l:.4g} events/s")
         h_l = histos()
+        from scipy import stats as sstats
         chi = {}
         for name, (a, a2), (b, b2) in zip(("z_pt", "phi_star", "n_jets"), h_plain, h_l):
             m = (a2 + b2) > 0
-            chi[name] = float(np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m])) / max(m.sum(), 1))
+            c2, ndf = float(np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m]))), int(max(m.sum(), 1))
+            chi[name] = {"chi2_ndf": c2 / ndf, "ndf": ndf, "p_value": float(sstats.chi2.sf(c2, ndf))}
         value, ms_per_step, roof, stats_main = v_l, ms_l, roof_l, st_l
         out_extra["plain"] = {"value": v_plain, "ms_per_step": ms_plain, "roofline": roof_plain,
                               "shower_stats": st_plain}
