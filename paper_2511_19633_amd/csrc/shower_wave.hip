@@ -106,10 +106,11 @@ __device__ __forceinline__ int wave_incl(int v, int lane) {
 // bit; in learned mode an initial-state entry of the incoming partons draws
 // against the constant of its scale's cell (refreshed here when the cell
 // changed), and a trial below the cell is a null at the cell's lower edge.
-// Returns whether a trial was drawn (the channel is open at this scale).
+// Returns whether a trial was drawn (the channel is open at this scale); kout
+// gets the stored key.
 __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64_t slot, int c, uint32_t info,
                                            double tl, double ltl, double ic, double u, double T, double lnT,
-                                           bool lrn) {
+                                           bool lrn, double& kout) {
   const int64_t oc = (int64_t)c * S.lanes + slot;
   double key = -INFINITY;
   bool isnull = false, tried = false;
@@ -146,6 +147,7 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
     S.cinfo[oc] = isnull ? (info | kNullBit) : (info & ~kNullBit);
   }
   S.ckey[oc] = key;
+  kout = key;
   return tried;
 }
 
@@ -210,7 +212,9 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   if constexpr (DRAW) {
     double ub[4];
     rng4(D.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)c >> 2, ub);
-    if (draw_entry(W.C, W.S, slot, c, pack(ch), ch.tlim, ch.lntlim, ch.invc, pick4(ub, c & 3), TL, lnTL, lrnL))
+    double key;
+    if (draw_entry(W.C, W.S, slot, c, pack(ch), ch.tlim, ch.lntlim, ch.invc, pick4(ub, c & 3), TL, lnTL, lrnL,
+                   key))
       atomicAdd(&B.count[L], 1u);
   }
 }
@@ -370,13 +374,15 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
 
 // Retained trials: the winner entry c of a vetoed or null cycle draws again,
 // in its own lane, at the new cycle from the new scale (T, lnT).
-// info, tl, ltl, ic: the entry's cache word and trial constants.
+// info, tl, ltl, ic: the entry's cache word and trial constants; kout gets
+// the new key.
 __device__ __forceinline__ bool redraw_winner(const Cfg& C, const Scratch& S, uint64_t seed, uint32_t strm,
                                               int64_t id, uint32_t cycle, int64_t slot, int c, uint32_t info,
-                                              double tl, double ltl, double ic, double T, double lnT, bool lrn) {
+                                              double tl, double ltl, double ic, double T, double lnT, bool lrn,
+                                              double& kout) {
   double ub[4];
   rng4(seed, strm, id, cycle, (uint32_t)c >> 2, ub);
-  return draw_entry(C, S, slot, c, info, tl, ltl, ic, pick4(ub, c & 3), T, lnT, lrn);
+  return draw_entry(C, S, slot, c, info, tl, ltl, ic, pick4(ub, c & 3), T, lnT, lrn, kout);
 }
 
 // batch of global queue index g: the last b with prefix[b] <= g
@@ -436,6 +442,13 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   // of the next iteration together with the refilled lanes
   bool rebuild = false, em_all = false;
   int em_i = 0, em_k = 0;
+  // retained trials: the second-largest pending trial (sec_k at entry sec_c)
+  // of the last scan, valid while no other entry's trial changed, and the last
+  // winner pw with its new trial pk; together they give the next winner
+  // without a scan
+  bool sec_ok = false;
+  int sec_c = -1, pw = -1;
+  double sec_k = -INFINITY, pk = -INFINITY;
   bool counted = false, tail = false;
   unsigned it_tail = 0;
 
@@ -503,6 +516,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         active = false;
         pending = false;
         rebuild = false;
+        sec_ok = false;
         if (got) {
           const LaneState& X = s_pool[threadIdx.x];
           e = X.e; id = X.id; slot = X.slot; b = X.b; lrn = X.lrn != 0; T = X.T; lnT = X.lnT; t1 = X.t1;
@@ -582,6 +596,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     // (reported first) or a broken colour line stops the event (its cycle
     // was already counted).
     const bool built = fresh || rebuild;
+    if (built) sec_ok = false;
     {
       const unsigned long long bm = __ballot(built);
       if (bm) {
@@ -634,51 +649,73 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     double rtl = 0.0, rltl = 0.0, ric = 0.0;
     if constexpr (RETAIN) {
       // ---- retained trials: the winner is the largest pending trial, ties
-      // to the lowest entry.  The events' groups of four entries are spread
-      // over the wave, one per lane; each owner merges its groups in order.
+      // to the lowest entry.  An event whose cached second-largest trial is
+      // valid takes the larger of it and its last winner's new trial; the
+      // others scan their entries, in groups of four spread over the wave, one
+      // group per lane, and each owner merges its groups' two largest in
+      // order (keeping the two largest for the cache).
       TrialLds& TQ = s_trial[wid];
-      const int ng = trialing ? (2 * n + 3) >> 2 : 0;
-      int incl = ng;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, (unsigned)o);
-        if (lane >= o) incl += v;
-      }
+      const bool scan = trialing && !sec_ok;
+      const int ng = scan ? (2 * n + 3) >> 2 : 0;
+      const int incl = wave_incl(ng, lane);
       const int total = __shfl(incl, 63);
       const int first = incl - ng;
+      double k2 = -INFINITY;
+      int c2 = -1;
       for (int g0 = 0; g0 < total; g0 += 64) {
         const int g = g0 + lane;
-        int L = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-          const int v = __shfl(incl, L + step - 1);
-          if (v <= g) L += step;
-        }
-        L = L > 63 ? 63 : L;
+        const int L = owner_of(incl, g);
         const int64_t sL = __shfl(slot, L);
         const int nL = __shfl(n, L), fL = __shfl(first, L);
-        double gk = -INFINITY;
-        int gc = 0;
+        double b1 = -INFINITY, b2 = -INFINITY;
+        int i1 = -1, i2 = -1;
         if (g < total) {
           const int c0 = 4 * (g - fL);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const double k = S.ckey[(int64_t)(c0 + j) * S.lanes + sL];
-            if (c0 + j < 2 * nL && k > gk) { gk = k; gc = c0 + j; }
+            if (c0 + j < 2 * nL) {
+              if (k > b1) { b2 = b1; i2 = i1; b1 = k; i1 = c0 + j; }
+              else if (k > b2) { b2 = k; i2 = c0 + j; }
+            }
           }
         }
-        TQ.c[lane].key = gk;
-        TQ.c[lane].bits = (uint32_t)gc;
+        TQ.c[lane].key = b1;
+        TQ.c[lane].bits = (uint32_t)i1;
+        TQ.c[lane].hi = b2;
+        TQ.c[lane].ntri = (uint32_t)i2;
         __builtin_amdgcn_wave_barrier();
-        if (trialing) {
+        if (scan) {
           const int kb = (first > g0 ? first : g0) - g0;
           const int ke = (incl < g0 + 64 ? incl : g0 + 64) - g0;
           for (int k = kb; k < ke; ++k) {
-            const double y = TQ.c[k].key;
-            if (y > wkey) { wkey = y; win = (int)TQ.c[k].bits; }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const double y = h == 0 ? TQ.c[k].key : TQ.c[k].hi;
+              const int yi = (int)(h == 0 ? TQ.c[k].bits : TQ.c[k].ntri);
+              if (y > wkey) { k2 = wkey; c2 = win; wkey = y; win = yi; }
+              else if (y > k2) { k2 = y; c2 = yi; }
+            }
           }
         }
         __builtin_amdgcn_wave_barrier();
+      }
+      if (scan) {
+        sec_k = k2;
+        sec_c = c2;
+        sec_ok = true;
+      } else if (trialing) {
+        // every entry other than pw and sec_c is at most sec_k (and after sec_c
+        // if equal): the winner is the larger of the two, ties to the lower entry
+        if (pk > sec_k || (pk == sec_k && pw < sec_c)) {
+          wkey = pk;
+          win = pw;
+        } else {
+          wkey = sec_k;
+          win = sec_c;
+          sec_ok = false;  // the next winner needs a scan
+        }
+        if (!(wkey > -INFINITY)) win = -1;
       }
       if (trialing && win >= 0) {
         // the winner's entry: null and cell bits now, trial constants for its
@@ -928,7 +965,11 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       }
     }
     if constexpr (RETAIN)
-      if (rdw) ntri += redraw_winner(C, S, A.seed, strm, id, cycle, slot, win, rinfo, rtl, rltl, ric, T, lnT, lrn) ? 1u : 0u;
+      if (rdw) {
+        ntri += redraw_winner(C, S, A.seed, strm, id, cycle, slot, win, rinfo, rtl, rltl, ric, T, lnT, lrn, pk)
+                    ? 1u : 0u;
+        pw = win;
+      }
     // ---- finished events: write out and free the lane
     const bool wout = active && done && loaded;  // partons copied by the wave below
     if (active && done) {
