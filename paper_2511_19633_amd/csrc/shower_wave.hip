@@ -237,7 +237,7 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
 // gets the number of trials drawn for this lane's event.
 template <bool DRAW>
 __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long mask, int n, int64_t myslot,
-                               bool all, int ei, int ek, const DrawState& D, uint32_t& drawn) {
+                               bool fresh, bool all, int ei, int ek, const DrawState& D, uint32_t& drawn) {
   __threadfence_block();
   const bool mine = (mask >> W.lane) & 1ull;
   const int ne = mine ? 2 * n : 0;
@@ -265,7 +265,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
     const int nL = __shfl(n, L);
     const int firstL = __shfl(incl, L) - 2 * nL;
     const int64_t slot = __shfl(myslot, L);
-    const bool allL = __shfl((int)all, L) != 0;
+    const bool allL = __shfl((int)all, L) != 0, freshL = __shfl((int)fresh, L) != 0;
     const int iL = __shfl(ei, L), kL = __shfl(ek, L);
     bool queue = false;
     int q = 0, side = 0, k = -1;
@@ -274,42 +274,50 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       q = e >> 1;
       side = e & 1;
       const Rec R = rec_of(W.S, slot);
-      // everything this entry reads is independent of the rest, so it is
-      // requested at once: its cache word, its parton's tags (and momentum,
-      // for the finiteness check), and the tags of the first eight partons
+      // its cache word and (for the finiteness check) its parton's momentum
       const int64_t oc = (int64_t)e * W.S.lanes + slot;
       const uint32_t old = W.S.cinfo[oc];
       const int64_t oq = R.o(q);
-      const int stq = R.st[oq], clq = R.col[oq], alq = R.acol[oq];
       bool fin = true;
       if (side == 0) fin = isfinite(R.E[oq]) && isfinite(R.px[oq]) && isfinite(R.py[oq]) && isfinite(R.pz[oq]);
-      int oth[8];
+      const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
+      // An emission changes colour tags only on the emitter (which only ever
+      // takes a new tag) and the new parton (which takes the emitter's old
+      // tags or the new one), and each tag sits on exactly one pair of
+      // partons.  So another parton keeps its partner unless that partner was
+      // the emitter; only those entries, the emitter's and the new parton's
+      // search, as every entry of a refilled event does.
+      const int jL = nL - 1;
+      if (freshL || q == iL || q == jL || (old != 0u && kold == iL)) {
+        const int stq = R.st[oq], clq = R.col[oq], alq = R.acol[oq];
+        int oth[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) oth[u] = u < nL ? (side == 0 ? R.effa(u) : R.effc(u)) : 0;
-      // this entry's tag: colour (side 0) or anticolour (side 1), as if outgoing
-      const int tag = side == 0 ? (stq < 0 ? alq : clq) : (stq < 0 ? clq : alq);
-      if (tag != 0) {
-        // the partner: the first other parton whose opposite tag matches,
-        // eight partons at a time
-        for (int j0 = 0; j0 < nL && k < 0; j0 += 8) {
-          if (j0 > 0) {
+        for (int u = 0; u < 8; ++u) oth[u] = u < nL ? (side == 0 ? R.effa(u) : R.effc(u)) : 0;
+        // this entry's tag: colour (side 0) or anticolour (side 1), as if outgoing
+        const int tag = side == 0 ? (stq < 0 ? alq : clq) : (stq < 0 ? clq : alq);
+        if (tag != 0) {
+          // the partner: the first other parton whose opposite tag matches,
+          // eight partons at a time
+          for (int j0 = 0; j0 < nL && k < 0; j0 += 8) {
+            if (j0 > 0) {
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u;
+                oth[u] = j < nL ? (side == 0 ? R.effa(j) : R.effc(j)) : 0;
+              }
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const int j = j0 + u;
-              oth[u] = j < nL ? (side == 0 ? R.effa(j) : R.effc(j)) : 0;
+              if (k < 0 && j < nL && j != q && oth[u] == tag) k = j;
             }
           }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int j = j0 + u;
-            if (k < 0 && j < nL && j != q && oth[u] == tag) k = j;
-          }
+          if (k < 0) atomicOr(&B.flags[L], fColour);
         }
-        if (k < 0) atomicOr(&B.flags[L], fColour);
+      } else {
+        k = kold;
       }
       if (!fin) atomicOr(&B.flags[L], fNaN);
-      const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
-      const int jL = nL - 1;
       const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
       if (dirty) {
         if (k < 0) W.S.cinfo[oc] = 0u;
@@ -602,7 +610,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (bm) {
         const DrawState D{T, lnT, id, cycle, lrn, A.seed};
         uint32_t drawn = 0;
-        uint32_t f = coop_build<RETAIN>(W, s_build[wid], bm, n, slot, fresh || em_all, em_i, em_k, D, drawn);
+        uint32_t f =
+            coop_build<RETAIN>(W, s_build[wid], bm, n, slot, fresh, fresh || em_all, em_i, em_k, D, drawn);
         if (fresh) f &= fColour;
         if (f & fNaN) f = fNaN;
         // an event stopped here draws nothing (its draws are not counted)
