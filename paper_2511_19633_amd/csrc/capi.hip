@@ -34,7 +34,7 @@ struct ScratchMem {
 gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   size_t per_lane = (size_t)slots * (4 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int8_t)) +
-                    (size_t)nch * (2 * sizeof(uint32_t) + 12 * sizeof(double));
+                    (size_t)nch * (sizeof(uint32_t) + 4 * sizeof(double) + sizeof(gaps::Win));
   size_t need = per_lane * (size_t)lanes + 256 * 32 + 64;
   if (need > m.bytes || m.S.lanes != lanes || m.S.max_slots != slots) {
     if (need > m.bytes) {
@@ -60,10 +60,8 @@ gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
     S.st = (int8_t*)take(ps);
     S.cinfo = (uint32_t*)take(cs * 4);
     S.ctlim = (double*)take(cs * 8); S.clntlim = (double*)take(cs * 8); S.cinvc = (double*)take(cs * 8);
-    S.cc = (double*)take(cs * 8); S.cs = (double*)take(cs * 8); S.czlo = (double*)take(cs * 8);
-    S.comzhi = (double*)take(cs * 8); S.cI1 = (double*)take(cs * 8); S.cI2 = (double*)take(cs * 8);
     S.ckey = (double*)take(cs * 8);
-    S.ceta = (double*)take(cs * 8); S.cetak = (double*)take(cs * 8); S.cpid = (uint32_t*)take(cs * 4);
+    S.cwin = (gaps::Win*)take(cs * sizeof(gaps::Win));
     S.queue = (unsigned long long*)take(64);
     if ((size_t)(p - (char*)m.mem) > m.bytes) return GAPS_ENOMEM;
   }

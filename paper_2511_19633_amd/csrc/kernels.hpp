@@ -6,6 +6,18 @@
 
 namespace gaps {
 
+// Winner data of a channel cache entry, contiguous (80 bytes: one or two cache
+// lines per entry): the total overestimate constant c (in learned mode the
+// constant of the current cell), the dipole invariant s, the z limits, the
+// z integrals of the channel's two shapes, the momentum fractions 2E/sqrt(S) of
+// an incoming emitter and spectator (0 when outgoing), and their flavours
+// (int8 each, emitter in the low byte).
+struct Win {
+  double c, s, zlo, omzhi, I1, I2, eta, etak;
+  uint32_t pid, pad0, pad1, pad2;
+};
+static_assert(sizeof(Win) == 80, "winner record layout");
+
 // Per-lane working storage of the shower kernels: event records and channel
 // caches, slot-major with stride = number of lanes (coalesced across a wave).
 struct Scratch {
@@ -14,13 +26,13 @@ struct Scratch {
   double *E, *px, *py, *pz;
   int32_t *pid, *col, *acol;
   int8_t* st;
-  // channel cache [2*max_slots][lanes]: trial data, then winner data
+  // channel cache [2*max_slots][lanes]: trial data (one array per field, so
+  // that lanes reading one entry of neighbouring events read contiguous
+  // memory), then the data only the winner needs, one record per entry
   uint32_t* cinfo;
   double *ctlim, *clntlim, *cinvc;
   double* ckey;  // retained trials: the entry's pending trial ln t (-inf: none above the cutoff)
-  double *ceta, *cetak;  // momentum fractions 2E/sqrt(S) of an incoming emitter and spectator (0: outgoing)
-  uint32_t* cpid;        // flavours of emitter and spectator (int8 each)
-  double *cc, *cs, *czlo, *comzhi, *cI1, *cI2;
+  struct Win* cwin;
   unsigned long long* queue;  // work-queue counters
 };
 

@@ -130,11 +130,11 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
         const int cell = cell_of(C, lnTch, floor);
         if ((int)((info & kCellMask) >> kCellShift) != cell) {
           const Rec R = Rec{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, 1, S.max_slots, slot};
-          const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cI1[oc],
-                                      S.cI2[oc], cell);
+          const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cwin[oc].I1,
+                                      S.cwin[oc].I2, cell);
           invc = 1.0 / ck;
           S.cinvc[oc] = invc;
-          S.cc[oc] = ck;
+          S.cwin[oc].c = ck;
           info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
         }
         if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
@@ -200,15 +200,12 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   W.S.ctlim[oc] = ch.tlim;
   W.S.clntlim[oc] = ch.lntlim;
   W.S.cinvc[oc] = ch.invc;
-  W.S.cc[oc] = ch.c;
-  W.S.cs[oc] = ch.s;
-  W.S.czlo[oc] = ch.zlo;
-  W.S.comzhi[oc] = ch.omzhi;
-  W.S.cI1[oc] = ch.I1;
-  W.S.cI2[oc] = ch.I2;
-  W.S.ceta[oc] = ch.eta;
-  W.S.cetak[oc] = ch.etak;
-  W.S.cpid[oc] = (uint32_t)(ch.pidi & 0xFF) | ((uint32_t)(ch.pidk & 0xFF) << 8);
+  Win wd;
+  wd.c = ch.c; wd.s = ch.s; wd.zlo = ch.zlo; wd.omzhi = ch.omzhi; wd.I1 = ch.I1; wd.I2 = ch.I2;
+  wd.eta = ch.eta; wd.etak = ch.etak;
+  wd.pid = (uint32_t)(ch.pidi & 0xFF) | ((uint32_t)(ch.pidk & 0xFF) << 8);
+  wd.pad0 = wd.pad1 = wd.pad2 = 0u;
+  W.S.cwin[oc] = wd;
   if constexpr (DRAW) {
     double ub[4];
     rng4(D.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)c >> 2, ub);
@@ -364,19 +361,20 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.ebin = (info >> 13) & 0x3Fu;
   ch.kbin = (info >> 19) & 0x3Fu;
   ch.m2 = ch.heavy == 1 ? C.mc2 : (ch.heavy == 2 ? C.mb2 : 0.0);
-  const uint32_t pk = S.cpid[oc];
+  const Win wd = S.cwin[oc];
+  const uint32_t pk = wd.pid;
   ch.pidi = (int)(int8_t)(pk & 0xFFu);
   ch.pidk = (int)(int8_t)((pk >> 8) & 0xFFu);
-  ch.s = S.cs[oc];
-  ch.c = S.cc[oc];
-  ch.zlo = S.czlo[oc];
-  ch.omzhi = S.comzhi[oc];
+  ch.s = wd.s;
+  ch.c = wd.c;
+  ch.zlo = wd.zlo;
+  ch.omzhi = wd.omzhi;
   ch.zhi = 1.0 - ch.omzhi;
   ch.omzlo = 1.0 - ch.zlo;
-  ch.I1 = S.cI1[oc];
-  ch.I2 = S.cI2[oc];
-  ch.eta = S.ceta[oc];
-  ch.etak = S.cetak[oc];
+  ch.I1 = wd.I1;
+  ch.I2 = wd.I2;
+  ch.eta = wd.eta;
+  ch.etak = wd.etak;
   ch.nterm = n_terms(ch, C.nf);
 }
 
@@ -810,10 +808,10 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                   const int64_t oc = (int64_t)c * S.lanes + sL;
                   const Rec RL = rec_of(S, sL);
                   const double ck = learned_c(C, type, RL.pid[RL.o(c >> 1)], (int)((info >> 13) & 0x3Fu),
-                                              S.cI1[oc], S.cI2[oc], cell);
+                                              S.cwin[oc].I1, S.cwin[oc].I2, cell);
                   invc = 1.0 / ck;
                   S.cinvc[oc] = invc;
-                  S.cc[oc] = ck;
+                  S.cwin[oc].c = ck;
                   S.cinfo[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
                 }
                 if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
