@@ -34,7 +34,7 @@ struct ScratchMem {
 gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   size_t per_lane = (size_t)slots * (4 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int8_t)) +
-                    (size_t)nch * (sizeof(uint32_t) + 4 * sizeof(double) + sizeof(gaps::Win));
+                    (size_t)nch * (sizeof(gaps::Trial) + sizeof(gaps::Win));
   size_t need = per_lane * (size_t)lanes + 256 * 32 + 64;
   if (need > m.bytes || m.S.lanes != lanes || m.S.max_slots != slots) {
     if (need > m.bytes) {
@@ -58,9 +58,8 @@ gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
     S.py = (double*)take(ps * 8); S.pz = (double*)take(ps * 8);
     S.pid = (int32_t*)take(ps * 4); S.col = (int32_t*)take(ps * 4); S.acol = (int32_t*)take(ps * 4);
     S.st = (int8_t*)take(ps);
-    S.cinfo = (uint32_t*)take(cs * 4);
-    S.ctlim = (double*)take(cs * 8); S.clntlim = (double*)take(cs * 8); S.cinvc = (double*)take(cs * 8);
-    S.ckey = (double*)take(cs * 8);
+    S.nch = nch;
+    S.ctr = (gaps::Trial*)take(cs * sizeof(gaps::Trial));
     S.cwin = (gaps::Win*)take(cs * sizeof(gaps::Win));
     S.queue = (unsigned long long*)take(64);
     if ((size_t)(p - (char*)m.mem) > m.bytes) return GAPS_ENOMEM;

@@ -6,6 +6,17 @@
 
 namespace gaps {
 
+// Trial data of a channel cache entry (48 bytes): the kinematic limit t_lim
+// and its log, 1/c of the current overestimate (of the current cell in learned
+// mode), the pending trial ln t of the retained form (-inf: none above the
+// cutoff), and the info word (alive | type << 1 | heavy << 3 | spectator << 5 |
+// eta bin << 13 | spectator eta bin << 19 | learned cell << 25 | null << 29).
+struct alignas(16) Trial {
+  double tl, ltl, ic, key;
+  uint32_t info, pad0, pad1, pad2;
+};
+static_assert(sizeof(Trial) == 48, "trial record layout");
+
 // Winner data of a channel cache entry, contiguous (80 bytes: one or two cache
 // lines per entry): the total overestimate constant c (in learned mode the
 // constant of the current cell), the dipole invariant s, the z limits, the
@@ -26,12 +37,11 @@ struct Scratch {
   double *E, *px, *py, *pz;
   int32_t *pid, *col, *acol;
   int8_t* st;
-  // channel cache [2*max_slots][lanes]: trial data (one array per field, so
-  // that lanes reading one entry of neighbouring events read contiguous
-  // memory), then the data only the winner needs, one record per entry
-  uint32_t* cinfo;
-  double *ctlim, *clntlim, *cinvc;
-  double* ckey;  // retained trials: the entry's pending trial ln t (-inf: none above the cutoff)
+  // channel cache [lanes][nch]: one event's entries contiguous (the wave's
+  // passes give consecutive lanes consecutive entries of an event), as a
+  // trial record and a winner record per entry
+  int nch;             // entries per event: 2 max_slots rounded up to a multiple of 4
+  struct Trial* ctr;
   struct Win* cwin;
   unsigned long long* queue;  // work-queue counters
 };

@@ -34,11 +34,11 @@ __device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& 
       }
       if (k < 0) return -1;
       chan_setup(C, R, i, side, k, ch);
-      int64_t oc = (int64_t)m * S.lanes + R.lane;
-      S.cinfo[oc] = pack_info(ch);
-      S.ctlim[oc] = ch.tlim;
-      S.clntlim[oc] = ch.lntlim;
-      S.cinvc[oc] = ch.invc;
+      int64_t oc = (int64_t)R.lane * S.nch + m;
+      S.ctr[oc].info = pack_info(ch);
+      S.ctr[oc].tl = ch.tlim;
+      S.ctr[oc].ltl = ch.lntlim;
+      S.ctr[oc].ic = ch.invc;
       ++m;
     }
   }
@@ -82,10 +82,10 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       uint32_t curblk = 0xFFFFFFFFu;
       double ub[4] = {0.0, 0.0, 0.0, 0.0};
       for (int c = 0; c < nch; ++c) {
-        int64_t oc = (int64_t)c * S.lanes + R.lane;
-        uint32_t info = S.cinfo[oc];
+        int64_t oc = (int64_t)R.lane * S.nch + c;
+        uint32_t info = S.ctr[oc].info;
         if (!((info >> 21) & 1u)) continue;
-        double tlim = S.ctlim[oc], lntlim = S.clntlim[oc];
+        double tlim = S.ctr[oc].tl, lntlim = S.ctr[oc].ltl;
         int type = (info >> 17) & 3u, heavy = (info >> 19) & 3u;
         double tcut, lntcut, m2 = 0.0;
         if (heavy == 1) { tcut = C.tch_c; lntcut = C.ln_tch_c; m2 = C.mc2; }
@@ -102,7 +102,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         }
         double lu = log(ub[slot & 3u]);
         ntri += 1;
-        double invc = S.cinvc[oc];
+        double invc = S.ctr[oc].ic;
         double key;
         if (!heavy) key = lnTch + lu * invc;
         else key = log(m2 + (Tch - m2) * exp(lu * invc));
@@ -111,7 +111,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       }
       if (win < 0) break;
       double t = exp(best);
-      uint32_t info = S.cinfo[(int64_t)win * S.lanes + R.lane];
+      uint32_t info = S.ctr[(int64_t)R.lane * S.nch + win].info;
       Chan ch;
       chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
       double u[4];

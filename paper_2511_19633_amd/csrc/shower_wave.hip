@@ -111,7 +111,7 @@ __device__ __forceinline__ int wave_incl(int v, int lane) {
 __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64_t slot, int c, uint32_t info,
                                            double tl, double ltl, double ic, double u, double T, double lnT,
                                            bool lrn, double& kout) {
-  const int64_t oc = (int64_t)c * S.lanes + slot;
+  const int64_t oc = (int64_t)slot * S.nch + c;
   double key = -INFINITY;
   bool isnull = false, tried = false;
   if (info & 1u) {
@@ -133,7 +133,7 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
           const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cwin[oc].I1,
                                       S.cwin[oc].I2, cell);
           invc = 1.0 / ck;
-          S.cinvc[oc] = invc;
+          S.ctr[oc].ic = invc;
           S.cwin[oc].c = ck;
           info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
         }
@@ -144,9 +144,9 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
       if (key < floor) { key = floor; isnull = true; }
       if (key < lntcut) { key = -INFINITY; isnull = false; }
     }
-    S.cinfo[oc] = isnull ? (info | kNullBit) : (info & ~kNullBit);
+    S.ctr[oc].info = isnull ? (info | kNullBit) : (info & ~kNullBit);
   }
-  S.ckey[oc] = key;
+  S.ctr[oc].key = key;
   kout = key;
   return tried;
 }
@@ -195,11 +195,11 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   Chan ch;
   chan_setup(W.C, R, q, side, k, ch);
   const int c = 2 * q + side;
-  const int64_t oc = (int64_t)c * W.S.lanes + slot;
-  W.S.cinfo[oc] = pack(ch);
-  W.S.ctlim[oc] = ch.tlim;
-  W.S.clntlim[oc] = ch.lntlim;
-  W.S.cinvc[oc] = ch.invc;
+  const int64_t oc = (int64_t)slot * W.S.nch + c;
+  W.S.ctr[oc].info = pack(ch);
+  W.S.ctr[oc].tl = ch.tlim;
+  W.S.ctr[oc].ltl = ch.lntlim;
+  W.S.ctr[oc].ic = ch.invc;
   Win wd;
   wd.c = ch.c; wd.s = ch.s; wd.zlo = ch.zlo; wd.omzhi = ch.omzhi; wd.I1 = ch.I1; wd.I2 = ch.I2;
   wd.eta = ch.eta; wd.etak = ch.etak;
@@ -272,8 +272,8 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       side = e & 1;
       const Rec R = rec_of(W.S, slot);
       // its cache word and (for the finiteness check) its parton's momentum
-      const int64_t oc = (int64_t)e * W.S.lanes + slot;
-      const uint32_t old = W.S.cinfo[oc];
+      const int64_t oc = (int64_t)slot * W.S.nch + e;
+      const uint32_t old = W.S.ctr[oc].info;
       const int64_t oq = R.o(q);
       bool fin = true;
       if (side == 0) fin = isfinite(R.E[oq]) && isfinite(R.px[oq]) && isfinite(R.py[oq]) && isfinite(R.pz[oq]);
@@ -317,13 +317,13 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       if (!fin) atomicOr(&B.flags[L], fNaN);
       const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
       if (dirty) {
-        if (k < 0) W.S.cinfo[oc] = 0u;
+        if (k < 0) W.S.ctr[oc].info = 0u;
         else queue = true;
       }
       // retained trials: an unchanged entry keeps its pending trial (its
       // process is unchanged); an entry without a partner has none
       if constexpr (DRAW)
-        if (k < 0) W.S.ckey[oc] = -INFINITY;
+        if (k < 0) W.S.ctr[oc].key = -INFINITY;
     }
     const unsigned long long qm = __ballot(queue);
     if (queue) {
@@ -350,8 +350,8 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
 // rebuild the channel description of cache entry c from the cache and record
 __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, const Rec& R, int64_t slot, int c,
                                                 Chan& ch) {
-  const int64_t oc = (int64_t)c * S.lanes + slot;
-  uint32_t info = S.cinfo[oc];
+  const int64_t oc = (int64_t)slot * S.nch + c;
+  uint32_t info = S.ctr[oc].info;
   ch.alive = 1;
   ch.i = c >> 1;
   ch.side = c & 1;
@@ -680,7 +680,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           const int c0 = 4 * (g - fL);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const double k = S.ckey[(int64_t)(c0 + j) * S.lanes + sL];
+            const double k = S.ctr[(int64_t)sL * S.nch + (c0 + j)].key;
             if (c0 + j < 2 * nL) {
               if (k > b1) { b2 = b1; i2 = i1; b1 = k; i1 = c0 + j; }
               else if (k > b2) { b2 = k; i2 = c0 + j; }
@@ -727,11 +727,11 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (trialing && win >= 0) {
         // the winner's entry: null and cell bits now, trial constants for its
         // redraw after a veto (loaded together, one memory round trip)
-        const int64_t ow = (int64_t)win * S.lanes + slot;
-        rinfo = S.cinfo[ow];
-        rtl = S.ctlim[ow];
-        rltl = S.clntlim[ow];
-        ric = S.cinvc[ow];
+        const int64_t ow = (int64_t)slot * S.nch + win;
+        rinfo = S.ctr[ow].info;
+        rtl = S.ctr[ow].tl;
+        rltl = S.ctr[ow].ltl;
+        ric = S.ctr[ow].ic;
         wnull = (rinfo & kNullBit) != 0u;
         wcell = (int)((rinfo & kCellMask) >> kCellShift);
       }
@@ -773,11 +773,11 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           double tl[4], ltl[4], ic[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int64_t oc = (int64_t)(c0 + j) * S.lanes + sL;
-            inf[j] = S.cinfo[oc];
-            tl[j] = S.ctlim[oc];
-            ltl[j] = S.clntlim[oc];
-            ic[j] = S.cinvc[oc];
+            const int64_t oc = (int64_t)sL * S.nch + (c0 + j);
+            inf[j] = S.ctr[oc].info;
+            tl[j] = S.ctr[oc].tl;
+            ltl[j] = S.ctr[oc].ltl;
+            ic[j] = S.ctr[oc].ic;
           }
           if ((inf[0] | inf[1] | inf[2] | inf[3]) & 1u) {
             double ub[4];
@@ -805,14 +805,14 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                 if ((int)((info & kCellMask) >> kCellShift) != cell) {
                   // the scale entered a new cell: that cell's constant replaces the
                   // entry's (1/c for the trials, c for the winner's term choice)
-                  const int64_t oc = (int64_t)c * S.lanes + sL;
+                  const int64_t oc = (int64_t)sL * S.nch + c;
                   const Rec RL = rec_of(S, sL);
                   const double ck = learned_c(C, type, RL.pid[RL.o(c >> 1)], (int)((info >> 13) & 0x3Fu),
                                               S.cwin[oc].I1, S.cwin[oc].I2, cell);
                   invc = 1.0 / ck;
-                  S.cinvc[oc] = invc;
+                  S.ctr[oc].ic = invc;
                   S.cwin[oc].c = ck;
-                  S.cinfo[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+                  S.ctr[oc].info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
                 }
                 if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
               }
