@@ -33,7 +33,7 @@ struct ScratchMem {
 
 gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
-  size_t per_lane = (size_t)slots * (4 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int8_t)) +
+  size_t per_lane = (size_t)slots * sizeof(gaps::Part) +
                     (size_t)nch * (sizeof(gaps::Trial) + sizeof(gaps::Win));
   size_t need = per_lane * (size_t)lanes + 256 * 32 + 64;
   if (need > m.bytes || m.S.lanes != lanes || m.S.max_slots != slots) {
@@ -54,10 +54,7 @@ gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
     S.lanes = lanes;
     S.max_slots = slots;
     size_t ps = (size_t)slots * lanes, cs = (size_t)nch * lanes;
-    S.E = (double*)take(ps * 8); S.px = (double*)take(ps * 8);
-    S.py = (double*)take(ps * 8); S.pz = (double*)take(ps * 8);
-    S.pid = (int32_t*)take(ps * 4); S.col = (int32_t*)take(ps * 4); S.acol = (int32_t*)take(ps * 4);
-    S.st = (int8_t*)take(ps);
+    S.part = (gaps::Part*)take(ps * sizeof(gaps::Part));
     S.nch = nch;
     S.ctr = (gaps::Trial*)take(cs * sizeof(gaps::Trial));
     S.cwin = (gaps::Win*)take(cs * sizeof(gaps::Win));

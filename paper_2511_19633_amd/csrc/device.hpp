@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace gaps {
@@ -161,13 +162,36 @@ __device__ __forceinline__ double dot4(const double* a, const double* b) {
 }
 
 // ---------------------------------------------------------------------------
-// Working event record of one lane: particle q of state slot `lane` lives at
-// q * sq + lane * sl (slot-major: sq = lanes, sl = 1; lane-major: sq = 1,
-// sl = slots).
+// A parton of a working event record (48 bytes, one or two cache lines):
+// momentum, flavour, colour tags and status side by side.
+struct alignas(16) Part {
+  double E, px, py, pz;
+  int32_t pid, col, acol;
+  int8_t st, pad0, pad1, pad2;
+};
+static_assert(sizeof(Part) == 48, "parton record layout");
+
+// one field of the partons of a record, indexed like an array
+template <typename T, size_t OFF>
+struct PartField {
+  Part* base;
+  __device__ __forceinline__ T& operator[](int64_t k) const {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base + k) + OFF);
+  }
+};
+
+// Working event record of one lane: parton q of state slot `lane` is
+// part[q * sq + lane * sl] (lane-major: sq = 1, sl = slots; slot-major:
+// sq = lanes, sl = 1).
 struct Rec {
-  double *E, *px, *py, *pz;
-  int32_t *pid, *col, *acol;
-  int8_t* st;
+  PartField<double, offsetof(Part, E)> E;
+  PartField<double, offsetof(Part, px)> px;
+  PartField<double, offsetof(Part, py)> py;
+  PartField<double, offsetof(Part, pz)> pz;
+  PartField<int32_t, offsetof(Part, pid)> pid;
+  PartField<int32_t, offsetof(Part, col)> col;
+  PartField<int32_t, offsetof(Part, acol)> acol;
+  PartField<int8_t, offsetof(Part, st)> st;
   int64_t sq, sl, lane;
   __device__ __forceinline__ int64_t o(int q) const { return (int64_t)q * sq + lane * sl; }
   __device__ __forceinline__ void get(int q, double p[4]) const {
@@ -186,6 +210,10 @@ struct Rec {
     if (st[k] < 0) { col[k] = a; acol[k] = c; } else { col[k] = c; acol[k] = a; }
   }
 };
+
+__device__ __forceinline__ Rec make_rec(Part* p, int64_t sq, int64_t sl, int64_t lane) {
+  return Rec{{p}, {p}, {p}, {p}, {p}, {p}, {p}, {p}, sq, sl, lane};
+}
 
 // ---------------------------------------------------------------------------
 // Channel: dipole end (emitter i, spectator k, colour side) with its constants.

@@ -34,9 +34,7 @@ static_assert(sizeof(Win) == 80, "winner record layout");
 struct Scratch {
   int64_t lanes;
   int max_slots;
-  double *E, *px, *py, *pz;
-  int32_t *pid, *col, *acol;
-  int8_t* st;
+  Part* part;  // working event records (lane-major in the wave kernels: one event's partons adjacent)
   // channel cache [lanes][nch]: one event's entries contiguous (the wave's
   // passes give consecutive lanes consecutive entries of an event), as a
   // trial record and a winner record per entry

@@ -179,7 +179,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
 __global__ void __launch_bounds__(256) k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S,
                                                       ShowerArgs A) {
   const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  Rec R{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, S.lanes, 1, lane};
+  Rec R = make_rec(S.part, S.lanes, 1, lane);
   for (;;) {
     unsigned long long e = atomicAdd(S.queue, 1ULL);
     if (e >= (unsigned long long)A.n) break;

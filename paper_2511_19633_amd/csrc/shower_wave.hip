@@ -64,7 +64,7 @@ struct LaneState {
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
 __device__ __forceinline__ Rec rec_of(const Scratch& S, int64_t slot) {
-  return Rec{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, 1, S.max_slots, slot};
+  return make_rec(S.part, 1, S.max_slots, slot);
 }
 
 // LDS of one wave for the cooperative channel build: a ring of entries that
@@ -129,7 +129,7 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
       if (lrn && c < 4 && (type == kIF || type == kII)) {
         const int cell = cell_of(C, lnTch, floor);
         if ((int)((info & kCellMask) >> kCellShift) != cell) {
-          const Rec R = Rec{S.E, S.px, S.py, S.pz, S.pid, S.col, S.acol, S.st, 1, S.max_slots, slot};
+          const Rec R = make_rec(S.part, 1, S.max_slots, slot);
           const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cwin[oc].I1,
                                       S.cwin[oc].I2, cell);
           invc = 1.0 / ck;
@@ -587,8 +587,11 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             const int q = g - fL;
             const int64_t k = (int64_t)q * in.cap + eL, o = rec_of(S, sL).o(q);
             const int cl = in.col[k], al = in.acol[k];
-            S.E[o] = in.E[k]; S.px[o] = in.px[k]; S.py[o] = in.py[k]; S.pz[o] = in.pz[k];
-            S.pid[o] = in.pid[k]; S.col[o] = cl; S.acol[o] = al; S.st[o] = in.status[k];
+            Part pt;
+            pt.E = in.E[k]; pt.px = in.px[k]; pt.py = in.py[k]; pt.pz = in.pz[k];
+            pt.pid = in.pid[k]; pt.col = cl; pt.acol = al; pt.st = in.status[k];
+            pt.pad0 = pt.pad1 = pt.pad2 = 0;
+            S.part[o] = pt;
             atomicMax(&B.tag[L], cl > al ? cl : al);
           }
         }
@@ -1022,8 +1025,9 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           const gaps_events& out = A.nbatch > 0 ? A.batches[bL].out : out1;
           const int q = g - fL;
           const int64_t k = (int64_t)q * out.cap + eL, o = rec_of(S, sL).o(q);
-          out.E[k] = S.E[o]; out.px[k] = S.px[o]; out.py[k] = S.py[o]; out.pz[k] = S.pz[o];
-          out.pid[k] = S.pid[o]; out.col[k] = S.col[o]; out.acol[k] = S.acol[o]; out.status[k] = S.st[o];
+          const Part pt = S.part[o];
+          out.E[k] = pt.E; out.px[k] = pt.px; out.py[k] = pt.py; out.pz[k] = pt.pz;
+          out.pid[k] = pt.pid; out.col[k] = pt.col; out.acol[k] = pt.acol; out.status[k] = pt.st;
         }
       }
     }
