@@ -248,7 +248,7 @@ def main():
     kernel = {1: "k_shower_lanes", 0: {0: "k_shower_wave", 2: "k_shower_wave", 3: "k_shower_wave3",
                                        4: "k_shower_wave4"}[args.waves_per_simd]}[args.variant]
     if args.trials == "retain":
-        kernel = "k_shower_wave_rt"
+        kernel = "k_shower_wave_rt3" if args.waves_per_simd == 3 else "k_shower_wave_rt"
 
     def summarise(r, mode, kname=None):
         nfin = float(np.mean([o.n.double().mean().item() for o in outs]))

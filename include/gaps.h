@@ -124,7 +124,9 @@ typedef struct {
     int variant;         /* 0: wave-cooperative kernel (default)
                             1: one event per lane, no cooperation (reference) */
     int waves_per_simd;  /* wave kernel register budget: 2, 3 or 4 resident
-                            waves per SIMD (0: 2) */
+                            waves per SIMD (0: 2); blocks of at most 512
+                            threads at 2, 384 at 3 with retained trials, 256
+                            otherwise */
     int tail_every;      /* wave kernel: once the queue is empty, repack live
                             events into the block's first waves every this
                             many cycles (0: off) */
@@ -143,7 +145,7 @@ typedef struct {
                             with word (2i+side) mod 4 of block (id, j,
                             (2i+side)/4); initial draws at cycle 0, redraws at
                             the cycle after the one they replace.  Wave kernel
-                            at 2 waves per SIMD only (GAPS_EINVAL otherwise). */
+                            at 2 or 3 waves per SIMD (GAPS_EINVAL otherwise). */
 } gaps_params;
 
 /* Create a context: validates the configuration, uploads the PDF grid and

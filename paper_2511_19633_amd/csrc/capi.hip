@@ -267,15 +267,16 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   }
   const int wps = P.waves_per_simd > 0 ? P.waves_per_simd : 2;
   if (wps < 2 || wps > 4) return GAPS_EINVAL;
-  if (P.retain != 0 && (P.retain != 1 || P.variant != 0 || wps != 2)) return GAPS_EINVAL;
-  // the 2-wave kernel compacts its tail across up to 8 waves of a block
-  const int max_block = (P.variant == 0 && wps == 2) ? 512 : 256;
+  if (P.retain != 0 && (P.retain != 1 || P.variant != 0 || wps > 3)) return GAPS_EINVAL;
+  // the 2-wave kernels compact their tail across up to 8 waves of a block
+  const int max_block = (P.variant == 0 && wps == 2) ? 512 : (P.retain && wps == 3) ? 384 : 256;
   pl.block = P.block > 0 ? P.block : max_block;
   if (pl.block % 64 != 0 || pl.block > max_block) return GAPS_EINVAL;
   if (P.grid < 0 || P.compact_every < 0 || P.tail_every < 0) return GAPS_EINVAL;
-  pl.dyn = P.variant == 1 ? 0 : (size_t)pl.block * gaps::kLaneStateBytes;
+  // the lane-state pool is used only by tail repacking
+  pl.dyn = (P.variant == 1 || P.tail_every == 0) ? 0 : (size_t)pl.block * gaps::kLaneStateBytes;
   pl.kern = P.variant == 1 ? (const void*)gaps::k_shower_lanes
-            : P.retain     ? (const void*)gaps::k_shower_wave_rt
+            : P.retain     ? (wps == 3 ? (const void*)gaps::k_shower_wave_rt3 : (const void*)gaps::k_shower_wave_rt)
             : wps == 2     ? (const void*)gaps::k_shower_wave
             : wps == 3     ? (const void*)gaps::k_shower_wave3
                            : (const void*)gaps::k_shower_wave4;

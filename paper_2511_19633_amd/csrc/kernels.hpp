@@ -75,6 +75,7 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
 __global__ void k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave_rt(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_shower_wave_rt3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave4(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 // a chunk of a stream's batch table, passed by value (fits the kernel-argument space)

@@ -1057,6 +1057,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 k_shower_wave_rt(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
   shower_wave_body<true>(C, in, out, S, A);
 }
+// retained trials at three waves per SIMD (blocks of 384 threads, two per CU)
+__global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(3)))
+k_shower_wave_rt3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
+  shower_wave_body<true>(C, in, out, S, A);
+}
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_shower_wave3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A) {
   shower_wave_body<false>(C, in, out, S, A);

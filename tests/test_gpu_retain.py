@@ -66,7 +66,8 @@ def test_retained_ragged_overflow_and_scheduling(gpu, oracles):
     gin = G.hard_events(0, n, 11)
     a = G.shower(gin, 5, block=512, retain=True).to_host()
     for kw in (dict(block=64, grid=7), dict(block=128, compact_every=1), dict(compact_every=33),
-               dict(tail_every=16), dict(tail_every=3, block=256)):
+               dict(tail_every=16), dict(tail_every=3, block=256), dict(waves_per_simd=3),
+               dict(waves_per_simd=3, block=128, tail_every=5)):
         _same(a, G.shower(gin, 5, retain=True, **kw).to_host(), kw)
 
 
@@ -74,7 +75,7 @@ def test_retained_rejects_other_kernels(gpu):
     from paper_2511_19633_amd import binding
     G = gpu["nlo"]
     gin = G.hard_events(0, 64, 1)
-    for kw in (dict(variant=1), dict(waves_per_simd=3)):
+    for kw in (dict(variant=1), dict(waves_per_simd=4), dict(waves_per_simd=3, block=448)):
         with pytest.raises(binding.GapsError):
             G.shower(gin, 1, retain=True, **kw)
 
