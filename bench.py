@@ -171,7 +171,7 @@ def timed_stream(G, binding, batches, seed, args, kw, mode):
         graph.close()
     n = sum(b[2] for b in batches)
     return {"wall_s": wall, "launch_ms": launch_ms, "events": n, "stats": stats.cpu().numpy().astype(float),
-            "launches": 1 if args.launch == "stream" else K}
+            "launches": 1 if args.launch == "stream" else len(batches)}
 
 
 def shower_stats(st, nev, nfin, overflow):
@@ -195,6 +195,9 @@ def main():
     ap.add_argument("--mode", choices=["learned", "plain"], default="learned",
                     help="learned: train the bound first and report the learned shower as `value`, "
                          "the plain shower beside it; plain: the plain shower only")
+    ap.add_argument("--batches", choices=["even", "uneven"], default="even",
+                    help="even: one batch of --events per step; uneven: the same events in batches of "
+                         "10^4..5*10^5 (uniform sizes, seed 1) streamed through the same launch")
     ap.add_argument("--launch", choices=["stream", "per-step"], default="stream",
                     help="stream: the timed steps' batches go through one graph-captured persistent "
                          "launch; per-step: one launch per step")
@@ -240,11 +243,15 @@ def main():
 
     # hard events of every step (ids k*n .. (k+1)*n-1); timed separately, not part of the metric
     t0 = time.perf_counter()
-    ins = [G.hard_events(k * n, n, seed, max_slots=8) for k in range(K)]
+    # even: K batches of n events; uneven: the same n*K events in batches whose
+    # sizes are uniform integers in [10^4, 5*10^5] (the last one truncated)
+    sizes = workloads.batch_sizes(n * K, seed=1) if args.batches == "uneven" else [n] * K
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    ins = [G.hard_events(int(a), int(m), seed, max_slots=8) for a, m in zip(starts, sizes)]
     torch.cuda.synchronize()
     t_hard = (time.perf_counter() - t0) / K
-    outs = [binding.DeviceEvents(n, workloads.MAX_SLOTS) for _ in range(K)]
-    batches = [(ins[k], outs[k], n) for k in range(K)]
+    outs = [binding.DeviceEvents(int(m), workloads.MAX_SLOTS) for m in sizes]
+    batches = [(ins[k], outs[k], int(sizes[k])) for k in range(len(sizes))]
     kernel = {1: "k_shower_lanes", 0: {0: "k_shower_wave", 2: "k_shower_wave", 3: "k_shower_wave3",
                                        4: "k_shower_wave4"}[args.waves_per_simd]}[args.variant]
     if args.trials == "retain":
@@ -346,6 +353,7 @@ def main():
                                "toy PDF grid 100x50), one step = one batch of 10^6 events with its own ids, "
                                "FP64 kinematics, up to 128 partons per event",
                    "events_per_step": n, "mode": args.mode, "trials": args.trials, "launch": args.launch,
+                   "batches": args.batches, "n_batches": len(batches),
                    "max_slots": workloads.MAX_SLOTS, "kernel": kernel, "block": args.block or "auto",
                    "compact_every": args.compact_every or 4},
         "roofline": roof,
