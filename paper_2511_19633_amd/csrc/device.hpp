@@ -321,6 +321,72 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
   return t;
 }
 
+// Initial-state channels (type IF or II) whose emitter has flavour pidi, from a
+// table of per-term constants R(entry): the terms in the order term_at
+// enumerates them (family A then B for a quark; C then D over the flavours
+// 1..nf, -1..-nf for a gluon).  Every term's constant is loaded first
+// (independent loads), then the products are summed in term order: the total
+// constant c, or the term a uniform draw of c picks.
+template <class Tab>
+__device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, Tab R_of, double (&R)[kMaxTerms]) {
+  const bool ii = type == kII;
+  if (pidi == 21) {
+    const int nt = 1 + 2 * C.nf;
+    R[0] = R_of(ent_s1(famC, 0));
+#pragma unroll
+    for (int m = 1; m < kMaxTerms; ++m) {
+      R[m] = 0.0;
+      if (m < nt) {
+        const int a = m <= C.nf ? m : -(m - C.nf);
+        const int T = pdf_tab(a);
+        R[m] = R_of(ii ? ent_s3(famD, T) : ent_s1(famD, T));
+      }
+    }
+    return nt;
+  }
+  const int T = pdf_tab(pidi);
+  R[0] = R_of(ent_s1(famA, T));
+  R[1] = R_of(ii ? ent_s3(famB, T) : ent_s1(famB, T));
+#pragma unroll
+  for (int m = 2; m < kMaxTerms; ++m) R[m] = 0.0;
+  return 2;
+}
+
+template <class Tab>
+__device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, double I1, double I2, Tab R_of) {
+  const double af = C.as_over / (2.0 * kPi) * C.over_scale;
+  double R[kMaxTerms];
+  const int nt = is_terms_load(C, type, pidi, R_of, R);
+  double c = 0.0;
+  c += af * R[0] * I1;
+#pragma unroll
+  for (int m = 1; m < kMaxTerms; ++m)
+    if (m < nt) c += af * R[m] * I2;
+  return c;
+}
+
+// The term of an initial-state channel whose running sum of constants (in
+// term order) first exceeds target, and its constant; -1 if none does.
+template <class Tab>
+__device__ __forceinline__ int is_terms_pick(const Cfg& C, int type, int pidi, double I1, double I2, double target,
+                                             Tab R_of, double& Rsel) {
+  const double af = C.as_over / (2.0 * kPi) * C.over_scale;
+  double R[kMaxTerms];
+  const int nt = is_terms_load(C, type, pidi, R_of, R);
+  int sel = -1;
+  Rsel = 0.0;
+  double cum = 0.0;
+  cum += af * R[0] * I1;
+  if (target < cum) { sel = 0; Rsel = R[0]; }
+#pragma unroll
+  for (int m = 1; m < kMaxTerms; ++m)
+    if (sel < 0 && m < nt) {
+      cum += af * R[m] * I2;
+      if (target < cum) { sel = m; Rsel = R[m]; }
+    }
+  return sel;
+}
+
 // Channel constants of dipole end (i, side) with spectator k: invariant,
 // momentum fractions, kinematic limit (appendix B), the widest z range (at the
 // cutoff), and the total overestimate c of G = c/t (appendix A.1).
@@ -384,32 +450,21 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
   ch.I1 = shape_int(sh1, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi);
   ch.I2 = shape_int(sh2, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi);
   ch.nterm = n_terms(ch, C.nf);
-  double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double c = 0.0;
-  for (int m = 0; m < ch.nterm; ++m) {
-    Term t = term_at(C, ch, m);
-    c += af * t.coefR * t.I;
+  if (isE) {
+    const int eb = ch.ebin;
+    c = is_terms_c(C, ch.type, ch.pidi, ch.I1, ch.I2, [&](int ent) { return C.bound[ent * kNB + eb]; });
+  } else {
+    double af = C.as_over / (2.0 * kPi) * C.over_scale;
+    for (int m = 0; m < ch.nterm; ++m) {
+      Term t = term_at(C, ch, m);
+      c += af * t.coefR * t.I;
+    }
   }
   if (!(c > 0.0)) return;
   ch.c = c;
   ch.invc = 1.0 / c;
   ch.alive = 1;
-}
-
-// Splitting family (term) of the winner in proportion to the overestimates
-__device__ inline Term select_term(const Cfg& C, const Chan& ch, double u) {
-  double af = C.as_over / (2.0 * kPi) * C.over_scale;
-  double target = u * ch.c, cum = 0.0;
-  for (int m = 0; m < ch.nterm; ++m) {
-    Term t = term_at(C, ch, m);
-    cum += af * t.coefR * t.I;
-    if (target < cum) return t;
-  }
-  for (int m = ch.nterm - 1; m >= 0; --m) {
-    Term t = term_at(C, ch, m);
-    if (af * t.coefR * t.I > 0.0) return t;
-  }
-  return term_at(C, ch, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,41 +476,52 @@ __device__ __forceinline__ double learned_R(const Cfg& C, int ent, int ebin, int
   return C.learn[((ent - kIS0) * kNB + ebin) * kNTB + k];
 }
 
-// constant of cell k of an initial-state channel (type IF or II) whose emitter
-// has flavour pidi: its terms in the order term_at enumerates them (family A
-// then B for a quark; C then D over the flavours 1..nf, -1..-nf for a gluon)
-__device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k) {
-  const double af = C.as_over / (2.0 * kPi) * C.over_scale;
-  const bool ii = type == kII;
-  // every term's constant first (independent loads), then the sum in order
-  double R[kMaxTerms];
-  int nt;
-  if (pidi == 21) {
-    nt = 1 + 2 * C.nf;
-    R[0] = learned_R(C, ent_s1(famC, 0), ebin, k);
-#pragma unroll
-    for (int m = 1; m < kMaxTerms; ++m) {
-      R[m] = 0.0;
-      if (m < nt) {
-        const int a = m <= C.nf ? m : -(m - C.nf);
-        const int T = pdf_tab(a);
-        R[m] = learned_R(C, ii ? ent_s3(famD, T) : ent_s1(famD, T), ebin, k);
-      }
+// Splitting family (term) of the winner in proportion to the overestimates.
+// A learned channel (lrn) draws from its constant ck in cell k, and the chosen
+// term carries its cell constant; if rounding leaves the draw past every term,
+// the last term of positive weight in the analytic bound.
+__device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool lrn, int k, double ck) {
+  double af = C.as_over / (2.0 * kPi) * C.over_scale;
+  double target = u * (lrn ? ck : ch.c), cum = 0.0;
+  if (ch.type == kIF || ch.type == kII) {
+    const int eb = ch.ebin;
+    double Rsel;
+    const int m = is_terms_pick(C, ch.type, ch.pidi, ch.I1, ch.I2, target, [&](int ent) {
+      return lrn ? learned_R(C, ent, eb, k) : C.bound[ent * kNB + eb];
+    }, Rsel);
+    if (m >= 0) {
+      Term t = term_at(C, ch, m);
+      t.coefR = Rsel;
+      return t;
     }
   } else {
-    nt = 2;
-    const int T = pdf_tab(pidi);
-    R[0] = learned_R(C, ent_s1(famA, T), ebin, k);
-    R[1] = learned_R(C, ii ? ent_s3(famB, T) : ent_s1(famB, T), ebin, k);
-#pragma unroll
-    for (int m = 2; m < kMaxTerms; ++m) R[m] = 0.0;
+    for (int m = 0; m < ch.nterm; ++m) {
+      Term t = term_at(C, ch, m);
+      cum += af * t.coefR * t.I;
+      if (target < cum) return t;
+    }
   }
-  double c = 0.0;
-  c += af * R[0] * I1;
-#pragma unroll
-  for (int m = 1; m < kMaxTerms; ++m)
-    if (m < nt) c += af * R[m] * I2;
-  return c;
+  for (int m = ch.nterm - 1; m >= 0; --m) {
+    Term t = term_at(C, ch, m);
+    if (af * t.coefR * t.I > 0.0) {
+      if (lrn) t.coefR = learned_R(C, t.ent, ch.ebin, k);
+      return t;
+    }
+  }
+  Term t = term_at(C, ch, 0);
+  if (lrn) t.coefR = learned_R(C, t.ent, ch.ebin, k);
+  return t;
+}
+
+__device__ __forceinline__ Term select_term(const Cfg& C, const Chan& ch, double u) {
+  return select_term(C, ch, u, false, 0, 0.0);
+}
+
+
+// constant of cell k of an initial-state channel (type IF or II) whose emitter
+// has flavour pidi, from the cell constants of its terms
+__device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k) {
+  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); });
 }
 
 // the cell of a scale: the largest k with edge[k] < ln t (0 if none), and its
@@ -471,30 +537,6 @@ __device__ __forceinline__ int cell_of(const Cfg& C, double lnt, double& edge) {
     }
   }
   return k;
-}
-
-// select_term with the cell constants (ck: the channel's constant in cell k);
-// the chosen term carries its cell R
-__device__ inline Term select_term_cell(const Cfg& C, const Chan& ch, double u, int k, double ck) {
-  const double af = C.as_over / (2.0 * kPi) * C.over_scale;
-  const double target = u * ck;
-  double cum = 0.0;
-  for (int m = 0; m < ch.nterm; ++m) {
-    Term t = term_at(C, ch, m);
-    t.coefR = learned_R(C, t.ent, ch.ebin, k);
-    cum += af * t.coefR * t.I;
-    if (target < cum) return t;
-  }
-  for (int m = ch.nterm - 1; m >= 0; --m) {
-    Term t = term_at(C, ch, m);
-    if (af * t.coefR * t.I > 0.0) {
-      t.coefR = learned_R(C, t.ent, ch.ebin, k);
-      return t;
-    }
-  }
-  Term t = term_at(C, ch, 0);
-  t.coefR = learned_R(C, t.ent, ch.ebin, k);
-  return t;
 }
 
 // transverse momentum of size sqrt(tp) at azimuth phi, orthogonal to pa, pb

@@ -919,7 +919,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         double u[4];
         rng4(A.seed, strm, id, cycle, 0xFFFFFFFFu, u);
         // a learned channel's cached c is that of its current cell (the winner's)
-        const Term tm = lch ? select_term_cell(C, ch, u[0], wcell, ch.c) : select_term(C, ch, u[0]);
+        const Term tm = select_term(C, ch, u[0], lch, wcell, ch.c);
         double z, omz;
         shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
         const double phi = 2.0 * kPi * u[2];
