@@ -67,13 +67,17 @@ def cpu_baseline(cfg, n_sample, seed, retain):
                       f"{threads} threads over contiguous id ranges, {dt:.2f} s wall"}
 
 
+SHOWER_SOURCES = ("capi.hip", "device.hpp", "kernels.hpp", "shower_wave.hip")
+
+
 def source_hash():
-    """Hash of the shower kernel sources: a stored traffic figure is used only
-    while it matches (the counters describe one build of the kernel)."""
+    """Hash of the shower kernel's sources (its device code, record layouts and
+    launch plan): a stored traffic figure is used only while it matches (the
+    counters describe one build of the kernel)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_19633_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in SHOWER_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
@@ -118,7 +122,6 @@ def learned_pipeline(G, binding, args, seed):
     del hin
     t0 = time.perf_counter()
     x, y, ent = G.mlp_features(rows)
-    del rows
     ntr = int(0.8 * x.shape[0])
     loss = G.mlp_train(x[:ntr], y[:ntr], steps=args.train_steps, batch=args.train_batch, lr=3e-3, tau=0.999,
                        seed=seed)
@@ -131,11 +134,27 @@ def learned_pipeline(G, binding, args, seed):
     G.mlp_tabulate()
     torch.cuda.synchronize()
     rep["calibrate_tabulate_s"] = time.perf_counter() - t0
-    tab = G.learned_table()
-    rep["mean_bound_over_analytic"] = float(np.mean(tab[tab > 0] / np.repeat(
-        G.bounds()[8:72, :, None], 8, axis=2)[tab > 0]))
+    rep["mean_bound_over_analytic"] = bound_over_analytic(G)
     del x, y, ent
-    return rep
+    return rep, rows
+
+
+def bound_over_analytic(G):
+    """Mean over the cells of the current learned table of its ratio to the analytic bound."""
+    tab = G.learned_table()
+    R = np.repeat(G.bounds()[8:72, :, None], 8, axis=2)
+    return float(np.mean(tab[tab > 0] / R[tab > 0]))
+
+
+def chi_vs_plain(h_plain, h_other):
+    """chi^2 of two sets of weighted histograms (sum w, sum w^2) bin by bin."""
+    from scipy import stats as sstats
+    chi = {}
+    for name, (a, a2), (b, b2) in zip(("z_pt", "phi_star", "n_jets"), h_plain, h_other):
+        m = (a2 + b2) > 0
+        c2, ndf = float(np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m]))), int(max(m.sum(), 1))
+        chi[name] = {"chi2_ndf": c2 / ndf, "ndf": ndf, "p_value": float(sstats.chi2.sf(c2, ndf))}
+    return chi
 
 
 def timed_stream(G, binding, batches, seed, args, kw, mode):
@@ -211,6 +230,9 @@ def main():
     ap.add_argument("--no-paper-form", action="store_true",
                     help="with --trials retain: skip timing the same batches with every channel redrawn each "
                          "cycle (the paper's form of the competition), reported under \"paper_form\"")
+    ap.add_argument("--no-cellmax", action="store_true",
+                    help="with --mode learned: skip timing the cell-maximum bound (the non-learned comparator "
+                         "built from the same logged trials), reported under \"cellmax\"")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
@@ -299,20 +321,14 @@ def main():
     t_obs = (time.perf_counter() - t0) / K  # observables and histograms of one step
     log(f"plain: {v_plain:.4g} events/s")
     if args.mode == "learned":
-        rep = learned_pipeline(G, binding, args, seed)
+        rep, log_rows = learned_pipeline(G, binding, args, seed)
         log(f"trained bound: {rep}")
         r_l = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
         v_l, ms_l, roof_l, st_l = summarise(r_l, "learned")
         # a weight above its bound that was used without the plain fallback
         unhandled = int(sum(((o.flags.to(torch.int64) & binding.F_VIOL) != 0).sum().item() for o in outs))
         log(f"learned: {v_l:.4g} events/s")
-        h_l = histos()
-        from scipy import stats as sstats
-        chi = {}
-        for name, (a, a2), (b, b2) in zip(("z_pt", "phi_star", "n_jets"), h_plain, h_l):
-            m = (a2 + b2) > 0
-            c2, ndf = float(np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m]))), int(max(m.sum(), 1))
-            chi[name] = {"chi2_ndf": c2 / ndf, "ndf": ndf, "p_value": float(sstats.chi2.sf(c2, ndf))}
+        chi = chi_vs_plain(h_plain, histos())
         value, ms_per_step, roof, stats_main = v_l, ms_l, roof_l, st_l
         out_extra["plain"] = {"value": v_plain, "ms_per_step": ms_plain, "roofline": roof_plain,
                               "shower_stats": st_plain}
@@ -335,6 +351,22 @@ def main():
             log(f"paper form {nm}: {v:.4g} events/s")
             pf[nm] = {"value": v, "ms_per_step": ms, "roofline": rf, "shower_stats": st}
         out_extra["paper_form"] = pf
+    if args.mode == "learned" and not args.no_cellmax:
+        # the non-learned comparator: cell maxima of the same logged trials
+        t0 = time.perf_counter()
+        G.cellmax_table(log_rows, int(0.8 * log_rows.shape[0]))
+        torch.cuda.synchronize()
+        t_tab = time.perf_counter() - t0
+        r = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
+        v, ms, rf, st = summarise(r, "learned")
+        log(f"cell-maximum bound: {v:.4g} events/s")
+        out_extra["cellmax"] = {"value": v, "ms_per_step": ms, "speedup_over_plain": v / v_plain,
+                                "speedup_over_learned": v / v_l, "table_s": t_tab,
+                                "mean_bound_over_analytic": bound_over_analytic(G),
+                                "histogram_chi2_ndf_vs_plain": chi_vs_plain(h_plain, histos()),
+                                "roofline": rf, "shower_stats": st}
+    if args.mode == "learned":
+        del log_rows
 
     out = {
         "metric": "showered events/sec, NLO pp→Z 13 TeV, 1 MI355X; plain vs learned-proposal",

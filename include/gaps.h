@@ -234,6 +234,27 @@ gaps_status gaps_graph_destroy(gaps_graph g);
 #define GAPS_MLP_PARAMS 4545
 #define GAPS_LEARN_CELLS (64 * 48 * 8)
 
+/* Cell-maximum bound (the non-learned comparator of the learned bound): the
+ * same cells and the same check and fallback in LEARNED mode, with each cell's
+ * constant set from presampled trials instead of a network, as adaptive
+ * overestimation does (the paper names it as future work, section 5).  rows:
+ * device [n_fit + n_cal][5] LOG-mode rows (ln t, ln eta, z, entry, ln W); the
+ * first n_fit give each cell (entry, eta bin, ln t cell as the shower takes it)
+ * its largest target y = ln W - ln R (rounded to float) and row count; the
+ * next n_cal (held out) give each entry delta = max(0, largest y - ymax(cell))
+ * + 2^-6 over rows of cells with at least GAPS_CELLMAX_MIN_CELL fitting rows.
+ * A cell with at least GAPS_CELLMAX_MIN_CELL fitting rows in an entry with at
+ * least GAPS_CELLMAX_MIN_CAL such held-out rows gets min(R, R e^v rounded up to
+ * a 7-bit mantissa), v = clip(ymax + delta, -20, 0); every other cell keeps the
+ * analytic R.  The table replaces the context's learned table (read it back
+ * with gaps_learned_table).  Asynchronous on stream; rows must stay valid until
+ * the stream reaches the call.  Errors: GAPS_EINVAL for a NULL context or rows,
+ * n_fit <= 0 or n_cal < 0; GAPS_ENOMEM if its 400 KB of cell counters cannot
+ * be allocated (first call only). */
+#define GAPS_CELLMAX_MIN_CELL 16
+#define GAPS_CELLMAX_MIN_CAL 2000
+gaps_status gaps_cellmax_table(gaps_ctx ctx, const float* rows, int64_t n_fit, int64_t n_cal, hipStream_t stream);
+
 /* Network weights of the context: Philox He-uniform initialisation (key
  * (seed, stream 4)) and zeroed Adam moments.  Synchronous. */
 gaps_status gaps_mlp_init(gaps_ctx ctx, uint64_t seed);

@@ -1,0 +1,78 @@
+"""CPU oracle of the cell-maximum initial-state bound (TEST INFRASTRUCTURE ONLY).
+
+Plain numpy, written from the definitions below; only tests/, the smoke check
+and bench.py's CPU baseline may use it.
+
+The non-learned comparator of the learned bound.  The paper replaces Herwig's
+adaptive overestimates (ExSample) with large fixed ones and names adaptive
+overestimation as future work (section 5); the first half of such a scheme is
+presampling: run trials, record the veto weight each one would have had, and
+set each cell's overestimate from the largest weight seen there.  This module
+does that on the same cells the learned bound uses, so that the shower's
+per-trial check and plain-mode fallback keep it exact in the same way, and the
+two bounds can be compared on the same logged trials.
+
+Cell of a logged trial (ln t, ln eta, z, entry, ln W):
+    (entry - 8, eta bin of ln eta, ln t cell), the ln t cell being the largest
+    k in 1..7 with edge[k] < ln t, else 0 (the cell the shower takes for a scale)
+Target: y = ln W - ln R[entry][eta bin], rounded to float32 (as for the network).
+Fitting rows: ymax[cell] = the largest y, n[cell] = the number of rows.
+Held-out rows, per entry, over cells with n >= MIN_CELL:
+    r_e = the largest y - ymax[cell]; delta_e = max(r_e, 0) + 2^-6,
+    entries with fewer than MIN_CAL such rows keep the analytic bound.
+Table: min(R, up6(R exp(v))), v = clip(ymax + delta_e, -20, 0), for cells with
+n >= MIN_CELL in calibrated entries; R (the analytic bound) elsewhere.
+
+Pinned by tests/test_oracle_cellmax.py (every fitting row covered, closed-form
+cells, calibration raising the bound over held-out rows, untouched cells).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle.mlp import CAL_MARGIN, DLE, IS0, LNETA0, MIN_CAL, NB, NENT_IS, NTB, V_MIN, up6
+
+MIN_CELL = 16
+NCELL = NENT_IS * NB * NTB
+
+
+def cells(rows, bounds, cell_edges):
+    """Cell index, target y (float64 of the float32 value) and entry of each
+    logged trial whose entry is an initial-state one (others are dropped)."""
+    r = np.asarray(rows, dtype=np.float32).reshape(-1, 5).astype(np.float64)
+    lnt, lne, lnw = r[:, 0], r[:, 1], r[:, 4]
+    ent = r[:, 3].astype(np.int64)
+    keep = (ent >= IS0) & (ent < IS0 + NENT_IS)
+    lnt, lne, lnw, ent = lnt[keep], lne[keep], lnw[keep], ent[keep]
+    b = np.floor((lne - LNETA0) / DLE)
+    b = np.where(b >= 0.0, b, 0.0)  # below the first bin, or not a number
+    b = np.minimum(b, NB - 1).astype(np.int64)
+    E = np.asarray(cell_edges, dtype=np.float64)
+    k = np.zeros(lnt.shape, dtype=np.int64)
+    for j in range(1, NTB):
+        k = np.where(E[j] < lnt, j, k)
+    y = (lnw - np.log(np.asarray(bounds, dtype=np.float64)[ent, b])).astype(np.float32).astype(np.float64)
+    return ((ent - IS0) * NB + b) * NTB + k, y, ent
+
+
+def cellmax_table(rows_fit, rows_cal, bounds, cell_edges):
+    """The cell-maximum table [64][48][8] (doubles), the per-entry delta (inf:
+    analytic) and the fitting-row count of each cell."""
+    c, y, _ = cells(rows_fit, bounds, cell_edges)
+    ymax = np.full(NCELL, -np.inf)
+    np.maximum.at(ymax, c, y)
+    n = np.bincount(c, minlength=NCELL)
+    cc, yc, ec = cells(rows_cal, bounds, cell_edges)
+    use = n[cc] >= MIN_CELL
+    e = ec[use] - IS0
+    excess = np.full(NENT_IS, -np.inf)
+    np.maximum.at(excess, e, yc[use] - ymax[cc[use]])
+    ncal = np.bincount(e, minlength=NENT_IS)
+    delta = np.where(ncal >= MIN_CAL, np.maximum(excess, 0.0) + CAL_MARGIN, np.inf)
+    R = np.broadcast_to(np.asarray(bounds, dtype=np.float64)[IS0:IS0 + NENT_IS, :, None], (NENT_IS, NB, NTB))
+    ym = ymax.reshape(NENT_IS, NB, NTB)
+    fitted = (n.reshape(NENT_IS, NB, NTB) >= MIN_CELL) & np.isfinite(delta)[:, None, None] & (R > 0.0)
+    with np.errstate(invalid="ignore", over="ignore"):
+        v = np.clip(ym + delta[:, None, None], V_MIN, 0.0)
+        tab = np.where(fitted, np.minimum(R, up6(R * np.exp(v))), R)
+    return np.ascontiguousarray(tab, dtype=np.float64), delta, n.reshape(NENT_IS, NB, NTB)

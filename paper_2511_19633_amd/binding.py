@@ -102,6 +102,7 @@ def lib():
         L.gaps_mlp_train.argtypes = [vp, vp, vp, i64, C.POINTER(GapsTrainParams), vp, vp]
         L.gaps_mlp_calibrate.argtypes = [vp, vp, vp, vp, i64, vp]
         L.gaps_mlp_set_delta.argtypes = [vp, vp]
+        L.gaps_cellmax_table.argtypes = [vp, vp, i64, i64, vp]
         L.gaps_mlp_get_delta.argtypes = [vp, vp]
         L.gaps_mlp_tabulate.argtypes = [vp, vp]
         L.gaps_learned_table.argtypes = [vp, vp]
@@ -330,6 +331,13 @@ class Gaps:
 
     def mlp_tabulate(self, stream=None):
         _check(lib().gaps_mlp_tabulate(self.h, _stream(stream)))
+
+    def cellmax_table(self, rows, n_fit, stream=None):
+        """Cell-maximum bound from LOG rows (device [n][5] float32): the first
+        n_fit rows fit the cells, the rest calibrate; becomes the learned table."""
+        assert rows.dtype == torch.float32 and rows.is_cuda and rows.dim() == 2 and rows.shape[1] == 5
+        rows = rows.contiguous()
+        _check(lib().gaps_cellmax_table(self.h, _ptr(rows), int(n_fit), int(rows.shape[0] - n_fit), _stream(stream)))
 
     def learned_table(self) -> np.ndarray:
         t = np.zeros(LEARN_SHAPE, dtype=np.float64)

@@ -108,6 +108,9 @@ struct gaps_ctx_s {
   double *delta = nullptr, *table = nullptr;
   unsigned long long *maxbits = nullptr, *count = nullptr;
   float *probe_x = nullptr, *probe_f = nullptr;
+  // cell-maximum bound: per-cell largest target and row count, per-entry
+  // largest held-out excess and row count
+  unsigned long long* cm_mem = nullptr;
   int64_t adam_step = 0;
 };
 
@@ -218,6 +221,7 @@ gaps_status gaps_destroy(gaps_ctx c) {
   free_batches(c->batches);
   if (c->mlp_mem) (void)hipFree(c->mlp_mem);
   if (c->probe_x) (void)hipFree(c->probe_x);
+  if (c->cm_mem) (void)hipFree(c->cm_mem);
   if (c->probe_f) (void)hipFree(c->probe_f);
   delete c;
   return GAPS_OK;
@@ -662,6 +666,28 @@ gaps_status gaps_mlp_tabulate(gaps_ctx c, hipStream_t stream) {
                      c->probe_f);
   hipLaunchKernelGGL(gaps::k_mlp_table, dim3(grid_for(GAPS_LEARN_CELLS, 256)), dim3(256), 0, stream, c->probe_f,
                      c->delta, c->d_bound, c->table);
+  GAPS_HIP(hipGetLastError());
+  c->C.learn = c->table;
+  return GAPS_OK;
+}
+
+gaps_status gaps_cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, int64_t n_cal, hipStream_t stream) {
+  if (!c || !rows || n_fit <= 0 || n_cal < 0) return GAPS_EINVAL;
+  gaps_status s = mlp_alloc(c);
+  if (s != GAPS_OK) return s;
+  const int64_t nc = GAPS_LEARN_CELLS, words = 2 * nc + 2 * 64;
+  if (!c->cm_mem && hipMalloc((void**)&c->cm_mem, (size_t)words * 8) != hipSuccess) return GAPS_ENOMEM;
+  unsigned long long *ymax = c->cm_mem, *cnt = ymax + nc, *emax = cnt + nc, *ecnt = emax + 64;
+  // fill kernels, not memsets, so that the call may be captured in a graph
+  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(grid_for(words, 256)), dim3(256), 0, stream, c->cm_mem, words, 0ull);
+  hipLaunchKernelGGL(gaps::k_cellmax_fit, dim3(grid_for(n_fit, 256) < 2048 ? grid_for(n_fit, 256) : 2048), dim3(256),
+                     0, stream, c->C, rows, n_fit, ymax, cnt);
+  if (n_cal > 0)
+    hipLaunchKernelGGL(gaps::k_cellmax_resid, dim3(grid_for(n_cal, 256) < 1024 ? grid_for(n_cal, 256) : 1024),
+                       dim3(256), 0, stream, c->C, rows + 5 * n_fit, n_cal, ymax, cnt, (long long)GAPS_CELLMAX_MIN_CELL,
+                       emax, ecnt);
+  hipLaunchKernelGGL(gaps::k_cellmax_table, dim3(grid_for(nc, 256)), dim3(256), 0, stream, ymax, cnt, emax, ecnt,
+                     (long long)GAPS_CELLMAX_MIN_CELL, (long long)GAPS_CELLMAX_MIN_CAL, 0.015625, c->d_bound, c->table);
   GAPS_HIP(hipGetLastError());
   c->C.learn = c->table;
   return GAPS_OK;

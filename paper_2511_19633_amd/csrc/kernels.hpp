@@ -109,6 +109,13 @@ __global__ void k_mlp_delta(const unsigned long long* maxbits, const unsigned lo
                             double margin, double* delta);
 __global__ void k_mlp_probes(Cfg C, float* x);
 __global__ void k_mlp_table(const float* f, const double* delta, const double* bound, double* table);
+__global__ void k_cellmax_fit(Cfg C, const float* rows, int64_t n, unsigned long long* ymax, unsigned long long* count);
+__global__ void k_cellmax_resid(Cfg C, const float* rows, int64_t n, const unsigned long long* ymax,
+                                const unsigned long long* count, long long min_cell, unsigned long long* emax,
+                                unsigned long long* ecount);
+__global__ void k_cellmax_table(const unsigned long long* ymax, const unsigned long long* count,
+                                const unsigned long long* emax, const unsigned long long* ecount, long long min_cell,
+                                long long min_cal, double margin, const double* bound, double* table);
 __global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
                             int nbins, double* sumw, double* sumw2);
 

@@ -361,9 +361,14 @@ __global__ void k_mlp_features(const float* rows, int64_t n, const double* bound
 }
 
 namespace {
+// doubles as unsigned keys of the same order (for atomicMax), and back
 __device__ __forceinline__ unsigned long long ord64(double d) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(d);
   return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unord64(unsigned long long o) {
+  const unsigned long long u = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
+  return __longlong_as_double((long long)u);
 }
 }  // namespace
 
@@ -395,9 +400,7 @@ __global__ void k_mlp_delta(const unsigned long long* maxbits, const unsigned lo
   const int q = threadIdx.x;
   if (q >= kNIS) return;
   if ((long long)count[q] < min_count) { delta[q] = INFINITY; return; }
-  const unsigned long long o = maxbits[q];
-  const unsigned long long u = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
-  delta[q] = __longlong_as_double((long long)u) + margin;
+  delta[q] = unord64(maxbits[q]) + margin;
 }
 
 // probe inputs of every cell (entry, eta bin, ln t cell): 3 ln t x 2 ln eta x 8 z
@@ -432,6 +435,91 @@ __global__ void k_mlp_table(const float* f, const double* delta, const double* b
   const double d = delta[e];
   if (!isfinite(d) || !(R > 0.0)) { table[cell] = R; return; }
   double v = d + (double)fm;
+  v = v < -20.0 ? -20.0 : (v > 0.0 ? 0.0 : v);
+  int ex;
+  const double m = frexp(R * exp(v), &ex);
+  const double up = ldexp(ceil(m * 128.0) / 128.0, ex);
+  table[cell] = up < R ? up : R;
+}
+
+// ---------------------------------------------------------------------------
+// Cell-maximum bound: the same cells and shower check as the learned bound,
+// with each cell's constant taken from the largest logged weight in the cell
+// (presampled maxima, the first half of adaptive overestimation) instead of
+// a network.  The non-learned comparator of the learned bound.
+
+namespace {
+// cell of a logged trial (entry, eta bin, ln t cell: the cell the shower
+// takes for that scale) and its target y = ln W - ln R rounded to FP32 like
+// the network's target; -1 for rows outside the initial-state entries
+__device__ __forceinline__ int cm_cell(const Cfg& C, const float* row, double& y) {
+  const double lnt = row[0], lne = row[1], lnw = row[4];
+  const int e = (int)row[3];
+  if (e < kIS0 || e >= kIS0 + kNIS) return -1;
+  const double bb = floor((lne - kLnEta0d) / kDle);
+  const int b = !(bb >= 0.0) ? 0 : (bb > 47.0 ? 47 : (int)bb);
+  double edge;
+  const int k = cell_of(C, lnt, edge);
+  y = (double)(float)(lnw - log(C.bound[e * kNB + b]));
+  return ((e - kIS0) * kNB + b) * kNTB + k;
+}
+}  // namespace
+
+// largest target and row count per cell over the fitting rows
+__global__ void k_cellmax_fit(Cfg C, const float* rows, int64_t n, unsigned long long* ymax,
+                              unsigned long long* count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double y;
+    const int c = cm_cell(C, rows + 5 * i, y);
+    if (c < 0) continue;
+    atomicMax(ymax + c, ord64(y));
+    atomicAdd(count + c, 1ull);
+  }
+}
+
+// largest excess y - ymax(cell) of the held-out rows per entry, over cells
+// with at least min_cell fitting rows, and the number of such rows
+__global__ void k_cellmax_resid(Cfg C, const float* rows, int64_t n, const unsigned long long* ymax,
+                                const unsigned long long* count, long long min_cell, unsigned long long* emax,
+                                unsigned long long* ecount) {
+  __shared__ unsigned long long sm[kNIS], sc[kNIS];
+  for (int q = threadIdx.x; q < kNIS; q += blockDim.x) { sm[q] = 0ull; sc[q] = 0ull; }
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double y;
+    const int c = cm_cell(C, rows + 5 * i, y);
+    if (c < 0 || (long long)count[c] < min_cell) continue;
+    const int e = c / (kNB * kNTB);
+    atomicMax(&sm[e], ord64(y - unord64(ymax[c])));
+    atomicAdd(&sc[e], 1ull);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kNIS; q += blockDim.x) {
+    if (sc[q]) {
+      atomicMax(emax + q, sm[q]);
+      atomicAdd(ecount + q, sc[q]);
+    }
+  }
+}
+
+// the bound of every cell: min(R, up6(R exp(clip(ymax + delta_e, -20, 0))))
+// with delta_e = max(largest excess, 0) + margin, for cells with at least
+// min_cell fitting rows in entries with at least min_cal held-out rows; R
+// (the analytic bound) elsewhere
+__global__ void k_cellmax_table(const unsigned long long* ymax, const unsigned long long* count,
+                                const unsigned long long* emax, const unsigned long long* ecount, long long min_cell,
+                                long long min_cal, double margin, const double* bound, double* table) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= kNIS * kNB * kNTB) return;
+  const int e = cell / (kNB * kNTB), b = (cell / kNTB) % kNB;
+  const double R = bound[(e + kIS0) * kNB + b];
+  if ((long long)count[cell] < min_cell || (long long)ecount[e] < min_cal || !(R > 0.0)) {
+    table[cell] = R;
+    return;
+  }
+  const double r = unord64(emax[e]);
+  const double d = (r > 0.0 ? r : 0.0) + margin;
+  double v = unord64(ymax[cell]) + d;
   v = v < -20.0 ? -20.0 : (v > 0.0 ? 0.0 : v);
   int ex;
   const double m = frexp(R * exp(v), &ex);
