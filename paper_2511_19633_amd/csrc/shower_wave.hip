@@ -70,6 +70,9 @@ __device__ __forceinline__ Rec rec_of(const Scratch& S, int64_t slot) {
 // LDS of one wave for the cooperative channel build: a ring of entries that
 // need their constants set up, and one flag word per lane.
 constexpr int kBuildRing = 128;
+// deferred rebuilds after emissions: build when this many lanes want one, when
+// one has waited this many iterations, or when fewer lanes are left to trial
+constexpr int kDeferLanes = 8, kDeferWait = 4, kDeferMin = 16;
 struct BuildLds {
   uint32_t ring[kBuildRing];  // lane L | particle q << 6 | side << 14 | spectator k << 15
   uint32_t flags[64];
@@ -444,6 +447,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   unsigned long long st_cyc = 0, st_tri = 0, st_acc = 0, st_viol = 0, st_iters = 0, st_active = 0;
   unsigned long long st_fb = 0, st_null = 0;
   int since = 1 << 30;
+  int rwait = 0;  // iterations an emission's rebuild has been deferred
   // the last cycle's accepted emission, whose channels are rebuilt at the top
   // of the next iteration together with the refilled lanes
   bool rebuild = false, em_all = false;
@@ -604,7 +608,22 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     // event before its first cycle; after an emission a non-finite momentum
     // (reported first) or a broken colour line stops the event (its cycle
     // was already counted).
-    const bool built = fresh || rebuild;
+    // A build pass costs about the same for one lane as for many (its memory
+    // round trips), so the rebuilds after emissions wait, without trialing,
+    // until kDeferLanes lanes want one, one has waited kDeferWait iterations,
+    // fewer than kDeferMin other lanes are left to trial, or refilled lanes
+    // are built anyway.  Results do not depend on it (every draw is keyed by
+    // the event id and cycle).
+    bool go = true;
+    {
+      const unsigned long long rm = __ballot(rebuild);
+      if (rm && !__ballot(fresh)) {
+        const bool aged = __ballot(rebuild && rwait >= kDeferWait) != 0ull;
+        go = aged || __popcll(rm) >= kDeferLanes || __popcll(__ballot(active) & ~rm) < kDeferMin;
+      }
+      rwait = rebuild ? rwait + 1 : 0;
+    }
+    const bool built = fresh || (rebuild && go);
     if (built) sec_ok = false;
     {
       const unsigned long long bm = __ballot(built);
@@ -618,7 +637,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         // an event stopped here draws nothing (its draws are not counted)
         if (built && f) { flags |= f; stop = true; }
         else ntri += drawn;
-        rebuild = false;
+        if (built) rebuild = false;
       }
     }
     if (act == 0ull) {
@@ -650,7 +669,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     // winner; the owner lane of each event then merges its groups' winners in
     // entry order with the same rule, which gives the same winner as one pass
     // over all entries.
-    const bool trialing = active && !done;
+    const bool trialing = active && !done && !rebuild;  // a deferred rebuild waits
     const uint32_t strm = lrn ? 1u : 0u;
     int win = -1, wcell = 0;
     bool wexact = false, wnull = false;
