@@ -733,18 +733,22 @@ __device__ inline void do_map(int type, const double* pe, const double* ps, doub
   }
 }
 
-// apply the accepted emission of term m: momenta, flavours and colour tags;
-// the emitted parton is appended at slot n
-__device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, const Term& tm, double z,
-                            double omz, const Veto& v, double phi) {
+// the two map variables of an accepted trial: y (FF), x and 1 - x (FI), x and
+// u (IF) or v (II)
+__device__ __forceinline__ void map_vars(int type, const Veto& v, double& a1, double& a2) {
+  a1 = type == kFF ? v.y : v.x;
+  a2 = type == kFF ? 0.0 : (type == kFI ? v.omx : v.uv);
+}
+
+// apply the accepted emission of splitting kernel kern (flavour flav for the
+// flavour-changing ones) with map variables a1, a2: momenta, flavours and
+// colour tags; the emitted parton is appended at slot n
+__device__ inline void emit_map(const Rec& R, int n, int& maxtag, const Chan& ch, int kern, int flav, double z,
+                                double omz, double a1, double a2, double phi) {
   int i = ch.i, k = ch.k, j = n;
   double pe[4], ps[4], pi[4], pj[4], pk[4];
   R.get(i, pe);
   R.get(k, ps);
-  double a1 = 0.0, a2 = 0.0;
-  if (ch.type == kFF) a1 = v.y;
-  else if (ch.type == kFI) { a1 = v.x; a2 = v.omx; }
-  else { a1 = v.x; a2 = v.uv; }
   do_map(ch.type, pe, ps, ch.s, z, omz, a1, a2, phi, pi, pj, pk);
   if (ch.type == kII) {
     double Kp[4], K[4];
@@ -762,7 +766,6 @@ __device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, co
   R.set(j, pj);
   R.st[R.o(j)] = 1;
   int ec = R.effc(i), ea = R.effa(i), jc = 0, ja = 0;
-  int kern = tm.kern;
   int pidi = R.pid[R.o(i)];
   if (kern == kQQG || kern == kGGG || kern == kA || kern == kC) {
     int N = ++maxtag;
@@ -770,7 +773,7 @@ __device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, co
     else { R.set_eff(i, ec, N); jc = N; ja = ea; }
     R.pid[R.o(j)] = 21;
   } else if (kern == kGQQ) {
-    int f = tm.flav;
+    int f = flav;
     if (ch.side == 0) { R.pid[R.o(i)] = f; R.set_eff(i, ec, 0); R.pid[R.o(j)] = -f; jc = 0; ja = ea; }
     else { R.pid[R.o(i)] = -f; R.set_eff(i, 0, ea); R.pid[R.o(j)] = f; jc = ec; ja = 0; }
   } else if (kern == kB) {
@@ -780,7 +783,7 @@ __device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, co
     else { R.set_eff(i, ec, N); jc = N; ja = 0; }
     R.pid[R.o(i)] = 21;
   } else {  // kD
-    int a = tm.flav;
+    int a = flav;
     if (a > 0) { R.set_eff(i, 0, ea); jc = ec; ja = 0; }
     else { R.set_eff(i, ec, 0); jc = 0; ja = ea; }
     R.pid[R.o(i)] = a;
@@ -788,6 +791,13 @@ __device__ inline void emit(const Rec& R, int n, int& maxtag, const Chan& ch, co
   }
   R.col[R.o(j)] = jc;
   R.acol[R.o(j)] = ja;
+}
+
+__device__ __forceinline__ void emit(const Rec& R, int n, int& maxtag, const Chan& ch, const Term& tm, double z,
+                                     double omz, const Veto& v, double phi) {
+  double a1, a2;
+  map_vars(ch.type, v, a1, a2);
+  emit_map(R, n, maxtag, ch, tm.kern, tm.flav, z, omz, a1, a2, phi);
 }
 
 }  // namespace gaps

@@ -448,6 +448,20 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   unsigned long long st_fb = 0, st_null = 0;
   int since = 1 << 30;
   int rwait = 0;  // iterations an emission's rebuild has been deferred
+  // the accepted emission awaiting its application (pe): channel entry,
+  // splitting kernel and flavour (pe_code), z, 1 - z, azimuth, map variables
+  bool pe = false;
+  uint32_t pe_code = 0u;
+  double pe_z = 0.0, pe_omz = 0.0, pe_phi = 0.0, pe_a1 = 0.0, pe_a2 = 0.0;
+  // apply it: the new parton goes to slot n
+  auto apply_emission = [&]() {
+    Chan ch;
+    chan_from_cache(C, S, R, slot, (int)(pe_code & 0xFFu), ch);
+    emit_map(R, n, maxtag, ch, (int)((pe_code >> 8) & 0xFFu), (int)(int8_t)((pe_code >> 16) & 0xFFu), pe_z, pe_omz,
+             pe_a1, pe_a2, pe_phi);
+    n += 1;
+    pe = false;
+  };
   // the last cycle's accepted emission, whose channels are rebuilt at the top
   // of the next iteration together with the refilled lanes
   bool rebuild = false, em_all = false;
@@ -512,6 +526,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       }
       if (total == 0) break;
       if ((total + 63) / 64 < used) {
+        if (pe) apply_emission();  // the lane state does not carry a pending emission
         if (live) {
           LaneState& X = s_pool[prefix + __popcll(a0 & lanemask_lt(lane))];
           X.e = e; X.id = id; X.slot = slot; X.b = b; X.lrn = lrn; X.T = T; X.lnT = lnT; X.t1 = t1;
@@ -625,6 +640,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     }
     const bool built = fresh || (rebuild && go);
     if (built) sec_ok = false;
+    if (built && pe) apply_emission();
     {
       const unsigned long long bm = __ballot(built);
       if (bm) {
@@ -972,13 +988,19 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
               flags |= fOverflow;
               done = true;
             } else {
-              emit(R, n, maxtag, ch, tm, z, omz, v, phi);
+              // the emission is applied by the next channel build, together
+              // with the other lanes' (one pass of the emission code for all)
+              pe_code = (uint32_t)win | ((uint32_t)tm.kern << 8) | ((uint32_t)(tm.flav & 0xFF) << 16);
+              pe_z = z;
+              pe_omz = omz;
+              pe_phi = phi;
+              map_vars(ch.type, v, pe_a1, pe_a2);
+              pe = true;
               // an initial-initial recoil boosts every final-state momentum
               rebuild = true;
               em_all = ch.type == kII;
               em_i = ch.i;
               em_k = ch.k;
-              n += 1;
               nacc += 1;
               if (t1 == 0.0) t1 = t;
             }
@@ -1000,6 +1022,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         pw = win;
       }
     // ---- finished events: write out and free the lane
+    if (active && done && pe) apply_emission();  // stopped while its rebuild waited
     const bool wout = active && done && loaded;  // partons copied by the wave below
     if (active && done) {
       const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
