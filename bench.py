@@ -387,7 +387,7 @@ def main():
                    "events_per_step": n, "mode": args.mode, "trials": args.trials, "launch": args.launch,
                    "batches": args.batches, "n_batches": len(batches),
                    "max_slots": workloads.MAX_SLOTS, "kernel": kernel, "block": args.block or "auto",
-                   "compact_every": args.compact_every or 4},
+                   "compact_every": args.compact_every or 8},
         "roofline": roof,
         "shower_stats": stats_main,
         "component_s": {"hard_events_per_step": t_hard, "shower_per_step": ms_per_step / 1e3,

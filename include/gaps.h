@@ -112,7 +112,7 @@ typedef struct {
     int block;           /* threads per block, multiple of 64, at most 512 for
                             the 2-wave kernel and 256 otherwise (0: largest) */
     int grid;            /* blocks of the persistent launch (0: fill the GPU) */
-    int compact_every;   /* cycles between wave refills (0: 4) */
+    int compact_every;   /* cycles between wave refills (0: 8) */
     float* trial_log;    /* LOG mode: device [log_cap][5] floats, one row per
                             initial-state winner trial with a positive weight:
                             ln t, ln eta, z, table entry, ln(alpha_s(t)/

@@ -294,7 +294,7 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   gaps::ShowerArgs& A = pl.A;
   A = gaps::ShowerArgs{};
   A.mode = P.mode;
-  A.compact_every = P.compact_every > 0 ? P.compact_every : 4;
+  A.compact_every = P.compact_every > 0 ? P.compact_every : 8;
   A.tail_every = P.tail_every;
   A.stream = 0u;
   A.seed = seed;

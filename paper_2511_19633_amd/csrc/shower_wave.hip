@@ -430,7 +430,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   const int M = S.max_slots;
   const WaveCtx W{C, S, lane, M};
   Rec R = rec_of(S, slot);
-  const int K = A.compact_every > 0 ? A.compact_every : 4;
+  const int K = A.compact_every > 0 ? A.compact_every : 8;
   const unsigned KC = A.tail_every > 0 ? (unsigned)A.tail_every : 16u;
   const bool compact = A.tail_every > 0;
   const bool learned_mode = A.mode == GAPS_MODE_LEARNED;
@@ -500,7 +500,63 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     return true;  // the partons are copied by the whole wave (below)
   };
 
+  bool owed = false;
+  // write out the events of the owed lanes (finished, not yet written): the
+  // headers per lane, then the partons one per lane over the whole wave
+  auto flush_owed = [&]() {
+    if (owed) {
+      const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
+      const gaps_events& out = A.nbatch > 0 ? A.batches[b].out : out1;
+      const int64_t co = out.cap;
+      const int nin = in.n[e];
+      const bool fits = loaded;
+      out.id[e] = id;
+      out.w[e] = in.w[e];
+      out.t_start[e] = in.t_start[e];
+      if (fits) {
+        out.n[e] = n;
+      } else {
+        out.n[e] = nin;
+        for (int q = 0; q < nin && q < out.max_slots && q < in.max_slots; ++q) {
+          const int64_t k = (int64_t)q * co + e, ki = (int64_t)q * in.cap + e;
+          out.E[k] = in.E[ki]; out.px[k] = in.px[ki]; out.py[k] = in.py[ki]; out.pz[k] = in.pz[ki];
+          out.pid[k] = in.pid[ki]; out.col[k] = in.col[ki]; out.acol[k] = in.acol[ki];
+          out.status[k] = in.status[ki];
+        }
+      }
+      if (out.flags) out.flags[e] = flags;
+      if (out.n_cycles) out.n_cycles[e] = cycle;
+      if (out.n_trials) out.n_trials[e] = ntri;
+      if (out.n_accept) out.n_accept[e] = nacc;
+      if (out.n_viol) out.n_viol[e] = nviol;
+      if (out.t1) out.t1[e] = t1;
+      st_cyc += cycle; st_tri += ntri; st_acc += nacc; st_viol += nviol;
+    }
+    {
+      // finished events' partons to their outputs, one parton per lane
+      const int np = owed && loaded ? n : 0;
+      const int incl = wave_incl(np, lane);
+      const int total = __shfl(incl, 63);
+      for (int g0 = 0; g0 < total; g0 += 64) {
+        const int g = g0 + lane;
+        const int L = owner_of(incl, g);
+        const int nL = __shfl(n, L), fL = __shfl(incl, L) - nL, bL = __shfl(b, L);
+        const int64_t sL = __shfl(slot, L), eL = __shfl(e, L);
+        if (g < total) {
+          const gaps_events& out = A.nbatch > 0 ? A.batches[bL].out : out1;
+          const int q = g - fL;
+          const int64_t k = (int64_t)q * out.cap + eL, o = rec_of(S, sL).o(q);
+          const Part pt = S.part[o];
+          out.E[k] = pt.E; out.px[k] = pt.px; out.py[k] = pt.py; out.pz[k] = pt.pz;
+          out.pid[k] = pt.pid; out.col[k] = pt.col; out.acol[k] = pt.acol; out.status[k] = pt.st;
+        }
+      }
+    }
+    owed = false;
+  };
+
   for (unsigned it = 0;; ++it) {
+    if (__ballot(owed) && (exhausted || since >= K || __ballot(active) == 0ull)) flush_owed();
     // ---- tail mode starts when every wave of the block has seen the queue empty
     if (compact && !tail && exhausted) {
       if (!counted) {
@@ -1021,57 +1077,13 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                     ? 1u : 0u;
         pw = win;
       }
-    // ---- finished events: write out and free the lane
+    // ---- finished events: their outputs are owed until the next flush (a
+    // pass for all of them: before the next refill, or at once when the
+    // queue is drained)
     if (active && done && pe) apply_emission();  // stopped while its rebuild waited
-    const bool wout = active && done && loaded;  // partons copied by the wave below
     if (active && done) {
-      const gaps_events& in = A.nbatch > 0 ? A.batches[b].in : in1;
-      const gaps_events& out = A.nbatch > 0 ? A.batches[b].out : out1;
-      const int64_t co = out.cap;
-      const int nin = in.n[e];
-      const bool fits = loaded;
-      out.id[e] = id;
-      out.w[e] = in.w[e];
-      out.t_start[e] = in.t_start[e];
-      if (fits) {
-        out.n[e] = n;
-      } else {
-        out.n[e] = nin;
-        for (int q = 0; q < nin && q < out.max_slots && q < in.max_slots; ++q) {
-          const int64_t k = (int64_t)q * co + e, ki = (int64_t)q * in.cap + e;
-          out.E[k] = in.E[ki]; out.px[k] = in.px[ki]; out.py[k] = in.py[ki]; out.pz[k] = in.pz[ki];
-          out.pid[k] = in.pid[ki]; out.col[k] = in.col[ki]; out.acol[k] = in.acol[ki];
-          out.status[k] = in.status[ki];
-        }
-      }
-      if (out.flags) out.flags[e] = flags;
-      if (out.n_cycles) out.n_cycles[e] = cycle;
-      if (out.n_trials) out.n_trials[e] = ntri;
-      if (out.n_accept) out.n_accept[e] = nacc;
-      if (out.n_viol) out.n_viol[e] = nviol;
-      if (out.t1) out.t1[e] = t1;
-      st_cyc += cycle; st_tri += ntri; st_acc += nacc; st_viol += nviol;
+      owed = true;
       active = false;
-    }
-    {
-      // finished events' partons to their outputs, one parton per lane
-      const int np = wout ? n : 0;
-      const int incl = wave_incl(np, lane);
-      const int total = __shfl(incl, 63);
-      for (int g0 = 0; g0 < total; g0 += 64) {
-        const int g = g0 + lane;
-        const int L = owner_of(incl, g);
-        const int nL = __shfl(n, L), fL = __shfl(incl, L) - nL, bL = __shfl(b, L);
-        const int64_t sL = __shfl(slot, L), eL = __shfl(e, L);
-        if (g < total) {
-          const gaps_events& out = A.nbatch > 0 ? A.batches[bL].out : out1;
-          const int q = g - fL;
-          const int64_t k = (int64_t)q * out.cap + eL, o = rec_of(S, sL).o(q);
-          const Part pt = S.part[o];
-          out.E[k] = pt.E; out.px[k] = pt.px; out.py[k] = pt.py; out.pz[k] = pt.pz;
-          out.pid[k] = pt.pid; out.col[k] = pt.col; out.acol[k] = pt.acol; out.status[k] = pt.st;
-        }
-      }
     }
     since += 1;
   }
