@@ -358,7 +358,7 @@ def main():
         torch.cuda.synchronize()
         t_tab = time.perf_counter() - t0
         r = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
-        v, ms, rf, st = summarise(r, "learned")
+        v, ms, rf, st = summarise(r, "cellmax")
         log(f"cell-maximum bound: {v:.4g} events/s")
         out_extra["cellmax"] = {"value": v, "ms_per_step": ms, "speedup_over_plain": v / v_plain,
                                 "speedup_over_learned": v / v_l, "table_s": t_tab,
