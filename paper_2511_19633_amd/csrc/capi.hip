@@ -446,7 +446,14 @@ gaps_status gaps_graph_destroy(gaps_graph g) {
 gaps_status gaps_observables(gaps_ctx c, const gaps_events* ev, int64_t n, double* obs, hipStream_t stream) {
   if (!c || !obs || bad_events(ev, n, 1)) return GAPS_EINVAL;
   if (n == 0) return GAPS_OK;
-  hipLaunchKernelGGL(gaps::k_observables, dim3(grid_for(n, 64)), dim3(64), 0, stream, c->C, *ev, n, obs);
+  if (c->C.process != 0 && ev->max_slots <= gaps::kObsW) {
+    // pp: one event per wave
+    const int64_t blocks = (n + gaps::kObsWaves - 1) / gaps::kObsWaves;
+    const unsigned grid = (unsigned)(blocks < 2048 ? blocks : 2048);
+    hipLaunchKernelGGL(gaps::k_observables_pp, dim3(grid), dim3(64 * gaps::kObsWaves), 0, stream, c->C, *ev, n, obs);
+  } else {
+    hipLaunchKernelGGL(gaps::k_observables, dim3(grid_for(n, 64)), dim3(64), 0, stream, c->C, *ev, n, obs);
+  }
   GAPS_HIP(hipGetLastError());
   return GAPS_OK;
 }
@@ -456,8 +463,9 @@ gaps_status gaps_histogram(gaps_ctx c, const double* obs, const double* w, int64
   if (!c || !obs || !sumw || !sumw2 || n < 0 || col < 0 || col >= 12 || nbins < 1 || !(hi > lo))
     return GAPS_EINVAL;
   if (n == 0) return GAPS_OK;
-  hipLaunchKernelGGL(gaps::k_histogram, dim3(grid_for(n, 256)), dim3(256), 0, stream, obs, w, n, col, lo, hi, nbins,
-                     sumw, sumw2);
+  const unsigned hg = grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024;
+  const size_t hl = nbins <= gaps::kHistLds ? (size_t)2 * nbins * sizeof(double) : 0;
+  hipLaunchKernelGGL(gaps::k_histogram, dim3(hg), dim3(256), hl, stream, obs, w, n, col, lo, hi, nbins, sumw, sumw2);
   GAPS_HIP(hipGetLastError());
   return GAPS_OK;
 }

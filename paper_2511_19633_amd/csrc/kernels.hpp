@@ -90,6 +90,10 @@ struct BatchChunk {
 };
 __global__ void k_store_batches(BatchChunk ch, gaps_batch* table, int64_t* prefix, int nbatch);
 __global__ void k_observables(Cfg C, gaps_events ev, int64_t n, double* obs);
+// pp observables with one event per wave, for events of at most kObsW slots
+constexpr int kObsW = 128, kObsWaves = 4;
+constexpr int kHistLds = 2048;  // histograms of at most this many bins accumulate in LDS
+__global__ void k_observables_pp(Cfg C, gaps_events ev, int64_t n, double* obs);
 
 // learned bound network (4 -> 64 -> 64 -> 1)
 constexpr int kMlpHidden = 64;

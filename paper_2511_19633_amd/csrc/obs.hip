@@ -17,27 +17,37 @@ __device__ __forceinline__ double pseudorap(const double* p) {
 }
 
 // anti-kT with E-scheme recombination over q[0..n-1] (modified in place);
-// jets written to jets[] sorted by pT (descending)
-__device__ int antikt(double (*q)[4], int n, double R, double (*jets)[4], bool* on) {
+// jets written to jets[] sorted by pT (descending).  Each pseudojet's
+// rapidity, azimuth and 1/pT^2 are computed once (and again after a merge),
+// not for every pair of every step: the same values, so the same clustering.
+__device__ int antikt(double (*q)[4], int n, double R, double (*jets)[4], bool* on, double* yv, double* phv,
+                      double* ipv) {
   int alive = n, nj = 0;
-  for (int i = 0; i < n; ++i) on[i] = true;
+  auto props = [&](int i) {
+    yv[i] = rapidity(q[i]);
+    phv[i] = atan2(q[i][2], q[i][1]);
+    ipv[i] = 1.0 / (q[i][1] * q[i][1] + q[i][2] * q[i][2]);
+  };
+  for (int i = 0; i < n; ++i) {
+    on[i] = true;
+    props(i);
+  }
+  const double iR2 = R * R;
   while (alive > 0) {
     double best = INFINITY;
     int bi = -1, bj = -1;
     for (int i = 0; i < n; ++i) {
       if (!on[i]) continue;
-      double pti2 = q[i][1] * q[i][1] + q[i][2] * q[i][2];
-      double diB = 1.0 / pti2;
+      const double diB = ipv[i];
       if (diB < best) { best = diB; bi = i; bj = -1; }
-      double yi = rapidity(q[i]), phii = atan2(q[i][2], q[i][1]);
+      const double yi = yv[i], phii = phv[i];
       for (int j = i + 1; j < n; ++j) {
         if (!on[j]) continue;
-        double ptj2 = q[j][1] * q[j][1] + q[j][2] * q[j][2];
-        double dy = yi - rapidity(q[j]);
-        double dphi = fabs(phii - atan2(q[j][2], q[j][1]));
+        double dy = yi - yv[j];
+        double dphi = fabs(phii - phv[j]);
         if (dphi > kPi) dphi = 2.0 * kPi - dphi;
         double dR2 = dy * dy + dphi * dphi;
-        double dij = fmin(1.0 / pti2, 1.0 / ptj2) * dR2 / (R * R);
+        double dij = fmin(diB, ipv[j]) * dR2 / iR2;
         if (dij < best) { best = dij; bi = i; bj = j; }
       }
     }
@@ -48,6 +58,7 @@ __device__ int antikt(double (*q)[4], int n, double R, double (*jets)[4], bool* 
     } else {
       for (int m = 0; m < 4; ++m) q[bi][m] += q[bj][m];
       on[bj] = false;
+      props(bi);
     }
     --alive;
   }
@@ -132,6 +143,7 @@ __global__ void __launch_bounds__(64) k_observables(Cfg C, gaps_events ev, int64
   if (e >= n) return;
   double ps[kObsMax][4];
   double jets[kObsMax][4];
+  double yv[kObsMax], phv[kObsMax], ipv[kObsMax];
   bool on[kObsMax];
   double* o = obs + e * kNObs;
   for (int k = 0; k < kNObs; ++k) o[k] = 0.0;
@@ -176,7 +188,7 @@ __global__ void __launch_bounds__(64) k_observables(Cfg C, gaps_events ev, int64
       for (int m = 0; m < 4; ++m) ps[nq][m] = ps[i][m];
       ++nq;
     }
-  int nj = antikt(ps, nq, 0.4, jets, on);
+  int nj = antikt(ps, nq, 0.4, jets, on, yv, phv, ipv);
   int njet = 0, n_eta = 0;
   double j1[4] = {0, 0, 0, 0}, j2[4] = {0, 0, 0, 0};
   double j1pt = 0.0, j2pt = 0.0, j1eta = 0.0;
@@ -210,17 +222,223 @@ __global__ void __launch_bounds__(64) k_observables(Cfg C, gaps_events ev, int64
   }
 }
 
+// ---------------------------------------------------------------------------
+// The pp observables with one event per wave: the event's slots one per lane,
+// its pseudojets in LDS, and every anti-kT step an argmin over all pairs spread
+// over the lanes (each lane the pairs of its pseudojets), reduced over the
+// wave with the serial loop's order as tie-break: the same clustering as the
+// one-thread loop above, without its private arrays.  For events of at most
+// kObsW slots.
+struct ObsWave {
+  double q[kObsW][4];
+  double y[kObsW], ph[kObsW], ip[kObsW];
+  int on[kObsW];
+  int jet[kObsW];  // the pseudojets that became jets, in order (their q is final)
+};
+namespace {
+// the pair (or beam distance) that comes first: smaller distance, then the
+// serial loop's order (emitter i, then beam before pairs, then partner j)
+__device__ __forceinline__ bool obs_before(double v, int i, int j, double bv, int bi, int bj) {
+  return v < bv || (v == bv && (i < bi || (i == bi && j < bj)));
+}
+}  // namespace
+
+__global__ void __launch_bounds__(64 * kObsWaves, 4) k_observables_pp(Cfg C, gaps_events ev, int64_t n, double* obs) {
+  __shared__ ObsWave sw[kObsWaves];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  ObsWave& W = sw[wid];
+  const int64_t nwaves = (int64_t)gridDim.x * kObsWaves;
+  for (int64_t e = (int64_t)blockIdx.x * kObsWaves + wid; e < n; e += nwaves) {
+    int nn = ev.n[e];
+    if (nn > ev.max_slots) nn = ev.max_slots;
+    // ---- slots: momentum balance, leptons (the last of each sign), partons
+    // and the pseudojets above the pT floor, both in slot order
+    double bal[4] = {0.0, 0.0, 0.0, 0.0};
+    double lm[4] = {0.0, 0.0, 0.0, 0.0}, lp[4] = {0.0, 0.0, 0.0, 0.0};
+    int np = 0, nq = 0;
+#pragma unroll
+    for (int h = 0; h < kObsW / 64; ++h) {
+      const int q = h * 64 + lane;
+      double p[4] = {0.0, 0.0, 0.0, 0.0};
+      int st = 0, pid = 0;
+      if (q < nn) {
+        const int64_t k = (int64_t)q * ev.cap + e;
+        p[0] = ev.E[k]; p[1] = ev.px[k]; p[2] = ev.py[k]; p[3] = ev.pz[k];
+        st = ev.status[k];
+        pid = ev.pid[k];
+        for (int m = 0; m < 4; ++m) bal[m] += st > 0 ? p[m] : -p[m];
+      }
+      const bool out = q < nn && st > 0;
+      const unsigned long long mm = __ballot(out && pid == 11), mp = __ballot(out && pid == -11);
+      if (mm) {
+        const int L = 63 - __clzll((long long)mm);
+        for (int m = 0; m < 4; ++m) lm[m] = __shfl(p[m], L);
+      }
+      if (mp) {
+        const int L = 63 - __clzll((long long)mp);
+        for (int m = 0; m < 4; ++m) lp[m] = __shfl(p[m], L);
+      }
+      const bool par = out && pid != 11 && pid != -11 && is_parton(pid);
+      const unsigned long long pm = __ballot(par);
+      np += __popcll(pm);
+      const bool jet = par && p[1] * p[1] + p[2] * p[2] > 1e-18 * C.S;
+      const unsigned long long jm = __ballot(jet);
+      if (jet) {
+        const int i = nq + __popcll(jm & ((1ull << lane) - 1ull));
+        for (int m = 0; m < 4; ++m) W.q[i][m] = p[m];
+      }
+      nq += __popcll(jm);
+    }
+    for (int o = 32; o > 0; o >>= 1)
+      for (int m = 0; m < 4; ++m) bal[m] += __shfl_xor(bal[m], o);
+    __builtin_amdgcn_wave_barrier();
+    // ---- anti-kT, R = 0.4, E-scheme
+    auto props = [&](int i) {
+      W.y[i] = rapidity(W.q[i]);
+      W.ph[i] = atan2(W.q[i][2], W.q[i][1]);
+      W.ip[i] = 1.0 / (W.q[i][1] * W.q[i][1] + W.q[i][2] * W.q[i][2]);
+    };
+    for (int i = lane; i < nq; i += 64) {
+      W.on[i] = 1;
+      props(i);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double iR2 = 0.4 * 0.4;
+    int nj = 0;
+    for (int alive = nq; alive > 0; --alive) {
+      double bv = INFINITY;
+      int bi = 1 << 30, bj = 1 << 30;
+      for (int i = lane; i < nq; i += 64) {
+        if (!W.on[i]) continue;
+        const double diB = W.ip[i];
+        if (obs_before(diB, i, -1, bv, bi, bj)) { bv = diB; bi = i; bj = -1; }
+        const double yi = W.y[i], phii = W.ph[i];
+        for (int j = i + 1; j < nq; ++j) {
+          if (!W.on[j]) continue;
+          double dy = yi - W.y[j];
+          double dphi = fabs(phii - W.ph[j]);
+          if (dphi > kPi) dphi = 2.0 * kPi - dphi;
+          double dR2 = dy * dy + dphi * dphi;
+          double dij = fmin(diB, W.ip[j]) * dR2 / iR2;
+          if (obs_before(dij, i, j, bv, bi, bj)) { bv = dij; bi = i; bj = j; }
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o);
+        const int oi = __shfl_xor(bi, o), oj = __shfl_xor(bj, o);
+        if (obs_before(ov, oi, oj, bv, bi, bj)) { bv = ov; bi = oi; bj = oj; }
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) {
+        if (bj < 0) {
+          W.jet[nj] = bi;
+          W.on[bi] = 0;
+        } else {
+          for (int m = 0; m < 4; ++m) W.q[bi][m] += W.q[bj][m];
+          W.on[bj] = 0;
+          props(bi);
+        }
+      }
+      if (bj < 0) ++nj;
+      __builtin_amdgcn_wave_barrier();
+    }
+    // ---- Z and jet observables (one lane)
+    if (lane == 0) {
+      double* o = obs + e * kNObs;
+      double imb = 0.0;
+      for (int m = 0; m < 4; ++m) imb = fmax(imb, fabs(bal[m]));
+      double Z[4];
+      for (int m = 0; m < 4; ++m) Z[m] = lm[m] + lp[m];
+      o[0] = sqrt(Z[1] * Z[1] + Z[2] * Z[2]);
+      o[1] = rapidity(Z);
+      o[2] = (Z[1] == 0.0 && Z[2] == 0.0) ? 0.0 : atan2(Z[2], Z[1]);
+      double dphi = fabs(atan2(lm[2], lm[1]) - atan2(lp[2], lp[1]));
+      if (dphi > kPi) dphi = 2.0 * kPi - dphi;
+      double cth = tanh(0.5 * (pseudorap(lm) - pseudorap(lp)));
+      o[3] = tan(0.5 * (kPi - dphi)) * sqrt(fmax(0.0, 1.0 - cth * cth));
+      // jets by pT, descending (insertion sort: equal pT keep their order)
+      auto pt2 = [&](int k) { return W.q[k][1] * W.q[k][1] + W.q[k][2] * W.q[k][2]; };
+      for (int i = 1; i < nj; ++i) {
+        const int t = W.jet[i];
+        const double pti = pt2(t);
+        int j = i - 1;
+        while (j >= 0 && pt2(W.jet[j]) < pti) {
+          W.jet[j + 1] = W.jet[j];
+          --j;
+        }
+        W.jet[j + 1] = t;
+      }
+      int njet = 0, n_eta = 0;
+      double j1[4] = {0, 0, 0, 0}, j2[4] = {0, 0, 0, 0};
+      double j1pt = 0.0, j2pt = 0.0, j1eta = 0.0;
+      bool have1 = false;
+      for (int k = 0; k < nj; ++k) {
+        const double* jt = W.q[W.jet[k]];
+        double pt = sqrt(jt[1] * jt[1] + jt[2] * jt[2]);
+        double et = pseudorap(jt);
+        if (fabs(et) < 5.0) {
+          if (n_eta == 0) j1pt = pt;
+          else if (n_eta == 1) j2pt = pt;
+          ++n_eta;
+        }
+        if (pt > 5.0 && !have1) { j1eta = et; have1 = true; }
+        if (pt > 5.0 && fabs(et) < 5.0) {
+          if (njet == 0) { for (int m = 0; m < 4; ++m) j1[m] = jt[m]; }
+          else if (njet == 1) { for (int m = 0; m < 4; ++m) j2[m] = jt[m]; }
+          ++njet;
+        }
+      }
+      o[4] = njet;
+      o[5] = j1pt;
+      o[6] = j1eta;
+      o[7] = j2pt;
+      if (njet >= 2) {
+        double dy = pseudorap(j1) - pseudorap(j2);
+        double dp = fabs(atan2(j1[2], j1[1]) - atan2(j2[2], j2[1]));
+        if (dp > kPi) dp = 2.0 * kPi - dp;
+        o[8] = sqrt(dy * dy + dp * dp);
+      } else {
+        o[8] = -1.0;
+      }
+      o[9] = np;
+      o[10] = imb;
+      o[11] = 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 __global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
                             int nbins, double* sumw, double* sumw2) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double v = obs[e * kNObs + col];
-  if (!(v >= lo && v < hi)) return;
-  int b = (int)((v - lo) / (hi - lo) * nbins);
-  if (b >= nbins) b = nbins - 1;
-  double ww = w ? w[e] : 1.0;
-  atomicAdd(sumw + b, ww);
-  atomicAdd(sumw2 + b, ww * ww);
+  // bins of the block in LDS when they fit (nbins <= kHistLds), one global
+  // atomic per bin per block at the end; else straight to the global bins
+  extern __shared__ double hs[];
+  const bool lds = nbins <= kHistLds;
+  if (lds) {
+    for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x) hs[b] = 0.0;
+    __syncthreads();
+  }
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double v = obs[e * kNObs + col];
+    if (!(v >= lo && v < hi)) continue;
+    int b = (int)((v - lo) / (hi - lo) * nbins);
+    if (b >= nbins) b = nbins - 1;
+    double ww = w ? w[e] : 1.0;
+    if (lds) {
+      atomicAdd(hs + b, ww);
+      atomicAdd(hs + nbins + b, ww * ww);
+    } else {
+      atomicAdd(sumw + b, ww);
+      atomicAdd(sumw2 + b, ww * ww);
+    }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+      if (hs[b] != 0.0) atomicAdd(sumw + b, hs[b]);
+      if (hs[nbins + b] != 0.0) atomicAdd(sumw2 + b, hs[nbins + b]);
+    }
+  }
 }
 
 }  // namespace gaps

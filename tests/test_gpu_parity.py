@@ -289,3 +289,16 @@ def test_observables_parity(gpu, oracles, key, n):
     sw, sw2 = G.histogram(torch.from_numpy(gobs).cuda(), w, 0, 0.0, 50.0 if key != "ee" else 0.5, 25)
     ref, _ = np.histogram(gobs[:, 0], bins=25, range=(0.0, 50.0 if key != "ee" else 0.5), weights=oout.w)
     assert np.allclose(sw.cpu().numpy(), ref, rtol=1e-12, atol=1e-300)
+
+
+def test_observables_both_kernels_agree(gpu):
+    """pp observables of events stored with at most 128 slots (one event per
+    wave) and with more (one event per thread): the same values."""
+    G = gpu["nlo"]
+    gin = G.hard_events(0, 4000, 3)
+    a = G.shower(gin, 5, max_slots=128)
+    b = G.shower(gin, 5, max_slots=160)
+    oa, ob = G.observables(a).cpu().numpy(), G.observables(b).cpu().numpy()
+    cols = [c for c in range(12) if c != 10]
+    assert np.array_equal(oa[:, cols], ob[:, cols])
+    assert np.all(oa[:, 4] >= 0) and oa[:, 9].max() > 8
