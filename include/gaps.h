@@ -146,6 +146,24 @@ typedef struct {
                             (2i+side)/4); initial draws at cycle 0, redraws at
                             the cycle after the one they replace.  Wave kernel
                             at 2 or 3 waves per SIMD (GAPS_EINVAL otherwise). */
+    int gen_select;      /* 1: the generate-select form (section 2 names it as
+                            the alternative to max-veto): each cycle one trial
+                            from the sum of every channel's overestimate, the
+                            channel picked in proportion to its share.  The
+                            scale range is cut into segments where a channel
+                            starts (its limit) or stops (its cutoff); in the
+                            segment [lo, T] the active channels sum to C/t (a
+                            heavy-quark channel's c/(t - m^2) bounded by
+                            c lo/(lo - m^2)/t and thinned back), ln t = ln T +
+                            ln(u0)/C, a null at lo below it (a jump to lo,
+                            without a draw, when no channel is active), the
+                            first channel in entry order whose running share
+                            exceeds u1 C, a heavy-quark trial kept when u2 <
+                            t (lo - m^2)/(lo (t - m^2)), then the usual veto.
+                            u0..u2 from block (id, cycle, 2^32 - 2).  The same
+                            distribution as max-veto, another use of the
+                            random numbers.  Plain mode, variant 1, retain 0
+                            (GAPS_EINVAL otherwise); not streamed. */
 } gaps_params;
 
 /* Create a context: validates the configuration, uploads the PDF grid and

@@ -120,6 +120,20 @@ typedef struct {
      * 4 of block (id, j, (2i+side)/4), the first draws at cycle 0 and the
      * redraws at the cycle that follows the one they replace. */
     int retain;
+    /* gen_select != 0 (plain mode, not with retain): the generate-select form.
+     * Each cycle draws one trial from the sum of every channel's overestimate
+     * and picks the channel in proportion to its share.  The scale range below
+     * T is cut into segments at the scales where a channel starts (its limit
+     * t_lim below T) or stops (its cutoff): in the segment just below T the
+     * active channels (t_cut < T <= t_lim) sum to C/t, with a heavy-quark
+     * channel's c/(t - m^2) bounded by c lo/(lo - m^2) / t over the segment
+     * [lo, T]; the trial is ln t = ln T + ln(u0)/C, a null at lo when below it
+     * (and a jump to lo without a draw when no channel is active), the channel
+     * the first whose running share exceeds u1 C (entry order), a heavy-quark
+     * channel's trial kept with probability t (lo - m^2) / (lo (t - m^2)) < u2
+     * failing, then the usual veto.  Block (id, cycle, 2^32 - 2) gives u0..u2;
+     * the winner block (id, cycle, 2^32 - 1) as in the max-veto forms. */
+    int gen_select;
 } or_opts;
 
 #define OR_LEARN_NTB 8

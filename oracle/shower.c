@@ -568,9 +568,18 @@ static double draw_trial(const or_state* S, const chan_t* C, double T, double ln
  * against the cell constants of the learned table Lt (random-number stream 1)
  * and returns 1, writing nothing, as soon as a weight exceeds its learned bound;
  * the caller then showers the event again in plain mode. */
+/* generate-select: is channel D active just below T, and its share of the sum
+ * over the segment whose lower end is lo */
+static int gs_active(const chan_t* D, double T) {
+    return D->alive && D->tlim > D->tcut && D->tlim >= T && D->tcut < T;
+}
+static double gs_share(const chan_t* D, double lo) {
+    return D->heavy ? D->c * lo / (lo - D->m2) : D->c;
+}
+
 static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint64_t seed,
                       or_events* out, int64_t e_out, ev_t* ev, chan_t* ch, logsink_t* L,
-                      int mode, const double* Lt, int retain) {
+                      int mode, const double* Lt, int retain, int gs) {
     const int learned = mode == OR_MODE_LEARNED;
     const uint32_t stream = learned ? 1u : 0u;
     const int64_t ci = in->cap, co = out->cap;
@@ -617,7 +626,66 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
                     if (key[c] > best) { best = key[c]; win = c; }
                 if (win >= 0) { wnull = knull[win]; wcell = kcell[win]; }
             }
-            for (int c = 0; !retain && c < nch; ++c) {
+            if (gs) {
+                /* generate-select: the segment below T ends at the largest scale
+                 * below T where a channel starts (its limit) or stops (its cutoff) */
+                double lo = -1.0, lnlo = 0.0;
+                int any = 0;
+                for (int c = 0; c < nch; ++c) {
+                    const chan_t* D = &ch[c];
+                    if (!D->alive || !(D->tlim > D->tcut)) continue;
+                    if (D->tlim < T) {
+                        if (D->tlim > lo) { lo = D->tlim; lnlo = D->lntlim; }
+                    } else if (D->tcut < T) {
+                        any = 1;
+                        if (D->tcut > lo) { lo = D->tcut; lnlo = D->lntcut; }
+                    }
+                }
+                if (lo < 0.0) break; /* no channel can emit below T */
+                if (!any) {          /* none active: move to where one starts */
+                    T = lo;
+                    lnT = lnlo;
+                    cycle += 1;
+                    continue;
+                }
+                double Csum = 0.0;
+                for (int c = 0; c < nch; ++c)
+                    if (gs_active(&ch[c], T)) Csum += gs_share(&ch[c], lo);
+                double g[4];
+                or_rng_block(seed, stream, id, cycle, 0xFFFFFFFEu, g);
+                ntri += 1;
+                const double lnt = lnT + log(g[0]) / Csum;
+                if (lnt < lnlo) { /* below the segment: a null at its lower end */
+                    T = lo;
+                    lnT = lnlo;
+                    cycle += 1;
+                    continue;
+                }
+                /* the channel whose running share first exceeds u1 C */
+                const double target = g[1] * Csum;
+                double cum = 0.0;
+                int sel = -1, last = -1;
+                for (int c = 0; c < nch && sel < 0; ++c) {
+                    if (!gs_active(&ch[c], T)) continue;
+                    cum += gs_share(&ch[c], lo);
+                    last = c;
+                    if (target < cum) sel = c;
+                }
+                if (sel < 0) sel = last;
+                if (ch[sel].heavy) { /* thin the bound back to c/(t - m^2) */
+                    const double t = exp(lnt), m2 = ch[sel].m2;
+                    const double keep = (t * (lo - m2)) / (lo * (t - m2));
+                    if (!(g[2] < keep)) {
+                        T = t;
+                        lnT = lnt;
+                        cycle += 1;
+                        continue;
+                    }
+                }
+                best = lnt;
+                win = sel;
+            }
+            for (int c = 0; !retain && !gs && c < nch; ++c) {
                 const chan_t* C = &ch[c];
                 if (!C->alive) continue;
                 double Tch = T < C->tlim ? T : C->tlim;
@@ -772,7 +840,7 @@ typedef struct {
     logsink_t* L;
     int mode;
     const double* Lt;
-    int retain;
+    int retain, gs;
 } job_t;
 
 static void* run_job(void* arg) {
@@ -781,9 +849,9 @@ static void* run_job(void* arg) {
     chan_t* ch = (chan_t*)malloc(sizeof(chan_t) * OR_MAXCH);
     for (int64_t e = J->lo; e < J->hi; ++e) {
         if (J->mode == OR_MODE_LEARNED &&
-            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt, J->retain) == 0)
+            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt, J->retain, 0) == 0)
             continue;
-        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL, J->retain);
+        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL, J->retain, J->gs);
         if (J->mode == OR_MODE_LEARNED && J->out->flags) J->out->flags[e] |= OR_F_FALLBACK;
     }
     free(ev);
@@ -798,6 +866,7 @@ int or_shower_ex(const or_state* S, const or_events* in, int64_t n, uint64_t see
     int mode = opts ? opts->mode : OR_MODE_PLAIN;
     if (mode != OR_MODE_PLAIN && mode != OR_MODE_LOG && mode != OR_MODE_LEARNED) return -1;
     if (mode == OR_MODE_LEARNED && !opts->learned) return -1;
+    if (opts && opts->gen_select && (mode != OR_MODE_PLAIN || opts->retain)) return -1;
     logsink_t sink, *L = NULL;
     if (mode == OR_MODE_LOG) {
         if (!opts->log_count || (opts->log_cap > 0 && !opts->log)) return -1;
@@ -815,6 +884,7 @@ int or_shower_ex(const or_state* S, const or_events* in, int64_t n, uint64_t see
         jobs[k].mode = mode;
         jobs[k].Lt = mode == OR_MODE_LEARNED ? opts->learned : NULL;
         jobs[k].retain = opts ? opts->retain != 0 : 0;
+        jobs[k].gs = opts ? opts->gen_select != 0 : 0;
     }
     if (nthreads == 1) run_job(&jobs[0]);
     else {

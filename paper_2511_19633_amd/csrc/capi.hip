@@ -272,6 +272,8 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   const int wps = P.waves_per_simd > 0 ? P.waves_per_simd : 2;
   if (wps < 2 || wps > 4) return GAPS_EINVAL;
   if (P.retain != 0 && (P.retain != 1 || P.variant != 0 || wps > 3)) return GAPS_EINVAL;
+  if (P.gen_select != 0 && (P.gen_select != 1 || P.variant != 1 || P.retain || P.mode != GAPS_MODE_PLAIN))
+    return GAPS_EINVAL;
   // the 2-wave kernels compact their tail across up to 8 waves of a block
   const int max_block = (P.variant == 0 && wps == 2) ? 512 : (P.retain && wps == 3) ? 384 : 256;
   pl.block = P.block > 0 ? P.block : max_block;
@@ -294,6 +296,7 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   gaps::ShowerArgs& A = pl.A;
   A = gaps::ShowerArgs{};
   A.mode = P.mode;
+  A.gen_select = P.gen_select;
   A.compact_every = P.compact_every > 0 ? P.compact_every : 8;
   A.tail_every = P.tail_every;
   A.stream = 0u;

@@ -49,6 +49,7 @@ constexpr size_t kLaneStateBytes = 96;
 
 struct ShowerArgs {
   int mode;
+  int gen_select;  // one event per lane kernel: the generate-select form
   int compact_every;
   int tail_every;
   uint32_t stream;

@@ -39,11 +39,23 @@ __device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& 
       S.ctr[oc].tl = ch.tlim;
       S.ctr[oc].ltl = ch.lntlim;
       S.ctr[oc].ic = ch.invc;
+      S.ctr[oc].key = ch.c;  // this kernel keeps no pending trials: the slot holds c
       ++m;
     }
   }
   nch = m;
   return 0;
+}
+
+// cutoff (and ln cutoff) and heavy-quark mass^2 of a channel from its type and
+// heavy flavour
+__device__ __forceinline__ void chan_cut(const Cfg& C, int type, int heavy, double& tcut, double& lntcut,
+                                         double& m2) {
+  m2 = 0.0;
+  if (heavy == 1) { tcut = C.tch_c; lntcut = C.ln_tch_c; m2 = C.mc2; }
+  else if (heavy == 2) { tcut = C.tch_b; lntcut = C.ln_tch_b; m2 = C.mb2; }
+  else if (type == kFF) { tcut = C.t_cut; lntcut = C.ln_tc; }
+  else { tcut = C.tc_is; lntcut = C.ln_tcis; }
 }
 
 __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const gaps_events& out,
@@ -81,7 +93,93 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       int win = -1;
       uint32_t curblk = 0xFFFFFFFFu;
       double ub[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int c = 0; c < nch; ++c) {
+      if (A.gen_select) {
+        // generate-select: the segment below T ends at the largest scale below
+        // T where a channel starts (its limit) or stops (its cutoff); its
+        // active channels' shares sum to C, a heavy-quark channel's bound
+        // c lo/(lo - m^2) over the segment
+        double lo = -1.0, lnlo = 0.0;
+        bool any = false;
+        for (int c = 0; c < nch; ++c) {
+          const int64_t oc = (int64_t)R.lane * S.nch + c;
+          const uint32_t info = S.ctr[oc].info;
+          if (!((info >> 21) & 1u)) continue;
+          const double tlim = S.ctr[oc].tl;
+          double tcut, lntcut, m2;
+          chan_cut(C, (info >> 17) & 3u, (info >> 19) & 3u, tcut, lntcut, m2);
+          if (!(tlim > tcut)) continue;
+          if (tlim < T) {
+            if (tlim > lo) { lo = tlim; lnlo = S.ctr[oc].ltl; }
+          } else if (tcut < T) {
+            any = true;
+            if (tcut > lo) { lo = tcut; lnlo = lntcut; }
+          }
+        }
+        if (lo < 0.0) break;  // no channel can emit below T
+        if (!any) {           // none active: move to where one starts
+          T = lo;
+          lnT = lnlo;
+          cycle += 1;
+          continue;
+        }
+        // active channels in entry order: their share of the segment's sum
+        auto share = [&](int c, double& sh) -> bool {
+          const int64_t oc = (int64_t)R.lane * S.nch + c;
+          const uint32_t info = S.ctr[oc].info;
+          if (!((info >> 21) & 1u)) return false;
+          const double tlim = S.ctr[oc].tl;
+          double tcut, lntcut, m2;
+          const int heavy = (info >> 19) & 3u;
+          chan_cut(C, (info >> 17) & 3u, heavy, tcut, lntcut, m2);
+          if (!(tlim > tcut && tlim >= T && tcut < T)) return false;
+          const double cc = S.ctr[oc].key;
+          sh = heavy ? cc * lo / (lo - m2) : cc;
+          return true;
+        };
+        double Csum = 0.0;
+        for (int c = 0; c < nch; ++c) {
+          double sh;
+          if (share(c, sh)) Csum += sh;
+        }
+        double g[4];
+        rng4(seed, stream, id, cycle, 0xFFFFFFFEu, g);
+        ntri += 1;
+        const double lnt = lnT + log(g[0]) / Csum;
+        if (lnt < lnlo) {  // below the segment: a null at its lower end
+          T = lo;
+          lnT = lnlo;
+          cycle += 1;
+          continue;
+        }
+        const double target = g[1] * Csum;
+        double cum = 0.0;
+        int sel = -1, last = -1;
+        for (int c = 0; c < nch && sel < 0; ++c) {
+          double sh;
+          if (!share(c, sh)) continue;
+          cum += sh;
+          last = c;
+          if (target < cum) sel = c;
+        }
+        if (sel < 0) sel = last;
+        const uint32_t sinfo = S.ctr[(int64_t)R.lane * S.nch + sel].info;
+        const int sheavy = (sinfo >> 19) & 3u;
+        if (sheavy) {  // thin the bound back to c/(t - m^2)
+          double tcut, lntcut, m2;
+          chan_cut(C, (sinfo >> 17) & 3u, sheavy, tcut, lntcut, m2);
+          const double t = exp(lnt);
+          const double keep = (t * (lo - m2)) / (lo * (t - m2));
+          if (!(g[2] < keep)) {
+            T = t;
+            lnT = lnt;
+            cycle += 1;
+            continue;
+          }
+        }
+        best = lnt;
+        win = sel;
+      }
+      for (int c = 0; !A.gen_select && c < nch; ++c) {
         int64_t oc = (int64_t)R.lane * S.nch + c;
         uint32_t info = S.ctr[oc].info;
         if (!((info >> 21) & 1u)) continue;

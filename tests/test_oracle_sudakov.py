@@ -87,7 +87,13 @@ def replicate(ev, k, n):
     return out
 
 
-RETAIN = pytest.mark.parametrize("retain", [False, True], ids=["regenerate", "retain"])
+# the forms of the competition: the paper's (every channel draws each cycle),
+# retained trials, and generate-select (one trial from the summed overestimate)
+RETAIN = pytest.mark.parametrize("retain", [False, True, "gs"], ids=["regenerate", "retain", "gen_select"])
+
+
+def _form(retain):
+    return dict(gen_select=True) if retain == "gs" else dict(retain=retain)
 
 
 @pytest.mark.slow
@@ -96,7 +102,7 @@ def test_ff_first_emission_ee(oracles, cfgs, retain):
     o = oracles["ee"]
     n = 20000
     ev = o.hard_events(0, n, 7)
-    out = o.shower(ev, 11, nthreads=8, retain=retain)
+    out = o.shower(ev, 11, nthreads=8, **_form(retain))
     s = 91.2 ** 2
 
     def F(t):
@@ -146,7 +152,7 @@ def test_ii_first_emission_drell_yan(oracles, cfgs, retain):
     k = next(e for e in range(64) if abs(base.pid[0, e]) == 2)
     n = 20000
     ev = replicate(base, k, n)
-    out = o.shower(ev, 5, nthreads=8, retain=retain)
+    out = o.shower(ev, 5, nthreads=8, **_form(retain))
     S = 13000.0 ** 2
     ea, eb = 2 * base.E[0, k] / 13000.0, 2 * base.E[1, k] / 13000.0
     s = ea * eb * S
@@ -167,7 +173,7 @@ def test_fi_if_first_emission_h_event(oracles, cfgs, retain):
     k = pick[0]
     n = 20000
     ev = replicate(base, k, n)
-    out = o.shower(ev, 13, nthreads=8, retain=retain)
+    out = o.shower(ev, 13, nthreads=8, **_form(retain))
     sqS = 13000.0
     pa = np.array([base.E[0, k], base.px[0, k], base.py[0, k], base.pz[0, k]])
     pb = np.array([base.E[1, k], base.px[1, k], base.py[1, k], base.pz[1, k]])
@@ -235,7 +241,7 @@ def test_no_violations_and_conservation(oracles, retain):
     for key, n in (("ee", 3000), ("lo", 1500), ("nlo", 1500)):
         o = oracles[key]
         ev = o.hard_events(0, n, 21)
-        out = o.shower(ev, 21, retain=retain)
+        out = o.shower(ev, 21, **_form(retain))
         assert int(out.n_viol.sum()) == 0, key
         assert int((out.flags & ~np.uint32(records.FLAG_HEVENT)).sum()) == 0, key
         obs = o.observables(out)
@@ -263,8 +269,8 @@ def test_overestimate_scaling_invariance(cfgs, retain):
     o1, o2 = Oracle(cfgs["lo"], 1.0), Oracle(cfgs["lo"], 2.0)
     n = 12000
     ev = o1.hard_events(0, n, 4)
-    a = o1.observables(o1.shower(ev, 1, nthreads=8, retain=retain))
-    b = o2.observables(o2.shower(ev, 2, nthreads=8, retain=retain))
+    a = o1.observables(o1.shower(ev, 1, nthreads=8, **_form(retain)))
+    b = o2.observables(o2.shower(ev, 2, nthreads=8, **_form(retain)))
     for col, edges in ((0, np.array([0, 1, 2, 4, 7, 10, 15, 20, 30, 50, 80, 150, 1e9])),
                        (4, np.arange(-0.5, 6.5, 1.0)),
                        (9, np.arange(-0.5, 30.5, 2.0))):
@@ -296,6 +302,40 @@ def test_retained_trials_match_regenerated(oracles):
         m = (ha + hb) > 0
         chi2 = (((ha - hb) ** 2)[m] / (ha + hb)[m]).sum() / m.sum()
         assert chi2 < 1.6, (name, chi2)
+    oa, ob = o.observables(a), o.observables(b)
+    for col, lo, hi in ((0, 0.0, 60.0), (3, 0.0, 1.0), (4, -0.5, 6.5), (9, 3.5, 30.5)):
+        ha, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w)
+        ha2, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w ** 2)
+        hb, _ = np.histogram(ob[:, col], bins=28, range=(lo, hi), weights=ev.w)
+        hb2, _ = np.histogram(ob[:, col], bins=28, range=(lo, hi), weights=ev.w ** 2)
+        m = (ha2 + hb2) > 0
+        chi2 = np.sum((ha[m] - hb[m]) ** 2 / (ha2[m] + hb2[m])) / m.sum()
+        assert chi2 < 2.0, (col, chi2)  # p < 0.2 % at 28 degrees of freedom
+
+
+@pytest.mark.slow
+def test_generate_select_matches_max_veto(oracles):
+    """Generate-select (one trial per cycle from the sum of every channel's
+    overestimate, the channel picked by its share, nulls where the sum
+    changes) and the paper's max-veto competition draw from the same
+    no-emission probability: on NLO inputs the same distributions of the
+    number of emissions and of the observables, with one draw per cycle.  A
+    share taken over the wrong channels, a missed segment edge or a heavy-quark
+    bound used without thinning would shift them."""
+    o = oracles["nlo"]
+    n = 40000
+    ev = o.hard_events(0, n, 2)
+    a = o.shower(ev, 3, nthreads=8)
+    b = o.shower(ev, 4, nthreads=8, gen_select=True)
+    # one draw per cycle (jumps to the next segment draw nothing): fewer draws
+    # than one per channel per cycle, more cycles than the winners of the
+    # max-veto form (the nulls at segment edges)
+    assert np.all(b.n_trials <= b.n_cycles)
+    assert b.n_trials.mean() < 0.5 * a.n_trials.mean() and b.n_cycles.mean() > a.n_cycles.mean()
+    ha, _ = np.histogram(a.n_accept, np.arange(-0.5, 40.5))
+    hb, _ = np.histogram(b.n_accept, np.arange(-0.5, 40.5))
+    m = (ha + hb) > 0
+    assert (((ha - hb) ** 2)[m] / (ha + hb)[m]).sum() / m.sum() < 1.6
     oa, ob = o.observables(a), o.observables(b)
     for col, lo, hi in ((0, 0.0, 60.0), (3, 0.0, 1.0), (4, -0.5, 6.5), (9, 3.5, 30.5)):
         ha, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w)
