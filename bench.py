@@ -234,8 +234,8 @@ def main():
                     help="with --mode learned: skip timing the cell-maximum bound (the non-learned comparator "
                          "built from the same logged trials), reported under \"cellmax\"")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip timing max-veto and generate-select in the one-event-per-lane kernel on the "
-                         "first two batches, reported under \"competition_forms\"")
+                    help="skip timing max-veto, generate-select and veto-max in the one-event-per-lane "
+                         "kernels on the first two batches, reported under \"competition_forms\"")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
@@ -371,15 +371,17 @@ def main():
     if args.mode == "learned":
         del log_rows
     if not args.no_forms:
-        # the three forms of the competition on the same first two batches,
-        # plain, in the one-event-per-lane kernel (generate-select runs there
-        # only): max-veto with every channel redrawn, generate-select
+        # the three forms of the competition section 2 names, on the same
+        # first two batches, plain, in the one-event-per-lane kernels (the
+        # other two forms run there only): max-veto with every channel
+        # redrawn, generate-select, veto-max
         import argparse as _ap
         a1 = _ap.Namespace(**vars(args))
         a1.launch, a1.warmup = "per-step", 1
         sub = batches[:2]
         forms = {"kernel": "k_shower_lanes", "events": sum(b[2] for b in sub)}
-        for nm, kwf in (("max_veto", dict(variant=1)), ("generate_select", dict(variant=1, gen_select=True))):
+        for nm, kwf in (("max_veto", dict(variant=1)), ("generate_select", dict(variant=1, gen_select=True)),
+                        ("veto_max", dict(variant=1, veto_max=True))):
             r = timed_stream(G, binding, sub, seed, a1, kwf, binding.MODE_PLAIN)
             st = r["stats"]
             forms[nm] = {"value": r["events"] / r["wall_s"], "draws_per_event": st[1] / r["events"],

@@ -164,6 +164,20 @@ typedef struct {
                             distribution as max-veto, another use of the
                             random numbers.  Plain mode, variant 1, retain 0
                             (GAPS_EINVAL otherwise); not streamed. */
+    int veto_max;        /* 1: the veto-max form (section 2 names it beside
+                            max-veto): every channel runs the veto algorithm on
+                            its own from the current scale down to its first
+                            accepted trial, and the largest of these is the
+                            emission, applied without a further veto; after it
+                            every channel runs its loop again.  A cycle is one
+                            emission.  Trial k of channel c (channel order) at
+                            cycle j: its scale from word 0 of block (id, j,
+                            2^31 | c << 20 | k << 1), term, z, azimuth and
+                            acceptance from block (id, j, 2^31 | c << 20 |
+                            k << 1 | 1); more than 2^19 trials in one loop
+                            stop the event (GAPS_F_MAXCYC).  Plain mode,
+                            variant 1, retain 0, gen_select 0 (GAPS_EINVAL
+                            otherwise); not streamed. */
 } gaps_params;
 
 /* Create a context: validates the configuration, uploads the PDF grid and

@@ -134,6 +134,15 @@ typedef struct {
      * failing, then the usual veto.  Block (id, cycle, 2^32 - 2) gives u0..u2;
      * the winner block (id, cycle, 2^32 - 1) as in the max-veto forms. */
     int gen_select;
+    /* veto_max != 0 (plain mode, neither retain nor gen_select): the veto-max
+     * form.  Every channel runs the veto algorithm on its own from T down to
+     * its first accepted trial; the largest of these is the emission (no
+     * further veto).  After it every channel runs its loop again from the
+     * emission's scale.  A cycle is one emission.  Trial k of channel entry c
+     * (in channel order) at cycle j: its scale from word 0 of block (id, j,
+     * 2^31 | c << 20 | k << 1), term, z, azimuth and acceptance from block
+     * (id, j, 2^31 | c << 20 | k << 1 | 1). */
+    int veto_max;
 } or_opts;
 
 #define OR_LEARN_NTB 8

@@ -21,7 +21,7 @@ MODE_PLAIN, MODE_LEARNED, MODE_LOG = 0, 1, 2
 class OrOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("log", C.POINTER(C.c_float)), ("log_cap", C.c_int64),
                 ("log_count", C.POINTER(C.c_int64)), ("learned", C.POINTER(C.c_double)),
-                ("retain", C.c_int), ("gen_select", C.c_int)]
+                ("retain", C.c_int), ("gen_select", C.c_int), ("veto_max", C.c_int)]
 
 
 def build():
@@ -171,16 +171,19 @@ class Oracle:
         lib().or_hard_events(self.h, first_id, n, seed, C.byref(s))
         return ev
 
-    def shower(self, ev_in: records.Events, seed, nthreads=1, max_slots=None, retain=False, gen_select=False):
+    def shower(self, ev_in: records.Events, seed, nthreads=1, max_slots=None, retain=False, gen_select=False,
+               veto_max=False):
         """Plain shower; retain=True: the retained-trial form of the competition;
         gen_select=True: the generate-select form (one trial per cycle from the
-        sum of the overestimates, the channel chosen by its share)."""
+        sum of the overestimates, the channel chosen by its share);
+        veto_max=True: the veto-max form (every channel's own first accepted
+        trial, the largest wins)."""
         out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
         si, so = events_struct(ev_in), events_struct(out)
-        if not retain and not gen_select:
+        if not retain and not gen_select and not veto_max:
             lib().or_shower(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads)
             return out
-        o = OrOpts(MODE_PLAIN, None, 0, None, None, int(retain), int(gen_select))
+        o = OrOpts(MODE_PLAIN, None, 0, None, None, int(retain), int(gen_select), int(veto_max))
         rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
         if rc != 0:
             raise RuntimeError("or_shower_ex failed")

@@ -568,6 +568,68 @@ static double draw_trial(const or_state* S, const chan_t* C, double T, double ln
  * against the cell constants of the learned table Lt (random-number stream 1)
  * and returns 1, writing nothing, as soon as a weight exceeds its learned bound;
  * the caller then showers the event again in plain mode. */
+/* veto-max: trial k of channel entry c at emission cycle j draws its scale
+ * from word 0 of block (id, j, VM_BLOCK(c, k, 0)) and its term, z, azimuth and
+ * acceptance from block (id, j, VM_BLOCK(c, k, 1)) */
+#define VM_BLOCK(c, k, b) (0x80000000u | ((uint32_t)(c) << 20) | ((uint32_t)(k) << 1) | (uint32_t)(b))
+#define VM_MAXTRIALS (1 << 19)
+
+/* the splitting term, z, azimuth and weight of a trial of channel C at scale t
+ * from the four numbers u (plain mode); returns whether it is accepted */
+static int vm_veto(const or_state* S, const ev_t* ev, const chan_t* C, double t, const double* u, term_t* tsel,
+                   double* z, double* omz, double* phi, veto_t* v) {
+    double target = u[0] * C->c, cum = 0.0;
+    int sel = -1;
+    for (int m = 0; m < C->nterm; ++m) {
+        cum += C->term[m].c;
+        if (target < cum) { sel = m; break; }
+    }
+    if (sel < 0)
+        for (int m = C->nterm - 1; m >= 0; --m)
+            if (C->term[m].c > 0.0) { sel = m; break; }
+    *tsel = C->term[sel];
+    shape_sample(tsel->shape, C, shape_int(tsel->shape, C), u[1], z, omz);
+    *phi = 2.0 * OR_PI * u[2];
+    *v = weight(S, ev, C, tsel, t, *z, *omz);
+    return v->ok && u[3] < v->w;
+}
+
+/* veto-max: the first accepted trial of channel entry c below T, by the
+ * channel's own veto loop at emission cycle j; its ln t (-INFINITY: none above
+ * the cutoff) and trial index *kk.  *capped is set when the loop runs out of
+ * trial indices. */
+static double vm_first(const or_state* S, const ev_t* ev, const chan_t* C, int c, double T, double lnT,
+                       uint64_t seed, uint32_t stream, int64_t id, uint32_t j, uint32_t* ntri, uint32_t* nviol,
+                       int* kk, int* capped) {
+    *kk = -1;
+    if (!C->alive) return -INFINITY;
+    double Tch = T < C->tlim ? T : C->tlim;
+    double lnTch = lnT < C->lntlim ? lnT : C->lntlim;
+    for (int k = 0; k < VM_MAXTRIALS; ++k) {
+        if (!(Tch > C->tcut)) return -INFINITY;
+        double ub[4], u[4];
+        or_rng_block(seed, stream, id, j, VM_BLOCK(c, k, 0), ub);
+        *ntri += 1;
+        const double lu = log(ub[0]);
+        double key;
+        if (!C->heavy) key = lnTch + lu * C->invc;
+        else key = log(C->m2 + (Tch - C->m2) * exp(lu * C->invc));
+        if (key < C->lntcut) return -INFINITY;
+        const double t = exp(key);
+        or_rng_block(seed, stream, id, j, VM_BLOCK(c, k, 1), u);
+        term_t tm;
+        double z, omz, phi;
+        veto_t v;
+        const int acc = vm_veto(S, ev, C, t, u, &tm, &z, &omz, &phi, &v);
+        if (v.ok && v.w > 1.0) *nviol += 1;
+        if (acc) { *kk = k; return key; }
+        Tch = t;
+        lnTch = key;
+    }
+    *capped = 1;
+    return -INFINITY;
+}
+
 /* generate-select: is channel D active just below T, and its share of the sum
  * over the segment whose lower end is lo */
 static int gs_active(const chan_t* D, double T) {
@@ -579,7 +641,7 @@ static double gs_share(const chan_t* D, double lo) {
 
 static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint64_t seed,
                       or_events* out, int64_t e_out, ev_t* ev, chan_t* ch, logsink_t* L,
-                      int mode, const double* Lt, int retain, int gs) {
+                      int mode, const double* Lt, int retain, int gs, int vm) {
     const int learned = mode == OR_MODE_LEARNED;
     const uint32_t stream = learned ? 1u : 0u;
     const int64_t ci = in->cap, co = out->cap;
@@ -611,7 +673,45 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
         if (retain)
             for (int c = 0; c < nch; ++c)
                 key[c] = draw_trial(S, &ch[c], T, lnT, seed, stream, id, 0u, learned, Lt, &ntri, &knull[c], &kcell[c]);
-        for (;;) {
+        /* veto-max: every channel runs its own veto loop down to its first
+         * accepted trial; the largest of these is the emission.  A cycle is
+         * one emission; after it every channel runs its loop again. */
+        for (; vm;) {
+            if (cycle >= OR_MAXCYC) { flags |= OR_F_MAXCYC; break; }
+            double best = -INFINITY;
+            int win = -1, wk = -1, capped = 0;
+            uint32_t nv = 0;
+            for (int c = 0; c < nch; ++c) {
+                int k;
+                const double key1 = vm_first(S, ev, &ch[c], c, T, lnT, seed, stream, id, cycle, &ntri, &nv, &k,
+                                             &capped);
+                if (key1 > best) { best = key1; win = c; wk = k; }
+            }
+            if (nv) { nviol += nv; flags |= OR_F_VIOL; }
+            if (capped) { flags |= OR_F_MAXCYC; break; }
+            if (win < 0) break;
+            /* the winner's accepted trial again, from the same numbers */
+            const chan_t* C = &ch[win];
+            const double t = exp(best);
+            double u[4];
+            or_rng_block(seed, stream, id, cycle, VM_BLOCK(win, wk, 1), u);
+            term_t tm;
+            double z, omz, phi;
+            veto_t v;
+            vm_veto(S, ev, C, t, u, &tm, &z, &omz, &phi, &v);
+            if (ev->n + 1 > M) { flags |= OR_F_OVERFLOW; break; }
+            emit(S, ev, C, &tm, z, omz, &v, phi);
+            nacc += 1;
+            if (t1 == 0.0) t1 = t;
+            cycle += 1;
+            int bad = 0;
+            for (int q = 0; q < ev->n; ++q) bad |= !finite4(ev->p[q]);
+            if (bad) { flags |= OR_F_NAN; break; }
+            if (build_channels(S, ev, ch, &nch) < 0) { flags |= OR_F_COLOUR; break; }
+            T = t;
+            lnT = best;
+        }
+        for (; !vm;) {
             if (cycle >= OR_MAXCYC) { flags |= OR_F_MAXCYC; break; }
             /* trial scales of every channel; the winner is the largest.  In
              * learned mode a trial of an initial-state channel that falls below
@@ -840,7 +940,7 @@ typedef struct {
     logsink_t* L;
     int mode;
     const double* Lt;
-    int retain, gs;
+    int retain, gs, vm;
 } job_t;
 
 static void* run_job(void* arg) {
@@ -849,9 +949,9 @@ static void* run_job(void* arg) {
     chan_t* ch = (chan_t*)malloc(sizeof(chan_t) * OR_MAXCH);
     for (int64_t e = J->lo; e < J->hi; ++e) {
         if (J->mode == OR_MODE_LEARNED &&
-            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt, J->retain, 0) == 0)
+            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt, J->retain, 0, 0) == 0)
             continue;
-        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL, J->retain, J->gs);
+        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL, J->retain, J->gs, J->vm);
         if (J->mode == OR_MODE_LEARNED && J->out->flags) J->out->flags[e] |= OR_F_FALLBACK;
     }
     free(ev);
@@ -867,6 +967,7 @@ int or_shower_ex(const or_state* S, const or_events* in, int64_t n, uint64_t see
     if (mode != OR_MODE_PLAIN && mode != OR_MODE_LOG && mode != OR_MODE_LEARNED) return -1;
     if (mode == OR_MODE_LEARNED && !opts->learned) return -1;
     if (opts && opts->gen_select && (mode != OR_MODE_PLAIN || opts->retain)) return -1;
+    if (opts && opts->veto_max && (mode != OR_MODE_PLAIN || opts->retain || opts->gen_select)) return -1;
     logsink_t sink, *L = NULL;
     if (mode == OR_MODE_LOG) {
         if (!opts->log_count || (opts->log_cap > 0 && !opts->log)) return -1;
@@ -885,6 +986,7 @@ int or_shower_ex(const or_state* S, const or_events* in, int64_t n, uint64_t see
         jobs[k].Lt = mode == OR_MODE_LEARNED ? opts->learned : NULL;
         jobs[k].retain = opts ? opts->retain != 0 : 0;
         jobs[k].gs = opts ? opts->gen_select != 0 : 0;
+        jobs[k].vm = opts ? opts->veto_max != 0 : 0;
     }
     if (nthreads == 1) run_job(&jobs[0]);
     else {

@@ -54,7 +54,7 @@ class GapsParams(C.Structure):
     _fields_ = [("mode", C.c_int), ("block", C.c_int), ("grid", C.c_int), ("compact_every", C.c_int),
                 ("trial_log", C.c_void_p), ("log_cap", C.c_int64), ("log_count", C.c_void_p),
                 ("stats", C.c_void_p), ("variant", C.c_int), ("waves_per_simd", C.c_int),
-                ("tail_every", C.c_int), ("retain", C.c_int), ("gen_select", C.c_int)]
+                ("tail_every", C.c_int), ("retain", C.c_int), ("gen_select", C.c_int), ("veto_max", C.c_int)]
 
 
 class GapsBatch(C.Structure):
@@ -215,7 +215,7 @@ class Gaps:
     @staticmethod
     def _params(mode=MODE_PLAIN, block=0, grid=0, compact_every=0, stats=None, trial_log=None,
                 log_count=None, variant=0, waves_per_simd=0, tail_every=0, retain=False,
-                gen_select=False) -> GapsParams:
+                gen_select=False, veto_max=False) -> GapsParams:
         p = GapsParams()
         p.mode, p.block, p.grid, p.compact_every = mode, block, grid, compact_every
         p.variant = variant
@@ -223,6 +223,7 @@ class Gaps:
         p.tail_every = tail_every
         p.retain = int(bool(retain))
         p.gen_select = int(bool(gen_select))
+        p.veto_max = int(bool(veto_max))
         p.stats = stats.data_ptr() if stats is not None else None
         if trial_log is not None:
             p.trial_log = trial_log.data_ptr()

@@ -274,6 +274,9 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   if (P.retain != 0 && (P.retain != 1 || P.variant != 0 || wps > 3)) return GAPS_EINVAL;
   if (P.gen_select != 0 && (P.gen_select != 1 || P.variant != 1 || P.retain || P.mode != GAPS_MODE_PLAIN))
     return GAPS_EINVAL;
+  if (P.veto_max != 0 &&
+      (P.veto_max != 1 || P.variant != 1 || P.retain || P.gen_select || P.mode != GAPS_MODE_PLAIN))
+    return GAPS_EINVAL;
   // the 2-wave kernels compact their tail across up to 8 waves of a block
   const int max_block = (P.variant == 0 && wps == 2) ? 512 : (P.retain && wps == 3) ? 384 : 256;
   pl.block = P.block > 0 ? P.block : max_block;
@@ -281,7 +284,9 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   if (P.grid < 0 || P.compact_every < 0 || P.tail_every < 0) return GAPS_EINVAL;
   // the lane-state pool is used only by tail repacking
   pl.dyn = (P.variant == 1 || P.tail_every == 0) ? 0 : (size_t)pl.block * gaps::kLaneStateBytes;
-  pl.kern = P.variant == 1 ? (const void*)gaps::k_shower_lanes
+  pl.kern = P.variant == 1 ? (P.gen_select ? (const void*)gaps::k_shower_lanes_gs
+                             : P.veto_max ? (const void*)gaps::k_shower_lanes_vm
+                                          : (const void*)gaps::k_shower_lanes)
             : P.retain     ? (wps == 3 ? (const void*)gaps::k_shower_wave_rt3 : (const void*)gaps::k_shower_wave_rt)
             : wps == 2     ? (const void*)gaps::k_shower_wave
             : wps == 3     ? (const void*)gaps::k_shower_wave3
@@ -297,6 +302,7 @@ gaps_status plan_shower(gaps_ctx c, const gaps_params* params, int64_t n, uint64
   A = gaps::ShowerArgs{};
   A.mode = P.mode;
   A.gen_select = P.gen_select;
+  A.veto_max = P.veto_max;
   A.compact_every = P.compact_every > 0 ? P.compact_every : 8;
   A.tail_every = P.tail_every;
   A.stream = 0u;

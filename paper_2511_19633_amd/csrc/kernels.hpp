@@ -50,6 +50,7 @@ constexpr size_t kLaneStateBytes = 96;
 struct ShowerArgs {
   int mode;
   int gen_select;  // one event per lane kernel: the generate-select form
+  int veto_max;    // one event per lane kernel: the veto-max form
   int compact_every;
   int tail_every;
   uint32_t stream;
@@ -74,6 +75,8 @@ __global__ void k_lo_scan(Cfg C, double* w);
 __global__ void k_lo_max(const double* w, int n, double* out);
 __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o);
 __global__ void k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_shower_lanes_gs(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
+__global__ void k_shower_lanes_vm(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave_rt(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);
 __global__ void k_shower_wave_rt3(Cfg C, gaps_events in, gaps_events out, Scratch S, ShowerArgs A);

@@ -58,6 +58,16 @@ __device__ __forceinline__ void chan_cut(const Cfg& C, int type, int heavy, doub
   else { tcut = C.tc_is; lntcut = C.ln_tcis; }
 }
 
+// veto-max: the Philox block of trial k of channel c (b = 0: its scale, 1:
+// term, z, azimuth and acceptance), and the longest loop of one channel
+__device__ __forceinline__ uint32_t vm_block(int c, int k, int b) {
+  return 0x80000000u | ((uint32_t)c << 20) | ((uint32_t)k << 1) | (uint32_t)b;
+}
+constexpr int kVmMaxTrials = 1 << 19;
+
+// FORM 0: max-veto (every channel draws each cycle), 1: generate-select,
+// 2: veto-max; one kernel each, so that each keeps its own register budget
+template <int FORM>
 __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const gaps_events& out,
                            const Rec& R, const Scratch& S, const ShowerArgs& A, unsigned long long* st) {
   const int M = out.max_slots < kMaxSlots ? out.max_slots : kMaxSlots;
@@ -87,13 +97,93 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
     uint32_t cycle = 0;
     const uint64_t seed = A.seed;
     const uint32_t stream = A.stream;
-    for (;;) {
+    // veto-max: every channel runs its own veto loop down to its first
+    // accepted trial; the largest of these is the emission; a cycle is one
+    // emission, after which every channel runs its loop again
+    for (; FORM == 2;) {
+      if (cycle >= kMaxCycles) { flags |= fMaxCyc; break; }
+      double best = -INFINITY;
+      int win = -1, wkern = 0, wflav = 0;
+      double wz = 0.0, womz = 0.0, wphi = 0.0, wa1 = 0.0, wa2 = 0.0;  // the best candidate's emission
+      bool capped = false;
+      for (int c = 0; c < nch && !capped; ++c) {
+        const int64_t oc = (int64_t)R.lane * S.nch + c;
+        const uint32_t info = S.ctr[oc].info;
+        if (!((info >> 21) & 1u)) continue;
+        double tcut, lntcut, m2;
+        const int heavy = (info >> 19) & 3u;
+        chan_cut(C, (info >> 17) & 3u, heavy, tcut, lntcut, m2);
+        double Tch = S.ctr[oc].tl, lnTch = S.ctr[oc].ltl;
+        if (T < Tch) { Tch = T; lnTch = lnT; }
+        const double invc = S.ctr[oc].ic;
+        Chan ch;
+        chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
+        for (int k = 0;; ++k) {
+          if (k >= kVmMaxTrials) { capped = true; break; }
+          if (!(Tch > tcut)) break;
+          double ub[4];
+          rng4(seed, stream, id, cycle, vm_block(c, k, 0), ub);
+          ntri += 1;
+          const double lu = log(ub[0]);
+          double key;
+          if (!heavy) key = lnTch + lu * invc;
+          else key = log(m2 + (Tch - m2) * exp(lu * invc));
+          if (key < lntcut) break;
+          const double t = exp(key);
+          double u[4];
+          rng4(seed, stream, id, cycle, vm_block(c, k, 1), u);
+          const Term tm = select_term(C, ch, u[0]);
+          double z, omz;
+          shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
+          const Veto v = veto_weight(C, R, ch, tm, t, z, omz);
+          if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
+          if (v.ok && u[3] < v.w) {
+            if (key > best) {
+              best = key;
+              win = c;
+              wkern = tm.kern;
+              wflav = tm.flav;
+              wz = z;
+              womz = omz;
+              wphi = 2.0 * kPi * u[2];
+              map_vars(ch.type, v, wa1, wa2);
+            }
+            break;
+          }
+          Tch = t;
+          lnTch = key;
+        }
+      }
+      if (capped) { flags |= fMaxCyc; break; }
+      if (win < 0) break;
+      // the winner's accepted trial, as recorded
+      const uint32_t info = S.ctr[(int64_t)R.lane * S.nch + win].info;
+      Chan ch;
+      chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
+      const double t = exp(best);
+      if (n + 1 > M) { flags |= fOverflow; break; }
+      emit_map(R, n, maxtag, ch, wkern, wflav, wz, womz, wa1, wa2, wphi);
+      n += 1;
+      nacc += 1;
+      if (t1 == 0.0) t1 = t;
+      cycle += 1;
+      bool bad = false;
+      for (int q = 0; q < n; ++q) {
+        const int64_t o = R.o(q);
+        bad |= !(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o]));
+      }
+      if (bad) { flags |= fNaN; break; }
+      if (build_channels(C, R, n, S, nch) < 0) { flags |= fColour; break; }
+      T = t;
+      lnT = best;
+    }
+    for (; FORM != 2;) {
       if (cycle >= kMaxCycles) { flags |= fMaxCyc; break; }
       double best = -INFINITY;
       int win = -1;
       uint32_t curblk = 0xFFFFFFFFu;
       double ub[4] = {0.0, 0.0, 0.0, 0.0};
-      if (A.gen_select) {
+      if constexpr (FORM == 1) {
         // generate-select: the segment below T ends at the largest scale below
         // T where a channel starts (its limit) or stops (its cutoff); its
         // active channels' shares sum to C, a heavy-quark channel's bound
@@ -179,7 +269,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         best = lnt;
         win = sel;
       }
-      for (int c = 0; !A.gen_select && c < nch; ++c) {
+      for (int c = 0; FORM == 0 && c < nch; ++c) {
         int64_t oc = (int64_t)R.lane * S.nch + c;
         uint32_t info = S.ctr[oc].info;
         if (!((info >> 21) & 1u)) continue;
@@ -274,15 +364,29 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
 
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S,
-                                                      ShowerArgs A) {
+template <int FORM>
+__device__ __forceinline__ void lanes_body(const Cfg& C, const gaps_events& in, const gaps_events& out,
+                                           const Scratch& S, const ShowerArgs& A) {
   const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   Rec R = make_rec(S.part, S.lanes, 1, lane);
   for (;;) {
     unsigned long long e = atomicAdd(S.queue, 1ULL);
     if (e >= (unsigned long long)A.n) break;
-    shower_one(C, in, (int64_t)e, out, R, S, A, A.stats);
+    shower_one<FORM>(C, in, (int64_t)e, out, R, S, A, A.stats);
   }
+}
+
+__global__ void __launch_bounds__(256) k_shower_lanes(Cfg C, gaps_events in, gaps_events out, Scratch S,
+                                                      ShowerArgs A) {
+  lanes_body<0>(C, in, out, S, A);
+}
+__global__ void __launch_bounds__(256) k_shower_lanes_gs(Cfg C, gaps_events in, gaps_events out, Scratch S,
+                                                         ShowerArgs A) {
+  lanes_body<1>(C, in, out, S, A);
+}
+__global__ void __launch_bounds__(256) k_shower_lanes_vm(Cfg C, gaps_events in, gaps_events out, Scratch S,
+                                                         ShowerArgs A) {
+  lanes_body<2>(C, in, out, S, A);
 }
 
 }  // namespace gaps

@@ -89,11 +89,16 @@ def replicate(ev, k, n):
 
 # the forms of the competition: the paper's (every channel draws each cycle),
 # retained trials, and generate-select (one trial from the summed overestimate)
-RETAIN = pytest.mark.parametrize("retain", [False, True, "gs"], ids=["regenerate", "retain", "gen_select"])
+RETAIN = pytest.mark.parametrize("retain", [False, True, "gs", "vm"], ids=["regenerate", "retain", "gen_select",
+                                                                          "veto_max"])
 
 
 def _form(retain):
-    return dict(gen_select=True) if retain == "gs" else dict(retain=retain)
+    if retain == "gs":
+        return dict(gen_select=True)
+    if retain == "vm":
+        return dict(veto_max=True)
+    return dict(retain=retain)
 
 
 @pytest.mark.slow
@@ -302,6 +307,36 @@ def test_retained_trials_match_regenerated(oracles):
         m = (ha + hb) > 0
         chi2 = (((ha - hb) ** 2)[m] / (ha + hb)[m]).sum() / m.sum()
         assert chi2 < 1.6, (name, chi2)
+    oa, ob = o.observables(a), o.observables(b)
+    for col, lo, hi in ((0, 0.0, 60.0), (3, 0.0, 1.0), (4, -0.5, 6.5), (9, 3.5, 30.5)):
+        ha, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w)
+        ha2, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w ** 2)
+        hb, _ = np.histogram(ob[:, col], bins=28, range=(lo, hi), weights=ev.w)
+        hb2, _ = np.histogram(ob[:, col], bins=28, range=(lo, hi), weights=ev.w ** 2)
+        m = (ha2 + hb2) > 0
+        chi2 = np.sum((ha[m] - hb[m]) ** 2 / (ha2[m] + hb2[m])) / m.sum()
+        assert chi2 < 2.0, (col, chi2)  # p < 0.2 % at 28 degrees of freedom
+
+
+@pytest.mark.slow
+def test_veto_max_matches_max_veto(oracles):
+    """Veto-max (every channel's own veto loop to its first accepted trial,
+    the largest wins) and max-veto draw from the same no-emission probability:
+    on NLO inputs the same distributions of the number of emissions and of the
+    observables, one cycle per emission.  A winner vetoed again, a loop that
+    restarts from the wrong scale or a channel dropped from the maximum would
+    shift them."""
+    o = oracles["nlo"]
+    n = 40000
+    ev = o.hard_events(0, n, 2)
+    a = o.shower(ev, 3, nthreads=8)
+    b = o.shower(ev, 4, nthreads=8, veto_max=True)
+    assert np.array_equal(b.n_cycles, b.n_accept)
+    assert b.n_trials.mean() < a.n_trials.mean()
+    ha, _ = np.histogram(a.n_accept, np.arange(-0.5, 40.5))
+    hb, _ = np.histogram(b.n_accept, np.arange(-0.5, 40.5))
+    m = (ha + hb) > 0
+    assert (((ha - hb) ** 2)[m] / (ha + hb)[m]).sum() / m.sum() < 1.6
     oa, ob = o.observables(a), o.observables(b)
     for col, lo, hi in ((0, 0.0, 60.0), (3, 0.0, 1.0), (4, -0.5, 6.5), (9, 3.5, 30.5)):
         ha, _ = np.histogram(oa[:, col], bins=28, range=(lo, hi), weights=ev.w)
