@@ -63,6 +63,14 @@ struct LaneState {
 };
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
+// sum of a per-lane count over the wave, as a wave-uniform value (so that the
+// statistics accumulate in scalar registers, not in every lane)
+__device__ __forceinline__ unsigned long long wave_total(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+         (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
 __device__ __forceinline__ Rec rec_of(const Scratch& S, int64_t slot) {
   return make_rec(S.part, 1, S.max_slots, slot);
 }
@@ -530,8 +538,11 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (out.n_accept) out.n_accept[e] = nacc;
       if (out.n_viol) out.n_viol[e] = nviol;
       if (out.t1) out.t1[e] = t1;
-      st_cyc += cycle; st_tri += ntri; st_acc += nacc; st_viol += nviol;
     }
+    st_cyc += wave_total(owed ? cycle : 0u);
+    st_tri += wave_total(owed ? ntri : 0u);
+    st_acc += wave_total(owed ? nacc : 0u);
+    st_viol += wave_total(owed ? nviol : 0u);
     {
       // finished events' partons to their outputs, one parton per lane
       const int np = owed && loaded ? n : 0;
@@ -990,6 +1001,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (learned_mode) __threadfence_block();
     }
     bool rdw = false;  // retained trials: the winner of a vetoed or null cycle draws again
+    bool nulled = false, fellback = false;  // this cycle: a null winner, a failed learned bound
     if (trialing) {
       double best = -INFINITY;
       if (win >= 0) best = wexact ? wkey : wlnT + log(wu) * winv;
@@ -1000,7 +1012,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         T = exp(best);
         lnT = best;
         cycle += 1;
-        st_null += 1;
+        nulled = true;
         rdw = true;
       } else {
         const double t = exp(best);
@@ -1036,7 +1048,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           // the learned bound failed: shower this event again in plain mode
           pending = true;
           active = false;
-          st_fb += 1;
+          fellback = true;
         } else {
           if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
           if (v.ok && u[3] < v.w) {
@@ -1077,6 +1089,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                     ? 1u : 0u;
         pw = win;
       }
+    st_null += (unsigned long long)__popcll(__ballot(nulled));
+    st_fb += (unsigned long long)__popcll(__ballot(fellback));
     // ---- finished events: their outputs are owed until the next flush (a
     // pass for all of them: before the next refill, or at once when the
     // queue is drained)
@@ -1087,17 +1101,15 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     }
     since += 1;
   }
-  if (A.stats) {
+  if (A.stats && lane == 0) {  // the counters are wave totals
     atomicAdd(A.stats + 0, st_cyc);
     atomicAdd(A.stats + 1, st_tri);
     atomicAdd(A.stats + 2, st_acc);
     atomicAdd(A.stats + 3, st_viol);
+    atomicAdd(A.stats + 4, st_iters);
+    atomicAdd(A.stats + 5, st_active);
     atomicAdd(A.stats + 6, st_fb);
     atomicAdd(A.stats + 7, st_null);
-    if (lane == 0) {
-      atomicAdd(A.stats + 4, st_iters);
-      atomicAdd(A.stats + 5, st_active);
-    }
   }
 }
 
