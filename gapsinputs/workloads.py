@@ -8,6 +8,8 @@ Processes (the ``process`` field):
   0  e+e- -> Z/gamma* -> q qbar at sqrt(s) = 91.2 GeV, final-state shower only
   1  pp -> Z -> e+e- LO Born at 13 TeV, initial + final-state shower
   2  pp -> Z (-> e+e-) NLO, MC@NLO-style S and H events, power shower
+  3  pp -> gamma*/Z -> e+e- LO Born with the photon and the interference,
+     m_ee in [mll_min, mll_max], at 13 TeV, initial + final-state shower
 """
 from __future__ import annotations
 
@@ -33,6 +35,7 @@ COMMON = dict(
 EE = dict(COMMON, process=0, sqrt_s=91.2)
 PP_LO = dict(COMMON, process=1, sqrt_s=13000.0)
 PP_NLO = dict(COMMON, process=2, sqrt_s=13000.0)
+PP_DY = dict(COMMON, process=3, sqrt_s=13000.0)
 
 MAX_SLOTS = 128
 

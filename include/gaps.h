@@ -59,7 +59,11 @@ typedef enum {
  * appendix C constants; the PDF grid stands in for the paper's LHAPDF set). */
 typedef struct {
     int process;        /* 0: e+e- -> q qbar (final state only)
-                           1: pp -> Z -> e+e- LO,  2: pp -> Z NLO S/H events */
+                           1: pp -> Z -> e+e- LO,  2: pp -> Z NLO S/H events
+                           3: pp -> Z/photon -> e+e- LO with the interference
+                              (m_ee in the window below; cos theta of the
+                              electron about the quark from (1 + cos^2) F1 +
+                              2 cos F2 by accept-reject) */
     int nf;             /* active quark flavours (5) */
     double sqrt_s;      /* collider energy, GeV */
     double t_cut;       /* shower cutoff on t = pT^2, GeV^2 */

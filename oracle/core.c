@@ -272,7 +272,7 @@ or_state* or_init(const or_config* cfg) {
         s->cell_edge[k] = cfg->lnq0 + (double)k * ((cfg->lnq1 - cfg->lnq0) / OR_NTB);
     if (cfg->pdf) {
         or_compute_bounds(s);
-        if (cfg->process == 1) s->lo_wmax = or_lo_scan_wmax(s);
+        if (cfg->process == 1 || cfg->process == 3) s->lo_wmax = or_lo_scan_wmax(s);
     }
     return s;
 }

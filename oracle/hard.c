@@ -56,9 +56,11 @@ static void put(or_events* o, int64_t e, int slot, const double* p, int pid, int
     o->pid[k] = pid; o->col[k] = col; o->acol[k] = acol; o->status[k] = (int8_t)st;
 }
 
-/* Z -> e- e+ with 1 + cos^2 in the Z rest frame, boosted along pZ */
-static void decay_z(const double* pZ, double m, double ucos, double uphi, double* em, double* ep) {
-    double c = cos_1pc2(ucos), st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * OR_PI * uphi;
+/* the pair of mass m and momentum pZ decays to e- e+, the electron at polar
+ * cosine c (about +z) and azimuth 2 pi uphi in the pair's rest frame, boosted
+ * along pZ */
+static void decay_zc(const double* pZ, double m, double c, double uphi, double* em, double* ep) {
+    double st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * OR_PI * uphi;
     double k[4] = {0.5 * m, 0.5 * m * st * cos(ph), 0.5 * m * st * sin(ph), 0.5 * m * c};
     double pk = pZ[1] * k[1] + pZ[2] * k[2] + pZ[3] * k[3];
     double E1 = (pZ[0] * k[0] + pk) / m;
@@ -66,6 +68,30 @@ static void decay_z(const double* pZ, double m, double ucos, double uphi, double
     em[0] = E1;
     for (int m3 = 1; m3 < 4; ++m3) em[m3] = k[m3] + f * pZ[m3];
     for (int m3 = 0; m3 < 4; ++m3) ep[m3] = pZ[m3] - em[m3];
+}
+
+/* Z -> e- e+ with 1 + cos^2 in the Z rest frame */
+static void decay_z(const double* pZ, double m, double ucos, double uphi, double* em, double* ep) {
+    decay_zc(pZ, m, cos_1pc2(ucos), uphi, em, ep);
+}
+
+/* q qbar -> Z/photon -> e- e+ at s = m2 for quark flavour f: the coefficients
+ * of (1 + cos^2 theta) and of 2 cos theta in the cross section over its
+ * photon-only value for unit charges, theta the angle between the incoming
+ * quark and the electron in the pair's rest frame.  Couplings v = T3 - 2 Q
+ * sin^2(theta_W), a = T3; chi = s / (s - mZ^2 + i mZ GammaZ) /
+ * (4 sin^2 cos^2). */
+static void dy_f12(const or_state* s, int f, double m2, double* F1, double* F2) {
+    const double sw2 = s->c.sw2, mz2 = s->c.mz * s->c.mz, mg = s->c.mz * s->c.gz;
+    const int up = abs(f) % 2 == 0;
+    const double Qq = up ? 2.0 / 3.0 : -1.0 / 3.0, Qe = -1.0;
+    const double vq = up ? 0.5 - 4.0 / 3.0 * sw2 : -0.5 + 2.0 / 3.0 * sw2, aq = up ? 0.5 : -0.5;
+    const double ve = -0.5 + 2.0 * sw2, ae = -0.5;
+    const double kap = 1.0 / (4.0 * sw2 * (1.0 - sw2));
+    const double d = m2 - mz2, D = d * d + mg * mg;
+    const double rechi = kap * m2 * d / D, chi2 = kap * kap * m2 * m2 / D;
+    *F1 = Qq * Qq * Qe * Qe + 2.0 * Qq * Qe * vq * ve * rechi + (vq * vq + aq * aq) * (ve * ve + ae * ae) * chi2;
+    *F2 = 2.0 * Qq * Qe * aq * ae * rechi + 4.0 * vq * aq * ve * ae * chi2;
 }
 
 static void clear_counters(or_events* o, int64_t e) {
@@ -105,6 +131,27 @@ static double lo_lumi(const or_state* s, double m, double y, double* csub) {
     return L;
 }
 
+/* The same with the Z/photon cross section: per q qbar orientation the
+ * luminosity times F1 (m^2 - mZ^2)^2 + mZ^2 GammaZ^2) / m^4, the density of
+ * d sigma / dm^2 dy over the Breit-Wigner the masses are drawn from */
+static double dy_lumi(const or_state* s, double m, double y, double* csub) {
+    double m2 = m * m;
+    double e1 = m / s->sqrtS * exp(y), e2 = m / s->sqrtS * exp(-y);
+    const double d = m2 - s->c.mz * s->c.mz, mg = s->c.mz * s->c.gz;
+    const double bw = (d * d + mg * mg) / (m2 * m2);
+    double L = 0.0;
+    for (int f = 1; f <= s->c.nf; ++f) {
+        double F1, F2;
+        dy_f12(s, f, m2, &F1, &F2);
+        double g = F1 * bw;
+        double a = g * xfp(s, f, e1, m2) * xfp(s, -f, e2, m2);
+        double b = g * xfp(s, -f, e1, m2) * xfp(s, f, e2, m2);
+        if (csub) { csub[2 * (f - 1)] = a; csub[2 * (f - 1) + 1] = b; }
+        L += a + b;
+    }
+    return L;
+}
+
 double or_lo_scan_wmax(const or_state* s) {
     double best = 0.0;
     for (int i = 0; i < 64; ++i) {
@@ -112,7 +159,7 @@ double or_lo_scan_wmax(const or_state* s) {
         double Y = log(s->sqrtS / m);
         for (int j = 0; j < 128; ++j) {
             double y = -Y + 2.0 * Y * (j + 0.5) / 128.0;
-            double W = lo_lumi(s, m, y, NULL) * 2.0 * Y;
+            double W = (s->c.process == 3 ? dy_lumi(s, m, y, NULL) : lo_lumi(s, m, y, NULL)) * 2.0 * Y;
             if (W > best) best = W;
         }
     }
@@ -153,6 +200,58 @@ static void gen_lo(const or_state* s, int64_t id, uint64_t seed, or_events* o, i
         put(o, e, 3, ep, -11, 0, 0, 1);
         o->n[e] = 4; o->w[e] = 1.0; o->t_start[e] = s->S; o->flags[e] = 0;
         return;
+    }
+    o->n[e] = 0; o->w[e] = 0.0; o->t_start[e] = s->S; o->flags[e] = OR_F_HARDFAIL;
+}
+
+/* pp -> Z/photon -> e- e+ at LO with the photon, the Z and their
+ * interference: (m, y) and the q qbar orientation as for the Z alone with the
+ * Z/photon weight, then cos(theta) between the quark and the electron by
+ * accept-reject on (1 + c^2) F1 + 2 c F2 from proposals distributed as 1 + c^2
+ * (block (id, 2^32 - 1, j) of attempt j: proposal, acceptance, azimuth) */
+static void gen_dy(const or_state* s, int64_t id, uint64_t seed, or_events* o, int64_t e) {
+    double mz2 = s->c.mz * s->c.mz, mg = s->c.mz * s->c.gz;
+    double r1 = atan((s->c.mll_min * s->c.mll_min - mz2) / mg);
+    double r2 = atan((s->c.mll_max * s->c.mll_max - mz2) / mg);
+    double csub[10];
+    for (int k = 0; k < LO_MAXATT; ++k) {
+        double u[4];
+        or_rng_block(seed, STREAM_HARD, id, (uint32_t)k, 0u, u);
+        double m2 = mz2 + mg * tan(r1 + u[0] * (r2 - r1));
+        double m = sqrt(m2);
+        double Y = log(s->sqrtS / m), y = -Y + 2.0 * Y * u[1];
+        double L = dy_lumi(s, m, y, csub);
+        if (!(u[2] * s->lo_wmax < L * 2.0 * Y)) continue;
+        double target = u[3] * L, cum = 0.0;
+        int sel = 2 * s->c.nf - 1;
+        for (int q = 0; q < 2 * s->c.nf; ++q) {
+            cum += csub[q];
+            if (target < cum) { sel = q; break; }
+        }
+        int f = sel / 2 + 1;
+        int pa = (sel % 2 == 0) ? f : -f, pb = -pa;
+        double e1 = m / s->sqrtS * exp(y), e2 = m / s->sqrtS * exp(-y);
+        double Ea = 0.5 * e1 * s->sqrtS, Eb = 0.5 * e2 * s->sqrtS;
+        double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+        double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4];
+        double F1, F2;
+        dy_f12(s, f, m2, &F1, &F2);
+        const double sq = pa > 0 ? 1.0 : -1.0; /* the quark moves along +z when beam A carries it */
+        for (int j = 0; j < LO_MAXATT; ++j) {
+            double ud[4];
+            or_rng_block(seed, STREAM_HARD, id, 0xFFFFFFFFu, (uint32_t)j, ud);
+            const double c = cos_1pc2(ud[0]);
+            const double acc = ((1.0 + c * c) * F1 + 2.0 * c * F2) / ((1.0 + c * c) * (F1 + fabs(F2)));
+            if (!(ud[1] < acc)) continue;
+            put(o, e, 0, A, pa, pa > 0 ? 1 : 0, pa > 0 ? 0 : 1, -1);
+            put(o, e, 1, B, pb, pb > 0 ? 1 : 0, pb > 0 ? 0 : 1, -1);
+            decay_zc(pZ, m, sq * c, ud[2], em, ep);
+            put(o, e, 2, em, 11, 0, 0, 1);
+            put(o, e, 3, ep, -11, 0, 0, 1);
+            o->n[e] = 4; o->w[e] = 1.0; o->t_start[e] = s->S; o->flags[e] = 0;
+            return;
+        }
+        break;
     }
     o->n[e] = 0; o->w[e] = 0.0; o->t_start[e] = s->S; o->flags[e] = OR_F_HARDFAIL;
 }
@@ -328,6 +427,7 @@ int or_hard_events(const or_state* s, int64_t first_id, int64_t n, uint64_t seed
         clear_counters(out, e);
         if (s->c.process == 0) gen_ee(s, id, seed, out, e);
         else if (s->c.process == 1) gen_lo(s, id, seed, out, e);
+        else if (s->c.process == 3) gen_dy(s, id, seed, out, e);
         else gen_nlo(s, id, seed, out, e);
     }
     return 0;

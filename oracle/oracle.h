@@ -31,7 +31,8 @@ extern "C" {
 #endif
 
 typedef struct {
-    int process;        /* 0 e+e- -> qq, 1 pp LO Z->ee, 2 pp NLO S/H */
+    int process;        /* 0 e+e- -> qq, 1 pp LO Z->ee, 2 pp NLO S/H,
+                           3 pp LO Z/photon -> ee with interference */
     int nf;             /* active flavours (5) */
     double sqrt_s, t_cut, alphas_mz, mz, gz, sw2, gf, mc, mb;
     double mll_min, mll_max, p_s;

@@ -137,7 +137,7 @@ const char* gaps_strerror(gaps_status s) {
 
 gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   if (!cfg || !out || !cfg->pdf_xf) return GAPS_EINVAL;
-  if (cfg->process < 0 || cfg->process > 2 || cfg->nf < 1 || cfg->nf > 5) return GAPS_EINVAL;
+  if (cfg->process < 0 || cfg->process > 3 || cfg->nf < 1 || cfg->nf > 5) return GAPS_EINVAL;
   if (cfg->ntab != 8 || cfg->nx < 4 || cfg->nx > 1024 || cfg->nq < 4 || cfg->nq > 64) return GAPS_EINVAL;
   if (!(cfg->sqrt_s > 0.0) || !(cfg->t_cut > 0.0) || !(cfg->alphas_mz > 0.0) || !(cfg->mz > 0.0))
     return GAPS_EINVAL;
@@ -194,7 +194,7 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
     gaps_destroy(c);
     return GAPS_EHIP;
   }
-  if (cfg->process == 1) {
+  if (cfg->process == 1 || cfg->process == 3) {
     double *scan = nullptr, *wmax = nullptr;
     if (hipMalloc(&scan, 64 * 128 * sizeof(double)) != hipSuccess || hipMalloc(&wmax, sizeof(double)) != hipSuccess) {
       gaps_destroy(c);

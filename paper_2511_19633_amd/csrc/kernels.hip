@@ -189,6 +189,45 @@ __device__ double lo_lumi(const Cfg& C, double m, double y, double* csub) {
   return L;
 }
 
+// q qbar -> Z/photon -> e- e+ at s = m2 for quark flavour f: the coefficients
+// of (1 + cos^2 theta) and of 2 cos theta, theta between the incoming quark
+// and the electron in the pair's rest frame (couplings v = T3 - 2 Q sin^2,
+// a = T3; chi = s / (s - mZ^2 + i mZ GZ) / (4 sin^2 cos^2))
+__device__ void dy_f12(const Cfg& C, int f, double m2, double& F1, double& F2) {
+  const double sw2 = C.sw2, mg = C.mz * C.gz;
+  const int a = f < 0 ? -f : f;
+  const bool up = a % 2 == 0;
+  const double Qq = up ? 2.0 / 3.0 : -1.0 / 3.0, Qe = -1.0;
+  const double vq = up ? 0.5 - 4.0 / 3.0 * sw2 : -0.5 + 2.0 / 3.0 * sw2, aq = up ? 0.5 : -0.5;
+  const double ve = -0.5 + 2.0 * sw2, ae = -0.5;
+  const double kap = 1.0 / (4.0 * sw2 * (1.0 - sw2));
+  const double d = m2 - C.mz2, D = d * d + mg * mg;
+  const double rechi = kap * m2 * d / D, chi2 = kap * kap * m2 * m2 / D;
+  F1 = Qq * Qq * Qe * Qe + 2.0 * Qq * Qe * vq * ve * rechi + (vq * vq + aq * aq) * (ve * ve + ae * ae) * chi2;
+  F2 = 2.0 * Qq * Qe * aq * ae * rechi + 4.0 * vq * aq * ve * ae * chi2;
+}
+
+// the Z/photon weight of (m, y) per q qbar orientation: luminosity times
+// F1 ((m^2 - mZ^2)^2 + mZ^2 GZ^2) / m^4 (d sigma / dm^2 dy over the
+// Breit-Wigner the masses are drawn from)
+__device__ double dy_lumi(const Cfg& C, double m, double y, double* csub) {
+  double m2 = m * m;
+  double e1 = m / C.sqrt_s * exp(y), e2 = m / C.sqrt_s * exp(-y);
+  const double d = m2 - C.mz2, mg = C.mz * C.gz;
+  const double bw = (d * d + mg * mg) / (m2 * m2);
+  double L = 0.0;
+  for (int f = 1; f <= C.nf; ++f) {
+    double F1, F2;
+    dy_f12(C, f, m2, F1, F2);
+    const double g = F1 * bw;
+    double a = g * pdf_xf(C, pdf_tab(f), e1, m2) * pdf_xf(C, pdf_tab(-f), e2, m2);
+    double b = g * pdf_xf(C, pdf_tab(-f), e1, m2) * pdf_xf(C, pdf_tab(f), e2, m2);
+    if (csub) { csub[2 * (f - 1)] = a; csub[2 * (f - 1) + 1] = b; }
+    L += a + b;
+  }
+  return L;
+}
+
 __global__ void k_lo_scan(Cfg C, double* w) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 64 * 128) return;
@@ -196,7 +235,7 @@ __global__ void k_lo_scan(Cfg C, double* w) {
   double m = C.mll_min + (C.mll_max - C.mll_min) * i / 63.0;
   double Y = log(C.sqrt_s / m);
   double y = -Y + 2.0 * Y * (j + 0.5) / 128.0;
-  w[t] = lo_lumi(C, m, y, nullptr) * 2.0 * Y;
+  w[t] = (C.process == 3 ? dy_lumi(C, m, y, nullptr) : lo_lumi(C, m, y, nullptr)) * 2.0 * Y;
 }
 
 __global__ void k_lo_max(const double* w, int n, double* out) {
@@ -216,8 +255,10 @@ struct HardOut {
   }
 };
 
-__device__ void decay_z(const double* pZ, double m, double ucos, double uphi, double* em, double* ep) {
-  double c = cos_1pc2(ucos), st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * kPi * uphi;
+// the pair of mass m and momentum pZ decays to e- e+, the electron at polar
+// cosine c (about +z) and azimuth 2 pi uphi in the pair's rest frame
+__device__ void decay_zc(const double* pZ, double m, double c, double uphi, double* em, double* ep) {
+  double st = sqrt(fmax(0.0, 1.0 - c * c)), ph = 2.0 * kPi * uphi;
   double k[4] = {0.5 * m, 0.5 * m * st * cos(ph), 0.5 * m * st * sin(ph), 0.5 * m * c};
   double pk = pZ[1] * k[1] + pZ[2] * k[2] + pZ[3] * k[3];
   double E1 = (pZ[0] * k[0] + pk) / m;
@@ -225,6 +266,11 @@ __device__ void decay_z(const double* pZ, double m, double ucos, double uphi, do
   em[0] = E1;
   for (int q = 1; q < 4; ++q) em[q] = k[q] + f * pZ[q];
   for (int q = 0; q < 4; ++q) ep[q] = pZ[q] - em[q];
+}
+
+// Z -> e- e+ with 1 + cos^2 in the Z rest frame
+__device__ void decay_z(const double* pZ, double m, double ucos, double uphi, double* em, double* ep) {
+  decay_zc(pZ, m, cos_1pc2(ucos), uphi, em, ep);
 }
 
 __device__ double li2(double x) {
@@ -333,6 +379,57 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
       H.put(3, ep, -11, 0, 0, 1);
       o.n[e] = 4; o.w[e] = 1.0; o.t_start[e] = C.S; o.flags[e] = 0u;
       return;
+    }
+    o.n[e] = 0; o.w[e] = 0.0; o.t_start[e] = C.S; o.flags[e] = fHardFail;
+    return;
+  }
+  if (C.process == 3) {
+    // LO Z/photon with interference: (m, y) and the orientation as for the Z
+    // alone with the Z/photon weight, then cos(theta) between the quark and
+    // the electron by accept-reject on (1 + c^2) F1 + 2 c F2 from proposals
+    // distributed as 1 + c^2 (block (id, 2^32 - 1, j) of attempt j)
+    double mg = C.mz * C.gz;
+    double r1 = atan((C.mll_min * C.mll_min - C.mz2) / mg);
+    double r2 = atan((C.mll_max * C.mll_max - C.mz2) / mg);
+    double csub[10];
+    for (int k = 0; k < 1000; ++k) {
+      double u[4];
+      rng4(seed, SH, id, (uint32_t)k, 0u, u);
+      double m2 = C.mz2 + mg * tan(r1 + u[0] * (r2 - r1));
+      double m = sqrt(m2);
+      double Y = log(C.sqrt_s / m), y = -Y + 2.0 * Y * u[1];
+      double L = dy_lumi(C, m, y, csub);
+      if (!(u[2] * C.lo_wmax < L * 2.0 * Y)) continue;
+      double target = u[3] * L, cum = 0.0;
+      int sel = 2 * C.nf - 1;
+      for (int q = 0; q < 2 * C.nf; ++q) {
+        cum += csub[q];
+        if (target < cum) { sel = q; break; }
+      }
+      int f = sel / 2 + 1;
+      int pa = (sel % 2 == 0) ? f : -f, pb = -pa;
+      double e1 = m / C.sqrt_s * exp(y), e2 = m / C.sqrt_s * exp(-y);
+      double Ea = 0.5 * e1 * C.sqrt_s, Eb = 0.5 * e2 * C.sqrt_s;
+      double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+      double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4];
+      double F1, F2;
+      dy_f12(C, f, m2, F1, F2);
+      const double sq = pa > 0 ? 1.0 : -1.0;  // the quark moves along +z when beam A carries it
+      for (int j = 0; j < 1000; ++j) {
+        double ud[4];
+        rng4(seed, SH, id, 0xFFFFFFFFu, (uint32_t)j, ud);
+        const double c = cos_1pc2(ud[0]);
+        const double acc = ((1.0 + c * c) * F1 + 2.0 * c * F2) / ((1.0 + c * c) * (F1 + fabs(F2)));
+        if (!(ud[1] < acc)) continue;
+        H.put(0, A, pa, pa > 0 ? 1 : 0, pa > 0 ? 0 : 1, -1);
+        H.put(1, B, pb, pb > 0 ? 1 : 0, pb > 0 ? 0 : 1, -1);
+        decay_zc(pZ, m, sq * c, ud[2], em, ep);
+        H.put(2, em, 11, 0, 0, 1);
+        H.put(3, ep, -11, 0, 0, 1);
+        o.n[e] = 4; o.w[e] = 1.0; o.t_start[e] = C.S; o.flags[e] = 0u;
+        return;
+      }
+      break;
     }
     o.n[e] = 0; o.w[e] = 0.0; o.t_start[e] = C.S; o.flags[e] = fHardFail;
     return;

@@ -20,6 +20,7 @@ def cfgs():
         "ee": workloads.config_dict(workloads.EE),
         "lo": workloads.config_dict(workloads.PP_LO),
         "nlo": workloads.config_dict(workloads.PP_NLO),
+        "dy": workloads.config_dict(workloads.PP_DY),
     }
 
 
