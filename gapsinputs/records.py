@@ -29,6 +29,7 @@ FLAG_VIOL = 16
 FLAG_HARDFAIL = 32
 FLAG_HEVENT = 64
 FLAG_MAXCYC = 128
+FLAG_MEC = 256
 
 
 class Events:

@@ -36,6 +36,11 @@ EE = dict(COMMON, process=0, sqrt_s=91.2)
 PP_LO = dict(COMMON, process=1, sqrt_s=13000.0)
 PP_NLO = dict(COMMON, process=2, sqrt_s=13000.0)
 PP_DY = dict(COMMON, process=3, sqrt_s=13000.0)
+# the matching variants of the NLO workload: MC@NLO with every event starting
+# at mZ^2 instead of the hadronic S, and POWHEG-like Born events whose first
+# emission the shower corrects to the real matrix element
+PP_NLO_MUQ = dict(PP_NLO, matching=1, mu_q2=91.1876 ** 2)
+PP_NLO_POWHEG = dict(PP_NLO, matching=2)
 
 MAX_SLOTS = 128
 

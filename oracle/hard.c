@@ -198,7 +198,9 @@ static void gen_lo(const or_state* s, int64_t id, uint64_t seed, or_events* o, i
         decay_z(pZ, m, ud[0], ud[1], em, ep);
         put(o, e, 2, em, 11, 0, 0, 1);
         put(o, e, 3, ep, -11, 0, 0, 1);
-        o->n[e] = 4; o->w[e] = 1.0; o->t_start[e] = s->S; o->flags[e] = 0;
+        o->n[e] = 4; o->w[e] = 1.0;
+        o->t_start[e] = s->c.matching == 1 ? s->c.mu_q2 : s->S;
+        o->flags[e] = s->c.matching == 2 ? OR_F_MEC : 0u;
         return;
     }
     o->n[e] = 0; o->w[e] = 0.0; o->t_start[e] = s->S; o->flags[e] = OR_F_HARDFAIL;
@@ -293,6 +295,47 @@ static double k_leg(const or_state* s, int b, double eta, double x, double q2) {
            (1.0 - eta) * ((rq - 1.0) * or_nlo_gqq(s, x) + rq * nlo_hqq(s, x) + rg * nlo_hqg(s, x));
 }
 
+/* Radiation integral of one leg of a Born event at fixed Born kinematics, as a
+ * one-point estimate (x uniform on [eta, 1], v uniform on [0, 1 - x]) relative
+ * to the Born.  It covers the real configurations that the initial-initial map
+ * with this leg as emitter (appendix B.5) sends onto the Born: the leg's parton
+ * then carries eta / x, and the gluon-initiated ones take the gluon PDF.  Per
+ * unit Born the real emission's measure is m^2 / (16 pi^2 |M_B|^2) dx dv times
+ * the PDF ratio.
+ *   matching 1: minus the leg's dipoles (appendix C.2) where the emission's
+ *               kT^2 = v (1 - x - v) m^2 / x reaches mu_q2 (the region that the
+ *               S events' shower, started at mu_q2, no longer subtracts)
+ *   matching 2: R - S assigned to this leg's map; for q qbar -> Z g the share
+ *               of this leg's dipole in the dipole sum, (1 - x - v) / (1 - x) */
+static double leg_rad(const or_state* s, int b, double eta, double x, double v, double q2) {
+    double den = or_pdf_f(s, or_pdf_table(b), eta, q2);
+    if (!(den > 0.0)) return 0.0;
+    double rq = or_pdf_f(s, or_pdf_table(b), eta / x, q2) / (x * den);
+    double rg = or_pdf_f(s, 0, eta / x, q2) / (x * den);
+    double aq = OR_CF * s->c.alphas_mz / (2.0 * OR_PI), ag = OR_TR * s->c.alphas_mz / (2.0 * OR_PI);
+    double omx = 1.0 - x, m2 = s->c.mz * s->c.mz, g;
+    if (s->c.matching == 1) {
+        double kt2 = v * (omx - v) * m2 / x;
+        if (!(kt2 >= s->c.mu_q2)) return 0.0;
+        g = -(aq * (1.0 + x * x) / (omx * v) * rq + ag * (x * x + omx * omx) / v * rg);
+    } else {
+        g = -2.0 * aq * (omx - v) / omx * rq + ag * (2.0 * x + v) * rg;
+    }
+    return (1.0 - eta) * omx * g;
+}
+
+/* The dipole sum S of a real configuration (appendix C.2) in the variables of
+ * its generation, x = m^2/sbar and va = -ubar/sbar (the emitted parton against
+ * beam A): for q qbar -> Z g (kind 0) the two initial-state q -> q g dipoles,
+ * for g q (kind 1: gluon at A, kind 2: gluon at B) the gluon's g -> q qbar
+ * dipole; in units of 8 pi alpha_s |M_B|^2 / m^2 times C_F (kind 0) or T_R, so
+ * that with or_nlo_rs it gives R = S + (R - S). */
+double or_nlo_sub(int kind, double x, double va) {
+    double vb = 1.0 - x - va;
+    if (kind == 0) return (1.0 + x * x) / (va * vb);
+    return (x * x + (1.0 - x) * (1.0 - x)) / (kind == 1 ? va : vb);
+}
+
 /* real minus subtraction in closed form (appendix C.2); kind 0: q qbar -> Z g,
  * kind 1: g q -> Z q with ubar measured from the gluon */
 void or_nlo_rs(const or_state* s, int kind, double sbar, double tbar, double ubar, double mborn2,
@@ -314,17 +357,28 @@ static void gen_nlo(const or_state* s, int64_t id, uint64_t seed, or_events* o, 
     or_rng_block(seed, STREAM_HARD, id, 1u, 0u, u1);
     const double m = s->c.mz, m2 = m * m, q2 = m2;
     const int nf = s->c.nf;
-    if (u0[0] < s->c.p_s) {
-        /* S event: Born x (B + V + I + collinear) */
+    const int mt = s->c.matching;
+    if (mt == 2 || u0[0] < s->c.p_s) {
+        /* S event: Born x (B + V + I + collinear); matching 1 and 2 add the
+         * legs' radiation integrals (x of the collinear term, v from u1[2] and
+         * block (id, 2)) */
         double Y = log(s->sqrtS / m), y = -Y + 2.0 * Y * u0[2];
         double e1 = m / s->sqrtS * exp(y), e2 = m / s->sqrtS * exp(-y);
         double xa = e1 + (1.0 - e1) * u1[0], xb = e2 + (1.0 - e2) * u1[1];
+        double va = 0.0, vb = 0.0;
+        if (mt != 0) {
+            double u2[4];
+            or_rng_block(seed, STREAM_HARD, id, 2u, 0u, u2);
+            va = (1.0 - xa) * u1[2];
+            vb = (1.0 - xb) * u2[0];
+        }
         double csub[10], W = 0.0;
         for (int f = 1; f <= nf; ++f)
             for (int o2 = 0; o2 < 2; ++o2) {
                 int a = o2 == 0 ? f : -f, b = -a;
                 double born = OR_PI / (m2 * m2) * mborn2(s, f) * xfp(s, a, e1, q2) * xfp(s, b, e2, q2);
                 double corr = or_nlo_bvi_factor(s) + k_leg(s, a, e1, xa, q2) + k_leg(s, b, e2, xb, q2);
+                if (mt != 0) corr += leg_rad(s, a, e1, xa, va, q2) + leg_rad(s, b, e2, xb, vb, q2);
                 csub[2 * (f - 1) + o2] = born * corr;
                 W += fabs(born * corr);
             }
@@ -344,9 +398,9 @@ static void gen_nlo(const or_state* s, int64_t id, uint64_t seed, or_events* o, 
         put(o, e, 2, em, 11, 0, 0, 1);
         put(o, e, 3, ep, -11, 0, 0, 1);
         o->n[e] = 4;
-        o->w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y / s->c.p_s;
-        o->t_start[e] = s->S;
-        o->flags[e] = 0;
+        o->w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y / (mt == 2 ? 1.0 : s->c.p_s);
+        o->t_start[e] = mt == 1 ? s->c.mu_q2 : s->S;
+        o->flags[e] = mt == 2 ? OR_F_MEC : 0u;
         return;
     }
     /* H event: real minus subtraction, kinematics from the II map with j = 2 */
@@ -369,15 +423,22 @@ static void gen_nlo(const or_state* s, int64_t id, uint64_t seed, or_events* o, 
     double csub[30], W = 0.0;
     int pa[30], pb[30], kind[30];
     int q = 0;
+    /* matching 1: above the start scale the S events' shower subtracts
+     * nothing, so there the H events keep the dipole sum (their weight is R) */
+    const int above = mt == 1 && v * (1.0 - x - v) * sbar >= s->c.mu_q2;
+    const double sq = 8.0 * OR_PI * s->c.alphas_mz * OR_CF / m2, sg = 8.0 * OR_PI * s->c.alphas_mz * OR_TR / m2;
     for (int f = 1; f <= nf; ++f) {
         double mb = mborn2(s, f), rs;
         or_nlo_rs(s, 0, sbar, tbar, ubar, mb, &rs);
+        if (above) rs += sq * mb * or_nlo_sub(0, x, v);
         pa[q] = f; pb[q] = -f; kind[q] = 0; csub[q++] = rs;
         pa[q] = -f; pb[q] = f; kind[q] = 0; csub[q++] = rs;
         or_nlo_rs(s, 1, sbar, tbar, ubar, mb, &rs);
+        if (above) rs += sg * mb * or_nlo_sub(1, x, v);
         pa[q] = 21; pb[q] = f; kind[q] = 1; csub[q++] = rs;
         pa[q] = 21; pb[q] = -f; kind[q] = 1; csub[q++] = rs;
         or_nlo_rs(s, 1, sbar, ubar, tbar, mb, &rs);
+        if (above) rs += sg * mb * or_nlo_sub(2, x, v);
         pa[q] = f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
         pa[q] = -f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
     }
@@ -416,11 +477,15 @@ static void gen_nlo(const or_state* s, int64_t id, uint64_t seed, or_events* o, 
     put(o, e, 4, ep, -11, 0, 0, 1);
     o->n[e] = 5;
     o->w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * YH * (1.0 - xmin) * (1.0 - x) / (1.0 - s->c.p_s);
-    o->t_start[e] = s->S;
+    o->t_start[e] = mt == 1 ? s->c.mu_q2 : s->S;
     o->flags[e] = OR_F_HEVENT;
 }
 
 int or_hard_events(const or_state* s, int64_t first_id, int64_t n, uint64_t seed, or_events* out) {
+    const int mt = s->c.matching;
+    if (mt < 0 || mt > 2) return -1;
+    if (mt != 0 && s->c.process != 1 && s->c.process != 2) return -1;
+    if (mt == 1 && !(s->c.mu_q2 > 0.0)) return -1;
     for (int64_t e = 0; e < n; ++e) {
         int64_t id = first_id + e;
         out->id[e] = id;

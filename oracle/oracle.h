@@ -20,6 +20,11 @@
  *   NLO pieces ................ pinned (printed B+V+I factor, B = int g,
  *                               Li2 vs library, R-S identities)
  *   observables ............... pinned (thrust/jets on hand-built events)
+ *   matching variants ......... pinned (S + printed R - S = textbook R; the
+ *                               correction factor = textbook R / dipoles; NLO
+ *                               totals equal across the variants; corrected and
+ *                               plain first-emission CDFs vs 2-D quadrature of
+ *                               R / B and of the dipoles in (x, v))
  */
 #ifndef GAPS_ORACLE_H
 #define GAPS_ORACLE_H
@@ -40,6 +45,19 @@ typedef struct {
     int nx, nq, ntab;
     double lnx0, lnx1, lnq0, lnq1;
     double over_scale;  /* multiplies every channel overestimate (1 default) */
+    int matching;       /* 0: MC@NLO with the power shower (every event starts at
+                              the hadronic S: the paper's choice)
+                           1: MC@NLO with the start scale mu_q2 (processes 1, 2):
+                              every event starts at mu_q2; H events keep the
+                              dipole sum where kT^2 >= mu_q2 (there the S events'
+                              shower no longer subtracts it) and S events lose its
+                              integral over that region (one-point estimate)
+                           2: POWHEG-like (processes 1, 2): Born-kinematics events
+                              (NLO: weight B + V + I + C plus the integral of R - S
+                              over the radiation, one-point estimate) flagged
+                              OR_F_MEC, whose first emission the shower corrects to
+                              the real matrix element */
+    double mu_q2;       /* start scale for matching 1, GeV^2 */
 } or_config;
 
 typedef struct {
@@ -60,6 +78,7 @@ typedef struct {
 #define OR_F_HARDFAIL 32u
 #define OR_F_HEVENT   64u
 #define OR_F_MAXCYC   128u
+#define OR_F_MEC      256u /* first emission corrected to the real matrix element */
 
 typedef struct or_state or_state;
 
@@ -175,6 +194,12 @@ double or_nlo_bqq(const or_state* s, double eta);
 double or_nlo_gqq(const or_state* s, double x);
 void or_nlo_rs(const or_state* s, int kind, double sbar, double tbar, double ubar,
                double mborn2, double* r_minus_s);
+double or_nlo_sub(int kind, double x, double va);
+/* the first-emission correction factor R / (dipole sum) of the shower's
+ * initial-initial families A (q -> q g) and B (q <- g) at (x, v), and the bound
+ * on family B's factor that the corrected channels' overestimate carries */
+double or_mec_ratio(int family_b, double x, double v);
+double or_mec_bound(void);
 
 #ifdef __cplusplus
 }

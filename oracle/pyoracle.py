@@ -37,7 +37,7 @@ class OrConfig(C.Structure):
         ("mll_min", C.c_double), ("mll_max", C.c_double), ("p_s", C.c_double),
         ("pdf", C.POINTER(C.c_float)), ("nx", C.c_int), ("nq", C.c_int), ("ntab", C.c_int),
         ("lnx0", C.c_double), ("lnx1", C.c_double), ("lnq0", C.c_double), ("lnq1", C.c_double),
-        ("over_scale", C.c_double),
+        ("over_scale", C.c_double), ("matching", C.c_int), ("mu_q2", C.c_double),
     ]
 
 
@@ -92,6 +92,12 @@ def _lib():
         getattr(lib, name).argtypes = [C.c_void_p, C.c_double]
     lib.or_nlo_rs.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                               C.POINTER(C.c_double)]
+    lib.or_nlo_sub.restype = C.c_double
+    lib.or_nlo_sub.argtypes = [C.c_int, C.c_double, C.c_double]
+    lib.or_mec_ratio.restype = C.c_double
+    lib.or_mec_ratio.argtypes = [C.c_int, C.c_double, C.c_double]
+    lib.or_mec_bound.restype = C.c_double
+    lib.or_mec_bound.argtypes = []
     return lib
 
 
@@ -168,7 +174,8 @@ class Oracle:
     def hard_events(self, first_id, n, seed, max_slots=128):
         ev = records.Events(n, max_slots)
         s = events_struct(ev)
-        lib().or_hard_events(self.h, first_id, n, seed, C.byref(s))
+        if lib().or_hard_events(self.h, first_id, n, seed, C.byref(s)) != 0:
+            raise ValueError("or_hard_events: invalid matching for this process")
         return ev
 
     def shower(self, ev_in: records.Events, seed, nthreads=1, max_slots=None, retain=False, gen_select=False,
@@ -248,6 +255,18 @@ class Oracle:
         r = C.c_double()
         lib().or_nlo_rs(self.h, kind, sbar, tbar, ubar, mborn2, C.byref(r))
         return r.value
+
+    @staticmethod
+    def nlo_sub(kind, x, va):
+        return lib().or_nlo_sub(kind, x, va)
+
+    @staticmethod
+    def mec_ratio(family_b, x, v):
+        return lib().or_mec_ratio(int(family_b), x, v)
+
+    @staticmethod
+    def mec_bound():
+        return lib().or_mec_bound()
 
 
 def kin_map(typ, pe, ps, v1, v2, phi, rest=None):

@@ -14,14 +14,16 @@ enum { K_QQG = 0, K_GGG = 1, K_GQQ = 2, K_A = 3, K_B = 4, K_C = 5, K_D = 6 };
 
 typedef struct {
     int n, maxtag;
+    int mec; /* the next emission is corrected to the real matrix element */
     double p[OR_MAXM][4];
     int pid[OR_MAXM], col[OR_MAXM], acol[OR_MAXM], st[OR_MAXM];
 } ev_t;
 
-typedef struct { int kern, shape, flav, ent; double coefR, c; } term_t;
+/* coefR: the term's constant in front of its z shape, mul times the table's */
+typedef struct { int kern, shape, flav, ent; double coefR, c, mul; } term_t;
 
 typedef struct {
-    int i, k, side, type, alive, heavy, ebin;
+    int i, k, side, type, alive, heavy, ebin, mec;
     double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
     double zlo, zhi, omzlo, omzhi;
     int nterm;
@@ -86,7 +88,26 @@ static double shape_val(int sh, double z, double omz) {
 static void add_term(chan_t* ch, int kern, int shape, int flav, double coefR, int ent) {
     term_t* t = &ch->term[ch->nterm++];
     t->kern = kern; t->shape = shape; t->flav = flav; t->coefR = coefR; t->c = 0.0; t->ent = ent;
+    t->mul = 1.0;
 }
+
+/* First-emission correction of a POWHEG-like event (flag OR_F_MEC): the real
+ * matrix element over the shower's own density at the same real
+ * configuration, at the initial-initial variables (x, v) of the emission
+ * (appendix B.5; the shower's initial-initial density is the dipole of
+ * appendix C.2).  q qbar -> Z g is reached from both incoming quarks' q -> q g
+ * (family A): R / (D_a + D_b) = 1 - 2 v (1 - x - v) / (1 + x^2), in [1/2, 1].
+ * A quark from a gluon (family B, g qbar -> Z qbar) has only its own dipole:
+ * R / D = 1 + v (2 x + v) / (x^2 + (1 - x)^2), at most the square of the golden
+ * ratio (2.618...), so while the correction applies the family-B overestimate
+ * carries the factor OR_MEC_KB. */
+#define OR_MEC_KB 2.625
+double or_mec_ratio(int family_b, double x, double v) {
+    double omx = 1.0 - x;
+    if (!family_b) return 1.0 - 2.0 * v * (omx - v) / (1.0 + x * x);
+    return 1.0 + v * (2.0 * x + v) / (x * x + omx * omx);
+}
+double or_mec_bound(void) { return OR_MEC_KB; }
 
 /* Channel constants (dipole end i with spectator k on colour side `side`):
  * invariant mass, momentum fractions, kinematic limit, the widest z range (at
@@ -169,6 +190,12 @@ static void setup_channel(const or_state* S, const ev_t* e, int i, int side, int
             add_term(ch, K_A, SH_S1, 0, S->bound[OR_ENT_S1(FAM_A, T)][bin], OR_ENT_S1(FAM_A, T));
             int ent = ch->type == T_II ? OR_ENT_S3(FAM_B, T) : OR_ENT_S1(FAM_B, T);
             add_term(ch, K_B, sh2, 0, S->bound[ent][bin], ent);
+            if (e->mec && ch->type == T_II) {
+                term_t* tb = &ch->term[ch->nterm - 1];
+                tb->mul = OR_MEC_KB;
+                tb->coefR *= OR_MEC_KB;
+                ch->mec = 1;
+            }
         }
     }
     double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
@@ -408,6 +435,7 @@ static veto_t weight(const or_state* S, const ev_t* e, const chan_t* ch, const t
         double pr = den > 0.0 ? or_pdf_f(S, Tnum, ch->eta / x, t) / den : 0.0;
         double hf = ch->heavy ? (t - ch->m2) / t : 1.0;
         W = J * P * pr * hf;
+        if (ch->mec) W *= or_mec_ratio(tm->kern == K_B, x, uv);
         r.x = x; r.omx = omx; r.uv = uv;
     }
     double over = S->c.over_scale * tm->coefR * shape_val(tm->shape, z, omz);
@@ -475,6 +503,7 @@ static void emit(const or_state* S, ev_t* e, const chan_t* ch, const term_t* tm,
     e->col[j] = jc;
     e->acol[j] = ja;
     e->n += 1;
+    e->mec = 0;
 }
 
 static int finite4(const double* p) {
@@ -501,7 +530,7 @@ static double learned_c(const or_state* S, const chan_t* ch, const double* L, in
     double c = 0.0;
     for (int m = 0; m < ch->nterm; ++m) {
         const term_t* t = &ch->term[m];
-        c += af * lrn(L, t->ent, ch->ebin, k) * shape_int(t->shape, ch);
+        c += af * lrn(L, t->ent, ch->ebin, k) * t->mul * shape_int(t->shape, ch);
     }
     return c;
 }
@@ -649,6 +678,7 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
     ev->n = in->n[e_in];
     ev->maxtag = 0;
     uint32_t flags = in->flags ? in->flags[e_in] : 0u;
+    ev->mec = (flags & OR_F_MEC) != 0u;
     for (int q = 0; q < ev->n; ++q) {
         int64_t o = (int64_t)q * ci + e_in;
         ev->p[q][0] = in->E[o]; ev->p[q][1] = in->px[o];
@@ -836,7 +866,8 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
             double target = u[0] * ctot, cum = 0.0;
             int sel = -1;
             for (int m = 0; m < C->nterm; ++m) {
-                cum += lch ? af * lrn(Lt, C->term[m].ent, C->ebin, wcell) * shape_int(C->term[m].shape, C)
+                cum += lch ? af * lrn(Lt, C->term[m].ent, C->ebin, wcell) * C->term[m].mul *
+                                 shape_int(C->term[m].shape, C)
                            : C->term[m].c;
                 if (target < cum) { sel = m; break; }
             }
@@ -844,14 +875,14 @@ static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint
                 for (int m = C->nterm - 1; m >= 0; --m)
                     if (C->term[m].c > 0.0) { sel = m; break; }
             term_t tsel = C->term[sel];
-            if (lch) tsel.coefR = lrn(Lt, tsel.ent, C->ebin, wcell);
+            if (lch) tsel.coefR = lrn(Lt, tsel.ent, C->ebin, wcell) * tsel.mul;
             const term_t* tm = &tsel;
             double I = shape_int(tm->shape, C);
             double z, omz;
             shape_sample(tm->shape, C, I, u[1], &z, &omz);
             double phi = 2.0 * OR_PI * u[2];
             veto_t v = weight(S, ev, C, tm, t, z, omz);
-            if (L && (C->type == T_IF || C->type == T_II) && v.ok && v.wn > 0.0)
+            if (L && (C->type == T_IF || C->type == T_II) && !C->mec && v.ok && v.wn > 0.0)
                 log_trial(L, t, C->eta, z, tm->ent, v.wn);
             if (lch && v.ok && v.w > 1.0) return 1; /* the learned bound failed */
             if (v.ok && v.w > 1.0) { nviol += 1; flags |= OR_F_VIOL; }

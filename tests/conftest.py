@@ -21,6 +21,8 @@ def cfgs():
         "lo": workloads.config_dict(workloads.PP_LO),
         "nlo": workloads.config_dict(workloads.PP_NLO),
         "dy": workloads.config_dict(workloads.PP_DY),
+        "muq": workloads.config_dict(workloads.PP_NLO_MUQ),
+        "powheg": workloads.config_dict(workloads.PP_NLO_POWHEG),
     }
 
 
