@@ -54,6 +54,8 @@ typedef enum {
 #define GAPS_F_HARDFAIL 32u /* the hard-event sampler found no event */
 #define GAPS_F_HEVENT 64u   /* NLO H (real-emission) event */
 #define GAPS_F_MAXCYC 128u  /* cycle guard reached */
+#define GAPS_F_MEC 256u     /* POWHEG-like event: the shower corrects its first
+                               emission to the real matrix element */
 
 /* Physics configuration, read from host memory by gaps_init (section 4 and
  * appendix C constants; the PDF grid stands in for the paper's LHAPDF set). */
@@ -77,6 +79,26 @@ typedef struct {
     int nx, nq, ntab;   /* grid sizes; ntab must be 8 (g d u s c b dbar ubar) */
     double lnx0, lnx1, lnq0, lnq1; /* node ranges in ln x and ln Q^2 */
     double over_scale;  /* multiplies every overestimate (1 = default) */
+    int matching;       /* how NLO events meet the shower (appendix C.4 and the
+                           alternatives it names; processes 1 and 2 only):
+                           0: MC@NLO with the power shower, every event starting
+                              at the hadronic S (the paper's choice)
+                           1: MC@NLO with the start scale mu_q2: every event
+                              starts at mu_q2; H events keep the dipole sum where
+                              the emission's kT^2 >= mu_q2 and S events lose its
+                              integral over that region (one-point estimate, x
+                              of the collinear term and v uniform on [0, 1 - x]
+                              from block (id, 1) word 2 and (id, 2) word 0)
+                           2: POWHEG-like: every event is a Born event (weight
+                              B + V + I + C plus the one-point integral of
+                              R - S, the q qbar part in the share of each leg's
+                              dipole) flagged GAPS_F_MEC; for LO (process 1) the
+                              LO events are flagged.  gaps_shower multiplies a
+                              flagged event's first emission by R over its
+                              initial-initial dipole density (family B's
+                              overestimate carries the factor 2.625 meanwhile).
+                           GAPS_EINVAL for other values and processes. */
+    double mu_q2;       /* start scale of matching 1, GeV^2 (> 0) */
 } gaps_config;
 
 /* Event record: DEVICE pointers.  The optional counters may be NULL. */

@@ -39,7 +39,7 @@ class GapsConfig(C.Structure):
         ("mll_min", C.c_double), ("mll_max", C.c_double), ("p_s", C.c_double),
         ("pdf_xf", C.POINTER(C.c_float)), ("nx", C.c_int), ("nq", C.c_int), ("ntab", C.c_int),
         ("lnx0", C.c_double), ("lnx1", C.c_double), ("lnq0", C.c_double), ("lnq1", C.c_double),
-        ("over_scale", C.c_double),
+        ("over_scale", C.c_double), ("matching", C.c_int), ("mu_q2", C.c_double),
     ]
 
 

@@ -143,6 +143,9 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
     return GAPS_EINVAL;
   if (!(cfg->lnx1 > cfg->lnx0) || !(cfg->lnq1 > cfg->lnq0)) return GAPS_EINVAL;
   if (cfg->process == 2 && !(cfg->p_s > 0.0 && cfg->p_s < 1.0)) return GAPS_EINVAL;
+  if (cfg->matching < 0 || cfg->matching > 2) return GAPS_EINVAL;
+  if (cfg->matching != 0 && cfg->process != 1 && cfg->process != 2) return GAPS_EINVAL;
+  if (cfg->matching == 1 && !(cfg->mu_q2 > 0.0)) return GAPS_EINVAL;
   gaps_ctx c = new (std::nothrow) gaps_ctx_s();
   if (!c) return GAPS_ENOMEM;
   c->cfg = *cfg;
@@ -179,6 +182,8 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   C.ln_tch_c = log(C.tch_c); C.ln_tch_b = log(C.tch_b);
   C.sw2 = cfg->sw2; C.gf = cfg->gf; C.mll_min = cfg->mll_min; C.mll_max = cfg->mll_max; C.p_s = cfg->p_s;
   C.over_scale = cfg->over_scale > 0.0 ? cfg->over_scale : 1.0;
+  C.matching = cfg->matching;
+  C.mu_q2 = cfg->mu_q2;
   C.lnx0 = cfg->lnx0; C.lnx1 = cfg->lnx1; C.lnq0 = cfg->lnq0; C.lnq1 = cfg->lnq1;
   for (int k = 0; k <= gaps::kNTB; ++k)
     C.cell_edge[k] = cfg->lnq0 + (double)k * ((cfg->lnq1 - cfg->lnq0) / gaps::kNTB);

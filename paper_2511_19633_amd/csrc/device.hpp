@@ -34,6 +34,7 @@ constexpr int kMaxSlots = 256;
 // most overestimate terms of a channel: an initial-state gluon, 1 + 2 nf (nf <= 5)
 constexpr int kMaxTerms = 11;
 constexpr uint32_t kMaxCycles = 2000000u;
+constexpr double kMecB = 2.625;  // overestimate factor of a corrected family-B term
 
 enum : int { kFF = 0, kFI = 1, kIF = 2, kII = 3 };
 enum : int { kSoft = 0, kFlat = 1, kS1 = 2, kS3 = 3 };
@@ -44,7 +45,7 @@ enum : int { famA = 0, famB = 1, famC = 2, famD = 3 };
 
 enum : uint32_t {
   fOverflow = 1u, fColour = 2u, fNaN = 4u, fFallback = 8u, fViol = 16u,
-  fHardFail = 32u, fHEvent = 64u, fMaxCyc = 128u
+  fHardFail = 32u, fHEvent = 64u, fMaxCyc = 128u, fMEC = 256u
 };
 
 // Everything the kernels need, passed by value (kernel-argument segment).
@@ -55,6 +56,8 @@ struct Cfg {
   double sw2, gf, mll_min, mll_max, p_s, over_scale;
   double lnx0, lnx1, lnq0, lnq1, dlnx, dlnq;
   double lo_wmax;
+  int matching;
+  double mu_q2;
   double cell_edge[kNTB + 1];  // ln t edges of the learned-bound cells
   const float* pdf;      // [8][nq][nx]
   const double* bound;   // [72][48]
@@ -219,8 +222,10 @@ __device__ __forceinline__ Rec make_rec(Part* p, int64_t sq, int64_t sl, int64_t
 // Channel: dipole end (emitter i, spectator k, colour side) with its constants.
 // Its overestimate terms are enumerated on demand by term_at(); the z
 // integrals of the (at most two) z shapes a channel uses are I1 and I2.
+// mec: an initial-initial channel of a quark whose next emission is corrected
+// to the real matrix element (see mec_ratio)
 struct Chan {
-  int i, k, side, type, heavy, alive, ebin, kbin, pidi, pidk, nterm;
+  int i, k, side, type, heavy, alive, ebin, kbin, pidi, pidk, nterm, mec;
   double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
   double zlo, zhi, omzlo, omzhi, I1, I2, c, invc;
 };
@@ -318,6 +323,7 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
     }
   }
   t.coefR = C.bound[t.ent * kNB + ch.ebin];
+  if (ch.mec && t.kern == kB) t.coefR *= kMecB;
   return t;
 }
 
@@ -328,7 +334,8 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
 // (independent loads), then the products are summed in term order: the total
 // constant c, or the term a uniform draw of c picks.
 template <class Tab>
-__device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, Tab R_of, double (&R)[kMaxTerms]) {
+__device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, Tab R_of, double (&R)[kMaxTerms],
+                                             bool mec) {
   const bool ii = type == kII;
   if (pidi == 21) {
     const int nt = 1 + 2 * C.nf;
@@ -347,16 +354,18 @@ __device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, T
   const int T = pdf_tab(pidi);
   R[0] = R_of(ent_s1(famA, T));
   R[1] = R_of(ii ? ent_s3(famB, T) : ent_s1(famB, T));
+  if (mec) R[1] *= kMecB;
 #pragma unroll
   for (int m = 2; m < kMaxTerms; ++m) R[m] = 0.0;
   return 2;
 }
 
 template <class Tab>
-__device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, double I1, double I2, Tab R_of) {
+__device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, double I1, double I2, Tab R_of,
+                                             bool mec) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R);
+  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
   double c = 0.0;
   c += af * R[0] * I1;
 #pragma unroll
@@ -369,10 +378,10 @@ __device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, d
 // term order) first exceeds target, and its constant; -1 if none does.
 template <class Tab>
 __device__ __forceinline__ int is_terms_pick(const Cfg& C, int type, int pidi, double I1, double I2, double target,
-                                             Tab R_of, double& Rsel) {
+                                             Tab R_of, bool mec, double& Rsel) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R);
+  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
   int sel = -1;
   Rsel = 0.0;
   double cum = 0.0;
@@ -389,8 +398,10 @@ __device__ __forceinline__ int is_terms_pick(const Cfg& C, int type, int pidi, d
 
 // Channel constants of dipole end (i, side) with spectator k: invariant,
 // momentum fractions, kinematic limit (appendix B), the widest z range (at the
-// cutoff), and the total overestimate c of G = c/t (appendix A.1).
-__device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, int k, Chan& ch) {
+// cutoff), and the total overestimate c of G = c/t (appendix A.1).  mec: the
+// event's next emission is corrected to the real matrix element (applies to
+// its initial-initial quark channels).
+__device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, int k, Chan& ch, bool mec) {
   ch.i = i; ch.k = k; ch.side = side; ch.alive = 0; ch.heavy = 0; ch.nterm = 0;
   ch.m2 = 0.0; ch.c = 0.0; ch.invc = 0.0; ch.ebin = 0; ch.kbin = 0;
   ch.zlo = ch.zhi = ch.omzlo = ch.omzhi = ch.I1 = ch.I2 = 0.0;
@@ -399,6 +410,7 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
   ch.pidi = R.pid[R.o(i)];
   ch.pidk = R.pid[R.o(k)];
   ch.type = isE ? (isS ? kII : kIF) : (isS ? kFI : kFF);
+  ch.mec = mec && ch.type == kII && ch.pidi != 21;
   double pi[4], pk[4];
   R.get(i, pi);
   R.get(k, pk);
@@ -453,7 +465,7 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
   double c = 0.0;
   if (isE) {
     const int eb = ch.ebin;
-    c = is_terms_c(C, ch.type, ch.pidi, ch.I1, ch.I2, [&](int ent) { return C.bound[ent * kNB + eb]; });
+    c = is_terms_c(C, ch.type, ch.pidi, ch.I1, ch.I2, [&](int ent) { return C.bound[ent * kNB + eb]; }, ch.mec);
   } else {
     double af = C.as_over / (2.0 * kPi) * C.over_scale;
     for (int m = 0; m < ch.nterm; ++m) {
@@ -488,7 +500,7 @@ __device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool 
     double Rsel;
     const int m = is_terms_pick(C, ch.type, ch.pidi, ch.I1, ch.I2, target, [&](int ent) {
       return lrn ? learned_R(C, ent, eb, k) : C.bound[ent * kNB + eb];
-    }, Rsel);
+    }, ch.mec, Rsel);
     if (m >= 0) {
       Term t = term_at(C, ch, m);
       t.coefR = Rsel;
@@ -504,7 +516,7 @@ __device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool 
   for (int m = ch.nterm - 1; m >= 0; --m) {
     Term t = term_at(C, ch, m);
     if (af * t.coefR * t.I > 0.0) {
-      if (lrn) t.coefR = learned_R(C, t.ent, ch.ebin, k);
+      if (lrn) t.coefR = learned_R(C, t.ent, ch.ebin, k) * (ch.mec && t.kern == kB ? kMecB : 1.0);
       return t;
     }
   }
@@ -520,8 +532,9 @@ __device__ __forceinline__ Term select_term(const Cfg& C, const Chan& ch, double
 
 // constant of cell k of an initial-state channel (type IF or II) whose emitter
 // has flavour pidi, from the cell constants of its terms
-__device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k) {
-  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); });
+__device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k,
+                                            bool mec) {
+  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); }, mec);
 }
 
 // the cell of a scale: the largest k with edge[k] < ln t (0 if none), and its
@@ -583,6 +596,21 @@ __device__ __forceinline__ void ii_lambda(const double* Kp, const double* K, dou
   double c1 = 2.0 * dot4(KK, p) / KK2;
   double c2 = 2.0 * dot4(Kp, p) / Kp2;
   for (int m = 0; m < 4; ++m) p[m] = p[m] - c1 * KK[m] + c2 * K[m];
+}
+
+// First-emission correction of a POWHEG-like event: the real matrix element
+// over the shower's own density at the same real configuration, at the
+// initial-initial (x, v) of the emission (appendix B.5; the density is the
+// dipole of appendix C.2).  q qbar -> Z g is reached from both incoming
+// quarks' family A (q -> q g), so R / (D_a + D_b) = 1 - 2 v (1 - x - v) /
+// (1 + x^2), in [1/2, 1]; a quark from a gluon (family B, g qbar -> Z qbar)
+// has only its own dipole: R / D = 1 + v (2 x + v) / (x^2 + (1 - x)^2), at
+// most the golden ratio squared (2.618...), which the family-B overestimate of
+// a corrected channel covers with the factor kMecB.
+__device__ __forceinline__ double mec_ratio(bool family_b, double x, double v) {
+  const double omx = 1.0 - x;
+  if (!family_b) return 1.0 - 2.0 * v * (omx - v) / (1.0 + x * x);
+  return 1.0 + v * (2.0 * x + v) / (x * x + omx * omx);
 }
 
 struct Veto {
@@ -677,6 +705,7 @@ __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, c
   if (type == kFF) W = (1.0 - y) * P;
   else if (type == kFI) W = P * pr;
   else W = J * P * pr * (ch.heavy ? (t - ch.m2) / t : 1.0);
+  if (ch.mec) W *= mec_ratio(kern == kB, x, uv);
   r.x = x; r.omx = omx; r.y = y; r.uv = uv;
   const double over = C.over_scale * tm.coefR * shape_val(tm.shape, z, omz);
   const double ar = alphas(C, t) / C.as_over;

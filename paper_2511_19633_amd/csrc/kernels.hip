@@ -303,12 +303,14 @@ __device__ double mborn2(const Cfg& C, int f) {
   return 1.0 / kNC * 0.25 * sqrt(2.0) * C.gf * C.mz2 * C.mz2 * zcoup(C, f);
 }
 
-// collinear insertion (K + P at muF = mZ) for a leg with Born parton b at eta
-__device__ double k_leg(const Cfg& C, int b, double eta, double x, double q2) {
+// collinear insertion (K + P at muF = mZ) for a leg with Born parton b at eta;
+// rq, rg get the leg's PDF ratios at eta / x (quark, gluon), 0 without a Born PDF
+__device__ double k_leg(const Cfg& C, int b, double eta, double x, double q2, double& rq, double& rg) {
+  rq = rg = 0.0;
   double den = pdf_f(C, pdf_tab(b), eta, q2);
   if (!(den > 0.0)) return 0.0;
-  double rq = pdf_f(C, pdf_tab(b), eta / x, q2) / (x * den);
-  double rg = pdf_f(C, 0, eta / x, q2) / (x * den);
+  rq = pdf_f(C, pdf_tab(b), eta / x, q2) / (x * den);
+  rg = pdf_f(C, 0, eta / x, q2) / (x * den);
   double pq = kCF * C.alphas_mz / (2.0 * kPi), pg = kTR * C.alphas_mz / (2.0 * kPi);
   double A = pq * (-5.0 + 2.0 * kPi * kPi / 3.0);
   double l = log(1.0 - eta);
@@ -318,6 +320,39 @@ __device__ double k_leg(const Cfg& C, int b, double eta, double x, double q2) {
   double h = pq * (-(1.0 + x) * L + (1.0 - x));
   double hg = pg * (2.0 * x * (1.0 - x) + (x * x + (1.0 - x) * (1.0 - x)) * L);
   return A - B + (1.0 - eta) * ((rq - 1.0) * g + rq * h + rg * hg);
+}
+
+// One leg's radiation integral at fixed Born kinematics (matching 1 and 2),
+// one point (x of the collinear term, v uniform on [0, 1 - x]) relative to the
+// Born, from the leg's PDF ratios rq, rg at eta / x.  The real configurations
+// that the initial-initial map with this leg as emitter sends onto the Born
+// have the measure m^2 / (16 pi^2 |M_B|^2) dx dv per unit Born.  Matching 1:
+// minus the leg's dipoles (q -> q g, and g -> q qbar for the gluon-initiated
+// configuration) where kT^2 = v (1 - x - v) m^2 / x >= mu_q2.  Matching 2:
+// R - S mapped by this leg, the q qbar -> Z g part in the share
+// (1 - x - v) / (1 - x) of this leg's dipole in the dipole sum.
+__device__ double leg_rad(const Cfg& C, double eta, double x, double v, double rq, double rg) {
+  const double omx = 1.0 - x;
+  const double aq = kCF * C.alphas_mz / (2.0 * kPi), ag = kTR * C.alphas_mz / (2.0 * kPi);
+  double g;
+  if (C.matching == 1) {
+    if (!(v * (omx - v) * C.mz2 / x >= C.mu_q2)) return 0.0;
+    g = -(aq * (1.0 + x * x) / (omx * v) * rq + ag * (x * x + omx * omx) / v * rg);
+  } else {
+    g = -2.0 * aq * (omx - v) / omx * rq + ag * (2.0 * x + v) * rg;
+  }
+  return (1.0 - eta) * omx * g;
+}
+
+// The dipole sum of a real configuration (appendix C.2) at x = m^2 / sbar and
+// va = -ubar / sbar (the emitted parton against beam A), over
+// 8 pi alpha_s |M_B|^2 / m^2 and the colour factor: both q -> q g dipoles of
+// q qbar -> Z g (kind 0), the gluon's g -> q qbar dipole for the gluon at A
+// (kind 1) or at B (kind 2).
+__device__ __forceinline__ double dipole_sum(int kind, double x, double va) {
+  const double vb = 1.0 - x - va;
+  if (kind == 0) return (1.0 + x * x) / (va * vb);
+  return (x * x + (1.0 - x) * (1.0 - x)) / (kind == 1 ? va : vb);
 }
 
 __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o) {
@@ -377,7 +412,9 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
       decay_z(pZ, m, ud[0], ud[1], em, ep);
       H.put(2, em, 11, 0, 0, 1);
       H.put(3, ep, -11, 0, 0, 1);
-      o.n[e] = 4; o.w[e] = 1.0; o.t_start[e] = C.S; o.flags[e] = 0u;
+      o.n[e] = 4; o.w[e] = 1.0;
+      o.t_start[e] = C.matching == 1 ? C.mu_q2 : C.S;
+      o.flags[e] = C.matching == 2 ? fMEC : 0u;
       return;
     }
     o.n[e] = 0; o.w[e] = 0.0; o.t_start[e] = C.S; o.flags[e] = fHardFail;
@@ -440,17 +477,28 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
   rng4(seed, SH, id, 1u, 0u, u1);
   const double m = C.mz, m2 = C.mz2, q2 = m2;
   const int nf = C.nf;
-  if (u0[0] < C.p_s) {
+  const int mt = C.matching;
+  if (mt == 2 || u0[0] < C.p_s) {
+    // S event (matching 2: every event, as a Born event with the radiation integral)
     double Y = log(C.sqrt_s / m), y = -Y + 2.0 * Y * u0[2];
     double e1 = m / C.sqrt_s * exp(y), e2 = m / C.sqrt_s * exp(-y);
     double xa = e1 + (1.0 - e1) * u1[0], xb = e2 + (1.0 - e2) * u1[1];
+    double va = 0.0, vb = 0.0;
+    if (mt != 0) {
+      double u2[4];
+      rng4(seed, SH, id, 2u, 0u, u2);
+      va = (1.0 - xa) * u1[2];
+      vb = (1.0 - xb) * u2[0];
+    }
     double csub[10], W = 0.0;
     double bvi = 1.0 + kCF * C.alphas_mz / (2.0 * kPi) * 2.0;
     for (int f = 1; f <= nf; ++f)
       for (int o2 = 0; o2 < 2; ++o2) {
         int a = o2 == 0 ? f : -f, b = -a;
         double born = kPi / (m2 * m2) * mborn2(C, f) * pdf_xf(C, pdf_tab(a), e1, q2) * pdf_xf(C, pdf_tab(b), e2, q2);
-        double corr = bvi + k_leg(C, a, e1, xa, q2) + k_leg(C, b, e2, xb, q2);
+        double rqa, rga, rqb, rgb;
+        double corr = bvi + k_leg(C, a, e1, xa, q2, rqa, rga) + k_leg(C, b, e2, xb, q2, rqb, rgb);
+        if (mt != 0) corr += leg_rad(C, e1, xa, va, rqa, rga) + leg_rad(C, e2, xb, vb, rqb, rgb);
         csub[2 * (f - 1) + o2] = born * corr;
         W += fabs(born * corr);
       }
@@ -470,9 +518,9 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
     H.put(2, em, 11, 0, 0, 1);
     H.put(3, ep, -11, 0, 0, 1);
     o.n[e] = 4;
-    o.w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y / C.p_s;
-    o.t_start[e] = C.S;
-    o.flags[e] = 0u;
+    o.w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y / (mt == 2 ? 1.0 : C.p_s);
+    o.t_start[e] = mt == 1 ? C.mu_q2 : C.S;
+    o.flags[e] = mt == 2 ? fMEC : 0u;
     return;
   }
   double xmin = m2 / C.S;
@@ -495,15 +543,21 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
   int pa[30], pb[30], kind[30];
   int q = 0;
   double pre_q = 8.0 * kPi * C.alphas_mz * kCF / m2, pre_g = 8.0 * kPi * C.alphas_mz * kTR / m2;
+  // matching 1: above mu_q2 the S events' shower subtracts nothing, so the H
+  // events keep the dipole sum there (their weight is R)
+  const bool above = mt == 1 && v * (1.0 - x - v) * sbar >= C.mu_q2;
   for (int f = 1; f <= nf; ++f) {
     double mb = mborn2(C, f);
     double rs = pre_q * mb * (-2.0);
+    if (above) rs += pre_q * mb * dipole_sum(0, x, v);
     pa[q] = f; pb[q] = -f; kind[q] = 0; csub[q++] = rs;
     pa[q] = -f; pb[q] = f; kind[q] = 0; csub[q++] = rs;
     rs = pre_g * mb * ((2.0 * m2 - ubar) / sbar);
+    if (above) rs += pre_g * mb * dipole_sum(1, x, v);
     pa[q] = 21; pb[q] = f; kind[q] = 1; csub[q++] = rs;
     pa[q] = 21; pb[q] = -f; kind[q] = 1; csub[q++] = rs;
     rs = pre_g * mb * ((2.0 * m2 - tbar) / sbar);
+    if (above) rs += pre_g * mb * dipole_sum(2, x, v);
     pa[q] = f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
     pa[q] = -f; pb[q] = 21; kind[q] = 2; csub[q++] = rs;
   }
@@ -541,7 +595,7 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
   H.put(4, ep, -11, 0, 0, 1);
   o.n[e] = 5;
   o.w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * YH * (1.0 - xmin) * (1.0 - x) / (1.0 - C.p_s);
-  o.t_start[e] = C.S;
+  o.t_start[e] = mt == 1 ? C.mu_q2 : C.S;
   o.flags[e] = fHEvent;
 }
 

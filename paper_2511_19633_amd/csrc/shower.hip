@@ -17,7 +17,7 @@ __device__ __forceinline__ uint32_t pack_info(const Chan& ch) {
 }
 
 // rebuild the channel list in (slot, side) order; -1 on a broken colour line
-__device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& S, int& nch) {
+__device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& S, int& nch, bool mec) {
   int m = 0;
   Chan ch;
   for (int i = 0; i < n; ++i) {
@@ -33,7 +33,7 @@ __device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& 
         if (other == tag) { k = j; break; }
       }
       if (k < 0) return -1;
-      chan_setup(C, R, i, side, k, ch);
+      chan_setup(C, R, i, side, k, ch, mec);
       int64_t oc = (int64_t)R.lane * S.nch + m;
       S.ctr[oc].info = pack_info(ch);
       S.ctr[oc].tl = ch.tlim;
@@ -89,9 +89,11 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
   double T = in.t_start[e], lnT = log(T), t1 = 0.0;
   uint32_t ncyc = 0, ntri = 0, nacc = 0, nviol = 0;
   int nch = 0;
+  // a flagged event's first emission is corrected to the real matrix element
+  auto mec_now = [&]() { return (flags & fMEC) != 0u && t1 == 0.0; };
   if (!fits) {
     flags |= fOverflow;
-  } else if (build_channels(C, R, n, S, nch) < 0) {
+  } else if (build_channels(C, R, n, S, nch, mec_now()) < 0) {
     flags |= fColour;
   } else {
     uint32_t cycle = 0;
@@ -117,7 +119,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         if (T < Tch) { Tch = T; lnTch = lnT; }
         const double invc = S.ctr[oc].ic;
         Chan ch;
-        chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
+        chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
         for (int k = 0;; ++k) {
           if (k >= kVmMaxTrials) { capped = true; break; }
           if (!(Tch > tcut)) break;
@@ -159,7 +161,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       // the winner's accepted trial, as recorded
       const uint32_t info = S.ctr[(int64_t)R.lane * S.nch + win].info;
       Chan ch;
-      chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
+      chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
       const double t = exp(best);
       if (n + 1 > M) { flags |= fOverflow; break; }
       emit_map(R, n, maxtag, ch, wkern, wflav, wz, womz, wa1, wa2, wphi);
@@ -173,7 +175,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         bad |= !(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o]));
       }
       if (bad) { flags |= fNaN; break; }
-      if (build_channels(C, R, n, S, nch) < 0) { flags |= fColour; break; }
+      if (build_channels(C, R, n, S, nch, mec_now()) < 0) { flags |= fColour; break; }
       T = t;
       lnT = best;
     }
@@ -301,7 +303,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       double t = exp(best);
       uint32_t info = S.ctr[(int64_t)R.lane * S.nch + win].info;
       Chan ch;
-      chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch);
+      chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
       double u[4];
       rng4(seed, stream, id, cycle, 0xFFFFFFFFu, u);
       Term tm = select_term(C, ch, u[0]);
@@ -322,7 +324,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
           bad |= !(isfinite(R.E[o]) && isfinite(R.px[o]) && isfinite(R.py[o]) && isfinite(R.pz[o]));
         }
         if (bad) { flags |= fNaN; cycle += 1; break; }
-        if (build_channels(C, R, n, S, nch) < 0) { flags |= fColour; cycle += 1; break; }
+        if (build_channels(C, R, n, S, nch, mec_now()) < 0) { flags |= fColour; cycle += 1; break; }
       }
       T = t;
       lnT = best;

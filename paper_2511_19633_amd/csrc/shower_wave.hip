@@ -25,13 +25,16 @@ namespace gaps {
 namespace {
 
 // cache word: alive | type<<1 | heavy<<3 | spectator<<5 | eta bin<<13 | spectator eta bin<<19 |
-// learned cell<<25 (the cell whose 1/c the trial entry holds; 15: none yet)
+// learned cell<<25 (the cell whose 1/c the trial entry holds; 15: none yet) | null<<29 |
+// first-emission correction<<30
 constexpr uint32_t kCellShift = 25u, kCellMask = 15u << kCellShift, kCellNone = 15u;
 // retained trials: the entry's pending trial is a null at its cell's lower edge
 constexpr uint32_t kNullBit = 1u << 29;
+constexpr uint32_t kMecBit = 1u << 30;
 __device__ __forceinline__ uint32_t pack(const Chan& ch) {
   return (uint32_t)ch.alive | ((uint32_t)ch.type << 1) | ((uint32_t)ch.heavy << 3) | ((uint32_t)ch.k << 5) |
-         ((uint32_t)ch.ebin << 13) | ((uint32_t)ch.kbin << 19) | (kCellNone << kCellShift);
+         ((uint32_t)ch.ebin << 13) | ((uint32_t)ch.kbin << 19) | (kCellNone << kCellShift) |
+         (ch.mec ? kMecBit : 0u);
 }
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
@@ -142,7 +145,7 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
         if ((int)((info & kCellMask) >> kCellShift) != cell) {
           const Rec R = make_rec(S.part, 1, S.max_slots, slot);
           const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cwin[oc].I1,
-                                      S.cwin[oc].I2, cell);
+                                      S.cwin[oc].I2, cell, (info & kMecBit) != 0u);
           invc = 1.0 / ck;
           S.ctr[oc].ic = invc;
           S.cwin[oc].c = ck;
@@ -181,6 +184,7 @@ struct DrawState {
   uint32_t cycle;
   bool lrn;
   uint64_t seed;
+  bool mec;  // the event's next emission is corrected to the real matrix element
 };
 
 // set up the channel constants of up to 64 queued entries, one per lane
@@ -200,11 +204,12 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
     TL = __shfl(D.T, L); lnTL = __shfl(D.lnT, L); idL = __shfl(D.id, L);
     cyL = (uint32_t)__shfl((int)D.cycle, L); lrnL = __shfl((int)D.lrn, L) != 0;
   }
+  const bool mecL = __shfl((int)D.mec, L) != 0;
   if (!valid) return;
   const int q = (int)((it >> 6) & 0xFFu), side = (int)((it >> 14) & 1u), k = (int)(it >> 15);
   const Rec R = rec_of(W.S, slot);
   Chan ch;
-  chan_setup(W.C, R, q, side, k, ch);
+  chan_setup(W.C, R, q, side, k, ch, mecL);
   const int c = 2 * q + side;
   const int64_t oc = (int64_t)slot * W.S.nch + c;
   W.S.ctr[oc].info = pack(ch);
@@ -371,6 +376,7 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.k = (info >> 5) & 0xFFu;
   ch.ebin = (info >> 13) & 0x3Fu;
   ch.kbin = (info >> 19) & 0x3Fu;
+  ch.mec = (info & kMecBit) != 0u;
   ch.m2 = ch.heavy == 1 ? C.mc2 : (ch.heavy == 2 ? C.mb2 : 0.0);
   const Win wd = S.cwin[oc];
   const uint32_t pk = wd.pid;
@@ -711,7 +717,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     {
       const unsigned long long bm = __ballot(built);
       if (bm) {
-        const DrawState D{T, lnT, id, cycle, lrn, A.seed};
+        const DrawState D{T, lnT, id, cycle, lrn, A.seed, (flags & fMEC) != 0u && t1 == 0.0};
         uint32_t drawn = 0;
         uint32_t f =
             coop_build<RETAIN>(W, s_build[wid], bm, n, slot, fresh, fresh || em_all, em_i, em_k, D, drawn);
@@ -913,7 +919,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                   const int64_t oc = (int64_t)sL * S.nch + c;
                   const Rec RL = rec_of(S, sL);
                   const double ck = learned_c(C, type, RL.pid[RL.o(c >> 1)], (int)((info >> 13) & 0x3Fu),
-                                              S.cwin[oc].I1, S.cwin[oc].I2, cell);
+                                              S.cwin[oc].I1, S.cwin[oc].I2, cell, (info & kMecBit) != 0u);
                   invc = 1.0 / ck;
                   S.ctr[oc].ic = invc;
                   S.cwin[oc].c = ck;
@@ -1029,7 +1035,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         const Veto v = veto_weight(C, R, ch, tm, t, z, omz);
         if (log_mode) {
           // trial log: one atomic for the lanes of this branch that log
-          const bool dolog = (ch.type == kIF || ch.type == kII) && v.ok && v.wn > 0.0;
+          const bool dolog = (ch.type == kIF || ch.type == kII) && !ch.mec && v.ok && v.wn > 0.0;
           const unsigned long long lm = __ballot(dolog);
           if (lm) {
             const int leader = __ffsll((long long)lm) - 1;
