@@ -236,6 +236,10 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip timing max-veto, generate-select and veto-max in the one-event-per-lane "
                          "kernels on the first two batches, reported under \"competition_forms\"")
+    ap.add_argument("--no-matching", action="store_true",
+                    help="skip timing the plain shower of the matching variants (MC@NLO started at mZ^2, "
+                         "POWHEG-like events with the first-emission correction) on two batches of their own "
+                         "events, reported under \"matching\"")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
@@ -388,6 +392,29 @@ def main():
                          "cycles_per_event": st[0] / r["events"], "accepted_per_event": st[2] / r["events"]}
             log(f"{nm} (one event per lane): {forms[nm]['value']:.4g} events/s")
         out_extra["competition_forms"] = forms
+    if not args.no_matching:
+        # the matching variants: their own hard events (the same ids as the
+        # first two batches), the plain shower in the benchmark's launch
+        sub_n = [b[2] for b in batches[:2]]
+        nb = len(sub_n)
+        mt = {"events": int(sum(sub_n)), "kernel": kernel}
+        for nm, wl in (("mcatnlo_start_mz2", workloads.PP_NLO_MUQ), ("powheg", workloads.PP_NLO_POWHEG)):
+            Gm = binding.Gaps(workloads.config_dict(wl))
+            ins_m = [Gm.hard_events(int(a), int(m), seed, max_slots=8) for a, m in zip(starts[:nb], sub_n)]
+            sub = [(ins_m[k], outs[k], sub_n[k]) for k in range(nb)]
+            r = timed_stream(Gm, binding, sub, seed, args, kw, binding.MODE_PLAIN)
+            st = r["stats"]
+            w = torch.cat([i.w for i in ins_m])
+            mt[nm] = {"value": r["events"] / r["wall_s"], "cycles_per_event": st[0] / r["events"],
+                      "accepted_per_event": st[2] / r["events"], "violations": int(st[3]),
+                      "sigma_per_event": float(w.mean().item()),
+                      "negative_weight_fraction": float((w < 0).double().mean().item())}
+            log(f"matching {nm}: {mt[nm]['value']:.4g} events/s")
+            del ins_m, sub
+            Gm.close()
+        w0 = torch.cat([b[0].w for b in batches[:nb]])
+        mt["mcatnlo_power_shower_sigma_per_event"] = float(w0.mean().item())
+        out_extra["matching"] = mt
 
     out = {
         "metric": "showered events/sec, NLO pp→Z 13 TeV, 1 MI355X; plain vs learned-proposal",

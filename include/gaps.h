@@ -143,7 +143,8 @@ typedef struct {
                             initial-state winner trial with a positive weight:
                             ln t, ln eta, z, table entry, ln(alpha_s(t)/
                             alpha_s(t_c) W / shape(z)); rows beyond log_cap are
-                            counted, not stored */
+                            counted, not stored; trials of a GAPS_F_MEC event's
+                            corrected first emission are not logged */
     int64_t log_cap;
     unsigned long long* log_count; /* LOG mode: device counter */
     unsigned long long* stats;     /* optional device [GAPS_NSTATS] */
