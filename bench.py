@@ -372,6 +372,20 @@ def main():
                                 "mean_bound_over_analytic": bound_over_analytic(G),
                                 "histogram_chi2_ndf_vs_plain": chi_vs_plain(h_plain, histos()),
                                 "roofline": rf, "shower_stats": st}
+        # the same with adaptive cell sizes (each cell from the finest block
+        # around it with enough logged trials)
+        t0 = time.perf_counter()
+        G.cellmax_table(log_rows, int(0.8 * log_rows.shape[0]), adaptive=True)
+        torch.cuda.synchronize()
+        t_tab = time.perf_counter() - t0
+        r = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
+        v, ms, rf, st = summarise(r, "cellmax_adaptive")
+        log(f"cell-maximum bound, adaptive cells: {v:.4g} events/s")
+        out_extra["cellmax_adaptive"] = {"value": v, "ms_per_step": ms, "speedup_over_plain": v / v_plain,
+                                         "speedup_over_learned": v / v_l, "table_s": t_tab,
+                                         "mean_bound_over_analytic": bound_over_analytic(G),
+                                         "histogram_chi2_ndf_vs_plain": chi_vs_plain(h_plain, histos()),
+                                         "roofline": rf, "shower_stats": st}
     if args.mode == "learned":
         del log_rows
     if not args.no_forms:

@@ -23,8 +23,18 @@ Held-out rows, per entry, over cells with n >= MIN_CELL:
 Table: min(R, up6(R exp(v))), v = clip(ymax + delta_e, -20, 0), for cells with
 n >= MIN_CELL in calibrated entries; R (the analytic bound) elsewhere.
 
+Adaptive cell sizes (adaptive=True): in the spirit of ExSample's cell
+splitting, every cell takes the finest block around it that holds enough
+presampled trials.  The blocks are dyadic in (eta bin, ln t cell): level l
+groups the cells whose indices agree after shifting right by SHIFTS[l]
+(level 0 is the cell itself, the last level the whole entry).  A cell's
+maximum is the largest y of the first level whose block has at least MIN_CELL
+fitting rows, and such cells count as fitted (for the held-out rows as for the
+table); cells of entries with fewer rows keep the analytic bound.
+
 Pinned by tests/test_oracle_cellmax.py (every fitting row covered, closed-form
-cells, calibration raising the bound over held-out rows, untouched cells).
+cells, calibration raising the bound over held-out rows, untouched cells, the
+adaptive blocks).
 """
 from __future__ import annotations
 
@@ -34,6 +44,33 @@ from oracle.mlp import CAL_MARGIN, DLE, IS0, LNETA0, MIN_CAL, NB, NENT_IS, NTB, 
 
 MIN_CELL = 16
 NCELL = NENT_IS * NB * NTB
+# (eta bin, ln t cell) shifts of the dyadic blocks of each level
+SHIFTS = ((0, 0), (1, 1), (2, 2), (3, 3), (4, 3), (5, 3), (6, 3))
+
+
+def adaptive_cells(ymax, n):
+    """Per cell the maximum and row count of the finest block around it with at
+    least MIN_CELL rows (-inf and 0 where even the whole entry has fewer)."""
+    ym = ymax.reshape(NENT_IS, NB, NTB)
+    nn = n.reshape(NENT_IS, NB, NTB)
+    out_y = np.full(ym.shape, -np.inf)
+    out_n = np.zeros(nn.shape, dtype=np.int64)
+    done = np.zeros(ym.shape, dtype=bool)
+    bi = np.arange(NB)[:, None]
+    ki = np.arange(NTB)[None, :]
+    for sb, sk in SHIFTS:
+        for e in range(NENT_IS):
+            for b in range(NB):
+                for k in range(NTB):
+                    if done[e, b, k]:
+                        continue
+                    blk = ((bi >> sb) == (b >> sb)) & ((ki >> sk) == (k >> sk))
+                    cnt = int(nn[e][blk].sum())
+                    if cnt >= MIN_CELL:
+                        out_y[e, b, k] = ym[e][blk].max()
+                        out_n[e, b, k] = cnt
+                        done[e, b, k] = True
+    return out_y.reshape(-1), out_n.reshape(-1)
 
 
 def cells(rows, bounds, cell_edges):
@@ -55,13 +92,15 @@ def cells(rows, bounds, cell_edges):
     return ((ent - IS0) * NB + b) * NTB + k, y, ent
 
 
-def cellmax_table(rows_fit, rows_cal, bounds, cell_edges):
+def cellmax_table(rows_fit, rows_cal, bounds, cell_edges, adaptive=False):
     """The cell-maximum table [64][48][8] (doubles), the per-entry delta (inf:
-    analytic) and the fitting-row count of each cell."""
+    analytic) and the fitting-row count of each cell (adaptive: of its block)."""
     c, y, _ = cells(rows_fit, bounds, cell_edges)
     ymax = np.full(NCELL, -np.inf)
     np.maximum.at(ymax, c, y)
     n = np.bincount(c, minlength=NCELL)
+    if adaptive:
+        ymax, n = adaptive_cells(ymax, n)
     cc, yc, ec = cells(rows_cal, bounds, cell_edges)
     use = n[cc] >= MIN_CELL
     e = ec[use] - IS0

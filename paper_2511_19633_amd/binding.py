@@ -103,6 +103,7 @@ def lib():
         L.gaps_mlp_calibrate.argtypes = [vp, vp, vp, vp, i64, vp]
         L.gaps_mlp_set_delta.argtypes = [vp, vp]
         L.gaps_cellmax_table.argtypes = [vp, vp, i64, i64, vp]
+        L.gaps_cellmax_table_adaptive.argtypes = [vp, vp, i64, i64, vp]
         L.gaps_mlp_get_delta.argtypes = [vp, vp]
         L.gaps_mlp_tabulate.argtypes = [vp, vp]
         L.gaps_learned_table.argtypes = [vp, vp]
@@ -335,12 +336,14 @@ class Gaps:
     def mlp_tabulate(self, stream=None):
         _check(lib().gaps_mlp_tabulate(self.h, _stream(stream)))
 
-    def cellmax_table(self, rows, n_fit, stream=None):
+    def cellmax_table(self, rows, n_fit, stream=None, adaptive=False):
         """Cell-maximum bound from LOG rows (device [n][5] float32): the first
-        n_fit rows fit the cells, the rest calibrate; becomes the learned table."""
+        n_fit rows fit the cells, the rest calibrate; becomes the learned table.
+        adaptive: each cell from the finest block around it with enough rows."""
         assert rows.dtype == torch.float32 and rows.is_cuda and rows.dim() == 2 and rows.shape[1] == 5
         rows = rows.contiguous()
-        _check(lib().gaps_cellmax_table(self.h, _ptr(rows), int(n_fit), int(rows.shape[0] - n_fit), _stream(stream)))
+        fn = lib().gaps_cellmax_table_adaptive if adaptive else lib().gaps_cellmax_table
+        _check(fn(self.h, _ptr(rows), int(n_fit), int(rows.shape[0] - n_fit), _stream(stream)))
 
     def learned_table(self) -> np.ndarray:
         t = np.zeros(LEARN_SHAPE, dtype=np.float64)

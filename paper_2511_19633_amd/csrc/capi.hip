@@ -693,17 +693,26 @@ gaps_status gaps_mlp_tabulate(gaps_ctx c, hipStream_t stream) {
   return GAPS_OK;
 }
 
-gaps_status gaps_cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, int64_t n_cal, hipStream_t stream) {
+static gaps_status cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, int64_t n_cal, bool adaptive,
+                                 hipStream_t stream) {
   if (!c || !rows || n_fit <= 0 || n_cal < 0) return GAPS_EINVAL;
   gaps_status s = mlp_alloc(c);
   if (s != GAPS_OK) return s;
-  const int64_t nc = GAPS_LEARN_CELLS, words = 2 * nc + 2 * 64;
+  const int64_t nc = GAPS_LEARN_CELLS, words = 4 * nc + 2 * 64;
   if (!c->cm_mem && hipMalloc((void**)&c->cm_mem, (size_t)words * 8) != hipSuccess) return GAPS_ENOMEM;
   unsigned long long *ymax = c->cm_mem, *cnt = ymax + nc, *emax = cnt + nc, *ecnt = emax + 64;
+  unsigned long long *aymax = ecnt + 64, *acnt = aymax + nc;
   // fill kernels, not memsets, so that the call may be captured in a graph
   hipLaunchKernelGGL(gaps::k_fill_u64, dim3(grid_for(words, 256)), dim3(256), 0, stream, c->cm_mem, words, 0ull);
   hipLaunchKernelGGL(gaps::k_cellmax_fit, dim3(grid_for(n_fit, 256) < 2048 ? grid_for(n_fit, 256) : 2048), dim3(256),
                      0, stream, c->C, rows, n_fit, ymax, cnt);
+  if (adaptive) {
+    // every cell's block maximum and count then stand in for its own
+    hipLaunchKernelGGL(gaps::k_cellmax_adapt, dim3(grid_for(nc, 256)), dim3(256), 0, stream, ymax, cnt,
+                       (long long)GAPS_CELLMAX_MIN_CELL, aymax, acnt);
+    ymax = aymax;
+    cnt = acnt;
+  }
   if (n_cal > 0)
     hipLaunchKernelGGL(gaps::k_cellmax_resid, dim3(grid_for(n_cal, 256) < 1024 ? grid_for(n_cal, 256) : 1024),
                        dim3(256), 0, stream, c->C, rows + 5 * n_fit, n_cal, ymax, cnt, (long long)GAPS_CELLMAX_MIN_CELL,
@@ -713,6 +722,15 @@ gaps_status gaps_cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, int
   GAPS_HIP(hipGetLastError());
   c->C.learn = c->table;
   return GAPS_OK;
+}
+
+gaps_status gaps_cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, int64_t n_cal, hipStream_t stream) {
+  return cellmax_table(c, rows, n_fit, n_cal, false, stream);
+}
+
+gaps_status gaps_cellmax_table_adaptive(gaps_ctx c, const float* rows, int64_t n_fit, int64_t n_cal,
+                                        hipStream_t stream) {
+  return cellmax_table(c, rows, n_fit, n_cal, true, stream);
 }
 
 gaps_status gaps_learned_table(gaps_ctx c, double* host_out) {

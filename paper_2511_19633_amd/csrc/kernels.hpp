@@ -121,6 +121,8 @@ __global__ void k_cellmax_fit(Cfg C, const float* rows, int64_t n, unsigned long
 __global__ void k_cellmax_resid(Cfg C, const float* rows, int64_t n, const unsigned long long* ymax,
                                 const unsigned long long* count, long long min_cell, unsigned long long* emax,
                                 unsigned long long* ecount);
+__global__ void k_cellmax_adapt(const unsigned long long* ymax, const unsigned long long* count, long long min_cell,
+                                unsigned long long* aymax, unsigned long long* acount);
 __global__ void k_cellmax_table(const unsigned long long* ymax, const unsigned long long* count,
                                 const unsigned long long* emax, const unsigned long long* ecount, long long min_cell,
                                 long long min_cal, double margin, const double* bound, double* table);

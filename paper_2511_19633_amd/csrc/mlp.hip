@@ -479,6 +479,35 @@ __global__ void k_cellmax_fit(Cfg C, const float* rows, int64_t n, unsigned long
 
 // largest excess y - ymax(cell) of the held-out rows per entry, over cells
 // with at least min_cell fitting rows, and the number of such rows
+// Adaptive cell sizes: each cell takes the finest dyadic block of (eta bin,
+// ln t cell) around it with at least min_cell fitting rows (level l: indices
+// equal after shifting right by (l, l) up to the ln t range, then the eta
+// range), and that block's largest target and row count; none: 0 and 0 (the
+// cell then keeps the analytic bound).  ymax holds order-preserving bit
+// patterns with 0 for an empty cell, below every value.
+__global__ void k_cellmax_adapt(const unsigned long long* ymax, const unsigned long long* count, long long min_cell,
+                                unsigned long long* aymax, unsigned long long* acount) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= kNIS * kNB * kNTB) return;
+  const int e = cell / (kNB * kNTB), b = (cell / kNTB) % kNB, k = cell % kNTB;
+  unsigned long long ay = 0ull, an = 0ull;
+  for (int l = 0; l < 7; ++l) {
+    const int sb = l, sk = l < 3 ? l : 3;
+    const int b0 = (b >> sb) << sb, k0 = (k >> sk) << sk;
+    const int b1 = b0 + (1 << sb) < kNB ? b0 + (1 << sb) : kNB, k1 = k0 + (1 << sk) < kNTB ? k0 + (1 << sk) : kNTB;
+    unsigned long long m = 0ull, n = 0ull;
+    for (int bb = b0; bb < b1; ++bb)
+      for (int kk = k0; kk < k1; ++kk) {
+        const int q = (e * kNB + bb) * kNTB + kk;
+        n += count[q];
+        m = ymax[q] > m ? ymax[q] : m;
+      }
+    if ((long long)n >= min_cell) { ay = m; an = n; break; }
+  }
+  aymax[cell] = ay;
+  acount[cell] = an;
+}
+
 __global__ void k_cellmax_resid(Cfg C, const float* rows, int64_t n, const unsigned long long* ymax,
                                 const unsigned long long* count, long long min_cell, unsigned long long* emax,
                                 unsigned long long* ecount) {

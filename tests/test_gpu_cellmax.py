@@ -106,3 +106,46 @@ def test_cellmax_distributions_and_gain(G):
         chi, ndf, p = chi2_compare(oa[:, col], ob[:, col], w, w, edges)
         say(f"  column {col}: chi2/ndf {chi / ndf:.3f} (p {p:.3g})")
         assert p > 1e-3
+
+
+def test_cellmax_adaptive_table_matches_oracle(G, oracles, logged):
+    """Adaptive cell sizes: the GPU table equals the oracle's bit for bit."""
+    import torch
+    O = oracles["nlo"]
+    rows, nf = logged[0], logged[1]
+    G.cellmax_table(torch.from_numpy(np.ascontiguousarray(rows)).cuda(), nf, adaptive=True)
+    g = G.learned_table()
+    o, _, na = cellmax.cellmax_table(rows[:nf], rows[nf:], O.bounds(), O.cell_edges(), adaptive=True)
+    say(f"  adaptive: cells differing {int((g != o).sum())}, cells with a block {int((na > 0).sum())}")
+    assert np.array_equal(g, o)
+
+
+def test_cellmax_adaptive_distributions_and_gain(G):
+    """10^6 NLO events with adaptive cells from 4 * 10^5 logged events: the
+    plain shower's distributions, rare fallbacks, no more veto cycles than the
+    fixed cells."""
+    import torch
+    from paper_2511_19633_amd import binding
+    from tests.histcheck import chi2_compare
+    _, rows, cnt = G.shower_log(G.hard_events(1 << 40, 400_000, 1, max_slots=8), 1, 50_000_000)
+    n = 1_000_000
+    gin = G.hard_events(0, n, 1, max_slots=8)
+    outs, cyc = {}, {}
+    for adaptive in (False, True):
+        G.cellmax_table(rows, int(0.8 * rows.shape[0]), adaptive=adaptive)
+        st = torch.zeros(binding.NSTATS, dtype=torch.uint64, device="cuda")
+        outs[adaptive] = G.shower(gin, 3, stats=st, mode=binding.MODE_LEARNED, retain=True,
+                                  max_slots=workloads.MAX_SLOTS)
+        cyc[adaptive] = float(st.cpu().numpy().astype(float)[0]) / n
+    a = G.shower(gin, 3, retain=True, max_slots=workloads.MAX_SLOTS)
+    b = outs[True]
+    fb = int(((b.flags.cpu().numpy() & records.FLAG_FALLBACK) != 0).sum())
+    say(f"  cycles/event fixed {cyc[False]:.1f}, adaptive {cyc[True]:.1f}; fallbacks {fb}")
+    assert cyc[True] <= cyc[False] * 1.01
+    assert fb < 1e-3 * n
+    w = gin.w.cpu().numpy()
+    oa, ob = G.observables(a).cpu().numpy(), G.observables(b).cpu().numpy()
+    for col, edges in ((0, np.linspace(0.0, 60.0, 31)), (4, np.arange(-0.5, 7.0)), (9, np.arange(3.5, 31.0))):
+        chi, ndf, p = chi2_compare(oa[:, col], ob[:, col], w, w, edges)
+        say(f"  column {col}: chi2/ndf {chi / ndf:.3f} (p {p:.3g})")
+        assert p > 1e-3

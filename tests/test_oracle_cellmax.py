@@ -129,3 +129,63 @@ def test_logged_trials_are_covered(nlo):
     cc, yc, _ = cellmax.cells(rows[nf:], B, E)
     over = rflat[cc] * np.exp(yc) > flat[cc]
     assert over.mean() < 1e-3
+
+
+def test_adaptive_blocks_closed_form(nlo):
+    """Adaptive cell sizes: a well sampled cell keeps its own maximum, a thin
+    neighbour takes the maximum of the smallest dyadic block with enough rows,
+    an empty corner of the entry the whole entry's, and an entry with too few
+    rows in all keeps the analytic bound."""
+    o, B, E = nlo
+    e = 33
+    rich = [_row(e, 16, 3, y, B, E) for y in np.linspace(-3.0, -2.5, 20)]
+    thin = [_row(e, 17, 3, -1.0, B, E)] * 5
+    lone = [_row(50, 9, 5, -2.0, B, E)] * 10
+    cal = [_row(e, 16, 3, -2.75, B, E)] * 2000 + [_row(50, 9, 5, -2.0, B, E)] * 2000
+    tab, delta, n = _table(rich + thin + lone, cal, B, E)
+    taba, deltaa, na = cellmax.cellmax_table(np.array(rich + thin + lone, dtype=np.float32),
+                                             np.array(cal, dtype=np.float32), B, E, adaptive=True)
+    R = B[e]
+    top_rich, top_thin = float(np.float32(-2.5)), float(np.float32(-1.0))
+    m = 2.0 ** -6
+    # the rich cell: its own maximum, as on the fixed grid
+    assert taba[e - 8, 16, 3] == tab[e - 8, 16, 3]
+    assert R[16] * math.exp(top_rich + m) <= taba[e - 8, 16, 3] <= R[16] * math.exp(top_rich + m) * (1 + m)
+    # the thin cell: the 2 x 2 block (eta bins 16-17, ln t cells 2-3) with 25 rows
+    assert na[e - 8, 17, 3] == 25 and n[e - 8, 17, 3] == 5
+    assert tab[e - 8, 17, 3] == R[17]
+    assert R[17] * math.exp(top_thin + m) <= taba[e - 8, 17, 3] <= R[17] * math.exp(top_thin + m) * (1 + m)
+    # far corners of the entry: the whole entry (25 rows) at the last level
+    assert na[e - 8, 47, 7] == 25 and na[e - 8, 0, 0] == 25
+    assert R[47] * math.exp(top_thin + m) <= taba[e - 8, 47, 7] <= R[47] * math.exp(top_thin + m) * (1 + m)
+    # a 4 x 4 block holds the thin and rich cells at level 2
+    assert na[e - 8, 19, 0] == 25
+    # entry 50 has 10 rows in all: analytic everywhere
+    R3 = np.broadcast_to(B[8:72, :, None], tab.shape)
+    assert np.array_equal(taba[50 - 8], R3[50 - 8]) and np.isinf(deltaa[50 - 8])
+    # entries without rows are untouched
+    assert np.array_equal(taba[20 - 8], R3[20 - 8])
+
+
+def test_adaptive_logged_trials(nlo):
+    """On logged trials of 6000 NLO events: with adaptive cells every fitting
+    row stays under its cell's bound, well sampled cells keep their own
+    maximum, fewer cells of calibrated entries stay analytic, and held-out
+    rows above the bound are rare."""
+    o, B, E = nlo
+    _, rows, cnt = o.shower_log(o.hard_events(2_000_000, 6000, 3), 3, 3_000_000, nthreads=1)
+    nf = int(0.8 * cnt)
+    tab, delta, n = cellmax.cellmax_table(rows[:nf], rows[nf:], B, E)
+    taba, deltaa, na = cellmax.cellmax_table(rows[:nf], rows[nf:], B, E, adaptive=True)
+    R3 = np.broadcast_to(B[8:72, :, None], tab.shape)
+    assert np.all(taba <= R3) and np.all(taba[R3 > 0] > 0)
+    c, y, _ = cellmax.cells(rows[:nf], B, E)
+    flat, rflat = taba.reshape(-1), R3.reshape(-1)
+    assert np.all(rflat[c] * np.exp(y) <= flat[c] * (1 + 1e-12))
+    own = n >= cellmax.MIN_CELL
+    assert np.array_equal(na[own], n[own])
+    cal = np.isfinite(deltaa)
+    live = cal[:, None, None] & (R3 > 0)
+    assert np.sum(live & (taba == R3)) < np.sum(live & (tab == R3))
+    cc, yc, _ = cellmax.cells(rows[nf:], B, E)
+    assert np.mean(rflat[cc] * np.exp(yc) > flat[cc]) < 1e-3
