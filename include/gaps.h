@@ -308,7 +308,7 @@ gaps_status gaps_graph_destroy(gaps_graph g);
  * analytic R.  The table replaces the context's learned table (read it back
  * with gaps_learned_table).  Asynchronous on stream; rows must stay valid until
  * the stream reaches the call.  Errors: GAPS_EINVAL for a NULL context or rows,
- * n_fit <= 0 or n_cal < 0; GAPS_ENOMEM if its 800 KB of cell counters cannot
+ * n_fit <= 0 or n_cal < 0; GAPS_ENOMEM if its 1 MB of cell counters cannot
  * be allocated (first call only, shared with the adaptive variant). */
 #define GAPS_CELLMAX_MIN_CELL 16
 #define GAPS_CELLMAX_MIN_CAL 2000
@@ -322,8 +322,11 @@ gaps_status gaps_cellmax_table(gaps_ctx ctx, const float* rows, int64_t n_fit, i
  * the cells whose indices agree after shifting right by (l, min(l, 3)), l = 0
  * (the cell alone) .. 6 (the whole entry).  So a thinly sampled cell is bounded
  * by the trials of its neighbourhood instead of the analytic bound, and a well
- * sampled one by its own.  Cells of entries with fewer rows in all keep R.
- * Same arguments, scratch, asynchrony and errors. */
+ * sampled one by its own.  The held-out margin of a level-0 cell is its
+ * entry's (from level-0 rows, as above); the cells of each coarser level share
+ * one margin from the held-out rows of all such cells of every entry (at least
+ * GAPS_CELLMAX_MIN_CAL, else they keep R).  Cells of entries with fewer rows
+ * in all keep R.  Same arguments, scratch, asynchrony and errors. */
 gaps_status gaps_cellmax_table_adaptive(gaps_ctx ctx, const float* rows, int64_t n_fit, int64_t n_cal,
                                         hipStream_t stream);
 

@@ -29,8 +29,11 @@ presampled trials.  The blocks are dyadic in (eta bin, ln t cell): level l
 groups the cells whose indices agree after shifting right by SHIFTS[l]
 (level 0 is the cell itself, the last level the whole entry).  A cell's
 maximum is the largest y of the first level whose block has at least MIN_CELL
-fitting rows, and such cells count as fitted (for the held-out rows as for the
-table); cells of entries with fewer rows keep the analytic bound.
+fitting rows; cells of entries with fewer rows keep the analytic bound.  The
+held-out margin of a cell at level 0 is its entry's, as on the fixed cells;
+cells at a coarser level l share one margin per level, from the held-out rows
+of all such cells of every entry (with the same MIN_CAL threshold), so that
+thinly sampled cells do not loosen the well sampled ones of their entry.
 
 Pinned by tests/test_oracle_cellmax.py (every fitting row covered, closed-form
 cells, calibration raising the bound over held-out rows, untouched cells, the
@@ -49,16 +52,18 @@ SHIFTS = ((0, 0), (1, 1), (2, 2), (3, 3), (4, 3), (5, 3), (6, 3))
 
 
 def adaptive_cells(ymax, n):
-    """Per cell the maximum and row count of the finest block around it with at
-    least MIN_CELL rows (-inf and 0 where even the whole entry has fewer)."""
+    """Per cell the maximum, row count and level of the finest block around it
+    with at least MIN_CELL rows (-inf, 0 and -1 where even the whole entry has
+    fewer)."""
     ym = ymax.reshape(NENT_IS, NB, NTB)
     nn = n.reshape(NENT_IS, NB, NTB)
     out_y = np.full(ym.shape, -np.inf)
     out_n = np.zeros(nn.shape, dtype=np.int64)
+    out_l = np.full(nn.shape, -1, dtype=np.int64)
     done = np.zeros(ym.shape, dtype=bool)
     bi = np.arange(NB)[:, None]
     ki = np.arange(NTB)[None, :]
-    for sb, sk in SHIFTS:
+    for lev, (sb, sk) in enumerate(SHIFTS):
         for e in range(NENT_IS):
             for b in range(NB):
                 for k in range(NTB):
@@ -69,8 +74,9 @@ def adaptive_cells(ymax, n):
                     if cnt >= MIN_CELL:
                         out_y[e, b, k] = ym[e][blk].max()
                         out_n[e, b, k] = cnt
+                        out_l[e, b, k] = lev
                         done[e, b, k] = True
-    return out_y.reshape(-1), out_n.reshape(-1)
+    return out_y.reshape(-1), out_n.reshape(-1), out_l.reshape(-1)
 
 
 def cells(rows, bounds, cell_edges):
@@ -93,25 +99,33 @@ def cells(rows, bounds, cell_edges):
 
 
 def cellmax_table(rows_fit, rows_cal, bounds, cell_edges, adaptive=False):
-    """The cell-maximum table [64][48][8] (doubles), the per-entry delta (inf:
-    analytic) and the fitting-row count of each cell (adaptive: of its block)."""
+    """The cell-maximum table [64][48][8] (doubles), the per-entry delta of the
+    entries' own cells (inf: analytic) and the fitting-row count of each cell
+    (adaptive: of its block)."""
     c, y, _ = cells(rows_fit, bounds, cell_edges)
     ymax = np.full(NCELL, -np.inf)
     np.maximum.at(ymax, c, y)
     n = np.bincount(c, minlength=NCELL)
+    # calibration group of each cell: its entry (the cell's own rows), or one
+    # group per coarser level of the adaptive blocks
+    grp = np.repeat(np.arange(NENT_IS), NB * NTB)
     if adaptive:
-        ymax, n = adaptive_cells(ymax, n)
+        ymax, n, lev = adaptive_cells(ymax, n)
+        grp = np.where(lev > 0, NENT_IS + lev - 1, grp)
+    ngrp = NENT_IS + len(SHIFTS) - 1
     cc, yc, ec = cells(rows_cal, bounds, cell_edges)
     use = n[cc] >= MIN_CELL
-    e = ec[use] - IS0
-    excess = np.full(NENT_IS, -np.inf)
-    np.maximum.at(excess, e, yc[use] - ymax[cc[use]])
-    ncal = np.bincount(e, minlength=NENT_IS)
-    delta = np.where(ncal >= MIN_CAL, np.maximum(excess, 0.0) + CAL_MARGIN, np.inf)
+    g = grp[cc[use]]
+    excess = np.full(ngrp, -np.inf)
+    np.maximum.at(excess, g, yc[use] - ymax[cc[use]])
+    ncal = np.bincount(g, minlength=ngrp)
+    dgrp = np.where(ncal >= MIN_CAL, np.maximum(excess, 0.0) + CAL_MARGIN, np.inf)
+    delta = dgrp[:NENT_IS]
+    dcell = dgrp[grp].reshape(NENT_IS, NB, NTB)
     R = np.broadcast_to(np.asarray(bounds, dtype=np.float64)[IS0:IS0 + NENT_IS, :, None], (NENT_IS, NB, NTB))
     ym = ymax.reshape(NENT_IS, NB, NTB)
-    fitted = (n.reshape(NENT_IS, NB, NTB) >= MIN_CELL) & np.isfinite(delta)[:, None, None] & (R > 0.0)
+    fitted = (n.reshape(NENT_IS, NB, NTB) >= MIN_CELL) & np.isfinite(dcell) & (R > 0.0)
     with np.errstate(invalid="ignore", over="ignore"):
-        v = np.clip(ym + delta[:, None, None], V_MIN, 0.0)
+        v = np.clip(ym + dcell, V_MIN, 0.0)
         tab = np.where(fitted, np.minimum(R, up6(R * np.exp(v))), R)
     return np.ascontiguousarray(tab, dtype=np.float64), delta, n.reshape(NENT_IS, NB, NTB)

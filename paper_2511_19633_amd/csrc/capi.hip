@@ -698,10 +698,11 @@ static gaps_status cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, i
   if (!c || !rows || n_fit <= 0 || n_cal < 0) return GAPS_EINVAL;
   gaps_status s = mlp_alloc(c);
   if (s != GAPS_OK) return s;
-  const int64_t nc = GAPS_LEARN_CELLS, words = 4 * nc + 2 * 64;
+  const int64_t nc = GAPS_LEARN_CELLS, words = 5 * nc + 2 * 128;
   if (!c->cm_mem && hipMalloc((void**)&c->cm_mem, (size_t)words * 8) != hipSuccess) return GAPS_ENOMEM;
-  unsigned long long *ymax = c->cm_mem, *cnt = ymax + nc, *emax = cnt + nc, *ecnt = emax + 64;
-  unsigned long long *aymax = ecnt + 64, *acnt = aymax + nc;
+  static_assert(gaps::kCmGroups <= 128, "calibration groups");
+  unsigned long long *ymax = c->cm_mem, *cnt = ymax + nc, *emax = cnt + nc, *ecnt = emax + 128;
+  unsigned long long *aymax = ecnt + 128, *acnt = aymax + nc, *alvl = acnt + nc, *lvl = nullptr;
   // fill kernels, not memsets, so that the call may be captured in a graph
   hipLaunchKernelGGL(gaps::k_fill_u64, dim3(grid_for(words, 256)), dim3(256), 0, stream, c->cm_mem, words, 0ull);
   hipLaunchKernelGGL(gaps::k_cellmax_fit, dim3(grid_for(n_fit, 256) < 2048 ? grid_for(n_fit, 256) : 2048), dim3(256),
@@ -709,15 +710,16 @@ static gaps_status cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, i
   if (adaptive) {
     // every cell's block maximum and count then stand in for its own
     hipLaunchKernelGGL(gaps::k_cellmax_adapt, dim3(grid_for(nc, 256)), dim3(256), 0, stream, ymax, cnt,
-                       (long long)GAPS_CELLMAX_MIN_CELL, aymax, acnt);
+                       (long long)GAPS_CELLMAX_MIN_CELL, aymax, acnt, alvl);
     ymax = aymax;
     cnt = acnt;
+    lvl = alvl;
   }
   if (n_cal > 0)
     hipLaunchKernelGGL(gaps::k_cellmax_resid, dim3(grid_for(n_cal, 256) < 1024 ? grid_for(n_cal, 256) : 1024),
-                       dim3(256), 0, stream, c->C, rows + 5 * n_fit, n_cal, ymax, cnt, (long long)GAPS_CELLMAX_MIN_CELL,
-                       emax, ecnt);
-  hipLaunchKernelGGL(gaps::k_cellmax_table, dim3(grid_for(nc, 256)), dim3(256), 0, stream, ymax, cnt, emax, ecnt,
+                       dim3(256), 0, stream, c->C, rows + 5 * n_fit, n_cal, ymax, cnt, lvl,
+                       (long long)GAPS_CELLMAX_MIN_CELL, emax, ecnt);
+  hipLaunchKernelGGL(gaps::k_cellmax_table, dim3(grid_for(nc, 256)), dim3(256), 0, stream, ymax, cnt, lvl, emax, ecnt,
                      (long long)GAPS_CELLMAX_MIN_CELL, (long long)GAPS_CELLMAX_MIN_CAL, 0.015625, c->d_bound, c->table);
   GAPS_HIP(hipGetLastError());
   c->C.learn = c->table;

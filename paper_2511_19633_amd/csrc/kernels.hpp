@@ -118,14 +118,18 @@ __global__ void k_mlp_delta(const unsigned long long* maxbits, const unsigned lo
 __global__ void k_mlp_probes(Cfg C, float* x);
 __global__ void k_mlp_table(const float* f, const double* delta, const double* bound, double* table);
 __global__ void k_cellmax_fit(Cfg C, const float* rows, int64_t n, unsigned long long* ymax, unsigned long long* count);
+// calibration groups of the cell-maximum bound: one per entry, and one per
+// coarser level of the adaptive blocks
+constexpr int kCmGroups = kNIS + 6;
 __global__ void k_cellmax_resid(Cfg C, const float* rows, int64_t n, const unsigned long long* ymax,
-                                const unsigned long long* count, long long min_cell, unsigned long long* emax,
-                                unsigned long long* ecount);
+                                const unsigned long long* count, const unsigned long long* level, long long min_cell,
+                                unsigned long long* emax, unsigned long long* ecount);
 __global__ void k_cellmax_adapt(const unsigned long long* ymax, const unsigned long long* count, long long min_cell,
-                                unsigned long long* aymax, unsigned long long* acount);
+                                unsigned long long* aymax, unsigned long long* acount, unsigned long long* alevel);
 __global__ void k_cellmax_table(const unsigned long long* ymax, const unsigned long long* count,
-                                const unsigned long long* emax, const unsigned long long* ecount, long long min_cell,
-                                long long min_cal, double margin, const double* bound, double* table);
+                                const unsigned long long* level, const unsigned long long* emax,
+                                const unsigned long long* ecount, long long min_cell, long long min_cal, double margin,
+                                const double* bound, double* table);
 __global__ void k_histogram(const double* obs, const double* w, int64_t n, int col, double lo, double hi,
                             int nbins, double* sumw, double* sumw2);
 

@@ -482,15 +482,15 @@ __global__ void k_cellmax_fit(Cfg C, const float* rows, int64_t n, unsigned long
 // Adaptive cell sizes: each cell takes the finest dyadic block of (eta bin,
 // ln t cell) around it with at least min_cell fitting rows (level l: indices
 // equal after shifting right by (l, l) up to the ln t range, then the eta
-// range), and that block's largest target and row count; none: 0 and 0 (the
-// cell then keeps the analytic bound).  ymax holds order-preserving bit
+// range), and that block's largest target, row count and level; none: 0, 0, 0
+// (the cell then keeps the analytic bound).  ymax holds order-preserving bit
 // patterns with 0 for an empty cell, below every value.
 __global__ void k_cellmax_adapt(const unsigned long long* ymax, const unsigned long long* count, long long min_cell,
-                                unsigned long long* aymax, unsigned long long* acount) {
+                                unsigned long long* aymax, unsigned long long* acount, unsigned long long* alevel) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= kNIS * kNB * kNTB) return;
   const int e = cell / (kNB * kNTB), b = (cell / kNTB) % kNB, k = cell % kNTB;
-  unsigned long long ay = 0ull, an = 0ull;
+  unsigned long long ay = 0ull, an = 0ull, al = 0ull;
   for (int l = 0; l < 7; ++l) {
     const int sb = l, sk = l < 3 ? l : 3;
     const int b0 = (b >> sb) << sb, k0 = (k >> sk) << sk;
@@ -502,28 +502,36 @@ __global__ void k_cellmax_adapt(const unsigned long long* ymax, const unsigned l
         n += count[q];
         m = ymax[q] > m ? ymax[q] : m;
       }
-    if ((long long)n >= min_cell) { ay = m; an = n; break; }
+    if ((long long)n >= min_cell) { ay = m; an = n; al = (unsigned long long)l; break; }
   }
   aymax[cell] = ay;
   acount[cell] = an;
+  alevel[cell] = al;
+}
+
+// calibration group of a cell: its entry, or (adaptive cells at a coarser
+// level l > 0) group kNIS + l - 1 shared by all entries
+__device__ __forceinline__ int cm_group(const unsigned long long* level, int cell) {
+  const int l = level ? (int)level[cell] : 0;
+  return l > 0 ? kNIS + l - 1 : cell / (kNB * kNTB);
 }
 
 __global__ void k_cellmax_resid(Cfg C, const float* rows, int64_t n, const unsigned long long* ymax,
-                                const unsigned long long* count, long long min_cell, unsigned long long* emax,
-                                unsigned long long* ecount) {
-  __shared__ unsigned long long sm[kNIS], sc[kNIS];
-  for (int q = threadIdx.x; q < kNIS; q += blockDim.x) { sm[q] = 0ull; sc[q] = 0ull; }
+                                const unsigned long long* count, const unsigned long long* level, long long min_cell,
+                                unsigned long long* emax, unsigned long long* ecount) {
+  __shared__ unsigned long long sm[kCmGroups], sc[kCmGroups];
+  for (int q = threadIdx.x; q < kCmGroups; q += blockDim.x) { sm[q] = 0ull; sc[q] = 0ull; }
   __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double y;
     const int c = cm_cell(C, rows + 5 * i, y);
     if (c < 0 || (long long)count[c] < min_cell) continue;
-    const int e = c / (kNB * kNTB);
-    atomicMax(&sm[e], ord64(y - unord64(ymax[c])));
-    atomicAdd(&sc[e], 1ull);
+    const int g = cm_group(level, c);
+    atomicMax(&sm[g], ord64(y - unord64(ymax[c])));
+    atomicAdd(&sc[g], 1ull);
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < kNIS; q += blockDim.x) {
+  for (int q = threadIdx.x; q < kCmGroups; q += blockDim.x) {
     if (sc[q]) {
       atomicMax(emax + q, sm[q]);
       atomicAdd(ecount + q, sc[q]);
@@ -536,17 +544,19 @@ __global__ void k_cellmax_resid(Cfg C, const float* rows, int64_t n, const unsig
 // min_cell fitting rows in entries with at least min_cal held-out rows; R
 // (the analytic bound) elsewhere
 __global__ void k_cellmax_table(const unsigned long long* ymax, const unsigned long long* count,
-                                const unsigned long long* emax, const unsigned long long* ecount, long long min_cell,
-                                long long min_cal, double margin, const double* bound, double* table) {
+                                const unsigned long long* level, const unsigned long long* emax,
+                                const unsigned long long* ecount, long long min_cell, long long min_cal, double margin,
+                                const double* bound, double* table) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= kNIS * kNB * kNTB) return;
   const int e = cell / (kNB * kNTB), b = (cell / kNTB) % kNB;
+  const int g = cm_group(level, cell);
   const double R = bound[(e + kIS0) * kNB + b];
-  if ((long long)count[cell] < min_cell || (long long)ecount[e] < min_cal || !(R > 0.0)) {
+  if ((long long)count[cell] < min_cell || (long long)ecount[g] < min_cal || !(R > 0.0)) {
     table[cell] = R;
     return;
   }
-  const double r = unord64(emax[e]);
+  const double r = unord64(emax[g]);
   const double d = (r > 0.0 ? r : 0.0) + margin;
   double v = unord64(ymax[cell]) + d;
   v = v < -20.0 ? -20.0 : (v > 0.0 ? 0.0 : v);

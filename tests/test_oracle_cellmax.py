@@ -134,14 +134,16 @@ def test_logged_trials_are_covered(nlo):
 def test_adaptive_blocks_closed_form(nlo):
     """Adaptive cell sizes: a well sampled cell keeps its own maximum, a thin
     neighbour takes the maximum of the smallest dyadic block with enough rows,
-    an empty corner of the entry the whole entry's, and an entry with too few
-    rows in all keeps the analytic bound."""
+    an empty corner of the entry the whole entry's, each coarser level with a
+    margin of its own (analytic without enough held-out rows), and an entry
+    with too few rows in all keeps the analytic bound."""
     o, B, E = nlo
     e = 33
     rich = [_row(e, 16, 3, y, B, E) for y in np.linspace(-3.0, -2.5, 20)]
     thin = [_row(e, 17, 3, -1.0, B, E)] * 5
     lone = [_row(50, 9, 5, -2.0, B, E)] * 10
-    cal = [_row(e, 16, 3, -2.75, B, E)] * 2000 + [_row(50, 9, 5, -2.0, B, E)] * 2000
+    cal = ([_row(e, 16, 3, -2.75, B, E)] * 2000 + [_row(e, 17, 3, -1.5, B, E)] * 2000 +
+           [_row(e, 47, 7, -2.0, B, E)] * 2000 + [_row(50, 9, 5, -2.0, B, E)] * 2000)
     tab, delta, n = _table(rich + thin + lone, cal, B, E)
     taba, deltaa, na = cellmax.cellmax_table(np.array(rich + thin + lone, dtype=np.float32),
                                              np.array(cal, dtype=np.float32), B, E, adaptive=True)
@@ -158,8 +160,15 @@ def test_adaptive_blocks_closed_form(nlo):
     # far corners of the entry: the whole entry (25 rows) at the last level
     assert na[e - 8, 47, 7] == 25 and na[e - 8, 0, 0] == 25
     assert R[47] * math.exp(top_thin + m) <= taba[e - 8, 47, 7] <= R[47] * math.exp(top_thin + m) * (1 + m)
-    # a 4 x 4 block holds the thin and rich cells at level 2
-    assert na[e - 8, 19, 0] == 25
+    # a 4 x 4 block holds the thin and rich cells at level 2; no held-out rows
+    # there, so the level has no margin and its cells stay analytic
+    assert na[e - 8, 19, 0] == 25 and taba[e - 8, 19, 0] == R[19]
+    # a held-out row above a coarse block raises that level's margin only
+    cal2 = cal + [_row(e, 17, 3, -0.5, B, E)]
+    taba2, _, _ = cellmax.cellmax_table(np.array(rich + thin + lone, dtype=np.float32),
+                                        np.array(cal2, dtype=np.float32), B, E, adaptive=True)
+    assert taba2[e - 8, 16, 3] == taba[e - 8, 16, 3] and taba2[e - 8, 47, 7] == taba[e - 8, 47, 7]
+    assert taba2[e - 8, 17, 3] >= R[17] * math.exp(-0.5)
     # entry 50 has 10 rows in all: analytic everywhere
     R3 = np.broadcast_to(B[8:72, :, None], tab.shape)
     assert np.array_equal(taba[50 - 8], R3[50 - 8]) and np.isinf(deltaa[50 - 8])
