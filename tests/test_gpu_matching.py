@@ -123,3 +123,51 @@ def test_rejected_configurations(cfgs):
                 dict(cfgs["nlo"], matching=1, mu_q2=0.0), dict(cfgs["nlo"], matching=3)):
         with pytest.raises(binding.GapsError):
             binding.Gaps(bad)
+
+
+def test_powheg_full_size_streamed_sampled(gpu, orc):
+    """POWHEG-like events at the benchmark's batch size and launch: two
+    batches of 10^6 events (ids 0 .. 2 * 10^6 - 1) streamed through one
+    graph-captured persistent launch with retained trials; 300 sampled events
+    against the oracle one by one."""
+    import torch
+    from paper_2511_19633_amd import binding
+    G, O = gpu["powheg"], orc["powheg"]
+    NPB, SEED = 1_000_000, 1
+    ins = [G.hard_events(k * NPB, NPB, SEED, max_slots=8) for k in range(2)]
+    outs = [binding.DeviceEvents(NPB, workloads.MAX_SLOTS) for _ in range(2)]
+    say("powheg full size: 2 x 10^6 events streamed")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = G.capture([(i, o, NPB) for i, o in zip(ins, outs)], SEED, stream, mode=binding.MODE_PLAIN, retain=True)
+    try:
+        graph.launch(stream)
+        stream.synchronize()
+    finally:
+        graph.close()
+    ids = np.sort(np.random.default_rng(11).choice(2 * NPB, size=300, replace=False))
+    g = records.Events(len(ids), workloads.MAX_SLOTS)
+    o_in = records.Events(len(ids), 8)
+    for s, i in enumerate(ids):
+        d = outs[int(i) // NPB]
+        j = int(i) % NPB
+        for name in g.fields():
+            t = getattr(d, name)
+            a = getattr(g, name)
+            if a.ndim == 1:
+                a[s] = t[j].item()
+            else:
+                a[:, s] = t[:, j].cpu().numpy()
+        one = O.hard_events(int(i), 1, SEED, max_slots=8)
+        for name in o_in.fields():
+            a = getattr(o_in, name)
+            if a.ndim == 1:
+                a[s] = getattr(one, name)[0]
+            else:
+                a[:, s] = getattr(one, name)[:, 0]
+    oout = O.shower(o_in, SEED, nthreads=8, max_slots=workloads.MAX_SLOTS, retain=True)
+    frac, worst, _ = compare_events(oout, g, SCALE)
+    say(f"  identical {frac:.5f}, worst rel diff {worst:.2e}")
+    assert np.array_equal(oout.id, g.id)
+    assert frac >= 0.999 and worst < 1e-9
+    assert np.all(g.flags == records.FLAG_MEC)
