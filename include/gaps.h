@@ -218,7 +218,9 @@ gaps_status gaps_destroy(gaps_ctx ctx);
 const char* gaps_strerror(gaps_status s);
 
 /* Hard events (appendix C; e+e- and LO by the workload definitions) for ids
- * first_id .. first_id+n-1 into out[0..n-1].  out->cap >= n, max_slots >= 5. */
+ * first_id .. first_id+n-1 into out[0..n-1].  out->cap >= n, max_slots >= 5.
+ * The matching of gaps_config decides the NLO events' weights, their t_start
+ * and the GAPS_F_MEC flag. */
 gaps_status gaps_hard_events(gaps_ctx ctx, int64_t first_id, int64_t n, uint64_t seed,
                              gaps_events* out, hipStream_t stream);
 
@@ -227,7 +229,9 @@ gaps_status gaps_hard_events(gaps_ctx ctx, int64_t first_id, int64_t n, uint64_t
  * (GAPS_F_OVERFLOW otherwise).  params may be NULL (plain mode, defaults).
  * Modes: PLAIN; LOG (plain, plus the trial log); LEARNED (needs
  * gaps_mlp_tabulate first, else GAPS_ESTATE).  LOG and LEARNED run on the wave
- * kernel (variant 0) only. */
+ * kernel (variant 0) only.  An event flagged GAPS_F_MEC has its first emission
+ * corrected to the real matrix element (see gaps_config.matching), in every
+ * mode, form and kernel; the flag is kept in the output. */
 gaps_status gaps_shower(gaps_ctx ctx, const gaps_events* in, int64_t n, const gaps_params* params,
                         uint64_t seed, gaps_events* out, hipStream_t stream);
 
