@@ -41,6 +41,9 @@ PP_DY = dict(COMMON, process=3, sqrt_s=13000.0)
 # emission the shower corrects to the real matrix element
 PP_NLO_MUQ = dict(PP_NLO, matching=1, mu_q2=91.1876 ** 2)
 PP_NLO_POWHEG = dict(PP_NLO, matching=2)
+# the second workload at NLO: pp -> Z/photon -> e+e- with the interference,
+# MC@NLO S/H events, the real emission by the Kleiss trick
+PP_DY_NLO = dict(COMMON, process=4, sqrt_s=13000.0)
 
 MAX_SLOTS = 128
 

@@ -481,6 +481,274 @@ static void gen_nlo(const or_state* s, int64_t id, uint64_t seed, or_events* o, 
     o->flags[e] = OR_F_HEVENT;
 }
 
+/* ---------------------------------------------------------------------------
+ * pp -> Z/photon -> e- e+ at NLO (the second workload at NLO, MC@NLO S and H
+ * events with the power shower), the real emission by the Kleiss trick.
+ *
+ * Born q(p_q) qbar -> e-(p3) e+(p4) at s = m^2, in units common to S and H
+ * events (coupling and colour constants dropped):
+ *   |M_0|^2 = (a(s) u^2 + b(s) t^2) / s^2,  t = (p_q - p3)^2,  u = (p_q - p4)^2,
+ *   a = |A_LL|^2 + |A_RR|^2,  b = |A_LR|^2 + |A_RL|^2,
+ *   A_ij = Q_q Q_e + g_i^q g_j^e s / (s - mZ^2 + i mZ GZ) / (sin^2 cos^2),
+ * chiral couplings g_L = T3 - Q sin^2, g_R = -Q sin^2 (helicity amplitudes;
+ * (1 + c^2) F1 + 2 c F2 of process 3 in other variables).
+ * Real q qbar -> e- e+ g by the Kleiss trick (every NLO matrix element from
+ * LO ones): with t' = (p_qbar - p4)^2, u' = (p_qbar - p3)^2 and s' = m^2,
+ *   |M_R|^2 = g^2 C_F (a(s') (u^2 + u'^2) + b(s') (t^2 + t'^2)) /
+ *             (2 s' (p_q.k)(p_qbar.k)),
+ * g^2 = 4 pi alpha_s; g qbar -> e- e+ qbar and g q -> e- e+ q by crossing
+ * (p_q = -p_j or p_qbar = -p_j, k = -p_g), times -3/8 (the colour and spin
+ * averages of a gluon, the fermion sign).  The subtraction is the sum of the
+ * initial-initial dipoles (appendix C.2) with the Born at the mapped momenta
+ * (appendix B.5's map backwards: the emitter x p_e, the leptons transformed
+ * by the Lorentz map of K = p_a + p_b - k onto x p_e + p_s).  The PDFs are at
+ * mu_F^2 = m^2; alpha_s is alpha_s(mZ) as for the Z. */
+static void dy_hel(const or_state* s, int f, double m2, double* al, double* be) {
+    const double sw2 = s->c.sw2, mz2 = s->c.mz * s->c.mz, mg = s->c.mz * s->c.gz;
+    const int up = abs(f) % 2 == 0;
+    const double Qq = up ? 2.0 / 3.0 : -1.0 / 3.0, T3 = up ? 0.5 : -0.5, Qe = -1.0, T3e = -0.5;
+    const double gq[2] = {T3 - Qq * sw2, -Qq * sw2}, ge[2] = {T3e - Qe * sw2, -Qe * sw2};
+    const double d = m2 - mz2, D = d * d + mg * mg, k = 1.0 / (sw2 * (1.0 - sw2));
+    const double rex = k * m2 * d / D, imx = -k * m2 * mg / D; /* s / (s - mZ^2 + i mZ GZ) */
+    double A2[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            double re = Qq * Qe + gq[i] * ge[j] * rex, im = gq[i] * ge[j] * imx;
+            A2[i][j] = re * re + im * im;
+        }
+    *al = A2[0][0] + A2[1][1];
+    *be = A2[0][1] + A2[1][0];
+}
+
+static double dot(const double* a, const double* b) {
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+static double born_dy(double al, double be, const double* pq, const double* p3, const double* p4) {
+    double t = -2.0 * dot(pq, p3), u = -2.0 * dot(pq, p4), s = 2.0 * dot(p3, p4);
+    return (al * u * u + be * t * t) / (s * s);
+}
+
+/* the Kleiss-trick real matrix element of q(pq) qbar(pqb) -> e-(p3) e+(p4) g(k)
+ * over g^2 C_F (momenta may be crossed, i.e. negative) */
+static double kleiss(double al, double be, const double* pq, const double* pqb, const double* k,
+                     const double* p3, const double* p4) {
+    double t = -2.0 * dot(pq, p3), u = -2.0 * dot(pq, p4);
+    double tp = -2.0 * dot(pqb, p4), up = -2.0 * dot(pqb, p3);
+    double sp = 2.0 * dot(p3, p4);
+    return (al * (u * u + up * up) + be * (t * t + tp * tp)) / (2.0 * sp * dot(pq, k) * dot(pqb, k));
+}
+
+/* the lepton momenta p of a real configuration mapped onto its Born by the
+ * initial-initial dipole of emitter pe (and spectator ps, emitted k): the
+ * Lorentz map of pe + ps - k onto x pe + ps */
+static void dy_project(const double* pe, const double* ps, const double* k, double x, double* p) {
+    double K[4], Kt[4], S[4];
+    for (int m = 0; m < 4; ++m) {
+        K[m] = pe[m] + ps[m] - k[m];
+        Kt[m] = x * pe[m] + ps[m];
+        S[m] = K[m] + Kt[m];
+    }
+    double c1 = 2.0 * dot(S, p) / dot(S, S), c2 = 2.0 * dot(K, p) / dot(K, K);
+    for (int m = 0; m < 4; ++m) p[m] = p[m] - c1 * S[m] + c2 * Kt[m];
+}
+
+/* the dipole sum of a real configuration, over 8 pi alpha_s: beams A (pa) and
+ * B (pb) with flavours fa, fb (21: gluon), emitted parton k, leptons p3, p4,
+ * the Born's angular weights al, be at the pair mass (the map keeps it) */
+static double dy_dipoles(int fa, int fb, const double* pa, const double* pb, const double* k, const double* p3,
+                         const double* p4, double x, double al, double be) {
+    double sum = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        const int fe = side == 0 ? fa : fb, fs = side == 0 ? fb : fa;
+        const double *pe = side == 0 ? pa : pb, *ps = side == 0 ? pb : pa;
+        if (fs == 21) continue; /* the spectator of a Born leg is a quark */
+        double q3[4], q4[4], pem[4];
+        memcpy(q3, p3, sizeof(q3));
+        memcpy(q4, p4, sizeof(q4));
+        dy_project(pe, ps, k, x, q3);
+        dy_project(pe, ps, k, x, q4);
+        for (int m = 0; m < 4; ++m) pem[m] = x * pe[m];
+        /* the Born's quark flavour at the emitter: the emitter's own, or (gluon)
+         * the one conjugate to the spectator */
+        const int qe = fe == 21 ? -fs : fe;
+        const double* pq = qe > 0 ? pem : ps;
+        double B = born_dy(al, be, pq, q3, q4);
+        double V = fe == 21 ? OR_TR * (1.0 - 2.0 * x * (1.0 - x)) : OR_CF * (1.0 + x * x) / (1.0 - x);
+        sum += V / (x * 2.0 * dot(pe, k)) * B;
+    }
+    return sum;
+}
+
+/* The momenta of a real configuration: beams A, B, the emitted parton J (the
+ * initial-initial map's variables x = m^2/sbar, v against beam A, azimuth
+ * phi, rapidity y of the pair of beams), the leptons from the pair's decay at
+ * polar cosine c and azimuth 2 pi uphi in its rest frame. */
+static void dy_real_kin(const or_state* s, double m2, double x, double y, double v, double ph, double c,
+                        double uphi, double* A, double* B, double* J, double* em, double* ep) {
+    double sbar = m2 / x;
+    double ea = exp(y) * sqrt(sbar / s->S), eb = exp(-y) * sqrt(sbar / s->S);
+    double Ea = 0.5 * ea * s->sqrtS, Eb = 0.5 * eb * s->sqrtS;
+    A[0] = Ea; A[1] = 0.0; A[2] = 0.0; A[3] = Ea;
+    B[0] = Eb; B[1] = 0.0; B[2] = 0.0; B[3] = -Eb;
+    double kt0 = sqrt(v * (1.0 - x - v) * sbar), pZ[4];
+    for (int k = 0; k < 4; ++k) J[k] = (1.0 - x - v) * A[k] + v * B[k];
+    J[1] -= kt0 * cos(ph);
+    J[2] -= kt0 * sin(ph);
+    for (int k = 0; k < 4; ++k) pZ[k] = A[k] + B[k] - J[k];
+    decay_zc(pZ, sqrt(m2), c, uphi, em, ep);
+}
+
+/* R and the dipole sum S of one channel of a real configuration: kind 0
+ * q qbar -> e- e+ g with the quark at A (fa > 0) or B; kind 1 the gluon at A,
+ * kind 2 at B, the (anti)quark fa or fb at the other beam */
+static void dy_real_rs(const or_state* s, int kind, int fa, int fb, double al, double be, const double* A,
+                       const double* B, const double* J, const double* em, const double* ep, double x, double* R,
+                       double* S) {
+    const double g2 = 4.0 * OR_PI * s->c.alphas_mz;
+    double mJ[4], mA[4], mB[4];
+    for (int k = 0; k < 4; ++k) { mJ[k] = -J[k]; mA[k] = -A[k]; mB[k] = -B[k]; }
+    if (kind == 0) {
+        *R = g2 * OR_CF * kleiss(al, be, fa > 0 ? A : B, fa > 0 ? B : A, J, em, ep);
+    } else if (kind == 1) {
+        /* the outgoing parton is the same as B's */
+        *R = -0.375 * g2 * OR_CF * (fb > 0 ? kleiss(al, be, B, mJ, mA, em, ep) : kleiss(al, be, mJ, B, mA, em, ep));
+    } else {
+        *R = -0.375 * g2 * OR_CF * (fa > 0 ? kleiss(al, be, A, mJ, mB, em, ep) : kleiss(al, be, mJ, A, mB, em, ep));
+    }
+    *S = 8.0 * OR_PI * s->c.alphas_mz * dy_dipoles(fa, fb, A, B, J, em, ep, x, al, be);
+}
+
+/* for the pins: R and S of channel (flavour f, kind, orientation o2) at one
+ * real configuration, and the Born weights al, be at m2 */
+void or_dy_real(const or_state* s, int f, int kind, int o2, double m2, double x, double y, double v, double ph,
+                double c, double uphi, double out[4]) {
+    double A[4], B[4], J[4], em[4], ep[4], al, be;
+    dy_real_kin(s, m2, x, y, v, ph, c, uphi, A, B, J, em, ep);
+    dy_hel(s, f, m2, &al, &be);
+    int fa, fb;
+    if (kind == 0) { fa = o2 == 0 ? f : -f; fb = -fa; }
+    else if (kind == 1) { fa = 21; fb = o2 == 0 ? f : -f; }
+    else { fa = o2 == 0 ? f : -f; fb = 21; }
+    dy_real_rs(s, kind, fa, fb, al, be, A, B, J, em, ep, x, &out[0], &out[1]);
+    out[2] = al;
+    out[3] = be;
+}
+
+/* NLO pp -> Z/photon -> e- e+ event: blocks (id, 0): S/H choice, channel,
+ * rapidity, lepton polar cosine; (id, 1): x_a and x_b of the collinear terms
+ * (S) or x and v (H), the emission azimuth (H), the lepton azimuth; (id, 2):
+ * the pair mass on the Breit-Wigner of the window. */
+static void gen_dy_nlo(const or_state* s, int64_t id, uint64_t seed, or_events* o, int64_t e) {
+    double u0[4], u1[4], u2[4];
+    or_rng_block(seed, STREAM_HARD, id, 0u, 0u, u0);
+    or_rng_block(seed, STREAM_HARD, id, 1u, 0u, u1);
+    or_rng_block(seed, STREAM_HARD, id, 2u, 0u, u2);
+    const double mz2 = s->c.mz * s->c.mz, mg = s->c.mz * s->c.gz;
+    const double r1 = atan((s->c.mll_min * s->c.mll_min - mz2) / mg);
+    const double r2 = atan((s->c.mll_max * s->c.mll_max - mz2) / mg);
+    const double m2 = mz2 + mg * tan(r1 + u2[0] * (r2 - r1)), m = sqrt(m2), q2 = m2;
+    const double jm = (r2 - r1) * ((m2 - mz2) * (m2 - mz2) + mg * mg) / mg; /* d m^2 / d u */
+    const double c = 2.0 * u0[3] - 1.0;
+    const int nf = s->c.nf;
+    if (u0[0] < s->c.p_s) {
+        double Y = log(s->sqrtS / m), y = -Y + 2.0 * Y * u0[2];
+        double e1 = m / s->sqrtS * exp(y), e2 = m / s->sqrtS * exp(-y);
+        double xa = e1 + (1.0 - e1) * u1[0], xb = e2 + (1.0 - e2) * u1[1];
+        double Ea = 0.5 * e1 * s->sqrtS, Eb = 0.5 * e2 * s->sqrtS;
+        double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+        double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4];
+        decay_zc(pZ, m, c, u1[3], em, ep);
+        double csub[10], W = 0.0;
+        for (int f = 1; f <= nf; ++f) {
+            double al, be;
+            dy_hel(s, f, m2, &al, &be);
+            for (int o2 = 0; o2 < 2; ++o2) {
+                int a = o2 == 0 ? f : -f, b = -a;
+                double M0 = born_dy(al, be, a > 0 ? A : B, em, ep);
+                double born = xfp(s, a, e1, q2) * xfp(s, b, e2, q2) * M0 / (16.0 * OR_PI * m2 * m2);
+                double corr = or_nlo_bvi_factor(s) + k_leg(s, a, e1, xa, q2) + k_leg(s, b, e2, xb, q2);
+                csub[2 * (f - 1) + o2] = born * corr;
+                W += fabs(born * corr);
+            }
+        }
+        double target = u0[1] * W, cum = 0.0;
+        int sel = 2 * nf - 1;
+        for (int q = 0; q < 2 * nf; ++q) {
+            cum += fabs(csub[q]);
+            if (target < cum) { sel = q; break; }
+        }
+        int f = sel / 2 + 1, a = (sel % 2 == 0) ? f : -f, b = -a;
+        put(o, e, 0, A, a, a > 0 ? 1 : 0, a > 0 ? 0 : 1, -1);
+        put(o, e, 1, B, b, b > 0 ? 1 : 0, b > 0 ? 0 : 1, -1);
+        put(o, e, 2, em, 11, 0, 0, 1);
+        put(o, e, 3, ep, -11, 0, 0, 1);
+        o->n[e] = 4;
+        o->w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y * jm / s->c.p_s;
+        o->t_start[e] = s->S;
+        o->flags[e] = 0u;
+        return;
+    }
+    double xmin = m2 / s->S;
+    double x = xmin + (1.0 - xmin) * u1[0];
+    double YH = 0.5 * log(s->S * x / m2), y = -YH + 2.0 * YH * u0[2];
+    double v = (1.0 - x) * u1[1], ph = 2.0 * OR_PI * u1[2];
+    double ea = exp(y) * sqrt(m2 / x / s->S), eb = exp(-y) * sqrt(m2 / x / s->S);
+    double A[4], B[4], J[4], em[4], ep[4];
+    dy_real_kin(s, m2, x, y, v, ph, c, u1[3], A, B, J, em, ep);
+    double csub[30], W = 0.0;
+    int pa[30], pb[30], kind[30];
+    int q = 0;
+    for (int f = 1; f <= nf; ++f) {
+        double al, be;
+        dy_hel(s, f, m2, &al, &be);
+        for (int kd = 0; kd < 3; ++kd)
+            for (int o2 = 0; o2 < 2; ++o2) {
+                int fa, fb;
+                if (kd == 0) { fa = o2 == 0 ? f : -f; fb = -fa; }
+                else if (kd == 1) { fa = 21; fb = o2 == 0 ? f : -f; }
+                else { fa = o2 == 0 ? f : -f; fb = 21; }
+                double R, S;
+                dy_real_rs(s, kd, fa, fb, al, be, A, B, J, em, ep, x, &R, &S);
+                pa[q] = fa; pb[q] = fb; kind[q] = kd; csub[q++] = R - S;
+            }
+    }
+    for (int k = 0; k < q; ++k) {
+        csub[k] *= xfp(s, pa[k], ea, q2) * xfp(s, pb[k], eb, q2) / (16.0 * OR_PI * m2) / (16.0 * OR_PI * OR_PI);
+        W += fabs(csub[k]);
+    }
+    double target = u0[1] * W, cum = 0.0;
+    int sel = q - 1;
+    for (int k = 0; k < q; ++k) {
+        cum += fabs(csub[k]);
+        if (target < cum) { sel = k; break; }
+    }
+    int a = pa[sel], b = pb[sel];
+    int ca, aa, cb, ab, jp, cj, aj;
+    if (kind[sel] == 0) {
+        ca = a > 0 ? 1 : 0; aa = a > 0 ? 0 : 2;
+        cb = b > 0 ? 1 : 0; ab = b > 0 ? 0 : 2;
+        jp = 21; cj = 1; aj = 2;
+    } else {
+        int qk = kind[sel] == 1 ? b : a;
+        int cq, aq;
+        if (qk > 0) { cq = 2; aq = 0; cj = 1; aj = 0; }
+        else { cq = 0; aq = 1; cj = 0; aj = 2; }
+        jp = qk;
+        if (kind[sel] == 1) { ca = 1; aa = 2; cb = cq; ab = aq; }
+        else { ca = cq; aa = aq; cb = 1; ab = 2; }
+    }
+    put(o, e, 0, A, a, ca, aa, -1);
+    put(o, e, 1, B, b, cb, ab, -1);
+    put(o, e, 2, J, jp, cj, aj, 1);
+    put(o, e, 3, em, 11, 0, 0, 1);
+    put(o, e, 4, ep, -11, 0, 0, 1);
+    o->n[e] = 5;
+    o->w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * YH * (1.0 - xmin) * (1.0 - x) * jm / (1.0 - s->c.p_s);
+    o->t_start[e] = s->S;
+    o->flags[e] = OR_F_HEVENT;
+}
+
 int or_hard_events(const or_state* s, int64_t first_id, int64_t n, uint64_t seed, or_events* out) {
     const int mt = s->c.matching;
     if (mt < 0 || mt > 2) return -1;
@@ -493,6 +761,7 @@ int or_hard_events(const or_state* s, int64_t first_id, int64_t n, uint64_t seed
         if (s->c.process == 0) gen_ee(s, id, seed, out, e);
         else if (s->c.process == 1) gen_lo(s, id, seed, out, e);
         else if (s->c.process == 3) gen_dy(s, id, seed, out, e);
+        else if (s->c.process == 4) gen_dy_nlo(s, id, seed, out, e);
         else gen_nlo(s, id, seed, out, e);
     }
     return 0;

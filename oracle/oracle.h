@@ -37,7 +37,9 @@ extern "C" {
 
 typedef struct {
     int process;        /* 0 e+e- -> qq, 1 pp LO Z->ee, 2 pp NLO S/H,
-                           3 pp LO Z/photon -> ee with interference */
+                           3 pp LO Z/photon -> ee with interference,
+                           4 pp NLO S/H Z/photon -> ee (the real emission by
+                             the Kleiss trick) */
     int nf;             /* active flavours (5) */
     double sqrt_s, t_cut, alphas_mz, mz, gz, sw2, gf, mc, mb;
     double mll_min, mll_max, p_s;
@@ -200,6 +202,12 @@ double or_nlo_sub(int kind, double x, double va);
  * on family B's factor that the corrected channels' overestimate carries */
 double or_mec_ratio(int family_b, double x, double v);
 double or_mec_bound(void);
+/* process 4: R and the dipole sum S of one real channel (kind 0 q qbar with
+ * the quark at A for o2 = 0, kind 1 gluon at A, kind 2 gluon at B; the other
+ * beam's (anti)quark by o2) at the pair mass m2, the map's x, y, v, phi, the
+ * lepton angles (c, uphi); out = {R, S, a, b} (the Born's angular weights) */
+void or_dy_real(const or_state* s, int f, int kind, int o2, double m2, double x, double y, double v, double ph,
+                double c, double uphi, double out[4]);
 
 #ifdef __cplusplus
 }

@@ -98,6 +98,7 @@ def _lib():
     lib.or_mec_ratio.argtypes = [C.c_int, C.c_double, C.c_double]
     lib.or_mec_bound.restype = C.c_double
     lib.or_mec_bound.argtypes = []
+    lib.or_dy_real.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int] + [C.c_double] * 7 + [C.c_void_p]
     return lib
 
 
@@ -267,6 +268,11 @@ class Oracle:
     @staticmethod
     def mec_bound():
         return lib().or_mec_bound()
+
+    def dy_real(self, f, kind, o2, m2, x, y, v, phi, c, uphi):
+        out = np.zeros(4)
+        lib().or_dy_real(self.h, f, kind, o2, m2, x, y, v, phi, c, uphi, out.ctypes.data_as(C.c_void_p))
+        return out
 
 
 def kin_map(typ, pe, ps, v1, v2, phi, rest=None):

@@ -23,6 +23,7 @@ def cfgs():
         "dy": workloads.config_dict(workloads.PP_DY),
         "muq": workloads.config_dict(workloads.PP_NLO_MUQ),
         "powheg": workloads.config_dict(workloads.PP_NLO_POWHEG),
+        "dynlo": workloads.config_dict(workloads.PP_DY_NLO),
     }
 
 
