@@ -137,12 +137,13 @@ const char* gaps_strerror(gaps_status s) {
 
 gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   if (!cfg || !out || !cfg->pdf_xf) return GAPS_EINVAL;
-  if (cfg->process < 0 || cfg->process > 3 || cfg->nf < 1 || cfg->nf > 5) return GAPS_EINVAL;
+  if (cfg->process < 0 || cfg->process > 4 || cfg->nf < 1 || cfg->nf > 5) return GAPS_EINVAL;
   if (cfg->ntab != 8 || cfg->nx < 4 || cfg->nx > 1024 || cfg->nq < 4 || cfg->nq > 64) return GAPS_EINVAL;
   if (!(cfg->sqrt_s > 0.0) || !(cfg->t_cut > 0.0) || !(cfg->alphas_mz > 0.0) || !(cfg->mz > 0.0))
     return GAPS_EINVAL;
   if (!(cfg->lnx1 > cfg->lnx0) || !(cfg->lnq1 > cfg->lnq0)) return GAPS_EINVAL;
-  if (cfg->process == 2 && !(cfg->p_s > 0.0 && cfg->p_s < 1.0)) return GAPS_EINVAL;
+  if ((cfg->process == 2 || cfg->process == 4) && !(cfg->p_s > 0.0 && cfg->p_s < 1.0)) return GAPS_EINVAL;
+  if (cfg->process == 4 && !(cfg->mll_min > 0.0 && cfg->mll_max > cfg->mll_min)) return GAPS_EINVAL;
   if (cfg->matching < 0 || cfg->matching > 2) return GAPS_EINVAL;
   if (cfg->matching != 0 && cfg->process != 1 && cfg->process != 2) return GAPS_EINVAL;
   if (cfg->matching == 1 && !(cfg->mu_q2 > 0.0)) return GAPS_EINVAL;

@@ -355,6 +355,221 @@ __device__ __forceinline__ double dipole_sum(int kind, double x, double va) {
   return (x * x + (1.0 - x) * (1.0 - x)) / (kind == 1 ? va : vb);
 }
 
+// ---------------------------------------------------------------------------
+// NLO pp -> Z/photon -> e- e+ (process 4): MC@NLO S and H events with the power
+// shower.  Born q(p_q) qbar -> e-(p3) e+(p4) at s = m^2, in units common to S
+// and H events: (a u^2 + b t^2) / s^2 with t = (p_q - p3)^2, u = (p_q - p4)^2,
+// a = |A_LL|^2 + |A_RR|^2, b = |A_LR|^2 + |A_RL|^2 from the helicity
+// amplitudes A_ij = Q_q Q_e + g_i^q g_j^e s / (s - mZ^2 + i mZ GZ) /
+// (sin^2 cos^2) (chiral couplings g_L = T3 - Q sin^2, g_R = -Q sin^2).  The
+// real emission by the Kleiss trick: g^2 C_F (a (u^2 + u'^2) + b (t^2 + t'^2))
+// / (2 s' (p_q.k)(p_qbar.k)), t' = (p_qbar - p4)^2, u' = (p_qbar - p3)^2,
+// s' = m^2; the gluon-initiated channels by crossing, times -3/8.  The
+// subtraction: the initial-initial dipoles with the Born at the mapped
+// momenta (appendix B.5's map run backwards).  PDFs at mu_F^2 = m^2.
+struct DyHel {
+  double al, be;
+};
+
+__device__ DyHel dy_hel(const Cfg& C, int f, double m2) {
+  const bool up = (f < 0 ? -f : f) % 2 == 0;
+  const double Qq = up ? 2.0 / 3.0 : -1.0 / 3.0, T3 = up ? 0.5 : -0.5, Qe = -1.0, T3e = -0.5;
+  const double mg = C.mz * C.gz, d = m2 - C.mz2, D = d * d + mg * mg, k = 1.0 / (C.sw2 * (1.0 - C.sw2));
+  const double rex = k * m2 * d / D, imx = -k * m2 * mg / D;
+  const double gq[2] = {T3 - Qq * C.sw2, -Qq * C.sw2}, ge[2] = {T3e - Qe * C.sw2, -Qe * C.sw2};
+  double A2[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const double re = Qq * Qe + gq[i] * ge[j] * rex, im = gq[i] * ge[j] * imx;
+      A2[i][j] = re * re + im * im;
+    }
+  return DyHel{A2[0][0] + A2[1][1], A2[0][1] + A2[1][0]};
+}
+
+__device__ __forceinline__ double dy_born(const DyHel& h, const double* pq, const double* p3, const double* p4) {
+  const double t = -2.0 * dot4(pq, p3), u = -2.0 * dot4(pq, p4), s = 2.0 * dot4(p3, p4);
+  return (h.al * u * u + h.be * t * t) / (s * s);
+}
+
+// the Kleiss-trick real matrix element over g^2 C_F (crossed momenta allowed)
+__device__ __forceinline__ double dy_kleiss(const DyHel& h, const double* pq, const double* pqb, const double* k,
+                                            const double* p3, const double* p4) {
+  const double t = -2.0 * dot4(pq, p3), u = -2.0 * dot4(pq, p4);
+  const double tp = -2.0 * dot4(pqb, p4), up = -2.0 * dot4(pqb, p3);
+  const double sp = 2.0 * dot4(p3, p4);
+  return (h.al * (u * u + up * up) + h.be * (t * t + tp * tp)) / (2.0 * sp * dot4(pq, k) * dot4(pqb, k));
+}
+
+// the dipole sum over 8 pi alpha_s: beams A, B of flavours fa, fb (21: gluon),
+// emitted k, leptons p3, p4; each dipole's Born at x p_e, p_s and the leptons
+// under the map of p_a + p_b - k onto x p_e + p_s
+__device__ double dy_dipoles(int fa, int fb, const double* A, const double* B, const double* k, const double* p3,
+                             const double* p4, double x, const DyHel& h) {
+  double sum = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    const int fe = side == 0 ? fa : fb, fs = side == 0 ? fb : fa;
+    if (fs == 21) continue;
+    const double* pe = side == 0 ? A : B;
+    const double* ps = side == 0 ? B : A;
+    double K[4], Kt[4], q3[4], q4[4], pem[4];
+    for (int m = 0; m < 4; ++m) {
+      K[m] = pe[m] + ps[m] - k[m];
+      Kt[m] = x * pe[m] + ps[m];
+      q3[m] = p3[m];
+      q4[m] = p4[m];
+      pem[m] = x * pe[m];
+    }
+    ii_lambda(K, Kt, q3);
+    ii_lambda(K, Kt, q4);
+    const int qe = fe == 21 ? -fs : fe;  // the Born's flavour at the emitter
+    const double Bn = dy_born(h, qe > 0 ? pem : ps, q3, q4);
+    const double V = fe == 21 ? kTR * (1.0 - 2.0 * x * (1.0 - x)) : kCF * (1.0 + x * x) / (1.0 - x);
+    sum += V / (x * 2.0 * dot4(pe, k)) * Bn;
+  }
+  return sum;
+}
+
+// colour tags of an NLO H event's beams and emitted parton (kind 0: q qbar ->
+// V g; kind 1: gluon at A; kind 2: gluon at B)
+__device__ void h_colours(int kind, int a, int b, int& ca, int& aa, int& cb, int& ab, int& jp, int& cj, int& aj) {
+  if (kind == 0) {
+    ca = a > 0 ? 1 : 0; aa = a > 0 ? 0 : 2;
+    cb = b > 0 ? 1 : 0; ab = b > 0 ? 0 : 2;
+    jp = 21; cj = 1; aj = 2;
+    return;
+  }
+  const int qk = kind == 1 ? b : a;
+  int cq, aq;
+  if (qk > 0) { cq = 2; aq = 0; cj = 1; aj = 0; }
+  else { cq = 0; aq = 1; cj = 0; aj = 2; }
+  jp = qk;
+  if (kind == 1) { ca = 1; aa = 2; cb = cq; ab = aq; }
+  else { ca = cq; aa = aq; cb = 1; ab = 2; }
+}
+
+// one process-4 event: blocks (id, 0) S/H, channel, rapidity, lepton polar
+// cosine; (id, 1) x_a, x_b (S) or x, v (H), emission azimuth, lepton azimuth;
+// (id, 2) the pair mass on the window's Breit-Wigner
+__device__ void hard_dy_nlo(const Cfg& C, int64_t id, uint64_t seed, const HardOut& H, gaps_events& o, int64_t e) {
+  const uint32_t SH = 2u;
+  double u0[4], u1[4], u2[4];
+  rng4(seed, SH, id, 0u, 0u, u0);
+  rng4(seed, SH, id, 1u, 0u, u1);
+  rng4(seed, SH, id, 2u, 0u, u2);
+  const double mg = C.mz * C.gz;
+  const double r1 = atan((C.mll_min * C.mll_min - C.mz2) / mg), r2 = atan((C.mll_max * C.mll_max - C.mz2) / mg);
+  const double m2 = C.mz2 + mg * tan(r1 + u2[0] * (r2 - r1)), m = sqrt(m2), q2 = m2;
+  const double jm = (r2 - r1) * ((m2 - C.mz2) * (m2 - C.mz2) + mg * mg) / mg;
+  const double c = 2.0 * u0[3] - 1.0;
+  const int nf = C.nf;
+  const double g2 = 4.0 * kPi * C.alphas_mz;
+  if (u0[0] < C.p_s) {
+    const double Y = log(C.sqrt_s / m), y = -Y + 2.0 * Y * u0[2];
+    const double e1 = m / C.sqrt_s * exp(y), e2 = m / C.sqrt_s * exp(-y);
+    const double xa = e1 + (1.0 - e1) * u1[0], xb = e2 + (1.0 - e2) * u1[1];
+    const double Ea = 0.5 * e1 * C.sqrt_s, Eb = 0.5 * e2 * C.sqrt_s;
+    double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb};
+    double pZ[4] = {A[0] + B[0], 0.0, 0.0, A[3] + B[3]}, em[4], ep[4];
+    decay_zc(pZ, m, c, u1[3], em, ep);
+    const double bvi = 1.0 + kCF * C.alphas_mz / (2.0 * kPi) * 2.0;
+    double csub[10], W = 0.0;
+    for (int f = 1; f <= nf; ++f) {
+      const DyHel h = dy_hel(C, f, m2);
+      for (int o2 = 0; o2 < 2; ++o2) {
+        const int a = o2 == 0 ? f : -f, b = -a;
+        const double M0 = dy_born(h, a > 0 ? A : B, em, ep);
+        const double born = pdf_xf(C, pdf_tab(a), e1, q2) * pdf_xf(C, pdf_tab(b), e2, q2) * M0 / (16.0 * kPi * m2 * m2);
+        double rq, rg;
+        const double corr = bvi + k_leg(C, a, e1, xa, q2, rq, rg) + k_leg(C, b, e2, xb, q2, rq, rg);
+        csub[2 * (f - 1) + o2] = born * corr;
+        W += fabs(born * corr);
+      }
+    }
+    const double target = u0[1] * W;
+    double cum = 0.0;
+    int sel = 2 * nf - 1;
+    for (int q = 0; q < 2 * nf; ++q) {
+      cum += fabs(csub[q]);
+      if (target < cum) { sel = q; break; }
+    }
+    const int f = sel / 2 + 1, a = (sel % 2 == 0) ? f : -f, b = -a;
+    H.put(0, A, a, a > 0 ? 1 : 0, a > 0 ? 0 : 1, -1);
+    H.put(1, B, b, b > 0 ? 1 : 0, b > 0 ? 0 : 1, -1);
+    H.put(2, em, 11, 0, 0, 1);
+    H.put(3, ep, -11, 0, 0, 1);
+    o.n[e] = 4;
+    o.w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * Y * jm / C.p_s;
+    o.t_start[e] = C.S;
+    o.flags[e] = 0u;
+    return;
+  }
+  const double xmin = m2 / C.S;
+  const double x = xmin + (1.0 - xmin) * u1[0], sbar = m2 / x;
+  const double YH = 0.5 * log(C.S * x / m2), y = -YH + 2.0 * YH * u0[2];
+  const double v = (1.0 - x) * u1[1], ph = 2.0 * kPi * u1[2];
+  const double ea = exp(y) * sqrt(sbar / C.S), eb = exp(-y) * sqrt(sbar / C.S);
+  const double Ea = 0.5 * ea * C.sqrt_s, Eb = 0.5 * eb * C.sqrt_s;
+  double A[4] = {Ea, 0.0, 0.0, Ea}, B[4] = {Eb, 0.0, 0.0, -Eb}, J[4], pZ[4], em[4], ep[4];
+  double mJ[4], mA[4], mB[4];
+  const double kt0 = sqrt(v * (1.0 - x - v) * sbar);
+  for (int q = 0; q < 4; ++q) J[q] = (1.0 - x - v) * A[q] + v * B[q];
+  J[1] -= kt0 * cos(ph);
+  J[2] -= kt0 * sin(ph);
+  for (int q = 0; q < 4; ++q) {
+    pZ[q] = A[q] + B[q] - J[q];
+    mJ[q] = -J[q]; mA[q] = -A[q]; mB[q] = -B[q];
+  }
+  decay_zc(pZ, m, c, u1[3], em, ep);
+  double csub[30], W = 0.0;
+  int pa[30], pb[30], kind[30];
+  int q = 0;
+  const double as8 = 8.0 * kPi * C.alphas_mz;
+  for (int f = 1; f <= nf; ++f) {
+    const DyHel h = dy_hel(C, f, m2);
+    for (int kd = 0; kd < 3; ++kd)
+      for (int o2 = 0; o2 < 2; ++o2) {
+        int fa, fb;
+        double R;
+        if (kd == 0) {
+          fa = o2 == 0 ? f : -f; fb = -fa;
+          R = g2 * kCF * dy_kleiss(h, fa > 0 ? A : B, fa > 0 ? B : A, J, em, ep);
+        } else if (kd == 1) {
+          fa = 21; fb = o2 == 0 ? f : -f;
+          R = -0.375 * g2 * kCF * (fb > 0 ? dy_kleiss(h, B, mJ, mA, em, ep) : dy_kleiss(h, mJ, B, mA, em, ep));
+        } else {
+          fa = o2 == 0 ? f : -f; fb = 21;
+          R = -0.375 * g2 * kCF * (fa > 0 ? dy_kleiss(h, A, mJ, mB, em, ep) : dy_kleiss(h, mJ, A, mB, em, ep));
+        }
+        const double S = as8 * dy_dipoles(fa, fb, A, B, J, em, ep, x, h);
+        pa[q] = fa; pb[q] = fb; kind[q] = kd; csub[q++] = R - S;
+      }
+  }
+  for (int k = 0; k < q; ++k) {
+    csub[k] *= pdf_xf(C, pdf_tab(pa[k]), ea, q2) * pdf_xf(C, pdf_tab(pb[k]), eb, q2) / (16.0 * kPi * m2) /
+               (16.0 * kPi * kPi);
+    W += fabs(csub[k]);
+  }
+  const double target = u0[1] * W;
+  double cum = 0.0;
+  int sel = q - 1;
+  for (int k = 0; k < q; ++k) {
+    cum += fabs(csub[k]);
+    if (target < cum) { sel = k; break; }
+  }
+  const int a = pa[sel], b = pb[sel];
+  int ca, aa, cb, ab, jp, cj, aj;
+  h_colours(kind[sel], a, b, ca, aa, cb, ab, jp, cj, aj);
+  H.put(0, A, a, ca, aa, -1);
+  H.put(1, B, b, cb, ab, -1);
+  H.put(2, J, jp, cj, aj, 1);
+  H.put(3, em, 11, 0, 0, 1);
+  H.put(4, ep, -11, 0, 0, 1);
+  o.n[e] = 5;
+  o.w[e] = (csub[sel] < 0.0 ? -W : W) * 2.0 * YH * (1.0 - xmin) * (1.0 - x) * jm / (1.0 - C.p_s);
+  o.t_start[e] = C.S;
+  o.flags[e] = fHEvent;
+}
+
 __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
@@ -469,6 +684,10 @@ __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_e
       break;
     }
     o.n[e] = 0; o.w[e] = 0.0; o.t_start[e] = C.S; o.flags[e] = fHardFail;
+    return;
+  }
+  if (C.process == 4) {
+    hard_dy_nlo(C, id, seed, H, o, e);
     return;
   }
   // NLO S and H events

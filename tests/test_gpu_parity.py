@@ -17,7 +17,7 @@ from gapsinputs import records, workloads
 
 pytestmark = pytest.mark.gpu
 
-SCALE = {"ee": 91.2, "lo": 13000.0, "nlo": 13000.0, "dy": 13000.0}
+SCALE = {"ee": 91.2, "lo": 13000.0, "nlo": 13000.0, "dy": 13000.0, "dynlo": 13000.0}
 
 
 def say(*a):
@@ -99,7 +99,8 @@ def test_overestimate_table(gpu, oracles, key):
     assert len(diff) == 0, diff[:10]
 
 
-@pytest.mark.parametrize("key,n", [("ee", 3000), ("lo", 3000), ("nlo", 3000), ("dy", 3000)])
+@pytest.mark.parametrize("key,n", [("ee", 3000), ("lo", 3000), ("nlo", 3000), ("dy", 3000),
+                                   ("dynlo", 3000)])
 def test_hard_events(gpu, oracles, key, n):
     say(f"hard events {key} n={n}")
     g = gpu[key].hard_events(0, n, 1).to_host()
@@ -113,7 +114,8 @@ def test_hard_events(gpu, oracles, key, n):
     assert np.allclose(g.t_start, o.t_start, rtol=0, atol=0)
 
 
-@pytest.mark.parametrize("key,n", [("ee", 10000), ("lo", 3000), ("nlo", 3000), ("dy", 3000)])
+@pytest.mark.parametrize("key,n", [("ee", 10000), ("lo", 3000), ("nlo", 3000), ("dy", 3000),
+                                   ("dynlo", 3000)])
 def test_shower_parity(gpu, oracles, key, n):
     from paper_2511_19633_amd import binding
     say(f"shower parity {key} n={n}")
@@ -269,7 +271,7 @@ def test_graph_replays_match_eager(gpu):
         g.close()
 
 
-@pytest.mark.parametrize("key,n", [("ee", 10000), ("nlo", 3000), ("dy", 3000)])
+@pytest.mark.parametrize("key,n", [("ee", 10000), ("nlo", 3000), ("dy", 3000), ("dynlo", 3000)])
 def test_observables_parity(gpu, oracles, key, n):
     G, O = gpu[key], oracles[key]
     gout = G.shower(G.hard_events(0, n, 1), 7)
