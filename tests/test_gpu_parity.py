@@ -110,7 +110,15 @@ def test_hard_events(gpu, oracles, key, n):
         assert np.array_equal(getattr(g, name), getattr(o, name))
     for name in ("E", "px", "py", "pz"):
         assert np.max(np.abs(getattr(g, name) - getattr(o, name))) < 1e-11 * SCALE[key]
-    assert np.allclose(g.w, o.w, rtol=1e-11, atol=0)
+    rel = np.abs(g.w - o.w) / np.abs(o.w)
+    h = (o.flags & records.FLAG_HEVENT) != 0
+    say(f"  weights: worst rel diff S {rel[~h].max():.2e}, H {rel[h].max() if h.any() else 0.0:.2e}")
+    assert np.all(rel[~h] <= 1e-11)
+    # an H weight of the Z/photon workload is R - S of a 2 -> 3 configuration
+    # with the leptons, which cancel to 1e-4 or less of |R| near the collinear
+    # limits: the last-bit differences of R and S (the device's transcendental
+    # functions) grow by that factor
+    assert np.all(rel[h] <= (1e-9 if key == "dynlo" else 1e-11))
     assert np.allclose(g.t_start, o.t_start, rtol=0, atol=0)
 
 
