@@ -238,8 +238,9 @@ def main():
                          "kernels on the first two batches, reported under \"competition_forms\"")
     ap.add_argument("--no-matching", action="store_true",
                     help="skip timing the plain shower of the matching variants (MC@NLO started at mZ^2, "
-                         "POWHEG-like events with the first-emission correction) on two batches of their own "
-                         "events, reported under \"matching\"")
+                         "POWHEG-like events with the first-emission correction) and of NLO pp -> Z/photon -> "
+                         "e+e- events on two batches of their own events, reported under \"matching\" and "
+                         "\"dy_nlo\"")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
@@ -412,7 +413,8 @@ def main():
         sub_n = [b[2] for b in batches[:2]]
         nb = len(sub_n)
         mt = {"events": int(sum(sub_n)), "kernel": kernel}
-        for nm, wl in (("mcatnlo_start_mz2", workloads.PP_NLO_MUQ), ("powheg", workloads.PP_NLO_POWHEG)):
+        for nm, wl in (("mcatnlo_start_mz2", workloads.PP_NLO_MUQ), ("powheg", workloads.PP_NLO_POWHEG),
+                       ("dy_nlo", workloads.PP_DY_NLO)):
             Gm = binding.Gaps(workloads.config_dict(wl))
             ins_m = [Gm.hard_events(int(a), int(m), seed, max_slots=8) for a, m in zip(starts[:nb], sub_n)]
             sub = [(ins_m[k], outs[k], sub_n[k]) for k in range(nb)]
@@ -428,6 +430,9 @@ def main():
             Gm.close()
         w0 = torch.cat([b[0].w for b in batches[:nb]])
         mt["mcatnlo_power_shower_sigma_per_event"] = float(w0.mean().item())
+        # the second workload at NLO (pp -> Z/photon -> e+e-, power shower) is
+        # reported with them, beside the matchings of the first
+        out_extra["dy_nlo"] = mt.pop("dy_nlo")
         out_extra["matching"] = mt
 
     out = {
