@@ -123,7 +123,7 @@ def learned_pipeline(G, binding, args, seed):
     t0 = time.perf_counter()
     x, y, ent = G.mlp_features(rows)
     ntr = int(0.8 * x.shape[0])
-    loss = G.mlp_train(x[:ntr], y[:ntr], steps=args.train_steps, batch=args.train_batch, lr=3e-3, tau=0.999,
+    loss = G.mlp_train(x[:ntr], y[:ntr], steps=args.train_steps, batch=args.train_batch, lr=3e-3, tau=args.train_tau,
                        seed=seed)
     torch.cuda.synchronize()
     rep["train_s"], rep["train_steps"], rep["train_batch"] = time.perf_counter() - t0, args.train_steps, args.train_batch
@@ -160,6 +160,8 @@ def chi_vs_plain(h_plain, h_other):
 def timed_stream(G, binding, batches, seed, args, kw, mode):
     """Warm-up passes and one timed pass of the graph-captured stream."""
     import torch
+    # the input batches may still be in the making on another stream
+    torch.cuda.synchronize()
     stats = torch.zeros(binding.NSTATS, dtype=torch.uint64, device="cuda")
     K = len(batches)
     if args.launch == "stream":
@@ -224,6 +226,7 @@ def main():
     ap.add_argument("--log-rows", type=int, default=50_000_000)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=65536)
+    ap.add_argument("--train-tau", type=float, default=0.999, help="quantile of the learned bound's pinball loss")
     ap.add_argument("--trials", choices=["retain", "regenerate"], default="retain",
                     help="retain: a losing channel keeps its trial scale (the same Markov chain, fewer draws); "
                          "regenerate: every channel draws again each cycle")
