@@ -127,6 +127,7 @@ def learned_pipeline(G, binding, args, seed):
                        seed=seed)
     torch.cuda.synchronize()
     rep["train_s"], rep["train_steps"], rep["train_batch"] = time.perf_counter() - t0, args.train_steps, args.train_batch
+    rep["train_tau"] = args.train_tau
     lv = loss.cpu().numpy()
     rep["loss_first"], rep["loss_last"] = float(lv[:10].mean()), float(lv[-10:].mean())
     t0 = time.perf_counter()

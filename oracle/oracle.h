@@ -20,6 +20,9 @@
  *   NLO pieces ................ pinned (printed B+V+I factor, B = int g,
  *                               Li2 vs library, R-S identities)
  *   observables ............... pinned (thrust/jets on hand-built events)
+ *   NLO Z/photon (process 4) .. pinned (Kleiss-trick R and the dipoles at mapped
+ *                               leptons, lepton-averaged, = textbook Z ones;
+ *                               collinear limits; S/H balance at the pole)
  *   matching variants ......... pinned (S + printed R - S = textbook R; the
  *                               correction factor = textbook R / dipoles; NLO
  *                               totals equal across the variants; corrected and
