@@ -65,7 +65,13 @@ typedef struct {
                            3: pp -> Z/photon -> e+e- LO with the interference
                               (m_ee in the window below; cos theta of the
                               electron about the quark from (1 + cos^2) F1 +
-                              2 cos F2 by accept-reject) */
+                              2 cos F2 by accept-reject)
+                           4: pp -> Z/photon -> e+e- at NLO, MC@NLO S and H
+                              events (weighted, p_s; m_ee from the Z
+                              Breit-Wigner on the window, the electron uniform
+                              in the pair's rest frame; the real emission by the
+                              Kleiss trick, the subtraction by the dipoles at
+                              mapped lepton momenta; mu_F = m_ee) */
     int nf;             /* active quark flavours (5) */
     double sqrt_s;      /* collider energy, GeV */
     double t_cut;       /* shower cutoff on t = pT^2, GeV^2 */
@@ -74,7 +80,7 @@ typedef struct {
     double sw2, gf;     /* sin^2(theta_W), Fermi constant */
     double mc, mb;      /* charm and bottom masses (heavy-quark measure) */
     double mll_min, mll_max; /* LO dilepton mass window, GeV */
-    double p_s;         /* NLO: probability of generating an S event */
+    double p_s;         /* NLO (processes 2, 4): probability of an S event */
     const float* pdf_xf; /* HOST [ntab][nq][nx] node values of x*f(x, Q^2) */
     int nx, nq, ntab;   /* grid sizes; ntab must be 8 (g d u s c b dbar ubar) */
     double lnx0, lnx1, lnq0, lnq1; /* node ranges in ln x and ln Q^2 */
