@@ -70,9 +70,9 @@ def test_collinear_limits(oracles, kind):
 
 def test_events_and_the_balance_of_s_and_h(cfgs):
     """In a narrow window at the pole the H events' share of the NLO cross
-    section is the on-shell Z workload's (the lepton-averaged R - S and Born
-    are the Z's), and the events are well formed: leptons in the window,
-    H events with a parton, the S fraction p_S."""
+    section and their emission spectrum are the on-shell Z workload's (the
+    lepton-averaged R - S and Born are the Z's), and the events are well
+    formed: leptons in the window, H events with a parton, the S fraction p_S."""
     n = 300_000
     win = dict(mll_min=91.0, mll_max=91.4)
     dy = Oracle(dict(cfgs["dynlo"], **win)).hard_events(0, n, 1, max_slots=8)
@@ -95,3 +95,16 @@ def test_events_and_the_balance_of_s_and_h(cfgs):
     ez = z.w[hz].std() * math.sqrt(hz.sum()) / z.w.sum()
     assert abs(fdy - fz) < 4.0 * math.hypot(edy, ez) + 2e-3, (fdy, fz, edy, ez)
     assert fz > 0.02
+    # the H events' emission spectrum (the parton's pT, as a fraction of the
+    # NLO cross section) is the Z's: chi^2 over 12 bins
+    edges = np.array([0.0, 1.0, 2.0, 4.0, 7.0, 10.0, 15.0, 20.0, 30.0, 45.0, 70.0, 120.0, 300.0])
+
+    def spectrum(ev, hh):
+        pt = np.hypot(ev.px[2], ev.py[2])[hh]
+        w = ev.w[hh] / ev.w.sum()
+        return np.histogram(pt, edges, weights=w)[0], np.histogram(pt, edges, weights=w * w)[0]
+
+    (a, va), (b, vb) = spectrum(dy, h), spectrum(z, hz)
+    chi2 = float(np.sum((a - b) ** 2 / (va + vb)))
+    from scipy import stats
+    assert stats.chi2.sf(chi2, len(edges) - 1) > 1e-3, (chi2, a, b)
