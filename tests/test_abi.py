@@ -42,3 +42,37 @@ def test_stream_and_graph_argument_errors():
     assert lib.gaps_graph_launch(None, None) == -1
     assert lib.gaps_graph_destroy(None) == -1
     assert C.sizeof(binding.GapsBatch) == 2 * C.sizeof(binding.GapsEvents) + 8
+
+
+def test_config_and_cellmax_argument_errors():
+    """Matching and process combinations gaps_init rejects before any device
+    work, and the cell-maximum entry points' argument checks."""
+    import numpy as np
+    from gapsinputs import workloads
+    from paper_2511_19633_amd import binding
+    lib = binding.lib()
+    base = workloads.config_dict(workloads.PP_NLO)
+    pdf = np.ascontiguousarray(base["pdf"], dtype=np.float32)
+
+    def init(**over):
+        cfg = dict(base, **over)
+        c = binding.GapsConfig()
+        for name, _ in binding.GapsConfig._fields_:
+            if name != "pdf_xf" and name in cfg:
+                setattr(c, name, cfg[name])
+        c.nf = 5
+        c.pdf_xf = pdf.ctypes.data_as(C.POINTER(C.c_float))
+        h = C.c_void_p()
+        return lib.gaps_init(C.byref(c), C.byref(h))
+
+    assert init(matching=3) == -1
+    assert init(matching=-1) == -1
+    assert init(matching=1, mu_q2=0.0) == -1
+    assert init(process=3, matching=2) == -1
+    assert init(process=0, matching=1, mu_q2=100.0) == -1
+    assert init(process=4, p_s=0.0) == -1
+    assert init(process=4, mll_min=120.0, mll_max=100.0) == -1
+    assert init(process=5) == -1
+    for fn in (lib.gaps_cellmax_table, lib.gaps_cellmax_table_adaptive):
+        fn.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
+        assert fn(None, None, 10, 0, None) == -1
