@@ -101,8 +101,11 @@ typedef struct {
                               dipole) flagged GAPS_F_MEC; for LO (process 1) the
                               LO events are flagged.  gaps_shower multiplies a
                               flagged event's first emission by R over its
-                              initial-initial dipole density (family B's
-                              overestimate carries the factor 2.625 meanwhile).
+                              initial-initial dipole density (meanwhile family
+                              B's overestimate comes from a table of its own,
+                              the kernel bound times the factor's largest value,
+                              scanned like the others; a learned constant
+                              carries 2.625, the factor's overall maximum).
                            GAPS_EINVAL for other values and processes. */
     double mu_q2;       /* start scale of matching 1, GeV^2 (> 0) */
 } gaps_config;

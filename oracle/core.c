@@ -112,6 +112,20 @@ static double gbound(int shape, int fam, double x) {
     return OR_CF * (x + 2.0 * omx / x);
 }
 
+/* The first-emission correction's largest value over the initial-initial
+ * phase space at momentum fraction x (family B, at v = 1 - x), and its
+ * largest value over [lo, hi] (one maximum, at x = (3 - sqrt 5) / 2). */
+static double mec_bmax(double x) {
+    double omx = 1.0 - x;
+    return 1.0 + (1.0 - x * x) / (x * x + omx * omx);
+}
+static double mec_bmax_range(double lo, double hi) {
+    const double xs = 0.5 * (3.0 - sqrt(5.0));
+    if (lo <= xs && xs <= hi) return mec_bmax(xs);
+    double a = mec_bmax(lo), b = mec_bmax(hi);
+    return a > b ? a : b;
+}
+
 /* x*f interpolated along ln x at row j (node column values exact). */
 static double xf_row(const or_state* s, int tab, int j, double x) {
     if (!(x > 0.0) || x >= 1.0) return 0.0;
@@ -127,8 +141,19 @@ static double xf_row(const or_state* s, int tab, int j, double x) {
 
 typedef struct { int kind, fam, T, num, den; double m2; } entry_t;
 
+/* entries OR_NENT + T: family B at the initial-initial end (shape 3) under
+ * the first-emission correction (kind 4) */
+#define OR_NALL (OR_NENT + 8)
 static int entry_info(const or_state* s, int e, entry_t* out) {
     out->m2 = 0.0;
+    if (e >= OR_NENT) {
+        int T = e - OR_NENT;
+        if (T == 0) return 0;
+        out->kind = 4; out->fam = FAM_B; out->T = T; out->num = 0; out->den = T;
+        if (T == 4) out->m2 = s->c.mc * s->c.mc;
+        if (T == 5) out->m2 = s->c.mb * s->c.mb;
+        return 1;
+    }
     if (e < 8) { out->kind = 0; out->fam = -1; out->T = e; out->num = e; out->den = e; return 1; }
     int kind = e < 40 ? 1 : 3;
     int r = e - (kind == 1 ? 8 : 40);
@@ -167,17 +192,18 @@ void or_compute_bounds(or_state* s) {
     for (int i = 0; i < nx; ++i) xn[i] = exp(s->c.lnx0 + i * s->dlnx);
     for (int j = 0; j < nq; ++j) qn[j] = exp(s->c.lnq0 + j * s->dlnq);
     /* per-row values v[e][j] for the current eta point */
-    double* v = (double*)malloc(sizeof(double) * OR_NENT * nq);
+    double* v = (double*)malloc(sizeof(double) * OR_NALL * nq);
     double* numc = (double*)malloc(sizeof(double) * 8 * nx);
-    double* gc = (double*)malloc(sizeof(double) * 8 * nx); /* combos: 4 S1 + 4 S3 */
-    entry_t info[OR_NENT];
-    int valid[OR_NENT];
-    for (int e = 0; e < OR_NENT; ++e) valid[e] = entry_info(s, e, &info[e]);
+    double* gc = (double*)malloc(sizeof(double) * 9 * nx); /* combos: 4 S1 + 4 S3 + corrected B */
+    entry_t info[OR_NALL];
+    int valid[OR_NALL];
+    for (int e = 0; e < OR_NALL; ++e) valid[e] = entry_info(s, e, &info[e]);
     memset(s->bound, 0, sizeof(s->bound));
+    memset(s->bound_mec, 0, sizeof(s->bound_mec));
 
     for (int bin = 0; bin < OR_NB; ++bin) {
-        double best[OR_NENT];
-        for (int e = 0; e < OR_NENT; ++e) best[e] = 0.0;
+        double best[OR_NALL];
+        for (int e = 0; e < OR_NALL; ++e) best[e] = 0.0;
         for (int p = 0; p < 3; ++p) {
             double eta = exp(OR_LNETA0 + (bin + 0.5 * p) * dle);
             if (!(eta < 1.0)) continue;
@@ -195,6 +221,7 @@ void or_compute_bounds(or_state* s) {
                     double b3 = (f == FAM_B || f == FAM_D) ? gbound(3, f, eta / xhi) : 0.0;
                     gc[(4 + f) * nx + i] = a3 > b3 ? a3 : b3;
                 }
+                gc[8 * nx + i] = gc[(4 + FAM_B) * nx + i] * mec_bmax_range(eta / xhi, eta / xlo);
             }
             for (int j = 0; j < nq; ++j) {
                 double den[8];
@@ -208,7 +235,7 @@ void or_compute_bounds(or_state* s) {
                         numc[T * nx + i] = (flo > fhi ? flo : fhi) / xlo;
                     }
                 }
-                for (int e = 0; e < OR_NENT; ++e) {
+                for (int e = 0; e < OR_NALL; ++e) {
                     v[e * nq + j] = -1.0; /* marks a zero denominator */
                     if (!valid[e]) continue;
                     double d = den[info[e].den];
@@ -216,6 +243,7 @@ void or_compute_bounds(or_state* s) {
                     const double* g = NULL;
                     if (info[e].kind == 1) g = gc + info[e].fam * nx;
                     if (info[e].kind == 3) g = gc + (4 + info[e].fam) * nx;
+                    if (info[e].kind == 4) g = gc + 8 * nx;
                     const double* nc = numc + info[e].num * nx;
                     double m = 0.0;
                     for (int i = i0; i <= nx - 2; ++i) {
@@ -226,7 +254,7 @@ void or_compute_bounds(or_state* s) {
                 }
             }
             /* scale intervals [row j, row j+1] that reach above the channel cutoff */
-            for (int e = 0; e < OR_NENT; ++e) {
+            for (int e = 0; e < OR_NALL; ++e) {
                 if (!valid[e]) continue;
                 double m2 = info[e].m2;
                 double tmin = m2 > 0.0 ? m2 + s->c.t_cut : s->tc_is;
@@ -242,6 +270,8 @@ void or_compute_bounds(or_state* s) {
         }
         for (int e = 0; e < OR_NENT; ++e)
             s->bound[e][bin] = valid[e] ? or_quarter_octave_up(1.5 * best[e]) : 0.0;
+        for (int T = 0; T < 8; ++T)
+            s->bound_mec[T][bin] = valid[OR_NENT + T] ? or_quarter_octave_up(1.5 * best[OR_NENT + T]) : 0.0;
     }
     free(xn); free(qn); free(v); free(numc); free(gc);
 }

@@ -39,6 +39,10 @@ struct or_state {
     double tc_is;              /* cutoff of channels that need a PDF ratio */
     double b0;
     double bound[OR_NENT][OR_NB];
+    /* family B at the initial-initial end while the first-emission correction
+     * applies (kernel bound times the correction's largest value), by the
+     * quark's PDF table */
+    double bound_mec[8][OR_NB];
     double cell_edge[OR_NTB + 1]; /* ln t edges of the learned-bound cells */
     double lo_wmax;
 };

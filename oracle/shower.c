@@ -99,8 +99,10 @@ static void add_term(chan_t* ch, int kern, int shape, int flav, double coefR, in
  * (family A): R / (D_a + D_b) = 1 - 2 v (1 - x - v) / (1 + x^2), in [1/2, 1].
  * A quark from a gluon (family B, g qbar -> Z qbar) has only its own dipole:
  * R / D = 1 + v (2 x + v) / (x^2 + (1 - x)^2), at most the square of the golden
- * ratio (2.618...), so while the correction applies the family-B overestimate
- * carries the factor OR_MEC_KB. */
+ * ratio (2.618...).  While the correction applies, family B's overestimate
+ * comes from a table of its own (the kernel bound times the correction's
+ * largest value at each momentum fraction, scanned like the others); a learned
+ * constant carries the factor OR_MEC_KB. */
 #define OR_MEC_KB 2.625
 double or_mec_ratio(int family_b, double x, double v) {
     double omx = 1.0 - x;
@@ -191,9 +193,11 @@ static void setup_channel(const or_state* S, const ev_t* e, int i, int side, int
             int ent = ch->type == T_II ? OR_ENT_S3(FAM_B, T) : OR_ENT_S1(FAM_B, T);
             add_term(ch, K_B, sh2, 0, S->bound[ent][bin], ent);
             if (e->mec && ch->type == T_II) {
+                /* plain: the corrected family-B table; learned: the learned
+                 * constant times the correction's bound */
                 term_t* tb = &ch->term[ch->nterm - 1];
                 tb->mul = OR_MEC_KB;
-                tb->coefR *= OR_MEC_KB;
+                tb->coefR = S->bound_mec[T][bin];
                 ch->mec = 1;
             }
         }

@@ -61,6 +61,7 @@ struct Cfg {
   double cell_edge[kNTB + 1];  // ln t edges of the learned-bound cells
   const float* pdf;      // [8][nq][nx]
   const double* bound;   // [72][48]
+  const double* bound_mec;  // [8][48] family B under the first-emission correction, by PDF table
   const double* learn;   // [64][48][8] learned bound (LEARNED mode), or null
 };
 
@@ -323,7 +324,7 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
     }
   }
   t.coefR = C.bound[t.ent * kNB + ch.ebin];
-  if (ch.mec && t.kern == kB) t.coefR *= kMecB;
+  if (ch.mec && t.kern == kB) t.coefR = C.bound_mec[pdf_tab(ch.pidi) * kNB + ch.ebin];
   return t;
 }
 
@@ -333,9 +334,11 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
 // 1..nf, -1..-nf for a gluon).  Every term's constant is loaded first
 // (independent loads), then the products are summed in term order: the total
 // constant c, or the term a uniform draw of c picks.
+// mec: the channel's first emission is corrected; family B's constant is then
+// rmec (the corrected table's, or a learned constant times kMecB)
 template <class Tab>
 __device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, Tab R_of, double (&R)[kMaxTerms],
-                                             bool mec) {
+                                             bool mec, double rmec) {
   const bool ii = type == kII;
   if (pidi == 21) {
     const int nt = 1 + 2 * C.nf;
@@ -354,7 +357,7 @@ __device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, T
   const int T = pdf_tab(pidi);
   R[0] = R_of(ent_s1(famA, T));
   R[1] = R_of(ii ? ent_s3(famB, T) : ent_s1(famB, T));
-  if (mec) R[1] *= kMecB;
+  if (mec) R[1] = rmec;
 #pragma unroll
   for (int m = 2; m < kMaxTerms; ++m) R[m] = 0.0;
   return 2;
@@ -362,10 +365,10 @@ __device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, T
 
 template <class Tab>
 __device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, double I1, double I2, Tab R_of,
-                                             bool mec) {
+                                             bool mec, double rmec) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
+  const int nt = is_terms_load(C, type, pidi, R_of, R, mec, rmec);
   double c = 0.0;
   c += af * R[0] * I1;
 #pragma unroll
@@ -378,10 +381,10 @@ __device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, d
 // term order) first exceeds target, and its constant; -1 if none does.
 template <class Tab>
 __device__ __forceinline__ int is_terms_pick(const Cfg& C, int type, int pidi, double I1, double I2, double target,
-                                             Tab R_of, bool mec, double& Rsel) {
+                                             Tab R_of, bool mec, double rmec, double& Rsel) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
+  const int nt = is_terms_load(C, type, pidi, R_of, R, mec, rmec);
   int sel = -1;
   Rsel = 0.0;
   double cum = 0.0;
@@ -465,7 +468,9 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
   double c = 0.0;
   if (isE) {
     const int eb = ch.ebin;
-    c = is_terms_c(C, ch.type, ch.pidi, ch.I1, ch.I2, [&](int ent) { return C.bound[ent * kNB + eb]; }, ch.mec);
+    const double rmec = ch.mec ? C.bound_mec[pdf_tab(ch.pidi) * kNB + eb] : 0.0;
+    c = is_terms_c(C, ch.type, ch.pidi, ch.I1, ch.I2, [&](int ent) { return C.bound[ent * kNB + eb]; }, ch.mec,
+                   rmec);
   } else {
     double af = C.as_over / (2.0 * kPi) * C.over_scale;
     for (int m = 0; m < ch.nterm; ++m) {
@@ -498,9 +503,14 @@ __device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool 
   if (ch.type == kIF || ch.type == kII) {
     const int eb = ch.ebin;
     double Rsel;
+    double rmec = 0.0;
+    if (ch.mec) {
+      const int T = pdf_tab(ch.pidi);
+      rmec = lrn ? learned_R(C, ent_s3(famB, T), eb, k) * kMecB : C.bound_mec[T * kNB + eb];
+    }
     const int m = is_terms_pick(C, ch.type, ch.pidi, ch.I1, ch.I2, target, [&](int ent) {
       return lrn ? learned_R(C, ent, eb, k) : C.bound[ent * kNB + eb];
-    }, ch.mec, Rsel);
+    }, ch.mec, rmec, Rsel);
     if (m >= 0) {
       Term t = term_at(C, ch, m);
       t.coefR = Rsel;
@@ -534,7 +544,8 @@ __device__ __forceinline__ Term select_term(const Cfg& C, const Chan& ch, double
 // has flavour pidi, from the cell constants of its terms
 __device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k,
                                             bool mec) {
-  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); }, mec);
+  const double rmec = mec ? learned_R(C, ent_s3(famB, pdf_tab(pidi)), ebin, k) * kMecB : 0.0;
+  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); }, mec, rmec);
 }
 
 // the cell of a scale: the largest k with edge[k] < ln t (0 if none), and its

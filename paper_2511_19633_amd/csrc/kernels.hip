@@ -84,15 +84,36 @@ __device__ double xf_on_row(const Cfg& C, int tab, int j, double x) {
   return (1.0 - a) * (double)F[i] + a * (double)F[i + 1];
 }
 
+// the first-emission correction's largest value at momentum fraction x
+// (family B, v = 1 - x), and over [lo, hi] (one maximum, at (3 - sqrt 5) / 2)
+__device__ double mec_bmax(double x) {
+  const double omx = 1.0 - x;
+  return 1.0 + (1.0 - x * x) / (x * x + omx * omx);
+}
+__device__ double mec_bmax_range(double lo, double hi) {
+  const double xs = 0.5 * (3.0 - sqrt(5.0));
+  if (lo <= xs && xs <= hi) return mec_bmax(xs);
+  const double a = mec_bmax(lo), b = mec_bmax(hi);
+  return a > b ? a : b;
+}
+
+// entries 0 .. kNEnt-1 of the table, then kNEnt + T: family B at the
+// initial-initial end (shape 3) while the first-emission correction applies
+// (kind 4: the kernel bound times the correction's largest value)
 __global__ void k_bounds(Cfg C, double* bound) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= kNEnt * kNB) return;
+  if (t >= (kNEnt + 8) * kNB) return;
   int e = t / kNB, bin = t % kNB;
   // which transition this entry bounds
   int kind, fam = -1, T, num, den;
   double m2 = 0.0;
   bool valid = true;
-  if (e < 8) {
+  if (e >= kNEnt) {
+    kind = 4; fam = famB; T = e - kNEnt; num = 0; den = T;
+    valid = T != 0;
+    if (T == 4) m2 = C.mc2;
+    if (T == 5) m2 = C.mb2;
+  } else if (e < 8) {
     kind = 0; T = e; num = e; den = e;
   } else {
     kind = e < 40 ? 1 : 3;
@@ -139,7 +160,9 @@ __global__ void k_bounds(Cfg C, double* bound) {
         if (kind != 0) {
           int sh = kind == 1 ? 1 : 3;
           double ga = gbound(sh, fam, eta / xlo), gb = gbound(sh, fam, eta / xhi);
-          val = (ga > gb ? ga : gb) * nc;
+          double g = ga > gb ? ga : gb;
+          if (kind == 4) g = g * mec_bmax_range(eta / xhi, eta / xlo);
+          val = g * nc;
         }
         if (val > m) m = val;
       }
