@@ -193,7 +193,6 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   C.dlnq = (cfg->lnq1 - cfg->lnq0) / (cfg->nq - 1);
   C.pdf = c->d_pdf;
   C.bound = c->d_bound;
-  C.bound_mec = c->d_bound + gaps::kNEnt * gaps::kNB;
   // the overestimate table, computed on the device
   int nthr = (gaps::kNEnt + 8) * gaps::kNB;
   hipLaunchKernelGGL(gaps::k_bounds, dim3(grid_for(nthr, 64)), dim3(64), 0, 0, C, c->d_bound);

@@ -34,7 +34,7 @@ constexpr int kMaxSlots = 256;
 // most overestimate terms of a channel: an initial-state gluon, 1 + 2 nf (nf <= 5)
 constexpr int kMaxTerms = 11;
 constexpr uint32_t kMaxCycles = 2000000u;
-constexpr double kMecB = 2.625;  // overestimate factor of a corrected family-B term
+constexpr double kMecB = 2.625;  // overestimate factor of a corrected learned family-B term
 
 enum : int { kFF = 0, kFI = 1, kIF = 2, kII = 3 };
 enum : int { kSoft = 0, kFlat = 1, kS1 = 2, kS3 = 3 };
@@ -60,8 +60,8 @@ struct Cfg {
   double mu_q2;
   double cell_edge[kNTB + 1];  // ln t edges of the learned-bound cells
   const float* pdf;      // [8][nq][nx]
-  const double* bound;   // [72][48]
-  const double* bound_mec;  // [8][48] family B under the first-emission correction, by PDF table
+  const double* bound;   // [72 + 8][48]: the entries, then family B under the
+                         // first-emission correction by the quark's PDF table
   const double* learn;   // [64][48][8] learned bound (LEARNED mode), or null
 };
 
@@ -323,8 +323,7 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
       t.kern = kB; t.shape = sh2; t.flav = 0; t.ent = ii ? ent_s3(famB, T) : ent_s1(famB, T); t.I = ch.I2;
     }
   }
-  t.coefR = C.bound[t.ent * kNB + ch.ebin];
-  if (ch.mec && t.kern == kB) t.coefR = C.bound_mec[pdf_tab(ch.pidi) * kNB + ch.ebin];
+  t.coefR = C.bound[t.ent * kNB + ch.ebin];  // (a corrected family B: see select_term)
   return t;
 }
 
@@ -334,11 +333,9 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
 // 1..nf, -1..-nf for a gluon).  Every term's constant is loaded first
 // (independent loads), then the products are summed in term order: the total
 // constant c, or the term a uniform draw of c picks.
-// mec: the channel's first emission is corrected; family B's constant is then
-// rmec (the corrected table's, or a learned constant times kMecB)
 template <class Tab>
 __device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, Tab R_of, double (&R)[kMaxTerms],
-                                             bool mec, double rmec) {
+                                             bool mec) {
   const bool ii = type == kII;
   if (pidi == 21) {
     const int nt = 1 + 2 * C.nf;
@@ -356,8 +353,8 @@ __device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, T
   }
   const int T = pdf_tab(pidi);
   R[0] = R_of(ent_s1(famA, T));
-  R[1] = R_of(ii ? ent_s3(famB, T) : ent_s1(famB, T));
-  if (mec) R[1] = rmec;
+  // a corrected channel's family B: the corrected table (entry kNEnt + T)
+  R[1] = R_of(mec ? kNEnt + T : (ii ? ent_s3(famB, T) : ent_s1(famB, T)));
 #pragma unroll
   for (int m = 2; m < kMaxTerms; ++m) R[m] = 0.0;
   return 2;
@@ -365,10 +362,10 @@ __device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, T
 
 template <class Tab>
 __device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, double I1, double I2, Tab R_of,
-                                             bool mec, double rmec) {
+                                             bool mec) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R, mec, rmec);
+  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
   double c = 0.0;
   c += af * R[0] * I1;
 #pragma unroll
@@ -381,10 +378,10 @@ __device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, d
 // term order) first exceeds target, and its constant; -1 if none does.
 template <class Tab>
 __device__ __forceinline__ int is_terms_pick(const Cfg& C, int type, int pidi, double I1, double I2, double target,
-                                             Tab R_of, bool mec, double rmec, double& Rsel) {
+                                             Tab R_of, bool mec, double& Rsel) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R, mec, rmec);
+  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
   int sel = -1;
   Rsel = 0.0;
   double cum = 0.0;
@@ -468,9 +465,7 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
   double c = 0.0;
   if (isE) {
     const int eb = ch.ebin;
-    const double rmec = ch.mec ? C.bound_mec[pdf_tab(ch.pidi) * kNB + eb] : 0.0;
-    c = is_terms_c(C, ch.type, ch.pidi, ch.I1, ch.I2, [&](int ent) { return C.bound[ent * kNB + eb]; }, ch.mec,
-                   rmec);
+    c = is_terms_c(C, ch.type, ch.pidi, ch.I1, ch.I2, [&](int ent) { return C.bound[ent * kNB + eb]; }, ch.mec);
   } else {
     double af = C.as_over / (2.0 * kPi) * C.over_scale;
     for (int m = 0; m < ch.nterm; ++m) {
@@ -489,8 +484,12 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
 // constant in cell k of ln t is the sum over its terms, in order, of
 // alpha_s(t_c)/(2 pi) * R_theta[entry][eta bin][k] * (z integral of the shape)
 // (computed for all cells at the channel build).
+// (an entry kNEnt + T, family B under the first-emission correction: the
+// learned family-B constant times kMecB, the correction's largest value)
 __device__ __forceinline__ double learned_R(const Cfg& C, int ent, int ebin, int k) {
-  return C.learn[((ent - kIS0) * kNB + ebin) * kNTB + k];
+  const bool mec = ent >= kNEnt;
+  const double v = C.learn[(((mec ? ent_s3(famB, ent - kNEnt) : ent) - kIS0) * kNB + ebin) * kNTB + k];
+  return mec ? v * kMecB : v;
 }
 
 // Splitting family (term) of the winner in proportion to the overestimates.
@@ -503,14 +502,9 @@ __device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool 
   if (ch.type == kIF || ch.type == kII) {
     const int eb = ch.ebin;
     double Rsel;
-    double rmec = 0.0;
-    if (ch.mec) {
-      const int T = pdf_tab(ch.pidi);
-      rmec = lrn ? learned_R(C, ent_s3(famB, T), eb, k) * kMecB : C.bound_mec[T * kNB + eb];
-    }
     const int m = is_terms_pick(C, ch.type, ch.pidi, ch.I1, ch.I2, target, [&](int ent) {
       return lrn ? learned_R(C, ent, eb, k) : C.bound[ent * kNB + eb];
-    }, ch.mec, rmec, Rsel);
+    }, ch.mec, Rsel);
     if (m >= 0) {
       Term t = term_at(C, ch, m);
       t.coefR = Rsel;
@@ -526,6 +520,7 @@ __device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool 
   for (int m = ch.nterm - 1; m >= 0; --m) {
     Term t = term_at(C, ch, m);
     if (af * t.coefR * t.I > 0.0) {
+      if (ch.mec && t.kern == kB) t.coefR = C.bound[(kNEnt + pdf_tab(ch.pidi)) * kNB + ch.ebin];
       if (lrn) t.coefR = learned_R(C, t.ent, ch.ebin, k) * (ch.mec && t.kern == kB ? kMecB : 1.0);
       return t;
     }
@@ -544,8 +539,7 @@ __device__ __forceinline__ Term select_term(const Cfg& C, const Chan& ch, double
 // has flavour pidi, from the cell constants of its terms
 __device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k,
                                             bool mec) {
-  const double rmec = mec ? learned_R(C, ent_s3(famB, pdf_tab(pidi)), ebin, k) * kMecB : 0.0;
-  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); }, mec, rmec);
+  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); }, mec);
 }
 
 // the cell of a scale: the largest k with edge[k] < ln t (0 if none), and its
@@ -616,8 +610,10 @@ __device__ __forceinline__ void ii_lambda(const double* Kp, const double* K, dou
 // quarks' family A (q -> q g), so R / (D_a + D_b) = 1 - 2 v (1 - x - v) /
 // (1 + x^2), in [1/2, 1]; a quark from a gluon (family B, g qbar -> Z qbar)
 // has only its own dipole: R / D = 1 + v (2 x + v) / (x^2 + (1 - x)^2), at
-// most the golden ratio squared (2.618...), which the family-B overestimate of
-// a corrected channel covers with the factor kMecB.
+// most the golden ratio squared (2.618...).  A corrected channel's family-B
+// overestimate covers it with a table of its own (the kernel bound times the
+// factor's largest value at each momentum fraction, scanned like the others),
+// or, for a learned constant, with the factor kMecB.
 __device__ __forceinline__ double mec_ratio(bool family_b, double x, double v) {
   const double omx = 1.0 - x;
   if (!family_b) return 1.0 - 2.0 * v * (omx - v) / (1.0 + x * x);

@@ -428,12 +428,12 @@ template <bool RETAIN>
 __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_events& in1, const gaps_events& out1,
                                                  const Scratch& S, const ShowerArgs& A) {
   // the overestimate table, staged in LDS for the term loops
-  __shared__ double s_bound[kNEnt * kNB];
+  __shared__ double s_bound[(kNEnt + 8) * kNB];
   __shared__ int s_cnt[16], s_nexh;
   __shared__ BuildLds s_build[8];  // one per wave (blocks of at most 512 threads)
   __shared__ TrialLds s_trial[8];
   extern __shared__ LaneState s_pool[];
-  for (int q = threadIdx.x; q < kNEnt * kNB; q += blockDim.x) s_bound[q] = Cg.bound[q];
+  for (int q = threadIdx.x; q < (kNEnt + 8) * kNB; q += blockDim.x) s_bound[q] = Cg.bound[q];
   if (threadIdx.x == 0) s_nexh = 0;
   __syncthreads();
   Cfg C = Cg;
