@@ -227,7 +227,7 @@ def main():
     ap.add_argument("--log-rows", type=int, default=50_000_000)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=65536)
-    ap.add_argument("--train-tau", type=float, default=0.9999, help="quantile of the learned bound's pinball loss")
+    ap.add_argument("--train-tau", type=float, default=0.999, help="quantile of the learned bound's pinball loss")
     ap.add_argument("--trials", choices=["retain", "regenerate"], default="retain",
                     help="retain: a losing channel keeps its trial scale (the same Markov chain, fewer draws); "
                          "regenerate: every channel draws again each cycle")
