@@ -126,7 +126,8 @@ def learned_pipeline(G, binding, args, seed):
     loss = G.mlp_train(x[:ntr], y[:ntr], steps=args.train_steps, batch=args.train_batch, lr=3e-3, tau=args.train_tau,
                        seed=seed)
     torch.cuda.synchronize()
-    rep["train_s"], rep["train_steps"], rep["train_batch"] = time.perf_counter() - t0, args.train_steps, args.train_batch
+    rep["train_s"] = time.perf_counter() - t0
+    rep["train_steps"], rep["train_batch"] = args.train_steps, args.train_batch
     rep["train_tau"] = args.train_tau
     lv = loss.cpu().numpy()
     rep["loss_first"], rep["loss_last"] = float(lv[:10].mean()), float(lv[-10:].mean())
