@@ -16,7 +16,15 @@
  *   FF/FI/IF/II maps, II boost  pinned (CS variables recomputed from momenta,
  *                               masslessness, momentum conservation, Lambda)
  *   veto loop ................. pinned (no-emission closed form; first-emission
- *                               CDF vs 2-D quadrature of the Sudakov integrands)
+ *                               CDF vs 2-D quadrature of the Sudakov integrands
+ *                               of every kernel: FF q->qg, g->gg, g->qqbar; FI
+ *                               q->qg and the gluon's; IF/II families A-D; the
+ *                               heavy-quark measure and factor; in all four
+ *                               forms; planted mistakes fail them)
+ *   learned bound ............. pinned (first-emission CDF with null trials;
+ *                               with the bound too low everywhere and in one
+ *                               planted cell: the weighted veto's weighted
+ *                               CDF vs quadrature)
  *   NLO pieces ................ pinned (printed B+V+I factor, B = int g,
  *                               Li2 vs library, R-S identities)
  *   observables ............... pinned (thrust/jets on hand-built events)
@@ -126,9 +134,13 @@ typedef struct {
     int64_t* log_count;  /* in/out: rows so far */
     /* LEARNED: the learned bound R_theta[64][48][8] (initial-state entries
      * 8..71, eta bins, ln t cells) for the initial-state channels of the
-     * partons in slots 0 and 1; random-number stream 1; an event whose
-     * weight exceeds its learned bound is showered again in plain mode and
-     * flagged OR_F_FALLBACK. */
+     * partons in slots 0 and 1; random-number stream 1.  A trial whose weight
+     * exceeds its learned bound goes through the weighted veto (accepted
+     * with probability w/(2w - 1), the event weight multiplied by 2w - 1 on
+     * acceptance and by -(2w - 1) on rejection), and the event continues on
+     * the analytic overestimate (every channel draws again), flagged
+     * OR_F_FALLBACK.  Violations of the learned bound are not counted in
+     * n_viol. */
     const double* learned;
     /* retain != 0: the retained-trial form of the max-veto competition.  A
      * channel's trial scale is the first point below the current scale of its

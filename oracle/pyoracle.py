@@ -53,10 +53,12 @@ class OrEvents(C.Structure):
     ]
 
 
-def _lib():
-    if not os.path.exists(_LIB):
-        build()
-    lib = C.CDLL(_LIB)
+def _lib(path=None):
+    if path is None:
+        path = _LIB
+        if not os.path.exists(path):
+            build()
+    lib = C.CDLL(path)
     lib.or_init.restype = C.c_void_p
     lib.or_init.argtypes = [C.POINTER(OrConfig)]
     lib.or_free.argtypes = [C.c_void_p]
@@ -103,10 +105,17 @@ def _lib():
 
 
 LIB = None
+_OTHER = {}
 
 
-def lib():
+def lib(path=None):
+    """The oracle library (path: another build of the oracle's sources, as the
+    mutation tests make; default the in-tree one)."""
     global LIB
+    if path is not None:
+        if path not in _OTHER:
+            _OTHER[path] = _lib(path)
+        return _OTHER[path]
     if LIB is None:
         LIB = _lib()
     return LIB
@@ -136,7 +145,7 @@ def events_struct(ev: records.Events) -> OrEvents:
 class Oracle:
     """One configured oracle instance (keeps the config arrays alive)."""
 
-    def __init__(self, cfg: dict, over_scale: float = 1.0):
+    def __init__(self, cfg: dict, over_scale: float = 1.0, lib_path=None):
         self._pdf = np.ascontiguousarray(cfg["pdf"], dtype=np.float32)
         c = OrConfig()
         for name, _ in OrConfig._fields_:
@@ -149,33 +158,34 @@ class Oracle:
         c.over_scale = over_scale
         self.cfg = cfg
         self._c = c
-        self.h = lib().or_init(C.byref(c))
+        self.L = lib(lib_path)
+        self.h = self.L.or_init(C.byref(c))
 
     def __del__(self):
-        if getattr(self, "h", None) and LIB is not None:
-            LIB.or_free(self.h)
+        if getattr(self, "h", None) and getattr(self, "L", None) is not None:
+            self.L.or_free(self.h)
             self.h = None
 
     def alphas(self, t):
-        return lib().or_alphas(self.h, t)
+        return self.L.or_alphas(self.h, t)
 
     def pdf_xf(self, tab, x, q2):
-        return lib().or_pdf_xf(self.h, tab, x, q2)
+        return self.L.or_pdf_xf(self.h, tab, x, q2)
 
     def bounds(self):
         ne, nb = C.c_int(), C.c_int()
-        lib().or_bounds_shape(C.byref(ne), C.byref(nb))
+        self.L.or_bounds_shape(C.byref(ne), C.byref(nb))
         out = np.zeros((ne.value, nb.value), dtype=np.float64)
-        lib().or_bounds(self.h, _ptr(out))
+        self.L.or_bounds(self.h, _ptr(out))
         return out
 
     def lo_wmax(self):
-        return lib().or_lo_wmax(self.h)
+        return self.L.or_lo_wmax(self.h)
 
     def hard_events(self, first_id, n, seed, max_slots=128):
         ev = records.Events(n, max_slots)
         s = events_struct(ev)
-        if lib().or_hard_events(self.h, first_id, n, seed, C.byref(s)) != 0:
+        if self.L.or_hard_events(self.h, first_id, n, seed, C.byref(s)) != 0:
             raise ValueError("or_hard_events: invalid matching for this process")
         return ev
 
@@ -189,10 +199,10 @@ class Oracle:
         out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
         si, so = events_struct(ev_in), events_struct(out)
         if not retain and not gen_select and not veto_max:
-            lib().or_shower(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads)
+            self.L.or_shower(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads)
             return out
         o = OrOpts(MODE_PLAIN, None, 0, None, None, int(retain), int(gen_select), int(veto_max))
-        rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
+        rc = self.L.or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
         if rc != 0:
             raise RuntimeError("or_shower_ex failed")
         return out
@@ -207,54 +217,57 @@ class Oracle:
         cnt = C.c_int64(0)
         o = OrOpts(MODE_LOG, log.ctypes.data_as(C.POINTER(C.c_float)), int(log_cap), C.pointer(cnt), None,
                    int(retain))
-        rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
+        rc = self.L.or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
         if rc != 0:
             raise RuntimeError("or_shower_ex failed")
         return out, log[:min(cnt.value, int(log_cap))], cnt.value
 
     def shower_learned(self, ev_in: records.Events, seed, table, nthreads=1, max_slots=None, retain=False):
-        """LEARNED mode with the bound table [64][48][8] (doubles)."""
+        """LEARNED mode with the bound table [64][48][8] (doubles).  A trial
+        above its learned bound goes through the weighted veto and its event
+        continues on the analytic bound (flag FALLBACK, weight multiplied by
+        +-(2w - 1))."""
         out = records.Events(ev_in.cap, max_slots or ev_in.max_slots)
         si, so = events_struct(ev_in), events_struct(out)
         tab = np.ascontiguousarray(table, dtype=np.float64)
         assert tab.shape == (64, 48, 8)
         o = OrOpts(MODE_LEARNED, None, 0, None, tab.ctypes.data_as(C.POINTER(C.c_double)), int(retain))
-        rc = lib().or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
+        rc = self.L.or_shower_ex(self.h, C.byref(si), ev_in.cap, seed, C.byref(so), nthreads, C.byref(o))
         if rc != 0:
             raise RuntimeError("or_shower_ex failed")
         return out
 
     def cell_edges(self):
         out = np.zeros(9, dtype=np.float64)
-        lib().or_cell_edges(self.h, out.ctypes.data_as(C.c_void_p))
+        self.L.or_cell_edges(self.h, out.ctypes.data_as(C.c_void_p))
         return out
 
     def observables(self, ev: records.Events):
-        nobs = lib().or_n_obs()
+        nobs = self.L.or_n_obs()
         obs = np.zeros((ev.cap, nobs), dtype=np.float64)
         s = events_struct(ev)
-        lib().or_observables(self.h, C.byref(s), ev.cap, _ptr(obs))
+        self.L.or_observables(self.h, C.byref(s), ev.cap, _ptr(obs))
         return obs
 
     # NLO pieces
     def li2(self, x):
-        return lib().or_li2(x)
+        return self.L.or_li2(x)
 
     def bvi_factor(self):
-        return lib().or_nlo_bvi_factor(self.h)
+        return self.L.or_nlo_bvi_factor(self.h)
 
     def aqq(self):
-        return lib().or_nlo_aqq(self.h)
+        return self.L.or_nlo_aqq(self.h)
 
     def bqq(self, eta):
-        return lib().or_nlo_bqq(self.h, eta)
+        return self.L.or_nlo_bqq(self.h, eta)
 
     def gqq(self, x):
-        return lib().or_nlo_gqq(self.h, x)
+        return self.L.or_nlo_gqq(self.h, x)
 
     def rs(self, kind, sbar, tbar, ubar, mborn2):
         r = C.c_double()
-        lib().or_nlo_rs(self.h, kind, sbar, tbar, ubar, mborn2, C.byref(r))
+        self.L.or_nlo_rs(self.h, kind, sbar, tbar, ubar, mborn2, C.byref(r))
         return r.value
 
     @staticmethod
@@ -271,7 +284,7 @@ class Oracle:
 
     def dy_real(self, f, kind, o2, m2, x, y, v, phi, c, uphi):
         out = np.zeros(4)
-        lib().or_dy_real(self.h, f, kind, o2, m2, x, y, v, phi, c, uphi, out.ctypes.data_as(C.c_void_p))
+        self.L.or_dy_real(self.h, f, kind, o2, m2, x, y, v, phi, c, uphi, out.ctypes.data_as(C.c_void_p))
         return out
 
 

@@ -597,10 +597,374 @@ static double draw_trial(const or_state* S, const chan_t* C, double T, double ln
     return key;
 }
 
-/* Shower one event.  mode OR_MODE_LEARNED draws the initial-state channels
- * against the cell constants of the learned table Lt (random-number stream 1)
- * and returns 1, writing nothing, as soon as a weight exceeds its learned bound;
- * the caller then showers the event again in plain mode. */
+/* ---- one event ----
+ * The working state of one event while it is showered: its record and channel
+ * list, the evolution scale, the random-number coordinates and the counters
+ * that go to the output.  lrn: the initial-state channels of the incoming
+ * partons still draw against the learned cell constants (LEARNED mode until
+ * the first violation of the learned bound); wfac: the weight factor that the
+ * weighted veto of such a violation leaves on the event. */
+typedef struct {
+    const or_state* S;
+    ev_t* ev;
+    chan_t* ch;
+    int nch, M;
+    int64_t id;
+    uint64_t seed;
+    uint32_t stream;
+    int lrn;
+    const double* Lt;
+    logsink_t* L;
+    double T, lnT, t1, wfac;
+    uint32_t cycle, ntri, nacc, nviol, flags;
+} sh_t;
+
+/* the learned cells apply to the initial-state channels of the incoming
+ * partons (emitter slot 0 or 1) */
+static int learned_chan(const sh_t* r, const chan_t* C) {
+    return r->lrn && (C->type == T_IF || C->type == T_II) && C->i < 2;
+}
+
+/* read event e of the input into the working record; returns 0 when the event
+ * can be showered (it fits and its colour lines pair up) */
+static int sh_load(sh_t* r, const or_events* in, int64_t e) {
+    ev_t* ev = r->ev;
+    const int64_t ci = in->cap;
+    ev->n = in->n[e];
+    ev->maxtag = 0;
+    r->flags = in->flags ? in->flags[e] : 0u;
+    ev->mec = (r->flags & OR_F_MEC) != 0u;
+    for (int q = 0; q < ev->n && q < OR_MAXM; ++q) {
+        int64_t o = (int64_t)q * ci + e;
+        ev->p[q][0] = in->E[o]; ev->p[q][1] = in->px[o];
+        ev->p[q][2] = in->py[o]; ev->p[q][3] = in->pz[o];
+        ev->pid[q] = in->pid[o]; ev->col[q] = in->col[o]; ev->acol[q] = in->acol[o];
+        ev->st[q] = in->status[o];
+        if (ev->col[q] > ev->maxtag) ev->maxtag = ev->col[q];
+        if (ev->acol[q] > ev->maxtag) ev->maxtag = ev->acol[q];
+    }
+    r->id = in->id[e];
+    r->T = in->t_start[e];
+    r->lnT = log(r->T);
+    r->t1 = 0.0;
+    r->wfac = 1.0;
+    r->cycle = r->ntri = r->nacc = r->nviol = 0u;
+    r->nch = 0;
+    if (ev->n > r->M) { r->flags |= OR_F_OVERFLOW; return -1; }
+    if (build_channels(r->S, ev, r->ch, &r->nch) < 0) { r->flags |= OR_F_COLOUR; return -1; }
+    return 0;
+}
+
+static void sh_store(const sh_t* r, const or_events* in, int64_t e_in, or_events* out, int64_t e_out) {
+    const ev_t* ev = r->ev;
+    const int64_t co = out->cap;
+    out->id[e_out] = r->id;
+    out->w[e_out] = in->w[e_in] * r->wfac;
+    out->t_start[e_out] = in->t_start[e_in];
+    out->n[e_out] = ev->n;
+    if (out->flags) out->flags[e_out] = r->flags;
+    for (int q = 0; q < ev->n && q < out->max_slots; ++q) {
+        int64_t o = (int64_t)q * co + e_out;
+        out->E[o] = ev->p[q][0]; out->px[o] = ev->p[q][1];
+        out->py[o] = ev->p[q][2]; out->pz[o] = ev->p[q][3];
+        out->pid[o] = ev->pid[q]; out->col[o] = ev->col[q]; out->acol[o] = ev->acol[q];
+        out->status[o] = (int8_t)ev->st[q];
+    }
+    if (out->n_cycles) out->n_cycles[e_out] = r->cycle;
+    if (out->n_trials) out->n_trials[e_out] = r->ntri;
+    if (out->n_accept) out->n_accept[e_out] = r->nacc;
+    if (out->n_viol) out->n_viol[e_out] = r->nviol;
+    if (out->t1) out->t1[e_out] = r->t1;
+}
+
+/* the trial of channel C from the current scale at the current cycle */
+static double sh_draw(sh_t* r, const chan_t* C, int* isnull, int* cell) {
+    return draw_trial(r->S, C, r->T, r->lnT, r->seed, r->stream, r->id, r->cycle, r->lrn, r->Lt, &r->ntri,
+                      isnull, cell);
+}
+
+/* what the winner of a cycle proposes */
+typedef struct {
+    int acc;     /* the emission is accepted */
+    term_t tm;   /* splitting term */
+    double z, omz, phi;
+    veto_t v;
+} step_t;
+
+/* The winner trial of channel C at scale t (section 2): its splitting term in
+ * proportion to the terms' overestimates (a learned channel: the cell
+ * constants of cell wcell), z from the term's shape and the azimuth, from the
+ * winner block of the cycle; then the weight and the veto.
+ *
+ * A weight above the learned bound (LEARNED mode) is handled by the weighted
+ * veto algorithm (Lonnblad, Eur. Phys. J. C 73 (2013) 2350): with a proposal
+ * density g below the true density f at the trial, accepting with any
+ * probability eps and multiplying the event weight by f/(g eps) on acceptance
+ * and by (1 - f/g)/(1 - eps) on rejection keeps the emission density exactly
+ * f.  eps = w/(2w - 1) (w = f/g > 1) minimises the second moment of the
+ * factor, which is then +(2w - 1) or -(2w - 1).  From this trial on the event
+ * draws against the analytic overestimate (its channels draw again from the
+ * new scale), so it sees no further learned-bound violation.  A weight above
+ * the analytic bound is counted (n_viol, OR_F_VIOL) and accepted with
+ * probability one. */
+static step_t winner(sh_t* r, const chan_t* C, double t, int lch, int wcell) {
+    const or_state* S = r->S;
+    const double* Lt = r->Lt;
+    step_t st;
+    double u[4];
+    or_rng_block(r->seed, r->stream, r->id, r->cycle, 0xFFFFFFFFu, u);
+    double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
+    double ctot = lch ? learned_c(S, C, Lt, wcell) : C->c;
+    double target = u[0] * ctot, cum = 0.0;
+    int sel = -1;
+    for (int m = 0; m < C->nterm; ++m) {
+        cum += lch ? af * lrn(Lt, C->term[m].ent, C->ebin, wcell) * C->term[m].mul * shape_int(C->term[m].shape, C)
+                   : C->term[m].c;
+        if (target < cum) { sel = m; break; }
+    }
+    if (sel < 0)
+        for (int m = C->nterm - 1; m >= 0; --m)
+            if (C->term[m].c > 0.0) { sel = m; break; }
+    st.tm = C->term[sel];
+    if (lch) st.tm.coefR = lrn(Lt, st.tm.ent, C->ebin, wcell) * st.tm.mul;
+    double I = shape_int(st.tm.shape, C);
+    shape_sample(st.tm.shape, C, I, u[1], &st.z, &st.omz);
+    st.phi = 2.0 * OR_PI * u[2];
+    st.v = weight(S, r->ev, C, &st.tm, t, st.z, st.omz);
+    const veto_t* v = &st.v;
+    if (r->L && (C->type == T_IF || C->type == T_II) && !C->mec && v->ok && v->wn > 0.0)
+        log_trial(r->L, t, C->eta, st.z, st.tm.ent, v->wn);
+    if (lch && v->ok && v->w > 1.0) {
+        const double g = 2.0 * v->w - 1.0;
+        st.acc = u[3] < v->w / g;
+        r->wfac *= st.acc ? g : -g;
+        r->lrn = 0;
+        r->flags |= OR_F_FALLBACK;
+        return st;
+    }
+    if (v->ok && v->w > 1.0) { r->nviol += 1; r->flags |= OR_F_VIOL; }
+    st.acc = v->ok && u[3] < v->w;
+    return st;
+}
+
+/* Apply the accepted emission of channel C at scale t and rebuild the channel
+ * list.  Returns 0 to go on, 1 when the event stops after this cycle (a
+ * non-finite momentum or a broken colour line: the cycle counts), 2 when it
+ * stops before (the record is full: the cycle does not count). */
+static int emit_step(sh_t* r, const chan_t* C, const step_t* st, double t) {
+    ev_t* ev = r->ev;
+    if (ev->n + 1 > r->M) { r->flags |= OR_F_OVERFLOW; return 2; }
+    emit(r->S, ev, C, &st->tm, st->z, st->omz, &st->v, st->phi);
+    r->nacc += 1;
+    if (r->t1 == 0.0) r->t1 = t;
+    int bad = 0;
+    for (int q = 0; q < ev->n; ++q) bad |= !finite4(ev->p[q]);
+    if (bad) { r->flags |= OR_F_NAN; return 1; }
+    if (build_channels(r->S, ev, r->ch, &r->nch) < 0) { r->flags |= OR_F_COLOUR; return 1; }
+    return 0;
+}
+
+/* Max-veto, the paper's form (section 2): each cycle every channel draws a
+ * trial scale from the current scale and the largest trial is the winner
+ * (ties to the lowest channel); it is vetoed or accepted, and the evolution
+ * continues from its scale.  In LEARNED mode an initial-state channel of an
+ * incoming parton draws against the constant of the cell of its scale, and a
+ * trial below that cell is a null at the cell's lower edge: when a null wins,
+ * no channel emits above the edge and the evolution continues from it. */
+static void run_max_veto(sh_t* r) {
+    for (;;) {
+        if (r->cycle >= OR_MAXCYC) { r->flags |= OR_F_MAXCYC; break; }
+        double best = -INFINITY;
+        int win = -1, wnull = 0, wcell = 0;
+        for (int c = 0; c < r->nch; ++c) {
+            int isnull, cell;
+            const double key = sh_draw(r, &r->ch[c], &isnull, &cell);
+            if (key > best) { best = key; win = c; wnull = isnull; wcell = cell; }
+        }
+        if (win < 0) break;
+        if (wnull) {
+            r->T = exp(best);
+            r->lnT = best;
+            r->cycle += 1;
+            continue;
+        }
+        const double t = exp(best);
+        const chan_t* C = &r->ch[win];
+        const step_t st = winner(r, C, t, learned_chan(r, C), wcell);
+        if (st.acc) {
+            const int rc = emit_step(r, C, &st, t);
+            if (rc == 2) break;
+            if (rc == 1) { r->cycle += 1; break; }
+        }
+        r->T = t;
+        r->lnT = best;
+        r->cycle += 1;
+    }
+}
+
+/* Retained trials (the same Markov chain as max-veto with fewer draws): a
+ * channel's trial scales are the points of its own Poisson process of
+ * intensity c/t below the current scale, so a channel that loses a cycle
+ * keeps its trial, and only the winner draws again after a veto or a null.
+ * After an emission a channel keeps its trial when its process is unchanged:
+ * the same spectator, and neither its emitter nor its spectator is the
+ * emitter, the spectator or the new parton of the emission (whose recoil is
+ * local).  An initial-initial emission boosts every final-state parton, and a
+ * violated learned bound changes the initial-state constants: then every
+ * channel draws again. */
+static void run_retained(sh_t* r) {
+    static _Thread_local double key[OR_MAXCH], okey[2 * OR_MAXM];
+    static _Thread_local int knull[OR_MAXCH], kcell[OR_MAXCH];
+    static _Thread_local int okspec[2 * OR_MAXM], onull[2 * OR_MAXM], ocell[2 * OR_MAXM];
+    for (int c = 0; c < r->nch; ++c) key[c] = sh_draw(r, &r->ch[c], &knull[c], &kcell[c]);
+    for (;;) {
+        if (r->cycle >= OR_MAXCYC) { r->flags |= OR_F_MAXCYC; break; }
+        double best = -INFINITY;
+        int win = -1;
+        for (int c = 0; c < r->nch; ++c)
+            if (key[c] > best) { best = key[c]; win = c; }
+        if (win < 0) break;
+        if (knull[win]) {
+            r->T = exp(best);
+            r->lnT = best;
+            r->cycle += 1;
+            key[win] = sh_draw(r, &r->ch[win], &knull[win], &kcell[win]);
+            continue;
+        }
+        const double t = exp(best);
+        const chan_t* C = &r->ch[win];
+        const int lch = learned_chan(r, C);
+        const int e_i = C->i, e_k = C->k;
+        const step_t st = winner(r, C, t, lch, kcell[win]);
+        const int fell = lch && !r->lrn;
+        const int e_all = C->type == T_II || fell;
+        if (st.acc) {
+            /* the pending trial and spectator of every entry 2i+side */
+            for (int q = 0; q < 2 * r->ev->n; ++q) okspec[q] = -1;
+            for (int c = 0; c < r->nch; ++c) {
+                int q = 2 * r->ch[c].i + r->ch[c].side;
+                okspec[q] = r->ch[c].k;
+                okey[q] = key[c];
+                onull[q] = knull[c];
+                ocell[q] = kcell[c];
+            }
+            const int rc = emit_step(r, C, &st, t);
+            if (rc == 2) break;
+            if (rc == 1) { r->cycle += 1; break; }
+        }
+        r->T = t;
+        r->lnT = best;
+        r->cycle += 1;
+        if (!st.acc && !fell) {
+            key[win] = sh_draw(r, &r->ch[win], &knull[win], &kcell[win]);
+            continue;
+        }
+        const int j = r->ev->n - 1;
+        for (int c = 0; c < r->nch; ++c) {
+            const chan_t* D = &r->ch[c];
+            const int q = 2 * D->i + D->side;
+            const int kept = st.acc && !e_all && q < 2 * j && okspec[q] == D->k && D->i != e_i && D->i != e_k &&
+                             D->i != j && D->k != e_i && D->k != e_k && D->k != j;
+            if (kept) {
+                key[c] = okey[q];
+                knull[c] = onull[q];
+                kcell[c] = ocell[q];
+            } else {
+                key[c] = sh_draw(r, D, &knull[c], &kcell[c]);
+            }
+        }
+    }
+}
+
+/* generate-select: is channel D active just below T, and its share of the sum
+ * over the segment whose lower end is lo */
+static int gs_active(const chan_t* D, double T) {
+    return D->alive && D->tlim > D->tcut && D->tlim >= T && D->tcut < T;
+}
+static double gs_share(const chan_t* D, double lo) {
+    return D->heavy ? D->c * lo / (lo - D->m2) : D->c;
+}
+
+/* Generate-select (the alternative section 2 names): each cycle one trial
+ * from the sum of the channels' overestimates, the channel picked in
+ * proportion to its share.  Channel limits and cutoffs cut the scale range
+ * into segments; in the segment [lo, T] the active channels sum to C/t (a
+ * heavy-quark channel's c/(t - m^2) bounded by c lo/(lo - m^2)/t and thinned
+ * back); a trial below lo is a null at lo, and with no channel active the
+ * evolution moves to lo without a draw.  Block (id, cycle, 2^32 - 2) gives
+ * the trial, the channel and the thinning; the winner block as in max-veto. */
+static void run_gen_select(sh_t* r) {
+    for (;;) {
+        if (r->cycle >= OR_MAXCYC) { r->flags |= OR_F_MAXCYC; break; }
+        /* the segment below T ends at the largest scale below T where a
+         * channel starts (its limit) or stops (its cutoff) */
+        double lo = -1.0, lnlo = 0.0;
+        int any = 0;
+        for (int c = 0; c < r->nch; ++c) {
+            const chan_t* D = &r->ch[c];
+            if (!D->alive || !(D->tlim > D->tcut)) continue;
+            if (D->tlim < r->T) {
+                if (D->tlim > lo) { lo = D->tlim; lnlo = D->lntlim; }
+            } else if (D->tcut < r->T) {
+                any = 1;
+                if (D->tcut > lo) { lo = D->tcut; lnlo = D->lntcut; }
+            }
+        }
+        if (lo < 0.0) break; /* no channel can emit below T */
+        if (!any) {          /* none active: move to where one starts */
+            r->T = lo;
+            r->lnT = lnlo;
+            r->cycle += 1;
+            continue;
+        }
+        double Csum = 0.0;
+        for (int c = 0; c < r->nch; ++c)
+            if (gs_active(&r->ch[c], r->T)) Csum += gs_share(&r->ch[c], lo);
+        double g[4];
+        or_rng_block(r->seed, r->stream, r->id, r->cycle, 0xFFFFFFFEu, g);
+        r->ntri += 1;
+        const double lnt = r->lnT + log(g[0]) / Csum;
+        if (lnt < lnlo) { /* below the segment: a null at its lower end */
+            r->T = lo;
+            r->lnT = lnlo;
+            r->cycle += 1;
+            continue;
+        }
+        /* the channel whose running share first exceeds u1 C */
+        const double target = g[1] * Csum;
+        double cum = 0.0;
+        int sel = -1, last = -1;
+        for (int c = 0; c < r->nch && sel < 0; ++c) {
+            if (!gs_active(&r->ch[c], r->T)) continue;
+            cum += gs_share(&r->ch[c], lo);
+            last = c;
+            if (target < cum) sel = c;
+        }
+        if (sel < 0) sel = last;
+        if (r->ch[sel].heavy) { /* thin the bound back to c/(t - m^2) */
+            const double t = exp(lnt), m2 = r->ch[sel].m2;
+            const double keep = (t * (lo - m2)) / (lo * (t - m2));
+            if (!(g[2] < keep)) {
+                r->T = t;
+                r->lnT = lnt;
+                r->cycle += 1;
+                continue;
+            }
+        }
+        const double t = exp(lnt);
+        const chan_t* C = &r->ch[sel];
+        const step_t st = winner(r, C, t, 0, 0);
+        if (st.acc) {
+            const int rc = emit_step(r, C, &st, t);
+            if (rc == 2) break;
+            if (rc == 1) { r->cycle += 1; break; }
+        }
+        r->T = t;
+        r->lnT = lnt;
+        r->cycle += 1;
+    }
+}
+
 /* veto-max: trial k of channel entry c at emission cycle j draws its scale
  * from word 0 of block (id, j, VM_BLOCK(c, k, 0)) and its term, z, azimuth and
  * acceptance from block (id, j, VM_BLOCK(c, k, 1)) */
@@ -663,308 +1027,44 @@ static double vm_first(const or_state* S, const ev_t* ev, const chan_t* C, int c
     return -INFINITY;
 }
 
-/* generate-select: is channel D active just below T, and its share of the sum
- * over the segment whose lower end is lo */
-static int gs_active(const chan_t* D, double T) {
-    return D->alive && D->tlim > D->tcut && D->tlim >= T && D->tcut < T;
-}
-static double gs_share(const chan_t* D, double lo) {
-    return D->heavy ? D->c * lo / (lo - D->m2) : D->c;
+/* Veto-max (the other form section 2 names): every channel runs the veto
+ * algorithm on its own from the current scale down to its first accepted
+ * trial, and the largest of these is the emission, applied without a further
+ * veto; after it every channel runs its loop again from the emission's scale.
+ * A cycle is one emission. */
+static void run_veto_max(sh_t* r) {
+    for (;;) {
+        if (r->cycle >= OR_MAXCYC) { r->flags |= OR_F_MAXCYC; break; }
+        double best = -INFINITY;
+        int win = -1, wk = -1, capped = 0;
+        uint32_t nv = 0;
+        for (int c = 0; c < r->nch; ++c) {
+            int k;
+            const double key1 = vm_first(r->S, r->ev, &r->ch[c], c, r->T, r->lnT, r->seed, r->stream, r->id,
+                                         r->cycle, &r->ntri, &nv, &k, &capped);
+            if (key1 > best) { best = key1; win = c; wk = k; }
+        }
+        if (nv) { r->nviol += nv; r->flags |= OR_F_VIOL; }
+        if (capped) { r->flags |= OR_F_MAXCYC; break; }
+        if (win < 0) break;
+        /* the winner's accepted trial again, from the same numbers */
+        const chan_t* C = &r->ch[win];
+        const double t = exp(best);
+        double u[4];
+        or_rng_block(r->seed, r->stream, r->id, r->cycle, VM_BLOCK(win, wk, 1), u);
+        step_t st;
+        vm_veto(r->S, r->ev, C, t, u, &st.tm, &st.z, &st.omz, &st.phi, &st.v);
+        st.acc = 1;
+        const int rc = emit_step(r, C, &st, t);
+        if (rc == 2) break;
+        r->cycle += 1;
+        if (rc == 1) break;
+        r->T = t;
+        r->lnT = best;
+    }
 }
 
-static int shower_one(const or_state* S, const or_events* in, int64_t e_in, uint64_t seed,
-                      or_events* out, int64_t e_out, ev_t* ev, chan_t* ch, logsink_t* L,
-                      int mode, const double* Lt, int retain, int gs, int vm) {
-    const int learned = mode == OR_MODE_LEARNED;
-    const uint32_t stream = learned ? 1u : 0u;
-    const int64_t ci = in->cap, co = out->cap;
-    int M = out->max_slots < OR_MAXM ? out->max_slots : OR_MAXM;
-    ev->n = in->n[e_in];
-    ev->maxtag = 0;
-    uint32_t flags = in->flags ? in->flags[e_in] : 0u;
-    ev->mec = (flags & OR_F_MEC) != 0u;
-    for (int q = 0; q < ev->n; ++q) {
-        int64_t o = (int64_t)q * ci + e_in;
-        ev->p[q][0] = in->E[o]; ev->p[q][1] = in->px[o];
-        ev->p[q][2] = in->py[o]; ev->p[q][3] = in->pz[o];
-        ev->pid[q] = in->pid[o]; ev->col[q] = in->col[o]; ev->acol[q] = in->acol[o];
-        ev->st[q] = in->status[o];
-        if (ev->col[q] > ev->maxtag) ev->maxtag = ev->col[q];
-        if (ev->acol[q] > ev->maxtag) ev->maxtag = ev->acol[q];
-    }
-    int64_t id = in->id[e_in];
-    double T = in->t_start[e_in], lnT = log(T), t1 = 0.0;
-    uint32_t ncyc = 0, ntri = 0, nacc = 0, nviol = 0;
-    int nch = 0;
-    /* retained-trial form: the pending trial of every channel */
-    static _Thread_local double key[OR_MAXCH], okey[2 * OR_MAXM];
-    static _Thread_local int knull[OR_MAXCH], kcell[OR_MAXCH];
-    static _Thread_local int okspec[2 * OR_MAXM], onull[2 * OR_MAXM], ocell[2 * OR_MAXM];
-    if (ev->n > M) flags |= OR_F_OVERFLOW;
-    else if (build_channels(S, ev, ch, &nch) < 0) flags |= OR_F_COLOUR;
-    else {
-        uint32_t cycle = 0;
-        if (retain)
-            for (int c = 0; c < nch; ++c)
-                key[c] = draw_trial(S, &ch[c], T, lnT, seed, stream, id, 0u, learned, Lt, &ntri, &knull[c], &kcell[c]);
-        /* veto-max: every channel runs its own veto loop down to its first
-         * accepted trial; the largest of these is the emission.  A cycle is
-         * one emission; after it every channel runs its loop again. */
-        for (; vm;) {
-            if (cycle >= OR_MAXCYC) { flags |= OR_F_MAXCYC; break; }
-            double best = -INFINITY;
-            int win = -1, wk = -1, capped = 0;
-            uint32_t nv = 0;
-            for (int c = 0; c < nch; ++c) {
-                int k;
-                const double key1 = vm_first(S, ev, &ch[c], c, T, lnT, seed, stream, id, cycle, &ntri, &nv, &k,
-                                             &capped);
-                if (key1 > best) { best = key1; win = c; wk = k; }
-            }
-            if (nv) { nviol += nv; flags |= OR_F_VIOL; }
-            if (capped) { flags |= OR_F_MAXCYC; break; }
-            if (win < 0) break;
-            /* the winner's accepted trial again, from the same numbers */
-            const chan_t* C = &ch[win];
-            const double t = exp(best);
-            double u[4];
-            or_rng_block(seed, stream, id, cycle, VM_BLOCK(win, wk, 1), u);
-            term_t tm;
-            double z, omz, phi;
-            veto_t v;
-            vm_veto(S, ev, C, t, u, &tm, &z, &omz, &phi, &v);
-            if (ev->n + 1 > M) { flags |= OR_F_OVERFLOW; break; }
-            emit(S, ev, C, &tm, z, omz, &v, phi);
-            nacc += 1;
-            if (t1 == 0.0) t1 = t;
-            cycle += 1;
-            int bad = 0;
-            for (int q = 0; q < ev->n; ++q) bad |= !finite4(ev->p[q]);
-            if (bad) { flags |= OR_F_NAN; break; }
-            if (build_channels(S, ev, ch, &nch) < 0) { flags |= OR_F_COLOUR; break; }
-            T = t;
-            lnT = best;
-        }
-        for (; !vm;) {
-            if (cycle >= OR_MAXCYC) { flags |= OR_F_MAXCYC; break; }
-            /* trial scales of every channel; the winner is the largest.  In
-             * learned mode a trial of an initial-state channel that falls below
-             * its cell is a null candidate at the cell edge. */
-            double best = -INFINITY;
-            int win = -1, wnull = 0, wcell = 0;
-            uint32_t curblk = 0xFFFFFFFFu;
-            double ub[4];
-            if (retain) {
-                /* the largest pending trial; ties go to the lowest entry */
-                for (int c = 0; c < nch; ++c)
-                    if (key[c] > best) { best = key[c]; win = c; }
-                if (win >= 0) { wnull = knull[win]; wcell = kcell[win]; }
-            }
-            if (gs) {
-                /* generate-select: the segment below T ends at the largest scale
-                 * below T where a channel starts (its limit) or stops (its cutoff) */
-                double lo = -1.0, lnlo = 0.0;
-                int any = 0;
-                for (int c = 0; c < nch; ++c) {
-                    const chan_t* D = &ch[c];
-                    if (!D->alive || !(D->tlim > D->tcut)) continue;
-                    if (D->tlim < T) {
-                        if (D->tlim > lo) { lo = D->tlim; lnlo = D->lntlim; }
-                    } else if (D->tcut < T) {
-                        any = 1;
-                        if (D->tcut > lo) { lo = D->tcut; lnlo = D->lntcut; }
-                    }
-                }
-                if (lo < 0.0) break; /* no channel can emit below T */
-                if (!any) {          /* none active: move to where one starts */
-                    T = lo;
-                    lnT = lnlo;
-                    cycle += 1;
-                    continue;
-                }
-                double Csum = 0.0;
-                for (int c = 0; c < nch; ++c)
-                    if (gs_active(&ch[c], T)) Csum += gs_share(&ch[c], lo);
-                double g[4];
-                or_rng_block(seed, stream, id, cycle, 0xFFFFFFFEu, g);
-                ntri += 1;
-                const double lnt = lnT + log(g[0]) / Csum;
-                if (lnt < lnlo) { /* below the segment: a null at its lower end */
-                    T = lo;
-                    lnT = lnlo;
-                    cycle += 1;
-                    continue;
-                }
-                /* the channel whose running share first exceeds u1 C */
-                const double target = g[1] * Csum;
-                double cum = 0.0;
-                int sel = -1, last = -1;
-                for (int c = 0; c < nch && sel < 0; ++c) {
-                    if (!gs_active(&ch[c], T)) continue;
-                    cum += gs_share(&ch[c], lo);
-                    last = c;
-                    if (target < cum) sel = c;
-                }
-                if (sel < 0) sel = last;
-                if (ch[sel].heavy) { /* thin the bound back to c/(t - m^2) */
-                    const double t = exp(lnt), m2 = ch[sel].m2;
-                    const double keep = (t * (lo - m2)) / (lo * (t - m2));
-                    if (!(g[2] < keep)) {
-                        T = t;
-                        lnT = lnt;
-                        cycle += 1;
-                        continue;
-                    }
-                }
-                best = lnt;
-                win = sel;
-            }
-            for (int c = 0; !retain && !gs && c < nch; ++c) {
-                const chan_t* C = &ch[c];
-                if (!C->alive) continue;
-                double Tch = T < C->tlim ? T : C->tlim;
-                double lnTch = lnT < C->lntlim ? lnT : C->lntlim;
-                if (!(Tch > C->tcut)) continue;
-                uint32_t slot = 2u * (uint32_t)C->i + (uint32_t)C->side;
-                if ((slot >> 2) != curblk) {
-                    curblk = slot >> 2;
-                    or_rng_block(seed, stream, id, cycle, curblk, ub);
-                }
-                double lu = log(ub[slot & 3u]);
-                ntri += 1;
-                double invc = C->invc, floor = -INFINITY;
-                /* learned cells apply to the incoming partons' channels (emitter slot 0 or 1) */
-                int lch = learned && (C->type == T_IF || C->type == T_II) && C->i < 2, k = 0;
-                if (lch) {
-                    k = cell_of(S, lnTch);
-                    invc = 1.0 / learned_c(S, C, Lt, k);
-                    floor = S->cell_edge[k];
-                }
-                double key;
-                if (!C->heavy) key = lnTch + lu * invc;
-                else key = log(C->m2 + (Tch - C->m2) * exp(lu * invc));
-                int isnull = 0;
-                if (lch && key < floor && floor > C->lntcut) { key = floor; isnull = 1; }
-                if (key < C->lntcut) continue;
-                if (key > best) { best = key; win = c; wnull = isnull; wcell = k; }
-            }
-            if (win < 0) break;
-            if (wnull) {
-                /* no channel emits above the edge: continue from it */
-                T = exp(best);
-                lnT = best;
-                cycle += 1;
-                if (retain)
-                    key[win] = draw_trial(S, &ch[win], T, lnT, seed, stream, id, cycle, learned, Lt, &ntri,
-                                          &knull[win], &kcell[win]);
-                continue;
-            }
-            double t = exp(best);
-            const chan_t* C = &ch[win];
-            const int lch = learned && (C->type == T_IF || C->type == T_II) && C->i < 2;
-            double u[4];
-            or_rng_block(seed, stream, id, cycle, 0xFFFFFFFFu, u);
-            /* splitting family and flavour in proportion to their overestimates */
-            double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
-            double ctot = lch ? learned_c(S, C, Lt, wcell) : C->c;
-            double target = u[0] * ctot, cum = 0.0;
-            int sel = -1;
-            for (int m = 0; m < C->nterm; ++m) {
-                cum += lch ? af * lrn(Lt, C->term[m].ent, C->ebin, wcell) * C->term[m].mul *
-                                 shape_int(C->term[m].shape, C)
-                           : C->term[m].c;
-                if (target < cum) { sel = m; break; }
-            }
-            if (sel < 0)
-                for (int m = C->nterm - 1; m >= 0; --m)
-                    if (C->term[m].c > 0.0) { sel = m; break; }
-            term_t tsel = C->term[sel];
-            if (lch) tsel.coefR = lrn(Lt, tsel.ent, C->ebin, wcell) * tsel.mul;
-            const term_t* tm = &tsel;
-            double I = shape_int(tm->shape, C);
-            double z, omz;
-            shape_sample(tm->shape, C, I, u[1], &z, &omz);
-            double phi = 2.0 * OR_PI * u[2];
-            veto_t v = weight(S, ev, C, tm, t, z, omz);
-            if (L && (C->type == T_IF || C->type == T_II) && !C->mec && v.ok && v.wn > 0.0)
-                log_trial(L, t, C->eta, z, tm->ent, v.wn);
-            if (lch && v.ok && v.w > 1.0) return 1; /* the learned bound failed */
-            if (v.ok && v.w > 1.0) { nviol += 1; flags |= OR_F_VIOL; }
-            int emitted = 0, e_i = C->i, e_k = C->k, e_all = C->type == T_II;
-            if (v.ok && u[3] < v.w) {
-                if (ev->n + 1 > M) { flags |= OR_F_OVERFLOW; break; }
-                emitted = 1;
-                if (retain) {
-                    /* the pending trial and spectator of every entry 2i+side */
-                    for (int q = 0; q < 2 * ev->n; ++q) okspec[q] = -1;
-                    for (int c = 0; c < nch; ++c) {
-                        int q = 2 * ch[c].i + ch[c].side;
-                        okspec[q] = ch[c].k;
-                        okey[q] = key[c];
-                        onull[q] = knull[c];
-                        ocell[q] = kcell[c];
-                    }
-                }
-                emit(S, ev, C, tm, z, omz, &v, phi);
-                nacc += 1;
-                if (t1 == 0.0) t1 = t;
-                int bad = 0;
-                for (int q = 0; q < ev->n; ++q) bad |= !finite4(ev->p[q]);
-                if (bad) { flags |= OR_F_NAN; cycle += 1; break; }
-                if (build_channels(S, ev, ch, &nch) < 0) { flags |= OR_F_COLOUR; cycle += 1; break; }
-            }
-            T = t;
-            lnT = best;
-            cycle += 1;
-            if (retain && !emitted) {
-                /* after a veto only the winner draws again */
-                key[win] = draw_trial(S, &ch[win], T, lnT, seed, stream, id, cycle, learned, Lt, &ntri,
-                                      &knull[win], &kcell[win]);
-            } else if (retain) {
-                /* after an emission a channel keeps its trial when its process
-                 * is unchanged: same spectator, and neither its emitter nor its
-                 * spectator is the emitter, the spectator or the new parton of
-                 * the emission, whose recoil is local (an initial-initial
-                 * emission boosts every final-state parton, so then every
-                 * channel draws again) */
-                const int j = ev->n - 1;
-                for (int c = 0; c < nch; ++c) {
-                    const chan_t* D = &ch[c];
-                    const int q = 2 * D->i + D->side;
-                    const int kept = !e_all && q < 2 * j && okspec[q] == D->k && D->i != e_i && D->i != e_k &&
-                                     D->i != j && D->k != e_i && D->k != e_k && D->k != j;
-                    if (kept) {
-                        key[c] = okey[q];
-                        knull[c] = onull[q];
-                        kcell[c] = ocell[q];
-                    } else {
-                        key[c] = draw_trial(S, D, T, lnT, seed, stream, id, cycle, learned, Lt, &ntri, &knull[c],
-                                            &kcell[c]);
-                    }
-                }
-            }
-        }
-        ncyc = cycle;
-    }
-    out->id[e_out] = id;
-    out->w[e_out] = in->w[e_in];
-    out->t_start[e_out] = in->t_start[e_in];
-    out->n[e_out] = ev->n;
-    if (out->flags) out->flags[e_out] = flags;
-    for (int q = 0; q < ev->n && q < out->max_slots; ++q) {
-        int64_t o = (int64_t)q * co + e_out;
-        out->E[o] = ev->p[q][0]; out->px[o] = ev->p[q][1];
-        out->py[o] = ev->p[q][2]; out->pz[o] = ev->p[q][3];
-        out->pid[o] = ev->pid[q]; out->col[o] = ev->col[q]; out->acol[o] = ev->acol[q];
-        out->status[o] = (int8_t)ev->st[q];
-    }
-    if (out->n_cycles) out->n_cycles[e_out] = ncyc;
-    if (out->n_trials) out->n_trials[e_out] = ntri;
-    if (out->n_accept) out->n_accept[e_out] = nacc;
-    if (out->n_viol) out->n_viol[e_out] = nviol;
-    if (out->t1) out->t1[e_out] = t1;
-    return 0;
-}
+enum { FORM_MAX_VETO = 0, FORM_RETAINED = 1, FORM_GEN_SELECT = 2, FORM_VETO_MAX = 3 };
 
 typedef struct {
     const or_state* S;
@@ -975,22 +1075,35 @@ typedef struct {
     logsink_t* L;
     int mode;
     const double* Lt;
-    int retain, gs, vm;
+    int form;
 } job_t;
 
 static void* run_job(void* arg) {
     job_t* J = (job_t*)arg;
-    ev_t* ev = (ev_t*)malloc(sizeof(ev_t));
-    chan_t* ch = (chan_t*)malloc(sizeof(chan_t) * OR_MAXCH);
+    sh_t r;
+    memset(&r, 0, sizeof(r));
+    r.S = J->S;
+    r.ev = (ev_t*)malloc(sizeof(ev_t));
+    r.ch = (chan_t*)malloc(sizeof(chan_t) * OR_MAXCH);
+    r.M = J->out->max_slots < OR_MAXM ? J->out->max_slots : OR_MAXM;
+    r.seed = J->seed;
+    r.stream = J->mode == OR_MODE_LEARNED ? 1u : 0u;
+    r.Lt = J->Lt;
+    r.L = J->L;
     for (int64_t e = J->lo; e < J->hi; ++e) {
-        if (J->mode == OR_MODE_LEARNED &&
-            shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, NULL, OR_MODE_LEARNED, J->Lt, J->retain, 0, 0) == 0)
-            continue;
-        shower_one(J->S, J->in, e, J->seed, J->out, e, ev, ch, J->L, OR_MODE_PLAIN, NULL, J->retain, J->gs, J->vm);
-        if (J->mode == OR_MODE_LEARNED && J->out->flags) J->out->flags[e] |= OR_F_FALLBACK;
+        r.lrn = J->mode == OR_MODE_LEARNED;
+        if (sh_load(&r, J->in, e) == 0) {
+            switch (J->form) {
+            case FORM_RETAINED: run_retained(&r); break;
+            case FORM_GEN_SELECT: run_gen_select(&r); break;
+            case FORM_VETO_MAX: run_veto_max(&r); break;
+            default: run_max_veto(&r); break;
+            }
+        }
+        sh_store(&r, J->in, e, J->out, e);
     }
-    free(ev);
-    free(ch);
+    free(r.ev);
+    free(r.ch);
     return NULL;
 }
 
@@ -1019,9 +1132,10 @@ int or_shower_ex(const or_state* S, const or_events* in, int64_t n, uint64_t see
         jobs[k].L = L;
         jobs[k].mode = mode;
         jobs[k].Lt = mode == OR_MODE_LEARNED ? opts->learned : NULL;
-        jobs[k].retain = opts ? opts->retain != 0 : 0;
-        jobs[k].gs = opts ? opts->gen_select != 0 : 0;
-        jobs[k].vm = opts ? opts->veto_max != 0 : 0;
+        jobs[k].form = !opts ? FORM_MAX_VETO
+                       : opts->retain ? FORM_RETAINED
+                       : opts->gen_select ? FORM_GEN_SELECT
+                       : opts->veto_max ? FORM_VETO_MAX : FORM_MAX_VETO;
     }
     if (nthreads == 1) run_job(&jobs[0]);
     else {
