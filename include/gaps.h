@@ -49,7 +49,10 @@ typedef enum {
 #define GAPS_F_OVERFLOW 1u  /* an accepted emission would exceed max_slots */
 #define GAPS_F_COLOUR 2u    /* a colour line has no partner */
 #define GAPS_F_NAN 4u       /* a non-finite momentum appeared */
-#define GAPS_F_FALLBACK 8u  /* learned mode: bound violated, event re-run plain */
+#define GAPS_F_FALLBACK 8u  /* learned mode: a weight exceeded the learned bound;
+                               the weighted veto's factor is in the event's
+                               weight and the event continued on the analytic
+                               overestimate */
 #define GAPS_F_VIOL 16u     /* a veto weight exceeded one (counted in n_viol) */
 #define GAPS_F_HARDFAIL 32u /* the hard-event sampler found no event */
 #define GAPS_F_HEVENT 64u   /* NLO H (real-emission) event */
@@ -138,7 +141,8 @@ typedef struct {
 #define GAPS_ST_VIOL 3        /* weights above one */
 #define GAPS_ST_LANE_ITERS 4  /* wave iterations x 64 (lane slots offered) */
 #define GAPS_ST_LANE_ACTIVE 5 /* lanes doing work in those iterations */
-#define GAPS_ST_FALLBACK 6    /* learned-mode events re-run plain */
+#define GAPS_ST_FALLBACK 6    /* learned-mode events whose bound failed (weighted
+                                 veto, then the analytic overestimate) */
 #define GAPS_ST_NULL 7        /* learned-mode cell boundary (null) winners */
 #define GAPS_NSTATS 8
 
@@ -288,9 +292,14 @@ gaps_status gaps_graph_destroy(gaps_graph g);
  * over the PDF grid's ln Q^2 range.  A channel draws against its cell's
  * constant; a trial below the cell is a null at the cell edge (the evolution
  * continues from there, exact by the factorisation of the no-emission
- * probability); every real trial checks its weight against the bound and an
- * event whose weight exceeds it is showered again in plain mode
- * (GAPS_F_FALLBACK), so no violation is ever used.  Random-number stream 1.
+ * probability); every real trial checks its weight w against the bound.  A
+ * trial with w > 1 is handled by the weighted veto algorithm (Lonnblad, Eur.
+ * Phys. J. C 73 (2013) 2350): accepted with probability w/(2w - 1), the event
+ * weight multiplied by 2w - 1 on acceptance and by -(2w - 1) on rejection, so
+ * the emission density stays exactly the true one; the event then continues on
+ * the analytic overestimate (every channel set up and drawn again), flagged
+ * GAPS_F_FALLBACK.  Such violations are not counted in n_viol (which counts
+ * weights above the analytic bound).  Random-number stream 1.
  *
  * The bound comes from a network 4 -> 64 -> 64 -> 1 (ReLU) on features
  * ((ln t - 10)/10, (ln eta + 7)/7, 2z - 1, (entry - 40)/32) predicting an upper
@@ -373,7 +382,11 @@ typedef struct {
 gaps_status gaps_mlp_train(gaps_ctx ctx, const float* x, const float* y, int64_t n, const gaps_train_params* p,
                            float* loss, hipStream_t stream);
 /* Calibration margins from held-out device rows (x, y, ent): per entry the
- * largest y - f plus 2^-6, or +inf below 2000 rows.  Asynchronous. */
+ * largest y - f plus 2^-6, or +inf below 2000 rows.  Asynchronous (no stream
+ * synchronisation): the network's outputs are staged through the context's
+ * tabulation buffers (24 MB, allocated by the first call of either function
+ * on a context), in chunks, in stream order.  GAPS_ENOMEM if they cannot be
+ * allocated. */
 gaps_status gaps_mlp_calibrate(gaps_ctx ctx, const float* x, const float* y, const int32_t* ent, int64_t n,
                                hipStream_t stream);
 /* Margins from / to HOST memory (64 doubles, entries 8..71; +inf: analytic). */
@@ -390,9 +403,19 @@ gaps_status gaps_learned_table(gaps_ctx ctx, double* host_out);
  * enable LEARNED mode.  Synchronous. */
 gaps_status gaps_learned_set_table(gaps_ctx ctx, const double* host_table);
 
-/* Per-event observables (section 4.1): obs is device [n][12], layout as in
- * the oracle's observables (Z pT, y, phi, phi*, jets; thrust and Durham y for
- * e+e-). */
+/* Per-event observables (section 4.1): obs is device [n][12], one row per
+ * event.  For pp processes the columns are
+ *   0 Z pT (the lepton pair's transverse momentum), 1 Z rapidity, 2 Z azimuth
+ *   (0 when the pair has no transverse recoil), 3 phi*, 4 number of anti-kT
+ *   jets (R = 0.4, E-scheme, pT > 5 GeV, |eta| < 5), 5 leading-jet pT
+ *   (|eta| < 5), 6 leading-jet pseudorapidity (pT > 5 GeV), 7 second-jet pT
+ *   (|eta| < 5), 8 Delta R of the two leading jets (both cuts; -1 with fewer
+ *   than two), 9 number of final-state partons, 10 largest component of the
+ *   final minus the initial total four-momentum (momentum conservation), 11
+ *   unused (0);
+ * for e+e- (process 0): 0 1 - thrust, 1-4 Durham y23, y34, y45, y56 (E
+ *   scheme), 9 number of final-state partons, 10 momentum imbalance as above,
+ *   the others 0. */
 gaps_status gaps_observables(gaps_ctx ctx, const gaps_events* ev, int64_t n, double* obs,
                              hipStream_t stream);
 

@@ -31,11 +31,39 @@ struct ScratchMem {
   gaps::Scratch S{};
 };
 
-gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
+// bytes of per-lane working storage for events of `slots` slots
+size_t scratch_per_lane(int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
-  size_t per_lane = (size_t)slots * sizeof(gaps::Part) +
-                    (size_t)nch * (sizeof(gaps::Trial) + sizeof(gaps::Win));
-  size_t need = per_lane * (size_t)lanes + 256 * 32 + 64;
+  return (size_t)slots * sizeof(gaps::Part) + (size_t)nch * (sizeof(gaps::Trial) + sizeof(gaps::Win)) +
+         sizeof(double);
+}
+
+// bytes the working storage of `lanes` lanes needs, alignment included
+size_t scratch_bytes(int64_t lanes, int slots) { return scratch_per_lane(slots) * (size_t)lanes + 256 * 32 + 64; }
+
+// Lay out the working storage of `lanes` lanes over [base, base + bytes).
+gaps_status scratch_layout(char* base, size_t bytes, int64_t lanes, int slots, gaps::Scratch& S) {
+  const int nch = (2 * slots + 3) & ~3;
+  char* p = base;
+  auto take = [&](size_t n) {
+    char* r = p;
+    p += (n + 255) & ~(size_t)255;
+    return (void*)r;
+  };
+  S.lanes = lanes;
+  S.max_slots = slots;
+  const size_t ps = (size_t)slots * lanes, cs = (size_t)nch * lanes;
+  S.part = (gaps::Part*)take(ps * sizeof(gaps::Part));
+  S.nch = nch;
+  S.ctr = (gaps::Trial*)take(cs * sizeof(gaps::Trial));
+  S.cwin = (gaps::Win*)take(cs * sizeof(gaps::Win));
+  S.wfac = (double*)take((size_t)lanes * sizeof(double));
+  S.queue = (unsigned long long*)take(64);
+  return (size_t)(p - base) > bytes ? GAPS_ECAPACITY : GAPS_OK;
+}
+
+gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
+  const size_t need = scratch_bytes(lanes, slots);
   if (need > m.bytes || m.S.lanes != lanes || m.S.max_slots != slots) {
     if (need > m.bytes) {
       if (m.mem) (void)hipFree(m.mem);
@@ -44,22 +72,7 @@ gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
       if (hipMalloc(&m.mem, need) != hipSuccess) return GAPS_ENOMEM;
       m.bytes = need;
     }
-    char* p = (char*)m.mem;
-    auto take = [&](size_t bytes) {
-      char* r = p;
-      p += (bytes + 255) & ~(size_t)255;
-      return (void*)r;
-    };
-    gaps::Scratch& S = m.S;
-    S.lanes = lanes;
-    S.max_slots = slots;
-    size_t ps = (size_t)slots * lanes, cs = (size_t)nch * lanes;
-    S.part = (gaps::Part*)take(ps * sizeof(gaps::Part));
-    S.nch = nch;
-    S.ctr = (gaps::Trial*)take(cs * sizeof(gaps::Trial));
-    S.cwin = (gaps::Win*)take(cs * sizeof(gaps::Win));
-    S.queue = (unsigned long long*)take(64);
-    if ((size_t)(p - (char*)m.mem) > m.bytes) return GAPS_ENOMEM;
+    if (scratch_layout((char*)m.mem, m.bytes, lanes, slots, m.S) != GAPS_OK) return GAPS_ENOMEM;
   }
   return GAPS_OK;
 }
@@ -640,23 +653,37 @@ gaps_status gaps_mlp_train(gaps_ctx c, const float* x, const float* y, int64_t n
   return GAPS_OK;
 }
 
+// the probe buffers of the tabulation (allocated once per context), also the
+// staging of the network's outputs for the calibration's residuals
+static gaps_status ensure_probes(gaps_ctx c) {
+  const int64_t np = gaps::kMlpProbeRows;
+  if (!c->probe_x) {
+    if (hipMalloc((void**)&c->probe_x, (size_t)np * 16) != hipSuccess) return GAPS_ENOMEM;
+    if (hipMalloc((void**)&c->probe_f, (size_t)np * 4) != hipSuccess) return GAPS_ENOMEM;
+  }
+  return GAPS_OK;
+}
+
 gaps_status gaps_mlp_calibrate(gaps_ctx c, const float* x, const float* y, const int32_t* ent, int64_t n,
                                hipStream_t stream) {
   if (!c || n <= 0 || !x || !y || !ent) return GAPS_EINVAL;
   if (!c->mlp_mem) return GAPS_ESTATE;
-  float* f = nullptr;
-  if (hipMalloc((void**)&f, (size_t)n * 4) != hipSuccess) return GAPS_ENOMEM;
+  const gaps_status st = ensure_probes(c);
+  if (st != GAPS_OK) return st;
   hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->maxbits, (int64_t)64, 0ull);
   hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->count, (int64_t)64, 0ull);
-  hipLaunchKernelGGL(gaps::k_mlp_fwd, dim3(mlp_grid(n, 4096)), dim3(256), 0, stream, c->wb, x, n, f);
-  hipLaunchKernelGGL(gaps::k_mlp_resid, dim3(grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024), dim3(256), 0, stream,
-                     f, y, ent, n, c->maxbits, c->count);
+  // the rows in chunks that fit the probe output buffer, in stream order
+  const int64_t chunk = gaps::kMlpProbeRows;
+  for (int64_t off = 0; off < n; off += chunk) {
+    const int64_t m = n - off < chunk ? n - off : chunk;
+    hipLaunchKernelGGL(gaps::k_mlp_fwd, dim3(mlp_grid(m, 4096)), dim3(256), 0, stream, c->wb, x + 4 * off, m,
+                       c->probe_f);
+    hipLaunchKernelGGL(gaps::k_mlp_resid, dim3(grid_for(m, 256) < 1024 ? grid_for(m, 256) : 1024), dim3(256), 0,
+                       stream, c->probe_f, y + off, ent + off, m, c->maxbits, c->count);
+  }
   hipLaunchKernelGGL(gaps::k_mlp_delta, dim3(1), dim3(64), 0, stream, c->maxbits, c->count, 2000ll, 0.015625,
                      c->delta);
-  hipError_t e = hipGetLastError();
-  hipError_t e2 = hipStreamSynchronize(stream);
-  (void)hipFree(f);
-  if (e != hipSuccess || e2 != hipSuccess) return GAPS_EHIP;
+  GAPS_HIP(hipGetLastError());
   return GAPS_OK;
 }
 
@@ -680,10 +707,8 @@ gaps_status gaps_mlp_tabulate(gaps_ctx c, hipStream_t stream) {
   if (!c) return GAPS_EINVAL;
   if (!c->mlp_mem) return GAPS_ESTATE;
   const int64_t np = gaps::kMlpProbeRows;
-  if (!c->probe_x) {
-    if (hipMalloc((void**)&c->probe_x, (size_t)np * 16) != hipSuccess) return GAPS_ENOMEM;
-    if (hipMalloc((void**)&c->probe_f, (size_t)np * 4) != hipSuccess) return GAPS_ENOMEM;
-  }
+  const gaps_status st = ensure_probes(c);
+  if (st != GAPS_OK) return st;
   hipLaunchKernelGGL(gaps::k_mlp_probes, dim3(grid_for(np, 256)), dim3(256), 0, stream, c->C, c->probe_x);
   hipLaunchKernelGGL(gaps::k_mlp_fwd, dim3(mlp_grid(np, 4096)), dim3(256), 0, stream, c->wb, c->probe_x, np,
                      c->probe_f);

@@ -41,6 +41,10 @@ struct Scratch {
   int nch;             // entries per event: 2 max_slots rounded up to a multiple of 4
   struct Trial* ctr;
   struct Win* cwin;
+  // weight factor of the event in each state slot, written by the weighted
+  // veto of a violated learned bound (valid while the event's flags carry
+  // fFallback)
+  double* wfac;
   unsigned long long* queue;  // work-queue counters
 };
 

@@ -61,7 +61,7 @@ struct LaneState {
   double T, lnT, t1;
   uint32_t cycle, ntri, nacc, nviol, flags;
   int32_t n, maxtag;
-  uint32_t bits;  // loaded | stop << 1 | pending << 2 | rebuild << 3 | em_all << 4
+  uint32_t bits;  // loaded | stop << 1 | rebuild << 3 | em_all << 4
   int32_t emik;   // emitter | spectator << 8 of the emission awaiting its channel rebuild
 };
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
@@ -182,7 +182,8 @@ struct DrawState {
   double T, lnT;
   int64_t id;
   uint32_t cycle;
-  bool lrn;
+  bool lrn;       // learned cells (else the analytic constants)
+  uint32_t strm;  // random-number stream of the event
   uint64_t seed;
   bool mec;  // the event's next emission is corrected to the real matrix element
 };
@@ -198,11 +199,12 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   const int64_t slot = __shfl(myslot, L);
   double TL = 0.0, lnTL = 0.0;
   int64_t idL = 0;
-  uint32_t cyL = 0;
+  uint32_t cyL = 0, stL = 0;
   bool lrnL = false;
   if constexpr (DRAW) {
     TL = __shfl(D.T, L); lnTL = __shfl(D.lnT, L); idL = __shfl(D.id, L);
     cyL = (uint32_t)__shfl((int)D.cycle, L); lrnL = __shfl((int)D.lrn, L) != 0;
+    stL = (uint32_t)__shfl((int)D.strm, L);
   }
   const bool mecL = __shfl((int)D.mec, L) != 0;
   if (!valid) return;
@@ -224,7 +226,7 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   W.S.cwin[oc] = wd;
   if constexpr (DRAW) {
     double ub[4];
-    rng4(D.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)c >> 2, ub);
+    rng4(D.seed, stL, idL, cyL, (uint32_t)c >> 2, ub);
     double key;
     if (draw_entry(W.C, W.S, slot, c, pack(ch), ch.tlim, ch.lntlim, ch.invc, pick4(ub, c & 3), TL, lnTL, lrnL,
                    key))
@@ -451,8 +453,10 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   const bool log_mode = A.mode == GAPS_MODE_LOG;
 
   bool active = false, exhausted = false, loaded = false, stop = false;
-  bool lrn = false;      // this event draws against the learned bound (stream 1)
-  bool pending = false;  // reload event (b, e) in plain mode: its learned bound failed
+  // this event draws its initial-state channels against the learned bound
+  // (LEARNED mode until the bound fails; the event keeps random-number stream 1
+  // after that, marked by fFallback in its flags)
+  bool lrn = false;
   int64_t e = 0, id = 0;
   int b = 0;
   double T = 0.0, lnT = 0.0, t1 = 0.0;
@@ -525,7 +529,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       const int nin = in.n[e];
       const bool fits = loaded;
       out.id[e] = id;
-      out.w[e] = in.w[e];
+      // a violated learned bound leaves the weighted veto's factor on the event
+      out.w[e] = (flags & fFallback) ? in.w[e] * S.wfac[slot] : in.w[e];
       out.t_start[e] = in.t_start[e];
       if (fits) {
         out.n[e] = n;
@@ -585,8 +590,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     }
     // ---- tail mode: block bookkeeping, termination and compaction
     if (tail && (it - it_tail) % KC == 0u) {
-      // live lanes: showering, or waiting to reload their event in plain mode
-      const bool live = active || pending;
+      const bool live = active;
       const unsigned long long a0 = __ballot(live);
       if (lane == 0) s_cnt[wid] = __popcll(a0);
       __syncthreads();
@@ -605,14 +609,12 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           X.e = e; X.id = id; X.slot = slot; X.b = b; X.lrn = lrn; X.T = T; X.lnT = lnT; X.t1 = t1;
           X.cycle = cycle; X.ntri = ntri; X.nacc = nacc; X.nviol = nviol; X.flags = flags;
           X.n = n; X.maxtag = maxtag;
-          X.bits = (uint32_t)loaded | ((uint32_t)stop << 1) | ((uint32_t)pending << 2) | ((uint32_t)rebuild << 3) |
-                   ((uint32_t)em_all << 4);
+          X.bits = (uint32_t)loaded | ((uint32_t)stop << 1) | ((uint32_t)rebuild << 3) | ((uint32_t)em_all << 4);
           X.emik = (em_i & 0xFF) | ((em_k & 0xFF) << 8);
         }
         __syncthreads();
         const bool got = (int)threadIdx.x < total;
         active = false;
-        pending = false;
         rebuild = false;
         sec_ok = false;
         if (got) {
@@ -620,45 +622,35 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           e = X.e; id = X.id; slot = X.slot; b = X.b; lrn = X.lrn != 0; T = X.T; lnT = X.lnT; t1 = X.t1;
           cycle = X.cycle; ntri = X.ntri; nacc = X.nacc; nviol = X.nviol; flags = X.flags;
           n = X.n; maxtag = X.maxtag;
-          loaded = (X.bits & 1u) != 0; stop = (X.bits & 2u) != 0; pending = (X.bits & 4u) != 0;
+          loaded = (X.bits & 1u) != 0; stop = (X.bits & 2u) != 0;
           rebuild = (X.bits & 8u) != 0; em_all = (X.bits & 16u) != 0;
           em_i = X.emik & 0xFF; em_k = (X.emik >> 8) & 0xFF;
-          active = !pending;
+          active = true;
           R = rec_of(S, slot);
         }
       }
       __syncthreads();
     }
-    // ---- refill finished lanes from the work queue (one atomic per wave);
-    // lanes whose learned bound failed reload their own event in plain mode
+    // ---- refill finished lanes from the work queue (one atomic per wave)
     unsigned long long act = __ballot(active);
-    const unsigned long long pend = __ballot(pending);
     bool fresh = false;
-    if (pend || (!exhausted && (since >= K || act == 0ull))) {
-      if (pending) {
-        pending = false;
-        active = true;
-        fresh = load(false);
-        flags |= fFallback;
-      }
-      if (!exhausted && (since >= K || act == 0ull)) {
-        const unsigned long long idle = ~(act | pend);
-        const int cnt = __popcll(idle);
-        unsigned long long base = 0ull;
-        if (lane == 0) base = atomicAdd(S.queue, (unsigned long long)cnt);
-        base = __shfl(base, 0);
-        if (base + (unsigned long long)cnt >= (unsigned long long)A.n) exhausted = true;
-        if (!active) {
-          const unsigned long long ev = base + (unsigned long long)__popcll(idle & lanemask_lt(lane));
-          if (ev < (unsigned long long)A.n) {
-            b = A.nbatch > 0 ? batch_of(A, (int64_t)ev) : 0;
-            e = (int64_t)ev - (A.nbatch > 0 ? A.prefix[b] : 0);
-            active = true;
-            fresh = load(learned_mode);
-          }
+    if (!exhausted && (since >= K || act == 0ull)) {
+      const unsigned long long idle = ~act;
+      const int cnt = __popcll(idle);
+      unsigned long long base = 0ull;
+      if (lane == 0) base = atomicAdd(S.queue, (unsigned long long)cnt);
+      base = __shfl(base, 0);
+      if (base + (unsigned long long)cnt >= (unsigned long long)A.n) exhausted = true;
+      if (!active) {
+        const unsigned long long ev = base + (unsigned long long)__popcll(idle & lanemask_lt(lane));
+        if (ev < (unsigned long long)A.n) {
+          b = A.nbatch > 0 ? batch_of(A, (int64_t)ev) : 0;
+          e = (int64_t)ev - (A.nbatch > 0 ? A.prefix[b] : 0);
+          active = true;
+          fresh = load(learned_mode);
         }
-        since = 0;
       }
+      since = 0;
       act = __ballot(active);
       // the refilled events' partons into their records, one parton per lane,
       // and the largest colour tag of each event
@@ -717,7 +709,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     {
       const unsigned long long bm = __ballot(built);
       if (bm) {
-        const DrawState D{T, lnT, id, cycle, lrn, A.seed, (flags & fMEC) != 0u && t1 == 0.0};
+        const DrawState D{T, lnT, id, cycle, lrn, (lrn || (flags & fFallback)) ? 1u : 0u, A.seed,
+                          (flags & fMEC) != 0u && t1 == 0.0};
         uint32_t drawn = 0;
         uint32_t f =
             coop_build<RETAIN>(W, s_build[wid], bm, n, slot, fresh, fresh || em_all, em_i, em_k, D, drawn);
@@ -759,7 +752,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     // entry order with the same rule, which gives the same winner as one pass
     // over all entries.
     const bool trialing = active && !done && !rebuild;  // a deferred rebuild waits
-    const uint32_t strm = lrn ? 1u : 0u;
+    const uint32_t strm = (lrn || (flags & fFallback)) ? 1u : 0u;
     int win = -1, wcell = 0;
     bool wexact = false, wnull = false;
     double wlo = 0.0, whi = 0.0, wkey = RETAIN ? -INFINITY : 0.0, wu = 0.5, wlnT = 0.0, winv = 0.0;
@@ -873,6 +866,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         const double TL = __shfl(T, L), lnTL = __shfl(lnT, L);
         const int nL = __shfl(n, L), fL = __shfl(first, L);
         const bool lrnL = __shfl((int)lrn, L) != 0;
+        const uint32_t stL = (uint32_t)__shfl((int)strm, L);
         // this lane's group: its winner (gw < 0: none) and trial count
         int gw = -1, gcell = 0;
         bool gexact = false, gnull = false;
@@ -892,7 +886,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           }
           if ((inf[0] | inf[1] | inf[2] | inf[3]) & 1u) {
             double ub[4];
-            rng4(A.seed, lrnL ? 1u : 0u, idL, cyL, (uint32_t)c0 >> 2, ub);
+            rng4(A.seed, stL, idL, cyL, (uint32_t)c0 >> 2, ub);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const int c = c0 + j;
@@ -1050,42 +1044,57 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             }
           }
         }
+        // A weight above the learned bound goes through the weighted veto
+        // (Lonnblad, Eur. Phys. J. C 73 (2013) 2350): accepted with probability
+        // w/(2w - 1), the event weight multiplied by 2w - 1 on acceptance and by
+        // -(2w - 1) on rejection, which keeps the emission density exact; the
+        // event then continues on the analytic overestimate (every channel set
+        // up and drawn again by a full rebuild), so it meets no further learned
+        // bound.  A weight above the analytic bound is counted and accepted.
+        bool acc;
         if (lch && v.ok && v.w > 1.0) {
-          // the learned bound failed: shower this event again in plain mode
-          pending = true;
-          active = false;
+          const double g = 2.0 * v.w - 1.0;
+          acc = u[3] < v.w / g;
+          S.wfac[slot] = acc ? g : -g;
+          flags |= fFallback;
+          lrn = false;
           fellback = true;
         } else {
           if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
-          if (v.ok && u[3] < v.w) {
-            if (n + 1 > M) {
-              flags |= fOverflow;
-              done = true;
-            } else {
-              // the emission is applied by the next channel build, together
-              // with the other lanes' (one pass of the emission code for all)
-              pe_code = (uint32_t)win | ((uint32_t)tm.kern << 8) | ((uint32_t)(tm.flav & 0xFF) << 16);
-              pe_z = z;
-              pe_omz = omz;
-              pe_phi = phi;
-              map_vars(ch.type, v, pe_a1, pe_a2);
-              pe = true;
-              // an initial-initial recoil boosts every final-state momentum
-              rebuild = true;
-              em_all = ch.type == kII;
-              em_i = ch.i;
-              em_k = ch.k;
-              nacc += 1;
-              if (t1 == 0.0) t1 = t;
-            }
+          acc = v.ok && u[3] < v.w;
+        }
+        if (acc) {
+          if (n + 1 > M) {
+            flags |= fOverflow;
+            done = true;
+          } else {
+            // the emission is applied by the next channel build, together
+            // with the other lanes' (one pass of the emission code for all)
+            pe_code = (uint32_t)win | ((uint32_t)tm.kern << 8) | ((uint32_t)(tm.flav & 0xFF) << 16);
+            pe_z = z;
+            pe_omz = omz;
+            pe_phi = phi;
+            map_vars(ch.type, v, pe_a1, pe_a2);
+            pe = true;
+            // an initial-initial recoil boosts every final-state momentum
+            rebuild = true;
+            em_all = ch.type == kII;
+            em_i = ch.i;
+            em_k = ch.k;
+            nacc += 1;
+            if (t1 == 0.0) t1 = t;
           }
-          if (!done) {
-            T = t;
-            lnT = best;
-            cycle += 1;
-            // retained trials: after a veto only the winner draws again
-            rdw = !rebuild;
-          }
+        }
+        if (fellback) {
+          rebuild = true;
+          em_all = true;
+        }
+        if (!done) {
+          T = t;
+          lnT = best;
+          cycle += 1;
+          // retained trials: after a veto only the winner draws again
+          rdw = !rebuild;
         }
       }
     }

@@ -68,7 +68,7 @@ def test_learned(G, oracles, retain):
 def test_full_size_streamed_sampled(G, oracles):
     """Two batches of 10^6 events streamed through one graph-captured
     persistent launch with retained trials (the benchmark's batch size and
-    launch); 300 sampled events against the oracle one by one."""
+    launch); 2000 sampled events against the oracle one by one."""
     import torch
     from paper_2511_19633_amd import binding
     O = oracles["dynlo"]
@@ -84,17 +84,11 @@ def test_full_size_streamed_sampled(G, oracles):
         stream.synchronize()
     finally:
         graph.close()
-    ids = np.sort(np.random.default_rng(13).choice(2 * NPB, size=300, replace=False))
-    g = records.Events(len(ids), workloads.MAX_SLOTS)
+    from tests.test_gpu_fullsize import _gather
+    ids = np.sort(np.random.default_rng(13).choice(2 * NPB, size=2000, replace=False))
+    g = _gather(outs, ids, NPB)
     o_in = records.Events(len(ids), 8)
     for s, i in enumerate(ids):
-        d, j = outs[int(i) // NPB], int(i) % NPB
-        for name in g.fields():
-            t, a = getattr(d, name), getattr(g, name)
-            if a.ndim == 1:
-                a[s] = t[j].item()
-            else:
-                a[:, s] = t[:, j].cpu().numpy()
         one = O.hard_events(int(i), 1, SEED, max_slots=8)
         for name in o_in.fields():
             a = getattr(o_in, name)

@@ -2,7 +2,8 @@
 10^6 NLO events (ids 0 .. 10^7 - 1, seed 1) streamed through one graph-captured
 persistent launch with retained trials, plain and learned; sampled events
 across all batches against the oracle, one by one (integer and colour data
-bit-exact, >= 99.9 % identical, momenta within 1e-9 of the event's scale)."""
+bit-exact, >= 99.9 % identical, weights within 1e-9, every parton's momentum
+within 1e-9 of its own energy)."""
 import sys
 
 import numpy as np
@@ -13,7 +14,9 @@ from tests.test_gpu_parity import SCALE, compare_events
 
 pytestmark = pytest.mark.gpu
 
-NB, NPB, SEED, NSAMPLE = 10, 1_000_000, 1, 600
+# 2000 sampled events: at the 99.9 % bar up to two may differ (300 would
+# allow none, a resolution of 0.33 %)
+NB, NPB, SEED, NSAMPLE = 10, 1_000_000, 1, 2000
 
 
 def say(*a):
@@ -46,15 +49,16 @@ def _run(G, ins, outs, mode):
         graph.close()
 
 
-def _gather(outs, ids):
-    """The sampled events of the device outputs, as one host record."""
+def _gather(outs, ids, npb=NPB):
+    """The sampled events (ids over the concatenated batches of npb events)
+    of the device outputs, as one host record."""
     import torch
     h = records.Events(len(ids), workloads.MAX_SLOTS)
-    for k in range(NB):
-        sel = np.nonzero(ids // NPB == k)[0]
+    for k in range(len(outs)):
+        sel = np.nonzero(ids // npb == k)[0]
         if not len(sel):
             continue
-        idx = torch.from_numpy((ids[sel] % NPB).astype(np.int64)).cuda()
+        idx = torch.from_numpy((ids[sel] % npb).astype(np.int64)).cuda()
         d = outs[k]
         for name in d.fields():
             t = getattr(d, name)

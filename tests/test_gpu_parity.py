@@ -2,10 +2,11 @@
 
 Both sides draw the same Philox coordinates; each generates its own hard
 events and showers them.  The bar: integer and flavour/colour data
-bit-exact, >= 99.9% of events with identical emission sequences, and their
-momenta within 1e-9 relative to the event's energy scale.  Transcendental
-functions differ by an ulp between the device and host libraries, which is
-the only expected source of disagreement.
+bit-exact, >= 99.9% of events with identical emission sequences, weights
+within 1e-9 relative, and every parton's momentum within 1e-9 of its own
+energy (tests/parity.py).  Transcendental functions differ by an ulp between
+the device and host libraries, which is the only expected source of
+disagreement.
 """
 import math
 import sys
@@ -14,6 +15,7 @@ import numpy as np
 import pytest
 
 from gapsinputs import records, workloads
+from tests.parity import compare_events  # noqa: F401  (shared with the other GPU tests)
 
 pytestmark = pytest.mark.gpu
 
@@ -31,29 +33,6 @@ def gpu(cfgs):
     from paper_2511_19633_amd import binding
     assert torch.cuda.is_available()
     return {k: binding.Gaps(v) for k, v in cfgs.items()}
-
-
-def compare_events(a: records.Events, b: records.Events, scale: float, need=0.999, tol=1e-9):
-    """a: oracle, b: GPU.  Returns (fraction identical, worst momentum diff)."""
-    n = a.cap
-    same = np.ones(n, dtype=bool)
-    same &= a.n == b.n
-    same &= a.flags == b.flags
-    for name in ("n_cycles", "n_trials", "n_accept", "n_viol"):
-        same &= getattr(a, name) == getattr(b, name)
-    M = min(a.max_slots, b.max_slots)
-    slot_ok = np.arange(M)[:, None] < a.n[None, :]
-    for name in ("pid", "col", "acol", "status"):
-        eq = (getattr(a, name)[:M] == getattr(b, name)[:M]) | ~slot_ok
-        same &= eq.all(axis=0)
-    worst = 0.0
-    for name in ("E", "px", "py", "pz"):
-        d = np.abs(getattr(a, name)[:M] - getattr(b, name)[:M]) * slot_ok
-        dm = d.max(axis=0) / scale
-        worst = max(worst, float(dm[same].max()) if same.any() else 0.0)
-        same &= dm < tol
-    frac = float(same.mean())
-    return frac, worst, same
 
 
 def test_rng_bit_exact():
@@ -100,7 +79,7 @@ def test_overestimate_table(gpu, oracles, key):
 
 
 @pytest.mark.parametrize("key,n", [("ee", 3000), ("lo", 3000), ("nlo", 3000), ("dy", 3000),
-                                   ("dynlo", 3000)])
+                                   ("dynlo", 10000)])
 def test_hard_events(gpu, oracles, key, n):
     say(f"hard events {key} n={n}")
     g = gpu[key].hard_events(0, n, 1).to_host()
@@ -122,8 +101,8 @@ def test_hard_events(gpu, oracles, key, n):
     assert np.allclose(g.t_start, o.t_start, rtol=0, atol=0)
 
 
-@pytest.mark.parametrize("key,n", [("ee", 10000), ("lo", 3000), ("nlo", 3000), ("dy", 3000),
-                                   ("dynlo", 3000)])
+@pytest.mark.parametrize("key,n", [("ee", 10000), ("lo", 10000), ("nlo", 10000), ("dy", 10000),
+                                   ("dynlo", 10000)])
 def test_shower_parity(gpu, oracles, key, n):
     from paper_2511_19633_amd import binding
     say(f"shower parity {key} n={n}")

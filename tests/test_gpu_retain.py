@@ -32,8 +32,8 @@ def _same(a, b, what):
         assert np.array_equal(getattr(a, name), getattr(b, name)), (what, name)
 
 
-@pytest.mark.parametrize("key,n", [("ee", 10000), ("lo", 3000), ("nlo", 3000), ("dy", 3000),
-                                   ("dynlo", 3000)])
+@pytest.mark.parametrize("key,n", [("ee", 10000), ("lo", 10000), ("nlo", 10000), ("dy", 10000),
+                                   ("dynlo", 10000)])
 def test_retained_shower_parity(gpu, oracles, key, n):
     say(f"retained parity {key} n={n}")
     G, O = gpu[key], oracles[key]
