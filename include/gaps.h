@@ -248,6 +248,28 @@ gaps_status gaps_hard_events(gaps_ctx ctx, int64_t first_id, int64_t n, uint64_t
 gaps_status gaps_shower(gaps_ctx ctx, const gaps_events* in, int64_t n, const gaps_params* params,
                         uint64_t seed, gaps_events* out, hipStream_t stream);
 
+/* gaps_shower for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, checks and results (every event bitwise what gaps_shower
+ * gives), with the per-lane working storage (event records, channel caches,
+ * weight factors, the work-queue counter) in a static device array of
+ * GAPS_NOALLOC_SCRATCH_BYTES per GPU instead of the context's grown
+ * allocation.  The array exists on every GPU the library is loaded on until
+ * the process ends; gaps_init resolves its address on the context's device.
+ * The call allocates nothing: the launch's grid is cut to the blocks of lanes
+ * whose storage fits the array (fewer lanes in flight than gaps_shower uses,
+ * so it is slower), and the queue counter is cleared by a fill kernel (no
+ * memset node under capture).  Calls on one GPU share the array and keep the
+ * last call's contents: calls that overlap on one GPU (on different streams,
+ * or from different contexts on the same device) race and must not be
+ * issued; calls in one stream are ordered.  Errors as gaps_shower, plus
+ * GAPS_ECAPACITY when one block's storage (block x per-lane bytes for
+ * out->max_slots) exceeds the array and GAPS_ESTATE when the address was not
+ * resolved on this device. */
+#define GAPS_NOALLOC_SCRATCH_BYTES (256ull << 20)
+gaps_status gaps_shower_noalloc(gaps_ctx ctx, const gaps_events* in, int64_t n, const gaps_params* params,
+                                uint64_t seed, gaps_events* out, hipStream_t stream);
+
 /* One batch of a stream: input and output records (their pointers are DEVICE
  * pointers, as in gaps_shower) and the number of events n (in->cap, out->cap >= n). */
 typedef struct {

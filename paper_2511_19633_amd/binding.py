@@ -87,6 +87,8 @@ def lib():
         L.gaps_hard_events.argtypes = [vp, i64, i64, u64, C.POINTER(GapsEvents), vp]
         L.gaps_shower.argtypes = [vp, C.POINTER(GapsEvents), i64, C.POINTER(GapsParams), u64,
                                   C.POINTER(GapsEvents), vp]
+        L.gaps_shower_noalloc.argtypes = [vp, C.POINTER(GapsEvents), i64, C.POINTER(GapsParams), u64,
+                                          C.POINTER(GapsEvents), vp]
         L.gaps_shower_stream.argtypes = [vp, C.POINTER(GapsBatch), C.c_int, C.POINTER(GapsParams), u64, vp]
         L.gaps_graph_capture.argtypes = [vp, C.POINTER(GapsBatch), C.c_int, C.POINTER(GapsParams), u64, vp,
                                          C.POINTER(vp)]
@@ -240,6 +242,17 @@ class Gaps:
         si, so = ev_in.struct(), ev_out.struct()
         _check(lib().gaps_shower(self.h, C.byref(si), n, C.byref(p), seed, C.byref(so), _stream(stream)))
         return ev_out
+
+    def shower_noalloc(self, ev_in: DeviceEvents, seed: int, out: DeviceEvents, n: int | None = None,
+                       stream=None, **params) -> DeviceEvents:
+        """gaps_shower_noalloc: the shower with the library's static working
+        storage (no device allocation in the call); the caller passes the
+        output record."""
+        n = ev_in.cap if n is None else n
+        p = self._params(**params)
+        si, so = ev_in.struct(), out.struct()
+        _check(lib().gaps_shower_noalloc(self.h, C.byref(si), n, C.byref(p), seed, C.byref(so), _stream(stream)))
+        return out
 
     @staticmethod
     def _batches(batches):

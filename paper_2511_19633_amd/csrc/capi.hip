@@ -3,6 +3,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 using gaps::Cfg;
@@ -75,6 +77,30 @@ gaps_status ensure_scratch(ScratchMem& m, int64_t lanes, int slots) {
     if (scratch_layout((char*)m.mem, m.bytes, lanes, slots, m.S) != GAPS_OK) return GAPS_ENOMEM;
   }
   return GAPS_OK;
+}
+
+// The working storage of gaps_shower_noalloc: a static device array, one per
+// GPU (its name on the host is only a stand-in; kernels get the device
+// address that gaps_init resolves per device with hipGetSymbolAddress).
+static __device__ __align__(256) unsigned char scratch[GAPS_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// resolve the array's address on the current device (once per device)
+gaps_status resolve_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return GAPS_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return GAPS_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GAPS_EHIP;
+  g_scratch_ptr[device] = ptr;
+  return GAPS_OK;
+}
+
+void* static_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
 }
 
 // Device copy of a stream's batch table and its offsets (grown on demand).
@@ -168,6 +194,8 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) { delete c; return GAPS_EHIP; }
   c->cus = prop.multiProcessorCount;
+  // the allocation-free shower's static working storage on this device
+  if (resolve_static_scratch(c->device) != GAPS_OK) { delete c; return GAPS_EHIP; }
   size_t npdf = (size_t)cfg->ntab * cfg->nq * cfg->nx;
   if (hipMalloc(&c->d_pdf, npdf * sizeof(float)) != hipSuccess ||
       hipMalloc(&c->d_bound, (gaps::kNEnt + 8) * gaps::kNB * sizeof(double)) != hipSuccess) {
@@ -416,6 +444,30 @@ gaps_status gaps_shower(gaps_ctx c, const gaps_events* in, int64_t n, const gaps
   s = ensure_scratch(c->scratch, pl.grid * pl.block, out->max_slots);
   if (s != GAPS_OK) return s;
   return launch_shower(c, pl, in, out, c->scratch.S, stream);
+}
+
+gaps_status gaps_shower_noalloc(gaps_ctx c, const gaps_events* in, int64_t n, const gaps_params* params,
+                                uint64_t seed, gaps_events* out, hipStream_t stream) {
+  if (!c || bad_events(in, n, 1) || bad_events(out, n, 1)) return GAPS_EINVAL;
+  if (n > 0 && (in->E == out->E || in->n == out->n)) return GAPS_EINVAL;
+  Plan pl;
+  gaps_status s = plan_shower(c, params, n, seed, pl);
+  if (s != GAPS_OK || n == 0) return s;
+  void* base = static_scratch(c->device);
+  if (!base) return GAPS_ESTATE;
+  // as many whole blocks of lanes as the static storage holds (the grid only
+  // changes the speed: every event's result is keyed by its id)
+  const size_t per_lane = scratch_per_lane(out->max_slots);
+  const size_t fixed = scratch_bytes(0, out->max_slots) + 256 * 6;
+  const int64_t lanes_cap = GAPS_NOALLOC_SCRATCH_BYTES > fixed
+                                ? (int64_t)((GAPS_NOALLOC_SCRATCH_BYTES - fixed) / per_lane) : 0;
+  const int64_t blocks_cap = lanes_cap / pl.block;
+  if (blocks_cap < 1) return GAPS_ECAPACITY;
+  if (pl.grid > blocks_cap) pl.grid = blocks_cap;
+  gaps::Scratch S{};
+  s = scratch_layout((char*)base, GAPS_NOALLOC_SCRATCH_BYTES, pl.grid * pl.block, out->max_slots, S);
+  if (s != GAPS_OK) return s;
+  return launch_shower(c, pl, in, out, S, stream);
 }
 
 gaps_status gaps_shower_stream(gaps_ctx c, const gaps_batch* batches, int nbatch, const gaps_params* params,
