@@ -2,28 +2,39 @@
 
 A step is one pass of the whole shower (every step of the veto algorithm) over
 one batch of 10^6 NLO S/H events that already sit in HBM; step k showers event
-ids k*10^6 .. (k+1)*10^6-1.  By default the timed steps' batches are streamed
-through one persistent launch captured in a HIP graph (gaps_shower_stream), so
-lanes refill across batch boundaries; --launch per-step launches gaps_shower
-once per batch instead.  Hard-event generation and observables are timed
+ids k*10^6 .. (k+1)*10^6-1.  The K timed steps' batches are streamed through
+one persistent launch captured in a HIP graph (gaps_shower_stream), so lanes
+refill across batch boundaries.  Every timed figure is the median of --repeats
+(default 5) timed passes over all K steps, each bracketed by device
+synchronisations, after --warmup untimed passes; the spread (min, max) is
+reported beside it.  Hard-event generation and observables are timed
 separately, as the paper's component table does, and are not part of `value`.
 
 With --mode learned (default) the learned initial-state bound is first
 trained on the GPU (trial log of the plain shower on separate event ids,
 training, calibration, tabulation; reported under "learned"), then the same
 batches are showered plain and learned; `value` is the learned shower and the
-plain one is reported beside it.
+plain one is reported beside it.  The launch shape of each mode (block,
+refill interval, waves per SIMD, lanes in flight) comes from the library's
+autotuner on the first batch (reported under "autotune", with the
+hand-picked default shape's time on the full run beside it).
 
---trials retain (default) runs the competition of the veto algorithm in its
-retained-trial form (a losing channel keeps its trial scale; the same Markov
-chain with fewer draws); the same batches are then also timed with every
-channel redrawn each cycle, the paper's form, and reported under
-"paper_form".
-
-Prints one JSON line.  Extra objects:
-  roofline      the shower kernel against the FP64 vector peak, with the
-                algorithmic operation count of the launches that were timed
-  cpu_baseline  the CPU oracle on the host cores on a bounded sample
+Reported beside `value`:
+  plain, learned, cellmax, cellmax_adaptive   the plain shower, the trained
+      bound and the cell-maximum comparators on the same batches
+  histograms    chi^2 of Z pT, phi* and the jet count of each form against a
+      plain shower of independent events (ids K*10^6 .. 2K*10^6 - 1, the
+      output weights), and the plain-vs-plain control under the same protocol
+  paper_form    the same batches with every channel redrawn each cycle
+  stream_uneven the same 10^7 events in batches of uniform sizes 10^4..5*10^5
+      (the batched-stream configuration), one captured launch
+  table1        hard events / shower / observables at 10^4, 10^5, 10^6 events
+      (the paper's component table), median of the repeats
+  competition_forms, matching, dy_nlo   the other forms and workloads
+  roofline      the shower kernel against the FP64 vector peak: the
+      algorithmic floating-point operations (transcendentals excluded,
+      reported as counts) per launch over the median launch time
+  cpu_baseline  the CPU oracle on one thread and on all the host's cores
 """
 from __future__ import annotations
 
@@ -40,31 +51,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
-LOG_ID0 = 1 << 40  # event ids of the trial-log run (disjoint from the timed steps)
 HBM_PEAK_GBS = 8000.0
-# algorithmic FP64 work per unit (a transcendental counted as 20 operations)
-OPS_TRIAL = 6 + 20            # one log, the key arithmetic and the compare
-OPS_WINNER = 200 + 2 * 50     # z/phi sampling, maps, weight; two PDF lookups
-OPS_ACCEPT_BASE = 150         # emission kinematics and bookkeeping
-OPS_ACCEPT_PER_PARTON = 28    # II boost: a 4x4 transformation per parton
+LOG_ID0 = 1 << 40  # event ids of the trial-log run (disjoint from the timed steps)
+# algorithmic work per unit of the veto algorithm, floating-point operations
+# without the transcendental functions (counted separately)
+FLOPS_TRIAL = 6               # the trial key ln T + ln(u)/c, its compare
+FLOPS_WINNER = 200            # term choice, z/phi sampling, maps, kernel, weight
+FLOPS_ACCEPT_BASE = 150       # emission kinematics and bookkeeping
+FLOPS_ACCEPT_PER_PARTON = 28  # the initial-initial boost: a 4x4 transformation per parton
+# transcendental evaluations per unit: a trial's log; a winner's exp of its
+# scale, the coupling's log, z sampling (one log or exp), the PDF lookups'
+# logs of x (two) and of Q^2, the trial log's and map's sqrt/cos/sin counted
+# with the accepts
+TRANS_TRIAL = 1
+TRANS_WINNER = 6
+PDF_LOOKUPS_WINNER = 2
+TRANS_ACCEPT = 6
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, n_sample, seed, retain):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(cfg, seed, retain, n_single, n_all):
+    """The oracle (test infrastructure, not tuned) on one thread, then on every
+    core this process may run on, over contiguous event-id ranges."""
     from oracle.pyoracle import Oracle
-    threads = min(16, os.cpu_count() or 1)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     o = Oracle(cfg)
-    ev = o.hard_events(0, n_sample, seed)
+    ev1 = o.hard_events(0, n_single, seed)
     t0 = time.perf_counter()
-    o.shower(ev, seed, nthreads=threads, retain=retain)
-    dt = time.perf_counter() - t0
+    o.shower(ev1, seed, nthreads=1, retain=retain)
+    dt1 = time.perf_counter() - t0
+    evn = o.hard_events(0, n_all, seed)
+    t0 = time.perf_counter()
+    o.shower(evn, seed, nthreads=cores, retain=retain)
+    dtn = time.perf_counter() - t0
     form = "retained trials" if retain else "every channel redrawn each cycle"
-    return {"value": n_sample / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_sample} NLO pp->Z event ids (seed {seed}), plain shower ({form}), "
-                      f"{threads} threads over contiguous id ranges, {dt:.2f} s wall"}
+    return {"value": n_all / dtn, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_all} NLO pp->Z event ids (seed {seed}), plain shower ({form}), {cores} threads "
+                      f"over contiguous id ranges, {dtn:.2f} s wall; single thread: first {n_single} ids, "
+                      f"{dt1:.2f} s",
+            "single_thread_value": n_single / dt1, "host_cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 SHOWER_SOURCES = ("capi.hip", "device.hpp", "kernels.hpp", "shower_wave.hip")
@@ -84,8 +123,8 @@ def source_hash():
 
 
 def stored_traffic(kernel, mode):
-    """HBM bytes per event of `kernel` in `mode` ("plain" or "learned") from the
-    committed counter summary, or None."""
+    """HBM bytes per event of `kernel` in `mode` from the committed counter
+    summary, or None (no summary, or taken with other sources)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_pp_nlo.traffic.json")
     if not os.path.exists(path):
         return None
@@ -108,7 +147,7 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
-def learned_pipeline(G, binding, args, seed):
+def learned_pipeline(G, args, seed, retain):
     """Trial log of the plain shower, training, calibration and tabulation, all
     on the GPU with the library's kernels (untimed for `value`, reported)."""
     import torch
@@ -116,7 +155,7 @@ def learned_pipeline(G, binding, args, seed):
     G.mlp_init(seed + 10)
     t0 = time.perf_counter()
     hin = G.hard_events(LOG_ID0, args.log_events, seed, max_slots=8)
-    _, rows, cnt = G.shower_log(hin, seed, args.log_rows, retain=args.trials == "retain")
+    _, rows, cnt = G.shower_log(hin, seed, args.log_rows, retain=retain)
     torch.cuda.synchronize()
     rep["log_s"], rep["log_events"], rep["log_rows"] = time.perf_counter() - t0, args.log_events, int(rows.shape[0])
     del hin
@@ -127,8 +166,7 @@ def learned_pipeline(G, binding, args, seed):
                        seed=seed)
     torch.cuda.synchronize()
     rep["train_s"] = time.perf_counter() - t0
-    rep["train_steps"], rep["train_batch"] = args.train_steps, args.train_batch
-    rep["train_tau"] = args.train_tau
+    rep["train_steps"], rep["train_batch"], rep["train_tau"] = args.train_steps, args.train_batch, args.train_tau
     lv = loss.cpu().numpy()
     rep["loss_first"], rep["loss_last"] = float(lv[:10].mean()), float(lv[-10:].mean())
     t0 = time.perf_counter()
@@ -148,53 +186,69 @@ def bound_over_analytic(G):
     return float(np.mean(tab[tab > 0] / R[tab > 0]))
 
 
-def chi_vs_plain(h_plain, h_other):
-    """chi^2 of two sets of weighted histograms (sum w, sum w^2) bin by bin."""
+HIST_SPEC = (("z_pt", 0, 0.0, 60.0, 30), ("phi_star", 3, 0.0, 1.0, 30), ("n_jets", 4, -0.5, 6.5, 7))
+
+
+def histograms(G, pairs):
+    """Weighted histograms (sum w, sum w^2, with each event's output weight)
+    of Z pT, phi* and the jet count over (record, n) pairs."""
+    acc = [None] * len(HIST_SPEC)
+    for ev, n in pairs:
+        ob = G.observables(ev, n=n)
+        for k, (_, col, lo, hi, nb) in enumerate(HIST_SPEC):
+            sw, sw2 = G.histogram(ob, ev.w[:n], col, lo, hi, nb)
+            acc[k] = (sw, sw2) if acc[k] is None else (acc[k][0] + sw, acc[k][1] + sw2)
+        del ob
+    return [(a.cpu().numpy(), b.cpu().numpy()) for a, b in acc]
+
+
+def chi2(h_ref, h_other):
+    """chi^2 per degree of freedom of two independent sets of weighted
+    histograms, bin by bin over the bins with content, with p-values."""
     from scipy import stats as sstats
-    chi = {}
-    for name, (a, a2), (b, b2) in zip(("z_pt", "phi_star", "n_jets"), h_plain, h_other):
+    out = {}
+    for (name, *_), (a, a2), (b, b2) in zip(HIST_SPEC, h_ref, h_other):
         m = (a2 + b2) > 0
         c2, ndf = float(np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m]))), int(max(m.sum(), 1))
-        chi[name] = {"chi2_ndf": c2 / ndf, "ndf": ndf, "p_value": float(sstats.chi2.sf(c2, ndf))}
-    return chi
+        out[name] = {"chi2_ndf": c2 / ndf, "ndf": ndf, "p_value": float(sstats.chi2.sf(c2, ndf))}
+    out["gate_chi2_ndf_below_1_5"] = all(v["chi2_ndf"] < 1.5 for v in out.values() if isinstance(v, dict))
+    return out
 
 
-def timed_stream(G, binding, batches, seed, args, kw, mode):
-    """Warm-up passes and one timed pass of the graph-captured stream."""
+def timed_stream(G, binding, batches, seed, args, kw, mode, repeats=None, warmup=None):
+    """Warm-up passes, then `repeats` timed passes of the graph-captured
+    stream (all batches in one launch), each bracketed by synchronisations;
+    HIP events on the launch's stream give its device time."""
     import torch
-    # the input batches may still be in the making on another stream
-    torch.cuda.synchronize()
+    repeats = args.repeats if repeats is None else repeats
+    warmup = args.warmup if warmup is None else warmup
+    torch.cuda.synchronize()  # the input batches may still be in the making on another stream
     stats = torch.zeros(binding.NSTATS, dtype=torch.uint64, device="cuda")
-    K = len(batches)
-    if args.launch == "stream":
-        stream = torch.cuda.Stream()
-        graph = G.capture(batches, seed, stream, stats=stats, mode=mode, **kw)
-        run = lambda: graph.launch(stream)  # noqa: E731
-    else:
-        stream = torch.cuda.current_stream()
-        graph = None
-
-        def run():
-            for ev_in, ev_out, _ in batches:
-                G.shower(ev_in, seed, out=ev_out, stats=stats, stream=stream, mode=mode, **kw)
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-    stats.zero_()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    start.record(stream)
-    run()
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    launch_ms = start.elapsed_time(end)
-    if graph is not None:
+    stream = torch.cuda.Stream()
+    graph = G.capture(batches, seed, stream, stats=stats, mode=mode, **kw)
+    try:
+        for _ in range(warmup):
+            graph.launch(stream)
+        torch.cuda.synchronize()
+        walls, launches = [], []
+        for r in range(repeats):
+            if r == repeats - 1:
+                stats.zero_()  # the last pass's counters (every pass does the same work)
+            start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            start.record(stream)
+            graph.launch(stream)
+            end.record(stream)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - w0)
+            launches.append(start.elapsed_time(end))
+    finally:
         graph.close()
     n = sum(b[2] for b in batches)
-    return {"wall_s": wall, "launch_ms": launch_ms, "events": n, "stats": stats.cpu().numpy().astype(float),
-            "launches": 1 if args.launch == "stream" else len(batches)}
+    return {"wall_s": float(np.median(walls)), "wall_s_min": min(walls), "wall_s_max": max(walls),
+            "launch_ms": float(np.median(launches)), "launch_ms_min": min(launches), "launch_ms_max": max(launches),
+            "repeats": repeats, "events": n, "stats": stats.cpu().numpy().astype(float)}
 
 
 def shower_stats(st, nev, nfin, overflow):
@@ -209,21 +263,44 @@ def shower_stats(st, nev, nfin, overflow):
             "active_lane_fraction": st[5] / st[4] if st[4] > 0 else None}
 
 
+def summarise(r, outs, kernel, mode_name, K):
+    """events/s (median pass), ms per step, the roofline entry and the shower statistics of a timed stream."""
+    import torch
+    nfin = float(np.mean([o.n.double().mean().item() for o in outs]))
+    flags = torch.cat([o.flags.to(torch.int64) for o in outs])
+    overflow = int(((flags & 1) != 0).sum().item())
+    st = r["stats"]
+    launch_s = r["launch_ms"] / 1e3
+    flops = st[1] * FLOPS_TRIAL + st[0] * FLOPS_WINNER + st[2] * (FLOPS_ACCEPT_BASE +
+                                                                  FLOPS_ACCEPT_PER_PARTON * 0.5 * nfin)
+    trans = st[1] * TRANS_TRIAL + st[0] * TRANS_WINNER + st[2] * TRANS_ACCEPT
+    achieved = flops / launch_s / 1e12
+    tr = stored_traffic(kernel, mode_name)
+    traffic = None if tr is None else tr["bytes_per_event"] * r["events"]
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel,
+            "launch_ms": r["launch_ms"], "launch_ms_min": r["launch_ms_min"], "launch_ms_max": r["launch_ms_max"],
+            "events_per_launch": r["events"], "flops_per_launch": flops,
+            "transcendentals_per_launch": trans, "pdf_lookups_per_launch": st[0] * PDF_LOOKUPS_WINNER,
+            "philox_blocks_per_launch": st[1] / 4.0 + st[0],
+            "transcendentals_per_s": trans / launch_s,
+            "hbm_gbs": None if traffic is None else traffic / launch_s / 1e9}
+    value = r["events"] / r["wall_s"]
+    return {"value": value, "value_min": r["events"] / r["wall_s_max"], "value_max": r["events"] / r["wall_s_min"],
+            "repeats": r["repeats"], "ms_per_step": r["wall_s"] * 1e3 / K, "roofline": roof,
+            "shower_stats": shower_stats(st, r["events"], nfin, overflow)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--repeats", type=int, default=5, help="timed passes per figure (the median is reported)")
     ap.add_argument("--events", type=int, default=1_000_000, help="events per step (one batch)")
     ap.add_argument("--mode", choices=["learned", "plain"], default="learned",
                     help="learned: train the bound first and report the learned shower as `value`, "
                          "the plain shower beside it; plain: the plain shower only")
-    ap.add_argument("--batches", choices=["even", "uneven"], default="even",
-                    help="even: one batch of --events per step; uneven: the same events in batches of "
-                         "10^4..5*10^5 (uniform sizes, seed 1) streamed through the same launch")
-    ap.add_argument("--launch", choices=["stream", "per-step"], default="stream",
-                    help="stream: the timed steps' batches go through one graph-captured persistent "
-                         "launch; per-step: one launch per step")
     ap.add_argument("--log-events", type=int, default=420_000, help="events whose trials train the bound")
     ap.add_argument("--log-rows", type=int, default=50_000_000)
     ap.add_argument("--train-steps", type=int, default=1500)
@@ -232,26 +309,15 @@ def main():
     ap.add_argument("--trials", choices=["retain", "regenerate"], default="retain",
                     help="retain: a losing channel keeps its trial scale (the same Markov chain, fewer draws); "
                          "regenerate: every channel draws again each cycle")
-    ap.add_argument("--no-paper-form", action="store_true",
-                    help="with --trials retain: skip timing the same batches with every channel redrawn each "
-                         "cycle (the paper's form of the competition), reported under \"paper_form\"")
-    ap.add_argument("--no-cellmax", action="store_true",
-                    help="with --mode learned: skip timing the cell-maximum bound (the non-learned comparator "
-                         "built from the same logged trials), reported under \"cellmax\"")
-    ap.add_argument("--no-forms", action="store_true",
-                    help="skip timing max-veto, generate-select and veto-max in the one-event-per-lane "
-                         "kernels on the first two batches, reported under \"competition_forms\"")
-    ap.add_argument("--no-matching", action="store_true",
-                    help="skip timing the plain shower of the matching variants (MC@NLO started at mZ^2, "
-                         "POWHEG-like events with the first-emission correction) and of NLO pp -> Z/photon -> "
-                         "e+e- events on two batches of their own events, reported under \"matching\" and "
-                         "\"dy_nlo\"")
+    ap.add_argument("--no-tune", action="store_true", help="use the hand-picked default launch shape")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--compact-every", type=int, default=0)
     ap.add_argument("--waves-per-simd", type=int, default=0)
-    ap.add_argument("--variant", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=150_000)
+    ap.add_argument("--lite", action="store_true",
+                    help="only the timed plain and learned legs (no comparators, forms, workloads, table, CPU)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-single", type=int, default=60_000, help="events of the single-thread oracle run")
+    ap.add_argument("--cpu-all", type=int, default=300_000, help="events of the all-core oracle run")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -261,169 +327,211 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
-    if args.variant != 0 and (args.launch == "stream" or args.mode == "learned"):
-        ap.error("only the wave kernel (variant 0) streams batches and runs the learned mode")
 
     import torch
     from gapsinputs import workloads
     from paper_2511_19633_amd import binding
+    from paper_2511_19633_amd import tune as tuner
 
     torch.cuda.set_device(0)
     cfg = workloads.config_dict(workloads.PP_NLO)
     seed = 1
     n, K = args.events, args.steps
+    retain = args.trials == "retain"
     G = binding.Gaps(cfg)
-    kw = dict(block=args.block, compact_every=args.compact_every, waves_per_simd=args.waves_per_simd,
-              variant=args.variant, retain=args.trials == "retain")
+    kernel = "k_shower_wave_rt" if retain else "k_shower_wave"
 
-    # hard events of every step (ids k*n .. (k+1)*n-1); timed separately, not part of the metric
-    t0 = time.perf_counter()
-    # even: K batches of n events; uneven: the same n*K events in batches whose
-    # sizes are uniform integers in [10^4, 5*10^5] (the last one truncated)
-    sizes = workloads.batch_sizes(n * K, seed=1) if args.batches == "uneven" else [n] * K
-    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    ins = [G.hard_events(int(a), int(m), seed, max_slots=8) for a, m in zip(starts, sizes)]
+    # hard events of every step (ids k*n .. (k+1)*n-1); timed separately
+    ins = [G.hard_events(k * n, n, seed, max_slots=8) for k in range(K)]
     torch.cuda.synchronize()
-    t_hard = (time.perf_counter() - t0) / K
-    outs = [binding.DeviceEvents(int(m), workloads.MAX_SLOTS) for m in sizes]
-    batches = [(ins[k], outs[k], int(sizes[k])) for k in range(len(sizes))]
-    kernel = {1: "k_shower_lanes", 0: {0: "k_shower_wave", 2: "k_shower_wave", 3: "k_shower_wave3",
-                                       4: "k_shower_wave4"}[args.waves_per_simd]}[args.variant]
-    if args.trials == "retain":
-        kernel = "k_shower_wave_rt3" if args.waves_per_simd == 3 else "k_shower_wave_rt"
+    outs = [binding.DeviceEvents(n, workloads.MAX_SLOTS) for _ in range(K)]
+    batches = [(ins[k], outs[k], n) for k in range(K)]
+    out = {}
 
-    def summarise(r, mode, kname=None):
-        nfin = float(np.mean([o.n.double().mean().item() for o in outs]))
-        flags = torch.cat([o.flags.to(torch.int64) for o in outs])
-        overflow = int(((flags & 1) != 0).sum().item())
-        st = r["stats"]
-        nev_launch = r["events"] / r["launches"]
-        mean_launch_s = r["launch_ms"] / 1e3 / r["launches"]
-        ops = (st[1] * OPS_TRIAL + st[0] * OPS_WINNER +
-               st[2] * (OPS_ACCEPT_BASE + OPS_ACCEPT_PER_PARTON * 0.5 * nfin)) / r["launches"]
-        achieved = ops / mean_launch_s / 1e12
-        kname = kname or kernel
-        tr = stored_traffic(kname, mode)
-        traffic = None if tr is None else tr["bytes_per_event"] * nev_launch
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic, "kernel": kname,
-                "launch_ms": mean_launch_s * 1e3, "events_per_launch": nev_launch, "ops_per_launch": ops,
-                "hbm_gbs": None if traffic is None else traffic / mean_launch_s / 1e9}
-        return (r["events"] / r["wall_s"], r["wall_s"] * 1e3 / K, roof,
-                shower_stats(st, r["events"], nfin, overflow))
+    def shape_for(mode):
+        """The launch shape of a mode: the autotuner's choice on the first batch
+        (or the command line's / the default shape)."""
+        if args.no_tune or args.block or args.compact_every or args.waves_per_simd:
+            return dict(block=args.block, compact_every=args.compact_every, waves_per_simd=args.waves_per_simd), None
+        rec = tuner.autotune(G, batches[:1], seed, "pp_nlo", mode, retain, repeats=3, use_cache=False)
+        log(f"autotune mode {mode}: {rec['chosen']} (default {rec['default']['ms']:.2f} ms)")
+        rep = {k: rec[k] for k in ("params", "chosen", "default", "tune_s", "repeats", "calibration_events")}
+        rep["points"] = rec["points"]
+        return dict(rec["params"]), rep
 
-    def histos():
-        """Weighted histograms (sum w, sum w^2) over every timed batch: Z pT and
-        phi* in 30 bins, the jet count one bin per integer."""
-        spec = ((0, 0.0, 60.0, 30), (3, 0.0, 1.0, 30), (4, -0.5, 6.5, 7))
-        acc = [None] * len(spec)
-        for ev_in, ev_out, _ in batches:
-            ob = G.observables(ev_out)
-            for k, (col, lo, hi, nb) in enumerate(spec):
-                sw, sw2 = G.histogram(ob, ev_in.w, col, lo, hi, nb)
-                acc[k] = (sw, sw2) if acc[k] is None else (acc[k][0] + sw, acc[k][1] + sw2)
-            del ob
-        return [(a.cpu().numpy(), b.cpu().numpy()) for a, b in acc]
+    def is_default(kw):
+        return all(kw.get(k, 0) in (0, v) for k, v in (("block", 512), ("compact_every", 8), ("waves_per_simd", 2))) \
+            and not kw.get("grid")
 
-    out_extra = {}
-    r_plain = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_PLAIN)
-    v_plain, ms_plain, roof_plain, st_plain = summarise(r_plain, "plain")
-    t0 = time.perf_counter()
-    h_plain = histos()
-    torch.cuda.synchronize()
-    t_obs = (time.perf_counter() - t0) / K  # observables and histograms of one step
-    log(f"plain: {v_plain:.4g} events/s")
+    # ---- plain
+    kw_plain, tune_plain = shape_for(binding.MODE_PLAIN)
+    s_plain = summarise(timed_stream(G, binding, batches, seed, args, dict(kw_plain, retain=retain),
+                                     binding.MODE_PLAIN), outs, kernel, "plain", K)
+    log(f"plain: {s_plain['value']:.4g} events/s")
+    out["plain"] = s_plain
+    autotune = {"plain": tune_plain}
+    if not args.lite:
+        # the reference sample: a plain shower of independent events (ids K n ..
+        # 2 K n - 1), one batch at a time through one spare record
+        ref_in = binding.DeviceEvents(n, 8)
+        ref_out = binding.DeviceEvents(n, workloads.MAX_SLOTS)
+        h_ref = None
+        for k in range(K):
+            G.hard_events((K + k) * n, n, seed, out=ref_in)
+            G.shower(ref_in, seed, out=ref_out, retain=retain)
+            h = histograms(G, [(ref_out, n)])
+            h_ref = h if h_ref is None else [(a + c, b + d) for (a, b), (c, d) in zip(h_ref, h)]
+        del ref_in, ref_out
+        t0 = time.perf_counter()
+        h_plain = histograms(G, [(o, n) for o in outs])
+        torch.cuda.synchronize()
+        t_obs = (time.perf_counter() - t0) / K
+        hist = {"reference": "plain shower of event ids %d .. %d" % (K * n, 2 * K * n - 1),
+                "plain_control": chi2(h_ref, h_plain)}
+    value, ms_per_step, roof, stats_main = s_plain["value"], s_plain["ms_per_step"], s_plain["roofline"], \
+        s_plain["shower_stats"]
+    kw_main, mode_main = dict(kw_plain, retain=retain), binding.MODE_PLAIN
+
+    # ---- learned
+    log_rows = None
     if args.mode == "learned":
-        rep, log_rows = learned_pipeline(G, binding, args, seed)
+        rep, log_rows = learned_pipeline(G, args, seed, retain)
         log(f"trained bound: {rep}")
-        r_l = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
-        v_l, ms_l, roof_l, st_l = summarise(r_l, "learned")
-        # a weight above its bound that was used without the plain fallback
-        unhandled = int(sum(((o.flags.to(torch.int64) & binding.F_VIOL) != 0).sum().item() for o in outs))
-        log(f"learned: {v_l:.4g} events/s")
-        chi = chi_vs_plain(h_plain, histos())
-        value, ms_per_step, roof, stats_main = v_l, ms_l, roof_l, st_l
-        out_extra["plain"] = {"value": v_plain, "ms_per_step": ms_plain, "roofline": roof_plain,
-                              "shower_stats": st_plain}
-        out_extra["learned"] = dict(rep, speedup_over_plain=v_l / v_plain,
-                                    histogram_chi2_ndf_vs_plain=chi,
-                                    unhandled_bound_violations=unhandled)
-    else:
-        value, ms_per_step, roof, stats_main = v_plain, ms_plain, roof_plain, st_plain
-    if args.trials == "retain" and not args.no_paper_form and args.variant == 0:
-        # the same batches with every channel redrawn each cycle (same Markov chain)
-        kw_p = dict(kw, retain=False)
-        kname_p = {0: "k_shower_wave", 2: "k_shower_wave", 3: "k_shower_wave3",
-                   4: "k_shower_wave4"}[args.waves_per_simd]
-        pf = {"kernel": kname_p}
+        kw_l, tune_l = shape_for(binding.MODE_LEARNED)
+        autotune["learned"] = tune_l
+        s_l = summarise(timed_stream(G, binding, batches, seed, args, dict(kw_l, retain=retain),
+                                     binding.MODE_LEARNED), outs, kernel, "learned", K)
+        log(f"learned: {s_l['value']:.4g} events/s")
+        neg = int(sum(((o.w < 0) & ((o.flags.to(torch.int64) & binding.F_FALLBACK) != 0)).sum().item() for o in outs))
+        out["learned"] = dict(rep, **s_l, speedup_over_plain=s_l["value"] / s_plain["value"],
+                              fallback_events_negative_weight=neg)
+        if not args.lite:
+            hist["learned"] = chi2(h_ref, histograms(G, [(o, n) for o in outs]))
+        if tune_l is not None and not is_default(kw_l):
+            s_d = summarise(timed_stream(G, binding, batches, seed, args, dict(retain=retain), binding.MODE_LEARNED),
+                            outs, kernel, "learned", K)
+            autotune["learned_default_shape_value"] = s_d["value"]
+            autotune["learned_tuned_over_default"] = s_l["value"] / s_d["value"]
+        value, ms_per_step, roof, stats_main = s_l["value"], s_l["ms_per_step"], s_l["roofline"], s_l["shower_stats"]
+        kw_main, mode_main = dict(kw_l, retain=retain), binding.MODE_LEARNED
+    out["autotune"] = autotune
+
+    if not args.lite:
+        # ---- the batched-stream configuration: the same events in uneven
+        # batches (sizes uniform in [10^4, 5*10^5], seed 1), views of the
+        # records above split where they cross a record's end
+        sizes = workloads.batch_sizes(n * K, seed=1)
+        ub, pos = [], 0
+        for m in sizes:
+            while m > 0:
+                k, off = divmod(pos, n)
+                take = min(m, n - off)
+                ub.append((ins[k].view(off, take), outs[k].view(off, take), take))
+                pos += take
+                m -= take
+        r = timed_stream(G, binding, ub, seed, args, kw_main, mode_main)
+        s_u = summarise(r, outs, kernel, "learned" if mode_main == binding.MODE_LEARNED else "plain", K)
+        out["stream_uneven"] = {"value": s_u["value"], "value_min": s_u["value_min"], "value_max": s_u["value_max"],
+                                "batch_sizes": len(sizes), "stream_batches": len(ub),
+                                "active_lane_fraction": s_u["shower_stats"]["active_lane_fraction"],
+                                "launch_ms": s_u["roofline"]["launch_ms"],
+                                "mode": "learned" if mode_main == binding.MODE_LEARNED else "plain"}
+        log(f"uneven stream: {s_u['value']:.4g} events/s")
+
+        # ---- the paper's form of the competition on the same batches
+        pf = {"kernel": "k_shower_wave"}
         for md, nm in ((binding.MODE_PLAIN, "plain"), (binding.MODE_LEARNED, "learned")):
             if md == binding.MODE_LEARNED and args.mode != "learned":
                 continue
-            r = timed_stream(G, binding, batches, seed, args, kw_p, md)
-            v, ms, rf, st = summarise(r, nm, kname_p)
-            log(f"paper form {nm}: {v:.4g} events/s")
-            pf[nm] = {"value": v, "ms_per_step": ms, "roofline": rf, "shower_stats": st}
-        out_extra["paper_form"] = pf
-    if args.mode == "learned" and not args.no_cellmax:
-        # the non-learned comparator: cell maxima of the same logged trials
-        t0 = time.perf_counter()
-        G.cellmax_table(log_rows, int(0.8 * log_rows.shape[0]))
-        torch.cuda.synchronize()
-        t_tab = time.perf_counter() - t0
-        r = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
-        v, ms, rf, st = summarise(r, "cellmax")
-        log(f"cell-maximum bound: {v:.4g} events/s")
-        out_extra["cellmax"] = {"value": v, "ms_per_step": ms, "speedup_over_plain": v / v_plain,
-                                "speedup_over_learned": v / v_l, "table_s": t_tab,
-                                "mean_bound_over_analytic": bound_over_analytic(G),
-                                "histogram_chi2_ndf_vs_plain": chi_vs_plain(h_plain, histos()),
-                                "roofline": rf, "shower_stats": st}
-        # the same with adaptive cell sizes (each cell from the finest block
-        # around it with enough logged trials)
-        t0 = time.perf_counter()
-        G.cellmax_table(log_rows, int(0.8 * log_rows.shape[0]), adaptive=True)
-        torch.cuda.synchronize()
-        t_tab = time.perf_counter() - t0
-        r = timed_stream(G, binding, batches, seed, args, kw, binding.MODE_LEARNED)
-        v, ms, rf, st = summarise(r, "cellmax_adaptive")
-        log(f"cell-maximum bound, adaptive cells: {v:.4g} events/s")
-        out_extra["cellmax_adaptive"] = {"value": v, "ms_per_step": ms, "speedup_over_plain": v / v_plain,
-                                         "speedup_over_learned": v / v_l, "table_s": t_tab,
-                                         "mean_bound_over_analytic": bound_over_analytic(G),
-                                         "histogram_chi2_ndf_vs_plain": chi_vs_plain(h_plain, histos()),
-                                         "roofline": rf, "shower_stats": st}
-    if args.mode == "learned":
+            if not retain:
+                break
+            s = summarise(timed_stream(G, binding, batches, seed, args, dict(retain=False), md), outs,
+                          "k_shower_wave", nm, K)
+            log(f"paper form {nm}: {s['value']:.4g} events/s")
+            pf[nm] = s
+        out["paper_form"] = pf
+
+        # ---- the non-learned comparators from the same logged trials
+        if args.mode == "learned":
+            for adaptive, key in ((False, "cellmax"), (True, "cellmax_adaptive")):
+                t0 = time.perf_counter()
+                G.cellmax_table(log_rows, int(0.8 * log_rows.shape[0]), adaptive=adaptive)
+                torch.cuda.synchronize()
+                t_tab = time.perf_counter() - t0
+                s = summarise(timed_stream(G, binding, batches, seed, args, kw_main, binding.MODE_LEARNED), outs,
+                              kernel, key, K)
+                log(f"{key}: {s['value']:.4g} events/s")
+                hist[key] = chi2(h_ref, histograms(G, [(o, n) for o in outs]))
+                out[key] = dict(s, speedup_over_plain=s["value"] / s_plain["value"],
+                                speedup_over_learned=s["value"] / out["learned"]["value"], table_s=t_tab,
+                                mean_bound_over_analytic=bound_over_analytic(G))
+            # back to the trained bound for the legs below
+            G.mlp_tabulate()
+        out["histograms"] = hist
         del log_rows
-    if not args.no_forms:
-        # the three forms of the competition section 2 names, on the same
-        # first two batches, plain, in the one-event-per-lane kernels (the
-        # other two forms run there only): max-veto with every channel
-        # redrawn, generate-select, veto-max
-        import argparse as _ap
-        a1 = _ap.Namespace(**vars(args))
-        a1.launch, a1.warmup = "per-step", 1
+
+        # ---- the paper's component table: hard events, shower, observables
+        # at 10^4, 10^5 and 10^6 events (views of the first batch)
+        t1 = {}
+        for m in (10_000, 100_000, 1_000_000):
+            if m > n:
+                continue
+            vi, vo = ins[0].view(0, m), outs[0].view(0, m)
+            row = {}
+            for what in ("hard", "shower_plain", "shower_" + args.mode, "observables"):
+                if what == "shower_learned" and args.mode != "learned":
+                    continue
+                ts = []
+                for r in range(args.repeats + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    if what == "hard":
+                        G.hard_events(0, m, seed, out=vi)
+                    elif what == "observables":
+                        histograms(G, [(vo, m)])
+                    else:
+                        md = binding.MODE_LEARNED if what == "shower_learned" else binding.MODE_PLAIN
+                        G.shower(vi, seed, n=m, out=vo, mode=md, **(kw_main if md == mode_main else
+                                                                    dict(kw_plain, retain=retain)))
+                    torch.cuda.synchronize()
+                    if r:
+                        ts.append(time.perf_counter() - t0)
+                row[what + "_s"] = float(np.median(ts))
+            t1[str(m)] = row
+        out["table1"] = t1
+
+        # ---- the three forms of the competition in the one-event-per-lane
+        # kernels (where the other two forms run), on the first two batches
         sub = batches[:2]
         forms = {"kernel": "k_shower_lanes", "events": sum(b[2] for b in sub)}
         for nm, kwf in (("max_veto", dict(variant=1)), ("generate_select", dict(variant=1, gen_select=True)),
                         ("veto_max", dict(variant=1, veto_max=True))):
-            r = timed_stream(G, binding, sub, seed, a1, kwf, binding.MODE_PLAIN)
-            st = r["stats"]
-            forms[nm] = {"value": r["events"] / r["wall_s"], "draws_per_event": st[1] / r["events"],
-                         "cycles_per_event": st[0] / r["events"], "accepted_per_event": st[2] / r["events"]}
+            ts = []
+            st = None
+            for r in range(3):
+                stt = torch.zeros(binding.NSTATS, dtype=torch.uint64, device="cuda")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for ev_in, ev_out, m in sub:
+                    G.shower(ev_in, seed, out=ev_out, stats=stt, **kwf)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                st = stt.cpu().numpy().astype(float)
+            ev = forms["events"]
+            forms[nm] = {"value": ev / float(np.median(ts[1:])), "draws_per_event": st[1] / ev,
+                         "cycles_per_event": st[0] / ev, "accepted_per_event": st[2] / ev}
             log(f"{nm} (one event per lane): {forms[nm]['value']:.4g} events/s")
-        out_extra["competition_forms"] = forms
-    if not args.no_matching:
-        # the matching variants: their own hard events (the same ids as the
-        # first two batches), the plain shower in the benchmark's launch
-        sub_n = [b[2] for b in batches[:2]]
-        nb = len(sub_n)
-        mt = {"events": int(sum(sub_n)), "kernel": kernel}
+        out["competition_forms"] = forms
+
+        # ---- the matching variants and the NLO Z/photon workload, plain, on
+        # their own hard events with the ids of the first two batches
+        mt = {"events": 2 * n, "kernel": kernel}
         for nm, wl in (("mcatnlo_start_mz2", workloads.PP_NLO_MUQ), ("powheg", workloads.PP_NLO_POWHEG),
                        ("dy_nlo", workloads.PP_DY_NLO)):
             Gm = binding.Gaps(workloads.config_dict(wl))
-            ins_m = [Gm.hard_events(int(a), int(m), seed, max_slots=8) for a, m in zip(starts[:nb], sub_n)]
-            sub = [(ins_m[k], outs[k], sub_n[k]) for k in range(nb)]
-            r = timed_stream(Gm, binding, sub, seed, args, kw, binding.MODE_PLAIN)
+            ins_m = [Gm.hard_events(k * n, n, seed, max_slots=8) for k in range(2)]
+            r = timed_stream(Gm, binding, [(ins_m[k], outs[k], n) for k in range(2)], seed, args,
+                             dict(kw_plain, retain=retain), binding.MODE_PLAIN, repeats=3)
             st = r["stats"]
             w = torch.cat([i.w for i in ins_m])
             mt[nm] = {"value": r["events"] / r["wall_s"], "cycles_per_event": st[0] / r["events"],
@@ -431,16 +539,15 @@ def main():
                       "sigma_per_event": float(w.mean().item()),
                       "negative_weight_fraction": float((w < 0).double().mean().item())}
             log(f"matching {nm}: {mt[nm]['value']:.4g} events/s")
-            del ins_m, sub
+            del ins_m
             Gm.close()
-        w0 = torch.cat([b[0].w for b in batches[:nb]])
-        mt["mcatnlo_power_shower_sigma_per_event"] = float(w0.mean().item())
-        # the second workload at NLO (pp -> Z/photon -> e+e-, power shower) is
-        # reported with them, beside the matchings of the first
-        out_extra["dy_nlo"] = mt.pop("dy_nlo")
-        out_extra["matching"] = mt
+        mt["mcatnlo_power_shower_sigma_per_event"] = float(torch.cat([b[0].w for b in batches[:2]]).mean().item())
+        out["dy_nlo"] = mt.pop("dy_nlo")
+        out["matching"] = mt
+        out["component_s"] = {"hard_events_per_step": out["table1"].get(str(n), {}).get("hard_s"),
+                              "shower_per_step": ms_per_step / 1e3, "observables_per_step": t_obs}
 
-    out = {
+    line = {
         "metric": "showered events/sec, NLO pp→Z 13 TeV, 1 MI355X; plain vs learned-proposal",
         "value": value,
         "unit": "events/s",
@@ -456,20 +563,17 @@ def main():
         "config": {"workload": "pp_nlo_1m: NLO-matched Z production at 13 TeV (MC@NLO-style S/H events, "
                                "toy PDF grid 100x50), one step = one batch of 10^6 events with its own ids, "
                                "FP64 kinematics, up to 128 partons per event",
-                   "events_per_step": n, "mode": args.mode, "trials": args.trials, "launch": args.launch,
-                   "batches": args.batches, "n_batches": len(batches),
-                   "max_slots": workloads.MAX_SLOTS, "kernel": kernel, "block": args.block or "auto",
-                   "compact_every": args.compact_every or 8},
+                   "events_per_step": n, "mode": args.mode, "trials": args.trials, "launch": "stream",
+                   "repeats": args.repeats, "max_slots": workloads.MAX_SLOTS, "kernel": kernel,
+                   "launch_shape": {k: v for k, v in kw_main.items() if k != "retain"}},
         "roofline": roof,
         "shower_stats": stats_main,
-        "component_s": {"hard_events_per_step": t_hard, "shower_per_step": ms_per_step / 1e3,
-                        "observables_per_step": t_obs},
     }
-    out.update(out_extra)
-    if not args.no_cpu:
+    line.update(out)
+    if not args.no_cpu and not args.lite:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, seed, args.trials == "retain")
-    print(json.dumps(out))
+        line["cpu_baseline"] = cpu_baseline(cfg, seed, retain, args.cpu_single, args.cpu_all)
+    print(json.dumps(line))
 
 
 if __name__ == "__main__":

@@ -306,6 +306,33 @@ gaps_status gaps_graph_capture(gaps_ctx ctx, const gaps_batch* batches, int nbat
 gaps_status gaps_graph_launch(gaps_graph g, hipStream_t stream);
 gaps_status gaps_graph_destroy(gaps_graph g);
 
+/* ---- Launch autotuner ----
+ * The paper tunes its kernels' block size by measurement (section 3.2) and
+ * finds where its event partitioning pays (section 3.1).  gaps_tune times the
+ * persistent streamed launch (gaps_shower_stream) over a caller's calibration
+ * batches for each candidate launch shape: threads per block, cycles between
+ * wave refills, resident waves per SIMD, and the fraction of the filling grid
+ * (the lanes in flight, whose working storage competes for the caches).  Each
+ * point is launched once untimed and then `repeats` times between HIP events
+ * on `stream`; its median time goes to ms and its resolved grid (blocks) to
+ * grid, so that gaps_params {block, grid, compact_every, waves_per_simd}
+ * reproduces it.  A point the kernels cannot run (a block or register budget
+ * outside gaps_params' limits) gets ms = -1.  The other fields of base (mode,
+ * retain, ...) apply to every point.  Synchronous (it reads the timings).
+ * The outputs of the batches are overwritten.  Errors: GAPS_EINVAL for a
+ * bad batch table, base, npoints < 1 or repeats < 1. */
+typedef struct {
+    int block;           /* threads per block (multiple of 64) */
+    int compact_every;   /* cycles between wave refills (> 0) */
+    int waves_per_simd;  /* 2 or 3 (retained trials), 2..4 otherwise */
+    float fill;          /* fraction (0, 1] of the grid that fills the GPU */
+    int grid;            /* out: blocks of the launch */
+    float ms;            /* out: median launch time, ms (-1: not runnable) */
+} gaps_tune_point;
+
+gaps_status gaps_tune(gaps_ctx ctx, const gaps_batch* batches, int nbatch, const gaps_params* base, uint64_t seed,
+                      gaps_tune_point* points, int npoints, int repeats, hipStream_t stream);
+
 /* ---- Learned initial-state veto bound (LEARNED mode) ----
  * The paper bounds the PDF ratio x kernel of initial-state emissions with
  * maxima fitted against eta (appendix A.2).  LEARNED mode replaces that

@@ -66,6 +66,11 @@ MLP_PARAMS = 4545
 LEARN_SHAPE = (64, 48, 8)
 
 
+class GapsTunePoint(C.Structure):
+    _fields_ = [("block", C.c_int), ("compact_every", C.c_int), ("waves_per_simd", C.c_int), ("fill", C.c_float),
+                ("grid", C.c_int), ("ms", C.c_float)]
+
+
 class GapsTrainParams(C.Structure):
     _fields_ = [("steps", C.c_int64), ("batch", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("tau", C.c_float), ("seed", C.c_uint64)]
@@ -92,6 +97,8 @@ def lib():
         L.gaps_shower_stream.argtypes = [vp, C.POINTER(GapsBatch), C.c_int, C.POINTER(GapsParams), u64, vp]
         L.gaps_graph_capture.argtypes = [vp, C.POINTER(GapsBatch), C.c_int, C.POINTER(GapsParams), u64, vp,
                                          C.POINTER(vp)]
+        L.gaps_tune.argtypes = [vp, C.POINTER(GapsBatch), C.c_int, C.POINTER(GapsParams), u64,
+                                C.POINTER(GapsTunePoint), C.c_int, C.c_int, vp]
         L.gaps_graph_launch.argtypes = [vp, vp]
         L.gaps_graph_destroy.argtypes = [vp]
         L.gaps_observables.argtypes = [vp, C.POINTER(GapsEvents), i64, vp, vp]
@@ -168,6 +175,38 @@ class DeviceEvents:
         for name in self.fields():
             getattr(ev, name)[...] = getattr(self, name).cpu().numpy()
         return ev
+
+    def view(self, start: int, n: int) -> "EventsView":
+        """Events start .. start+n-1 of this record, without a copy."""
+        return EventsView(self, start, n)
+
+
+class EventsView:
+    """A contiguous range of events of a DeviceEvents record, in place: its
+    fields are torch views, and its C-ABI description points at the range's
+    first event with the parent's stride (cap), so the library reads and
+    writes the parent's storage.  Pass its length `n` explicitly to the
+    library calls."""
+
+    def __init__(self, parent: DeviceEvents, start: int, n: int):
+        if start < 0 or n < 0 or start + n > parent.cap:
+            raise ValueError("view outside the record")
+        self.parent, self.start, self.n_events = parent, int(start), int(n)
+        self.cap, self.max_slots = parent.cap, parent.max_slots
+        for name in parent.fields():
+            t = getattr(parent, name)
+            setattr(self, name, t[start:start + n] if t.dim() == 1 else t[:, start:start + n])
+
+    def fields(self):
+        return self.parent.fields()
+
+    def struct(self) -> GapsEvents:
+        s = GapsEvents()
+        for name in self.fields():
+            t = getattr(self.parent, name)
+            setattr(s, name, t.data_ptr() + self.start * t.element_size())
+        s.max_slots, s.cap = self.max_slots, self.cap
+        return s
 
 
 class Gaps:
@@ -270,6 +309,21 @@ class Gaps:
         arr = self._batches(batches)
         p = self._params(**params)
         _check(lib().gaps_shower_stream(self.h, arr, len(batches), C.byref(p), seed, _stream(stream)))
+
+    def tune(self, batches, seed: int, points, repeats: int = 3, stream=None, **params):
+        """gaps_tune: time the streamed launch over `batches` for each point
+        (dicts with block, compact_every, waves_per_simd, fill); returns the
+        points with their resolved grid and median ms (-1: not runnable)."""
+        arr = self._batches(batches)
+        pts = (GapsTunePoint * len(points))()
+        for k, q in enumerate(points):
+            pts[k].block, pts[k].compact_every = int(q["block"]), int(q["compact_every"])
+            pts[k].waves_per_simd, pts[k].fill = int(q["waves_per_simd"]), float(q["fill"])
+        p = self._params(**params)
+        _check(lib().gaps_tune(self.h, arr, len(batches), C.byref(p), seed, pts, len(points), repeats,
+                               _stream(stream)))
+        return [dict(block=q.block, compact_every=q.compact_every, waves_per_simd=q.waves_per_simd,
+                     fill=round(float(q.fill), 4), grid=q.grid, ms=float(q.ms)) for q in pts]
 
     def capture(self, batches, seed: int, stream, **params) -> "Graph":
         """HIP graph of one shower_stream call, captured on `stream` (a side stream)."""

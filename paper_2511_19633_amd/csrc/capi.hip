@@ -507,6 +507,67 @@ gaps_status gaps_graph_capture(gaps_ctx c, const gaps_batch* batches, int nbatch
   return GAPS_OK;
 }
 
+gaps_status gaps_tune(gaps_ctx c, const gaps_batch* batches, int nbatch, const gaps_params* base, uint64_t seed,
+                      gaps_tune_point* pts, int npts, int repeats, hipStream_t stream) {
+  if (!c || !pts || npts < 1 || repeats < 1 || repeats > 64) return GAPS_EINVAL;
+  int64_t total = 0;
+  int slots = 0;
+  gaps_status s = check_batches(batches, nbatch, total, slots);
+  if (s != GAPS_OK) return s;
+  if (base && base->variant != 0) return GAPS_EINVAL;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return GAPS_EHIP;
+  }
+  gaps_status out = GAPS_OK;
+  float times[64];
+  for (int k = 0; k < npts && out == GAPS_OK; ++k) {
+    gaps_tune_point& q = pts[k];
+    q.grid = 0;
+    q.ms = -1.0f;
+    gaps_params P{};
+    if (base) P = *base;
+    P.block = q.block;
+    P.compact_every = q.compact_every;
+    P.waves_per_simd = q.waves_per_simd;
+    P.grid = 0;
+    P.stats = nullptr;
+    if (q.block <= 0 || q.compact_every <= 0 || !(q.fill > 0.0f && q.fill <= 1.0f)) continue;
+    Plan pl;
+    int64_t tot = 0;
+    s = prepare_stream(c, batches, nbatch, &P, seed, c->scratch, c->batches, pl, tot);
+    if (s == GAPS_EINVAL) continue;  // a shape the kernels cannot run
+    if (s != GAPS_OK) { out = s; break; }
+    if (tot == 0) { q.ms = 0.0f; continue; }
+    int64_t g = (int64_t)((double)pl.grid * (double)q.fill + 0.5);
+    pl.grid = g < 1 ? 1 : g;
+    q.grid = (int)pl.grid;
+    s = store_batches(batches, nbatch, tot, c->batches, stream);
+    for (int r = 0; r <= repeats && s == GAPS_OK; ++r) {
+      if (hipEventRecord(e0, stream) != hipSuccess) { s = GAPS_EHIP; break; }
+      s = launch_shower(c, pl, nullptr, nullptr, c->scratch.S, stream);
+      if (s != GAPS_OK) break;
+      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { s = GAPS_EHIP; break; }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { s = GAPS_EHIP; break; }
+      if (r > 0) times[r - 1] = ms;  // the first launch is a warm-up
+    }
+    if (s != GAPS_OK) { out = s; break; }
+    // median of the timed launches (insertion sort of at most 64)
+    for (int i = 1; i < repeats; ++i)
+      for (int j = i; j > 0 && times[j - 1] > times[j]; --j) {
+        const float t = times[j];
+        times[j] = times[j - 1];
+        times[j - 1] = t;
+      }
+    q.ms = repeats % 2 ? times[repeats / 2] : 0.5f * (times[repeats / 2 - 1] + times[repeats / 2]);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return out;
+}
+
 gaps_status gaps_graph_launch(gaps_graph g, hipStream_t stream) {
   if (!g || !g->exec) return GAPS_EINVAL;
   GAPS_HIP(hipGraphLaunch(g->exec, stream));

@@ -76,3 +76,12 @@ def test_config_and_cellmax_argument_errors():
     for fn in (lib.gaps_cellmax_table, lib.gaps_cellmax_table_adaptive):
         fn.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
         assert fn(None, None, 10, 0, None) == -1
+
+
+def test_noalloc_and_tune_argument_errors():
+    from paper_2511_19633_amd import binding
+    lib = binding.lib()
+    assert lib.gaps_shower_noalloc(None, None, 0, None, 0, None, None) == -1
+    pts = (binding.GapsTunePoint * 1)()
+    assert lib.gaps_tune(None, None, 0, None, 0, pts, 1, 3, None) == -1
+    assert C.sizeof(binding.GapsTunePoint) == 24
