@@ -24,6 +24,7 @@ typedef struct { int kern, shape, flav, ent; double coefR, c, mul; } term_t;
 
 typedef struct {
     int i, k, side, type, alive, heavy, ebin, mec;
+    int shared; /* an incoming gluon: the terms after the first share one shape */
     double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
     double zlo, zhi, omzlo, omzhi;
     int nterm;
@@ -83,6 +84,55 @@ static double shape_val(int sh, double z, double omz) {
     case SH_S1: return 1.0 / (z * omz);
     default: return 1.0 / z;
     }
+}
+
+/* The overestimate constant of a channel is the sum over its terms of
+ * af R_m I_m (appendix A.1: alpha_s(t_c)/(2 pi), the term's PDF-ratio and
+ * kernel bound R_m, the z integral I_m of its shape).  The terms of an
+ * incoming gluon after the first (g <- q for every quark flavour) all have the
+ * same shape, and their part is taken as one product, af (sum of their R_m) I
+ * (R summed in term order).  The running sum that picks the winner's term is
+ * written the same way.  R: each term's constant (table value times mul). */
+static double terms_total(const or_state* S, const chan_t* ch, const double* R) {
+    const double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
+    if (ch->shared) {
+        double sum = 0.0;
+        for (int m = 1; m < ch->nterm; ++m) sum += R[m];
+        return af * R[0] * shape_int(ch->term[0].shape, ch) + af * sum * shape_int(ch->term[1].shape, ch);
+    }
+    double c = 0.0;
+    for (int m = 0; m < ch->nterm; ++m) c += af * R[m] * shape_int(ch->term[m].shape, ch);
+    return c;
+}
+
+/* the first term whose running sum of constants exceeds target (-1: none) */
+static int terms_pick(const or_state* S, const chan_t* ch, const double* R, double target) {
+    const double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
+    if (ch->shared) {
+        const double c0 = af * R[0] * shape_int(ch->term[0].shape, ch);
+        if (target < c0) return 0;
+        const double I = shape_int(ch->term[1].shape, ch);
+        double sum = 0.0;
+        for (int m = 1; m < ch->nterm; ++m) {
+            sum += R[m];
+            if (target < c0 + af * sum * I) return m;
+        }
+        return -1;
+    }
+    double cum = 0.0;
+    for (int m = 0; m < ch->nterm; ++m) {
+        cum += af * R[m] * shape_int(ch->term[m].shape, ch);
+        if (target < cum) return m;
+    }
+    return -1;
+}
+
+/* if rounding leaves a draw past every term: the last term of positive
+ * (analytic) constant */
+static int terms_last(const chan_t* ch) {
+    for (int m = ch->nterm - 1; m >= 0; --m)
+        if (ch->term[m].c > 0.0) return m;
+    return 0;
 }
 
 static void add_term(chan_t* ch, int kern, int shape, int flav, double coefR, int ent) {
@@ -203,12 +253,14 @@ static void setup_channel(const or_state* S, const ev_t* e, int i, int side, int
         }
     }
     double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
-    double c = 0.0;
+    double R[12];
+    ch->shared = isE && e->pid[i] == 21;
     for (int m = 0; m < ch->nterm; ++m) {
         term_t* t = &ch->term[m];
         t->c = af * t->coefR * shape_int(t->shape, ch);
-        c += t->c;
+        R[m] = t->coefR;
     }
+    double c = terms_total(S, ch, R);
     if (!(c > 0.0)) return;
     ch->c = c;
     ch->invc = 1.0 / c;
@@ -529,14 +581,15 @@ static int cell_of(const or_state* S, double lnt) {
     return k;
 }
 
+/* the terms' learned constants in cell k */
+static void learned_R(const chan_t* ch, const double* L, int k, double* R) {
+    for (int m = 0; m < ch->nterm; ++m) R[m] = lrn(L, ch->term[m].ent, ch->ebin, k) * ch->term[m].mul;
+}
+
 static double learned_c(const or_state* S, const chan_t* ch, const double* L, int k) {
-    double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
-    double c = 0.0;
-    for (int m = 0; m < ch->nterm; ++m) {
-        const term_t* t = &ch->term[m];
-        c += af * lrn(L, t->ent, ch->ebin, k) * t->mul * shape_int(t->shape, ch);
-    }
-    return c;
+    double R[12];
+    learned_R(ch, L, k, R);
+    return terms_total(S, ch, R);
 }
 
 /* trial log shared by the threads of one or_shower_ex call */
@@ -713,20 +766,15 @@ static step_t winner(sh_t* r, const chan_t* C, double t, int lch, int wcell) {
     step_t st;
     double u[4];
     or_rng_block(r->seed, r->stream, r->id, r->cycle, 0xFFFFFFFFu, u);
-    double af = S->as_over / (2.0 * OR_PI) * S->c.over_scale;
-    double ctot = lch ? learned_c(S, C, Lt, wcell) : C->c;
-    double target = u[0] * ctot, cum = 0.0;
-    int sel = -1;
-    for (int m = 0; m < C->nterm; ++m) {
-        cum += lch ? af * lrn(Lt, C->term[m].ent, C->ebin, wcell) * C->term[m].mul * shape_int(C->term[m].shape, C)
-                   : C->term[m].c;
-        if (target < cum) { sel = m; break; }
-    }
-    if (sel < 0)
-        for (int m = C->nterm - 1; m >= 0; --m)
-            if (C->term[m].c > 0.0) { sel = m; break; }
+    double R[12];
+    if (lch) learned_R(C, Lt, wcell, R);
+    else
+        for (int m = 0; m < C->nterm; ++m) R[m] = C->term[m].coefR;
+    const double ctot = lch ? terms_total(S, C, R) : C->c;
+    int sel = terms_pick(S, C, R, u[0] * ctot);
+    if (sel < 0) sel = terms_last(C);
     st.tm = C->term[sel];
-    if (lch) st.tm.coefR = lrn(Lt, st.tm.ent, C->ebin, wcell) * st.tm.mul;
+    st.tm.coefR = R[sel];
     double I = shape_int(st.tm.shape, C);
     shape_sample(st.tm.shape, C, I, u[1], &st.z, &st.omz);
     st.phi = 2.0 * OR_PI * u[2];
@@ -975,15 +1023,10 @@ static void run_gen_select(sh_t* r) {
  * from the four numbers u (plain mode); returns whether it is accepted */
 static int vm_veto(const or_state* S, const ev_t* ev, const chan_t* C, double t, const double* u, term_t* tsel,
                    double* z, double* omz, double* phi, veto_t* v) {
-    double target = u[0] * C->c, cum = 0.0;
-    int sel = -1;
-    for (int m = 0; m < C->nterm; ++m) {
-        cum += C->term[m].c;
-        if (target < cum) { sel = m; break; }
-    }
-    if (sel < 0)
-        for (int m = C->nterm - 1; m >= 0; --m)
-            if (C->term[m].c > 0.0) { sel = m; break; }
+    double R[12] = {0.0};
+    for (int m = 0; m < C->nterm; ++m) R[m] = C->term[m].coefR;
+    int sel = terms_pick(S, C, R, u[0] * C->c);
+    if (sel < 0) sel = terms_last(C);
     *tsel = C->term[sel];
     shape_sample(tsel->shape, C, shape_int(tsel->shape, C), u[1], z, omz);
     *phi = 2.0 * OR_PI * u[2];

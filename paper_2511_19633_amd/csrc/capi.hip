@@ -36,12 +36,12 @@ struct ScratchMem {
 // bytes of per-lane working storage for events of `slots` slots
 size_t scratch_per_lane(int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
-  return (size_t)slots * sizeof(gaps::Part) + (size_t)nch * (sizeof(gaps::Trial) + sizeof(gaps::Win)) +
-         sizeof(double);
+  return (size_t)slots * sizeof(gaps::Part) +
+         (size_t)nch * (sizeof(gaps::Ent) + sizeof(double)) + sizeof(double);
 }
 
 // bytes the working storage of `lanes` lanes needs, alignment included
-size_t scratch_bytes(int64_t lanes, int slots) { return scratch_per_lane(slots) * (size_t)lanes + 256 * 32 + 64; }
+size_t scratch_bytes(int64_t lanes, int slots) { return scratch_per_lane(slots) * (size_t)lanes + 256 * 8 + 64; }
 
 // Lay out the working storage of `lanes` lanes over [base, base + bytes).
 gaps_status scratch_layout(char* base, size_t bytes, int64_t lanes, int slots, gaps::Scratch& S) {
@@ -57,8 +57,8 @@ gaps_status scratch_layout(char* base, size_t bytes, int64_t lanes, int slots, g
   const size_t ps = (size_t)slots * lanes, cs = (size_t)nch * lanes;
   S.part = (gaps::Part*)take(ps * sizeof(gaps::Part));
   S.nch = nch;
-  S.ctr = (gaps::Trial*)take(cs * sizeof(gaps::Trial));
-  S.cwin = (gaps::Win*)take(cs * sizeof(gaps::Win));
+  S.ent = (gaps::Ent*)take(cs * sizeof(gaps::Ent));
+  S.key = (double*)take(cs * sizeof(double));
   S.wfac = (double*)take((size_t)lanes * sizeof(double));
   S.queue = (unsigned long long*)take(64);
   return (size_t)(p - base) > bytes ? GAPS_ECAPACITY : GAPS_OK;
@@ -144,7 +144,7 @@ struct gaps_ctx_s {
   void* mlp_mem = nullptr;
   float *theta = nullptr, *mom1 = nullptr, *mom2 = nullptr, *grad = nullptr;
   uint16_t* wb = nullptr;
-  double *delta = nullptr, *table = nullptr;
+  double *delta = nullptr, *table = nullptr, *table_sd = nullptr;
   unsigned long long *maxbits = nullptr, *count = nullptr;
   float *probe_x = nullptr, *probe_f = nullptr;
   // cell-maximum bound: per-cell largest target and row count, per-entry
@@ -198,7 +198,7 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   if (resolve_static_scratch(c->device) != GAPS_OK) { delete c; return GAPS_EHIP; }
   size_t npdf = (size_t)cfg->ntab * cfg->nq * cfg->nx;
   if (hipMalloc(&c->d_pdf, npdf * sizeof(float)) != hipSuccess ||
-      hipMalloc(&c->d_bound, (gaps::kNEnt + 8) * gaps::kNB * sizeof(double)) != hipSuccess) {
+      hipMalloc(&c->d_bound, gaps::kBoundRows * gaps::kNB * sizeof(double)) != hipSuccess) {
     gaps_destroy(c);
     return GAPS_ENOMEM;
   }
@@ -237,6 +237,7 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   // the overestimate table, computed on the device
   int nthr = (gaps::kNEnt + 8) * gaps::kNB;
   hipLaunchKernelGGL(gaps::k_bounds, dim3(grid_for(nthr, 64)), dim3(64), 0, 0, C, c->d_bound);
+  hipLaunchKernelGGL(gaps::k_bound_sums, dim3(grid_for(2 * gaps::kNB, 64)), dim3(64), 0, 0, C, c->d_bound);
   if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     gaps_destroy(c);
     return GAPS_EHIP;
@@ -639,11 +640,22 @@ namespace {
 
 constexpr int kNP = gaps::kMlpParams;
 
+// Make the context's learned table the one LEARNED mode reads, with its
+// g <- q sums (stream-ordered after the table's writers on `stream`).
+gaps_status learn_enable(gaps_ctx c, hipStream_t stream) {
+  const int n = 2 * gaps::kNB * gaps::kNTB;
+  hipLaunchKernelGGL(gaps::k_learn_sums, dim3(grid_for(n, 128)), dim3(128), 0, stream, c->C, c->table, c->table_sd);
+  GAPS_HIP(hipGetLastError());
+  c->C.learn = c->table;
+  c->C.learn_sd = c->table_sd;
+  return GAPS_OK;
+}
+
 gaps_status mlp_alloc(gaps_ctx c) {
   if (c->mlp_mem) return GAPS_OK;
   const size_t fl = ((size_t)kNP * 4 + 255) & ~(size_t)255;
   const size_t need = 4 * fl + (((size_t)kNP * 2 + 255) & ~(size_t)255) + 64 * 8 +
-                      (size_t)GAPS_LEARN_CELLS * 8 + 2 * 64 * 8 + 1024;
+                      (size_t)GAPS_LEARN_CELLS * 8 + 2 * gaps::kNB * gaps::kNTB * 8 + 2 * 64 * 8 + 1280;
   if (hipMalloc(&c->mlp_mem, need) != hipSuccess) return GAPS_ENOMEM;
   char* p = (char*)c->mlp_mem;
   auto take = [&](size_t bytes) {
@@ -658,6 +670,7 @@ gaps_status mlp_alloc(gaps_ctx c) {
   c->wb = (uint16_t*)take((size_t)kNP * 2);
   c->delta = (double*)take(64 * 8);
   c->table = (double*)take((size_t)GAPS_LEARN_CELLS * 8);
+  c->table_sd = (double*)take(2 * gaps::kNB * gaps::kNTB * 8);
   c->maxbits = (unsigned long long*)take(64 * 8);
   c->count = (unsigned long long*)take(64 * 8);
   return GAPS_OK;
@@ -828,8 +841,7 @@ gaps_status gaps_mlp_tabulate(gaps_ctx c, hipStream_t stream) {
   hipLaunchKernelGGL(gaps::k_mlp_table, dim3(grid_for(GAPS_LEARN_CELLS, 256)), dim3(256), 0, stream, c->probe_f,
                      c->delta, c->d_bound, c->table);
   GAPS_HIP(hipGetLastError());
-  c->C.learn = c->table;
-  return GAPS_OK;
+  return learn_enable(c, stream);
 }
 
 static gaps_status cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, int64_t n_cal, bool adaptive,
@@ -861,8 +873,7 @@ static gaps_status cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, i
   hipLaunchKernelGGL(gaps::k_cellmax_table, dim3(grid_for(nc, 256)), dim3(256), 0, stream, ymax, cnt, lvl, emax, ecnt,
                      (long long)GAPS_CELLMAX_MIN_CELL, (long long)GAPS_CELLMAX_MIN_CAL, 0.015625, c->d_bound, c->table);
   GAPS_HIP(hipGetLastError());
-  c->C.learn = c->table;
-  return GAPS_OK;
+  return learn_enable(c, stream);
 }
 
 gaps_status gaps_cellmax_table(gaps_ctx c, const float* rows, int64_t n_fit, int64_t n_cal, hipStream_t stream) {
@@ -900,7 +911,9 @@ gaps_status gaps_learned_set_table(gaps_ctx c, const double* host_table) {
   if (!ok) return GAPS_EINVAL;
   GAPS_HIP(hipDeviceSynchronize());
   GAPS_HIP(hipMemcpy(c->table, host_table, (size_t)GAPS_LEARN_CELLS * 8, hipMemcpyHostToDevice));
-  c->C.learn = c->table;
+  const gaps_status st = learn_enable(c, nullptr);
+  if (st != GAPS_OK) return st;
+  GAPS_HIP(hipDeviceSynchronize());
   return GAPS_OK;
 }
 

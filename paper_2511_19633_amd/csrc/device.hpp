@@ -25,6 +25,12 @@ __host__ __device__ constexpr int ent_fi(int T) { return T; }
 __host__ __device__ constexpr int ent_s1(int f, int T) { return 8 + 8 * f + T; }
 __host__ __device__ constexpr int ent_s3(int f, int T) { return 40 + 8 * f + T; }
 
+// Rows of the bound table after the entries and the corrected family-B rows:
+// per eta bin the sums, in term order, of an initial-state gluon's g <- q
+// constants (the D entries of every flavour) at an IF and at an II end
+constexpr int kSumIF = kNEnt + 8, kSumII = kNEnt + 9;
+constexpr int kBoundRows = kNEnt + 10;
+
 // learned bound: initial-state entries kIS0.. (kNIS of them), kNTB cells in ln t
 constexpr int kIS0 = 8;
 constexpr int kNIS = 64;
@@ -60,9 +66,11 @@ struct Cfg {
   double mu_q2;
   double cell_edge[kNTB + 1];  // ln t edges of the learned-bound cells
   const float* pdf;      // [8][nq][nx]
-  const double* bound;   // [72 + 8][48]: the entries, then family B under the
-                         // first-emission correction by the quark's PDF table
+  const double* bound;   // [kBoundRows][48]: the entries, family B under the
+                         // first-emission correction by the quark's PDF table,
+                         // and the gluon's g <- q sums (kSumIF, kSumII)
   const double* learn;   // [64][48][8] learned bound (LEARNED mode), or null
+  const double* learn_sd;  // [2][48][8] its g <- q sums (IF, II) per eta bin and cell
 };
 
 // ---------------------------------------------------------------------------
@@ -327,73 +335,87 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
   return t;
 }
 
-// Initial-state channels (type IF or II) whose emitter has flavour pidi, from a
-// table of per-term constants R(entry): the terms in the order term_at
-// enumerates them (family A then B for a quark; C then D over the flavours
-// 1..nf, -1..-nf for a gluon).  Every term's constant is loaded first
-// (independent loads), then the products are summed in term order: the total
-// constant c, or the term a uniform draw of c picks.
-template <class Tab>
-__device__ __forceinline__ int is_terms_load(const Cfg& C, int type, int pidi, Tab R_of, double (&R)[kMaxTerms],
-                                             bool mec) {
-  const bool ii = type == kII;
-  if (pidi == 21) {
-    const int nt = 1 + 2 * C.nf;
-    R[0] = R_of(ent_s1(famC, 0));
-#pragma unroll
-    for (int m = 1; m < kMaxTerms; ++m) {
-      R[m] = 0.0;
-      if (m < nt) {
-        const int a = m <= C.nf ? m : -(m - C.nf);
-        const int T = pdf_tab(a);
-        R[m] = R_of(ii ? ent_s3(famD, T) : ent_s1(famD, T));
-      }
-    }
-    return nt;
-  }
-  const int T = pdf_tab(pidi);
-  R[0] = R_of(ent_s1(famA, T));
-  // a corrected channel's family B: the corrected table (entry kNEnt + T)
-  R[1] = R_of(mec ? kNEnt + T : (ii ? ent_s3(famB, T) : ent_s1(famB, T)));
-#pragma unroll
-  for (int m = 2; m < kMaxTerms; ++m) R[m] = 0.0;
-  return 2;
+// Entry of the m-th g <- q term of an initial-state gluon (m = 1 .. 2 nf):
+// flavours 1..nf, then -1..-nf.
+__device__ __forceinline__ int gluon_d_entry(const Cfg& C, bool ii, int m) {
+  const int a = m <= C.nf ? m : -(m - C.nf);
+  const int T = pdf_tab(a);
+  return ii ? ent_s3(famD, T) : ent_s1(famD, T);
 }
 
+// The channel's constant c: the sum over its terms of af R_m I_m.  A quark's
+// two terms are added in order; the terms of a gluon after the first (g <- q
+// for every flavour) share one z shape, so their part is af (sum of their R
+// in term order) I2, the sum being a precomputed row (kSumIF, kSumII) of the
+// table R_of reads.
 template <class Tab>
 __device__ __forceinline__ double is_terms_c(const Cfg& C, int type, int pidi, double I1, double I2, Tab R_of,
                                              bool mec) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
-  double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
+  const bool ii = type == kII;
+  if (pidi == 21) {
+    const double R0 = R_of(ent_s1(famC, 0)), sum = R_of(ii ? kSumII : kSumIF);
+    return af * R0 * I1 + af * sum * I2;
+  }
+  const int T = pdf_tab(pidi);
+  const double RA = R_of(ent_s1(famA, T));
+  // a corrected channel's family B: the corrected table (entry kNEnt + T)
+  const double RB = R_of(mec ? kNEnt + T : (ii ? ent_s3(famB, T) : ent_s1(famB, T)));
   double c = 0.0;
-  c += af * R[0] * I1;
-#pragma unroll
-  for (int m = 1; m < kMaxTerms; ++m)
-    if (m < nt) c += af * R[m] * I2;
+  c += af * RA * I1;
+  c += af * RB * I2;
   return c;
 }
 
 // The term of an initial-state channel whose running sum of constants (in
-// term order) first exceeds target, and its constant; -1 if none does.
+// term order, written as in is_terms_c) first exceeds target, and its
+// constant; -1 if none does.  A gluon's g <- q constants are loaded only when
+// the draw passes its first term.
 template <class Tab>
 __device__ __forceinline__ int is_terms_pick(const Cfg& C, int type, int pidi, double I1, double I2, double target,
                                              Tab R_of, bool mec, double& Rsel) {
   const double af = C.as_over / (2.0 * kPi) * C.over_scale;
-  double R[kMaxTerms];
-  const int nt = is_terms_load(C, type, pidi, R_of, R, mec);
+  const bool ii = type == kII;
   int sel = -1;
   Rsel = 0.0;
-  double cum = 0.0;
-  cum += af * R[0] * I1;
-  if (target < cum) { sel = 0; Rsel = R[0]; }
-#pragma unroll
-  for (int m = 1; m < kMaxTerms; ++m)
-    if (sel < 0 && m < nt) {
-      cum += af * R[m] * I2;
-      if (target < cum) { sel = m; Rsel = R[m]; }
+  if (pidi == 21) {
+    const double R0 = R_of(ent_s1(famC, 0));
+    const double c0 = af * R0 * I1;
+    if (target < c0) {
+      Rsel = R0;
+      return 0;
     }
+    double R[kMaxTerms];
+    const int nt = 1 + 2 * C.nf;
+#pragma unroll
+    for (int m = 1; m < kMaxTerms; ++m) R[m] = m < nt ? R_of(gluon_d_entry(C, ii, m)) : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int m = 1; m < kMaxTerms; ++m)
+      if (sel < 0 && m < nt) {
+        sum += R[m];
+        if (target < c0 + af * sum * I2) { sel = m; Rsel = R[m]; }
+      }
+    return sel;
+  }
+  const int T = pdf_tab(pidi);
+  const double RA = R_of(ent_s1(famA, T));
+  const double RB = R_of(mec ? kNEnt + T : (ii ? ent_s3(famB, T) : ent_s1(famB, T)));
+  double cum = 0.0;
+  cum += af * RA * I1;
+  if (target < cum) { sel = 0; Rsel = RA; }
+  cum += af * RB * I2;
+  if (sel < 0 && target < cum) { sel = 1; Rsel = RB; }
   return sel;
+}
+
+// the sum, in term order, of the g <- q constants of a gluon at an IF (ii
+// false) or II end, from a table of per-entry constants
+template <class Tab>
+__device__ __forceinline__ double gluon_d_sum(const Cfg& C, bool ii, Tab R_of) {
+  double sum = 0.0;
+  for (int m = 1; m < 1 + 2 * C.nf; ++m) sum += R_of(gluon_d_entry(C, ii, m));
+  return sum;
 }
 
 // Channel constants of dipole end (i, side) with spectator k: invariant,
@@ -487,6 +509,7 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
 // (an entry kNEnt + T, family B under the first-emission correction: the
 // learned family-B constant times kMecB, the correction's largest value)
 __device__ __forceinline__ double learned_R(const Cfg& C, int ent, int ebin, int k) {
+  if (ent >= kSumIF) return C.learn_sd[((ent - kSumIF) * kNB + ebin) * kNTB + k];
   const bool mec = ent >= kNEnt;
   const double v = C.learn[(((mec ? ent_s3(famB, ent - kNEnt) : ent) - kIS0) * kNB + ebin) * kNTB + k];
   return mec ? v * kMecB : v;

@@ -100,6 +100,23 @@ __device__ double mec_bmax_range(double lo, double hi) {
 // entries 0 .. kNEnt-1 of the table, then kNEnt + T: family B at the
 // initial-initial end (shape 3) while the first-emission correction applies
 // (kind 4: the kernel bound times the correction's largest value)
+// The rows kSumIF, kSumII of the bound table: per eta bin the sum, in term
+// order, of an initial-state gluon's g <- q entries (after k_bounds).
+__global__ void k_bound_sums(Cfg C, double* bound) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * kNB) return;
+  const int ii = t / kNB, bin = t % kNB;
+  bound[(kSumIF + ii) * kNB + bin] = gluon_d_sum(C, ii != 0, [&](int ent) { return bound[ent * kNB + bin]; });
+}
+
+// The same sums of a learned table [64][48][8], per eta bin and ln t cell.
+__global__ void k_learn_sums(Cfg C, const double* learn, double* sd) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * kNB * kNTB) return;
+  const int ii = t / (kNB * kNTB), bin = (t / kNTB) % kNB, k = t % kNTB;
+  sd[t] = gluon_d_sum(C, ii != 0, [&](int ent) { return learn[((ent - kIS0) * kNB + bin) * kNTB + k]; });
+}
+
 __global__ void k_bounds(Cfg C, double* bound) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (kNEnt + 8) * kNB) return;

@@ -6,16 +6,17 @@
 
 namespace gaps {
 
-// Trial data of a channel cache entry (48 bytes): the kinematic limit t_lim
+// Trial data of a channel cache entry (32 bytes): the kinematic limit t_lim
 // and its log, 1/c of the current overestimate (of the current cell in learned
-// mode), the pending trial ln t of the retained form (-inf: none above the
-// cutoff), and the info word (alive | type << 1 | heavy << 3 | spectator << 5 |
+// mode), and the info word (alive | type << 1 | heavy << 3 | spectator << 5 |
 // eta bin << 13 | spectator eta bin << 19 | learned cell << 25 | null << 29).
+// The pending trial keys of the retained form sit in an array of their own
+// (Scratch::key), which is all the argmax scan reads.
 struct alignas(16) Trial {
-  double tl, ltl, ic, key;
-  uint32_t info, pad0, pad1, pad2;
+  double tl, ltl, ic;
+  uint32_t info, pad0;
 };
-static_assert(sizeof(Trial) == 48, "trial record layout");
+static_assert(sizeof(Trial) == 32, "trial record layout");
 
 // Winner data of a channel cache entry, contiguous (80 bytes: one or two cache
 // lines per entry): the total overestimate constant c (in learned mode the
@@ -29,6 +30,15 @@ struct Win {
 };
 static_assert(sizeof(Win) == 80, "winner record layout");
 
+// One channel cache entry: its winner and trial data side by side in one
+// 128-byte line, so that the winner of a cycle (and its redraw) reads one line.
+struct alignas(128) Ent {
+  Win w;
+  Trial t;
+  uint32_t pad[4];
+};
+static_assert(sizeof(Ent) == 128, "channel cache entry layout");
+
 // Per-lane working storage of the shower kernels: event records and channel
 // caches, slot-major with stride = number of lanes (coalesced across a wave).
 struct Scratch {
@@ -36,11 +46,14 @@ struct Scratch {
   int max_slots;
   Part* part;  // working event records (lane-major in the wave kernels: one event's partons adjacent)
   // channel cache [lanes][nch]: one event's entries contiguous (the wave's
-  // passes give consecutive lanes consecutive entries of an event), as a
-  // trial record and a winner record per entry
+  // passes give consecutive lanes consecutive entries of an event), one line
+  // of winner and trial data per entry
   int nch;             // entries per event: 2 max_slots rounded up to a multiple of 4
-  struct Trial* ctr;
-  struct Win* cwin;
+  struct Ent* ent;
+  // pending trial key ln t of each entry (retained form; -inf: none above the
+  // cutoff), [lanes][nch] like the records: an event's keys are contiguous, so
+  // the argmax scan reads 8 bytes per entry
+  double* key;
   // weight factor of the event in each state slot, written by the weighted
   // veto of a violated learned bound (valid while the event's flags carry
   // fFallback)
@@ -75,6 +88,8 @@ __global__ void k_rng_blocks(uint64_t seed, uint32_t stream, const int64_t* id, 
 __global__ void k_pdf_eval(Cfg C, const int32_t* tab, const double* x, const double* q2, int64_t n,
                            double* out);
 __global__ void k_bounds(Cfg C, double* bound);
+__global__ void k_bound_sums(Cfg C, double* bound);
+__global__ void k_learn_sums(Cfg C, const double* learn, double* sd);
 __global__ void k_lo_scan(Cfg C, double* w);
 __global__ void k_lo_max(const double* w, int n, double* out);
 __global__ void k_hard(Cfg C, int64_t first_id, int64_t n, uint64_t seed, gaps_events o);

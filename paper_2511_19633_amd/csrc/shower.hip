@@ -35,11 +35,11 @@ __device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& 
       if (k < 0) return -1;
       chan_setup(C, R, i, side, k, ch, mec);
       int64_t oc = (int64_t)R.lane * S.nch + m;
-      S.ctr[oc].info = pack_info(ch);
-      S.ctr[oc].tl = ch.tlim;
-      S.ctr[oc].ltl = ch.lntlim;
-      S.ctr[oc].ic = ch.invc;
-      S.ctr[oc].key = ch.c;  // this kernel keeps no pending trials: the slot holds c
+      S.ent[oc].t.info = pack_info(ch);
+      S.ent[oc].t.tl = ch.tlim;
+      S.ent[oc].t.ltl = ch.lntlim;
+      S.ent[oc].t.ic = ch.invc;
+      S.key[oc] = ch.c;  // this kernel keeps no pending trials: the slot holds c
       ++m;
     }
   }
@@ -110,14 +110,14 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       bool capped = false;
       for (int c = 0; c < nch && !capped; ++c) {
         const int64_t oc = (int64_t)R.lane * S.nch + c;
-        const uint32_t info = S.ctr[oc].info;
+        const uint32_t info = S.ent[oc].t.info;
         if (!((info >> 21) & 1u)) continue;
         double tcut, lntcut, m2;
         const int heavy = (info >> 19) & 3u;
         chan_cut(C, (info >> 17) & 3u, heavy, tcut, lntcut, m2);
-        double Tch = S.ctr[oc].tl, lnTch = S.ctr[oc].ltl;
+        double Tch = S.ent[oc].t.tl, lnTch = S.ent[oc].t.ltl;
         if (T < Tch) { Tch = T; lnTch = lnT; }
-        const double invc = S.ctr[oc].ic;
+        const double invc = S.ent[oc].t.ic;
         Chan ch;
         chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
         for (int k = 0;; ++k) {
@@ -159,7 +159,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       if (capped) { flags |= fMaxCyc; break; }
       if (win < 0) break;
       // the winner's accepted trial, as recorded
-      const uint32_t info = S.ctr[(int64_t)R.lane * S.nch + win].info;
+      const uint32_t info = S.ent[(int64_t)R.lane * S.nch + win].t.info;
       Chan ch;
       chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
       const double t = exp(best);
@@ -194,14 +194,14 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         bool any = false;
         for (int c = 0; c < nch; ++c) {
           const int64_t oc = (int64_t)R.lane * S.nch + c;
-          const uint32_t info = S.ctr[oc].info;
+          const uint32_t info = S.ent[oc].t.info;
           if (!((info >> 21) & 1u)) continue;
-          const double tlim = S.ctr[oc].tl;
+          const double tlim = S.ent[oc].t.tl;
           double tcut, lntcut, m2;
           chan_cut(C, (info >> 17) & 3u, (info >> 19) & 3u, tcut, lntcut, m2);
           if (!(tlim > tcut)) continue;
           if (tlim < T) {
-            if (tlim > lo) { lo = tlim; lnlo = S.ctr[oc].ltl; }
+            if (tlim > lo) { lo = tlim; lnlo = S.ent[oc].t.ltl; }
           } else if (tcut < T) {
             any = true;
             if (tcut > lo) { lo = tcut; lnlo = lntcut; }
@@ -217,14 +217,14 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         // active channels in entry order: their share of the segment's sum
         auto share = [&](int c, double& sh) -> bool {
           const int64_t oc = (int64_t)R.lane * S.nch + c;
-          const uint32_t info = S.ctr[oc].info;
+          const uint32_t info = S.ent[oc].t.info;
           if (!((info >> 21) & 1u)) return false;
-          const double tlim = S.ctr[oc].tl;
+          const double tlim = S.ent[oc].t.tl;
           double tcut, lntcut, m2;
           const int heavy = (info >> 19) & 3u;
           chan_cut(C, (info >> 17) & 3u, heavy, tcut, lntcut, m2);
           if (!(tlim > tcut && tlim >= T && tcut < T)) return false;
-          const double cc = S.ctr[oc].key;
+          const double cc = S.key[oc];
           sh = heavy ? cc * lo / (lo - m2) : cc;
           return true;
         };
@@ -254,7 +254,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
           if (target < cum) sel = c;
         }
         if (sel < 0) sel = last;
-        const uint32_t sinfo = S.ctr[(int64_t)R.lane * S.nch + sel].info;
+        const uint32_t sinfo = S.ent[(int64_t)R.lane * S.nch + sel].t.info;
         const int sheavy = (sinfo >> 19) & 3u;
         if (sheavy) {  // thin the bound back to c/(t - m^2)
           double tcut, lntcut, m2;
@@ -273,9 +273,9 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       }
       for (int c = 0; FORM == 0 && c < nch; ++c) {
         int64_t oc = (int64_t)R.lane * S.nch + c;
-        uint32_t info = S.ctr[oc].info;
+        uint32_t info = S.ent[oc].t.info;
         if (!((info >> 21) & 1u)) continue;
-        double tlim = S.ctr[oc].tl, lntlim = S.ctr[oc].ltl;
+        double tlim = S.ent[oc].t.tl, lntlim = S.ent[oc].t.ltl;
         int type = (info >> 17) & 3u, heavy = (info >> 19) & 3u;
         double tcut, lntcut, m2 = 0.0;
         if (heavy == 1) { tcut = C.tch_c; lntcut = C.ln_tch_c; m2 = C.mc2; }
@@ -292,7 +292,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         }
         double lu = log(ub[slot & 3u]);
         ntri += 1;
-        double invc = S.ctr[oc].ic;
+        double invc = S.ent[oc].t.ic;
         double key;
         if (!heavy) key = lnTch + lu * invc;
         else key = log(m2 + (Tch - m2) * exp(lu * invc));
@@ -301,7 +301,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       }
       if (win < 0) break;
       double t = exp(best);
-      uint32_t info = S.ctr[(int64_t)R.lane * S.nch + win].info;
+      uint32_t info = S.ent[(int64_t)R.lane * S.nch + win].t.info;
       Chan ch;
       chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
       double u[4];

@@ -144,11 +144,11 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
         const int cell = cell_of(C, lnTch, floor);
         if ((int)((info & kCellMask) >> kCellShift) != cell) {
           const Rec R = make_rec(S.part, 1, S.max_slots, slot);
-          const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.cwin[oc].I1,
-                                      S.cwin[oc].I2, cell, (info & kMecBit) != 0u);
+          const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.ent[oc].w.I1,
+                                      S.ent[oc].w.I2, cell, (info & kMecBit) != 0u);
           invc = 1.0 / ck;
-          S.ctr[oc].ic = invc;
-          S.cwin[oc].c = ck;
+          S.ent[oc].t.ic = invc;
+          S.ent[oc].w.c = ck;
           info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
         }
         if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
@@ -158,9 +158,9 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
       if (key < floor) { key = floor; isnull = true; }
       if (key < lntcut) { key = -INFINITY; isnull = false; }
     }
-    S.ctr[oc].info = isnull ? (info | kNullBit) : (info & ~kNullBit);
+    S.ent[oc].t.info = isnull ? (info | kNullBit) : (info & ~kNullBit);
   }
-  S.ctr[oc].key = key;
+  S.key[oc] = key;
   kout = key;
   return tried;
 }
@@ -214,16 +214,16 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   chan_setup(W.C, R, q, side, k, ch, mecL);
   const int c = 2 * q + side;
   const int64_t oc = (int64_t)slot * W.S.nch + c;
-  W.S.ctr[oc].info = pack(ch);
-  W.S.ctr[oc].tl = ch.tlim;
-  W.S.ctr[oc].ltl = ch.lntlim;
-  W.S.ctr[oc].ic = ch.invc;
+  W.S.ent[oc].t.info = pack(ch);
+  W.S.ent[oc].t.tl = ch.tlim;
+  W.S.ent[oc].t.ltl = ch.lntlim;
+  W.S.ent[oc].t.ic = ch.invc;
   Win wd;
   wd.c = ch.c; wd.s = ch.s; wd.zlo = ch.zlo; wd.omzhi = ch.omzhi; wd.I1 = ch.I1; wd.I2 = ch.I2;
   wd.eta = ch.eta; wd.etak = ch.etak;
   wd.pid = (uint32_t)(ch.pidi & 0xFF) | ((uint32_t)(ch.pidk & 0xFF) << 8);
   wd.pad0 = wd.pad1 = wd.pad2 = 0u;
-  W.S.cwin[oc] = wd;
+  W.S.ent[oc].w = wd;
   if constexpr (DRAW) {
     double ub[4];
     rng4(D.seed, stL, idL, cyL, (uint32_t)c >> 2, ub);
@@ -291,7 +291,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       const Rec R = rec_of(W.S, slot);
       // its cache word and (for the finiteness check) its parton's momentum
       const int64_t oc = (int64_t)slot * W.S.nch + e;
-      const uint32_t old = W.S.ctr[oc].info;
+      const uint32_t old = W.S.ent[oc].t.info;
       const int64_t oq = R.o(q);
       bool fin = true;
       if (side == 0) fin = isfinite(R.E[oq]) && isfinite(R.px[oq]) && isfinite(R.py[oq]) && isfinite(R.pz[oq]);
@@ -335,13 +335,13 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       if (!fin) atomicOr(&B.flags[L], fNaN);
       const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
       if (dirty) {
-        if (k < 0) W.S.ctr[oc].info = 0u;
+        if (k < 0) W.S.ent[oc].t.info = 0u;
         else queue = true;
       }
       // retained trials: an unchanged entry keeps its pending trial (its
       // process is unchanged); an entry without a partner has none
       if constexpr (DRAW)
-        if (k < 0) W.S.ctr[oc].key = -INFINITY;
+        if (k < 0) W.S.key[oc] = -INFINITY;
     }
     const unsigned long long qm = __ballot(queue);
     if (queue) {
@@ -369,7 +369,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
 __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, const Rec& R, int64_t slot, int c,
                                                 Chan& ch) {
   const int64_t oc = (int64_t)slot * S.nch + c;
-  uint32_t info = S.ctr[oc].info;
+  uint32_t info = S.ent[oc].t.info;
   ch.alive = 1;
   ch.i = c >> 1;
   ch.side = c & 1;
@@ -380,7 +380,7 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.kbin = (info >> 19) & 0x3Fu;
   ch.mec = (info & kMecBit) != 0u;
   ch.m2 = ch.heavy == 1 ? C.mc2 : (ch.heavy == 2 ? C.mb2 : 0.0);
-  const Win wd = S.cwin[oc];
+  const Win wd = S.ent[oc].w;
   const uint32_t pk = wd.pid;
   ch.pidi = (int)(int8_t)(pk & 0xFFu);
   ch.pidk = (int)(int8_t)((pk >> 8) & 0xFFu);
@@ -430,12 +430,12 @@ template <bool RETAIN>
 __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_events& in1, const gaps_events& out1,
                                                  const Scratch& S, const ShowerArgs& A) {
   // the overestimate table, staged in LDS for the term loops
-  __shared__ double s_bound[(kNEnt + 8) * kNB];
+  __shared__ double s_bound[kBoundRows * kNB];
   __shared__ int s_cnt[16], s_nexh;
   __shared__ BuildLds s_build[8];  // one per wave (blocks of at most 512 threads)
   __shared__ TrialLds s_trial[8];
   extern __shared__ LaneState s_pool[];
-  for (int q = threadIdx.x; q < (kNEnt + 8) * kNB; q += blockDim.x) s_bound[q] = Cg.bound[q];
+  for (int q = threadIdx.x; q < kBoundRows * kNB; q += blockDim.x) s_bound[q] = Cg.bound[q];
   if (threadIdx.x == 0) s_nexh = 0;
   __syncthreads();
   Cfg C = Cg;
@@ -784,7 +784,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           const int c0 = 4 * (g - fL);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const double k = S.ctr[(int64_t)sL * S.nch + (c0 + j)].key;
+            const double k = S.key[(int64_t)sL * S.nch + (c0 + j)];
             if (c0 + j < 2 * nL) {
               if (k > b1) { b2 = b1; i2 = i1; b1 = k; i1 = c0 + j; }
               else if (k > b2) { b2 = k; i2 = c0 + j; }
@@ -832,10 +832,10 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         // the winner's entry: null and cell bits now, trial constants for its
         // redraw after a veto (loaded together, one memory round trip)
         const int64_t ow = (int64_t)slot * S.nch + win;
-        rinfo = S.ctr[ow].info;
-        rtl = S.ctr[ow].tl;
-        rltl = S.ctr[ow].ltl;
-        ric = S.ctr[ow].ic;
+        rinfo = S.ent[ow].t.info;
+        rtl = S.ent[ow].t.tl;
+        rltl = S.ent[ow].t.ltl;
+        ric = S.ent[ow].t.ic;
         wnull = (rinfo & kNullBit) != 0u;
         wcell = (int)((rinfo & kCellMask) >> kCellShift);
       }
@@ -879,10 +879,10 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int64_t oc = (int64_t)sL * S.nch + (c0 + j);
-            inf[j] = S.ctr[oc].info;
-            tl[j] = S.ctr[oc].tl;
-            ltl[j] = S.ctr[oc].ltl;
-            ic[j] = S.ctr[oc].ic;
+            inf[j] = S.ent[oc].t.info;
+            tl[j] = S.ent[oc].t.tl;
+            ltl[j] = S.ent[oc].t.ltl;
+            ic[j] = S.ent[oc].t.ic;
           }
           if ((inf[0] | inf[1] | inf[2] | inf[3]) & 1u) {
             double ub[4];
@@ -913,11 +913,11 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                   const int64_t oc = (int64_t)sL * S.nch + c;
                   const Rec RL = rec_of(S, sL);
                   const double ck = learned_c(C, type, RL.pid[RL.o(c >> 1)], (int)((info >> 13) & 0x3Fu),
-                                              S.cwin[oc].I1, S.cwin[oc].I2, cell, (info & kMecBit) != 0u);
+                                              S.ent[oc].w.I1, S.ent[oc].w.I2, cell, (info & kMecBit) != 0u);
                   invc = 1.0 / ck;
-                  S.ctr[oc].ic = invc;
-                  S.cwin[oc].c = ck;
-                  S.ctr[oc].info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+                  S.ent[oc].t.ic = invc;
+                  S.ent[oc].w.c = ck;
+                  S.ent[oc].t.info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
                 }
                 if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
               }
