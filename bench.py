@@ -160,7 +160,7 @@ def learned_pipeline(G, args, seed, retain):
     rep["log_s"], rep["log_events"], rep["log_rows"] = time.perf_counter() - t0, args.log_events, int(rows.shape[0])
     del hin
     t0 = time.perf_counter()
-    x, y, ent = G.mlp_features(rows)
+    x, y, _, cell = G.mlp_features(rows)
     ntr = int(0.8 * x.shape[0])
     loss = G.mlp_train(x[:ntr], y[:ntr], steps=args.train_steps, batch=args.train_batch, lr=3e-3, tau=args.train_tau,
                        seed=seed)
@@ -170,12 +170,12 @@ def learned_pipeline(G, args, seed, retain):
     lv = loss.cpu().numpy()
     rep["loss_first"], rep["loss_last"] = float(lv[:10].mean()), float(lv[-10:].mean())
     t0 = time.perf_counter()
-    G.mlp_calibrate(x[ntr:], y[ntr:], ent[ntr:])
+    G.mlp_calibrate(x[ntr:], y[ntr:], cell[ntr:])
     G.mlp_tabulate()
     torch.cuda.synchronize()
     rep["calibrate_tabulate_s"] = time.perf_counter() - t0
     rep["mean_bound_over_analytic"] = bound_over_analytic(G)
-    del x, y, ent
+    del x, y, cell
     return rep, rows
 
 
@@ -301,11 +301,11 @@ def main():
     ap.add_argument("--mode", choices=["learned", "plain"], default="learned",
                     help="learned: train the bound first and report the learned shower as `value`, "
                          "the plain shower beside it; plain: the plain shower only")
-    ap.add_argument("--log-events", type=int, default=420_000, help="events whose trials train the bound")
-    ap.add_argument("--log-rows", type=int, default=50_000_000)
+    ap.add_argument("--log-events", type=int, default=460_000, help="events whose trials train the bound")
+    ap.add_argument("--log-rows", type=int, default=52_000_000)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=65536)
-    ap.add_argument("--train-tau", type=float, default=0.999, help="quantile of the learned bound's pinball loss")
+    ap.add_argument("--train-tau", type=float, default=0.9999, help="quantile of the learned bound's pinball loss")
     ap.add_argument("--trials", choices=["retain", "regenerate"], default="retain",
                     help="retain: a losing channel keeps its trial scale (the same Markov chain, fewer draws); "
                          "regenerate: every channel draws again each cycle")

@@ -354,15 +354,20 @@ gaps_status gaps_tune(gaps_ctx ctx, const gaps_batch* batches, int nbatch, const
  * ((ln t - 10)/10, (ln eta + 7)/7, 2z - 1, (entry - 40)/32) predicting an upper
  * quantile of ln(W / R) for logged trials (LOG mode rows), trained with the
  * pinball loss: bfloat16 weights and first hidden layer, FP32 accumulation on
- * the matrix cores, FP32 master weights and Adam.  Calibration takes, per
- * entry, the largest residual on held-out rows plus 2^-6 (entries with fewer
- * than 2000 rows keep the analytic bound); tabulation evaluates the network
- * on 48 probe points per cell (3 ln t x 2 ln eta x 8 z), takes
- * v = clip(delta + max, -20, 0) and stores min(R, R e^v rounded up to a 7-bit
- * mantissa).  Parameter layout (4545 floats): W1[64][4] b1[64] W2[64][64]
+ * the matrix cores, FP32 master weights and Adam.  Calibration gives each cell
+ * the largest residual of the held-out rows in it plus 2^-6 when it holds at
+ * least GAPS_MLP_MIN_CAL_CELL of them, else that of its (entry, eta bin) when
+ * those hold GAPS_MLP_MIN_CAL_BIN, else that of its entry when the entry holds
+ * GAPS_MLP_MIN_CAL (entries with fewer keep the analytic bound); tabulation
+ * evaluates the network on 48 probe points per cell (3 ln t x 2 ln eta x 8
+ * z), takes v = clip(delta + max, -20, 0) and stores min(R, R e^v rounded up
+ * to a 7-bit mantissa).  Parameter layout (4545 floats): W1[64][4] b1[64] W2[64][64]
  * b2[64] W3[64] b3. */
 #define GAPS_MLP_PARAMS 4545
 #define GAPS_LEARN_CELLS (64 * 48 * 8)
+#define GAPS_MLP_MIN_CAL_CELL 200
+#define GAPS_MLP_MIN_CAL_BIN 200
+#define GAPS_MLP_MIN_CAL 2000
 
 /* Cell-maximum bound (the non-learned comparator of the learned bound): the
  * same cells and the same check and fallback in LEARNED mode, with each cell's
@@ -409,9 +414,11 @@ gaps_status gaps_mlp_init(gaps_ctx ctx, uint64_t seed);
 gaps_status gaps_mlp_set(gaps_ctx ctx, const float* host_theta);
 gaps_status gaps_mlp_get(gaps_ctx ctx, float* host_theta);
 /* Features of n logged trials: rows device [n][5] -> x device [n][4], y [n],
- * ent [n] (may be NULL). */
+ * ent [n] (the table entry; may be NULL) and cell [n] (the row's cell
+ * (entry - 8) * 384 + eta bin * 8 + ln t cell, the ln t cell being the largest
+ * k in 1..7 whose lower edge lies below ln t, else 0; may be NULL). */
 gaps_status gaps_mlp_features(gaps_ctx ctx, const float* rows, int64_t n, float* x, float* y, int32_t* ent,
-                              hipStream_t stream);
+                              int32_t* cell, hipStream_t stream);
 /* f[i] = network(x[i]), device arrays. */
 gaps_status gaps_mlp_forward(gaps_ctx ctx, const float* x, int64_t n, float* f, hipStream_t stream);
 /* Pinball-loss (quantile tau) gradient of the mean over n rows, ADDED to
@@ -430,15 +437,17 @@ typedef struct {
  * to device loss[steps] (may be NULL).  Asynchronous. */
 gaps_status gaps_mlp_train(gaps_ctx ctx, const float* x, const float* y, int64_t n, const gaps_train_params* p,
                            float* loss, hipStream_t stream);
-/* Calibration margins from held-out device rows (x, y, ent): per entry the
- * largest y - f plus 2^-6, or +inf below 2000 rows.  Asynchronous (no stream
+/* Calibration margins from held-out device rows (x, y, cell as
+ * gaps_mlp_features gives it): one per cell, as described above (+inf: the
+ * analytic bound).  Asynchronous (no stream
  * synchronisation): the network's outputs are staged through the context's
  * tabulation buffers (24 MB, allocated by the first call of either function
  * on a context), in chunks, in stream order.  GAPS_ENOMEM if they cannot be
  * allocated. */
-gaps_status gaps_mlp_calibrate(gaps_ctx ctx, const float* x, const float* y, const int32_t* ent, int64_t n,
+gaps_status gaps_mlp_calibrate(gaps_ctx ctx, const float* x, const float* y, const int32_t* cell, int64_t n,
                                hipStream_t stream);
-/* Margins from / to HOST memory (64 doubles, entries 8..71; +inf: analytic). */
+/* Margins from / to HOST memory ([64][48][8] doubles: entries 8..71, eta
+ * bins, ln t cells; +inf: analytic). */
 gaps_status gaps_mlp_set_delta(gaps_ctx ctx, const double* host_delta);
 gaps_status gaps_mlp_get_delta(gaps_ctx ctx, double* host_delta);
 /* Tabulate the learned bound from the current weights and margins and enable

@@ -20,10 +20,14 @@ Target: y = ln W - ln R[entry][eta bin], the log of the plain-mode weight up to
 the alpha_s overestimate (<= 0 because R is a strict bound).
 
 Loss: pinball (quantile) loss at tau, mean over the batch.
-Calibration: per entry, delta = the largest residual y - f on held-out rows plus
-2^-6 (entries with fewer than MIN_CAL rows keep the analytic bound).
-Table: R_theta[e][b][k] = min(R[e][b], up6(R[e][b] exp(v))), v = delta_e + max f
-clipped to [-20, 0],
+Calibration: the margin of a cell (entry, eta bin, ln t cell, the cell the
+shower takes for a row's scale) is the largest residual y - f of the held-out
+rows in the cell plus 2^-6 when the cell holds at least MIN_CAL_CELL of them;
+else that of its (entry, eta bin) over all its cells when they hold at least
+MIN_CAL_BIN; else that of its entry when the entry holds at least MIN_CAL;
+else infinite (the cell keeps the analytic bound).
+Table: R_theta[e][b][k] = min(R[e][b], up6(R[e][b] exp(v))), v = delta_ebk +
+max f clipped to [-20, 0],
 with f over the probe points of the cell and up6 rounding up to a 7-bit
 mantissa (a relative grid of at most 2^-6).
 
@@ -50,6 +54,8 @@ NENT_IS, IS0, NB, NTB = 64, 8, 48, 8
 LNETA0 = -13.815510557964274  # ln(1e-6): eta bins uniform in ln eta on [1e-6, 1)
 DLE = -LNETA0 / NB
 MIN_CAL = 2000
+MIN_CAL_BIN = 200
+MIN_CAL_CELL = 200
 V_MIN = -20.0  # the learned bound is at least e^-20 of the analytic one
 CAL_MARGIN = 2.0 ** -6
 STREAM_MLP = 4
@@ -164,18 +170,38 @@ def adam_step(theta, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def calibrate(theta, x, y, ent, round_bf16=True):
-    """Per-entry margin delta (+inf: no learned bound for the entry) and row counts."""
+def cell_ids(rows, cell_edges):
+    """Cell of each logged trial: (entry - 8) * 384 + eta bin * 8 + ln t cell,
+    the ln t cell the largest k in 1..7 with edge[k] < ln t, else 0 (the cell
+    the shower takes for that scale)."""
+    r = np.asarray(rows, dtype=np.float32).astype(np.float64)
+    ent = np.clip(r[:, 3].astype(np.int64), IS0, IS0 + NENT_IS - 1) - IS0
+    E = np.asarray(cell_edges, dtype=np.float64)
+    k = np.zeros(len(r), dtype=np.int64)
+    for j in range(1, NTB):
+        k = np.where(E[j] < r[:, 0], j, k)
+    return (ent * NB + eta_bin_of_ln(r[:, 1])) * NTB + k
+
+
+def calibrate(theta, x, y, cell, round_bf16=True):
+    """Margins delta[64][48][8] (+inf: the analytic bound) from held-out rows
+    with their cells, and the row count of each cell."""
     f = forward(theta, x, round_bf16=round_bf16).astype(np.float64)
     res = np.asarray(y, dtype=np.float64) - f
-    delta = np.full(NENT_IS, np.inf)
-    count = np.zeros(NENT_IS, dtype=np.int64)
-    for e in range(NENT_IS):
-        m = ent == e + IS0
-        count[e] = int(m.sum())
-        if count[e] >= MIN_CAL:
-            delta[e] = float(res[m].max()) + CAL_MARGIN
-    return delta, count
+    cell = np.asarray(cell, dtype=np.int64)
+    ncell = NENT_IS * NB * NTB
+    mx = np.full(ncell, -np.inf)
+    np.maximum.at(mx, cell, res)
+    cnt = np.bincount(cell, minlength=ncell)
+    mx3, cnt3 = mx.reshape(NENT_IS, NB, NTB), cnt.reshape(NENT_IS, NB, NTB)
+    mxb, cntb = mx3.max(axis=2), cnt3.sum(axis=2)
+    mxe, cnte = mxb.max(axis=1), cntb.sum(axis=1)
+    d_ent = np.where(cnte >= MIN_CAL, mxe + CAL_MARGIN, np.inf)
+    d_bin = np.where(cntb >= MIN_CAL_BIN, mxb + CAL_MARGIN, d_ent[:, None])
+    delta = np.where(cnt3 >= MIN_CAL_CELL, mx3 + CAL_MARGIN, d_bin[:, :, None])
+    # an entry without enough rows keeps the analytic bound in every cell
+    delta = np.where(np.isfinite(d_ent)[:, None, None], delta, np.inf)
+    return delta, cnt3
 
 
 def probe_features(cell_edges):
@@ -211,7 +237,9 @@ def tabulate(theta, delta, bounds, cell_edges, fmax=None):
         f = forward(theta, probe_features(cell_edges))
         fmax = f.reshape(NENT_IS, NB, NTB, NPROBE).max(axis=3)
     R = np.asarray(bounds, dtype=np.float64)[IS0:IS0 + NENT_IS, :, None]
-    d = np.asarray(delta, dtype=np.float64)[:, None, None]
+    d = np.asarray(delta, dtype=np.float64)
+    if d.ndim == 1:  # one margin per entry
+        d = d[:, None, None]
     v = np.clip(d + fmax.astype(np.float64), V_MIN, 0.0)
     tab = np.where(np.isfinite(d), np.minimum(R, up6(R * np.exp(v))), R)
     return np.ascontiguousarray(np.broadcast_to(tab, (NENT_IS, NB, NTB)), dtype=np.float64)

@@ -105,7 +105,7 @@ def lib():
         L.gaps_mlp_init.argtypes = [vp, u64]
         L.gaps_mlp_set.argtypes = [vp, vp]
         L.gaps_mlp_get.argtypes = [vp, vp]
-        L.gaps_mlp_features.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.gaps_mlp_features.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
         L.gaps_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.gaps_mlp_grad.argtypes = [vp, vp, vp, i64, C.c_float, vp, vp, vp]
         L.gaps_mlp_train.argtypes = [vp, vp, vp, i64, C.POINTER(GapsTrainParams), vp, vp]
@@ -362,9 +362,10 @@ class Gaps:
         x = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
         y = torch.zeros(n, dtype=torch.float32, device="cuda")
         ent = torch.zeros(n, dtype=torch.int32, device="cuda")
-        _check(lib().gaps_mlp_features(self.h, _ptr(rows.contiguous()), n, _ptr(x), _ptr(y), _ptr(ent),
+        cell = torch.zeros(n, dtype=torch.int32, device="cuda")
+        _check(lib().gaps_mlp_features(self.h, _ptr(rows.contiguous()), n, _ptr(x), _ptr(y), _ptr(ent), _ptr(cell),
                                        _stream(stream)))
-        return x, y, ent
+        return x, y, ent, cell
 
     def mlp_forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
         f = torch.zeros(x.shape[0], dtype=torch.float32, device="cuda")
@@ -386,17 +387,18 @@ class Gaps:
                                     _ptr(loss), _stream(stream)))
         return loss
 
-    def mlp_calibrate(self, x, y, ent, stream=None):
-        _check(lib().gaps_mlp_calibrate(self.h, _ptr(x.contiguous()), _ptr(y.contiguous()), _ptr(ent.contiguous()),
+    def mlp_calibrate(self, x, y, cell, stream=None):
+        """Margins per cell from held-out rows (cell: as mlp_features gives it)."""
+        _check(lib().gaps_mlp_calibrate(self.h, _ptr(x.contiguous()), _ptr(y.contiguous()), _ptr(cell.contiguous()),
                                         x.shape[0], _stream(stream)))
 
     def mlp_set_delta(self, delta):
-        d = np.ascontiguousarray(delta, dtype=np.float64)
-        assert d.shape == (64,)
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(delta, dtype=np.float64).reshape(
+            (64, 1, 1) if np.size(delta) == 64 else LEARN_SHAPE), LEARN_SHAPE))
         _check(lib().gaps_mlp_set_delta(self.h, d.ctypes.data_as(C.c_void_p)))
 
     def mlp_get_delta(self) -> np.ndarray:
-        d = np.zeros(64, dtype=np.float64)
+        d = np.zeros(LEARN_SHAPE, dtype=np.float64)
         _check(lib().gaps_mlp_get_delta(self.h, d.ctypes.data_as(C.c_void_p)))
         return d
 

@@ -654,8 +654,9 @@ gaps_status learn_enable(gaps_ctx c, hipStream_t stream) {
 gaps_status mlp_alloc(gaps_ctx c) {
   if (c->mlp_mem) return GAPS_OK;
   const size_t fl = ((size_t)kNP * 4 + 255) & ~(size_t)255;
-  const size_t need = 4 * fl + (((size_t)kNP * 2 + 255) & ~(size_t)255) + 64 * 8 +
-                      (size_t)GAPS_LEARN_CELLS * 8 + 2 * gaps::kNB * gaps::kNTB * 8 + 2 * 64 * 8 + 1280;
+  const size_t need = 4 * fl + (((size_t)kNP * 2 + 255) & ~(size_t)255) + (size_t)GAPS_LEARN_CELLS * 8 +
+                      (size_t)GAPS_LEARN_CELLS * 8 + 2 * gaps::kNB * gaps::kNTB * 8 +
+                      2 * (size_t)GAPS_LEARN_CELLS * 8 + 1280;
   if (hipMalloc(&c->mlp_mem, need) != hipSuccess) return GAPS_ENOMEM;
   char* p = (char*)c->mlp_mem;
   auto take = [&](size_t bytes) {
@@ -668,11 +669,11 @@ gaps_status mlp_alloc(gaps_ctx c) {
   c->mom2 = (float*)take((size_t)kNP * 4);
   c->grad = (float*)take((size_t)kNP * 4);
   c->wb = (uint16_t*)take((size_t)kNP * 2);
-  c->delta = (double*)take(64 * 8);
+  c->delta = (double*)take((size_t)GAPS_LEARN_CELLS * 8);
   c->table = (double*)take((size_t)GAPS_LEARN_CELLS * 8);
   c->table_sd = (double*)take(2 * gaps::kNB * gaps::kNTB * 8);
-  c->maxbits = (unsigned long long*)take(64 * 8);
-  c->count = (unsigned long long*)take(64 * 8);
+  c->maxbits = (unsigned long long*)take((size_t)GAPS_LEARN_CELLS * 8);
+  c->count = (unsigned long long*)take((size_t)GAPS_LEARN_CELLS * 8);
   return GAPS_OK;
 }
 
@@ -683,9 +684,9 @@ gaps_status mlp_reset(gaps_ctx c) {
   GAPS_HIP(hipMemset(c->grad, 0, (size_t)kNP * 4));
   hipLaunchKernelGGL(gaps::k_mlp_pack, dim3((kNP + 255) / 256), dim3(256), 0, 0, c->theta, c->wb, kNP);
   GAPS_HIP(hipGetLastError());
-  double inf[64];
-  for (int q = 0; q < 64; ++q) inf[q] = INFINITY;
-  GAPS_HIP(hipMemcpy(c->delta, inf, sizeof(inf), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(grid_for(GAPS_LEARN_CELLS, 256)), dim3(256), 0, 0,
+                     (unsigned long long*)c->delta, (int64_t)GAPS_LEARN_CELLS, 0x7FF0000000000000ull);  // +inf
+  GAPS_HIP(hipGetLastError());
   GAPS_HIP(hipDeviceSynchronize());
   c->adam_step = 0;
   return GAPS_OK;
@@ -728,11 +729,11 @@ gaps_status gaps_mlp_get(gaps_ctx c, float* host_theta) {
 }
 
 gaps_status gaps_mlp_features(gaps_ctx c, const float* rows, int64_t n, float* x, float* y, int32_t* ent,
-                              hipStream_t stream) {
+                              int32_t* cell, hipStream_t stream) {
   if (!c || n < 0 || (n > 0 && (!rows || !x || !y))) return GAPS_EINVAL;
   if (n == 0) return GAPS_OK;
-  hipLaunchKernelGGL(gaps::k_mlp_features, dim3(grid_for(n, 256)), dim3(256), 0, stream, rows, n, c->d_bound, x, y,
-                     ent);
+  hipLaunchKernelGGL(gaps::k_mlp_features, dim3(grid_for(n, 256)), dim3(256), 0, stream, c->C, rows, n, c->d_bound,
+                     x, y, ent, cell);
   GAPS_HIP(hipGetLastError());
   return GAPS_OK;
 }
@@ -790,14 +791,16 @@ static gaps_status ensure_probes(gaps_ctx c) {
   return GAPS_OK;
 }
 
-gaps_status gaps_mlp_calibrate(gaps_ctx c, const float* x, const float* y, const int32_t* ent, int64_t n,
+gaps_status gaps_mlp_calibrate(gaps_ctx c, const float* x, const float* y, const int32_t* cell, int64_t n,
                                hipStream_t stream) {
-  if (!c || n <= 0 || !x || !y || !ent) return GAPS_EINVAL;
+  if (!c || n <= 0 || !x || !y || !cell) return GAPS_EINVAL;
   if (!c->mlp_mem) return GAPS_ESTATE;
   const gaps_status st = ensure_probes(c);
   if (st != GAPS_OK) return st;
-  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->maxbits, (int64_t)64, 0ull);
-  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(1), dim3(64), 0, stream, c->count, (int64_t)64, 0ull);
+  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(grid_for(GAPS_LEARN_CELLS, 256)), dim3(256), 0, stream, c->maxbits,
+                     (int64_t)GAPS_LEARN_CELLS, 0ull);
+  hipLaunchKernelGGL(gaps::k_fill_u64, dim3(grid_for(GAPS_LEARN_CELLS, 256)), dim3(256), 0, stream, c->count,
+                     (int64_t)GAPS_LEARN_CELLS, 0ull);
   // the rows in chunks that fit the probe output buffer, in stream order
   const int64_t chunk = gaps::kMlpProbeRows;
   for (int64_t off = 0; off < n; off += chunk) {
@@ -805,10 +808,11 @@ gaps_status gaps_mlp_calibrate(gaps_ctx c, const float* x, const float* y, const
     hipLaunchKernelGGL(gaps::k_mlp_fwd, dim3(mlp_grid(m, 4096)), dim3(256), 0, stream, c->wb, x + 4 * off, m,
                        c->probe_f);
     hipLaunchKernelGGL(gaps::k_mlp_resid, dim3(grid_for(m, 256) < 1024 ? grid_for(m, 256) : 1024), dim3(256), 0,
-                       stream, c->probe_f, y + off, ent + off, m, c->maxbits, c->count);
+                       stream, c->probe_f, y + off, cell + off, m, c->maxbits, c->count);
   }
-  hipLaunchKernelGGL(gaps::k_mlp_delta, dim3(1), dim3(64), 0, stream, c->maxbits, c->count, 2000ll, 0.015625,
-                     c->delta);
+  hipLaunchKernelGGL(gaps::k_mlp_delta, dim3(gaps::kNIS), dim3(gaps::kNB * gaps::kNTB), 0, stream, c->maxbits,
+                     c->count, (long long)GAPS_MLP_MIN_CAL_CELL, (long long)GAPS_MLP_MIN_CAL_BIN,
+                     (long long)GAPS_MLP_MIN_CAL, 0.015625, c->delta);
   GAPS_HIP(hipGetLastError());
   return GAPS_OK;
 }
@@ -817,7 +821,7 @@ gaps_status gaps_mlp_set_delta(gaps_ctx c, const double* host_delta) {
   if (!c || !host_delta) return GAPS_EINVAL;
   if (!c->mlp_mem) return GAPS_ESTATE;
   GAPS_HIP(hipDeviceSynchronize());
-  GAPS_HIP(hipMemcpy(c->delta, host_delta, 64 * sizeof(double), hipMemcpyHostToDevice));
+  GAPS_HIP(hipMemcpy(c->delta, host_delta, (size_t)GAPS_LEARN_CELLS * sizeof(double), hipMemcpyHostToDevice));
   return GAPS_OK;
 }
 
@@ -825,7 +829,7 @@ gaps_status gaps_mlp_get_delta(gaps_ctx c, double* host_delta) {
   if (!c || !host_delta) return GAPS_EINVAL;
   if (!c->mlp_mem) return GAPS_ESTATE;
   GAPS_HIP(hipDeviceSynchronize());
-  GAPS_HIP(hipMemcpy(host_delta, c->delta, 64 * sizeof(double), hipMemcpyDeviceToHost));
+  GAPS_HIP(hipMemcpy(host_delta, c->delta, (size_t)GAPS_LEARN_CELLS * sizeof(double), hipMemcpyDeviceToHost));
   return GAPS_OK;
 }
 

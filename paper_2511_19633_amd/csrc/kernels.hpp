@@ -129,11 +129,12 @@ __global__ void k_adam(float* theta, uint16_t* wb, float* grad, float* m, float*
                        float b2, float eps, float bc1, float bc2);
 __global__ void k_mlp_pack(const float* theta, uint16_t* wb, int n);
 __global__ void k_mlp_init(uint64_t seed, float* theta, int n);
-__global__ void k_mlp_features(const float* rows, int64_t n, const double* bound, float* x, float* y, int32_t* ent);
-__global__ void k_mlp_resid(const float* f, const float* y, const int32_t* ent, int64_t n,
+__global__ void k_mlp_features(Cfg C, const float* rows, int64_t n, const double* bound, float* x, float* y,
+                               int32_t* ent, int32_t* cell);
+__global__ void k_mlp_resid(const float* f, const float* y, const int32_t* cell, int64_t n,
                             unsigned long long* maxbits, unsigned long long* count);
-__global__ void k_mlp_delta(const unsigned long long* maxbits, const unsigned long long* count, long long min_count,
-                            double margin, double* delta);
+__global__ void k_mlp_delta(const unsigned long long* maxbits, const unsigned long long* count, long long min_cell,
+                            long long min_bin, long long min_entry, double margin, double* delta);
 __global__ void k_mlp_probes(Cfg C, float* x);
 __global__ void k_mlp_table(const float* f, const double* delta, const double* bound, double* table);
 __global__ void k_cellmax_fit(Cfg C, const float* rows, int64_t n, unsigned long long* ymax, unsigned long long* count);

@@ -344,7 +344,8 @@ __global__ void k_mlp_init(uint64_t seed, float* theta, int n) {
 
 // features and target of logged trials (rows of 5 floats: ln t, ln eta, z,
 // table entry, ln weight); bound is the analytic table [72][48]
-__global__ void k_mlp_features(const float* rows, int64_t n, const double* bound, float* x, float* y, int32_t* ent) {
+__global__ void k_mlp_features(Cfg C, const float* rows, int64_t n, const double* bound, float* x, float* y,
+                               int32_t* ent, int32_t* cell) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double lnt = rows[5 * i], lne = rows[5 * i + 1], z = rows[5 * i + 2], lnw = rows[5 * i + 4];
@@ -358,6 +359,14 @@ __global__ void k_mlp_features(const float* rows, int64_t n, const double* bound
   x[4 * i + 3] = (float)((e - 40.0) / 32.0);
   y[i] = (float)(lnw - log(bound[e * kNB + b]));
   if (ent) ent[i] = e;
+  if (cell) {
+    // the ln t cell the shower takes for that scale
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < kNTB; ++j)
+      if (C.cell_edge[j] < lnt) k = j;
+    cell[i] = ((e - kIS0) * kNB + b) * kNTB + k;
+  }
 }
 
 namespace {
@@ -372,35 +381,46 @@ __device__ __forceinline__ double unord64(unsigned long long o) {
 }
 }  // namespace
 
-// largest residual y - f and row count per initial-state entry
-__global__ void k_mlp_resid(const float* f, const float* y, const int32_t* ent, int64_t n,
+// largest residual y - f and row count per cell (entry, eta bin, ln t cell)
+__global__ void k_mlp_resid(const float* f, const float* y, const int32_t* cell, int64_t n,
                             unsigned long long* maxbits, unsigned long long* count) {
-  __shared__ unsigned long long sm[kNIS], sc[kNIS];
-  for (int q = threadIdx.x; q < kNIS; q += blockDim.x) { sm[q] = 0ull; sc[q] = 0ull; }
-  __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int e = ent[i] - kIS0;
-    if (e < 0 || e >= kNIS) continue;
+    const int c = cell[i];
+    if (c < 0 || c >= kNIS * kNB * kNTB) continue;
     const double r = (double)y[i] - (double)f[i];
-    atomicMax(&sm[e], ord64(r));
-    atomicAdd(&sc[e], 1ull);
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < kNIS; q += blockDim.x) {
-    if (sc[q]) {
-      atomicMax(maxbits + q, sm[q]);
-      atomicAdd(count + q, sc[q]);
-    }
+    atomicMax(maxbits + c, ord64(r));
+    atomicAdd(count + c, 1ull);
   }
 }
 
-// calibration margin per entry: largest residual + margin, +inf below min_count rows
-__global__ void k_mlp_delta(const unsigned long long* maxbits, const unsigned long long* count, long long min_count,
-                            double margin, double* delta) {
-  const int q = threadIdx.x;
-  if (q >= kNIS) return;
-  if ((long long)count[q] < min_count) { delta[q] = INFINITY; return; }
-  delta[q] = unord64(maxbits[q]) + margin;
+// Calibration margin of each cell, one block per entry and one thread per
+// cell: the cell's largest residual + margin when it has min_cell rows, else
+// its eta bin's (all its cells) when that has min_bin, else its entry's when
+// that has min_entry; +inf (the analytic bound) when the entry has fewer.
+__global__ void __launch_bounds__(kNB * kNTB) k_mlp_delta(const unsigned long long* maxbits,
+                                                         const unsigned long long* count, long long min_cell,
+                                                         long long min_bin, long long min_entry, double margin,
+                                                         double* delta) {
+  __shared__ unsigned long long bm[kNB], bc[kNB], em, ec;
+  const int e = blockIdx.x, q = threadIdx.x, b = q / kNTB;
+  const int c = (e * kNB + b) * kNTB + q % kNTB;
+  if (q < kNB) { bm[q] = 0ull; bc[q] = 0ull; }
+  if (q == 0) { em = 0ull; ec = 0ull; }
+  __syncthreads();
+  const unsigned long long m = maxbits[c], n = count[c];
+  if (n) {
+    atomicMax(&bm[b], m);
+    atomicAdd(&bc[b], n);
+    atomicMax(&em, m);
+    atomicAdd(&ec, n);
+  }
+  __syncthreads();
+  double d;
+  if ((long long)ec < min_entry) d = INFINITY;
+  else if ((long long)n >= min_cell) d = unord64(m) + margin;
+  else if ((long long)bc[b] >= min_bin) d = unord64(bm[b]) + margin;
+  else d = unord64(em) + margin;
+  delta[c] = d;
 }
 
 // probe inputs of every cell (entry, eta bin, ln t cell): 3 ln t x 2 ln eta x 8 z
@@ -432,7 +452,7 @@ __global__ void k_mlp_table(const float* f, const double* delta, const double* b
   float fm = f[(int64_t)cell * 48];
   for (int q = 1; q < 48; ++q) fm = fmaxf(fm, f[(int64_t)cell * 48 + q]);
   const double R = bound[(e + kIS0) * kNB + b];
-  const double d = delta[e];
+  const double d = delta[cell];
   if (!isfinite(d) || !(R > 0.0)) { table[cell] = R; return; }
   double v = d + (double)fm;
   v = v < -20.0 ? -20.0 : (v > 0.0 ? 0.0 : v);

@@ -36,9 +36,10 @@ def oracle_model(oracles):
     # one thread: the rows come in event order, so the trained network is reproducible
     _, rows, _ = o.shower_log(o.hard_events(1_000_000, 8000, 1), 1, 2_000_000, nthreads=1)
     x, y, ent = mlp.features(rows, B)
+    cell = mlp.cell_ids(rows, o.cell_edges())
     ntr = int(0.8 * len(x))
     th = mlp.train(mlp.init_params(7), x[:ntr], y[:ntr], steps=150, batch=4096, lr=3e-3, tau=0.999)
-    delta, _ = mlp.calibrate(th, x[ntr:], y[ntr:], ent[ntr:])
+    delta, _ = mlp.calibrate(th, x[ntr:], y[ntr:], cell[ntr:])
     return th, delta, mlp.tabulate(th, delta, B, o.cell_edges()), rows
 
 
@@ -139,10 +140,11 @@ def test_adam_step_matches_oracle(G):
 def test_features_match_oracle(G, oracles, oracle_model):
     import torch
     rows = oracle_model[3][:200000]
-    x, y, ent = G.mlp_features(torch.from_numpy(np.ascontiguousarray(rows)).cuda())
+    x, y, ent, cell = G.mlp_features(torch.from_numpy(np.ascontiguousarray(rows)).cuda())
     xr, yr, er = mlp.features(rows, oracles["nlo"].bounds())
     assert np.array_equal(x.cpu().numpy(), xr)
     assert np.array_equal(ent.cpu().numpy(), er.astype(np.int32))
+    assert np.array_equal(cell.cpu().numpy(), mlp.cell_ids(rows, oracles["nlo"].cell_edges()).astype(np.int32))
     assert np.allclose(y.cpu().numpy(), yr, rtol=0, atol=2e-6)
 
 
@@ -168,9 +170,10 @@ def test_calibration_matches_oracle(G, oracles, oracle_model):
     th, _, _, rows = oracle_model
     G.mlp_set(th)
     x, y, ent = mlp.features(rows, oracles["nlo"].bounds())
-    dref, _ = mlp.calibrate(th, x, y, ent)
+    cell = mlp.cell_ids(rows, oracles["nlo"].cell_edges())
+    dref, _ = mlp.calibrate(th, x, y, cell)
     G.mlp_calibrate(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(),
-                    torch.from_numpy(ent.astype(np.int32)).cuda())
+                    torch.from_numpy(cell.astype(np.int32)).cuda())
     d = G.mlp_get_delta()
     fin = np.isfinite(dref)
     assert np.array_equal(np.isfinite(d), fin)
@@ -251,14 +254,14 @@ def test_trained_bound_gains_over_plain(G):
     G.mlp_init(11)
     _, rows, cnt = G.shower_log(G.hard_events(5_000_000, 40000, 1), 1, 6_000_000)
     say("trial rows", cnt)
-    x, y, ent = G.mlp_features(rows)
+    x, y, _, cell = G.mlp_features(rows)
     ntr = int(0.8 * x.shape[0])
     loss = G.mlp_train(x[:ntr], y[:ntr], steps=600, batch=32768, lr=3e-3, tau=0.999, seed=3)
     torch.cuda.synchronize()
     lv = loss.cpu().numpy()
     say("loss first/last", lv[:3], lv[-3:])
     assert lv[-50:].mean() < lv[:10].mean()
-    G.mlp_calibrate(x[ntr:], y[ntr:], ent[ntr:])
+    G.mlp_calibrate(x[ntr:], y[ntr:], cell[ntr:])
     G.mlp_tabulate()
     tab = G.learned_table()
     say("mean table / analytic", float(np.mean(tab > 0)))

@@ -132,6 +132,57 @@ def test_up6_and_tabulation(oracles):
     assert np.all(t1 <= R[:, :, None])
 
 
+def test_calibration_margins_closed_form(oracles):
+    """With a network that outputs a constant f, the residual of a row is
+    y - f: a cell with MIN_CAL_CELL rows gets its own largest residual + 2^-6;
+    a thinner cell that of its (entry, eta bin) when the bin's cells hold
+    MIN_CAL_BIN rows together, else that of its entry; an entry with fewer than
+    MIN_CAL rows keeps the analytic bound (+inf); and the cell of a row is the
+    ln t cell the shower takes for its scale (the lower edge itself belongs to
+    the cell below)."""
+    o = oracles["nlo"]
+    E = o.cell_edges()
+    th = np.zeros(mlp.NPARAM, dtype=np.float32)
+    th[mlp.OFF_B3] = -1.0  # f = -1 everywhere
+    lne_bin = lambda b: mlp.LNETA0 + (b + 0.5) * mlp.DLE
+    rows, ys = [], []
+
+    def add(ent, b, k, y, count, lnt=None):
+        lt = 0.5 * (E[k] + E[k + 1]) if lnt is None else lnt
+        for _ in range(count):
+            rows.append((lt, lne_bin(b), 0.5, ent, 0.0))
+            ys.append(y)
+    # entry 10: a full cell (3, 2), a thin cell (3, 5) in a full bin, a thin bin 7
+    add(10, 3, 2, -0.5, mlp.MIN_CAL_CELL)
+    add(10, 3, 5, -0.2, 10)
+    add(10, 7, 1, -0.9, 10)
+    add(10, 9, 4, -0.3, mlp.MIN_CAL - mlp.MIN_CAL_CELL - 20)
+    # entry 20: too few rows in all
+    add(20, 0, 0, 0.0, 50)
+    # a row on the lower edge of cell 4 (as stored: the float at or just below
+    # it) belongs to cell 3
+    lt32 = np.float32(E[4])
+    if float(lt32) > E[4]:
+        lt32 = np.nextafter(lt32, np.float32(-np.inf))
+    add(10, 11, 3, -0.1, 1, lnt=float(lt32))
+    rows = np.asarray(rows, dtype=np.float32)
+    x = np.zeros((len(rows), 4), dtype=np.float32)
+    y = np.asarray(ys, dtype=np.float32)
+    cell = mlp.cell_ids(rows, E)
+    assert cell[-1] == ((10 - 8) * 48 + 11) * 8 + 3
+    d, cnt = mlp.calibrate(th, x, y, cell, round_bf16=False)
+    m = mlp.CAL_MARGIN
+    f = -1.0
+    y32 = lambda v: float(np.float32(v))
+    assert d[2, 3, 2] == y32(-0.5) - f + m                      # its own
+    assert d[2, 3, 5] == max(y32(-0.5), y32(-0.2)) - f + m     # its bin's (two cells)
+    assert d[2, 3, 0] == d[2, 3, 5]                            # an empty cell of a full bin
+    assert d[2, 7, 1] == y32(-0.1) - f + m                     # a thin bin: the entry's maximum
+    assert d[2, 47, 7] == d[2, 7, 1]
+    assert np.all(np.isinf(d[12]))                             # entry 20: analytic
+    assert cnt[2, 3, 2] == mlp.MIN_CAL_CELL and cnt[2, 11, 3] == 1
+
+
 def test_forced_fallback_weighted(oracles):
     """A bound 16 times below the analytic one fails on most events' first
     initial-state winners.  Each failing trial goes through the weighted veto:
@@ -225,9 +276,10 @@ def trained(oracles):
     # one thread: the rows come in event order, so the trained bound is reproducible
     _, rows, _ = o.shower_log(o.hard_events(1_000_000, 12000, 1), 1, 3_000_000, nthreads=1)
     x, y, ent = mlp.features(rows, B)
+    cell = mlp.cell_ids(rows, o.cell_edges())
     ntr = int(0.8 * len(x))
     th = mlp.train(mlp.init_params(7), x[:ntr], y[:ntr], steps=250, batch=4096, lr=3e-3, tau=0.999)
-    delta, _ = mlp.calibrate(th, x[ntr:], y[ntr:], ent[ntr:])
+    delta, _ = mlp.calibrate(th, x[ntr:], y[ntr:], cell[ntr:])
     return th, delta, mlp.tabulate(th, delta, B, o.cell_edges())
 
 
