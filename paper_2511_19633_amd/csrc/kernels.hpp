@@ -8,13 +8,13 @@ namespace gaps {
 
 // Trial data of a channel cache entry (32 bytes): the kinematic limit t_lim
 // and its log, 1/c of the current overestimate (of the current cell in learned
-// mode), and the info word (alive | type << 1 | heavy << 3 | spectator << 5 |
-// eta bin << 13 | spectator eta bin << 19 | learned cell << 25 | null << 29).
-// The pending trial keys of the retained form sit in an array of their own
-// (Scratch::key), which is all the argmax scan reads.
+// mode).  The entry's info word and the pending trial key of the retained form
+// sit in arrays of their own (Scratch::info, Scratch::key): the channel build's
+// walk over an event's entries reads only the info words, the argmax scan only
+// the keys.
 struct alignas(16) Trial {
   double tl, ltl, ic;
-  uint32_t info, pad0;
+  uint32_t pad0, pad1;
 };
 static_assert(sizeof(Trial) == 32, "trial record layout");
 
@@ -54,6 +54,10 @@ struct Scratch {
   // cutoff), [lanes][nch] like the records: an event's keys are contiguous, so
   // the argmax scan reads 8 bytes per entry
   double* key;
+  // info word of each entry, [lanes][nch]: alive | type << 1 | heavy << 3 |
+  // spectator << 5 | eta bin << 13 | spectator eta bin << 19 | learned cell
+  // << 25 | null << 29 | first-emission correction << 30
+  uint32_t* info;
   // weight factor of the event in each state slot, written by the weighted
   // veto of a violated learned bound (valid while the event's flags carry
   // fFallback)

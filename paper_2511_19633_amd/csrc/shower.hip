@@ -35,7 +35,7 @@ __device__ int build_channels(const Cfg& C, const Rec& R, int n, const Scratch& 
       if (k < 0) return -1;
       chan_setup(C, R, i, side, k, ch, mec);
       int64_t oc = (int64_t)R.lane * S.nch + m;
-      S.ent[oc].t.info = pack_info(ch);
+      S.info[oc] = pack_info(ch);
       S.ent[oc].t.tl = ch.tlim;
       S.ent[oc].t.ltl = ch.lntlim;
       S.ent[oc].t.ic = ch.invc;
@@ -110,7 +110,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       bool capped = false;
       for (int c = 0; c < nch && !capped; ++c) {
         const int64_t oc = (int64_t)R.lane * S.nch + c;
-        const uint32_t info = S.ent[oc].t.info;
+        const uint32_t info = S.info[oc];
         if (!((info >> 21) & 1u)) continue;
         double tcut, lntcut, m2;
         const int heavy = (info >> 19) & 3u;
@@ -159,7 +159,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       if (capped) { flags |= fMaxCyc; break; }
       if (win < 0) break;
       // the winner's accepted trial, as recorded
-      const uint32_t info = S.ent[(int64_t)R.lane * S.nch + win].t.info;
+      const uint32_t info = S.info[(int64_t)R.lane * S.nch + win];
       Chan ch;
       chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
       const double t = exp(best);
@@ -194,7 +194,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         bool any = false;
         for (int c = 0; c < nch; ++c) {
           const int64_t oc = (int64_t)R.lane * S.nch + c;
-          const uint32_t info = S.ent[oc].t.info;
+          const uint32_t info = S.info[oc];
           if (!((info >> 21) & 1u)) continue;
           const double tlim = S.ent[oc].t.tl;
           double tcut, lntcut, m2;
@@ -217,7 +217,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
         // active channels in entry order: their share of the segment's sum
         auto share = [&](int c, double& sh) -> bool {
           const int64_t oc = (int64_t)R.lane * S.nch + c;
-          const uint32_t info = S.ent[oc].t.info;
+          const uint32_t info = S.info[oc];
           if (!((info >> 21) & 1u)) return false;
           const double tlim = S.ent[oc].t.tl;
           double tcut, lntcut, m2;
@@ -254,7 +254,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
           if (target < cum) sel = c;
         }
         if (sel < 0) sel = last;
-        const uint32_t sinfo = S.ent[(int64_t)R.lane * S.nch + sel].t.info;
+        const uint32_t sinfo = S.info[(int64_t)R.lane * S.nch + sel];
         const int sheavy = (sinfo >> 19) & 3u;
         if (sheavy) {  // thin the bound back to c/(t - m^2)
           double tcut, lntcut, m2;
@@ -273,7 +273,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       }
       for (int c = 0; FORM == 0 && c < nch; ++c) {
         int64_t oc = (int64_t)R.lane * S.nch + c;
-        uint32_t info = S.ent[oc].t.info;
+        uint32_t info = S.info[oc];
         if (!((info >> 21) & 1u)) continue;
         double tlim = S.ent[oc].t.tl, lntlim = S.ent[oc].t.ltl;
         int type = (info >> 17) & 3u, heavy = (info >> 19) & 3u;
@@ -301,7 +301,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       }
       if (win < 0) break;
       double t = exp(best);
-      uint32_t info = S.ent[(int64_t)R.lane * S.nch + win].t.info;
+      uint32_t info = S.info[(int64_t)R.lane * S.nch + win];
       Chan ch;
       chan_setup(C, R, info & 0xFFu, (info >> 16) & 1u, (info >> 8) & 0xFFu, ch, mec_now());
       double u[4];

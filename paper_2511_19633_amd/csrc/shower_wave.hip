@@ -158,7 +158,7 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
       if (key < floor) { key = floor; isnull = true; }
       if (key < lntcut) { key = -INFINITY; isnull = false; }
     }
-    S.ent[oc].t.info = isnull ? (info | kNullBit) : (info & ~kNullBit);
+    S.info[oc] = isnull ? (info | kNullBit) : (info & ~kNullBit);
   }
   S.key[oc] = key;
   kout = key;
@@ -214,7 +214,7 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   chan_setup(W.C, R, q, side, k, ch, mecL);
   const int c = 2 * q + side;
   const int64_t oc = (int64_t)slot * W.S.nch + c;
-  W.S.ent[oc].t.info = pack(ch);
+  W.S.info[oc] = pack(ch);
   W.S.ent[oc].t.tl = ch.tlim;
   W.S.ent[oc].t.ltl = ch.lntlim;
   W.S.ent[oc].t.ic = ch.invc;
@@ -289,12 +289,18 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       q = e >> 1;
       side = e & 1;
       const Rec R = rec_of(W.S, slot);
-      // its cache word and (for the finiteness check) its parton's momentum
+      // its cache word and (for the finiteness check) its parton's momentum:
+      // an emission changes only the momenta of its emitter, spectator and
+      // new parton, and an initial-initial one (a full build) every
+      // final-state momentum, so only those are checked (the others were
+      // checked when they last changed)
       const int64_t oc = (int64_t)slot * W.S.nch + e;
-      const uint32_t old = W.S.ent[oc].t.info;
+      const uint32_t old = W.S.info[oc];
       const int64_t oq = R.o(q);
+      const int jL = nL - 1;
       bool fin = true;
-      if (side == 0) fin = isfinite(R.E[oq]) && isfinite(R.px[oq]) && isfinite(R.py[oq]) && isfinite(R.pz[oq]);
+      if (side == 0 && (allL || q == iL || q == kL || q == jL))
+        fin = isfinite(R.E[oq]) && isfinite(R.px[oq]) && isfinite(R.py[oq]) && isfinite(R.pz[oq]);
       const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
       // An emission changes colour tags only on the emitter (which only ever
       // takes a new tag) and the new parton (which takes the emitter's old
@@ -302,7 +308,6 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       // partons.  So another parton keeps its partner unless that partner was
       // the emitter; only those entries, the emitter's and the new parton's
       // search, as every entry of a refilled event does.
-      const int jL = nL - 1;
       if (freshL || q == iL || q == jL || (old != 0u && kold == iL)) {
         const int stq = R.st[oq], clq = R.col[oq], alq = R.acol[oq];
         int oth[8];
@@ -335,7 +340,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       if (!fin) atomicOr(&B.flags[L], fNaN);
       const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
       if (dirty) {
-        if (k < 0) W.S.ent[oc].t.info = 0u;
+        if (k < 0) W.S.info[oc] = 0u;
         else queue = true;
       }
       // retained trials: an unchanged entry keeps its pending trial (its
@@ -369,7 +374,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
 __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, const Rec& R, int64_t slot, int c,
                                                 Chan& ch) {
   const int64_t oc = (int64_t)slot * S.nch + c;
-  uint32_t info = S.ent[oc].t.info;
+  uint32_t info = S.info[oc];
   ch.alive = 1;
   ch.i = c >> 1;
   ch.side = c & 1;
@@ -832,7 +837,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         // the winner's entry: null and cell bits now, trial constants for its
         // redraw after a veto (loaded together, one memory round trip)
         const int64_t ow = (int64_t)slot * S.nch + win;
-        rinfo = S.ent[ow].t.info;
+        rinfo = S.info[ow];
         rtl = S.ent[ow].t.tl;
         rltl = S.ent[ow].t.ltl;
         ric = S.ent[ow].t.ic;
@@ -879,7 +884,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int64_t oc = (int64_t)sL * S.nch + (c0 + j);
-            inf[j] = S.ent[oc].t.info;
+            inf[j] = S.info[oc];
             tl[j] = S.ent[oc].t.tl;
             ltl[j] = S.ent[oc].t.ltl;
             ic[j] = S.ent[oc].t.ic;
@@ -917,7 +922,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                   invc = 1.0 / ck;
                   S.ent[oc].t.ic = invc;
                   S.ent[oc].w.c = ck;
-                  S.ent[oc].t.info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+                  S.info[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
                 }
                 if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
               }
