@@ -147,6 +147,36 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}))
 
 
+def counter_dispatches(args):
+    """One gaps_shower dispatch of the first batch (10^6 events) per mode, in a
+    fixed order (plain, learned after the training, cell maxima fixed and
+    adaptive), at the hand-picked launch shape: the run that hardware
+    counters are collected on, one dispatch per mode.  Prints the order."""
+    import torch
+    from gapsinputs import workloads
+    from paper_2511_19633_amd import binding
+    torch.cuda.set_device(0)
+    G = binding.Gaps(workloads.config_dict(workloads.PP_NLO))
+    retain = args.trials == "retain"
+    n = args.events
+    ev_in = G.hard_events(0, n, 1, max_slots=8)
+    ev_out = binding.DeviceEvents(n, workloads.MAX_SLOTS)
+    order = []
+
+    def run(name, mode):
+        G.shower(ev_in, 1, out=ev_out, mode=mode, retain=retain)
+        torch.cuda.synchronize()
+        order.append(name)
+    run("plain", binding.MODE_PLAIN)
+    _, rows = learned_pipeline(G, args, 1, retain)
+    run("learned", binding.MODE_LEARNED)
+    for adaptive, key in ((False, "cellmax"), (True, "cellmax_adaptive")):
+        G.cellmax_table(rows, int(0.8 * rows.shape[0]), adaptive=adaptive)
+        run(key, binding.MODE_LEARNED)
+    print(json.dumps({"dispatch_order": order, "events_per_dispatch": n,
+                      "kernel": "k_shower_wave_rt" if retain else "k_shower_wave"}))
+
+
 def learned_pipeline(G, args, seed, retain):
     """Trial log of the plain shower, training, calibration and tabulation, all
     on the GPU with the library's kernels (untimed for `value`, reported)."""
@@ -210,7 +240,9 @@ def chi2(h_ref, h_other):
     for (name, *_), (a, a2), (b, b2) in zip(HIST_SPEC, h_ref, h_other):
         m = (a2 + b2) > 0
         c2, ndf = float(np.sum((a[m] - b[m]) ** 2 / (a2[m] + b2[m]))), int(max(m.sum(), 1))
-        out[name] = {"chi2_ndf": c2 / ndf, "ndf": ndf, "p_value": float(sstats.chi2.sf(c2, ndf))}
+        pulls = np.where(m, (b - a) / np.sqrt(np.where(m, a2 + b2, 1.0)), 0.0)
+        out[name] = {"chi2_ndf": c2 / ndf, "ndf": ndf, "p_value": float(sstats.chi2.sf(c2, ndf)),
+                     "pulls": [round(float(v), 2) for v in pulls]}
     out["gate_chi2_ndf_below_1_5"] = all(v["chi2_ndf"] < 1.5 for v in out.values() if isinstance(v, dict))
     return out
 
@@ -319,6 +351,8 @@ def main():
     ap.add_argument("--cpu-single", type=int, default=60_000, help="events of the single-thread oracle run")
     ap.add_argument("--cpu-all", type=int, default=300_000, help="events of the all-core oracle run")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--dispatches", action="store_true",
+                    help="only one shower dispatch of the first batch per mode (for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the shower runs on one GPU only (events shard trivially by id range; "
@@ -326,6 +360,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.dispatches:
+        counter_dispatches(args)
         return
 
     import torch
