@@ -426,6 +426,19 @@ gaps_status gaps_mlp_forward(gaps_ctx ctx, const float* x, int64_t n, float* f, 
 gaps_status gaps_mlp_grad(gaps_ctx ctx, const float* x, const float* y, int64_t n, float tau, float* grad,
                           float* loss, hipStream_t stream);
 
+/* One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) of the context's
+ * master weights with the device gradient grad[GAPS_MLP_PARAMS] (as
+ * gaps_mlp_grad accumulates it; caller-owned): moments m <- beta1 m +
+ * (1 - beta1) g and v <- beta2 v + (1 - beta2) g^2, theta <- theta - lr
+ * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps) with t the context's
+ * step count plus one, the bfloat16 copy refreshed, grad cleared to zero (so
+ * the next gaps_mlp_grad starts from it).  FP32 throughout.  The step count is
+ * shared with gaps_mlp_train and reset by gaps_mlp_init/gaps_mlp_set.
+ * Asynchronous.  GAPS_EINVAL for a null pointer, lr <= 0, beta outside [0, 1)
+ * or eps <= 0; GAPS_ESTATE before the weights exist. */
+gaps_status gaps_mlp_adam_step(gaps_ctx ctx, float* grad, float lr, float beta1, float beta2, float eps,
+                               hipStream_t stream);
+
 typedef struct {
     int64_t steps;       /* Adam steps */
     int64_t batch;       /* rows per step, drawn at random from the n rows */

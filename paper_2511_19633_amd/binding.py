@@ -109,6 +109,7 @@ def lib():
         L.gaps_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.gaps_mlp_grad.argtypes = [vp, vp, vp, i64, C.c_float, vp, vp, vp]
         L.gaps_mlp_train.argtypes = [vp, vp, vp, i64, C.POINTER(GapsTrainParams), vp, vp]
+        L.gaps_mlp_adam_step.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.gaps_mlp_calibrate.argtypes = [vp, vp, vp, vp, i64, vp]
         L.gaps_mlp_set_delta.argtypes = [vp, vp]
         L.gaps_cellmax_table.argtypes = [vp, vp, i64, i64, vp]
@@ -378,6 +379,12 @@ class Gaps:
         _check(lib().gaps_mlp_grad(self.h, _ptr(x.contiguous()), _ptr(y.contiguous()), x.shape[0], tau, _ptr(g),
                                    _ptr(loss), _stream(stream)))
         return g, loss
+
+    def mlp_adam_step(self, grad: torch.Tensor, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """One Adam step of the weights with a device gradient (cleared afterwards)."""
+        if grad.dtype != torch.float32 or grad.numel() != MLP_PARAMS or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous float32 tensor of MLP_PARAMS elements")
+        _check(lib().gaps_mlp_adam_step(self.h, _ptr(grad), lr, beta1, beta2, eps, _stream(stream)))
 
     def mlp_train(self, x: torch.Tensor, y: torch.Tensor, steps: int, batch: int = 65536, lr: float = 3e-3,
                   tau: float = 0.999, beta1=0.9, beta2=0.999, eps=1e-8, seed=0, stream=None) -> torch.Tensor:

@@ -781,6 +781,21 @@ gaps_status gaps_mlp_train(gaps_ctx c, const float* x, const float* y, int64_t n
   return GAPS_OK;
 }
 
+gaps_status gaps_mlp_adam_step(gaps_ctx c, float* grad, float lr, float beta1, float beta2, float eps,
+                               hipStream_t stream) {
+  if (!c || !grad || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return GAPS_EINVAL;
+  if (!c->mlp_mem) return GAPS_ESTATE;
+  const int64_t t = c->adam_step + 1;
+  const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+  const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+  hipLaunchKernelGGL(gaps::k_adam, dim3((kNP + 255) / 256), dim3(256), 0, stream, c->theta, c->wb, grad, c->mom1,
+                     c->mom2, kNP, lr, beta1, beta2, eps, bc1, bc2);
+  GAPS_HIP(hipGetLastError());
+  c->adam_step = t;
+  return GAPS_OK;
+}
+
 // the probe buffers of the tabulation (allocated once per context), also the
 // staging of the network's outputs for the calibration's residuals
 static gaps_status ensure_probes(gaps_ctx c) {

@@ -73,6 +73,7 @@ def test_config_and_cellmax_argument_errors():
     assert init(process=4, p_s=0.0) == -1
     assert init(process=4, mll_min=120.0, mll_max=100.0) == -1
     assert init(process=5) == -1
+    assert lib.gaps_mlp_adam_step(None, None, 1e-3, 0.9, 0.999, 1e-8, None) == -1
     for fn in (lib.gaps_cellmax_table, lib.gaps_cellmax_table_adaptive):
         fn.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p]
         assert fn(None, None, 10, 0, None) == -1
