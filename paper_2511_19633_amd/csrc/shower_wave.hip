@@ -234,16 +234,49 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   }
 }
 
+// The entries a rebuild after a local emission visits: the two of the
+// emitter i, of the spectator k and of the new parton j, then the entries
+// paired with the old colour partners of the emitter's and the spectator's
+// entries (rp: the partner slots of (i, 0), (i, 1), (k, 0), (k, 1), eight bits
+// each, i where there was none), each entry once.  Colour partnership is
+// mutual: when (q, side) pairs with p, (p, 1 - side) pairs with q, so an entry
+// whose old partner was i or k is one of these.  Returns the entry (2 q +
+// side) of item e, or for e < 0 the number of items.
+__device__ __forceinline__ int partial_item(int e, int i, int k, int j, uint32_t rp) {
+  if (e >= 0 && e < 6) {
+    const int x = e < 2 ? i : (e < 4 ? k : j);
+    return 2 * x + (e & 1);
+  }
+  int m = 6;
+  int seen[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int p = (int)((rp >> (8 * u)) & 0xFFu);
+    const int c = 2 * p + ((u & 1) ^ 1);
+    bool ok = p != i && p != k && p != j;
+#pragma unroll
+    for (int v = 0; v < u; ++v) ok = ok && seen[v] != c;
+    seen[u] = ok ? c : -1;
+    if (ok) {
+      if (m == e) return c;
+      ++m;
+    }
+  }
+  return e < 0 ? m : -1;
+}
+
 // Cooperative (re)build of the channel entries of the events whose lanes are
-// set in `mask`.  The entries (slot, side) of all these events are laid end to
+// set in `mask`.  The entries (slot, side) these events visit are laid end to
 // end and the wave walks them 64 at a time: each lane finds the colour partner
 // of one entry by scanning its event's colour tags.  Only entries whose
 // constants can have changed are set up again: all of them after a refill
 // (`all`) or an initial-initial emission (whose recoil boosts every
-// final-state momentum); otherwise those of emitter `ei`, spectator `ek` and
-// the new parton n - 1, entries whose partner is one of those three, and
-// entries whose partner changed.  The others are bitwise what a full set-up
-// would write, because their inputs did not change.  Entries to set up are
+// final-state momentum), which visit every entry; otherwise those of emitter
+// `ei`, spectator `ek` and the new parton n - 1, entries whose partner is one
+// of those three, and entries whose partner changed (its old partner was the
+// emitter), and only those candidates are visited (partial_item).  The others
+// are bitwise what a full set-up would write, because their inputs did not
+// change.  Entries to set up are
 // queued in LDS and set up 64 at a time, one per lane.  Returns (per lane)
 // whether this lane's own event has a broken colour line or a non-finite
 // momentum.  DRAW (retained trials): every entry that is set up also draws a
@@ -255,7 +288,17 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
                                bool fresh, bool all, int ei, int ek, const DrawState& D, uint32_t& drawn) {
   __threadfence_block();
   const bool mine = (mask >> W.lane) & 1ull;
-  const int ne = mine ? 2 * n : 0;
+  // a local emission's candidates: the old partners of the emitter's and the
+  // spectator's entries, read before any entry is rewritten
+  uint32_t rp = 0u;
+  if (mine && !all) {
+    const int64_t b = myslot * W.S.nch;
+    const uint32_t w0 = W.S.info[b + 2 * ei], w1 = W.S.info[b + 2 * ei + 1];
+    const uint32_t w2 = W.S.info[b + 2 * ek], w3 = W.S.info[b + 2 * ek + 1];
+    const auto pt = [&](uint32_t w) -> uint32_t { return w ? (w >> 5) & 0xFFu : (uint32_t)ei; };
+    rp = pt(w0) | (pt(w1) << 8) | (pt(w2) << 16) | (pt(w3) << 24);
+  }
+  const int ne = mine ? (all ? 2 * n : partial_item(-1, ei, ek, n - 1, rp)) : 0;
   int incl = ne;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -278,14 +321,15 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
     }
     L = L > 63 ? 63 : L;
     const int nL = __shfl(n, L);
-    const int firstL = __shfl(incl, L) - 2 * nL;
+    const int firstL = __shfl(incl - ne, L);
     const int64_t slot = __shfl(myslot, L);
     const bool allL = __shfl((int)all, L) != 0, freshL = __shfl((int)fresh, L) != 0;
     const int iL = __shfl(ei, L), kL = __shfl(ek, L);
+    const uint32_t rpL = (uint32_t)__shfl((int)rp, L);
     bool queue = false;
     int q = 0, side = 0, k = -1;
     if (g < total) {
-      const int e = g - firstL;
+      const int e = allL ? g - firstL : partial_item(g - firstL, iL, kL, nL - 1, rpL);
       q = e >> 1;
       side = e & 1;
       const Rec R = rec_of(W.S, slot);
