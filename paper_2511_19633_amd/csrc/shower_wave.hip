@@ -811,12 +811,14 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       // ---- retained trials: the winner is the largest pending trial, ties
       // to the lowest entry.  An event whose cached second-largest trial is
       // valid takes the larger of it and its last winner's new trial; the
-      // others scan their entries, in groups of four spread over the wave, one
-      // group per lane, and each owner merges its groups' two largest in
-      // order (keeping the two largest for the cache).
+      // others scan their entries, in groups of eight spread over the wave,
+      // one group per lane, and each owner merges its groups' two largest in
+      // order (keeping the two largest for the cache).  A pass over 64 groups
+      // costs one memory round trip, so the groups are as large as one lane's
+      // eight loads allow.
       TrialLds& TQ = s_trial[wid];
       const bool scan = trialing && !sec_ok;
-      const int ng = scan ? (2 * n + 3) >> 2 : 0;
+      const int ng = scan ? (2 * n + 7) >> 3 : 0;
       const int incl = wave_incl(ng, lane);
       const int total = __shfl(incl, 63);
       const int first = incl - ng;
@@ -830,14 +832,16 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         double b1 = -INFINITY, b2 = -INFINITY;
         int i1 = -1, i2 = -1;
         if (g < total) {
-          const int c0 = 4 * (g - fL);
+          const int c0 = 8 * (g - fL);
+          double kk[8];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const double k = S.key[(int64_t)sL * S.nch + (c0 + j)];
-            if (c0 + j < 2 * nL) {
-              if (k > b1) { b2 = b1; i2 = i1; b1 = k; i1 = c0 + j; }
-              else if (k > b2) { b2 = k; i2 = c0 + j; }
-            }
+          for (int j = 0; j < 8; ++j)
+            kk[j] = c0 + j < 2 * nL ? S.key[(int64_t)sL * S.nch + (c0 + j)] : -INFINITY;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const double k = kk[j];
+            if (k > b1) { b2 = b1; i2 = i1; b1 = k; i1 = c0 + j; }
+            else if (k > b2) { b2 = k; i2 = c0 + j; }
           }
         }
         TQ.c[lane].key = b1;
