@@ -84,6 +84,9 @@ constexpr int kBuildRing = 128;
 // deferred rebuilds after emissions: build when this many lanes want one, when
 // one has waited this many iterations, or when fewer lanes are left to trial
 constexpr int kDeferLanes = 8, kDeferWait = 4, kDeferMin = 16;
+// entries per lane in a pass of the retained form's argmax scan
+constexpr int kScanGroup = 16;
+
 struct BuildLds {
   uint32_t ring[kBuildRing];  // lane L | particle q << 6 | side << 14 | spectator k << 15
   uint32_t flags[64];
@@ -818,7 +821,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       // eight loads allow.
       TrialLds& TQ = s_trial[wid];
       const bool scan = trialing && !sec_ok;
-      const int ng = scan ? (2 * n + 7) >> 3 : 0;
+      const int ng = scan ? (2 * n + kScanGroup - 1) / kScanGroup : 0;
       const int incl = wave_incl(ng, lane);
       const int total = __shfl(incl, 63);
       const int first = incl - ng;
@@ -832,13 +835,13 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         double b1 = -INFINITY, b2 = -INFINITY;
         int i1 = -1, i2 = -1;
         if (g < total) {
-          const int c0 = 8 * (g - fL);
-          double kk[8];
+          const int c0 = kScanGroup * (g - fL);
+          double kk[kScanGroup];
 #pragma unroll
-          for (int j = 0; j < 8; ++j)
+          for (int j = 0; j < kScanGroup; ++j)
             kk[j] = c0 + j < 2 * nL ? S.key[(int64_t)sL * S.nch + (c0 + j)] : -INFINITY;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
+          for (int j = 0; j < kScanGroup; ++j) {
             const double k = kk[j];
             if (k > b1) { b2 = b1; i2 = i1; b1 = k; i1 = c0 + j; }
             else if (k > b2) { b2 = k; i2 = c0 + j; }
