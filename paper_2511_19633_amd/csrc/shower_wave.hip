@@ -291,10 +291,11 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
                                bool fresh, bool all, int ei, int ek, const DrawState& D, uint32_t& drawn) {
   __threadfence_block();
   const bool mine = (mask >> W.lane) & 1ull;
-  // a local emission's candidates: the old partners of the emitter's and the
-  // spectator's entries, read before any entry is rewritten
+  // after an emission, the old partners of the emitter's and the spectator's
+  // entries, read before any entry is rewritten: the candidates of a local
+  // rebuild's walk, and (the emitter's) of the partner searches
   uint32_t rp = 0u;
-  if (mine && !all) {
+  if (mine && !fresh) {
     const int64_t b = myslot * W.S.nch;
     const uint32_t w0 = W.S.info[b + 2 * ei], w1 = W.S.info[b + 2 * ei + 1];
     const uint32_t w2 = W.S.info[b + 2 * ek], w3 = W.S.info[b + 2 * ek + 1];
@@ -349,6 +350,23 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       if (side == 0 && (allL || q == iL || q == kL || q == jL))
         fin = isfinite(R.E[oq]) && isfinite(R.px[oq]) && isfinite(R.py[oq]) && isfinite(R.pz[oq]);
       const int kold = old ? (int)((old >> 5) & 0xFFu) : -1;
+      // this entry's tag: colour (side 0) or anticolour (side 1), as if outgoing
+      const int stq = R.st[oq], clq = R.col[oq], alq = R.acol[oq];
+      const int tag = side == 0 ? (stq < 0 ? alq : clq) : (stq < 0 ? clq : alq);
+      // After an emission the partner can only be among the emitter, the new
+      // parton and the emitter's old partners (no other parton's tags
+      // changed), so their opposite tags are read together with the entry's
+      // word, in the same memory round trip; the full scan below is the
+      // fallback if none of them matches.
+      int cand[4], ctag[4];
+      if (!freshL) {
+        cand[0] = iL;
+        cand[1] = jL;
+        cand[2] = (int)(rpL & 0xFFu);
+        cand[3] = (int)((rpL >> 8) & 0xFFu);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ctag[u] = cand[u] < nL ? (side == 0 ? R.effa(cand[u]) : R.effc(cand[u])) : 0;
+      }
       // An emission changes colour tags only on the emitter (which only ever
       // takes a new tag) and the new parton (which takes the emitter's old
       // tags or the new one), and each tag sits on exactly one pair of
@@ -356,27 +374,27 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       // the emitter; only those entries, the emitter's and the new parton's
       // search, as every entry of a refilled event does.
       if (freshL || q == iL || q == jL || (old != 0u && kold == iL)) {
-        const int stq = R.st[oq], clq = R.col[oq], alq = R.acol[oq];
-        int oth[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) oth[u] = u < nL ? (side == 0 ? R.effa(u) : R.effc(u)) : 0;
-        // this entry's tag: colour (side 0) or anticolour (side 1), as if outgoing
-        const int tag = side == 0 ? (stq < 0 ? alq : clq) : (stq < 0 ? clq : alq);
         if (tag != 0) {
-          // the partner: the first other parton whose opposite tag matches,
-          // eight partons at a time
-          for (int j0 = 0; j0 < nL && k < 0; j0 += 8) {
-            if (j0 > 0) {
+          if (!freshL) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (cand[u] != q && cand[u] < nL && ctag[u] == tag && (k < 0 || cand[u] < k)) k = cand[u];
+          }
+          if (k < 0) {
+            // the partner: the first other parton whose opposite tag matches,
+            // eight partons at a time
+            int oth[8];
+            for (int j0 = 0; j0 < nL && k < 0; j0 += 8) {
 #pragma unroll
               for (int u = 0; u < 8; ++u) {
                 const int j = j0 + u;
                 oth[u] = j < nL ? (side == 0 ? R.effa(j) : R.effc(j)) : 0;
               }
-            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int j = j0 + u;
-              if (k < 0 && j < nL && j != q && oth[u] == tag) k = j;
+              for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u;
+                if (k < 0 && j < nL && j != q && oth[u] == tag) k = j;
+              }
             }
           }
           if (k < 0) atomicOr(&B.flags[L], fColour);
