@@ -37,11 +37,11 @@ struct ScratchMem {
 size_t scratch_per_lane(int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   return (size_t)slots * sizeof(gaps::Part) +
-         (size_t)nch * (sizeof(gaps::Ent) + sizeof(double) + sizeof(uint32_t)) + sizeof(double);
+         (size_t)nch * (sizeof(gaps::Ent) + sizeof(double) + sizeof(uint32_t)) + 6 * sizeof(double);
 }
 
 // bytes the working storage of `lanes` lanes needs, alignment included
-size_t scratch_bytes(int64_t lanes, int slots) { return scratch_per_lane(slots) * (size_t)lanes + 256 * 9 + 64; }
+size_t scratch_bytes(int64_t lanes, int slots) { return scratch_per_lane(slots) * (size_t)lanes + 256 * 10 + 64; }
 
 // Lay out the working storage of `lanes` lanes over [base, base + bytes).
 gaps_status scratch_layout(char* base, size_t bytes, int64_t lanes, int slots, gaps::Scratch& S) {
@@ -61,6 +61,7 @@ gaps_status scratch_layout(char* base, size_t bytes, int64_t lanes, int slots, g
   S.key = (double*)take(cs * sizeof(double));
   S.info = (uint32_t*)take(cs * sizeof(uint32_t));
   S.wfac = (double*)take((size_t)lanes * sizeof(double));
+  S.pend = (double*)take((size_t)5 * lanes * sizeof(double));
   S.queue = (unsigned long long*)take(64);
   return (size_t)(p - base) > bytes ? GAPS_ECAPACITY : GAPS_OK;
 }

@@ -298,6 +298,9 @@ __device__ __forceinline__ int n_terms(const Chan& ch, int nf) {
 // of the overestimate table for initial-state and final-initial channels).
 __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
   Term t;
+  // the two shape integrals as values (a choice between the fields' addresses
+  // would keep the channel record in private memory)
+  const double I1 = ch.I1, I2 = ch.I2;
   if (is_fs(ch)) {
     double R = 1.0;
     t.ent = -1;
@@ -306,10 +309,10 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
       R = C.bound[t.ent * kNB + ch.kbin];
     }
     if (ch.pidi == 21) {
-      if (m == 0) { t.kern = kGGG; t.shape = kSoft; t.flav = 0; t.coefR = kCA * R; t.I = ch.I1; }
-      else { t.kern = kGQQ; t.shape = kFlat; t.flav = m; t.coefR = 0.5 * kTR * R; t.I = ch.I2; }
+      if (m == 0) { t.kern = kGGG; t.shape = kSoft; t.flav = 0; t.coefR = kCA * R; t.I = I1; }
+      else { t.kern = kGQQ; t.shape = kFlat; t.flav = m; t.coefR = 0.5 * kTR * R; t.I = I2; }
     } else {
-      t.kern = kQQG; t.shape = kSoft; t.flav = 0; t.coefR = 2.0 * kCF * R; t.I = ch.I1;
+      t.kern = kQQG; t.shape = kSoft; t.flav = 0; t.coefR = 2.0 * kCF * R; t.I = I1;
     }
     return t;
   }
@@ -317,18 +320,18 @@ __device__ __forceinline__ Term term_at(const Cfg& C, const Chan& ch, int m) {
   const int sh2 = ii ? kS3 : kS1;
   if (ch.pidi == 21) {
     if (m == 0) {
-      t.kern = kC; t.shape = kS1; t.flav = 0; t.ent = ent_s1(famC, 0); t.I = ch.I1;
+      t.kern = kC; t.shape = kS1; t.flav = 0; t.ent = ent_s1(famC, 0); t.I = I1;
     } else {
       int a = m <= C.nf ? m : -(m - C.nf);
       int T = pdf_tab(a);
-      t.kern = kD; t.shape = sh2; t.flav = a; t.ent = ii ? ent_s3(famD, T) : ent_s1(famD, T); t.I = ch.I2;
+      t.kern = kD; t.shape = sh2; t.flav = a; t.ent = ii ? ent_s3(famD, T) : ent_s1(famD, T); t.I = I2;
     }
   } else {
     int T = pdf_tab(ch.pidi);
     if (m == 0) {
-      t.kern = kA; t.shape = kS1; t.flav = 0; t.ent = ent_s1(famA, T); t.I = ch.I1;
+      t.kern = kA; t.shape = kS1; t.flav = 0; t.ent = ent_s1(famA, T); t.I = I1;
     } else {
-      t.kern = kB; t.shape = sh2; t.flav = 0; t.ent = ii ? ent_s3(famB, T) : ent_s1(famB, T); t.I = ch.I2;
+      t.kern = kB; t.shape = sh2; t.flav = 0; t.ent = ii ? ent_s3(famB, T) : ent_s1(famB, T); t.I = I2;
     }
   }
   t.coefR = C.bound[t.ent * kNB + ch.ebin];  // (a corrected family B: see select_term)
@@ -534,10 +537,22 @@ __device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool 
       return t;
     }
   } else {
-    for (int m = 0; m < ch.nterm; ++m) {
-      Term t = term_at(C, ch, m);
-      cum += af * t.coefR * t.I;
-      if (target < cum) return t;
+    // a final-state emitter: its first term, then (a gluon) the g -> q qbar
+    // terms, which share one constant: the running sum adds it once per
+    // flavour, in term order
+    const Term t0 = term_at(C, ch, 0);
+    cum += af * t0.coefR * t0.I;
+    if (target < cum) return t0;
+    if (ch.nterm > 1) {
+      Term t1 = term_at(C, ch, 1);
+      const double inc = af * t1.coefR * t1.I;
+      for (int m = 1; m < ch.nterm; ++m) {
+        cum += inc;
+        if (target < cum) {
+          t1.flav = m;
+          return t1;
+        }
+      }
     }
   }
   for (int m = ch.nterm - 1; m >= 0; --m) {
@@ -590,8 +605,9 @@ __device__ inline void kperp(const double* pa, const double* pb, double tp, doub
   double best = fabs(d0);
   if (fabs(d1) < best) { best = fabs(d1); ax = 1; }
   if (fabs(d2) < best) { best = fabs(d2); ax = 2; }
-  double r[4] = {0.0, 0.0, 0.0, 0.0};
-  r[ax + 1] = 1.0;
+  // the lab axis as a four-vector (written without an indexed store, which
+  // would put the array in private memory)
+  const double r[4] = {0.0, ax == 0 ? 1.0 : 0.0, ax == 1 ? 1.0 : 0.0, ax == 2 ? 1.0 : 0.0};
   double ra = dot4(r, pa), rb = dot4(r, pb);
   double n1[4];
   for (int m = 0; m < 4; ++m) n1[m] = r[m] - rb / pab * pa[m] - ra / pab * pb[m];

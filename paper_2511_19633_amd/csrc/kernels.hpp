@@ -62,6 +62,9 @@ struct Scratch {
   // veto of a violated learned bound (valid while the event's flags carry
   // fFallback)
   double* wfac;
+  // the accepted emission awaiting its channel build, per lane slot,
+  // [5][lanes]: z, 1 - z, azimuth and the two map variables
+  double* pend;
   unsigned long long* queue;  // work-queue counters
 };
 

@@ -537,16 +537,20 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   int since = 1 << 30;
   int rwait = 0;  // iterations an emission's rebuild has been deferred
   // the accepted emission awaiting its application (pe): channel entry,
-  // splitting kernel and flavour (pe_code), z, 1 - z, azimuth, map variables
+  // splitting kernel and flavour (pe_code) in a register; z, 1 - z, azimuth
+  // and the map variables in the lane slot's pending-emission record (memory:
+  // they would otherwise hold ten registers through the whole loop)
   bool pe = false;
   uint32_t pe_code = 0u;
-  double pe_z = 0.0, pe_omz = 0.0, pe_phi = 0.0, pe_a1 = 0.0, pe_a2 = 0.0;
   // apply it: the new parton goes to slot n
   auto apply_emission = [&]() {
+    const double* P = S.pend + slot;
+    const int64_t L = S.lanes;
+    const double pz = P[0], pomz = P[L], pphi = P[2 * L], pa1 = P[3 * L], pa2 = P[4 * L];
     Chan ch;
     chan_from_cache(C, S, R, slot, (int)(pe_code & 0xFFu), ch);
-    emit_map(R, n, maxtag, ch, (int)((pe_code >> 8) & 0xFFu), (int)(int8_t)((pe_code >> 16) & 0xFFu), pe_z, pe_omz,
-             pe_a1, pe_a2, pe_phi);
+    emit_map(R, n, maxtag, ch, (int)((pe_code >> 8) & 0xFFu), (int)(int8_t)((pe_code >> 16) & 0xFFu), pz, pomz,
+             pa1, pa2, pphi);
     n += 1;
     pe = false;
   };
@@ -1145,10 +1149,15 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             // the emission is applied by the next channel build, together
             // with the other lanes' (one pass of the emission code for all)
             pe_code = (uint32_t)win | ((uint32_t)tm.kern << 8) | ((uint32_t)(tm.flav & 0xFF) << 16);
-            pe_z = z;
-            pe_omz = omz;
-            pe_phi = phi;
-            map_vars(ch.type, v, pe_a1, pe_a2);
+            double a1, a2;
+            map_vars(ch.type, v, a1, a2);
+            double* P = S.pend + slot;
+            const int64_t L = S.lanes;
+            P[0] = z;
+            P[L] = omz;
+            P[2 * L] = phi;
+            P[3 * L] = a1;
+            P[4 * L] = a2;
             pe = true;
             // an initial-initial recoil boosts every final-state momentum
             rebuild = true;
