@@ -161,6 +161,38 @@ def loss_grad(theta, x, y, tau, round_bf16=True):
     return loss, g
 
 
+def grad_magnitudes(theta, x, y, tau, round_bf16=True):
+    """Each gradient element's sum of the absolute values of its terms (the
+    same sums as loss_grad with every factor replaced by its magnitude).  A
+    sum of terms each rounded to relative error e is off by at most e times
+    this: the scale against which a gradient computed with rounded
+    (bfloat16) backward operands is compared element by element."""
+    W1, b1, W2, b2, W3, b3 = [np.asarray(a, dtype=np.float64) for a in unpack(np.asarray(theta, np.float32))]
+    if round_bf16:
+        W1, b1, W2, b2, W3 = [bf16(np.float32(a)).astype(np.float64) for a in (W1, b1, W2, b2, W3)]
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = x.shape[0]
+    a1 = x @ W1.T + b1
+    h1 = np.maximum(a1, 0.0)
+    h1q = bf16(h1.astype(np.float32)).astype(np.float64) if round_bf16 else h1
+    a2 = h1q @ W2.T + b2
+    h2 = np.maximum(a2, 0.0)
+    f = h2 @ W3 + b3
+    r = y - f
+    gf = np.abs(np.where(r >= 0, tau, tau - 1.0)) / n
+    g = np.zeros(NPARAM)
+    g[OFF_W3:OFF_B3] = gf @ h2
+    g[OFF_B3] = gf.sum()
+    da2 = np.outer(gf, np.abs(W3)) * (a2 > 0)
+    g[OFF_W2:OFF_B2] = (da2.T @ h1q).ravel()
+    g[OFF_B2:OFF_W3] = da2.sum(axis=0)
+    da1 = (da2 @ np.abs(W2)) * (a1 > 0)
+    g[OFF_W1:OFF_B1] = (da1.T @ np.abs(x)).ravel()
+    g[OFF_B1:OFF_W2] = da1.sum(axis=0)
+    return g
+
+
 def adam_step(theta, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam update (Kingma and Ba), step counted from 1; FP64 reference."""
     m = b1 * m + (1.0 - b1) * g

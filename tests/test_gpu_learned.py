@@ -110,16 +110,18 @@ def test_mlp_grad_matches_oracle(G):
         g, loss = G.mlp_grad(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), tau)
         g = g.cpu().numpy().astype(np.float64)
         lref, gref = mlp.loss_grad(th, x, y, tau)
+        gmag = mlp.grad_magnitudes(th, x, y, tau)
         assert abs(loss.item() - lref) <= 1e-4 * abs(lref)
         for a, b in ((mlp.OFF_W1, mlp.OFF_B1), (mlp.OFF_B1, mlp.OFF_W2), (mlp.OFF_W2, mlp.OFF_B2),
                      (mlp.OFF_B2, mlp.OFF_W3), (mlp.OFF_W3, mlp.OFF_B3), (mlp.OFF_B3, mlp.NPARAM)):
             err = np.linalg.norm(g[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-12)
             assert err < 1e-2, (tau, a, err)
-            # element by element: 1 % of the element, with a floor of 1e-3 of the
-            # block's rms for elements that cancel to near zero (bfloat16
-            # operands, FP32 sums in another order)
-            floor = 1e-3 * np.sqrt(np.mean(gref[a:b] ** 2))
-            excess = np.abs(g[a:b] - gref[a:b]) / (1e-2 * np.abs(gref[a:b]) + floor)
+            # element by element: 1 % of the element, plus the rounding bound
+            # of a sum whose terms carry a bfloat16 backward operand (relative
+            # 2^-9) and FP32 accumulation over the rows: 4e-3 of the sum of the
+            # terms' magnitudes (an element that cancels to near zero is only
+            # as accurate as its terms)
+            excess = np.abs(g[a:b] - gref[a:b]) / (1e-2 * np.abs(gref[a:b]) + 4e-3 * gmag[a:b] + 1e-12)
             print(f"tau {tau} block {a}: worst element at {excess.max():.3f} of its tolerance")
             assert np.all(excess <= 1.0), (tau, a, int(np.argmax(excess)), excess.max())
 
@@ -145,9 +147,10 @@ def test_adam_step_matches_oracle(G):
 
 
 def test_adam_step_entry_matches_oracle(G):
-    """gaps_mlp_adam_step on a gradient from gaps_mlp_grad equals the oracle's
-    Adam update of the oracle's gradient, twice in a row (the step count and
-    moments carry over), and clears the gradient."""
+    """gaps_mlp_adam_step, twice in a row (the step count and moments carry
+    over), equals the oracle's Adam update applied to the same gradient (the
+    device's own, from gaps_mlp_grad: the gradient itself is compared with the
+    oracle's above), and clears the gradient."""
     import torch
     th = _test_theta(6)
     G.mlp_set(th)
@@ -156,28 +159,21 @@ def test_adam_step_entry_matches_oracle(G):
     y = (rng.normal(size=3001) - 2.0).astype(np.float32)
     xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
     lr = 1e-3
-    ref = th.astype(np.float64)
+    prev = th.astype(np.float64)
     m = np.zeros(mlp.NPARAM)
     v = np.zeros(mlp.NPARAM)
     for step in (1, 2):
         g, _ = G.mlp_grad(xd, yd, 0.7)
+        gh = g.cpu().numpy().astype(np.float64)
         G.mlp_adam_step(g, lr)
         assert np.all(g.cpu().numpy() == 0.0)
         got = G.mlp_get().astype(np.float64)
-        # the oracle's gradient at the device's current weights, so that the
-        # two updates compare one step at a time
-        _, gr = mlp.loss_grad(ref.astype(np.float32), x, y, 0.7)
-        ref, m, v = mlp.adam_step(ref, m, v, gr, step, lr)
-        # elements whose gradient is well above the device's rounding (1e-2 of
-        # the rms of its block): the update agrees to 2 % of lr; the others
-        # may flip sign, but no update exceeds about lr in size
-        moved = np.zeros(mlp.NPARAM, dtype=bool)
-        for a, b in ((mlp.OFF_W1, mlp.OFF_B1), (mlp.OFF_B1, mlp.OFF_W2), (mlp.OFF_W2, mlp.OFF_B2),
-                     (mlp.OFF_B2, mlp.OFF_W3), (mlp.OFF_W3, mlp.OFF_B3), (mlp.OFF_B3, mlp.NPARAM)):
-            moved[a:b] = np.abs(gr[a:b]) > 1e-2 * np.sqrt(np.mean(gr[a:b] ** 2))
-        assert np.mean(np.abs(got - ref)[moved] <= 2e-2 * lr + 1e-7) > 0.99, step
-        assert np.all(np.abs(got - ref) <= 2.0 * lr * 1.001 + 1e-6), step
-        ref = got
+        ref, m, v = mlp.adam_step(prev, m, v, gh, step, lr)
+        # FP32 update arithmetic against FP64: well within 1e-3 of a step
+        err = np.abs(got - ref)
+        print(f"step {step}: worst update difference {err.max() / lr:.2e} of lr")
+        assert np.all(err <= 1e-3 * lr + 1e-7), (step, err.max())
+        prev = got
 
 
 def test_features_match_oracle(G, oracles, oracle_model):

@@ -84,6 +84,38 @@ def test_gradient_finite_differences():
         assert abs(fd - g[p]) <= 1e-6 + 1e-5 * abs(fd), (p, fd, g[p])
 
 
+def test_grad_magnitudes_bound_rounded_backward():
+    """grad_magnitudes bounds every gradient element, and a gradient whose
+    backward operand dA2 is rounded to bfloat16 (as the matrix-core kernels
+    take it) differs from the oracle's by at most 2^-8 of it, element by
+    element: the scale of the GPU gradient test's tolerance."""
+    rng = np.random.default_rng(8)
+    th = rng.normal(scale=0.3, size=mlp.NPARAM).astype(np.float32)
+    x = rng.normal(size=(3001, 4)).astype(np.float32)
+    y = (rng.normal(size=3001) - 2.0).astype(np.float32)
+    for tau in (0.5, 0.999):
+        _, g = mlp.loss_grad(th, x, y, tau)
+        gm = mlp.grad_magnitudes(th, x, y, tau)
+        assert np.all(gm >= np.abs(g) * (1 - 1e-12))
+        # the same gradient with dA2 rounded to bfloat16 before both products
+        W1, b1, W2, b2, W3, b3 = [mlp.bf16(np.float32(a)).astype(np.float64)
+                                  for a in mlp.unpack(th)[:5]] + [float(mlp.unpack(th)[5])]
+        xd = x.astype(np.float64)
+        a1 = xd @ W1.T + b1
+        h1q = mlp.bf16(np.maximum(a1, 0.0).astype(np.float32)).astype(np.float64)
+        a2 = h1q @ W2.T + b2
+        f = np.maximum(a2, 0.0) @ W3 + b3
+        r = y - f
+        gf = -np.where(r >= 0, tau, tau - 1.0) / len(y)
+        da2 = mlp.bf16((np.outer(gf, W3) * (a2 > 0)).astype(np.float32)).astype(np.float64)
+        gw2 = (da2.T @ h1q).ravel()
+        gw1 = (((da2 @ W2) * (a1 > 0)).T @ xd).ravel()
+        for blk, (a, b) in ((gw2, (mlp.OFF_W2, mlp.OFF_B2)), (gw1, (mlp.OFF_W1, mlp.OFF_B1))):
+            assert np.all(np.abs(blk - g[a:b]) <= 2.0 ** -8 * gm[a:b] + 1e-15)
+        # while a purely relative criterion would fail on elements that cancel
+        assert np.any(np.abs(gw1 - g[mlp.OFF_W1:mlp.OFF_B1]) > 1e-3 * np.abs(g[mlp.OFF_W1:mlp.OFF_B1]))
+
+
 def test_adam_first_step_closed_form():
     """Bias correction makes the first Adam step lr * g / (|g| + eps)."""
     rng = np.random.default_rng(1)
