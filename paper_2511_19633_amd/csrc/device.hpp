@@ -237,6 +237,7 @@ struct Chan {
   int i, k, side, type, heavy, alive, ebin, kbin, pidi, pidk, nterm, mec;
   double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
   double zlo, zhi, omzlo, omzhi, I1, I2, c, invc;
+  double lz1;  // log(zlo / (1 - zlo)) of an initial-state channel (its 1/(z(1-z)) shape), else 0
 };
 
 struct Term {
@@ -252,28 +253,38 @@ __device__ __forceinline__ int eta_bin(double eta) {
   return (int)b;
 }
 
-__device__ __forceinline__ double shape_int(int sh, double zlo, double zhi, double omzlo, double omzhi) {
+// lz1: log(zlo / omzlo), the lower end of the 1/(z(1-z)) shape's log-odds
+__device__ __forceinline__ double shape_int(int sh, double zlo, double zhi, double omzlo, double omzhi, double lz1) {
   switch (sh) {
     case kSoft: return log(omzlo / omzhi);
     case kFlat: return zhi - zlo;
-    case kS1: return log(zhi / omzhi) - log(zlo / omzlo);
+    case kS1: return log(zhi / omzhi) - lz1;
     default: return log(zhi / zlo);
   }
 }
 
+// Inverse of the shape's integral at u I.  Every curved shape takes one
+// exponential, of an argument chosen per shape, so that lanes of a wave with
+// different shapes share one evaluation.
 __device__ __forceinline__ void shape_sample(int sh, const Chan& ch, double I, double u, double& z,
                                              double& omz) {
-  switch (sh) {
-    case kSoft: omz = ch.omzlo * exp(-u * I); z = 1.0 - omz; break;
-    case kFlat: z = ch.zlo + u * (ch.zhi - ch.zlo); omz = 1.0 - z; break;
-    case kS1: {
-      double L = log(ch.zlo / ch.omzlo) + u * I;
-      double e = exp(-L);
-      z = 1.0 / (1.0 + e);
-      omz = e / (1.0 + e);
-      break;
-    }
-    default: z = ch.zlo * exp(u * I); omz = 1.0 - z; break;
+  if (sh == kFlat) {
+    z = ch.zlo + u * (ch.zhi - ch.zlo);
+    omz = 1.0 - z;
+    return;
+  }
+  const double uI = u * I;
+  const double arg = sh == kSoft ? -uI : (sh == kS1 ? -(ch.lz1 + uI) : uI);
+  const double e = exp(arg);
+  if (sh == kSoft) {
+    omz = ch.omzlo * e;
+    z = 1.0 - omz;
+  } else if (sh == kS1) {
+    z = 1.0 / (1.0 + e);
+    omz = e / (1.0 + e);
+  } else {
+    z = ch.zlo * e;
+    omz = 1.0 - z;
   }
 }
 
@@ -429,7 +440,7 @@ __device__ __forceinline__ double gluon_d_sum(const Cfg& C, bool ii, Tab R_of) {
 __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, int k, Chan& ch, bool mec) {
   ch.i = i; ch.k = k; ch.side = side; ch.alive = 0; ch.heavy = 0; ch.nterm = 0;
   ch.m2 = 0.0; ch.c = 0.0; ch.invc = 0.0; ch.ebin = 0; ch.kbin = 0;
-  ch.zlo = ch.zhi = ch.omzlo = ch.omzhi = ch.I1 = ch.I2 = 0.0;
+  ch.zlo = ch.zhi = ch.omzlo = ch.omzhi = ch.I1 = ch.I2 = ch.lz1 = 0.0;
   int sti = R.st[R.o(i)], stk = R.st[R.o(k)];
   bool isE = sti < 0, isS = stk < 0;
   ch.pidi = R.pid[R.o(i)];
@@ -484,8 +495,9 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
   if (ch.type == kFI) ch.kbin = eta_bin(etak);
   int sh1 = is_fs(ch) ? kSoft : kS1;
   int sh2 = is_fs(ch) ? kFlat : (ch.type == kII ? kS3 : kS1);
-  ch.I1 = shape_int(sh1, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi);
-  ch.I2 = shape_int(sh2, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi);
+  if (isE) ch.lz1 = log(ch.zlo / ch.omzlo);
+  ch.I1 = shape_int(sh1, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi, ch.lz1);
+  ch.I2 = shape_int(sh2, ch.zlo, ch.zhi, ch.omzlo, ch.omzhi, ch.lz1);
   ch.nterm = n_terms(ch, C.nf);
   double c = 0.0;
   if (isE) {

@@ -18,15 +18,15 @@ struct alignas(16) Trial {
 };
 static_assert(sizeof(Trial) == 32, "trial record layout");
 
-// Winner data of a channel cache entry, contiguous (80 bytes: one or two cache
-// lines per entry): the total overestimate constant c (in learned mode the
-// constant of the current cell), the dipole invariant s, the z limits, the
-// z integrals of the channel's two shapes, the momentum fractions 2E/sqrt(S) of
-// an incoming emitter and spectator (0 when outgoing), and their flavours
-// (int8 each, emitter in the low byte).
+// Winner data of a channel cache entry, contiguous (80 bytes): the total
+// overestimate constant c (in learned mode the constant of the current cell),
+// the dipole invariant s, the z limits, the z integrals of the channel's two
+// shapes, the momentum fractions 2E/sqrt(S) of an incoming emitter and
+// spectator (0 when outgoing), log(zlo / (1 - zlo)) of an incoming emitter's
+// channel, and the two flavours (int8 each, emitter in the low byte).
 struct Win {
-  double c, s, zlo, omzhi, I1, I2, eta, etak;
-  uint32_t pid, pad0, pad1, pad2;
+  double c, s, zlo, omzhi, I1, I2, eta, etak, lz1;
+  uint32_t pid, pad0;
 };
 static_assert(sizeof(Win) == 80, "winner record layout");
 

@@ -223,9 +223,9 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   W.S.ent[oc].t.ic = ch.invc;
   Win wd;
   wd.c = ch.c; wd.s = ch.s; wd.zlo = ch.zlo; wd.omzhi = ch.omzhi; wd.I1 = ch.I1; wd.I2 = ch.I2;
-  wd.eta = ch.eta; wd.etak = ch.etak;
+  wd.eta = ch.eta; wd.etak = ch.etak; wd.lz1 = ch.lz1;
   wd.pid = (uint32_t)(ch.pidi & 0xFF) | ((uint32_t)(ch.pidk & 0xFF) << 8);
-  wd.pad0 = wd.pad1 = wd.pad2 = 0u;
+  wd.pad0 = 0u;
   W.S.ent[oc].w = wd;
   if constexpr (DRAW) {
     double ub[4];
@@ -464,6 +464,7 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.I2 = wd.I2;
   ch.eta = wd.eta;
   ch.etak = wd.etak;
+  ch.lz1 = wd.lz1;
   ch.nterm = n_terms(ch, C.nf);
 }
 
