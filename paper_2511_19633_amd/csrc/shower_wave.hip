@@ -859,10 +859,25 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         int i1 = -1, i2 = -1;
         if (g < total) {
           const int c0 = kScanGroup * (g - fL);
+          const double* kr = S.key + (int64_t)sL * S.nch + c0;
           double kk[kScanGroup];
+          if (c0 + kScanGroup <= S.nch) {
+            // the whole group lies in the event's row: one vector load per
+            // two keys, entries past the event's masked afterwards
+            const double2* k2 = reinterpret_cast<const double2*>(kr);
 #pragma unroll
-          for (int j = 0; j < kScanGroup; ++j)
-            kk[j] = c0 + j < 2 * nL ? S.key[(int64_t)sL * S.nch + (c0 + j)] : -INFINITY;
+            for (int j = 0; j < kScanGroup / 2; ++j) {
+              const double2 v = k2[j];
+              kk[2 * j] = v.x;
+              kk[2 * j + 1] = v.y;
+            }
+#pragma unroll
+            for (int j = 0; j < kScanGroup; ++j)
+              if (c0 + j >= 2 * nL) kk[j] = -INFINITY;
+          } else {
+#pragma unroll
+            for (int j = 0; j < kScanGroup; ++j) kk[j] = c0 + j < 2 * nL ? kr[j] : -INFINITY;
+          }
 #pragma unroll
           for (int j = 0; j < kScanGroup; ++j) {
             const double k = kk[j];
