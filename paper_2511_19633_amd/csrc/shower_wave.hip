@@ -156,8 +156,9 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
         }
         if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
       }
-      if (heavy) key = log(m2 + (Tch - m2) * exp(log(u) * invc));
-      else key = lnTch + log(u) * invc;
+      const double lu = log(u);  // one evaluation for the light and heavy measures
+      if (heavy) key = log(m2 + (Tch - m2) * exp(lu * invc));
+      else key = lnTch + lu * invc;
       if (key < floor) { key = floor; isnull = true; }
       if (key < lntcut) { key = -INFINITY; isnull = false; }
     }
@@ -1099,17 +1100,19 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     if (trialing) {
       double best = -INFINITY;
       if (win >= 0) best = wexact ? wkey : wlnT + log(wu) * winv;
+      // the winner's scale, one evaluation for null and real winners alike
+      const double tbest = win >= 0 ? exp(best) : 0.0;
       if (win < 0) {
         done = true;
       } else if (wnull) {
         // no channel emits above the cell edge: continue the evolution from it
-        T = exp(best);
+        T = tbest;
         lnT = best;
         cycle += 1;
         nulled = true;
         rdw = true;
       } else {
-        const double t = exp(best);
+        const double t = tbest;
         Chan ch;
         chan_from_cache(C, S, R, slot, win, ch);
         const bool lch = lrn && win < 4 && (ch.type == kIF || ch.type == kII);
