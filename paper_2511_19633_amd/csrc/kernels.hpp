@@ -63,7 +63,7 @@ struct Scratch {
   // fFallback)
   double* wfac;
   // the accepted emission awaiting its channel build, per lane slot,
-  // [5][lanes]: z, 1 - z, azimuth and the two map variables
+  // [6][lanes]: z, 1 - z, azimuth, the two map variables, the dipole's s
   double* pend;
   unsigned long long* queue;  // work-queue counters
 };

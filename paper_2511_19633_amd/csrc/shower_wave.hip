@@ -538,21 +538,29 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   unsigned long long st_fb = 0, st_null = 0;
   int since = 1 << 30;
   int rwait = 0;  // iterations an emission's rebuild has been deferred
-  // the accepted emission awaiting its application (pe): channel entry,
-  // splitting kernel and flavour (pe_code) in a register; z, 1 - z, azimuth
-  // and the map variables in the lane slot's pending-emission record (memory:
-  // they would otherwise hold ten registers through the whole loop)
+  // the accepted emission awaiting its application (pe): its channel entry
+  // (bits 0-8), splitting kernel (9-11), flavour + 8 (12-15), dipole type
+  // (16-17) and spectator (18-25) in pe_code; z, 1 - z, azimuth, the map
+  // variables and the dipole invariant s in the lane slot's pending-emission
+  // record (memory: they would otherwise hold twelve registers through the
+  // whole loop).  Applying it needs no channel-cache read: the partons'
+  // momenta are the only memory round trip.
   bool pe = false;
   uint32_t pe_code = 0u;
   // apply it: the new parton goes to slot n
   auto apply_emission = [&]() {
     const double* P = S.pend + slot;
     const int64_t L = S.lanes;
-    const double pz = P[0], pomz = P[L], pphi = P[2 * L], pa1 = P[3 * L], pa2 = P[4 * L];
+    const double pz = P[0], pomz = P[L], pphi = P[2 * L], pa1 = P[3 * L], pa2 = P[4 * L], ps = P[5 * L];
+    const int c = (int)(pe_code & 0x1FFu);
     Chan ch;
-    chan_from_cache(C, S, R, slot, (int)(pe_code & 0xFFu), ch);
-    emit_map(R, n, maxtag, ch, (int)((pe_code >> 8) & 0xFFu), (int)(int8_t)((pe_code >> 16) & 0xFFu), pz, pomz,
-             pa1, pa2, pphi);
+    ch.i = c >> 1;
+    ch.side = c & 1;
+    ch.type = (int)((pe_code >> 16) & 3u);
+    ch.k = (int)((pe_code >> 18) & 0xFFu);
+    ch.s = ps;
+    emit_map(R, n, maxtag, ch, (int)((pe_code >> 9) & 7u), (int)((pe_code >> 12) & 15u) - 8, pz, pomz, pa1, pa2,
+             pphi);
     n += 1;
     pe = false;
   };
@@ -1167,7 +1175,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           } else {
             // the emission is applied by the next channel build, together
             // with the other lanes' (one pass of the emission code for all)
-            pe_code = (uint32_t)win | ((uint32_t)tm.kern << 8) | ((uint32_t)(tm.flav & 0xFF) << 16);
+            pe_code = (uint32_t)win | ((uint32_t)tm.kern << 9) | ((uint32_t)(tm.flav + 8) << 12) |
+                      ((uint32_t)ch.type << 16) | ((uint32_t)ch.k << 18);
             double a1, a2;
             map_vars(ch.type, v, a1, a2);
             double* P = S.pend + slot;
@@ -1177,6 +1186,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             P[2 * L] = phi;
             P[3 * L] = a1;
             P[4 * L] = a2;
+            P[5 * L] = ch.s;
             pe = true;
             // an initial-initial recoil boosts every final-state momentum
             rebuild = true;
