@@ -253,14 +253,15 @@ __device__ __forceinline__ int eta_bin(double eta) {
   return (int)b;
 }
 
-// lz1: log(zlo / omzlo), the lower end of the 1/(z(1-z)) shape's log-odds
+// lz1: log(zlo / omzlo), the lower end of the 1/(z(1-z)) shape's log-odds.
+// The curved shapes' integrals are each one logarithm of a ratio, taken once
+// with the ratio chosen per shape (lanes with different shapes share it).
 __device__ __forceinline__ double shape_int(int sh, double zlo, double zhi, double omzlo, double omzhi, double lz1) {
-  switch (sh) {
-    case kSoft: return log(omzlo / omzhi);
-    case kFlat: return zhi - zlo;
-    case kS1: return log(zhi / omzhi) - lz1;
-    default: return log(zhi / zlo);
-  }
+  if (sh == kFlat) return zhi - zlo;
+  const double num = sh == kSoft ? omzlo : zhi;
+  const double den = sh == kS3 ? zlo : omzhi;
+  const double l = log(num / den);
+  return sh == kS1 ? l - lz1 : l;
 }
 
 // Inverse of the shape's integral at u I.  Every curved shape takes one
@@ -491,8 +492,11 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
     ch.zlo = (4.0 * eta + (1.0 - eta) * (1.0 - eta) * d) / (2.0 * ((1.0 + eta) + (1.0 - eta) * sq));
     ch.omzlo = 1.0 - ch.zlo;
   }
-  if (isE) ch.ebin = eta_bin(eta);
-  if (ch.type == kFI) ch.kbin = eta_bin(etak);
+  if (isE || ch.type == kFI) {  // one bin evaluation: the emitter's or the spectator's
+    const int b = eta_bin(isE ? eta : etak);
+    if (isE) ch.ebin = b;
+    else ch.kbin = b;
+  }
   int sh1 = is_fs(ch) ? kSoft : kS1;
   int sh2 = is_fs(ch) ? kFlat : (ch.type == kII ? kS3 : kS1);
   if (isE) ch.lz1 = log(ch.zlo / ch.omzlo);
