@@ -177,6 +177,60 @@ def counter_dispatches(args):
                       "kernel": "k_shower_wave_rt" if retain else "k_shower_wave"}))
 
 
+def seed_scan(args):
+    """The histogram comparison repeated on independent samples: for sample
+    k = 1..S, the plain, learned and cell-maximum showers of 10^7 NLO events
+    (event ids from 2 k 10^7) each against a plain reference of the next 10^7
+    ids, all independent of every other sample.  Under no bias each p-value is
+    uniform and the S p-values of a form and observable combine by Fisher's
+    method (-2 sum ln p, chi^2 with 2 S degrees of freedom); one run's p-value
+    alone says little."""
+    import torch
+    from scipy import stats as sstats
+    from gapsinputs import workloads
+    from paper_2511_19633_amd import binding
+    torch.cuda.set_device(0)
+    G = binding.Gaps(workloads.config_dict(workloads.PP_NLO))
+    n, K = args.events, args.steps
+    ev_in = binding.DeviceEvents(n, 8)
+    ev_out = binding.DeviceEvents(n, workloads.MAX_SLOTS)
+
+    def sample(first, mode):
+        h = None
+        for k in range(K):
+            G.hard_events(first + k * n, n, 1, out=ev_in)
+            G.shower(ev_in, 1, out=ev_out, retain=True, mode=mode)
+            hk = histograms(G, [(ev_out, n)])
+            h = hk if h is None else [(a + c, b + d) for (a, b), (c, d) in zip(h, hk)]
+        return h
+
+    _, rows = learned_pipeline(G, args, 1, True)
+    forms = ("plain", "learned", "cellmax")
+    res = {"events_per_sample": K * n, "samples": args.seed_scan, "p_values": {f: {} for f in forms},
+           "chi2_ndf": {f: {} for f in forms}}
+    hs = {f: [] for f in forms}
+    refs = []
+    for k in range(1, args.seed_scan + 1):
+        base = 2 * k * K * n
+        refs.append(sample(base + K * n, binding.MODE_PLAIN))
+        hs["plain"].append(sample(base, binding.MODE_PLAIN))
+        hs["learned"].append(sample(base, binding.MODE_LEARNED))
+        log(f"sample {k}: plain and learned done")
+    G.cellmax_table(rows, int(0.8 * rows.shape[0]))
+    for k in range(args.seed_scan):
+        hs["cellmax"].append(sample(2 * (k + 1) * K * n, binding.MODE_LEARNED))
+    for f in forms:
+        for k in range(args.seed_scan):
+            c = chi2(refs[k], hs[f][k])
+            for o, v in c.items():
+                if isinstance(v, dict):
+                    res["p_values"][f].setdefault(o, []).append(round(v["p_value"], 4))
+                    res["chi2_ndf"][f].setdefault(o, []).append(round(v["chi2_ndf"], 3))
+    res["fisher_p"] = {f: {o: float(sstats.chi2.sf(-2.0 * np.sum(np.log(np.maximum(ps, 1e-300))), 2 * len(ps)))
+                           for o, ps in res["p_values"][f].items()} for f in forms}
+    print(json.dumps(res))
+
+
 def learned_pipeline(G, args, seed, retain):
     """Trial log of the plain shower, training, calibration and tabulation, all
     on the GPU with the library's kernels (untimed for `value`, reported)."""
@@ -357,6 +411,9 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--dispatches", action="store_true",
                     help="only one shower dispatch of the first batch per mode (for hardware counters)")
+    ap.add_argument("--seed-scan", type=int, default=0,
+                    help="only the histogram comparison of plain, learned and cell-maximum showers against "
+                         "plain references, on this many independent samples (no timing)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the shower runs on one GPU only (events shard trivially by id range; "
@@ -367,6 +424,9 @@ def main():
         return
     if args.dispatches:
         counter_dispatches(args)
+        return
+    if args.seed_scan:
+        seed_scan(args)
         return
 
     import torch
