@@ -838,6 +838,10 @@ __device__ inline void emit_map(const Rec& R, int n, int& maxtag, const Chan& ch
                                 double omz, double a1, double a2, double phi) {
   int i = ch.i, k = ch.k, j = n;
   double pe[4], ps[4], pi[4], pj[4], pk[4];
+  // everything read of the emitter and spectator, before any write (a write
+  // of a status byte may alias any later read, which would then wait for it)
+  const int ec = R.effc(i), ea = R.effa(i);
+  const int pidi = R.pid[R.o(i)];
   R.get(i, pe);
   R.get(k, ps);
   do_map(ch.type, pe, ps, ch.s, z, omz, a1, a2, phi, pi, pj, pk);
@@ -856,8 +860,7 @@ __device__ inline void emit_map(const Rec& R, int n, int& maxtag, const Chan& ch
   R.set(k, pk);
   R.set(j, pj);
   R.st[R.o(j)] = 1;
-  int ec = R.effc(i), ea = R.effa(i), jc = 0, ja = 0;
-  int pidi = R.pid[R.o(i)];
+  int jc = 0, ja = 0;
   if (kern == kQQG || kern == kGGG || kern == kA || kern == kC) {
     int N = ++maxtag;
     if (ch.side == 0) { R.set_eff(i, N, ea); jc = ec; ja = N; }
