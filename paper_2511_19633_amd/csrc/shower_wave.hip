@@ -131,6 +131,7 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
   const int64_t oc = (int64_t)slot * S.nch + c;
   double key = -INFINITY;
   bool isnull = false, tried = false;
+  const uint32_t info0 = info;
   if (info & 1u) {
     const int type = (info >> 1) & 3u, heavy = (info >> 3) & 3u;
     double tcut, lntcut, m2 = 0.0;
@@ -162,7 +163,10 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
       if (key < floor) { key = floor; isnull = true; }
       if (key < lntcut) { key = -INFINITY; isnull = false; }
     }
-    S.info[oc] = isnull ? (info | kNullBit) : (info & ~kNullBit);
+    // the word is written only when its cell or null bit changed, so that a
+    // plain redraw dirties no line of the info array
+    const uint32_t nw = isnull ? (info | kNullBit) : (info & ~kNullBit);
+    if (nw != info0) S.info[oc] = nw;
   }
   S.key[oc] = key;
   kout = key;
