@@ -37,7 +37,7 @@ struct ScratchMem {
 size_t scratch_per_lane(int slots) {
   const int nch = (2 * slots + 3) & ~3;  // whole chunks of four entries
   return (size_t)slots * sizeof(gaps::Part) +
-         (size_t)nch * (sizeof(gaps::Ent) + sizeof(double) + sizeof(uint32_t)) + 7 * sizeof(double);
+         (size_t)nch * (sizeof(gaps::Ent) + sizeof(double) + sizeof(uint32_t)) + (1 + gaps::kPendStride) * sizeof(double);
 }
 
 // bytes the working storage of `lanes` lanes needs, alignment included
@@ -61,7 +61,7 @@ gaps_status scratch_layout(char* base, size_t bytes, int64_t lanes, int slots, g
   S.key = (double*)take(cs * sizeof(double));
   S.info = (uint32_t*)take(cs * sizeof(uint32_t));
   S.wfac = (double*)take((size_t)lanes * sizeof(double));
-  S.pend = (double*)take((size_t)6 * lanes * sizeof(double));
+  S.pend = (double*)take((size_t)gaps::kPendStride * lanes * sizeof(double));
   S.queue = (unsigned long long*)take(64);
   return (size_t)(p - base) > bytes ? GAPS_ECAPACITY : GAPS_OK;
 }

@@ -63,10 +63,16 @@ struct Scratch {
   // fFallback)
   double* wfac;
   // the accepted emission awaiting its channel build, per lane slot,
-  // [6][lanes]: z, 1 - z, azimuth, the two map variables, the dipole's s
+  // [lanes][kPendStride]: z, 1 - z, azimuth, the two map variables, the
+  // dipole's s (one lane's record in one 64-byte piece of a line: accepts are
+  // sparse, so a lane-major record touches one line where a slot-major one
+  // would touch six)
   double* pend;
   unsigned long long* queue;  // work-queue counters
 };
+
+// doubles per lane of the pending-emission record
+constexpr int kPendStride = 8;
 
 // bytes of LDS per thread for the tail-compaction state pool of the wave kernel
 constexpr size_t kLaneStateBytes = 96;

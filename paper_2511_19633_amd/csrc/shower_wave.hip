@@ -553,9 +553,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   uint32_t pe_code = 0u;
   // apply it: the new parton goes to slot n
   auto apply_emission = [&]() {
-    const double* P = S.pend + slot;
-    const int64_t L = S.lanes;
-    const double pz = P[0], pomz = P[L], pphi = P[2 * L], pa1 = P[3 * L], pa2 = P[4 * L], ps = P[5 * L];
+    const double* P = S.pend + kPendStride * slot;
+    const double pz = P[0], pomz = P[1], pphi = P[2], pa1 = P[3], pa2 = P[4], ps = P[5];
     const int c = (int)(pe_code & 0x1FFu);
     Chan ch;
     ch.i = c >> 1;
@@ -1183,14 +1182,13 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                       ((uint32_t)ch.type << 16) | ((uint32_t)ch.k << 18);
             double a1, a2;
             map_vars(ch.type, v, a1, a2);
-            double* P = S.pend + slot;
-            const int64_t L = S.lanes;
+            double* P = S.pend + kPendStride * slot;
             P[0] = z;
-            P[L] = omz;
-            P[2 * L] = phi;
-            P[3 * L] = a1;
-            P[4 * L] = a2;
-            P[5 * L] = ch.s;
+            P[1] = omz;
+            P[2] = phi;
+            P[3] = a1;
+            P[4] = a2;
+            P[5] = ch.s;
             pe = true;
             // an initial-initial recoil boosts every final-state momentum
             rebuild = true;
