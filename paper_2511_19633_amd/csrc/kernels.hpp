@@ -8,13 +8,15 @@ namespace gaps {
 
 // Trial data of a channel cache entry (32 bytes): the kinematic limit t_lim
 // and its log, 1/c of the current overestimate (of the current cell in learned
-// mode).  The entry's info word and the pending trial key of the retained form
-// sit in arrays of their own (Scratch::info, Scratch::key): the channel build's
-// walk over an event's entries reads only the info words, the argmax scan only
-// the keys.
+// mode), and a copy of the entry's info word.  The info words and the pending
+// trial keys of the retained form also sit in arrays of their own
+// (Scratch::info, Scratch::key): the channel build's walk over an event's
+// entries reads only the info words, the argmax scan only the keys, and the
+// winner reads its info word from this copy, in the line it loads anyway.
+// Every write of an info word writes both.
 struct alignas(16) Trial {
   double tl, ltl, ic;
-  uint32_t pad0, pad1;
+  uint32_t info, pad0;
 };
 static_assert(sizeof(Trial) == 32, "trial record layout");
 

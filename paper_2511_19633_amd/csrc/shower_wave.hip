@@ -166,7 +166,10 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
     // the word is written only when its cell or null bit changed, so that a
     // plain redraw dirties no line of the info array
     const uint32_t nw = isnull ? (info | kNullBit) : (info & ~kNullBit);
-    if (nw != info0) S.info[oc] = nw;
+    if (nw != info0) {
+      S.info[oc] = nw;
+      S.ent[oc].t.info = nw;
+    }
   }
   S.key[oc] = key;
   kout = key;
@@ -222,7 +225,9 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   chan_setup(W.C, R, q, side, k, ch, mecL);
   const int c = 2 * q + side;
   const int64_t oc = (int64_t)slot * W.S.nch + c;
-  W.S.info[oc] = pack(ch);
+  const uint32_t pw = pack(ch);
+  W.S.info[oc] = pw;
+  W.S.ent[oc].t.info = pw;
   W.S.ent[oc].t.tl = ch.tlim;
   W.S.ent[oc].t.ltl = ch.lntlim;
   W.S.ent[oc].t.ic = ch.invc;
@@ -410,7 +415,10 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
       if (!fin) atomicOr(&B.flags[L], fNaN);
       const bool dirty = allL || k != kold || q == iL || q == kL || q == jL || k == iL || k == kL || k == jL;
       if (dirty) {
-        if (k < 0) W.S.info[oc] = 0u;
+        if (k < 0) {
+          W.S.info[oc] = 0u;
+          W.S.ent[oc].t.info = 0u;
+        }
         else queue = true;
       }
       // retained trials: an unchanged entry keeps its pending trial (its
@@ -444,7 +452,7 @@ __device__ uint32_t coop_build(const WaveCtx& W, BuildLds& B, unsigned long long
 __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, const Rec& R, int64_t slot, int c,
                                                 Chan& ch) {
   const int64_t oc = (int64_t)slot * S.nch + c;
-  uint32_t info = S.info[oc];
+  uint32_t info = S.ent[oc].t.info;
   ch.alive = 1;
   ch.i = c >> 1;
   ch.side = c & 1;
@@ -938,7 +946,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         // the winner's entry: null and cell bits now, trial constants for its
         // redraw after a veto (loaded together, one memory round trip)
         const int64_t ow = (int64_t)slot * S.nch + win;
-        rinfo = S.info[ow];
+        rinfo = S.ent[ow].t.info;
         rtl = S.ent[ow].t.tl;
         rltl = S.ent[ow].t.ltl;
         ric = S.ent[ow].t.ic;
@@ -1023,7 +1031,9 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                   invc = 1.0 / ck;
                   S.ent[oc].t.ic = invc;
                   S.ent[oc].w.c = ck;
-                  S.info[oc] = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+                  const uint32_t nw = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
+                  S.info[oc] = nw;
+                  S.ent[oc].t.info = nw;
                 }
                 if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
               }
