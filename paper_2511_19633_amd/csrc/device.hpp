@@ -538,14 +538,25 @@ __device__ __forceinline__ double learned_R(const Cfg& C, int ent, int ebin, int
 // A learned channel (lrn) draws from its constant ck in cell k, and the chosen
 // term carries its cell constant; if rounding leaves the draw past every term,
 // the last term of positive weight in the analytic bound.
-__device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool lrn, int k, double ck) {
+// lr: a learned channel's cell constants of its first table reads (a quark's
+// families A and B, a gluon's family C), as learned_c2 gave them when the
+// channel entered cell k, so that they need no load; the others (a gluon's
+// g <- q terms) load.
+__device__ inline Term select_term(const Cfg& C, const Chan& ch, double u, bool lrn, int k, double ck,
+                                   const double* lr = nullptr) {
   double af = C.as_over / (2.0 * kPi) * C.over_scale;
   double target = u * (lrn ? ck : ch.c), cum = 0.0;
   if (ch.type == kIF || ch.type == kII) {
     const int eb = ch.ebin;
     double Rsel;
+    int nread = 0;
     const int m = is_terms_pick(C, ch.type, ch.pidi, ch.I1, ch.I2, target, [&](int ent) {
-      return lrn ? learned_R(C, ent, eb, k) : C.bound[ent * kNB + eb];
+      const int r = nread++;
+      if (!lrn) return C.bound[ent * kNB + eb];
+      // a quark reads A then B, as learned_c2 did; a gluon reads C, then its
+      // g <- q terms one by one (learned_c2's second read was their sum)
+      if (lr && (r == 0 || (r == 1 && ch.pidi != 21))) return lr[r];
+      return learned_R(C, ent, eb, k);
     }, ch.mec, Rsel);
     if (m >= 0) {
       Term t = term_at(C, ch, m);
@@ -590,10 +601,19 @@ __device__ __forceinline__ Term select_term(const Cfg& C, const Chan& ch, double
 
 
 // constant of cell k of an initial-state channel (type IF or II) whose emitter
-// has flavour pidi, from the cell constants of its terms
-__device__ __forceinline__ double learned_c(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k,
-                                            bool mec) {
-  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) { return learned_R(C, ent, ebin, k); }, mec);
+// has flavour pidi, from the cell constants of its terms; the values of its
+// first two table reads (a quark's families A and B, a gluon's family C and
+// g <- q sum) go to lr[0], lr[1]
+__device__ __forceinline__ double learned_c2(const Cfg& C, int type, int pidi, int ebin, double I1, double I2, int k,
+                                             bool mec, double lr[2]) {
+  int nread = 0;
+  lr[0] = lr[1] = 0.0;
+  return is_terms_c(C, type, pidi, I1, I2, [&](int ent) {
+    const double v = learned_R(C, ent, ebin, k);
+    if (nread < 2) lr[nread] = v;
+    ++nread;
+    return v;
+  }, mec);
 }
 
 // the cell of a scale: the largest k with edge[k] < ln t (0 if none), and its

@@ -33,11 +33,14 @@ struct Win {
 static_assert(sizeof(Win) == 80, "winner record layout");
 
 // One channel cache entry: its winner and trial data side by side in one
-// 128-byte line, so that the winner of a cycle (and its redraw) reads one line.
+// 128-byte line, so that the winner of a cycle (and its redraw) reads one line;
+// for a learned channel also the learned constants of its current cell that
+// its term choice reads first (lr: a quark's families A and B, a gluon's
+// family C), written with the cell constant.
 struct alignas(128) Ent {
   Win w;
   Trial t;
-  uint32_t pad[4];
+  double lr[2];
 };
 static_assert(sizeof(Ent) == 128, "channel cache entry layout");
 

@@ -147,12 +147,16 @@ __device__ __forceinline__ bool draw_entry(const Cfg& C, const Scratch& S, int64
       if (lrn && c < 4 && (type == kIF || type == kII)) {
         const int cell = cell_of(C, lnTch, floor);
         if ((int)((info & kCellMask) >> kCellShift) != cell) {
-          const Rec R = make_rec(S.part, 1, S.max_slots, slot);
-          const double ck = learned_c(C, type, R.pid[R.o(c >> 1)], (int)((info >> 13) & 0x3Fu), S.ent[oc].w.I1,
-                                      S.ent[oc].w.I2, cell, (info & kMecBit) != 0u);
+          // the emitter's flavour, I1 and I2 from the entry's own line
+          const Win& wd = S.ent[oc].w;
+          double lr[2];
+          const double ck = learned_c2(C, type, (int)(int8_t)(wd.pid & 0xFFu), (int)((info >> 13) & 0x3Fu), wd.I1,
+                                       wd.I2, cell, (info & kMecBit) != 0u, lr);
           invc = 1.0 / ck;
           S.ent[oc].t.ic = invc;
           S.ent[oc].w.c = ck;
+          S.ent[oc].lr[0] = lr[0];
+          S.ent[oc].lr[1] = lr[1];
           info = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
         }
         if (!(floor > lntcut)) floor = -INFINITY;  // the cutoff lies inside this cell
@@ -1025,12 +1029,15 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                   // the scale entered a new cell: that cell's constant replaces the
                   // entry's (1/c for the trials, c for the winner's term choice)
                   const int64_t oc = (int64_t)sL * S.nch + c;
-                  const Rec RL = rec_of(S, sL);
-                  const double ck = learned_c(C, type, RL.pid[RL.o(c >> 1)], (int)((info >> 13) & 0x3Fu),
-                                              S.ent[oc].w.I1, S.ent[oc].w.I2, cell, (info & kMecBit) != 0u);
+                  const Win& wd = S.ent[oc].w;
+                  double lr[2];
+                  const double ck = learned_c2(C, type, (int)(int8_t)(wd.pid & 0xFFu), (int)((info >> 13) & 0x3Fu),
+                                               wd.I1, wd.I2, cell, (info & kMecBit) != 0u, lr);
                   invc = 1.0 / ck;
                   S.ent[oc].t.ic = invc;
                   S.ent[oc].w.c = ck;
+                  S.ent[oc].lr[0] = lr[0];
+                  S.ent[oc].lr[1] = lr[1];
                   const uint32_t nw = (info & ~kCellMask) | ((uint32_t)cell << kCellShift);
                   S.info[oc] = nw;
                   S.ent[oc].t.info = nw;
@@ -1140,7 +1147,12 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         double u[4];
         rng4(A.seed, strm, id, cycle, 0xFFFFFFFFu, u);
         // a learned channel's cached c is that of its current cell (the winner's)
-        const Term tm = select_term(C, ch, u[0], lch, wcell, ch.c);
+        double lr[2] = {0.0, 0.0};
+        if (lch) {
+          lr[0] = S.ent[(int64_t)slot * S.nch + win].lr[0];
+          lr[1] = S.ent[(int64_t)slot * S.nch + win].lr[1];
+        }
+        const Term tm = select_term(C, ch, u[0], lch, wcell, ch.c, lr);
         double z, omz;
         shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
         const double phi = 2.0 * kPi * u[2];
