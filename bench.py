@@ -109,16 +109,30 @@ def cpu_baseline(cfg, seed, retain, n_single, n_all):
 SHOWER_SOURCES = ("capi.hip", "device.hpp", "kernels.hpp", "shower_wave.hip")
 
 
-def source_hash():
-    """Hash of the shower kernel's sources (its device code, record layouts and
-    launch plan): a stored traffic figure is used only while it matches (the
-    counters describe one build of the kernel)."""
+def code_text(src):
+    """Source text without comments and blank space (what the compiler sees
+    of it)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def source_hash(read=None):
+    """Hash of the shower kernel's code (its device code, record layouts and
+    launch plan, comments excluded): a stored traffic figure is used only while
+    it matches (the counters describe one build of the kernel).  read(name)
+    gives a source's text (default: the working tree's)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_19633_amd", "csrc")
     for name in SHOWER_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        if read is None:
+            with open(os.path.join(csrc, name)) as f:
+                text = f.read()
+        else:
+            text = read(name)
+        h.update((name + "\n" + code_text(text)).encode())
     return h.hexdigest()[:16]
 
 

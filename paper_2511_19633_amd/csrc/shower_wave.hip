@@ -861,11 +861,11 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       // ---- retained trials: the winner is the largest pending trial, ties
       // to the lowest entry.  An event whose cached second-largest trial is
       // valid takes the larger of it and its last winner's new trial; the
-      // others scan their entries, in groups of eight spread over the wave,
-      // one group per lane, and each owner merges its groups' two largest in
-      // order (keeping the two largest for the cache).  A pass over 64 groups
-      // costs one memory round trip, so the groups are as large as one lane's
-      // eight loads allow.
+      // others scan their entries, in groups of kScanGroup (one 128-byte line
+      // of keys) spread over the wave, one group per lane, and each owner
+      // merges its groups' two largest in order (keeping the two largest for
+      // the cache).  A pass over 64 groups costs one memory round trip, and
+      // some lane scans in almost every iteration, so the groups are large.
       TrialLds& TQ = s_trial[wid];
       const bool scan = trialing && !sec_ok;
       const int ng = scan ? (2 * n + kScanGroup - 1) / kScanGroup : 0;
