@@ -40,6 +40,11 @@ double or_alphas(const or_state* s, double t) {
     return s->c.alphas_mz / (1.0 + s->c.alphas_mz * s->b0 * log(t / (s->c.mz * s->c.mz)));
 }
 
+/* The same coupling at ln t, with ln(t / mZ^2) = ln t - ln mZ^2. */
+double or_alphas_ln(const or_state* s, double lnt) {
+    return s->c.alphas_mz / (1.0 + s->c.alphas_mz * s->b0 * (lnt - s->ln_mz2));
+}
+
 int or_pdf_table(int pid) {
     switch (pid) {
     case 21: return 0;
@@ -57,9 +62,9 @@ int or_pdf_table(int pid) {
 /* x*f by bilinear interpolation in (ln x, ln Q^2) of the node values.  Zero for
  * x >= 1, below the smallest x node and outside the Q^2 range: no extrapolation
  * (the paper's PDF edge policy, appendix B.6 and section 4.1). */
-double or_pdf_xf(const or_state* s, int tab, double x, double q2) {
+static double pdf_xf_lq(const or_state* s, int tab, double x, double q2, double lq) {
     if (!(x > 0.0) || x >= 1.0 || !(q2 > 0.0)) return 0.0;
-    double lx = log(x), lq = log(q2);
+    double lx = log(x);
     if (lx < s->c.lnx0 || lq < s->c.lnq0 || lq > s->c.lnq1) return 0.0;
     double fx = (lx - s->c.lnx0) / s->dlnx;
     int i = (int)fx;
@@ -75,8 +80,19 @@ double or_pdf_xf(const or_state* s, int tab, double x, double q2) {
     return (1.0 - b) * ((1.0 - a) * f00 + a * f10) + b * ((1.0 - a) * f01 + a * f11);
 }
 
+double or_pdf_xf(const or_state* s, int tab, double x, double q2) {
+    return q2 > 0.0 ? pdf_xf_lq(s, tab, x, q2, log(q2)) : 0.0;
+}
+
 double or_pdf_f(const or_state* s, int tab, double x, double q2) {
     double xf = or_pdf_xf(s, tab, x, q2);
+    return xf > 0.0 ? xf / x : 0.0;
+}
+
+/* At a trial scale the veto algorithm has ln t itself (the trial is drawn in
+ * ln t), so the interpolation's ln Q^2 is that ln t. */
+double or_pdf_f_lq(const or_state* s, int tab, double x, double q2, double lq) {
+    double xf = pdf_xf_lq(s, tab, x, q2, lq);
     return xf > 0.0 ? xf / x : 0.0;
 }
 
@@ -295,6 +311,7 @@ or_state* or_init(const or_config* cfg) {
     s->sqrtS = cfg->sqrt_s;
     s->S = cfg->sqrt_s * cfg->sqrt_s;
     s->b0 = (33.0 - 2.0 * 5.0) / (12.0 * OR_PI);
+    s->ln_mz2 = log(cfg->mz * cfg->mz);
     s->as_over = or_alphas(s, cfg->t_cut);
     double q2min = exp(cfg->lnq0);
     s->tc_is = cfg->t_cut > q2min ? cfg->t_cut : q2min;

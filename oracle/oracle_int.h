@@ -38,6 +38,7 @@ struct or_state {
     double as_over;            /* alpha_s(t_c): the alpha_s overestimate */
     double tc_is;              /* cutoff of channels that need a PDF ratio */
     double b0;
+    double ln_mz2;             /* log(m_Z^2): the coupling at a trial's ln t */
     double bound[OR_NENT][OR_NB];
     /* family B at the initial-initial end while the first-emission correction
      * applies (kernel bound times the correction's largest value), by the
@@ -48,6 +49,10 @@ struct or_state {
 };
 
 double or_pdf_f(const or_state* s, int tab, double x, double q2); /* f, not x*f */
+/* the same at ln Q^2 = lq given by the caller (a trial's ln t) */
+double or_pdf_f_lq(const or_state* s, int tab, double x, double q2, double lq);
+/* the one-loop coupling at ln t (one logarithm fewer than or_alphas(exp(lnt))) */
+double or_alphas_ln(const or_state* s, double lnt);
 void or_compute_bounds(or_state* s);
 double or_quarter_octave_up(double v);
 void or_rng_block(uint64_t seed, uint32_t stream, int64_t id, uint32_t c2, uint32_t c3,

@@ -65,6 +65,10 @@ def _lib(path=None):
     lib.or_philox4x32.argtypes = [C.POINTER(C.c_uint32)] * 3
     lib.or_alphas.restype = C.c_double
     lib.or_alphas.argtypes = [C.c_void_p, C.c_double]
+    lib.or_alphas_ln.restype = C.c_double
+    lib.or_alphas_ln.argtypes = [C.c_void_p, C.c_double]
+    lib.or_pdf_f_lq.restype = C.c_double
+    lib.or_pdf_f_lq.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double]
     lib.or_pdf_xf.restype = C.c_double
     lib.or_pdf_xf.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
     lib.or_bounds_shape.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -168,6 +172,14 @@ class Oracle:
 
     def alphas(self, t):
         return self.L.or_alphas(self.h, t)
+
+    def alphas_ln(self, lnt):
+        """The coupling at ln t (the veto weight's form: the trial's ln t)."""
+        return self.L.or_alphas_ln(self.h, lnt)
+
+    def pdf_f_lq(self, tab, x, q2, lq):
+        """f (not x f) at ln Q^2 = lq given with Q^2."""
+        return self.L.or_pdf_f_lq(self.h, tab, x, q2, lq)
 
     def pdf_xf(self, tab, x, q2):
         return self.L.or_pdf_xf(self.h, tab, x, q2)

@@ -426,9 +426,11 @@ typedef struct {
     double wn; /* the weight before division by the table constant: w * over_scale * coefR */
 } veto_t;
 
-/* acceptance weight of the winner trial (term tm, scale t, momentum fraction z) */
+/* acceptance weight of the winner trial (term tm, scale t with its ln t lnt as
+ * drawn, momentum fraction z); the PDF ratio and the coupling are evaluated at
+ * that ln t */
 static veto_t weight(const or_state* S, const ev_t* e, const chan_t* ch, const term_t* tm,
-                     double t, double z, double omz) {
+                     double t, double lnt, double z, double omz) {
     veto_t r;
     memset(&r, 0, sizeof(r));
     double W = 0.0, s = ch->s;
@@ -452,8 +454,8 @@ static veto_t weight(const or_state* S, const ev_t* e, const chan_t* ch, const t
         else if (tm->kern == K_GGG) P = 0.5 * OR_CA * (2.0 / den1 - 2.0 + z * omz);
         else P = 0.5 * OR_TR * (1.0 - 2.0 * z * omz);
         int Tk = or_pdf_table(e->pid[ch->k]);
-        double den = or_pdf_f(S, Tk, ch->etak, t);
-        double pr = den > 0.0 ? or_pdf_f(S, Tk, ch->etak / x, t) / den : 0.0;
+        double den = or_pdf_f_lq(S, Tk, ch->etak, t, lnt);
+        double pr = den > 0.0 ? or_pdf_f_lq(S, Tk, ch->etak / x, t, lnt) / den : 0.0;
         W = P * pr;
         r.x = x; r.omx = omx;
     } else {
@@ -487,15 +489,15 @@ static veto_t weight(const or_state* S, const ev_t* e, const chan_t* ch, const t
         case K_C: Tnum = 0; Tden = 0; break;
         default: Tnum = or_pdf_table(tm->flav); Tden = 0; break;
         }
-        double den = or_pdf_f(S, Tden, ch->eta, t);
-        double pr = den > 0.0 ? or_pdf_f(S, Tnum, ch->eta / x, t) / den : 0.0;
+        double den = or_pdf_f_lq(S, Tden, ch->eta, t, lnt);
+        double pr = den > 0.0 ? or_pdf_f_lq(S, Tnum, ch->eta / x, t, lnt) / den : 0.0;
         double hf = ch->heavy ? (t - ch->m2) / t : 1.0;
         W = J * P * pr * hf;
         if (ch->mec) W *= or_mec_ratio(tm->kern == K_B, x, uv);
         r.x = x; r.omx = omx; r.uv = uv;
     }
     double over = S->c.over_scale * tm->coefR * shape_val(tm->shape, z, omz);
-    double ar = or_alphas(S, t) / S->as_over;
+    double ar = or_alphas_ln(S, lnt) / S->as_over;
     r.w = ar * W / over;
     r.wn = ar * W / shape_val(tm->shape, z, omz);
     r.ok = 1;
@@ -760,7 +762,7 @@ typedef struct {
  * new scale), so it sees no further learned-bound violation.  A weight above
  * the analytic bound is counted (n_viol, OR_F_VIOL) and accepted with
  * probability one. */
-static step_t winner(sh_t* r, const chan_t* C, double t, int lch, int wcell) {
+static step_t winner(sh_t* r, const chan_t* C, double t, double lnt, int lch, int wcell) {
     const or_state* S = r->S;
     const double* Lt = r->Lt;
     step_t st;
@@ -778,7 +780,7 @@ static step_t winner(sh_t* r, const chan_t* C, double t, int lch, int wcell) {
     double I = shape_int(st.tm.shape, C);
     shape_sample(st.tm.shape, C, I, u[1], &st.z, &st.omz);
     st.phi = 2.0 * OR_PI * u[2];
-    st.v = weight(S, r->ev, C, &st.tm, t, st.z, st.omz);
+    st.v = weight(S, r->ev, C, &st.tm, t, lnt, st.z, st.omz);
     const veto_t* v = &st.v;
     if (r->L && (C->type == T_IF || C->type == T_II) && !C->mec && v->ok && v->wn > 0.0)
         log_trial(r->L, t, C->eta, st.z, st.tm.ent, v->wn);
@@ -838,7 +840,7 @@ static void run_max_veto(sh_t* r) {
         }
         const double t = exp(best);
         const chan_t* C = &r->ch[win];
-        const step_t st = winner(r, C, t, learned_chan(r, C), wcell);
+        const step_t st = winner(r, C, t, best, learned_chan(r, C), wcell);
         if (st.acc) {
             const int rc = emit_step(r, C, &st, t);
             if (rc == 2) break;
@@ -883,7 +885,7 @@ static void run_retained(sh_t* r) {
         const chan_t* C = &r->ch[win];
         const int lch = learned_chan(r, C);
         const int e_i = C->i, e_k = C->k;
-        const step_t st = winner(r, C, t, lch, kcell[win]);
+        const step_t st = winner(r, C, t, best, lch, kcell[win]);
         const int fell = lch && !r->lrn;
         const int e_all = C->type == T_II || fell;
         if (st.acc) {
@@ -1001,7 +1003,7 @@ static void run_gen_select(sh_t* r) {
         }
         const double t = exp(lnt);
         const chan_t* C = &r->ch[sel];
-        const step_t st = winner(r, C, t, 0, 0);
+        const step_t st = winner(r, C, t, lnt, 0, 0);
         if (st.acc) {
             const int rc = emit_step(r, C, &st, t);
             if (rc == 2) break;
@@ -1021,8 +1023,8 @@ static void run_gen_select(sh_t* r) {
 
 /* the splitting term, z, azimuth and weight of a trial of channel C at scale t
  * from the four numbers u (plain mode); returns whether it is accepted */
-static int vm_veto(const or_state* S, const ev_t* ev, const chan_t* C, double t, const double* u, term_t* tsel,
-                   double* z, double* omz, double* phi, veto_t* v) {
+static int vm_veto(const or_state* S, const ev_t* ev, const chan_t* C, double t, double lnt, const double* u,
+                   term_t* tsel, double* z, double* omz, double* phi, veto_t* v) {
     double R[12] = {0.0};
     for (int m = 0; m < C->nterm; ++m) R[m] = C->term[m].coefR;
     int sel = terms_pick(S, C, R, u[0] * C->c);
@@ -1030,7 +1032,7 @@ static int vm_veto(const or_state* S, const ev_t* ev, const chan_t* C, double t,
     *tsel = C->term[sel];
     shape_sample(tsel->shape, C, shape_int(tsel->shape, C), u[1], z, omz);
     *phi = 2.0 * OR_PI * u[2];
-    *v = weight(S, ev, C, tsel, t, *z, *omz);
+    *v = weight(S, ev, C, tsel, t, lnt, *z, *omz);
     return v->ok && u[3] < v->w;
 }
 
@@ -1060,7 +1062,7 @@ static double vm_first(const or_state* S, const ev_t* ev, const chan_t* C, int c
         term_t tm;
         double z, omz, phi;
         veto_t v;
-        const int acc = vm_veto(S, ev, C, t, u, &tm, &z, &omz, &phi, &v);
+        const int acc = vm_veto(S, ev, C, t, key, u, &tm, &z, &omz, &phi, &v);
         if (v.ok && v.w > 1.0) *nviol += 1;
         if (acc) { *kk = k; return key; }
         Tch = t;
@@ -1096,7 +1098,7 @@ static void run_veto_max(sh_t* r) {
         double u[4];
         or_rng_block(r->seed, r->stream, r->id, r->cycle, VM_BLOCK(win, wk, 1), u);
         step_t st;
-        vm_veto(r->S, r->ev, C, t, u, &st.tm, &st.z, &st.omz, &st.phi, &st.v);
+        vm_veto(r->S, r->ev, C, t, best, u, &st.tm, &st.z, &st.omz, &st.phi, &st.v);
         st.acc = 1;
         const int rc = emit_step(r, C, &st, t);
         if (rc == 2) break;

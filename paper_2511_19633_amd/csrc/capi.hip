@@ -216,6 +216,7 @@ gaps_status gaps_init(const gaps_config* cfg, gaps_ctx* out) {
   C.mz2 = cfg->mz * cfg->mz;
   C.b0 = (33.0 - 2.0 * 5.0) / (12.0 * gaps::kPi);
   C.as_over = cfg->alphas_mz / (1.0 + cfg->alphas_mz * C.b0 * log(cfg->t_cut / C.mz2));
+  C.ln_mz2 = log(C.mz2);
   double q2min = exp(cfg->lnq0);
   C.tc_is = cfg->t_cut > q2min ? cfg->t_cut : q2min;
   C.mc2 = cfg->mc * cfg->mc;

@@ -58,6 +58,7 @@ enum : uint32_t {
 struct Cfg {
   int process, nf, nx, nq;
   double sqrt_s, S, t_cut, tc_is, alphas_mz, mz, gz, mz2, b0, as_over;
+  double ln_mz2;  // log(mz2), computed on the host
   double mc2, mb2, tch_c, tch_b, ln_tc, ln_tcis, ln_tch_c, ln_tch_b;
   double sw2, gf, mll_min, mll_max, p_s, over_scale;
   double lnx0, lnx1, lnq0, lnq1, dlnx, dlnq;
@@ -103,6 +104,12 @@ __device__ __forceinline__ void rng4(uint64_t seed, uint32_t stream, int64_t id,
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double alphas(const Cfg& C, double t) {
   return C.alphas_mz / (1.0 + C.alphas_mz * C.b0 * log(t / C.mz2));
+}
+
+// the same coupling at ln t: ln(t / mZ^2) = ln t - ln mZ^2 (a trial is drawn
+// in ln t, so its coupling needs no logarithm)
+__device__ __forceinline__ double alphas_ln(const Cfg& C, double lnt) {
+  return C.alphas_mz / (1.0 + C.alphas_mz * C.b0 * (lnt - C.ln_mz2));
 }
 
 __device__ __forceinline__ int pdf_tab(int pid) {
@@ -718,8 +725,10 @@ __device__ __forceinline__ void is_vars(int type, double z, double omz, double t
 // acceptance weight of the winner trial: kinematic variables and phase-space
 // check per dipole type, the splitting kernel, then one shared pair of PDF
 // lookups for the ratio (spectator for FI, emitter for IF and II)
+// t: the trial scale, lnt: its ln t as drawn (the PDF ratio's ln Q^2 and the
+// coupling's logarithm)
 __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, const Term& tm, double t,
-                                   double z, double omz) {
+                                   double lnt, double z, double omz) {
   Veto r;
   r.ok = 0; r.x = 0.0; r.omx = 0.0; r.y = 0.0; r.uv = 0.0; r.w = 0.0; r.wn = 0.0;
   const double s = ch.s;
@@ -779,7 +788,7 @@ __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, c
       xn = ch.eta / x;
     }
     if (tnum < 0 || tden < 0) return r;
-    const double lq = log(t);
+    const double lq = lnt;
     const double den = pdf_f_l(C, tden, xd, t, lq);
     pr = den > 0.0 ? pdf_f_l(C, tnum, xn, t, lq) / den : 0.0;
   }
@@ -790,7 +799,7 @@ __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, c
   if (ch.mec) W *= mec_ratio(kern == kB, x, uv);
   r.x = x; r.omx = omx; r.y = y; r.uv = uv;
   const double over = C.over_scale * tm.coefR * shape_val(tm.shape, z, omz);
-  const double ar = alphas(C, t) / C.as_over;
+  const double ar = alphas_ln(C, lnt) / C.as_over;
   r.w = ar * W / over;
   r.wn = ar * W / shape_val(tm.shape, z, omz);
   r.ok = 1;

@@ -137,7 +137,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
           const Term tm = select_term(C, ch, u[0]);
           double z, omz;
           shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
-          const Veto v = veto_weight(C, R, ch, tm, t, z, omz);
+          const Veto v = veto_weight(C, R, ch, tm, t, key, z, omz);
           if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
           if (v.ok && u[3] < v.w) {
             if (key > best) {
@@ -310,7 +310,7 @@ __device__ void shower_one(const Cfg& C, const gaps_events& in, int64_t e, const
       double z, omz;
       shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
       double phi = 2.0 * kPi * u[2];
-      Veto v = veto_weight(C, R, ch, tm, t, z, omz);
+      Veto v = veto_weight(C, R, ch, tm, t, best, z, omz);
       if (v.ok && v.w > 1.0) { nviol += 1; flags |= fViol; }
       if (v.ok && u[3] < v.w) {
         if (n + 1 > M) { flags |= fOverflow; break; }

@@ -1156,7 +1156,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         double z, omz;
         shape_sample(tm.shape, ch, tm.I, u[1], z, omz);
         const double phi = 2.0 * kPi * u[2];
-        const Veto v = veto_weight(C, R, ch, tm, t, z, omz);
+        const Veto v = veto_weight(C, R, ch, tm, t, best, z, omz);
         if (log_mode) {
           // trial log: one atomic for the lanes of this branch that log
           const bool dolog = (ch.type == kIF || ch.type == kII) && !ch.mec && v.ok && v.wn > 0.0;

@@ -56,6 +56,21 @@ def test_alphas_rge_and_reference(oracles):
     assert o.alphas(1.0) == pytest.approx(0.336931, abs=2e-6)
 
 
+def test_coupling_and_pdf_at_ln_t(oracles):
+    """The veto weight evaluates the coupling and the PDF interpolation at the
+    trial's ln t: the same functions as at t, to rounding (the coupling's
+    logarithm ln(t / mZ^2) taken as ln t - ln mZ^2), and exactly the same PDF
+    value when the ln Q^2 given is log(Q^2)."""
+    o = oracles["lo"]
+    for t in (1.0, 2.5, 91.1876 ** 2, 1e4, 1e7):
+        lnt = math.log(t)
+        assert o.alphas_ln(lnt) == pytest.approx(o.alphas(t), rel=1e-14)
+    assert o.alphas_ln(math.log(91.1876 ** 2)) == pytest.approx(0.118, rel=1e-15)
+    for tab in (0, 1, 2, 7):
+        for x, q2 in ((1e-4, 3.0), (0.05, 91.0), (0.3, 1e4), (0.9, 2e6)):
+            assert o.pdf_f_lq(tab, x, q2, math.log(q2)) == o.pdf_xf(tab, x, q2) / x
+
+
 def test_pdf_nodes_exact(oracles, cfgs):
     o, grid = oracles["lo"], cfgs["lo"]["pdf"]
     lnx, lnq = toypdf.grid_axes()
