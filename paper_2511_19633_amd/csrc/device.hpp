@@ -166,6 +166,25 @@ __device__ inline double pdf_xf_l(const Cfg& C, int tab, double x, double q2, do
   return (1.0 - b) * ((1.0 - a) * f00 + a * f10) + b * ((1.0 - a) * f01 + a * f11);
 }
 
+// the same lookup with ln(x) supplied too (a channel's cached momentum fraction)
+__device__ inline double pdf_f_lx(const Cfg& C, int tab, double x, double lx, double q2, double lq) {
+  if (!(x > 0.0) || x >= 1.0 || !(q2 > 0.0)) return 0.0;
+  if (lx < C.lnx0 || lq < C.lnq0 || lq > C.lnq1) return 0.0;
+  double fx = (lx - C.lnx0) / C.dlnx;
+  int i = (int)fx;
+  if (i > C.nx - 2) i = C.nx - 2;
+  double a = fx - (double)i;
+  double fq = (lq - C.lnq0) / C.dlnq;
+  int j = (int)fq;
+  if (j > C.nq - 2) j = C.nq - 2;
+  double b = fq - (double)j;
+  const float* F = C.pdf + (size_t)tab * C.nq * C.nx;
+  double f00 = F[j * C.nx + i], f10 = F[j * C.nx + i + 1];
+  double f01 = F[(j + 1) * C.nx + i], f11 = F[(j + 1) * C.nx + i + 1];
+  const double xf = (1.0 - b) * ((1.0 - a) * f00 + a * f10) + b * ((1.0 - a) * f01 + a * f11);
+  return xf > 0.0 ? xf / x : 0.0;
+}
+
 __device__ __forceinline__ double pdf_f_l(const Cfg& C, int tab, double x, double q2, double lq) {
   double xf = pdf_xf_l(C, tab, x, q2, lq);
   return xf > 0.0 ? xf / x : 0.0;
@@ -245,6 +264,9 @@ struct Chan {
   double s, eta, etak, tlim, lntlim, tcut, lntcut, m2;
   double zlo, zhi, omzlo, omzhi, I1, I2, c, invc;
   double lz1;  // log(zlo / (1 - zlo)) of an initial-state channel (its 1/(z(1-z)) shape), else 0
+  // log of the momentum fraction in the PDF ratio's denominator: the
+  // emitter's eta (IF, II) or the spectator's (FI); 0 for FF
+  double lnep;
 };
 
 struct Term {
@@ -252,9 +274,10 @@ struct Term {
   double coefR, I;
 };
 
-__device__ __forceinline__ int eta_bin(double eta) {
+// bin of a momentum fraction, from its logarithm
+__device__ __forceinline__ int eta_bin_ln(double lneta) {
   const double dle = -kLnEta0 / kNB;
-  double b = floor((log(eta) - kLnEta0) / dle);
+  double b = floor((lneta - kLnEta0) / dle);
   if (!(b >= 0.0)) return 0;
   if (b > kNB - 1) return kNB - 1;
   return (int)b;
@@ -448,7 +471,7 @@ __device__ __forceinline__ double gluon_d_sum(const Cfg& C, bool ii, Tab R_of) {
 __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, int k, Chan& ch, bool mec) {
   ch.i = i; ch.k = k; ch.side = side; ch.alive = 0; ch.heavy = 0; ch.nterm = 0;
   ch.m2 = 0.0; ch.c = 0.0; ch.invc = 0.0; ch.ebin = 0; ch.kbin = 0;
-  ch.zlo = ch.zhi = ch.omzlo = ch.omzhi = ch.I1 = ch.I2 = ch.lz1 = 0.0;
+  ch.zlo = ch.zhi = ch.omzlo = ch.omzhi = ch.I1 = ch.I2 = ch.lz1 = ch.lnep = 0.0;
   int sti = R.st[R.o(i)], stk = R.st[R.o(k)];
   bool isE = sti < 0, isS = stk < 0;
   ch.pidi = R.pid[R.o(i)];
@@ -500,7 +523,8 @@ __device__ inline void chan_setup(const Cfg& C, const Rec& R, int i, int side, i
     ch.omzlo = 1.0 - ch.zlo;
   }
   if (isE || ch.type == kFI) {  // one bin evaluation: the emitter's or the spectator's
-    const int b = eta_bin(isE ? eta : etak);
+    ch.lnep = log(isE ? eta : etak);
+    const int b = eta_bin_ln(ch.lnep);
     if (isE) ch.ebin = b;
     else ch.kbin = b;
   }
@@ -789,7 +813,7 @@ __device__ inline Veto veto_weight(const Cfg& C, const Rec& R, const Chan& ch, c
     }
     if (tnum < 0 || tden < 0) return r;
     const double lq = lnt;
-    const double den = pdf_f_l(C, tden, xd, t, lq);
+    const double den = pdf_f_lx(C, tden, xd, ch.lnep, t, lq);
     pr = den > 0.0 ? pdf_f_l(C, tnum, xn, t, lq) / den : 0.0;
   }
   double W;

@@ -23,11 +23,12 @@ static_assert(sizeof(Trial) == 32, "trial record layout");
 // Winner data of a channel cache entry, contiguous (80 bytes): the total
 // overestimate constant c (in learned mode the constant of the current cell),
 // the dipole invariant s, the z limits, the z integrals of the channel's two
-// shapes, the momentum fractions 2E/sqrt(S) of an incoming emitter and
-// spectator (0 when outgoing), log(zlo / (1 - zlo)) of an incoming emitter's
-// channel, and the two flavours (int8 each, emitter in the low byte).
+// shapes, the momentum fraction 2E/sqrt(S) in the PDF ratio's denominator (the
+// incoming emitter's for IF and II, the incoming spectator's for FI, 0 for FF)
+// and its logarithm, log(zlo / (1 - zlo)) of an incoming emitter's channel,
+// and the two flavours (int8 each, emitter in the low byte).
 struct Win {
-  double c, s, zlo, omzhi, I1, I2, eta, etak, lz1;
+  double c, s, zlo, omzhi, I1, I2, etap, lnep, lz1;
   uint32_t pid, pad0;
 };
 static_assert(sizeof(Win) == 80, "winner record layout");

@@ -237,7 +237,9 @@ __device__ __forceinline__ void build_setup(const WaveCtx& W, BuildLds& B, int h
   W.S.ent[oc].t.ic = ch.invc;
   Win wd;
   wd.c = ch.c; wd.s = ch.s; wd.zlo = ch.zlo; wd.omzhi = ch.omzhi; wd.I1 = ch.I1; wd.I2 = ch.I2;
-  wd.eta = ch.eta; wd.etak = ch.etak; wd.lz1 = ch.lz1;
+  wd.etap = ch.type == kFI ? ch.etak : ch.eta;
+  wd.lnep = ch.lnep;
+  wd.lz1 = ch.lz1;
   wd.pid = (uint32_t)(ch.pidi & 0xFF) | ((uint32_t)(ch.pidk & 0xFF) << 8);
   wd.pad0 = 0u;
   W.S.ent[oc].w = wd;
@@ -479,8 +481,11 @@ __device__ __forceinline__ void chan_from_cache(const Cfg& C, const Scratch& S, 
   ch.omzlo = 1.0 - ch.zlo;
   ch.I1 = wd.I1;
   ch.I2 = wd.I2;
-  ch.eta = wd.eta;
-  ch.etak = wd.etak;
+  // the winner needs only the PDF ratio's momentum fraction: the emitter's
+  // (IF, II) or the spectator's (FI)
+  ch.eta = ch.type == kFI ? 0.0 : wd.etap;
+  ch.etak = ch.type == kFI ? wd.etap : 0.0;
+  ch.lnep = wd.lnep;
   ch.lz1 = wd.lz1;
   ch.nterm = n_terms(ch, C.nf);
 }
@@ -1169,7 +1174,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
             const unsigned long long r = base + (unsigned long long)__popcll(lm & lanemask_lt(lane));
             if (dolog && r < (unsigned long long)A.log_cap) {
               float* row = A.log + 5ull * r;
-              row[0] = (float)log(t); row[1] = (float)log(ch.eta); row[2] = (float)z;
+              row[0] = (float)log(t); row[1] = (float)ch.lnep; row[2] = (float)z;
               row[3] = (float)tm.ent; row[4] = (float)log(v.wn);
             }
           }
