@@ -224,22 +224,33 @@ __global__ void __launch_bounds__(64) k_observables(Cfg C, gaps_events ev, int64
 
 // ---------------------------------------------------------------------------
 // The pp observables with one event per wave: the event's slots one per lane,
-// its pseudojets in LDS, and every anti-kT step an argmin over all pairs spread
-// over the lanes (each lane the pairs of its pseudojets), reduced over the
-// wave with the serial loop's order as tie-break: the same clustering as the
-// one-thread loop above, without its private arrays.  For events of at most
-// kObsW slots.
+// its pseudojets in LDS, and every anti-kT step an argmin over the step's
+// distances (each alive pseudojet's beam distance, then its pairs with the
+// later ones) laid out flat over the lanes in the serial loop's order, so the
+// first of equal minima is the serial loop's choice: the same clustering as
+// the one-thread loop above, without its private arrays.  The transcendentals
+// of the jet and Z observables run on several lanes at once.  For events of
+// at most kObsW slots.
 struct ObsWave {
   double q[kObsW][4];
   double y[kObsW], ph[kObsW], ip[kObsW];
-  int on[kObsW];
+  int map[kObsW];  // the alive pseudojets in index order
   int jet[kObsW];  // the pseudojets that became jets, in order (their q is final)
+  int srt[kObsW];  // the jets by pT, descending, equal pT in order
 };
 namespace {
-// the pair (or beam distance) that comes first: smaller distance, then the
-// serial loop's order (emitter i, then beam before pairs, then partner j)
-__device__ __forceinline__ bool obs_before(double v, int i, int j, double bv, int bi, int bj) {
-  return v < bv || (v == bv && (i < bi || (i == bi && j < bj)));
+// first item of row a of an anti-kT step with A alive pseudojets: row a holds
+// pseudojet a's beam distance and its pairs with a+1 .. A-1
+__device__ __forceinline__ int obs_row0(int a, int A) { return a * (2 * A - a + 1) / 2; }
+// the row of item p (0 <= p < A (A + 1) / 2): the smaller root of the row
+// start's quadratic, then corrected to the integer row
+__device__ __forceinline__ int obs_row(int p, int A) {
+  const float b = (float)(2 * A + 1);
+  int a = (int)(0.5f * (b - sqrtf(b * b - 8.0f * (float)p)));
+  a = a < 0 ? 0 : (a > A - 1 ? A - 1 : a);
+  while (a > 0 && obs_row0(a, A) > p) --a;
+  while (a < A - 1 && obs_row0(a + 1, A) <= p) ++a;
+  return a;
 }
 }  // namespace
 
@@ -299,102 +310,155 @@ __global__ void __launch_bounds__(64 * kObsWaves, 4) k_observables_pp(Cfg C, gap
       W.ip[i] = 1.0 / (W.q[i][1] * W.q[i][1] + W.q[i][2] * W.q[i][2]);
     };
     for (int i = lane; i < nq; i += 64) {
-      W.on[i] = 1;
+      W.map[i] = i;
       props(i);
     }
     __builtin_amdgcn_wave_barrier();
     const double iR2 = 0.4 * 0.4;
     int nj = 0;
-    for (int alive = nq; alive > 0; --alive) {
+    for (int A = nq; A > 0; --A) {
+      // the smallest distance of the step, the first in item order on ties
+      const int nitem = A * (A + 1) / 2;
       double bv = INFINITY;
-      int bi = 1 << 30, bj = 1 << 30;
-      for (int i = lane; i < nq; i += 64) {
-        if (!W.on[i]) continue;
-        const double diB = W.ip[i];
-        if (obs_before(diB, i, -1, bv, bi, bj)) { bv = diB; bi = i; bj = -1; }
-        const double yi = W.y[i], phii = W.ph[i];
-        for (int j = i + 1; j < nq; ++j) {
-          if (!W.on[j]) continue;
-          double dy = yi - W.y[j];
-          double dphi = fabs(phii - W.ph[j]);
+      int bp = 0x7fffffff;
+      for (int p = lane; p < nitem; p += 64) {
+        const int a = obs_row(p, A), o = p - obs_row0(a, A);
+        const int ia = W.map[a];
+        const double diB = W.ip[ia];
+        double v = diB;
+        if (o > 0) {
+          const int ib = W.map[a + o];
+          double dy = W.y[ia] - W.y[ib];
+          double dphi = fabs(W.ph[ia] - W.ph[ib]);
           if (dphi > kPi) dphi = 2.0 * kPi - dphi;
           double dR2 = dy * dy + dphi * dphi;
-          double dij = fmin(diB, W.ip[j]) * dR2 / iR2;
-          if (obs_before(dij, i, j, bv, bi, bj)) { bv = dij; bi = i; bj = j; }
+          v = fmin(diB, W.ip[ib]) * dR2 / iR2;
+        }
+        if (v < bv) { bv = v; bp = p; }
+      }
+      double m = bv;
+      for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
+      const unsigned long long hit = __ballot(bp != 0x7fffffff && bv == m);
+      int wp = 0;  // no finite distance at all (no such event): the first pseudojet becomes a jet
+      if (__popcll(hit) == 1) {
+        wp = __shfl(bp, __ffsll((long long)hit) - 1);
+      } else if (hit) {
+        int c = (bp != 0x7fffffff && bv == m) ? bp : 0x7fffffff;
+        for (int o = 32; o > 0; o >>= 1) c = min(c, __shfl_xor(c, o));
+        wp = c;
+      }
+      const int a = obs_row(wp, A), o = wp - obs_row0(a, A);
+      const int ia = W.map[a];
+      int gone = a;
+      if (o == 0) {
+        if (lane == 0) W.jet[nj] = ia;
+        ++nj;
+      } else {
+        gone = a + o;
+        if (lane == 0) {
+          const int ib = W.map[gone];
+          for (int mm = 0; mm < 4; ++mm) W.q[ia][mm] += W.q[ib][mm];
+          props(ia);
         }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o);
-        const int oi = __shfl_xor(bi, o), oj = __shfl_xor(bj, o);
-        if (obs_before(ov, oi, oj, bv, bi, bj)) { bv = ov; bi = oi; bj = oj; }
+      // drop the finished pseudojet from the alive list, keeping index order
+      for (int k0 = gone; k0 < A - 1; k0 += 64) {
+        const int k = k0 + lane;
+        const int v = k < A - 1 ? W.map[k + 1] : 0;
+        if (k < A - 1) W.map[k] = v;
       }
-      __builtin_amdgcn_wave_barrier();
-      if (lane == 0) {
-        if (bj < 0) {
-          W.jet[nj] = bi;
-          W.on[bi] = 0;
-        } else {
-          for (int m = 0; m < 4; ++m) W.q[bi][m] += W.q[bj][m];
-          W.on[bj] = 0;
-          props(bi);
-        }
-      }
-      if (bj < 0) ++nj;
       __builtin_amdgcn_wave_barrier();
     }
+    // ---- jets by pT, descending, equal pT keep their order: each jet's rank
+    auto pt2 = [&](int k) { return W.q[k][1] * W.q[k][1] + W.q[k][2] * W.q[k][2]; };
+    for (int k = lane; k < nj; k += 64) {
+      const int t = W.jet[k];
+      const double p2 = pt2(t);
+      int r = 0;
+      for (int mm = 0; mm < nj; ++mm) {
+        const double o2 = pt2(W.jet[mm]);
+        r += (o2 > p2 || (o2 == p2 && mm < k)) ? 1 : 0;
+      }
+      W.srt[r] = t;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // ---- jet pT and pseudorapidity of each jet on a lane of its own; items
+    // nj and nj + 1 are the two leptons' pseudorapidities
+    int njet = 0, n_eta = 0;
+    double j1pt = 0.0, j2pt = 0.0, j1eta = 0.0, et1 = 0.0, et2 = 0.0, etm = 0.0, etp = 0.0;
+    bool have1 = false;
+    int i1 = -1, i2 = -1;
+    for (int k0 = 0; k0 < nj + 2; k0 += 64) {
+      const int k = k0 + lane;
+      double p[4] = {0.0, 0.0, 0.0, 1.0};
+      if (k < nj) {
+        for (int mm = 0; mm < 4; ++mm) p[mm] = W.q[W.srt[k]][mm];
+      } else if (k == nj) {
+        for (int mm = 0; mm < 4; ++mm) p[mm] = lm[mm];
+      } else if (k == nj + 1) {
+        for (int mm = 0; mm < 4; ++mm) p[mm] = lp[mm];
+      }
+      double pt = 0.0, et = 0.0;
+      if (k < nj + 2) {
+        pt = sqrt(p[1] * p[1] + p[2] * p[2]);
+        et = pseudorap(p);
+      }
+      const bool jt = k < nj;
+      unsigned long long me = __ballot(jt && fabs(et) < 5.0);
+      const unsigned long long mp = __ballot(jt && pt > 5.0);
+      unsigned long long mb = __ballot(jt && pt > 5.0 && fabs(et) < 5.0);
+      if (nj >= k0 && nj < k0 + 64) etm = __shfl(et, nj - k0);
+      if (nj + 1 >= k0 && nj + 1 < k0 + 64) etp = __shfl(et, nj + 1 - k0);
+      for (; n_eta < 2 && me; me &= me - 1, ++n_eta) {
+        const double v = __shfl(pt, __ffsll((long long)me) - 1);
+        if (n_eta == 0) j1pt = v;
+        else j2pt = v;
+      }
+      if (!have1 && mp) {
+        j1eta = __shfl(et, __ffsll((long long)mp) - 1);
+        have1 = true;
+      }
+      for (; njet < 2 && mb; mb &= mb - 1, ++njet) {
+        const int L = __ffsll((long long)mb) - 1;
+        if (njet == 0) { i1 = W.srt[k0 + L]; et1 = __shfl(et, L); }
+        else { i2 = W.srt[k0 + L]; et2 = __shfl(et, L); }
+      }
+      njet += __popcll(mb);
+    }
+    // ---- the azimuths (Z, leptons, the two leading jets) on a lane each
+    double Z[4];
+    for (int mm = 0; mm < 4; ++mm) Z[mm] = lm[mm] + lp[mm];
+    double az = 0.0;
+    {
+      double ax = 0.0, ay = 0.0;
+      bool need = false;
+      if (lane == 0) { ax = Z[1]; ay = Z[2]; need = !(Z[1] == 0.0 && Z[2] == 0.0); }
+      else if (lane == 1) { ax = lm[1]; ay = lm[2]; need = true; }
+      else if (lane == 2) { ax = lp[1]; ay = lp[2]; need = true; }
+      else if (lane == 3 && njet >= 2) { ax = W.q[i1][1]; ay = W.q[i1][2]; need = true; }
+      else if (lane == 4 && njet >= 2) { ax = W.q[i2][1]; ay = W.q[i2][2]; need = true; }
+      if (need) az = atan2(ay, ax);
+    }
+    const double phm = __shfl(az, 1), php = __shfl(az, 2), ph1 = __shfl(az, 3), ph2 = __shfl(az, 4);
     // ---- Z and jet observables (one lane)
     if (lane == 0) {
       double* o = obs + e * kNObs;
       double imb = 0.0;
-      for (int m = 0; m < 4; ++m) imb = fmax(imb, fabs(bal[m]));
-      double Z[4];
-      for (int m = 0; m < 4; ++m) Z[m] = lm[m] + lp[m];
+      for (int mm = 0; mm < 4; ++mm) imb = fmax(imb, fabs(bal[mm]));
       o[0] = sqrt(Z[1] * Z[1] + Z[2] * Z[2]);
       o[1] = rapidity(Z);
-      o[2] = (Z[1] == 0.0 && Z[2] == 0.0) ? 0.0 : atan2(Z[2], Z[1]);
-      double dphi = fabs(atan2(lm[2], lm[1]) - atan2(lp[2], lp[1]));
+      o[2] = az;
+      double dphi = fabs(phm - php);
       if (dphi > kPi) dphi = 2.0 * kPi - dphi;
-      double cth = tanh(0.5 * (pseudorap(lm) - pseudorap(lp)));
+      double cth = tanh(0.5 * (etm - etp));
       o[3] = tan(0.5 * (kPi - dphi)) * sqrt(fmax(0.0, 1.0 - cth * cth));
-      // jets by pT, descending (insertion sort: equal pT keep their order)
-      auto pt2 = [&](int k) { return W.q[k][1] * W.q[k][1] + W.q[k][2] * W.q[k][2]; };
-      for (int i = 1; i < nj; ++i) {
-        const int t = W.jet[i];
-        const double pti = pt2(t);
-        int j = i - 1;
-        while (j >= 0 && pt2(W.jet[j]) < pti) {
-          W.jet[j + 1] = W.jet[j];
-          --j;
-        }
-        W.jet[j + 1] = t;
-      }
-      int njet = 0, n_eta = 0;
-      double j1[4] = {0, 0, 0, 0}, j2[4] = {0, 0, 0, 0};
-      double j1pt = 0.0, j2pt = 0.0, j1eta = 0.0;
-      bool have1 = false;
-      for (int k = 0; k < nj; ++k) {
-        const double* jt = W.q[W.jet[k]];
-        double pt = sqrt(jt[1] * jt[1] + jt[2] * jt[2]);
-        double et = pseudorap(jt);
-        if (fabs(et) < 5.0) {
-          if (n_eta == 0) j1pt = pt;
-          else if (n_eta == 1) j2pt = pt;
-          ++n_eta;
-        }
-        if (pt > 5.0 && !have1) { j1eta = et; have1 = true; }
-        if (pt > 5.0 && fabs(et) < 5.0) {
-          if (njet == 0) { for (int m = 0; m < 4; ++m) j1[m] = jt[m]; }
-          else if (njet == 1) { for (int m = 0; m < 4; ++m) j2[m] = jt[m]; }
-          ++njet;
-        }
-      }
       o[4] = njet;
       o[5] = j1pt;
       o[6] = j1eta;
       o[7] = j2pt;
       if (njet >= 2) {
-        double dy = pseudorap(j1) - pseudorap(j2);
-        double dp = fabs(atan2(j1[2], j1[1]) - atan2(j2[2], j2[1]));
+        double dy = et1 - et2;
+        double dp = fabs(ph1 - ph2);
         if (dp > kPi) dp = 2.0 * kPi - dp;
         o[8] = sqrt(dy * dy + dp * dp);
       } else {
