@@ -225,33 +225,35 @@ __global__ void __launch_bounds__(64) k_observables(Cfg C, gaps_events ev, int64
 // ---------------------------------------------------------------------------
 // The pp observables with one event per wave: the event's slots one per lane,
 // its pseudojets in LDS, and every anti-kT step an argmin over the step's
-// distances (each alive pseudojet's beam distance, then its pairs with the
-// later ones) laid out flat over the lanes in the serial loop's order, so the
-// first of equal minima is the serial loop's choice: the same clustering as
-// the one-thread loop above, without its private arrays.  The transcendentals
-// of the jet and Z observables run on several lanes at once.  For events of
-// at most kObsW slots.
+// distances (each alive pseudojet's beam distance and its pairs), the pairs
+// dealt to the lanes once for the whole kernel in triangular order and the
+// minimum taken with the serial loop's order (emitter, beam before pairs,
+// partner) as tie-break: the same clustering as the one-thread loop above,
+// without its private arrays.  The transcendentals of the jet and Z
+// observables run on several lanes at once.  For events of at most kObsW
+// slots.
 struct ObsWave {
   double q[kObsW][4];
-  double y[kObsW], ph[kObsW], ip[kObsW];
-  int map[kObsW];  // the alive pseudojets in index order
-  int jet[kObsW];  // the pseudojets that became jets, in order (their q is final)
-  int srt[kObsW];  // the jets by pT, descending, equal pT in order
+  double y[kObsW], ph[kObsW];
+  double ip[kObsW];  // 1/pT^2 of an alive pseudojet, -1 once it is merged or a jet
+  int jet[kObsW];    // the pseudojets that became jets, in order (their q is final)
+  int srt[kObsW];    // the jets by pT, descending, equal pT in order
 };
 namespace {
-// first item of row a of an anti-kT step with A alive pseudojets: row a holds
-// pseudojet a's beam distance and its pairs with a+1 .. A-1
-__device__ __forceinline__ int obs_row0(int a, int A) { return a * (2 * A - a + 1) / 2; }
-// the row of item p (0 <= p < A (A + 1) / 2): the smaller root of the row
-// start's quadratic, then corrected to the integer row
-__device__ __forceinline__ int obs_row(int p, int A) {
-  const float b = (float)(2 * A + 1);
-  int a = (int)(0.5f * (b - sqrtf(b * b - 8.0f * (float)p)));
-  a = a < 0 ? 0 : (a > A - 1 ? A - 1 : a);
-  while (a > 0 && obs_row0(a, A) > p) --a;
-  while (a < A - 1 && obs_row0(a + 1, A) <= p) ++a;
-  return a;
+// item q of the triangle a <= b (row b holds a = 0 .. b): b the largest with
+// b (b + 1) / 2 <= q, from the root of the quadratic corrected to the integer
+__device__ __forceinline__ void obs_tri(int q, int& a, int& b) {
+  b = (int)(0.5f * (sqrtf(8.0f * (float)q + 1.0f) - 1.0f));
+  b = b < 0 ? 0 : b;
+  while (b > 0 && b * (b + 1) / 2 > q) --b;
+  while ((b + 1) * (b + 2) / 2 <= q) ++b;
+  a = q - b * (b + 1) / 2;
 }
+// the serial loop's position of an item: emitter a, its beam distance (b ==
+// a) before its pairs, then partner b
+__device__ __forceinline__ int obs_ord(int a, int b) { return (a << 8) | (a == b ? 0 : b + 1); }
+constexpr int kNoItem = 0x7fffffff;
+constexpr int kObsPass = 4;  // items dealt once per lane: events of up to 22 pseudojets
 }  // namespace
 
 __global__ void __launch_bounds__(64 * kObsWaves, 4) k_observables_pp(Cfg C, gaps_events ev, int64_t n, double* obs) {
@@ -259,6 +261,10 @@ __global__ void __launch_bounds__(64 * kObsWaves, 4) k_observables_pp(Cfg C, gap
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   ObsWave& W = sw[wid];
   const int64_t nwaves = (int64_t)gridDim.x * kObsWaves;
+  // this lane's items of the first kObsPass passes (the same for every event)
+  int pa[kObsPass], pb[kObsPass];
+#pragma unroll
+  for (int k = 0; k < kObsPass; ++k) obs_tri(lane + 64 * k, pa[k], pb[k]);
   for (int64_t e = (int64_t)blockIdx.x * kObsWaves + wid; e < n; e += nwaves) {
     int nn = ev.n[e];
     if (nn > ev.max_slots) nn = ev.max_slots;
@@ -309,64 +315,64 @@ __global__ void __launch_bounds__(64 * kObsWaves, 4) k_observables_pp(Cfg C, gap
       W.ph[i] = atan2(W.q[i][2], W.q[i][1]);
       W.ip[i] = 1.0 / (W.q[i][1] * W.q[i][1] + W.q[i][2] * W.q[i][2]);
     };
-    for (int i = lane; i < nq; i += 64) {
-      W.map[i] = i;
-      props(i);
-    }
+    for (int i = lane; i < nq; i += 64) props(i);
     __builtin_amdgcn_wave_barrier();
     const double iR2 = 0.4 * 0.4;
+    const int nitem = nq * (nq + 1) / 2;
     int nj = 0;
-    for (int A = nq; A > 0; --A) {
-      // the smallest distance of the step, the first in item order on ties
-      const int nitem = A * (A + 1) / 2;
+    for (int alive = nq; alive > 0; --alive) {
+      // this lane's smallest distance, the serial loop's first on ties
       double bv = INFINITY;
-      int bp = 0x7fffffff;
-      for (int p = lane; p < nitem; p += 64) {
-        const int a = obs_row(p, A), o = p - obs_row0(a, A);
-        const int ia = W.map[a];
-        const double diB = W.ip[ia];
-        double v = diB;
-        if (o > 0) {
-          const int ib = W.map[a + o];
-          double dy = W.y[ia] - W.y[ib];
-          double dphi = fabs(W.ph[ia] - W.ph[ib]);
+      int bo = kNoItem;
+      auto take = [&](int a, int b) {
+        const double ipa = W.ip[a];
+        if (!(ipa > 0.0)) return;
+        double v = ipa;
+        if (a != b) {
+          const double ipb = W.ip[b];
+          if (!(ipb > 0.0)) return;
+          double dy = W.y[a] - W.y[b];
+          double dphi = fabs(W.ph[a] - W.ph[b]);
           if (dphi > kPi) dphi = 2.0 * kPi - dphi;
           double dR2 = dy * dy + dphi * dphi;
-          v = fmin(diB, W.ip[ib]) * dR2 / iR2;
+          v = fmin(ipa, ipb) * dR2 / iR2;
         }
-        if (v < bv) { bv = v; bp = p; }
+        const int o = obs_ord(a, b);
+        if (v < bv || (v == bv && o < bo)) { bv = v; bo = o; }
+      };
+#pragma unroll
+      for (int k = 0; k < kObsPass; ++k)
+        if (lane + 64 * k < nitem) take(pa[k], pb[k]);
+      for (int q = lane + 64 * kObsPass; q < nitem; q += 64) {
+        int a, b;
+        obs_tri(q, a, b);
+        take(a, b);
       }
       double m = bv;
       for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
-      const unsigned long long hit = __ballot(bp != 0x7fffffff && bv == m);
-      int wp = 0;  // no finite distance at all (no such event): the first pseudojet becomes a jet
+      const bool mine = bo != kNoItem && bv == m;
+      const unsigned long long hit = __ballot(mine);
+      if (!hit) break;  // no finite distance (no such event): stop clustering
+      int wo;
       if (__popcll(hit) == 1) {
-        wp = __shfl(bp, __ffsll((long long)hit) - 1);
-      } else if (hit) {
-        int c = (bp != 0x7fffffff && bv == m) ? bp : 0x7fffffff;
-        for (int o = 32; o > 0; o >>= 1) c = min(c, __shfl_xor(c, o));
-        wp = c;
-      }
-      const int a = obs_row(wp, A), o = wp - obs_row0(a, A);
-      const int ia = W.map[a];
-      int gone = a;
-      if (o == 0) {
-        if (lane == 0) W.jet[nj] = ia;
-        ++nj;
+        wo = __shfl(bo, __ffsll((long long)hit) - 1);
       } else {
-        gone = a + o;
-        if (lane == 0) {
-          const int ib = W.map[gone];
-          for (int mm = 0; mm < 4; ++mm) W.q[ia][mm] += W.q[ib][mm];
-          props(ia);
+        int c = mine ? bo : kNoItem;
+        for (int o = 32; o > 0; o >>= 1) c = min(c, __shfl_xor(c, o));
+        wo = c;
+      }
+      const int a = wo >> 8, r = wo & 0xFF;
+      if (lane == 0) {
+        if (r == 0) {
+          W.jet[nj] = a;
+          W.ip[a] = -1.0;
+        } else {
+          for (int mm = 0; mm < 4; ++mm) W.q[a][mm] += W.q[r - 1][mm];
+          props(a);
+          W.ip[r - 1] = -1.0;
         }
       }
-      // drop the finished pseudojet from the alive list, keeping index order
-      for (int k0 = gone; k0 < A - 1; k0 += 64) {
-        const int k = k0 + lane;
-        const int v = k < A - 1 ? W.map[k + 1] : 0;
-        if (k < A - 1) W.map[k] = v;
-      }
+      if (r == 0) ++nj;
       __builtin_amdgcn_wave_barrier();
     }
     // ---- jets by pT, descending, equal pT keep their order: each jet's rank
