@@ -149,6 +149,23 @@ def stored_traffic(kernel, mode):
     return d.get("modes", {}).get(mode)
 
 
+def counted_fp64(tr, events_per_s):
+    """FP64 rates from the committed counter summary's per-event figures at
+    the measured events/s: the flops the SIMDs issued (SQ_INSTS_VALU_FLOPS_FP64
+    and _TRANS, one count per wave instruction, times 64) and those weighted by
+    the fraction of lanes active in a VALU instruction; None without a
+    summary of these sources."""
+    fp = None if tr is None else tr.get("fp64")
+    if fp is None:
+        return None
+    issued = fp["issued_flop_per_event"] * events_per_s / 1e12
+    lane = fp["lane_flop_per_event"] * events_per_s / 1e12
+    return {"unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS, "issued": issued, "issued_frac": issued / FP64_PEAK_TFLOPS,
+            "lane_weighted": lane, "lane_weighted_frac": lane / FP64_PEAK_TFLOPS,
+            "issued_flop_per_event": fp["issued_flop_per_event"], "lane_flop_per_event": fp["lane_flop_per_event"],
+            "trans_f64_per_event": fp["trans_per_event"]}
+
+
 def copy_probe(nbytes):
     """A plain device copy of known size: the calibration run for the HBM byte counters."""
     import torch
@@ -388,7 +405,8 @@ def summarise(r, outs, kernel, mode_name, K):
             "transcendentals_per_launch": trans, "pdf_lookups_per_launch": st[0] * PDF_LOOKUPS_WINNER,
             "philox_blocks_per_launch": st[1] / 4.0 + st[0],
             "transcendentals_per_s": trans / launch_s,
-            "hbm_gbs": None if traffic is None else traffic / launch_s / 1e9}
+            "hbm_gbs": None if traffic is None else traffic / launch_s / 1e9,
+            "counted_fp64": counted_fp64(tr, r["events"] / launch_s)}
     value = r["events"] / r["wall_s"]
     return {"value": value, "value_min": r["events"] / r["wall_s_max"], "value_max": r["events"] / r["wall_s_min"],
             "repeats": r["repeats"], "ms_per_step": r["wall_s"] * 1e3 / K, "roofline": roof,
