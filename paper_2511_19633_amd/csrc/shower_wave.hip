@@ -66,8 +66,7 @@ struct LaneState {
 };
 static_assert(sizeof(LaneState) <= kLaneStateBytes, "lane state exceeds its LDS budget");
 
-// sum of a per-lane count over the wave, as a wave-uniform value (so that the
-// statistics accumulate in scalar registers, not in every lane)
+// sum of a per-lane count over the wave, as a wave-uniform value
 __device__ __forceinline__ unsigned long long wave_total(unsigned long long v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
@@ -555,6 +554,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   double T = 0.0, lnT = 0.0, t1 = 0.0;
   uint32_t cycle = 0, ntri = 0, nacc = 0, nviol = 0, flags = 0;
   int n = 0, maxtag = 0;
+  // statistics, per lane (summed over the wave once, at the end: wave-uniform
+  // accumulators would hold scalar registers, which the loop is short of)
   unsigned long long st_cyc = 0, st_tri = 0, st_acc = 0, st_viol = 0, st_iters = 0, st_active = 0;
   unsigned long long st_fb = 0, st_null = 0;
   int since = 1 << 30;
@@ -654,10 +655,12 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (out.n_viol) out.n_viol[e] = nviol;
       if (out.t1) out.t1[e] = t1;
     }
-    st_cyc += wave_total(owed ? cycle : 0u);
-    st_tri += wave_total(owed ? ntri : 0u);
-    st_acc += wave_total(owed ? nacc : 0u);
-    st_viol += wave_total(owed ? nviol : 0u);
+    if (owed) {
+      st_cyc += cycle;
+      st_tri += ntri;
+      st_acc += nacc;
+      st_viol += nviol;
+    }
     {
       // finished events' partons to their outputs, one parton per lane
       const int np = owed && loaded ? n : 0;
@@ -831,8 +834,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
       if (exhausted && !tail) __builtin_amdgcn_s_sleep(2);
       continue;
     }
-    st_iters += 64ull;
-    st_active += (unsigned long long)__popcll(act);
+    st_iters += 1ull;
+    st_active += active ? 1ull : 0ull;
 
     // ---- one cycle of the veto algorithm on every active lane
     bool done = false;
@@ -1245,8 +1248,8 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
                     ? 1u : 0u;
         pw = win;
       }
-    st_null += (unsigned long long)__popcll(__ballot(nulled));
-    st_fb += (unsigned long long)__popcll(__ballot(fellback));
+    st_null += nulled ? 1ull : 0ull;
+    st_fb += fellback ? 1ull : 0ull;
     // ---- finished events: their outputs are owed until the next flush (a
     // pass for all of them: before the next refill, or at once when the
     // queue is drained)
@@ -1257,15 +1260,12 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     }
     since += 1;
   }
-  if (A.stats && lane == 0) {  // the counters are wave totals
-    atomicAdd(A.stats + 0, st_cyc);
-    atomicAdd(A.stats + 1, st_tri);
-    atomicAdd(A.stats + 2, st_acc);
-    atomicAdd(A.stats + 3, st_viol);
-    atomicAdd(A.stats + 4, st_iters);
-    atomicAdd(A.stats + 5, st_active);
-    atomicAdd(A.stats + 6, st_fb);
-    atomicAdd(A.stats + 7, st_null);
+  if (A.stats) {  // wave totals, one atomic each
+    const unsigned long long v[8] = {wave_total(st_cyc), wave_total(st_tri), wave_total(st_acc), wave_total(st_viol),
+                                     wave_total(st_iters), wave_total(st_active), wave_total(st_fb),
+                                     wave_total(st_null)};
+    if (lane == 0)
+      for (int k = 0; k < 8; ++k) atomicAdd(A.stats + k, v[k]);
   }
 }
 
