@@ -518,9 +518,37 @@ __device__ __forceinline__ int batch_of(const ShowerArgs& A, int64_t g) {
 // RETAIN: the retained-trial form of the competition (a losing channel keeps
 // its trial; only the winner draws again after a veto or a null, every channel
 // after an emission); otherwise every channel draws again each cycle.
+// Wave-uniform values held in vector registers.  The compiler keeps uniform
+// values in scalar registers, and the shower kernel runs out of them: its
+// arguments and hot constants end up spilled to lanes of vector registers and
+// restored (one instruction per dword) at every use.  An empty asm with a
+// vector-register operand moves a value into vector registers once, at the
+// start; a pointer keeps its global address space by a cast back.
+template <typename T>
+__device__ __forceinline__ T* vreg_ptr(T* p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+v"(v));
+  typedef __attribute__((address_space(1))) T GT;
+  return (T*)(GT*)v;
+}
+__device__ __forceinline__ void vreg(double& d) { asm volatile("" : "+v"(d)); }
+__device__ __forceinline__ uint64_t vreg_u64(uint64_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <bool RETAIN>
 __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_events& in1, const gaps_events& out1,
-                                                 const Scratch& S, const ShowerArgs& A) {
+                                                 const Scratch& Sg, const ShowerArgs& A) {
+  // the scratch pointers and the seed in vector registers
+  Scratch S = Sg;
+  S.part = vreg_ptr(S.part);
+  S.ent = vreg_ptr(S.ent);
+  S.key = vreg_ptr(S.key);
+  S.info = vreg_ptr(S.info);
+  S.wfac = vreg_ptr(S.wfac);
+  S.pend = vreg_ptr(S.pend);
+  const uint64_t seed = vreg_u64(A.seed);
   // the overestimate table, staged in LDS for the term loops
   __shared__ double s_bound[kBoundRows * kNB];
   __shared__ int s_cnt[16], s_nexh;
@@ -532,6 +560,16 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
   __syncthreads();
   Cfg C = Cg;
   C.bound = s_bound;
+  // the table pointers and the constants of the draws, the PDF lookups and
+  // the coupling in vector registers
+  C.learn = vreg_ptr(C.learn);
+  C.learn_sd = vreg_ptr(C.learn_sd);
+  C.pdf = vreg_ptr(C.pdf);
+  vreg(C.t_cut); vreg(C.tc_is); vreg(C.ln_tc); vreg(C.ln_tcis);
+  vreg(C.tch_c); vreg(C.ln_tch_c); vreg(C.tch_b); vreg(C.ln_tch_b);
+  vreg(C.mc2); vreg(C.mb2);
+  vreg(C.lnx0); vreg(C.dlnx); vreg(C.lnq0); vreg(C.dlnq);
+  vreg(C.b0); vreg(C.ln_mz2); vreg(C.as_over); vreg(C.over_scale);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int64_t slot = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   // every batch's output has at least S.max_slots slots (checked by the host)
@@ -816,7 +854,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     {
       const unsigned long long bm = __ballot(built);
       if (bm) {
-        const DrawState D{T, lnT, id, cycle, lrn, (lrn || (flags & fFallback)) ? 1u : 0u, A.seed,
+        const DrawState D{T, lnT, id, cycle, lrn, (lrn || (flags & fFallback)) ? 1u : 0u, seed,
                           (flags & fMEC) != 0u && t1 == 0.0};
         uint32_t drawn = 0;
         uint32_t f =
@@ -1012,7 +1050,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
           }
           if ((inf[0] | inf[1] | inf[2] | inf[3]) & 1u) {
             double ub[4];
-            rng4(A.seed, stL, idL, cyL, (uint32_t)c0 >> 2, ub);
+            rng4(seed, stL, idL, cyL, (uint32_t)c0 >> 2, ub);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const int c = c0 + j;
@@ -1153,7 +1191,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
         chan_from_cache(C, S, R, slot, win, ch);
         const bool lch = lrn && win < 4 && (ch.type == kIF || ch.type == kII);
         double u[4];
-        rng4(A.seed, strm, id, cycle, 0xFFFFFFFFu, u);
+        rng4(seed, strm, id, cycle, 0xFFFFFFFFu, u);
         // a learned channel's cached c is that of its current cell (the winner's)
         double lr[2] = {0.0, 0.0};
         if (lch) {
@@ -1244,7 +1282,7 @@ __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_event
     }
     if constexpr (RETAIN)
       if (rdw) {
-        ntri += redraw_winner(C, S, A.seed, strm, id, cycle, slot, win, rinfo, rtl, rltl, ric, T, lnT, lrn, pk)
+        ntri += redraw_winner(C, S, seed, strm, id, cycle, slot, win, rinfo, rtl, rltl, ric, T, lnT, lrn, pk)
                     ? 1u : 0u;
         pw = win;
       }
