@@ -208,58 +208,79 @@ def counter_dispatches(args):
                       "kernel": "k_shower_wave_rt" if retain else "k_shower_wave"}))
 
 
-def seed_scan(args):
+def scan_sample(G, binding, first, mode, n, K, ev_in, ev_out):
+    """Histograms of one independent sample: K batches of n NLO events with ids
+    from `first`, showered (retained trials) in `mode`."""
+    h = None
+    for k in range(K):
+        G.hard_events(first + k * n, n, 1, out=ev_in)
+        G.shower(ev_in, 1, out=ev_out, retain=True, mode=mode)
+        hk = histograms(G, [(ev_out, n)])
+        h = hk if h is None else [(a + c, b + d) for (a, b), (c, d) in zip(h, hk)]
+    return h
+
+
+class IndependentScan:
     """The histogram comparison repeated on independent samples: for sample
-    k = 1..S, the plain, learned and cell-maximum showers of 10^7 NLO events
-    (event ids from 2 k 10^7) each against a plain reference of the next 10^7
-    ids, all independent of every other sample.  Under no bias each p-value is
-    uniform and the S p-values of a form and observable combine by Fisher's
-    method (-2 sum ln p, chi^2 with 2 S degrees of freedom); one run's p-value
-    alone says little."""
+    k = 1..S, the plain, learned and cell-maximum showers of K n NLO events
+    (event ids from 2 k K n) each against a plain reference of the next K n
+    ids, all independent of every other sample and of the benchmark's own
+    comparison (ids below 2 K n).  Under no bias each p-value is uniform and
+    the S p-values of a form and observable combine by Fisher's method
+    (-2 sum ln p, chi^2 with 2 S degrees of freedom); one comparison's p-value
+    alone says little.  A form's samples are showered while its table is the
+    context's bound."""
+
+    def __init__(self, G, binding, S, n, K):
+        from gapsinputs import workloads
+        self.G, self.binding, self.S, self.n, self.K = G, binding, S, n, K
+        self.ev_in = binding.DeviceEvents(n, 8)
+        self.ev_out = binding.DeviceEvents(n, workloads.MAX_SLOTS)
+        self.refs, self.hs = [], {}
+
+    def base(self, k):
+        return 2 * (k + 1) * self.K * self.n
+
+    def run(self, form, mode):
+        b = self.binding
+        if not self.refs:
+            self.refs = [scan_sample(self.G, b, self.base(k) + self.K * self.n, b.MODE_PLAIN, self.n, self.K,
+                                     self.ev_in, self.ev_out) for k in range(self.S)]
+        self.hs[form] = [scan_sample(self.G, b, self.base(k), mode, self.n, self.K, self.ev_in, self.ev_out)
+                         for k in range(self.S)]
+
+    def result(self):
+        from scipy import stats as sstats
+        res = {"events_per_sample": self.K * self.n, "samples": self.S,
+               "ids": "sample k = 1..S: ids from 2 k K n, reference the next K n ids",
+               "p_values": {f: {} for f in self.hs}, "chi2_ndf": {f: {} for f in self.hs}}
+        for f, hl in self.hs.items():
+            for k in range(self.S):
+                for o, v in chi2(self.refs[k], hl[k]).items():
+                    if isinstance(v, dict):
+                        res["p_values"][f].setdefault(o, []).append(round(v["p_value"], 4))
+                        res["chi2_ndf"][f].setdefault(o, []).append(round(v["chi2_ndf"], 3))
+        res["fisher_p"] = {f: {o: float(sstats.chi2.sf(-2.0 * np.sum(np.log(np.maximum(ps, 1e-300))), 2 * len(ps)))
+                               for o, ps in res["p_values"][f].items()} for f in self.hs}
+        return res
+
+
+def seed_scan(args):
+    """Only the independent-sample histogram comparison (IndependentScan) with
+    a bound trained here, args.seed_scan samples."""
     import torch
-    from scipy import stats as sstats
     from gapsinputs import workloads
     from paper_2511_19633_amd import binding
     torch.cuda.set_device(0)
     G = binding.Gaps(workloads.config_dict(workloads.PP_NLO))
-    n, K = args.events, args.steps
-    ev_in = binding.DeviceEvents(n, 8)
-    ev_out = binding.DeviceEvents(n, workloads.MAX_SLOTS)
-
-    def sample(first, mode):
-        h = None
-        for k in range(K):
-            G.hard_events(first + k * n, n, 1, out=ev_in)
-            G.shower(ev_in, 1, out=ev_out, retain=True, mode=mode)
-            hk = histograms(G, [(ev_out, n)])
-            h = hk if h is None else [(a + c, b + d) for (a, b), (c, d) in zip(h, hk)]
-        return h
-
     _, rows = learned_pipeline(G, args, 1, True)
-    forms = ("plain", "learned", "cellmax")
-    res = {"events_per_sample": K * n, "samples": args.seed_scan, "p_values": {f: {} for f in forms},
-           "chi2_ndf": {f: {} for f in forms}}
-    hs = {f: [] for f in forms}
-    refs = []
-    for k in range(1, args.seed_scan + 1):
-        base = 2 * k * K * n
-        refs.append(sample(base + K * n, binding.MODE_PLAIN))
-        hs["plain"].append(sample(base, binding.MODE_PLAIN))
-        hs["learned"].append(sample(base, binding.MODE_LEARNED))
-        log(f"sample {k}: plain and learned done")
+    sc = IndependentScan(G, binding, args.seed_scan, args.events, args.steps)
+    sc.run("plain", binding.MODE_PLAIN)
+    sc.run("learned", binding.MODE_LEARNED)
+    log("plain and learned samples done")
     G.cellmax_table(rows, int(0.8 * rows.shape[0]))
-    for k in range(args.seed_scan):
-        hs["cellmax"].append(sample(2 * (k + 1) * K * n, binding.MODE_LEARNED))
-    for f in forms:
-        for k in range(args.seed_scan):
-            c = chi2(refs[k], hs[f][k])
-            for o, v in c.items():
-                if isinstance(v, dict):
-                    res["p_values"][f].setdefault(o, []).append(round(v["p_value"], 4))
-                    res["chi2_ndf"][f].setdefault(o, []).append(round(v["chi2_ndf"], 3))
-    res["fisher_p"] = {f: {o: float(sstats.chi2.sf(-2.0 * np.sum(np.log(np.maximum(ps, 1e-300))), 2 * len(ps)))
-                           for o, ps in res["p_values"][f].items()} for f in forms}
-    print(json.dumps(res))
+    sc.run("cellmax", binding.MODE_LEARNED)
+    print(json.dumps(sc.result()))
 
 
 def learned_pipeline(G, args, seed, retain):
@@ -443,6 +464,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--dispatches", action="store_true",
                     help="only one shower dispatch of the first batch per mode (for hardware counters)")
+    ap.add_argument("--scan-samples", type=int, default=5,
+                    help="independent samples of the histogram comparison in the default run (0: none)")
     ap.add_argument("--seed-scan", type=int, default=0,
                     help="only the histogram comparison of plain, learned and cell-maximum showers against "
                          "plain references, on this many independent samples (no timing)")
@@ -540,6 +563,11 @@ def main():
                               fallback_events_negative_weight=neg)
         if not args.lite:
             hist["learned"] = chi2(h_ref, histograms(G, [(o, n) for o in outs]))
+            if args.scan_samples > 0:
+                scan = IndependentScan(G, binding, args.scan_samples, n, K)
+                scan.run("plain", binding.MODE_PLAIN)
+                scan.run("learned", binding.MODE_LEARNED)
+                log("independent samples: plain and learned done")
         if tune_l is not None and not is_default(kw_l):
             s_d = summarise(timed_stream(G, binding, batches, seed, args, dict(retain=retain), binding.MODE_LEARNED),
                             outs, kernel, "learned", K)
@@ -595,12 +623,17 @@ def main():
                               kernel, key, K)
                 log(f"{key}: {s['value']:.4g} events/s")
                 hist[key] = chi2(h_ref, histograms(G, [(o, n) for o in outs]))
+                if args.scan_samples > 0 and not adaptive:
+                    scan.run("cellmax", binding.MODE_LEARNED)
                 out[key] = dict(s, speedup_over_plain=s["value"] / s_plain["value"],
                                 speedup_over_learned=s["value"] / out["learned"]["value"], table_s=t_tab,
                                 mean_bound_over_analytic=bound_over_analytic(G))
             # back to the trained bound for the legs below
             G.mlp_tabulate()
         out["histograms"] = hist
+        if args.mode == "learned" and args.scan_samples > 0:
+            out["histograms_independent"] = scan.result()
+            del scan
         del log_rows
 
         # ---- the paper's component table: hard events, shower, observables
