@@ -103,7 +103,24 @@ def cpu_baseline(cfg, seed, retain, n_single, n_all):
             "sample": f"first {n_all} NLO pp->Z event ids (seed {seed}), plain shower ({form}), {cores} threads "
                       f"over contiguous id ranges, {dtn:.2f} s wall; single thread: first {n_single} ids, "
                       f"{dt1:.2f} s",
-            "single_thread_value": n_single / dt1, "host_cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
+            "single_thread_value": n_single / dt1, "host_cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+            "single_thread_per_workload": single_thread_rates(seed, retain)}
+
+
+def single_thread_rates(seed, retain, m=10_000):
+    """The oracle on one thread over the first m event ids of each workload
+    (e+e- -> q qbar at 91.2 GeV, LO and NLO pp -> Z at 13 TeV), plain shower."""
+    from gapsinputs import workloads
+    from oracle.pyoracle import Oracle
+    out = {}
+    for name, wcfg in (("ee", workloads.EE), ("pp_lo", workloads.PP_LO), ("pp_nlo", workloads.PP_NLO)):
+        o = Oracle(workloads.config_dict(wcfg))
+        ev = o.hard_events(0, m, seed)
+        t0 = time.perf_counter()
+        o.shower(ev, seed, nthreads=1, retain=retain)
+        dt = time.perf_counter() - t0
+        out[name] = {"events": m, "events_per_s": m / dt, "wall_s": dt}
+    return out
 
 
 SHOWER_SOURCES = ("capi.hip", "device.hpp", "kernels.hpp", "shower_wave.hip")
