@@ -225,6 +225,14 @@ def counter_dispatches(args):
                       "kernel": "k_shower_wave_rt" if retain else "k_shower_wave"}))
 
 
+def fisher_p(ps):
+    """Fisher's combination of independent p-values: -2 sum ln p follows chi^2
+    with 2 k degrees of freedom when all k are uniform; its upper tail."""
+    from scipy import stats as sstats
+    ps = np.maximum(np.asarray(ps, dtype=np.float64), 1e-300)
+    return float(sstats.chi2.sf(-2.0 * np.sum(np.log(ps)), 2 * len(ps)))
+
+
 def scan_sample(G, binding, first, mode, n, K, ev_in, ev_out):
     """Histograms of one independent sample: K batches of n NLO events with ids
     from `first`, showered (retained trials) in `mode`."""
@@ -267,7 +275,6 @@ class IndependentScan:
                          for k in range(self.S)]
 
     def result(self):
-        from scipy import stats as sstats
         res = {"events_per_sample": self.K * self.n, "samples": self.S,
                "ids": "sample k = 1..S: ids from 2 k K n, reference the next K n ids",
                "p_values": {f: {} for f in self.hs}, "chi2_ndf": {f: {} for f in self.hs}}
@@ -277,8 +284,7 @@ class IndependentScan:
                     if isinstance(v, dict):
                         res["p_values"][f].setdefault(o, []).append(round(v["p_value"], 4))
                         res["chi2_ndf"][f].setdefault(o, []).append(round(v["chi2_ndf"], 3))
-        res["fisher_p"] = {f: {o: float(sstats.chi2.sf(-2.0 * np.sum(np.log(np.maximum(ps, 1e-300))), 2 * len(ps)))
-                               for o, ps in res["p_values"][f].items()} for f in self.hs}
+        res["fisher_p"] = {f: {o: fisher_p(ps) for o, ps in res["p_values"][f].items()} for f in self.hs}
         return res
 
 
