@@ -515,9 +515,6 @@ __device__ __forceinline__ int batch_of(const ShowerArgs& A, int64_t g) {
 
 }  // namespace
 
-// RETAIN: the retained-trial form of the competition (a losing channel keeps
-// its trial; only the winner draws again after a veto or a null, every channel
-// after an emission); otherwise every channel draws again each cycle.
 // Wave-uniform values held in vector registers.  The compiler keeps uniform
 // values in scalar registers, and the shower kernel runs out of them: its
 // arguments and hot constants end up spilled to lanes of vector registers and
@@ -537,6 +534,9 @@ __device__ __forceinline__ uint64_t vreg_u64(uint64_t v) {
   return v;
 }
 
+// RETAIN: the retained-trial form of the competition (a losing channel keeps
+// its trial; only the winner draws again after a veto or a null, every channel
+// after an emission); otherwise every channel draws again each cycle.
 template <bool RETAIN>
 __device__ __forceinline__ void shower_wave_body(const Cfg& Cg, const gaps_events& in1, const gaps_events& out1,
                                                  const Scratch& Sg, const ShowerArgs& A) {
