@@ -26,11 +26,12 @@ DEFAULT = dict(block=512, compact_every=8, waves_per_simd=2, fill=1.0)
 
 def default_space(retain: bool):
     """The candidate shapes: blocks of 256 and 512 threads at two waves per
-    SIMD, refills every 4, 8 or 16 cycles, 100 %, 75 % or 50 % of the filling
-    grid; with retained trials also the three-wave kernel (384 threads)."""
+    SIMD, refills every 4, 8, 16, 24 or 32 cycles, 100 %, 75 % or 50 % of the
+    filling grid; with retained trials also the three-wave kernel (384
+    threads)."""
     pts = []
     for block in (512, 256):
-        for ce in (4, 8, 16):
+        for ce in (4, 8, 16, 24, 32):
             for fill in (1.0, 0.75, 0.5):
                 pts.append(dict(block=block, compact_every=ce, waves_per_simd=2, fill=fill))
     if retain:
